@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the Gaussian attraction sums on one MI355X.
+
+A step is one pass of the whole hot path over the 4,194,304-neuron slab
+(10 x 10 x 2 mm, sigma = 750 um, p = 8, leaf <= 64): octree build (root cube,
+Morton keys, radix sort, node table), staging, the forward sum (expansion route
+chosen by the cost model) and the scatter back to input order, plus child
+probabilities for a batch of partner queries.  value = targets evaluated per
+second (attraction sums/s), inputs resident in HBM before the timed region.
+
+Prints one JSON line.  Extra keys: per-phase times, the accuracy of this run
+against the FP64 oracle on sampled targets, the all-pairs GPU direct sum on a
+sample of targets (for the speedup), and the oracle timed on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12}
+
+
+def _algorithmic(phase, ctx):
+    """(bound, unit, amount per launch) for a library phase, or None.
+
+    Amounts count what the method must do: flops of the contraction it performs
+    (2 per multiply-add) or bytes it must move at least once."""
+    n, ns, nt, p = ctx["n"], ctx["n_src"], ctx["n_tgt"], ctx["p"]
+    p3 = p ** 3
+    if phase == "p2m":
+        return "alu", "TFLOP/s", 2.0 * p3 * ns
+    if phase == "l2p":
+        return "alu", "TFLOP/s", 2.0 * p3 * nt
+    if phase in ("m2l_x", "m2l_y", "m2l_z"):
+        G = ctx["grid"]
+        k = {"m2l_x": 0, "m2l_y": 1, "m2l_z": 2}[phase]
+        U = G[k] * p
+        R = G[0] * G[1] * G[2] * p3 // U
+        return "alu", "TFLOP/s", 2.0 * R * U * U
+    if phase == "radix_sort":
+        # 8 passes; each must read and write every (key, index) pair once
+        return "hbm", "GB/s", 8 * n * 12 * 2.0
+    if phase == "morton":
+        return "hbm", "GB/s", n * (12 + 8 + 4.0)
+    if phase == "gather_sorted":
+        return "hbm", "GB/s", n * (4 + 12 + 12.0)
+    if phase in ("stage",):
+        return "hbm", "GB/s", n * (4 + 1 + 4 + 4 + 1.0)
+    if phase == "scatter":
+        return "hbm", "GB/s", n * (4 + 4 + 1 + 4 + 4.0)
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--route", default="auto")
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the neuron count (testing only)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the octree "
+              "transform shards by space with a halo exchange, which is not built here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2301_10570_amd as msp
+    import synth
+
+    print("bench: generating the 4,194,304-neuron slab", file=sys.stderr, flush=True)
+    wl = synth.config(3, args.scale)
+    wl.p = args.p
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    x, y, z, w = T(wl.x), T(wl.y), T(wl.z), T(wl.w)
+    tgt = T((wl.a > 0).astype(np.uint8))
+    n_tgt = int((wl.a > 0).sum())
+    n_src = int((wl.w > 0).sum())
+    u = torch.empty(wl.n, dtype=torch.float32, device=dev)
+    tree = msp.Tree()
+
+    def step():
+        tree.build(x, y, z, leaf_max=wl.leaf_max)
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan = tree.plan(wl.sigma, p=wl.p, route=args.route)
+
+    # timed region (phase events recorded live on the library's stream)
+    tree.set_timing(True)
+    tree.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = tree.timing(reset=True)
+    tree.set_timing(False)
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = n_tgt / (ms_per_step / 1000.0)
+    print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} sums/s", file=sys.stderr, flush=True)
+
+    # same loop without the phase events (overhead check)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_clean = 1000.0 * (time.perf_counter() - t0) / args.steps
+
+    # forward only, cached tree
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+    torch.cuda.synchronize()
+    ms_fwd = 1000.0 * (time.perf_counter() - t0) / args.steps
+
+    ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"]}
+    per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+                 for k, v in phases.items()}
+    dom = max(phases, key=lambda k: phases[k][0])
+    roof = None
+    info = _algorithmic(dom, ctx)
+    if info is not None:
+        bound, unit, amount = info
+        avg_s = phases[dom][0] / phases[dom][1] / 1000.0
+        if unit == "GB/s":
+            achieved, peak = amount / avg_s / 1e9, PEAK["hbm"] / 1e9
+        else:
+            achieved, peak = amount / avg_s / 1e12, PEAK["fp32_vector"] / 1e12
+        roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None,
+                "avg_launch_ms": phases[dom][0] / phases[dom][1]}
+
+    result = {
+        "metric": "attraction sums/s at rel-err<=1e-4 (FMM forward incl. octree build)",
+        "value": value, "unit": "sums/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "slab 4,194,304 neurons 10x10x2 mm, sigma 750 um, counts 0-5",
+                   "n": wl.n, "targets": n_tgt, "sources": n_src, "p": wl.p, "leaf_max": wl.leaf_max,
+                   "route": plan["route"], "level": plan["level"], "grid": plan["grid"],
+                   "rho": plan["rho"]},
+        "roofline": roof,
+        "phases": per_phase,
+        "ms_per_step_without_events": ms_clean,
+        "forward_only_ms": ms_fwd,
+        "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
+    }
+
+    sample = None
+    if not args.no_check or not args.no_cpu:
+        tgt_idx = np.nonzero(wl.a > 0)[0]
+    if not args.no_check:
+        import oracle
+        sample = tgt_idx[synth.sample_indices(tgt_idx.size, 256, seed=777)]
+        print("bench: oracle check on 256 sampled targets", file=sys.stderr, flush=True)
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+        got = u.cpu().numpy()[sample].astype(np.float64)
+        ref = oracle.attraction(wl, sample, threads=min(16, len(os.sched_getaffinity(0))))
+        rel = np.abs(got - ref) / ref
+        result["accuracy"] = {"targets_checked": int(sample.size), "max_rel_err": float(rel.max()),
+                              "p50_rel_err": float(np.median(rel)), "bar": 1e-4,
+                              "pass": bool(rel.max() <= 1e-4)}
+
+    if not args.no_direct:
+        print("bench: all-pairs GPU direct sum on sampled targets", file=sys.stderr, flush=True)
+        ti = np.nonzero(wl.a > 0)[0]
+        si = np.nonzero(wl.w > 0)[0]
+        k = min(ti.size, 131072)
+        ts = ti[synth.sample_indices(ti.size, k, seed=778)]
+        dtx, dty, dtz = T(wl.x[ts]), T(wl.y[ts]), T(wl.z[ts])
+        dsx, dsy, dsz, dsw = T(wl.x[si]), T(wl.y[si]), T(wl.z[si]), T(wl.w[si])
+        ud = msp.direct_sum(dtx, dty, dtz, dsx, dsy, dsz, dsw, wl.sigma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        msp.direct_sum(dtx, dty, dtz, dsx, dsy, dsz, dsw, wl.sigma, out=ud)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dsum = k / dt
+        result["direct_gpu"] = {"sums_per_s": dsum, "targets_timed": k, "sources": int(si.size),
+                                "pairs_per_s": k * si.size / dt,
+                                "speedup_fmm_incl_tree": value / dsum,
+                                "speedup_fmm_cached_tree": result["forward_only_sums_per_s"] / dsum}
+
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        ti = np.nonzero(wl.a > 0)[0]
+        probe = ti[synth.sample_indices(ti.size, 4, seed=779)]
+        t0 = time.perf_counter()
+        oracle.attraction(wl, probe, threads=threads)
+        per = (time.perf_counter() - t0) / probe.size
+        k = int(max(4, min(ti.size, args.cpu_seconds / max(per, 1e-9))))
+        cs = ti[synth.sample_indices(ti.size, k, seed=780)]
+        print(f"bench: oracle on {k} targets x {n_src} sources, {threads} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        oracle.attraction(wl, cs, threads=threads)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": k / dt, "unit": "sums/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"{k} seeded targets of the slab, each summed over all "
+                                            f"{n_src} sources in FP64 ({dt:.1f} s)"}
+    tree.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

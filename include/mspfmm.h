@@ -1,0 +1,209 @@
+/*
+ * mspfmm: Gaussian attraction sums of the Model of Structural Plasticity on one
+ * AMD Instinct MI355X (gfx950), evaluated by an octree fast Gauss transform.
+ *
+ * The quantity is the n-body sum of the paper's section "Mathematical
+ * Formulation of the Fast Multipole Method" (Eq. (2)) with the Gaussian kernel
+ * of the direct evaluation in the algorithm section (Eq. (8)):
+ *
+ *     u(t_i) = sum_j w_j exp(-|t_i - s_j|^2 / sigma^2)
+ *
+ * t_i runs over targets (neurons with vacant axons), s_j over sources (neurons
+ * with vacant dendrites, w_j = number of vacant dendrites).  One point set holds
+ * both roles: a neuron is a target if its is_target flag is set and a source
+ * if its weight is non-zero.  The per-neuron attraction is a_i * u(t_i) with a_i
+ * the number of vacant axons; forming that product is left to the caller.
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers on the current HIP device unless a
+ *     comment says "host".  The caller owns them; the library never frees or
+ *     retains them beyond the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it.  Calls return before the GPU finishes except where a
+ *     comment says the call synchronises the stream.
+ *   - Internal device memory (sorted copies, node table, expansion grids,
+ *     interaction lists) belongs to the msp_tree handle: allocated on demand,
+ *     reused by later calls, released by msp_tree_destroy.  A handle must not be
+ *     used from two host threads at once, and two calls on one handle must use
+ *     the same stream (or be ordered by the caller).
+ *   - Return value: MSP_OK (0) or a negative MSP_E* code; msp_last_error()
+ *     then gives a human-readable reason (thread-local).  No C++ exception
+ *     crosses this interface.
+ *   - Positions are float32 micrometres (any unit works if sigma uses it).
+ *     Indices are int32, so n < 2^31.
+ */
+#ifndef MSPFMM_H
+#define MSPFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum msp_status {
+    MSP_OK = 0,
+    MSP_EINVAL = -1,    /* bad argument: NULL pointer, size, sigma, p, flags, non-finite position */
+    MSP_ENOSPC = -2,    /* a required buffer would exceed the library's size limits */
+    MSP_EOVERFLOW = -3, /* more than 2^31-1 points or nodes */
+    MSP_EHIP = -4,      /* HIP runtime error (allocation, launch, copy) */
+    MSP_ENOTSUP = -5,   /* unsupported device or option combination */
+    MSP_ESTATE = -6     /* handle not ready (e.g. no tree built yet) */
+};
+
+enum msp_route {
+    MSP_ROUTE_AUTO = 0,   /* pick by a cost model (see msp_fgt_info.route) */
+    MSP_ROUTE_FGT = 1,    /* expansions on one level of the octree (P2M, M2L, L2P) */
+    MSP_ROUTE_DIRECT = 2  /* near-field pairs only: leaf interaction lists + P2P */
+};
+
+enum msp_flags {
+    /* Skip the pair j == i (a neuron does not attract its own axons).  The direct
+     * route skips the pair exactly; the expansion route subtracts w_i after the
+     * fact, which loses relative accuracy when u_i is close to w_i. */
+    MSP_EXCLUDE_SELF = 1u << 0
+};
+
+typedef struct msp_tree msp_tree; /* opaque handle */
+
+/* Geometry and shape of a built tree (host struct, filled by msp_tree_get_info). */
+typedef struct msp_tree_info {
+    int64_t n;              /* points */
+    int64_t n_nodes;        /* nodes, breadth-first: by level, then Morton order */
+    int32_t depth;          /* deepest level that holds a node */
+    int32_t leaf_max;
+    int32_t max_depth;
+    int32_t qmax[3];        /* largest quantised coordinate per axis (0 .. 2^21-1) */
+    double lo[3];           /* lower corner of the root cube (min over points) */
+    double side;            /* side of the root cube (max extent over axes; 1 if 0) */
+    int64_t level_offset[23]; /* first node of each level; entries past depth+1 equal n_nodes */
+} msp_tree_info;
+
+/* Device destinations for msp_tree_export; any member may be NULL (skipped).
+ * Node arrays have n_nodes entries, point arrays n entries. */
+typedef struct msp_tree_arrays {
+    uint64_t *keys;          /* sorted 63-bit Morton keys */
+    int32_t *perm;           /* perm[k] = input index of the k-th point in key order */
+    int32_t *node_level;
+    int32_t *node_first;     /* first point (key order) */
+    int32_t *node_count;     /* number of points */
+    int32_t *node_parent;    /* -1 for the root */
+    int32_t *node_first_child; /* -1 for a leaf; children are contiguous */
+    int32_t *node_n_children;
+    int32_t *node_digit;     /* octant inside the parent: (x<<2)|(y<<1)|z of the next bit */
+    int32_t *node_ix, *node_iy, *node_iz; /* lattice coordinates at the node's level */
+} msp_tree_arrays;
+
+typedef struct msp_fgt_params {
+    int32_t p;            /* expansion terms per axis, 1..16 (p^3 coefficients per box) */
+    int32_t level;        /* octree level whose cells carry expansions; -1 = choose from p, sigma, side */
+    float sigma;          /* kernel width, > 0 and finite */
+    float cutoff_sigmas;  /* direct route: sources farther than cutoff_sigmas*sigma from a target
+                             leaf's box are dropped; <= 0 means no cutoff */
+    int32_t route;        /* enum msp_route */
+    uint32_t flags;       /* enum msp_flags */
+} msp_fgt_params;
+
+/* What a forward call will do for given params (host struct). */
+typedef struct msp_fgt_info {
+    int32_t route;        /* MSP_ROUTE_FGT or MSP_ROUTE_DIRECT after resolving AUTO */
+    int32_t level;        /* expansion level (FGT route) */
+    int32_t grid[3];      /* cells per axis on that level (bounding box of occupied cells) */
+    int32_t p;
+    double rho;           /* cell half-side / sigma on that level */
+    double fgt_cost;      /* cost-model estimates (arbitrary units, same scale) */
+    double direct_cost;
+} msp_fgt_info;
+
+/* Status text for a code (static string). */
+const char *msp_status_string(int status);
+/* Reason for the last failure on this host thread (empty if none). */
+const char *msp_last_error(void);
+
+/* Create / destroy a handle.  Destroy synchronises the device before freeing. */
+int msp_tree_create(msp_tree **out);
+void msp_tree_destroy(msp_tree *t);
+
+/* Build the adaptive octree of the points (section "A Distributed Octree": a cell
+ * is split into its non-empty octants while it holds more than leaf_max points
+ * and its level is below max_depth).  Root cube: lower corner = per-axis minimum,
+ * side = largest per-axis extent.  Each coordinate is quantised to 21 bits as
+ * min(floor((x - lo) * (2^21 / side)), 2^21 - 1) in float64 and the three are
+ * interleaved (x highest within each 3-bit digit) into a 63-bit key; points are
+ * stably sorted by key.  x, y, z: device float32[n], input order.  leaf_max >= 1,
+ * 0 <= max_depth <= 21, 0 <= n < 2^31.  Synchronises `stream` twice (root cube,
+ * node count).  Replaces any tree held by the handle. */
+int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
+                     int32_t leaf_max, int32_t max_depth, void *stream);
+
+/* Host copy of the tree's geometry and shape. */
+int msp_tree_get_info(const msp_tree *t, msp_tree_info *info);
+
+/* Copy the sorted keys, permutation and node table into caller buffers (device). */
+int msp_tree_export(const msp_tree *t, const msp_tree_arrays *dst, void *stream);
+
+/* Resolve route and level for params without running anything. */
+int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info);
+
+/* u_out[i] = u(t_i) for every point i with is_target[i] != 0, and 0 for the others.
+ * w: device float32[n] source weights (0 = not a source; any finite value works,
+ * the sum is linear in w).  is_target: device uint8[n], or NULL for all points.
+ * u_out: device float32[n].  All in input order.
+ * FGT route: moments (Eq. (7)) of the sources in every cell of one octree level,
+ * Hermite-to-Taylor translation between every pair of cells of that level (the
+ * transform the paper's Eqs. (6)-(7) combine), and evaluation of each cell's
+ * Taylor series (Eq. (6)) at its targets.  Direct route: Eq. (8) summed over all
+ * source leaves within the cutoff of each target leaf.  The direct route
+ * synchronises `stream` once when its interaction lists are (re)built. */
+int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
+                    const msp_fgt_params *prm, float *u_out, void *stream);
+
+/* All-pairs direct sum on the GPU, Eq. (8), no tree and no cutoff (the baseline
+ * that the transform is measured against).  Targets tx,ty,tz: device float32[nt];
+ * sources sx,sy,sz,w: device float32[ns]; u: device float32[nt].  The sum over
+ * sources is accumulated in float32 per tile of 1024 sources with compensated
+ * addition of the tile sums. */
+int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
+                   const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
+                   float *u, void *stream);
+
+/* Child probabilities for proportional partner choice (Algorithm 2).  For query q
+ * (target point target_idx[q], an input index, and tree node node_id[q]) the
+ * attraction of child c of that node is S_c = sum_{j below c} w_j K(t, s_j), and
+ * probs[8*q + octant(c)] = S_c / sum_c' S_c' (0 for absent children).  Children
+ * far enough for an expansion to meet the accuracy of `prm->p` are evaluated from
+ * their Hermite moments (Eq. (7)), the rest directly (Eq. (8)).  If `uniforms`
+ * (device float32[nq] in [0,1)) is non-NULL, choice[q] receives the node id of
+ * the first child, in octant order, whose running sum of S exceeds
+ * uniforms[q] * total, or -1 when the total is 0 or the node is a leaf.
+ * prm->flags & MSP_EXCLUDE_SELF skips the query's own point.  probs: device
+ * float32[8*nq]; choice: device int32[nq] or NULL. */
+int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
+                              const int32_t *target_idx, const int32_t *node_id, int64_t nq,
+                              const float *uniforms, float *probs, int32_t *choice, void *stream);
+
+/* Copy an internal buffer of the last expansion-route forward call, for
+ * pass-level checks.  which: 0 = Hermite moment grid after P2M, 1 = Taylor grid
+ * after M2L.  Layout of both: float32 [kz][az][ky][ay][kx][ax], with (kx,ky,kz)
+ * the cell's lattice coordinates inside the grid reported by msp_fgt_plan and
+ * (ax,ay,az) the coefficient multi-index (p values each).  *bytes receives the
+ * buffer size; if dst (device) is non-NULL and dst_bytes >= *bytes the buffer is
+ * copied there on `stream`, otherwise MSP_EINVAL (dst non-NULL but too small). */
+int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
+                         void *stream);
+
+/* Per-phase GPU timing.  When enabled, the library records a pair of HIP events
+ * around each phase it launches on the caller's stream; msp_tree_get_timing
+ * waits for them and returns, per phase, the summed milliseconds and the number
+ * of launches since the last reset.  Phase names come from msp_phase_name. */
+enum { MSP_PHASE_COUNT = 24 };
+int msp_tree_set_timing(msp_tree *t, int enable);
+int msp_tree_get_timing(msp_tree *t, double *ms /* host [MSP_PHASE_COUNT] */,
+                        int64_t *launches /* host [MSP_PHASE_COUNT] */, int reset);
+const char *msp_phase_name(int phase);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSPFMM_H */

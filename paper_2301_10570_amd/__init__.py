@@ -1,0 +1,258 @@
+"""Python binding of libmspfmm (include/mspfmm.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of the shared library;
+this module checks tensors, passes their device pointers and the current torch
+stream, and turns status codes into exceptions.  PyTorch supplies device memory
+and streams.  The library must have been built (python -m
+paper_2301_10570_amd.build); importing without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmspfmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mspfmm.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2301_10570_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MSP_OK, MSP_EINVAL, MSP_ENOSPC, MSP_EOVERFLOW, MSP_EHIP, MSP_ENOTSUP, MSP_ESTATE = 0, -1, -2, -3, -4, -5, -6
+ROUTES = {"auto": 0, "fgt": 1, "direct": 2}
+ROUTE_NAMES = {v: k for k, v in ROUTES.items()}
+EXCLUDE_SELF = 1
+
+
+class MspError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.msp_last_error().decode(errors="replace")
+        status = _lib.msp_status_string(code).decode()
+        super().__init__(f"{where}: {status} ({code}): {msg}")
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("qmax", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double),
+                ("level_offset", ctypes.c_int64 * 23)]
+
+
+class TreeArrays(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("keys", "perm", "node_level", "node_first", "node_count", "node_parent",
+                 "node_first_child", "node_n_children", "node_digit", "node_ix", "node_iy", "node_iz")]
+
+
+class FgtParams(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("level", ctypes.c_int32), ("sigma", ctypes.c_float),
+                ("cutoff_sigmas", ctypes.c_float), ("route", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FgtInfo(ctypes.Structure):
+    _fields_ = [("route", ctypes.c_int32), ("level", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
+                ("p", ctypes.c_int32), ("rho", ctypes.c_double), ("fgt_cost", ctypes.c_double),
+                ("direct_cost", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_lib.msp_status_string.restype = ctypes.c_char_p
+_lib.msp_status_string.argtypes = [ctypes.c_int]
+_lib.msp_last_error.restype = ctypes.c_char_p
+_lib.msp_last_error.argtypes = []
+_lib.msp_tree_create.argtypes = [ctypes.POINTER(_vp)]
+_lib.msp_tree_destroy.argtypes = [_vp]
+_lib.msp_tree_destroy.restype = None
+_lib.msp_octree_build.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp]
+_lib.msp_tree_get_info.argtypes = [_vp, ctypes.POINTER(TreeInfo)]
+_lib.msp_tree_export.argtypes = [_vp, ctypes.POINTER(TreeArrays), _vp]
+_lib.msp_fgt_plan.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(FgtInfo)]
+_lib.msp_fgt_forward.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp]
+_lib.msp_direct_sum.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
+_lib.msp_partner_probabilities.argtypes = [_vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _i64, _vp,
+                                           _vp, _vp, _vp]
+_lib.msp_fgt_debug_buffer.argtypes = [_vp, _i32, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), _vp]
+_lib.msp_tree_set_timing.argtypes = [_vp, ctypes.c_int]
+_lib.msp_tree_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]
+_lib.msp_phase_name.restype = ctypes.c_char_p
+_lib.msp_phase_name.argtypes = [ctypes.c_int]
+PHASE_COUNT = 24
+for _f in ("msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
+           "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
+           "msp_fgt_debug_buffer"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/mspfmm.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(msp_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc: int, where: str):
+    if rc != MSP_OK:
+        raise MspError(rc, where)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None, dtype: torch.dtype, n: int | None, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr() if t.numel() else None
+
+
+def _params(sigma, p, level, route, cutoff_sigmas, exclude_self) -> FgtParams:
+    return FgtParams(int(p), int(level), float(sigma), float(cutoff_sigmas),
+                     ROUTES[route] if isinstance(route, str) else int(route),
+                     EXCLUDE_SELF if exclude_self else 0)
+
+
+class Tree:
+    """An octree built on the GPU (owns the library handle and its device memory)."""
+
+    def __init__(self):
+        h = _vp()
+        _check(_lib.msp_tree_create(ctypes.byref(h)), "msp_tree_create")
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.msp_tree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, x, y, z, leaf_max=64, max_depth=21):
+        n = x.numel()
+        px, py, pz = (_ptr(v, torch.float32, n, nm) for v, nm in ((x, "x"), (y, "y"), (z, "z")))
+        _check(_lib.msp_octree_build(self._h, px, py, pz, n, int(leaf_max), int(max_depth), _stream()),
+               "msp_octree_build")
+        self.n = n
+        self._keep = (x, y, z)
+        return self
+
+    def info(self) -> dict:
+        inf = TreeInfo()
+        _check(_lib.msp_tree_get_info(self._h, ctypes.byref(inf)), "msp_tree_get_info")
+        return {"n": inf.n, "n_nodes": inf.n_nodes, "depth": inf.depth, "leaf_max": inf.leaf_max,
+                "max_depth": inf.max_depth, "qmax": list(inf.qmax), "lo": list(inf.lo), "side": inf.side,
+                "level_offset": list(inf.level_offset)}
+
+    def export(self) -> dict:
+        inf = self.info()
+        n, nn = inf["n"], inf["n_nodes"]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = {"keys": torch.empty(n, dtype=torch.int64, device=dev),
+               "perm": torch.empty(n, dtype=torch.int32, device=dev)}
+        for k in ("node_level", "node_first", "node_count", "node_parent", "node_first_child",
+                  "node_n_children", "node_digit", "node_ix", "node_iy", "node_iz"):
+            out[k] = torch.empty(nn, dtype=torch.int32, device=dev)
+        arr = TreeArrays(*[out[f[0]].data_ptr() if out[f[0]].numel() else None for f in TreeArrays._fields_])
+        _check(_lib.msp_tree_export(self._h, ctypes.byref(arr), _stream()), "msp_tree_export")
+        return out
+
+    def plan(self, sigma, p=8, level=-1, route="auto", cutoff_sigmas=4.5, exclude_self=False) -> dict:
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+        inf = FgtInfo()
+        _check(_lib.msp_fgt_plan(self._h, ctypes.byref(prm), ctypes.byref(inf)), "msp_fgt_plan")
+        return {"route": ROUTE_NAMES[inf.route], "level": inf.level, "grid": list(inf.grid), "p": inf.p,
+                "rho": inf.rho, "fgt_cost": inf.fgt_cost, "direct_cost": inf.direct_cost}
+
+    def forward(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
+                exclude_self=False, out=None):
+        """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere."""
+        n = self.n
+        pw = _ptr(w, torch.float32, n, "w")
+        pt = _ptr(is_target, torch.uint8, n, "is_target")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=w.device)
+        po = _ptr(out, torch.float32, n, "out")
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+        _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
+        return out
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around every library phase on the caller's stream."""
+        _check(_lib.msp_tree_set_timing(self._h, 1 if enable else 0), "msp_tree_set_timing")
+
+    def timing(self, reset: bool = True) -> dict:
+        """{phase: (total ms, launches)} for phases that ran since the last reset."""
+        ms = (ctypes.c_double * PHASE_COUNT)()
+        cnt = (_i64 * PHASE_COUNT)()
+        _check(_lib.msp_tree_get_timing(self._h, ms, cnt, 1 if reset else 0), "msp_tree_get_timing")
+        out = {}
+        for k in range(PHASE_COUNT):
+            if cnt[k]:
+                out[_lib.msp_phase_name(k).decode()] = (ms[k], int(cnt[k]))
+        return out
+
+    def debug_buffer(self, which: int) -> torch.Tensor:
+        """Copy of the moment grid (0) or Taylor grid (1) of the last expansion-route call."""
+        nbytes = ctypes.c_size_t()
+        _check(_lib.msp_fgt_debug_buffer(self._h, int(which), None, 0, ctypes.byref(nbytes), None),
+               "msp_fgt_debug_buffer")
+        out = torch.empty(nbytes.value // 4, dtype=torch.float32, device="cuda")
+        _check(_lib.msp_fgt_debug_buffer(self._h, int(which), out.data_ptr(), nbytes.value,
+                                         ctypes.byref(nbytes), _stream()), "msp_fgt_debug_buffer")
+        return out
+
+    def partner_probabilities(self, w, target_idx, node_id, sigma, p=8, uniforms=None,
+                              exclude_self=False, level=-1, cutoff_sigmas=4.5):
+        nq = target_idx.numel()
+        pw = _ptr(w, torch.float32, self.n, "w")
+        pti = _ptr(target_idx, torch.int32, nq, "target_idx")
+        pni = _ptr(node_id, torch.int32, nq, "node_id")
+        pu = _ptr(uniforms, torch.float32, nq, "uniforms")
+        probs = torch.empty(nq * 8, dtype=torch.float32, device=w.device)
+        choice = torch.empty(nq, dtype=torch.int32, device=w.device)
+        prm = _params(sigma, p, level, "auto", cutoff_sigmas, exclude_self)
+        _check(_lib.msp_partner_probabilities(self._h, pw, ctypes.byref(prm), pti, pni, nq, pu,
+                                              probs.data_ptr() if nq else None,
+                                              choice.data_ptr() if nq else None, _stream()),
+               "msp_partner_probabilities")
+        return probs.view(nq, 8), choice
+
+
+def build_tree(x, y, z, leaf_max=64, max_depth=21) -> Tree:
+    return Tree().build(x, y, z, leaf_max, max_depth)
+
+
+def direct_sum(tx, ty, tz, sx, sy, sz, w, sigma, out=None):
+    """All-pairs GPU direct sum (no tree, no cutoff)."""
+    nt, ns = tx.numel(), sx.numel()
+    ptrs_t = [_ptr(v, torch.float32, nt, nm) for v, nm in ((tx, "tx"), (ty, "ty"), (tz, "tz"))]
+    ptrs_s = [_ptr(v, torch.float32, ns, nm) for v, nm in ((sx, "sx"), (sy, "sy"), (sz, "sz"), (w, "w"))]
+    if out is None:
+        out = torch.empty(nt, dtype=torch.float32, device=tx.device)
+    po = _ptr(out, torch.float32, nt, "out")
+    _check(_lib.msp_direct_sum(*ptrs_t, nt, *ptrs_s[:3], ptrs_s[3], ns, float(sigma), po, _stream()),
+           "msp_direct_sum")
+    return out

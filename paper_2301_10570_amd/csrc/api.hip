@@ -1,0 +1,303 @@
+// C-ABI entry points declared in include/mspfmm.h: argument checks, handle
+// management, and the order of the steps of a forward call.
+#include "internal.hpp"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+namespace msp {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int DevBuf::ensure(size_t need) {
+    if (need == 0) need = 1;
+    if (need <= bytes) return MSP_OK;
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) return fail(MSP_EHIP, "hipFree: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(MSP_EHIP, "hipMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+    }
+    bytes = need;
+    return MSP_OK;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+hipEvent_t Timing::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void Timing::resolve() {
+    for (const Rec &r : pending) {
+        float ms_ = 0.f;
+        (void)hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms_, r.a, r.b) == hipSuccess) {
+            ms[r.phase] += ms_;
+            launches[r.phase] += 1;
+        }
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+}
+
+Timing::~Timing() {
+    for (const Rec &r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+static int check_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MSP_EHIP, "no HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(MSP_EHIP, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MSP_ENOTSUP, "device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
+    return MSP_OK;
+}
+
+static int check_params(const msp_fgt_params *prm) {
+    if (!prm) return fail(MSP_EINVAL, "params is NULL");
+    if (prm->p < 1 || prm->p > kMaxP) return fail(MSP_EINVAL, "p = %d outside 1..%d", prm->p, kMaxP);
+    if (!(prm->sigma > 0.f) || !std::isfinite(prm->sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
+    if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
+    if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
+    if (prm->flags & ~(uint32_t)MSP_EXCLUDE_SELF) return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (std::isnan(prm->cutoff_sigmas)) return fail(MSP_EINVAL, "cutoff_sigmas is NaN");
+    return MSP_OK;
+}
+
+}  // namespace msp
+
+msp_tree::~msp_tree() {
+    for (msp::DevBuf *b : {&keys, &perm, &xs, &ys, &zs, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
+                           &nnchild, &ndigit, &nix, &niy, &niz, &d_level_off, &keys2, &perm2, &hist,
+                           &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &ws, &tflag, &usort,
+                           &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
+                           &node_wsum})
+        b->release();
+}
+
+using namespace msp;
+
+extern "C" {
+
+const char *msp_status_string(int status) {
+    switch (status) {
+        case MSP_OK: return "ok";
+        case MSP_EINVAL: return "invalid argument";
+        case MSP_ENOSPC: return "size limit exceeded";
+        case MSP_EOVERFLOW: return "index overflow";
+        case MSP_EHIP: return "HIP runtime error";
+        case MSP_ENOTSUP: return "not supported";
+        case MSP_ESTATE: return "handle not ready";
+    }
+    return "unknown status";
+}
+
+const char *msp_last_error(void) { return g_err; }
+
+int msp_tree_create(msp_tree **out) {
+    if (!out) return fail(MSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    MSP_TRY(check_device());
+    msp_tree *t = new (std::nothrow) msp_tree();
+    if (!t) return fail(MSP_ENOSPC, "host allocation failed");
+    (void)hipGetDevice(&t->device);
+    *out = t;
+    return MSP_OK;
+}
+
+void msp_tree_destroy(msp_tree *t) {
+    if (!t) return;
+    (void)hipDeviceSynchronize();
+    delete t;
+}
+
+int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
+                     int32_t leaf_max, int32_t max_depth, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (n < 0) return fail(MSP_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "n = %lld exceeds 2^31-1", (long long)n);
+    if (n > 0 && (!x || !y || !z)) return fail(MSP_EINVAL, "NULL coordinate array");
+    if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    return build_tree(t, x, y, z, n, leaf_max, max_depth, (hipStream_t)stream);
+}
+
+int msp_tree_get_info(const msp_tree *t, msp_tree_info *info) {
+    if (!t || !info) return fail(MSP_EINVAL, "NULL argument");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    std::memset(info, 0, sizeof(*info));
+    info->n = t->n;
+    info->n_nodes = t->n_nodes;
+    info->depth = t->depth;
+    info->leaf_max = t->leaf_max;
+    info->max_depth = t->max_depth;
+    for (int k = 0; k < 3; ++k) {
+        info->qmax[k] = t->geo.qmax[k];
+        info->lo[k] = t->geo.lo[k];
+    }
+    info->side = t->geo.side;
+    for (int l = 0; l < kMaxLevels; ++l) info->level_offset[l] = t->level_off[l];
+    return MSP_OK;
+}
+
+int msp_tree_export(const msp_tree *t, const msp_tree_arrays *d, void *stream) {
+    if (!t || !d) return fail(MSP_EINVAL, "NULL argument");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)t->n, nn = (size_t)t->n_nodes;
+    struct Item { void *dst; const DevBuf *src; size_t bytes; };
+    const Item items[] = {
+        {d->keys, &t->keys, nb * 8},          {d->perm, &t->perm, nb * 4},
+        {d->node_level, &t->nlevel, nn * 4},  {d->node_first, &t->nfirst, nn * 4},
+        {d->node_count, &t->ncount, nn * 4},  {d->node_parent, &t->nparent, nn * 4},
+        {d->node_first_child, &t->nfchild, nn * 4}, {d->node_n_children, &t->nnchild, nn * 4},
+        {d->node_digit, &t->ndigit, nn * 4},  {d->node_ix, &t->nix, nn * 4},
+        {d->node_iy, &t->niy, nn * 4},        {d->node_iz, &t->niz, nn * 4},
+    };
+    for (const Item &it : items)
+        if (it.dst && it.bytes) MSP_HIP(hipMemcpyAsync(it.dst, it.src->p, it.bytes, hipMemcpyDeviceToDevice, s));
+    return MSP_OK;
+}
+
+int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info) {
+    if (!t || !info) return fail(MSP_EINVAL, "NULL argument");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    FgtPlan pl;
+    MSP_TRY(plan_fgt(t, prm, &pl));
+    info->route = pl.route;
+    info->level = pl.level;
+    for (int k = 0; k < 3; ++k) info->grid[k] = pl.G[k];
+    info->p = pl.p;
+    info->rho = pl.rho;
+    info->fgt_cost = pl.fgt_cost;
+    info->direct_cost = pl.direct_cost;
+    return MSP_OK;
+}
+
+int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
+                    const msp_fgt_params *prm, float *u_out, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (t->n > 0 && (!w || !u_out)) return fail(MSP_EINVAL, "NULL weight or output array");
+    hipStream_t s = (hipStream_t)stream;
+    FgtPlan pl;
+    MSP_TRY(plan_fgt(t, prm, &pl));
+    MSP_TRY(stage_inputs(t, w, is_target, s));
+    const bool excl = (prm->flags & MSP_EXCLUDE_SELF) != 0;
+    if (pl.route == MSP_ROUTE_FGT) {
+        MSP_TRY(fgt_forward_grid(t, pl, prm, s));
+        return scatter_output(t, u_out, prm->flags, excl, s);
+    }
+    MSP_TRY(direct_route(t, prm, s));
+    return scatter_output(t, u_out, prm->flags, false, s);
+}
+
+int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
+                   const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
+                   float *u, void *stream) {
+    g_err[0] = 0;
+    if (nt < 0 || ns < 0) return fail(MSP_EINVAL, "negative size");
+    if (nt > 0x7fffffffLL || ns > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "size exceeds 2^31-1");
+    if (nt > 0 && (!tx || !ty || !tz || !u)) return fail(MSP_EINVAL, "NULL target array");
+    if (ns > 0 && (!sx || !sy || !sz || !w)) return fail(MSP_EINVAL, "NULL source array");
+    if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
+    MSP_TRY(check_device());
+    return direct_all_pairs(tx, ty, tz, nt, sx, sy, sz, w, ns, sigma, u, (hipStream_t)stream);
+}
+
+int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
+                              const int32_t *target_idx, const int32_t *node_id, int64_t nq,
+                              const float *uniforms, float *probs, int32_t *choice, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (nq < 0) return fail(MSP_EINVAL, "nq < 0");
+    if (nq > 0 && (!w || !target_idx || !node_id || !probs)) return fail(MSP_EINVAL, "NULL array");
+    if (nq > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "nq exceeds 2^31-1");
+    return partner_probabilities(t, w, prm, target_idx, node_id, nq, uniforms, probs, choice,
+                                 (hipStream_t)stream);
+}
+
+int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
+                         void *stream) {
+    if (!t || !bytes) return fail(MSP_EINVAL, "NULL argument");
+    if (which != 0 && which != 1) return fail(MSP_EINVAL, "which must be 0 or 1");
+    if (t->grid_bytes_valid <= 0) return fail(MSP_ESTATE, "no expansion-route call yet");
+    *bytes = (size_t)t->grid_bytes_valid;
+    if (!dst) return MSP_OK;
+    if (dst_bytes < *bytes) return fail(MSP_EINVAL, "destination holds %zu bytes, need %zu", dst_bytes, *bytes);
+    MSP_HIP(hipMemcpyAsync(dst, which == 0 ? t->gridA.p : t->gridB.p, *bytes, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return MSP_OK;
+}
+
+int msp_tree_set_timing(msp_tree *t, int enable) {
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    t->timing.on = enable != 0;
+    return MSP_OK;
+}
+
+int msp_tree_get_timing(msp_tree *t, double *ms, int64_t *launches, int reset) {
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    t->timing.resolve();
+    for (int k = 0; k < MSP_PHASE_COUNT; ++k) {
+        if (ms) ms[k] = t->timing.ms[k];
+        if (launches) launches[k] = t->timing.launches[k];
+        if (reset) { t->timing.ms[k] = 0.0; t->timing.launches[k] = 0; }
+    }
+    return MSP_OK;
+}
+
+const char *msp_phase_name(int phase) {
+    static const char *names[PH_COUNT_] = {"bbox", "morton", "radix_sort", "node_levels", "node_table",
+                                           "gather_sorted", "stage", "m2l_operators", "p2m", "m2l_x",
+                                           "m2l_y", "m2l_z", "l2p", "interaction_lists", "p2p",
+                                           "scatter", "node_moments", "partner", "direct"};
+    if (phase < 0 || phase >= PH_COUNT_) return "";
+    return names[phase];
+}
+
+}  // extern "C"

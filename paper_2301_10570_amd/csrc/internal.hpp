@@ -1,0 +1,231 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mspfmm.h"
+
+namespace msp {
+
+constexpr int kDepth = 21;                    // levels resolved by a 63-bit key
+constexpr uint32_t kQMax = (1u << kDepth) - 1;
+constexpr int kMaxLevels = kDepth + 2;        // level_offset entries
+constexpr int kMaxP = 16;
+
+// Thread-local error text, set by fail().
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+#define MSP_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::msp::fail(MSP_EHIP, "%s failed: %s (%s:%d)", #expr,               \
+                               hipGetErrorString(e_), __FILE__, __LINE__);             \
+    } while (0)
+
+#define MSP_CHECK_LAUNCH() MSP_HIP(hipGetLastError())
+
+#define MSP_TRY(expr)                \
+    do {                             \
+        int rc_ = (expr);            \
+        if (rc_ != MSP_OK) return rc_; \
+    } while (0)
+
+// A grow-only device allocation owned by a handle.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Parameters that kernels need about the tree's geometry.
+struct Geometry {
+    double lo[3];
+    double side;
+    double scale;   // 2^21 / side
+    int32_t qmax[3];
+};
+
+enum Phase {
+    PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
+    PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
+    PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_COUNT_
+};
+static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
+
+// Pairs of events recorded around library phases when timing is on.
+struct Timing {
+    bool on = false;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[MSP_PHASE_COUNT] = {};
+    int64_t launches[MSP_PHASE_COUNT] = {};
+    hipEvent_t get();
+    void resolve();
+    ~Timing();
+};
+
+// Records the start of a phase on construction and its end on destruction.
+struct PhaseScope {
+    Timing *tm;
+    hipStream_t s;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseScope(Timing *tm_, int ph, hipStream_t s_) : tm(tm_), s(s_), phase(ph) {
+        if (tm && tm->on) { a = tm->get(); (void)hipEventRecord(a, s); }
+    }
+    ~PhaseScope() {
+        if (tm && tm->on && a) {
+            hipEvent_t b = tm->get();
+            (void)hipEventRecord(b, s);
+            tm->pending.push_back({phase, a, b});
+        }
+    }
+};
+
+}  // namespace msp
+
+struct msp_tree {
+    msp::Timing timing;
+    int device = -1;
+    bool built = false;
+    int64_t n = 0;
+    int32_t leaf_max = 0, max_depth = 0, depth = 0;
+    int64_t n_nodes = 0;
+    int64_t level_off[msp::kMaxLevels] = {};
+    msp::Geometry geo{};
+
+    // points in key order
+    msp::DevBuf keys, perm, xs, ys, zs;
+    // node table (SoA, int32)
+    msp::DevBuf nlevel, nfirst, ncount, nparent, nfchild, nnchild, ndigit, nix, niy, niz;
+    msp::DevBuf d_level_off;  // int64[kMaxLevels] on the device
+
+    // build scratch
+    msp::DevBuf keys2, perm2, hist, tmp_a, tmp_b, tmp_c, dlev, llev, blkcnt, bbox;
+
+    // per-call staging
+    msp::DevBuf ws, tflag, usort;
+    // expansion grids and translation operators
+    msp::DevBuf gridA, gridB, ops;
+    int64_t grid_bytes_valid = 0;
+    // direct-route interaction lists (cached per sigma/cutoff)
+    msp::DevBuf list_off, list_idx, list_cnt;
+    int64_t list_total = 0;
+    float list_sigma = -1.f, list_cutoff = -2.f;
+    bool lists_valid = false;
+    // node moments for partner queries
+    msp::DevBuf nodeA, node_hasA, node_wsum;
+
+    ~msp_tree();
+};
+
+namespace msp {
+
+// tree.hip
+int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
+               int max_depth, hipStream_t s);
+
+// fgt.hip
+struct FgtPlan {
+    int route;
+    int level;
+    int p;
+    int G[3];
+    double rho;
+    double cell;      // cell side at `level`
+    double fgt_cost, direct_cost;
+};
+int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
+double rho_max_for_p(int p);
+int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s);
+int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, hipStream_t s);
+int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s);
+
+// p2p.hip
+int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
+int direct_all_pairs(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
+                     const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
+                     float *u, hipStream_t s);
+
+// partner.hip
+int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
+                          const int32_t *target_idx, const int32_t *node_id, int64_t nq,
+                          const float *uniforms, float *probs, int32_t *choice, hipStream_t s);
+
+// helpers
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace msp
+
+// ---------------------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------------------
+namespace msp {
+
+// Spread the low 21 bits of v so that bit b lands at bit 3b.
+__host__ __device__ inline uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Inverse of spread3: gather every third bit starting at bit 0.
+__host__ __device__ inline uint32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
+__host__ __device__ inline uint64_t morton3(uint32_t qx, uint32_t qy, uint32_t qz) {
+    return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
+// First index in [lo, hi) with keys[idx] >= v.
+__device__ inline int64_t lower_bound_u64(const uint64_t *keys, int64_t lo, int64_t hi, uint64_t v) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// First index in [lo, hi) with a[idx] >= v (int32 array).
+__device__ inline int64_t lower_bound_i32(const int32_t *a, int64_t lo, int64_t hi, int32_t v) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// First index in [lo, hi) with a[idx] > v (int32 array).
+__device__ inline int64_t upper_bound_i32(const int32_t *a, int64_t lo, int64_t hi, int32_t v) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace msp

@@ -1,0 +1,560 @@
+// Octree build on the GPU: root cube, Morton keys, stable radix sort, and the
+// adaptive node table (section "A Distributed Octree": a cell splits into its
+// non-empty octants while it holds more than leaf_max points, up to max_depth).
+//
+// The node table is produced without a level-by-level descent.  For a point i in
+// key order, the cells that contain it are nested and their point counts shrink
+// with the level, so the cells containing i that are nodes are exactly those at
+// levels 0..leaf_level(i), where leaf_level(i) = min(lambda(i) + 1, max_depth)
+// and lambda(i) is the deepest level at which i's cell holds more than leaf_max
+// points.  That cell holds more than leaf_max points iff some window of
+// leaf_max + 1 consecutive sorted keys that contains i shares its prefix, so
+// lambda(i) is a sliding-window maximum of L(j) = common-prefix level of
+// key[j] and key[j + leaf_max].  A point starts a node at level l iff it is the
+// first of its level-l cell (d(i) <= l, d from the highest differing bit of
+// key[i-1] and key[i]) and l <= leaf_level(i).  Counting those starts per level
+// gives breadth-first node order directly.
+#include "internal.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace msp {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;   // points per block in tiled passes
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        uint32_t s = lds[w];
+        if (w < wid) wbase += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wbase + x - v;
+}
+
+// ---- root cube --------------------------------------------------------------------------
+
+__global__ void k_bbox_partial(const float *x, const float *y, const float *z, int64_t n,
+                               float *part, int *bad) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int nonfinite = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!isfinite(v[k])) { nonfinite = 1; continue; }
+            mn[k] = fminf(mn[k], v[k]);
+            mx[k] = fmaxf(mx[k], v[k]);
+        }
+    }
+    __shared__ float smn[3][kBlock], smx[3][kBlock];
+    for (int k = 0; k < 3; ++k) { smn[k][threadIdx.x] = mn[k]; smx[k][threadIdx.x] = mx[k]; }
+    if (nonfinite) atomicOr(bad, 1);
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) {
+                smn[k][threadIdx.x] = fminf(smn[k][threadIdx.x], smn[k][threadIdx.x + s]);
+                smx[k][threadIdx.x] = fmaxf(smx[k][threadIdx.x], smx[k][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) { part[blockIdx.x * 6 + k] = smn[k][0]; part[blockIdx.x * 6 + 3 + k] = smx[k][0]; }
+}
+
+__global__ void k_bbox_final(const float *part, int nparts, float *out) {
+    if (threadIdx.x != 0) return;
+    float r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nparts; ++b)
+        for (int k = 0; k < 3; ++k) {
+            r[k] = fminf(r[k], part[b * 6 + k]);
+            r[3 + k] = fmaxf(r[3 + k], part[b * 6 + 3 + k]);
+        }
+    for (int k = 0; k < 6; ++k) out[k] = r[k];
+}
+
+// ---- keys ----------------------------------------------------------------------------------
+
+// q = min(floor((x - lo) * scale), 2^21 - 1) in float64: a subtraction, then a
+// multiplication, each rounded once (no contraction is possible in this form).
+__device__ inline uint32_t quantise(float v, double lo, double scale) {
+    double q = floor(((double)v - lo) * scale);
+    return q >= (double)kQMax ? kQMax : (uint32_t)q;
+}
+
+__global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, double lx,
+                         double ly, double lz, double scale, uint64_t *key, int32_t *idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = morton3(quantise(x[i], lx, scale), quantise(y[i], ly, scale), quantise(z[i], lz, scale));
+    idx[i] = (int32_t)i;
+}
+
+// ---- stable LSD radix sort of (key, index), 8 bits per pass ----------------------------------
+
+__global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist, int nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's per-block counts, and its total.
+__global__ void k_rs_digit_scan(uint32_t *hist, int nblk, uint32_t *total) {
+    __shared__ uint32_t lds[kBlock / 64];
+    uint32_t *row = hist + (int64_t)blockIdx.x * nblk;
+    const int per = (nblk + kBlock - 1) / kBlock;
+    const int b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nblk) s += row[b0 + k];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, lds, tot);
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nblk) {
+            uint32_t v = row[b0 + k];
+            row[b0 + k] = run;
+            run += v;
+        }
+    if (threadIdx.x == 0) total[blockIdx.x] = tot;
+}
+
+__global__ void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout,
+                             int64_t n, int shift, const uint32_t *hist, const uint32_t *total,
+                             int nblk) {
+    __shared__ uint32_t lds[kBlock / 64];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint32_t tot;
+    uint32_t dbase = block_exclusive_scan(total[tid], lds, tot);
+    base[tid] = dbase + hist[(int64_t)tid * nblk + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kItems; ++r) {
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        const int64_t i = tile + r * kBlock + tid;
+        const bool valid = i < n;
+        const uint64_t k = valid ? kin[i] : 0ull;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt);
+        if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d];
+            for (int w = 0; w < wid; ++w) off += wcnt[w][d];
+            const uint32_t pos = off + rank;
+            kout[pos] = k;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---- node table ------------------------------------------------------------------------------
+
+// Level of the deepest common cell of two keys (21 if equal).
+__device__ inline int common_level(uint64_t a, uint64_t b) {
+    const uint64_t x = a ^ b;
+    if (x == 0) return kDepth;
+    const int hb = 63 - __clzll((long long)x);
+    return kDepth - 1 - hb / 3;
+}
+
+// L[j] = common level of key[j] and key[j + leaf_max], j in [0, m).
+__global__ void k_window_L(const uint64_t *keys, int64_t m, int leaf_max, int8_t *L) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    L[j] = (int8_t)common_level(keys[j], keys[j + leaf_max]);
+}
+
+// Prefix / suffix maxima of L inside consecutive blocks of W entries.
+__global__ void k_window_presuf(const int8_t *L, int64_t m, int W, int8_t *pre, int8_t *suf) {
+    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t s = b * W;
+    if (s >= m) return;
+    int64_t e = s + W < m ? s + W : m;
+    int8_t run = -1;
+    for (int64_t j = s; j < e; ++j) { run = L[j] > run ? L[j] : run; pre[j] = run; }
+    run = -1;
+    for (int64_t j = e - 1; j >= s; --j) { run = L[j] > run ? L[j] : run; suf[j] = run; }
+}
+
+struct PointLevels {
+    int d;   // first level at which the point starts a cell (22: never)
+    int ll;  // level of its leaf
+};
+
+__device__ inline PointLevels point_levels(const uint64_t *keys, int64_t n, int64_t i, int leaf_max,
+                                           int max_depth, const int8_t *pre, const int8_t *suf,
+                                           int64_t m, int W) {
+    PointLevels r;
+    if (i == 0) r.d = 0;
+    else {
+        const uint64_t x = keys[i] ^ keys[i - 1];
+        r.d = (x == 0) ? kDepth + 1 : kDepth - (63 - __clzll((long long)x)) / 3;
+    }
+    int lam = -1;
+    if (m > 0) {
+        const int64_t lo = i - leaf_max > 0 ? i - leaf_max : 0;
+        const int64_t hi = i < m - 1 ? i : m - 1;
+        if (lo <= hi) {
+            if (lo / W == hi / W) lam = (lo % W == 0) ? pre[hi] : suf[lo];
+            else lam = pre[hi] > suf[lo] ? pre[hi] : suf[lo];
+        }
+    }
+    r.ll = lam + 1 < max_depth ? lam + 1 : max_depth;
+    return r;
+}
+
+__global__ void k_levels(const uint64_t *keys, int64_t n, int leaf_max, int max_depth,
+                         const int8_t *pre, const int8_t *suf, int64_t m, int W, uint8_t *dlev,
+                         uint8_t *llev, uint32_t *blkcnt, int nblk) {
+    __shared__ uint32_t cnt[kMaxLevels];
+    if (threadIdx.x < kMaxLevels) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t local[kDepth + 1];
+#pragma unroll
+    for (int l = 0; l <= kDepth; ++l) local[l] = 0;
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + k;
+        if (i >= n) break;
+        PointLevels pl = point_levels(keys, n, i, leaf_max, max_depth, pre, suf, m, W);
+        dlev[i] = (uint8_t)pl.d;
+        llev[i] = (uint8_t)pl.ll;
+#pragma unroll
+        for (int l = 0; l <= kDepth; ++l) local[l] += (pl.d <= l && l <= pl.ll) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int l = 0; l <= kDepth; ++l)
+        if (local[l]) atomicAdd(&cnt[l], local[l]);
+    __syncthreads();
+    if (threadIdx.x <= kDepth) blkcnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// One block per level: exclusive scan over blocks of that level's start counts.
+__global__ void k_level_scan(uint32_t *blkcnt, int nblk, uint32_t *total) {
+    __shared__ uint32_t lds[kBlock / 64];
+    uint32_t *row = blkcnt + (int64_t)blockIdx.x * nblk;
+    const int per = (nblk + kBlock - 1) / kBlock;
+    const int b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nblk) s += row[b0 + k];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, lds, tot);
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nblk) {
+            uint32_t v = row[b0 + k];
+            row[b0 + k] = run;
+            run += v;
+        }
+    if (threadIdx.x == 0) total[blockIdx.x] = tot;
+}
+
+__global__ void k_level_offsets(const uint32_t *total, int64_t *level_off) {
+    if (threadIdx.x != 0) return;
+    int64_t run = 0;
+    for (int l = 0; l <= kDepth; ++l) { level_off[l] = run; run += total[l]; }
+    level_off[kDepth + 1] = run;
+}
+
+__global__ void k_emit(const uint8_t *dlev, const uint8_t *llev, int64_t n, const uint32_t *blkoff,
+                       int nblk, const int64_t *level_off, int32_t *nfirst, int32_t *nlevel) {
+    __shared__ uint32_t lds[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint8_t d[kItems], ll[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + k;
+        d[k] = i < n ? dlev[i] : (uint8_t)255;
+        ll[k] = i < n ? llev[i] : (uint8_t)0;
+    }
+    for (int l = 0; l <= kDepth; ++l) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) c += (d[k] <= l && l <= ll[k]) ? 1u : 0u;
+        uint32_t tot;
+        uint32_t r = block_exclusive_scan(c, lds, tot);
+        if (tot == 0) continue;
+        int64_t pos = level_off[l] + blkoff[(int64_t)l * nblk + blockIdx.x] + r;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (d[k] <= l && l <= ll[k]) {
+                nfirst[pos] = (int32_t)(base + k);
+                nlevel[pos] = l;
+                ++pos;
+            }
+    }
+}
+
+__global__ void k_nodes(const uint64_t *keys, int64_t n, const uint8_t *llev, int64_t n_nodes,
+                        const int32_t *nlevel, const int32_t *nfirst, int32_t *ncount,
+                        int32_t *ndigit, int32_t *nix, int32_t *niy, int32_t *niz) {
+    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n_nodes) return;
+    const int l = nlevel[v];
+    const int64_t i = nfirst[v];
+    int64_t end = n;
+    uint64_t prefix = 0;
+    if (n > 0) {
+        const int sh = 3 * (kDepth - l);
+        prefix = l == 0 ? 0ull : (keys[i] >> sh);
+        const uint64_t next = (prefix + 1ull) << sh;
+        end = lower_bound_u64(keys, i + 1, n, next);
+    }
+    ncount[v] = (int32_t)(end - i);
+    ndigit[v] = l > 0 ? (int32_t)(prefix & 7ull) : 0;
+    nix[v] = (int32_t)compact3(prefix >> 2);
+    niy[v] = (int32_t)compact3(prefix >> 1);
+    niz[v] = (int32_t)compact3(prefix);
+}
+
+__global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *level_off,
+                        const int32_t *nlevel, const int32_t *nfirst, const int32_t *ncount,
+                        int32_t *nparent, int32_t *nfchild, int32_t *nnchild, int n_points) {
+    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n_nodes) return;
+    const int l = nlevel[v];
+    const int32_t f = nfirst[v];
+    nparent[v] = l == 0 ? -1
+                        : (int32_t)(upper_bound_i32(nfirst, level_off[l - 1], level_off[l], f) - 1);
+    const bool leaf = n_points == 0 || (int)llev[f] == l;
+    if (leaf) {
+        nfchild[v] = -1;
+        nnchild[v] = 0;
+    } else {
+        const int64_t a = lower_bound_i32(nfirst, level_off[l + 1], level_off[l + 2], f);
+        const int64_t b = lower_bound_i32(nfirst, level_off[l + 1], level_off[l + 2], f + ncount[v]);
+        nfchild[v] = (int32_t)a;
+        nnchild[v] = (int32_t)(b - a);
+    }
+}
+
+__global__ void k_gather3(const float *x, const float *y, const float *z, const int32_t *perm,
+                          int64_t n, float *xs, float *ys, float *zs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t j = perm[i];
+    xs[i] = x[j];
+    ys[i] = y[j];
+    zs[i] = z[j];
+}
+
+}  // namespace
+
+int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
+               int max_depth, hipStream_t s) {
+    t->built = false;
+    t->lists_valid = false;
+    t->n = n;
+    t->leaf_max = leaf_max;
+    t->max_depth = max_depth;
+    const int64_t nb = n > 0 ? n : 1;
+
+    // root cube
+    float box[6] = {0, 0, 0, 0, 0, 0};
+    if (n > 0) {
+        const int parts = 512;
+        MSP_TRY(t->bbox.ensure(parts * 6 * sizeof(float) + 8 * sizeof(float) + sizeof(int)));
+        float *part = t->bbox.as<float>();
+        float *out = part + parts * 6;
+        int *bad = reinterpret_cast<int *>(out + 8);
+        MSP_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+        {
+            PhaseScope ps(&t->timing, PH_BBOX, s);
+            hipLaunchKernelGGL(k_bbox_partial, dim3(parts), dim3(kBlock), 0, s, x, y, z, n, part, bad);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, parts, out);
+            MSP_CHECK_LAUNCH();
+        }
+        float host[8];
+        int hbad = 0;
+        MSP_HIP(hipMemcpyAsync(host, out, 6 * sizeof(float), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+        if (hbad) return fail(MSP_EINVAL, "msp_octree_build: non-finite coordinate in input");
+        for (int k = 0; k < 6; ++k) box[k] = host[k];
+    }
+    Geometry &g = t->geo;
+    double side = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        g.lo[k] = (double)box[k];
+        const double ext = (double)box[3 + k] - g.lo[k];
+        if (ext > side) side = ext;
+    }
+    if (side == 0.0) side = 1.0;
+    g.side = side;
+    g.scale = 2097152.0 / side;
+    for (int k = 0; k < 3; ++k) {
+        const double q = std::floor(((double)box[3 + k] - g.lo[k]) * g.scale);
+        g.qmax[k] = q >= (double)kQMax ? (int32_t)kQMax : (int32_t)q;
+    }
+
+    // keys and sort
+    MSP_TRY(t->keys.ensure(nb * 8));
+    MSP_TRY(t->keys2.ensure(nb * 8));
+    MSP_TRY(t->perm.ensure(nb * 4));
+    MSP_TRY(t->perm2.ensure(nb * 4));
+    const int nblk = (int)((n + kTile - 1) / kTile) > 0 ? (int)((n + kTile - 1) / kTile) : 1;
+    MSP_TRY(t->hist.ensure((size_t)256 * nblk * 4 + 256 * 4));
+    if (n > 0) {
+        {
+        PhaseScope ps(&t->timing, PH_KEYS, s);
+        hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
+                           g.lo[0], g.lo[1], g.lo[2], g.scale, t->keys.as<uint64_t>(),
+                           t->perm.as<int32_t>());
+        MSP_CHECK_LAUNCH();
+        }
+        PhaseScope ps(&t->timing, PH_SORT, s);
+        uint64_t *ka = t->keys.as<uint64_t>(), *kb = t->keys2.as<uint64_t>();
+        int32_t *va = t->perm.as<int32_t>(), *vb = t->perm2.as<int32_t>();
+        uint32_t *hist = t->hist.as<uint32_t>();
+        uint32_t *total = hist + (size_t)256 * nblk;
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = pass * 8;
+            hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift,
+                               hist, total, nblk);
+            MSP_CHECK_LAUNCH();
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        // after an even number of passes the result is back in keys/perm
+    }
+
+    // per-point levels and node counts per level
+    MSP_TRY(t->dlev.ensure(nb));
+    MSP_TRY(t->llev.ensure(nb));
+    MSP_TRY(t->blkcnt.ensure((size_t)kMaxLevels * nblk * 4 + kMaxLevels * 4));
+    MSP_TRY(t->d_level_off.ensure(kMaxLevels * 8));
+    const int64_t m = n - leaf_max;   // windows of leaf_max + 1 keys
+    const int W = leaf_max + 1;
+    MSP_TRY(t->tmp_a.ensure(nb));
+    MSP_TRY(t->tmp_b.ensure(nb));
+    MSP_TRY(t->tmp_c.ensure(nb));
+    int8_t *L = t->tmp_a.as<int8_t>(), *pre = t->tmp_b.as<int8_t>(), *suf = t->tmp_c.as<int8_t>();
+    uint32_t *blkcnt = t->blkcnt.as<uint32_t>();
+    uint32_t *ltot = blkcnt + (size_t)kMaxLevels * nblk;
+    if (n > 0) {
+        PhaseScope ps(&t->timing, PH_LEVELS, s);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_window_L, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s,
+                               t->keys.as<uint64_t>(), m, leaf_max, L);
+            MSP_CHECK_LAUNCH();
+            const int64_t nwb = (m + W - 1) / W;
+            hipLaunchKernelGGL(k_window_presuf, dim3(grid_for(nwb, kBlock)), dim3(kBlock), 0, s, L, m,
+                               W, pre, suf);
+            MSP_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_levels, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
+                           leaf_max, max_depth, pre, suf, m, W, t->dlev.as<uint8_t>(),
+                           t->llev.as<uint8_t>(), blkcnt, nblk);
+        MSP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_level_scan, dim3(kDepth + 1), dim3(kBlock), 0, s, blkcnt, nblk, ltot);
+        MSP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, ltot,
+                           t->d_level_off.as<int64_t>());
+        MSP_CHECK_LAUNCH();
+        MSP_HIP(hipMemcpyAsync(t->level_off, t->d_level_off.p, kMaxLevels * 8, hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+    } else {
+        // empty input: a single empty root leaf
+        t->level_off[0] = 0;
+        for (int l = 1; l < kMaxLevels; ++l) t->level_off[l] = 1;
+        MSP_HIP(hipMemcpyAsync(t->d_level_off.p, t->level_off, kMaxLevels * 8, hipMemcpyHostToDevice, s));
+    }
+    t->n_nodes = t->level_off[kDepth + 1];
+    if (t->n_nodes > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "msp_octree_build: too many nodes");
+    t->depth = 0;
+    for (int l = 0; l <= kDepth; ++l)
+        if (t->level_off[l + 1] > t->level_off[l]) t->depth = l;
+
+    const int64_t nn = t->n_nodes;
+    for (DevBuf *b : {&t->nlevel, &t->nfirst, &t->ncount, &t->nparent, &t->nfchild, &t->nnchild,
+                      &t->ndigit, &t->nix, &t->niy, &t->niz})
+        MSP_TRY(b->ensure(nn * 4));
+    {
+    PhaseScope ps_nodes(&t->timing, PH_NODES, s);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_emit, dim3(nblk), dim3(kBlock), 0, s, t->dlev.as<uint8_t>(),
+                           t->llev.as<uint8_t>(), n, blkcnt, nblk, t->d_level_off.as<int64_t>(),
+                           t->nfirst.as<int32_t>(), t->nlevel.as<int32_t>());
+        MSP_CHECK_LAUNCH();
+    } else {
+        int32_t zero = 0;
+        MSP_HIP(hipMemcpyAsync(t->nfirst.p, &zero, 4, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipMemcpyAsync(t->nlevel.p, &zero, 4, hipMemcpyHostToDevice, s));
+        MSP_HIP(hipStreamSynchronize(s));
+    }
+    hipLaunchKernelGGL(k_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, t->keys.as<uint64_t>(),
+                       n, t->llev.as<uint8_t>(), nn, t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
+                       t->ncount.as<int32_t>(), t->ndigit.as<int32_t>(), t->nix.as<int32_t>(),
+                       t->niy.as<int32_t>(), t->niz.as<int32_t>());
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_links, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, t->llev.as<uint8_t>(),
+                       nn, t->d_level_off.as<int64_t>(), t->nlevel.as<int32_t>(),
+                       t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nparent.as<int32_t>(),
+                       t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), (int)n);
+    MSP_CHECK_LAUNCH();
+    }
+
+    // sorted coordinates
+    MSP_TRY(t->xs.ensure(nb * 4));
+    MSP_TRY(t->ys.ensure(nb * 4));
+    MSP_TRY(t->zs.ensure(nb * 4));
+    if (n > 0) {
+        PhaseScope ps(&t->timing, PH_GATHER, s);
+        hipLaunchKernelGGL(k_gather3, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z,
+                           t->perm.as<int32_t>(), n, t->xs.as<float>(), t->ys.as<float>(),
+                           t->zs.as<float>());
+        MSP_CHECK_LAUNCH();
+    }
+    t->built = true;
+    return MSP_OK;
+}
+
+}  // namespace msp
