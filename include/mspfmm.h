@@ -183,13 +183,18 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
                               const int32_t *target_idx, const int32_t *node_id, int64_t nq,
                               const float *uniforms, float *probs, int32_t *choice, void *stream);
 
-/* Copy an internal buffer of the last expansion-route forward call, for
- * pass-level checks.  which: 0 = Hermite moment grid after P2M, 1 = Taylor grid
- * after M2L.  Layout of both: float32 [kz][az][ky][ay][kx][ax], with (kx,ky,kz)
- * the cell's lattice coordinates inside the grid reported by msp_fgt_plan and
- * (ax,ay,az) the coefficient multi-index (p values each).  *bytes receives the
- * buffer size; if dst (device) is non-NULL and dst_bytes >= *bytes the buffer is
- * copied there on `stream`, otherwise MSP_EINVAL (dst non-NULL but too small). */
+/* Copy an internal buffer, for pass-level checks.
+ *   which 0: Hermite moment grid after P2M of the last expansion-route forward call
+ *   which 1: Taylor grid after M2L of that call
+ *     layout of both: float32 [kz][az][ky][ay][kx][ax], with (kx,ky,kz) the cell's
+ *     lattice coordinates inside the grid reported by msp_fgt_plan and (ax,ay,az)
+ *     the coefficient multi-index (p values each);
+ *   which 2: node moments of the last partner call, float32 [node - first][az][ay][ax]
+ *     for the nodes from the first node of the moment level on (entries of nodes
+ *     without moments are unspecified);
+ *   which 3: per-node flag of that call (uint8 [n_nodes], 1 = node carries moments).
+ * *bytes receives the buffer size; if dst (device) is non-NULL and dst_bytes >= *bytes
+ * the buffer is copied there on `stream`, otherwise MSP_EINVAL (dst too small). */
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
                          void *stream);
 

@@ -215,11 +215,15 @@ class Tree:
         return out
 
     def debug_buffer(self, which: int) -> torch.Tensor:
-        """Copy of the moment grid (0) or Taylor grid (1) of the last expansion-route call."""
+        """Copy of an internal buffer: 0 moment grid, 1 Taylor grid (last expansion-route
+        forward), 2 node moments, 3 node moment flags (last partner call)."""
         nbytes = ctypes.c_size_t()
         _check(_lib.msp_fgt_debug_buffer(self._h, int(which), None, 0, ctypes.byref(nbytes), None),
                "msp_fgt_debug_buffer")
-        out = torch.empty(nbytes.value // 4, dtype=torch.float32, device="cuda")
+        if which == 3:
+            out = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        else:
+            out = torch.empty(nbytes.value // 4, dtype=torch.float32, device="cuda")
         _check(_lib.msp_fgt_debug_buffer(self._h, int(which), out.data_ptr(), nbytes.value,
                                          ctypes.byref(nbytes), _stream()), "msp_fgt_debug_buffer")
         return out

@@ -105,11 +105,11 @@ static int check_params(const msp_fgt_params *prm) {
 }  // namespace msp
 
 msp_tree::~msp_tree() {
-    for (msp::DevBuf *b : {&keys, &perm, &xs, &ys, &zs, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
+    for (msp::DevBuf *b : {&keys, &perm, &iperm, &xs, &ys, &zs, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
                            &nnchild, &ndigit, &nix, &niy, &niz, &d_level_off, &keys2, &perm2, &hist,
                            &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &ws, &tflag, &usort,
                            &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
-                           &node_wsum})
+                           &node_nsrc})
         b->release();
 }
 
@@ -264,13 +264,21 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
                          void *stream) {
     if (!t || !bytes) return fail(MSP_EINVAL, "NULL argument");
-    if (which != 0 && which != 1) return fail(MSP_EINVAL, "which must be 0 or 1");
-    if (t->grid_bytes_valid <= 0) return fail(MSP_ESTATE, "no expansion-route call yet");
-    *bytes = (size_t)t->grid_bytes_valid;
+    const void *src = nullptr;
+    if (which == 0 || which == 1) {
+        if (t->grid_bytes_valid <= 0) return fail(MSP_ESTATE, "no expansion-route call yet");
+        *bytes = (size_t)t->grid_bytes_valid;
+        src = which == 0 ? t->gridA.p : t->gridB.p;
+    } else if (which == 2 || which == 3) {
+        if (t->node_moments_level < 0) return fail(MSP_ESTATE, "no partner call yet");
+        *bytes = which == 2 ? (size_t)t->node_moments_bytes : (size_t)t->n_nodes;
+        src = which == 2 ? t->nodeA.p : t->node_hasA.p;
+    } else {
+        return fail(MSP_EINVAL, "which must be 0..3");
+    }
     if (!dst) return MSP_OK;
     if (dst_bytes < *bytes) return fail(MSP_EINVAL, "destination holds %zu bytes, need %zu", dst_bytes, *bytes);
-    MSP_HIP(hipMemcpyAsync(dst, which == 0 ? t->gridA.p : t->gridB.p, *bytes, hipMemcpyDeviceToDevice,
-                           (hipStream_t)stream));
+    MSP_HIP(hipMemcpyAsync(dst, src, *bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return MSP_OK;
 }
 

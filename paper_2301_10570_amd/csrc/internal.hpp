@@ -105,7 +105,7 @@ struct msp_tree {
     msp::Geometry geo{};
 
     // points in key order
-    msp::DevBuf keys, perm, xs, ys, zs;
+    msp::DevBuf keys, perm, iperm, xs, ys, zs;
     // node table (SoA, int32)
     msp::DevBuf nlevel, nfirst, ncount, nparent, nfchild, nnchild, ndigit, nix, niy, niz;
     msp::DevBuf d_level_off;  // int64[kMaxLevels] on the device
@@ -124,7 +124,9 @@ struct msp_tree {
     float list_sigma = -1.f, list_cutoff = -2.f;
     bool lists_valid = false;
     // node moments for partner queries
-    msp::DevBuf nodeA, node_hasA, node_wsum;
+    msp::DevBuf nodeA, node_hasA, node_nsrc;
+    int node_moments_level = -1, node_moments_p = 0;
+    int64_t node_moments_bytes = 0;
 
     ~msp_tree();
 };

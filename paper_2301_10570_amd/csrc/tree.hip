@@ -372,13 +372,14 @@ __global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *lev
 }
 
 __global__ void k_gather3(const float *x, const float *y, const float *z, const int32_t *perm,
-                          int64_t n, float *xs, float *ys, float *zs) {
+                          int64_t n, float *xs, float *ys, float *zs, int32_t *iperm) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t j = perm[i];
     xs[i] = x[j];
     ys[i] = y[j];
     zs[i] = z[j];
+    iperm[j] = (int32_t)i;
 }
 
 }  // namespace
@@ -387,6 +388,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
                int max_depth, hipStream_t s) {
     t->built = false;
     t->lists_valid = false;
+    t->node_moments_level = -1;
     t->n = n;
     t->leaf_max = leaf_max;
     t->max_depth = max_depth;
@@ -546,11 +548,12 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     MSP_TRY(t->xs.ensure(nb * 4));
     MSP_TRY(t->ys.ensure(nb * 4));
     MSP_TRY(t->zs.ensure(nb * 4));
+    MSP_TRY(t->iperm.ensure(nb * 4));
     if (n > 0) {
         PhaseScope ps(&t->timing, PH_GATHER, s);
         hipLaunchKernelGGL(k_gather3, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z,
                            t->perm.as<int32_t>(), n, t->xs.as<float>(), t->ys.as<float>(),
-                           t->zs.as<float>());
+                           t->zs.as<float>(), t->iperm.as<int32_t>());
         MSP_CHECK_LAUNCH();
     }
     t->built = true;

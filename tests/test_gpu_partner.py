@@ -1,0 +1,162 @@
+"""Child probabilities and proportional choice (Algorithm 2) vs the oracle's
+restricted FP64 direct sums on the same (bit-exact) octree."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import octree, partner
+from tests.helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _queries(tree, n, k, seed, ancestors_only=False):
+    """k (target, node) pairs: targets drawn from all points, nodes either an
+    ancestor of the target's leaf at a random level or any inner node."""
+    rng = np.random.default_rng(seed)
+    tq = rng.integers(0, n, k)
+    inner = np.nonzero(tree.is_leaf == 0)[0]
+    # leaf of every sorted position
+    leaf_of = np.empty(n, np.int64)
+    for v in np.nonzero(tree.is_leaf)[0]:
+        leaf_of[tree.first[v]:tree.first[v] + tree.count[v]] = v
+    inv = np.empty(n, np.int64)
+    inv[tree.perm] = np.arange(n)
+    nq = np.empty(k, np.int64)
+    for j in range(k):
+        if ancestors_only or j % 2 == 0:
+            path = []
+            v = tree.parent[leaf_of[inv[tq[j]]]]
+            while v >= 0:
+                path.append(v)
+                v = tree.parent[v]
+            nq[j] = path[rng.integers(0, len(path))] if path else 0
+        else:
+            nq[j] = rng.choice(inner)
+    return tq, nq
+
+
+def _run(wl, tq, nq, uniforms=None, cutoff=0.0, exclude_self=False, p=8):
+    import torch
+    import paper_2301_10570_amd as msp
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(d["x"].device)
+    P, ch = tree.partner_probabilities(d["w"], T(tq, np.int32), T(nq, np.int32), wl.sigma, p=p,
+                                       uniforms=None if uniforms is None else T(uniforms, np.float32),
+                                       exclude_self=exclude_self, cutoff_sigmas=cutoff)
+    return P.cpu().numpy().astype(np.float64), ch.cpu().numpy()
+
+
+def _check(wl, tq, nq, seed, cutoff=0.0, exclude_self=False, p=8):
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    u = synth.uniforms(len(tq), seed)
+    P, ch = _run(wl, tq, nq, u, cutoff, exclude_self, p)
+    Pr, Sr, chr_ = partner.probabilities(tr, wl.pos64(), wl.w, wl.sigma, tq, nq, uniforms=u,
+                                         exclude_self=exclude_self)
+    # queries whose FP64 sums underflow entirely (node beyond ~26 sigma) have no
+    # defined probabilities in the oracle; compare the rest
+    live = Sr.sum(axis=1) > 0
+    err = np.abs(P - Pr)[live]
+    assert np.all(err <= 1e-4 * Pr[live] + 1e-6), (err.max(), np.argmax(err))
+    # choices agree unless r*total sits within 1e-4*total of a running-sum boundary
+    run = np.cumsum(Sr, axis=1)
+    tot = run[:, -1:]
+    near = np.any(np.abs(run - u[:, None] * tot) <= 1e-4 * tot, axis=1)
+    ok = (ch == chr_) | near | ~live
+    assert np.all(ok), np.nonzero(~ok)
+    return err.max()
+
+
+def test_partner_config1():
+    wl = synth.config(1)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 300, seed=5)
+    print("partner config 1, 300 queries", flush=True)
+    e = _check(wl, tq, nq, seed=6)
+    print(f"  max |dP| {e:.2e}")
+
+
+def test_partner_blobs_exclude_self():
+    wl = synth.config(2, 0.125)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 200, seed=7)
+    print("partner blobs (1/8), exclude self", flush=True)
+    _check(wl, tq, nq, seed=8, exclude_self=True)
+
+
+def test_partner_slab_ancestors():
+    """Full 4M slab: moments are used for the large children."""
+    wl = synth.config(3)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 48, seed=9, ancestors_only=True)
+    print("partner slab 4M, 48 ancestor queries", flush=True)
+    e = _check(wl, tq, nq, seed=10)
+    print(f"  max |dP| {e:.2e}")
+
+
+@pytest.mark.parametrize("p", [4, 10])
+def test_partner_other_p(p):
+    wl = synth.config(3, 0.0625)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 64, seed=11 + p, ancestors_only=True)
+    print(f"partner slab 1/16, p={p}", flush=True)
+    _check(wl, tq, nq, seed=12, p=p)
+
+
+def test_partner_edge_cases():
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.uniform_box(500, seed=3)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=16)
+    ex = tree.export()
+    leaf = int(np.nonzero(ex["node_n_children"].cpu().numpy() == 0)[0][0])
+    dev = d["x"].device
+    tq = torch.tensor([0, 1, 2, 10**6], dtype=torch.int32, device=dev)
+    nq = torch.tensor([leaf, 0, -3, 0], dtype=torch.int32, device=dev)
+    uni = torch.full((4,), 0.5, device=dev)
+    P, ch = tree.partner_probabilities(d["w"], tq, nq, wl.sigma, uniforms=uni)
+    P, ch = P.cpu().numpy(), ch.cpu().numpy()
+    # leaf, bad node id, bad target id: zeros and no choice
+    for q in (0, 2, 3):
+        assert np.all(P[q] == 0) and ch[q] == -1
+    assert abs(P[1].sum() - 1) < 1e-5 and ch[1] >= 1
+    # zero weights everywhere: total 0, no choice
+    P, ch = tree.partner_probabilities(torch.zeros_like(d["w"]), tq, nq, wl.sigma, uniforms=uni)
+    assert np.all(P.cpu().numpy() == 0) and np.all(ch.cpu().numpy() == -1)
+    # no queries
+    e = torch.zeros(0, dtype=torch.int32, device=dev)
+    P, ch = tree.partner_probabilities(d["w"], e, e, wl.sigma)
+    assert P.shape == (0, 8)
+
+
+def test_node_moments_m2m_parity():
+    """Node moments (P2M at the lowest moment-carrying nodes, M2M upward) equal the
+    oracle's P2M over all points of the node about its centre (M2M is exact
+    under the tensor truncation), and the slab's large nodes carry them."""
+    import torch
+    import paper_2301_10570_amd as msp
+    from oracle import fgt as ofgt
+    wl = synth.config(3, 0.0625)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    e = torch.zeros(0, dtype=torch.int32, device=d["x"].device)
+    print("node moments parity (slab 1/16, p=8)", flush=True)
+    p = 8
+    tree.partner_probabilities(d["w"], e, e, wl.sigma, p=p)
+    has = tree.debug_buffer(3).cpu().numpy()
+    A = tree.debug_buffer(2).cpu().numpy()
+    nodes = np.nonzero(has)[0]
+    assert nodes.size > 50
+    slot0 = tr.level_offset[tree.plan(wl.sigma, p=p)["level"]]
+    A = A.reshape(-1, p, p, p)   # [slot][az][ay][ax]
+    pos = wl.pos64()
+    rng = np.random.default_rng(1)
+    for v in rng.choice(nodes, 40, replace=False):
+        c, _ = octree.node_box(tr, v)
+        ids = tr.perm[tr.first[v]:tr.first[v] + tr.count[v]]
+        ref = ofgt.p2m(pos[ids], wl.w[ids], c, wl.sigma, p)   # [ax, ay, az]
+        got = A[v - slot0].transpose(2, 1, 0)
+        assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max(), v
