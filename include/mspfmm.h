@@ -62,7 +62,10 @@ enum msp_flags {
     /* Skip the pair j == i (a neuron does not attract its own axons).  The direct
      * route skips the pair exactly; the expansion route subtracts w_i after the
      * fact, which loses relative accuracy when u_i is close to w_i. */
-    MSP_EXCLUDE_SELF = 1u << 0
+    MSP_EXCLUDE_SELF = 1u << 0,
+    /* Run the Hermite-to-Taylor translation on the vector ALUs instead of the
+     * matrix cores (same result up to float32 rounding; for cross-checks). */
+    MSP_M2L_VALU = 1u << 1
 };
 
 typedef struct msp_tree msp_tree; /* opaque handle */

@@ -27,6 +27,7 @@ MSP_OK, MSP_EINVAL, MSP_ENOSPC, MSP_EOVERFLOW, MSP_EHIP, MSP_ENOTSUP, MSP_ESTATE
 ROUTES = {"auto": 0, "fgt": 1, "direct": 2}
 ROUTE_NAMES = {v: k for k, v in ROUTES.items()}
 EXCLUDE_SELF = 1
+M2L_VALU = 2
 
 
 class MspError(RuntimeError):
@@ -120,10 +121,12 @@ def _ptr(t: torch.Tensor | None, dtype: torch.dtype, n: int | None, name: str):
     return t.data_ptr() if t.numel() else None
 
 
-def _params(sigma, p, level, route, cutoff_sigmas, exclude_self) -> FgtParams:
+def _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l="mfma") -> FgtParams:
+    flags = (EXCLUDE_SELF if exclude_self else 0) | (M2L_VALU if m2l == "valu" else 0)
+    if m2l not in ("mfma", "valu"):
+        raise ValueError(f"m2l must be 'mfma' or 'valu', got {m2l!r}")
     return FgtParams(int(p), int(level), float(sigma), float(cutoff_sigmas),
-                     ROUTES[route] if isinstance(route, str) else int(route),
-                     EXCLUDE_SELF if exclude_self else 0)
+                     ROUTES[route] if isinstance(route, str) else int(route), flags)
 
 
 class Tree:
@@ -187,7 +190,7 @@ class Tree:
                 "rho": inf.rho, "fgt_cost": inf.fgt_cost, "direct_cost": inf.direct_cost}
 
     def forward(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
-                exclude_self=False, out=None):
+                exclude_self=False, out=None, m2l="mfma"):
         """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere."""
         n = self.n
         pw = _ptr(w, torch.float32, n, "w")
@@ -195,7 +198,7 @@ class Tree:
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=w.device)
         po = _ptr(out, torch.float32, n, "out")
-        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l)
         _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
         return out
 

@@ -97,7 +97,8 @@ static int check_params(const msp_fgt_params *prm) {
     if (!(prm->sigma > 0.f) || !std::isfinite(prm->sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
     if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
     if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
-    if (prm->flags & ~(uint32_t)MSP_EXCLUDE_SELF) return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU))
+        return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
     if (std::isnan(prm->cutoff_sigmas)) return fail(MSP_EINVAL, "cutoff_sigmas is NaN");
     return MSP_OK;
 }
@@ -105,9 +106,9 @@ static int check_params(const msp_fgt_params *prm) {
 }  // namespace msp
 
 msp_tree::~msp_tree() {
-    for (msp::DevBuf *b : {&keys, &perm, &iperm, &xs, &ys, &zs, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
+    for (msp::DevBuf *b : {&keys, &perm, &iperm, &ps, &pin, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
                            &nnchild, &ndigit, &nix, &niy, &niz, &d_level_off, &keys2, &perm2, &hist,
-                           &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &ws, &tflag, &usort,
+                           &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &tflag, &usort,
                            &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
                            &node_nsrc})
         b->release();
@@ -224,12 +225,8 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     hipStream_t s = (hipStream_t)stream;
     FgtPlan pl;
     MSP_TRY(plan_fgt(t, prm, &pl));
+    if (pl.route == MSP_ROUTE_FGT) return fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
     MSP_TRY(stage_inputs(t, w, is_target, s));
-    const bool excl = (prm->flags & MSP_EXCLUDE_SELF) != 0;
-    if (pl.route == MSP_ROUTE_FGT) {
-        MSP_TRY(fgt_forward_grid(t, pl, prm, s));
-        return scatter_output(t, u_out, prm->flags, excl, s);
-    }
     MSP_TRY(direct_route(t, prm, s));
     return scatter_output(t, u_out, prm->flags, false, s);
 }

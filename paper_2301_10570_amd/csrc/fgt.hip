@@ -35,16 +35,24 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// T_k[o][b][a] = (-1)^b / b! * h_{a+b}(o * step), o = -(G-1) .. G-1.
-__global__ void k_m2l_ops(int p, int G, double step, float *out) {
-    const int o = (int)(blockIdx.x * blockDim.x + threadIdx.x) - (G - 1);
-    if (o > G - 1) return;
+// T_k[o][b][a] = (-1)^b / b! * h_{a+b}(o * step), o = -(G_k-1) .. G_k-1, for the three
+// axes in one launch (thread -> axis, offset); computed in float64, stored as float32.
+__global__ void k_m2l_ops(int p, int Gx, int Gy, int Gz, double step, float *ox, float *oy, float *oz) {
+    int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int nx = 2 * Gx - 1, ny = 2 * Gy - 1, nz = 2 * Gz - 1;
+    int G;
+    float *out;
+    if (t < nx) { G = Gx; out = ox; }
+    else if (t < nx + ny) { t -= nx; G = Gy; out = oy; }
+    else if (t < nx + ny + nz) { t -= nx + ny; G = Gz; out = oz; }
+    else return;
+    const int o = t - (G - 1);
     const double x = o * step;
     double h[2 * kMaxP];
     h[0] = exp(-x * x);
     if (2 * p - 1 > 1) h[1] = 2.0 * x * h[0];
     for (int n = 1; n + 1 < 2 * p - 1; ++n) h[n + 1] = 2.0 * x * h[n] - 2.0 * n * h[n - 1];
-    float *T = out + (size_t)(o + G - 1) * p * p;
+    float *T = out + (size_t)t * p * p;
     double inv_fact = 1.0;
     for (int b = 0; b < p; ++b) {
         if (b > 0) inv_fact /= b;
@@ -53,94 +61,94 @@ __global__ void k_m2l_ops(int p, int G, double step, float *out) {
     }
 }
 
+// Point range of a grid cell: the points whose level-`level` key prefix is the
+// cell's Morton code (contiguous in key order).
+__device__ inline void cell_range(const uint64_t *keys, int64_t n, int level, int kx, int ky, int kz,
+                                  int64_t &start, int64_t &end) {
+    const int sh = 3 * (kDepth - level);
+    const uint64_t prefix = morton3((uint32_t)kx, (uint32_t)ky, (uint32_t)kz);
+    start = lower_bound_u64(keys, 0, n, prefix << sh);
+    end = lower_bound_u64(keys, start, n, (prefix + 1ull) << sh);
+}
+
 // One block per cell of the grid; moments written in the grid layout
-// [kz][az][ky][ay][kx][ax].
+// [kz][az][ky][ay][kx][ax].  Lane l of a wave owns az = l % P and handles every
+// (64/P)-th point of the wave's share; it keeps the P x P moments (ax, ay) of its
+// az in registers.  Partial moments are added in a fixed order (lanes, then waves).
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n, const float *xs,
-                                                const float *ys, const float *zs, const float *ws,
+__global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                const int32_t *perm, const float *w,
                                                 int level, int Gx, int Gy, int Gz, double lox,
                                                 double loy, double loz, double cell,
                                                 double inv_sigma, float *A) {
-    constexpr int P2 = P * P;
-    constexpr int NG = kBlock / P2 > 0 ? kBlock / P2 : 1;   // point groups
-    constexpr int STR = 3 * P + 1;
-    __shared__ float pts[kBlock * STR];
-    __shared__ float red[NG > 1 ? NG * P2 * P : 1];
-
+    constexpr int P3 = P * P * P;
+    constexpr int PL = 64 / P;            // point lanes per wave
+    constexpr int NW = kBlock / 64;
+    constexpr int NB = P <= 12 ? NW : 1;  // partial buffers (LDS budget for large P)
+    __shared__ float red[NB][P3];
     const int64_t g = blockIdx.x;
     const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
-    const int sh = 3 * (kDepth - level);
-    const uint64_t prefix = morton3((uint32_t)kx, (uint32_t)ky, (uint32_t)kz);
-    const int64_t start = lower_bound_u64(keys, 0, n, prefix << sh);
-    const int64_t end = lower_bound_u64(keys, start, n, (prefix + 1ull) << sh);
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
     const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
-
-    const int tid = threadIdx.x;
-    const int grp = tid / P2, yz = tid % P2;
-    const int ay = yz % P, az = yz / P;
-    const bool active = grp < NG;
-    float acc[P];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int az = lane % P, pl = lane / P;
+    const bool active = pl < PL;
+    float acc[P][P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = 0.f;
-
-    for (int64_t c0 = start; c0 < end; c0 += kBlock) {
-        const int64_t i = c0 + tid;
-        if (i < end) {
-            const float X = (float)(((double)xs[i] - cx) * inv_sigma);
-            const float Y = (float)(((double)ys[i] - cy) * inv_sigma);
-            const float Z = (float)(((double)zs[i] - cz) * inv_sigma);
-            float *r = pts + tid * STR;
-            float px = ws[i], py = 1.f, pz = 1.f;
+    for (int a = 0; a < P; ++a)
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                r[k] = px;
-                r[P + k] = py;
-                r[2 * P + k] = pz;
-                px *= X;
-                py *= Y;
-                pz *= Z;
+        for (int b = 0; b < P; ++b) acc[a][b] = 0.f;
+    if (active) {
+        for (int64_t j = start + wid * PL + pl; j < end; j += NW * PL) {
+            const float4 q = ps[j];
+            const float X = (float)(((double)q.x - cx) * inv_sigma);
+            const float Y = (float)(((double)q.y - cy) * inv_sigma);
+            const float Z = (float)(((double)q.z - cz) * inv_sigma);
+            float zw = w[perm[j]];
+#pragma unroll
+            for (int k = 1; k < P; ++k) zw = k <= az ? zw * Z : zw;
+            float px[P], yz[P];
+            px[0] = 1.f;
+            yz[0] = zw;
+#pragma unroll
+            for (int k = 1; k < P; ++k) {
+                px[k] = px[k - 1] * X;
+                yz[k] = yz[k - 1] * Y;
             }
-        }
-        __syncthreads();
-        const int cnt = (int)(end - c0 < kBlock ? end - c0 : kBlock);
-        if (active) {
-            for (int j = grp; j < cnt; j += NG) {
-                const float *r = pts + j * STR;
-                const float f = r[P + ay] * r[2 * P + az];
 #pragma unroll
-                for (int k = 0; k < P; ++k) acc[k] = fmaf(f, r[k], acc[k]);
-            }
-        }
-        __syncthreads();
-    }
-    if (NG > 1) {
-        if (active)
+            for (int a = 0; a < P; ++a)
 #pragma unroll
-            for (int k = 0; k < P; ++k) red[(grp * P2 + yz) * P + k] = acc[k];
-        __syncthreads();
-        if (grp == 0) {
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                float s = 0.f;
-                for (int q = 0; q < NG; ++q) s += red[(q * P2 + yz) * P + k];
-                acc[k] = s;
-            }
+                for (int b = 0; b < P; ++b) acc[a][b] = fmaf(px[a], yz[b], acc[a][b]);
         }
     }
-    if (grp == 0) {
-        // 1 / (ax! ay! az!)
-        float fy = 1.f, fz = 1.f;
-        for (int k = 2; k <= ay; ++k) fy *= (float)k;
-        for (int k = 2; k <= az; ++k) fz *= (float)k;
-        const float inv_yz = 1.f / (fy * fz);
-        const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
-        float *dst = A + (((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P;
-        float fx = 1.f;
+    // lanes with the same az in point-lane order (per wave, or waves in turn)
+    for (int e = tid; e < NB * P3; e += kBlock) (&red[0][0])[e] = 0.f;
+    __syncthreads();
+    const int wb = NB == NW ? wid : 0;
+    for (int w = 0; w < NW / NB; ++w) {
+        for (int r = 0; r < PL; ++r) {
+            if (active && pl == r && (NB == NW || wid == w)) {
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (k > 1) fx *= (float)k;
-            dst[k] = acc[k] * inv_yz / fx;
+                for (int b = 0; b < P; ++b)
+#pragma unroll
+                    for (int a = 0; a < P; ++a) red[wb][(az * P + b) * P + a] += acc[a][b];
+            }
+            __syncthreads();
         }
+    }
+    // waves in order, then 1/(ax! ay! az!) and the grid layout
+    const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    for (int e = tid; e < P3; e += kBlock) {
+        float s = 0.f;
+#pragma unroll
+        for (int w = 0; w < NB; ++w) s += red[w][e];
+        const int ax = e % P, ay = (e / P) % P, zz = e / (P * P);
+        float f = 1.f;
+        for (int k = 2; k <= ax; ++k) f *= (float)k;
+        for (int k = 2; k <= ay; ++k) f *= (float)k;
+        for (int k = 2; k <= zz; ++k) f *= (float)k;
+        A[(((int64_t)kz * P + zz) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax] = s / f;
     }
 }
 
@@ -200,22 +208,82 @@ __global__ void __launch_bounds__(kBlock) k_m2l_pass(const float *In, float *Out
     }
 }
 
-// One block per cell: evaluate the cell's Taylor series at its points.
+// The same pass on the matrix cores: D[v][r] = sum_u M[v][u] In[r][u] with
+// v_mfma_f32_16x16x4f32 (A = operator tile, B = input tile, both staged in LDS).
+// One wavefront per 32 x 32 tile of D, built from 2 x 2 MFMA tiles; K steps of 16.
+// Lane layout of the 16x16x4 instruction: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and receives D[4*(l/16) + i][l%16], i = 0..3.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MT = 32, MK = 16;
+__global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Out, int64_t R, int p,
+                                                      int G, const float *T) {
+    __shared__ float sA[MT][MK + 1];   // operator rows v, columns u
+    __shared__ float sB[MT][MK + 1];   // input rows r, columns u
+    const int U = G * p;
+    const int64_t r0 = (int64_t)blockIdx.x * MT;
+    const int v0 = blockIdx.y * MT;
+    const int lane = threadIdx.x;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int u0 = 0; u0 < U; u0 += MK) {
+#pragma unroll
+        for (int e = lane; e < MT * MK; e += 64) {
+            const int row = e / MK, kk = e % MK;
+            const int u = u0 + kk;
+            const int v = v0 + row;
+            float m = 0.f;
+            if (v < U && u < U) {
+                const int t = v / p, b = v % p, sI = u / p, a = u % p;
+                m = T[((size_t)(t - sI + G - 1) * p + b) * p + a];
+            }
+            sA[row][kk] = m;
+            const int64_t r = r0 + row;
+            sB[row][kk] = (r < R && u < U) ? In[r * U + u] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < MK; k4 += 4) {
+            const int kk = k4 + (lane >> 4), rr = lane & 15;
+            const float a0 = sA[rr][kk], a1 = sA[16 + rr][kk];
+            const float b0 = sB[rr][kk], b1 = sB[16 + rr][kk];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = v0 + 16 * a + 4 * (lane >> 4) + i;
+                const int64_t r = r0 + 16 * b + (lane & 15);
+                if (v < U && r < R) Out[(int64_t)v * R + r] = acc[a][b][i];
+            }
+}
+
+// One block per cell: evaluate the cell's Taylor series at its targets (Horner
+// in x, then y, then z), two targets per thread so that every coefficient read
+// from LDS feeds two multiply-adds.
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n, const float *xs,
-                                                const float *ys, const float *zs,
-                                                const uint8_t *tflag, int level, int Gx, int Gy,
-                                                int Gz, double lox, double loy, double loz,
+__global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                const int32_t *perm, const uint8_t *is_target,
+                                                const float *w, int subtract_self, int level, int Gx,
+                                                int Gy, int Gz, double lox, double loy, double loz,
                                                 double cell, double inv_sigma, const float *C,
-                                                float *usort) {
+                                                float *u_out) {
     constexpr int P3 = P * P * P;
     __shared__ float sC[P3];
     const int64_t g = blockIdx.x;
     const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
-    const int sh = 3 * (kDepth - level);
-    const uint64_t prefix = morton3((uint32_t)kx, (uint32_t)ky, (uint32_t)kz);
-    const int64_t start = lower_bound_u64(keys, 0, n, prefix << sh);
-    const int64_t end = lower_bound_u64(keys, start, n, (prefix + 1ull) << sh);
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
     if (start == end) return;
     const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
     for (int e = threadIdx.x; e < P3; e += kBlock) {
@@ -224,69 +292,94 @@ __global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n,
     }
     __syncthreads();
     const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
-    for (int64_t i = start + threadIdx.x; i < end; i += kBlock) {
-        if (!tflag[i]) { usort[i] = 0.f; continue; }
-        const float X = (float)(((double)xs[i] - cx) * inv_sigma);
-        const float Y = (float)(((double)ys[i] - cy) * inv_sigma);
-        const float Z = (float)(((double)zs[i] - cz) * inv_sigma);
-        float uz = 0.f;
+    for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += 2 * kBlock) {
+        const int64_t i1 = i0 + kBlock;
+        const bool has1 = i1 < end;
+        const float4 q0 = ps[i0];
+        const float4 q1 = has1 ? ps[i1] : q0;
+        const float X0 = (float)(((double)q0.x - cx) * inv_sigma), X1 = (float)(((double)q1.x - cx) * inv_sigma);
+        const float Y0 = (float)(((double)q0.y - cy) * inv_sigma), Y1 = (float)(((double)q1.y - cy) * inv_sigma);
+        const float Z0 = (float)(((double)q0.z - cz) * inv_sigma), Z1 = (float)(((double)q1.z - cz) * inv_sigma);
+        float uz0 = 0.f, uz1 = 0.f;
         for (int az = P - 1; az >= 0; --az) {
-            float uy = 0.f;
+            float uy0 = 0.f, uy1 = 0.f;
+#pragma unroll
             for (int ay = P - 1; ay >= 0; --ay) {
                 const float *c = sC + (az * P + ay) * P;
-                float ux = c[P - 1];
+                float ux0 = c[P - 1], ux1 = c[P - 1];
 #pragma unroll
-                for (int ax = P - 2; ax >= 0; --ax) ux = fmaf(ux, X, c[ax]);
-                uy = fmaf(uy, Y, ux);
+                for (int ax = P - 2; ax >= 0; --ax) {
+                    const float cv = c[ax];
+                    ux0 = fmaf(ux0, X0, cv);
+                    ux1 = fmaf(ux1, X1, cv);
+                }
+                uy0 = fmaf(uy0, Y0, ux0);
+                uy1 = fmaf(uy1, Y1, ux1);
             }
-            uz = fmaf(uz, Z, uy);
+            uz0 = fmaf(uz0, Z0, uy0);
+            uz1 = fmaf(uz1, Z1, uy1);
         }
-        usort[i] = uz;
+        // back to input order; non-targets get 0
+        const int32_t j0 = perm[i0];
+        const bool t0 = !is_target || is_target[j0];
+        u_out[j0] = t0 ? (subtract_self ? uz0 - w[j0] : uz0) : 0.f;
+        if (has1) {
+            const int32_t j1 = perm[i1];
+            const bool t1 = !is_target || is_target[j1];
+            u_out[j1] = t1 ? (subtract_self ? uz1 - w[j1] : uz1) : 0.f;
+        }
     }
 }
 
+// Weights and target flags into key order (the w slot of the sorted positions).
 __global__ void k_stage(const float *w, const uint8_t *is_target, const int32_t *perm, int64_t n,
-                        float *ws, uint8_t *tflag) {
+                        float4 *ps, uint8_t *tflag) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t j = perm[i];
-    ws[i] = w[j];
+    ps[i].w = w[j];
     tflag[i] = is_target ? (is_target[j] != 0) : (uint8_t)1;
 }
 
-__global__ void k_scatter(const float *usort, const float *ws, const uint8_t *tflag,
+__global__ void k_scatter(const float *usort, const float4 *ps, const uint8_t *tflag,
                           const int32_t *perm, int64_t n, int subtract_self, float *u_out) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     float u = 0.f;
-    if (tflag[i]) u = subtract_self ? usort[i] - ws[i] : usort[i];
+    if (tflag[i]) u = subtract_self ? usort[i] - ps[i].w : usort[i];
     u_out[perm[i]] = u;
 }
 
+struct GridArgs {
+    const float *w;
+    const uint8_t *is_target;
+    int subtract_self;
+    float *u_out;
+};
+
 template <int P>
 int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, const float *C,
-                   float *A, hipStream_t s) {
+                   float *A, const GridArgs &ga, hipStream_t s) {
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
-                           t->keys.as<uint64_t>(), t->n, t->xs.as<float>(), t->ys.as<float>(),
-                           t->zs.as<float>(), t->ws.as<float>(), pl.level, pl.G[0], pl.G[1], pl.G[2],
-                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A);
+                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
+                           ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
+                           t->geo.lo[2], pl.cell, inv_sigma, A);
     } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
-                           t->keys.as<uint64_t>(), t->n, t->xs.as<float>(), t->ys.as<float>(),
-                           t->zs.as<float>(), t->tflag.as<uint8_t>(), pl.level, pl.G[0], pl.G[1],
-                           pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C,
-                           t->usort.as<float>());
+                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
+                           ga.is_target, ga.w, ga.subtract_self, pl.level, pl.G[0], pl.G[1], pl.G[2],
+                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, ga.u_out);
     }
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
 
 int dispatch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, const float *C,
-                     float *A, hipStream_t s) {
+                     float *A, const GridArgs &ga, hipStream_t s) {
     switch (pl.p) {
-#define CASE(P) case P: return launch_p2m_l2p<P>(t, pl, inv_sigma, l2p, C, A, s);
+#define CASE(P) case P: return launch_p2m_l2p<P>(t, pl, inv_sigma, l2p, C, A, ga, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
@@ -345,18 +438,19 @@ int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *pl) {
 
 int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s) {
     const int64_t n = t->n, nb = n > 0 ? n : 1;
-    MSP_TRY(t->ws.ensure(nb * 4));
     MSP_TRY(t->tflag.ensure(nb));
     MSP_TRY(t->usort.ensure(nb * 4));
     if (n == 0) return MSP_OK;
     PhaseScope ps(&t->timing, PH_STAGE, s);
     hipLaunchKernelGGL(k_stage, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, w, is_target,
-                       t->perm.as<int32_t>(), n, t->ws.as<float>(), t->tflag.as<uint8_t>());
+                       t->perm.as<int32_t>(), n, t->ps.as<float4>(), t->tflag.as<uint8_t>());
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
 
-int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, hipStream_t s) {
+int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
+                     const uint8_t *is_target, float *u_out, hipStream_t s) {
+    const GridArgs ga{w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out};
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     const size_t gbytes = (size_t)ncell * p * p * p * 4;
@@ -372,17 +466,17 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
     float *opsy = opsx + (size_t)(2 * pl.G[0] - 1) * p * p;
     float *opsz = opsy + (size_t)(2 * pl.G[1] - 1) * p * p;
     const double step = pl.cell / prm->sigma;
-    float *opsk[3] = {opsx, opsy, opsz};
-    for (int k = 0; k < 3; ++k) {
-        const int no = 2 * pl.G[k] - 1;
+    {
         PhaseScope ps(&t->timing, PH_OPS, s);
-        hipLaunchKernelGGL(k_m2l_ops, dim3(grid_for(no, 64)), dim3(64), 0, s, p, pl.G[k], step, opsk[k]);
+        const int nops = 2 * (pl.G[0] + pl.G[1] + pl.G[2]) - 3;
+        hipLaunchKernelGGL(k_m2l_ops, dim3(grid_for(nops, 64)), dim3(64), 0, s, p, pl.G[0], pl.G[1],
+                           pl.G[2], step, opsx, opsy, opsz);
         MSP_CHECK_LAUNCH();
     }
     const double inv_sigma = 1.0 / prm->sigma;
     {
         PhaseScope ps(&t->timing, PH_P2M, s);
-        MSP_TRY(dispatch_p2m_l2p(t, pl, inv_sigma, false, nullptr, A, s));
+        MSP_TRY(dispatch_p2m_l2p(t, pl, inv_sigma, false, nullptr, A, ga, s));
     }
     // three passes: contract x (In [Uz][Uy][Ux]), then y, then z
     const int64_t Ux = (int64_t)pl.G[0] * p, Uy = (int64_t)pl.G[1] * p, Uz = (int64_t)pl.G[2] * p;
@@ -390,15 +484,21 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
     const Pass passes[3] = {{A, B, Uz * Uy, pl.G[0], opsx, Ux},
                             {B, Tmp, Ux * Uz, pl.G[1], opsy, Uy},
                             {Tmp, B, Uy * Ux, pl.G[2], opsz, Uz}};
+    const bool valu = (prm->flags & MSP_M2L_VALU) != 0;
     for (int k = 0; k < 3; ++k) {
         const Pass &ps = passes[k];
         PhaseScope sc(&t->timing, PH_M2L_X + k, s);
-        dim3 grid((unsigned)((ps.R + TR - 1) / TR), (unsigned)((ps.U + TV - 1) / TV));
-        hipLaunchKernelGGL(k_m2l_pass, grid, dim3(kBlock), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+        if (valu) {
+            dim3 grid((unsigned)((ps.R + TR - 1) / TR), (unsigned)((ps.U + TV - 1) / TV));
+            hipLaunchKernelGGL(k_m2l_pass, grid, dim3(kBlock), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+        } else {
+            dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
+            hipLaunchKernelGGL(k_m2l_pass_mfma, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+        }
         MSP_CHECK_LAUNCH();
     }
     PhaseScope ps(&t->timing, PH_L2P, s);
-    return dispatch_p2m_l2p(t, pl, inv_sigma, true, B, nullptr, s);
+    return dispatch_p2m_l2p(t, pl, inv_sigma, true, B, nullptr, ga, s);
 }
 
 int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s) {
@@ -406,7 +506,7 @@ int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self
     if (t->n == 0) return MSP_OK;
     PhaseScope ps(&t->timing, PH_SCATTER, s);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(t->n, kBlock)), dim3(kBlock), 0, s,
-                       t->usort.as<float>(), t->ws.as<float>(), t->tflag.as<uint8_t>(),
+                       t->usort.as<float>(), t->ps.as<float4>(), t->tflag.as<uint8_t>(),
                        t->perm.as<int32_t>(), t->n, subtract_self ? 1 : 0, u_out);
     MSP_CHECK_LAUNCH();
     return MSP_OK;

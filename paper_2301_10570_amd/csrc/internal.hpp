@@ -105,16 +105,17 @@ struct msp_tree {
     msp::Geometry geo{};
 
     // points in key order
-    msp::DevBuf keys, perm, iperm, xs, ys, zs;
+    msp::DevBuf keys, perm, iperm, ps;
+    bool iperm_valid = false;   // ps: float4 (x, y, z, staged weight) in key order
     // node table (SoA, int32)
     msp::DevBuf nlevel, nfirst, ncount, nparent, nfchild, nnchild, ndigit, nix, niy, niz;
     msp::DevBuf d_level_off;  // int64[kMaxLevels] on the device
 
     // build scratch
-    msp::DevBuf keys2, perm2, hist, tmp_a, tmp_b, tmp_c, dlev, llev, blkcnt, bbox;
+    msp::DevBuf keys2, perm2, pin, hist, tmp_a, tmp_b, tmp_c, dlev, llev, blkcnt, bbox;
 
     // per-call staging
-    msp::DevBuf ws, tflag, usort;
+    msp::DevBuf tflag, usort;
     // expansion grids and translation operators
     msp::DevBuf gridA, gridB, ops;
     int64_t grid_bytes_valid = 0;
@@ -150,7 +151,9 @@ struct FgtPlan {
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
 double rho_max_for_p(int p);
 int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s);
-int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, hipStream_t s);
+int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, const float *w,
+                     const uint8_t *is_target, float *u_out, hipStream_t s);
+int ensure_iperm(msp_tree *t, hipStream_t s);
 int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s);
 
 // p2p.hip

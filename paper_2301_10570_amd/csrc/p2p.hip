@@ -112,8 +112,7 @@ __global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfir
                                             const int32_t *ncount, const int32_t *nnchild,
                                             const int32_t *nlevel, const int32_t *nix,
                                             const int32_t *niy, const int32_t *niz, BoxGeo geo,
-                                            const int64_t *off, const int32_t *lst, const float *xs,
-                                            const float *ys, const float *zs, const float *ws,
+                                            const int64_t *off, const int32_t *lst, const float4 *ps,
                                             const uint8_t *tflag, float k_scale, int exclude_self,
                                             float *usort) {
     const int64_t v = blockIdx.x;
@@ -133,9 +132,10 @@ __global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfir
         const int G = 64 / tp;
         const int a = lane % tp, grp = lane / tp;
         const int32_t ti = tf + t0 + (a < nt ? a : 0);
-        const float tx = (xs[ti] - ct[0]) * k_scale;
-        const float ty = (ys[ti] - ct[1]) * k_scale;
-        const float tz = (zs[ti] - ct[2]) * k_scale;
+        const float4 qt = ps[ti];
+        const float tx = (qt.x - ct[0]) * k_scale;
+        const float ty = (qt.y - ct[1]) * k_scale;
+        const float tz = (qt.z - ct[2]) * k_scale;
         float total = 0.f, comp = 0.f;
         for (int64_t q = l0; q < l1; ++q) {
             const int32_t u = lst[q];
@@ -146,10 +146,11 @@ __global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfir
                 __syncthreads();
                 if (lane < ns) {
                     const int32_t j = sf + s0 + lane;
-                    sx[lane] = (xs[j] - ct[0]) * k_scale;
-                    sy[lane] = (ys[j] - ct[1]) * k_scale;
-                    sz[lane] = (zs[j] - ct[2]) * k_scale;
-                    sw[lane] = ws[j];
+                    const float4 qs = ps[j];
+                    sx[lane] = (qs.x - ct[0]) * k_scale;
+                    sy[lane] = (qs.y - ct[1]) * k_scale;
+                    sz[lane] = (qs.z - ct[2]) * k_scale;
+                    sw[lane] = qs.w;
                     sid[lane] = j;
                 }
                 __syncthreads();
@@ -266,8 +267,7 @@ int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p, dim3((unsigned)nn), dim3(64), 0, s, nn, t->nfirst.as<int32_t>(),
                        t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(), t->nlevel.as<int32_t>(),
                        t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), geo,
-                       t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->xs.as<float>(),
-                       t->ys.as<float>(), t->zs.as<float>(), t->ws.as<float>(),
+                       t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(),
                        t->tflag.as<uint8_t>(), k_scale, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0,
                        t->usort.as<float>());
     MSP_CHECK_LAUNCH();

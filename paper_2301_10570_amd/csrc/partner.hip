@@ -43,8 +43,8 @@ __global__ void __launch_bounds__(kBlock)
 k_node_moments(int64_t v0, int level, int lh, const int32_t *nfirst, const int32_t *ncount,
                const int32_t *nfchild, const int32_t *nnchild, const int32_t *nix,
                const int32_t *niy, const int32_t *niz, const int32_t *ndigit, double lox,
-               double loy, double loz, double side, const float *xs, const float *ys,
-               const float *zs, const float *ws, double inv_sigma, int32_t *nsrc, uint8_t *hasA,
+               double loy, double loz, double side, const float4 *ps, double inv_sigma,
+               int32_t *nsrc, uint8_t *hasA,
                float *nodeA, int64_t slot0) {
     constexpr int P2 = P * P, P3 = P * P * P;
     constexpr int NG = kBlock / P2 > 0 ? kBlock / P2 : 1;
@@ -66,7 +66,7 @@ k_node_moments(int64_t v0, int level, int lh, const int32_t *nfirst, const int32
     int32_t ns = 0;
     if (nc == 0) {
         int32_t c = 0;
-        for (int32_t j = f + tid; j < f + cnt; j += kBlock) c += ws[j] != 0.f;
+        for (int32_t j = f + tid; j < f + cnt; j += kBlock) c += ps[j].w != 0.f;
         for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
         if ((tid & 63) == 0) s_cnt[tid >> 6] = c;
         __syncthreads();
@@ -104,11 +104,12 @@ k_node_moments(int64_t v0, int level, int lh, const int32_t *nfirst, const int32
             const int32_t i = pf + c0 + tid;
             __syncthreads();
             if (tid < CH && c0 + tid < pn) {
-                const float X = (float)(((double)xs[i] - cx) * inv_sigma);
-                const float Y = (float)(((double)ys[i] - cy) * inv_sigma);
-                const float Z = (float)(((double)zs[i] - cz) * inv_sigma);
+                const float4 qp = ps[i];
+                const float X = (float)(((double)qp.x - cx) * inv_sigma);
+                const float Y = (float)(((double)qp.y - cy) * inv_sigma);
+                const float Z = (float)(((double)qp.z - cz) * inv_sigma);
                 float *r = pts + tid * STR;
-                float px = ws[i], py = 1.f, pz = 1.f;
+                float px = qp.w, py = 1.f, pz = 1.f;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     r[k] = px; r[P + k] = py; r[2 * P + k] = pz;
@@ -214,8 +215,8 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
           int64_t n, int64_t n_nodes, const int32_t *iperm, const int32_t *nlevel,
           const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
           const int32_t *nnchild, const int32_t *ndigit, const int32_t *nix, const int32_t *niy,
-          const int32_t *niz, double lox, double loy, double loz, double side, const float *xs,
-          const float *ys, const float *zs, const float *ws, const uint8_t *hasA,
+          const int32_t *niz, double lox, double loy, double loz, double side, const float4 *ps,
+          const uint8_t *hasA,
           const float *nodeA, int64_t slot0, int lh, double sigma, float cutoff2, int unlimited,
           float rho_ref, int exclude_self, float *probs, int32_t *choice) {
     constexpr int P3 = P * P * P;
@@ -237,7 +238,8 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         return;
     }
     const int32_t si = iperm[ti];
-    const double tx = xs[si], ty = ys[si], tz = zs[si];
+    const float4 qt = ps[si];
+    const double tx = qt.x, ty = qt.y, tz = qt.z;
     const double inv_sigma = 1.0 / sigma;
     const double kexp = 1.4426950408889634 / (sigma * sigma);
     // distance from the target to the box of X
@@ -309,14 +311,15 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                     mp = fmaf(A[e], hfun[0][ax] * hfun[1][ay] * hfun[2][az], mp);
                 }
                 // the query's own point inside this node contributes w_self * K(0)
-                if (exclude_self && lane == 0 && si >= uf && si < uf + un) mp -= ws[si];
+                if (exclude_self && lane == 0 && si >= uf && si < uf + un) mp -= qt.w;
                 part += (double)mp;
                 __syncthreads();
             } else if (unc == 0) {
                 for (int32_t j = uf + lane; j < uf + un; j += 64) {
-                    const float wj = ws[j];
+                    const float4 qj = ps[j];
+                    const float wj = qj.w;
                     if (wj == 0.f || (exclude_self && j == si)) continue;
-                    const double ex = tx - xs[j], ey = ty - ys[j], ez = tz - zs[j];
+                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
                     const double d2 = ex * ex + ey * ey + ez * ez;
                     part += (double)wj * exp2_neg(d2 * kexp);
                 }
@@ -382,8 +385,7 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                                0, s, a, l, lh, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(),
                                t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), t->nix.as<int32_t>(),
                                t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->ndigit.as<int32_t>(),
-                               t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->xs.as<float>(),
-                               t->ys.as<float>(), t->zs.as<float>(), t->ws.as<float>(), 1.0 / sigma,
+                               t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(), 1.0 / sigma,
                                t->node_nsrc.as<int32_t>(), t->node_hasA.as<uint8_t>(),
                                t->nodeA.as<float>(), slot0);
             MSP_CHECK_LAUNCH();
@@ -401,8 +403,7 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                        t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                        t->nnchild.as<int32_t>(), t->ndigit.as<int32_t>(), t->nix.as<int32_t>(),
                        t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1],
-                       t->geo.lo[2], t->geo.side, t->xs.as<float>(), t->ys.as<float>(), t->zs.as<float>(),
-                       t->ws.as<float>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, lh,
+                       t->geo.lo[2], t->geo.side, t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, lh,
                        sigma, R * R, unlimited ? 1 : 0, (float)rmax,
                        (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice);
     MSP_CHECK_LAUNCH();
@@ -419,6 +420,7 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
         return MSP_OK;
     }
     MSP_TRY(stage_inputs(t, w, nullptr, s));
+    MSP_TRY(ensure_iperm(t, s));
     switch (prm->p) {
 #define CASE(P) case P: return run_partner<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)

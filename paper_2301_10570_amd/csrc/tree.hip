@@ -81,14 +81,24 @@ __global__ void k_bbox_partial(const float *x, const float *y, const float *z, i
 }
 
 __global__ void k_bbox_final(const float *part, int nparts, float *out) {
-    if (threadIdx.x != 0) return;
+    __shared__ float sm[6][kBlock];
     float r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nparts; ++b)
+    for (int b = threadIdx.x; b < nparts; b += kBlock)
         for (int k = 0; k < 3; ++k) {
             r[k] = fminf(r[k], part[b * 6 + k]);
             r[3 + k] = fmaxf(r[3 + k], part[b * 6 + 3 + k]);
         }
-    for (int k = 0; k < 6; ++k) out[k] = r[k];
+    for (int k = 0; k < 6; ++k) sm[k][threadIdx.x] = r[k];
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) {
+                sm[k][threadIdx.x] = fminf(sm[k][threadIdx.x], sm[k][threadIdx.x + st]);
+                sm[3 + k][threadIdx.x] = fmaxf(sm[3 + k][threadIdx.x], sm[3 + k][threadIdx.x + st]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 // ---- keys ----------------------------------------------------------------------------------
@@ -101,11 +111,14 @@ __device__ inline uint32_t quantise(float v, double lo, double scale) {
 }
 
 __global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, double lx,
-                         double ly, double lz, double scale, uint64_t *key, int32_t *idx) {
+                         double ly, double lz, double scale, uint64_t *key, int32_t *idx,
+                         float4 *pin) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    key[i] = morton3(quantise(x[i], lx, scale), quantise(y[i], ly, scale), quantise(z[i], lz, scale));
+    const float a = x[i], b = y[i], c = z[i];
+    key[i] = morton3(quantise(a, lx, scale), quantise(b, ly, scale), quantise(c, lz, scale));
     idx[i] = (int32_t)i;
+    pin[i] = make_float4(a, b, c, 0.f);   // packed so that the sorted gather reads one line per point
 }
 
 // ---- stable LSD radix sort of (key, index), 8 bits per pass ----------------------------------
@@ -144,26 +157,51 @@ __global__ void k_rs_digit_scan(uint32_t *hist, int nblk, uint32_t *total) {
     if (threadIdx.x == 0) total[blockIdx.x] = tot;
 }
 
-__global__ void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout,
-                             int64_t n, int shift, const uint32_t *hist, const uint32_t *total,
-                             int nblk) {
+// Stable scatter of one 8-bit digit.  The tile is first ordered by digit in LDS
+// (stable: ranks follow item order), then written out so that consecutive
+// threads store consecutive positions of each digit's output run.
+__global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t *kin, const int32_t *vin,
+                                                       uint64_t *kout, int32_t *vout, int64_t n,
+                                                       int shift, const uint32_t *hist,
+                                                       const uint32_t *total, int nblk,
+                                                       const float4 *pin, float4 *ps) {
+    __shared__ uint64_t sk[kTile];
+    __shared__ int32_t sv[kTile];
     __shared__ uint32_t lds[kBlock / 64];
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t toff[256];
+    __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kBlock / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint32_t tot;
-    uint32_t dbase = block_exclusive_scan(total[tid], lds, tot);
-    base[tid] = dbase + hist[(int64_t)tid * nblk + blockIdx.x];
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const int64_t tile = (int64_t)blockIdx.x * kTile;
-    for (int r = 0; r < kItems; ++r) {
+    const int cnt = n - tile < kTile ? (int)(n - tile) : kTile;
+    uint32_t tot;
+    const uint32_t dbase = block_exclusive_scan(total[tid], lds, tot);
+    gbase[tid] = dbase + hist[(int64_t)tid * nblk + blockIdx.x];
+    run[tid] = 0;
+    toff[tid] = 0;
+    __syncthreads();
+    uint64_t k[kItems];
+    int32_t v[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int idx = j * kBlock + tid;
+        k[j] = idx < cnt ? kin[tile + idx] : 0ull;
+        v[j] = idx < cnt ? vin[tile + idx] : 0;
+        if (idx < cnt) atomicAdd(&toff[(uint32_t)(k[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = toff[tid];
+    __syncthreads();
+    toff[tid] = block_exclusive_scan(c, lds, tot);
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
         __syncthreads();
-        const int64_t i = tile + r * kBlock + tid;
-        const bool valid = i < n;
-        const uint64_t k = valid ? kin[i] : 0ull;
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const bool valid = j * kBlock + tid < cnt;
+        const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -171,22 +209,32 @@ __global__ void k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = __popcll(peers & lt);
         if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t off = base[d];
+            uint32_t off = toff[d] + run[d] + __popcll(peers & lt);
             for (int w = 0; w < wid; ++w) off += wcnt[w][d];
-            const uint32_t pos = off + rank;
-            kout[pos] = k;
-            vout[pos] = vin[i];
+            sk[off] = k[j];
+            sv[off] = v[j];
         }
         __syncthreads();
         uint32_t add = 0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
-        base[tid] += add;
-        __syncthreads();
+        run[tid] += add;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int p = j * kBlock + tid;
+        if (p < cnt) {
+            const uint64_t key = sk[p];
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            const uint32_t pos = gbase[d] + (uint32_t)p - toff[d];
+            kout[pos] = key;
+            vout[pos] = sv[p];
+            if (ps) ps[pos] = pin[sv[p]];   // last pass: positions into key order
+        }
     }
 }
 
@@ -244,6 +292,105 @@ __device__ inline PointLevels point_levels(const uint64_t *keys, int64_t n, int6
     }
     r.ll = lam + 1 < max_depth ? lam + 1 : max_depth;
     return r;
+}
+
+// Levels for leaf_max <= kWinMax: the window levels L(j) for the tile's windows are
+// formed in LDS from the keys, and lambda(i) is the maximum over the windows
+// containing i.  Points are striped over threads (coalesced); per-level start
+// counts come from wave ballots.
+constexpr int kWinMax = 1024;
+__global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, int64_t n, int leaf_max,
+                                                        int max_depth, uint8_t *dlev, uint8_t *llev,
+                                                        uint32_t *blkcnt, int nblk) {
+    __shared__ int8_t Ls[kTile + kWinMax];
+    __shared__ uint32_t wc[kBlock / 64][kDepth + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
+    const int64_t m = n - leaf_max;
+    for (int idx = tid; idx < kTile + leaf_max; idx += kBlock) {
+        const int64_t j = tile - leaf_max + idx;
+        Ls[idx] = (j >= 0 && j < m) ? (int8_t)common_level(keys[j], keys[j + leaf_max]) : (int8_t)-1;
+    }
+    if (tid <= kDepth)
+        for (int w = 0; w < kBlock / 64; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    uint32_t mycnt[kDepth + 1];
+#pragma unroll
+    for (int l = 0; l <= kDepth; ++l) mycnt[l] = 0;
+    for (int r = 0; r < kItems; ++r) {
+        const int off = r * kBlock + tid;
+        const int64_t i = tile + off;
+        int d = 255, ll = 0;
+        if (i < n) {
+            if (i == 0) d = 0;
+            else {
+                const uint64_t x = keys[i] ^ keys[i - 1];
+                d = (x == 0) ? kDepth + 1 : kDepth - (63 - __clzll((long long)x)) / 3;
+            }
+            int lam = -1;
+            for (int k = 0; k <= leaf_max; ++k) {
+                const int v = Ls[off + k];
+                lam = v > lam ? v : lam;
+            }
+            ll = lam + 1 < max_depth ? lam + 1 : max_depth;
+            dlev[i] = (uint8_t)d;
+            llev[i] = (uint8_t)ll;
+        }
+#pragma unroll
+        for (int l = 0; l <= kDepth; ++l) mycnt[l] += __popcll(__ballot(d <= l && l <= ll));
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int l = 0; l <= kDepth; ++l) wc[wid][l] = mycnt[l];
+    __syncthreads();
+    if (tid <= kDepth) {
+        uint32_t c = 0;
+        for (int w = 0; w < kBlock / 64; ++w) c += wc[w][tid];
+        blkcnt[(int64_t)tid * nblk + blockIdx.x] = c;
+    }
+}
+
+// Node emission with striped points: for every level, the rank of a starting
+// point among the block's starts at that level (in point order) from ballots,
+// wave offsets and a running count per level.
+__global__ void __launch_bounds__(kBlock) k_emit_tile(const uint8_t *dlev, const uint8_t *llev,
+                                                      int64_t n, const uint32_t *blkoff, int nblk,
+                                                      const int64_t *level_off, int32_t *nfirst,
+                                                      int32_t *nlevel) {
+    __shared__ uint32_t wc[kBlock / 64][kDepth + 1];
+    __shared__ uint32_t run[kDepth + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    if (tid <= kDepth) run[tid] = 0;
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = tile + r * kBlock + tid;
+        const int d = i < n ? dlev[i] : 255;
+        const int ll = i < n ? llev[i] : 0;
+        uint64_t masks[kDepth + 1];
+#pragma unroll
+        for (int l = 0; l <= kDepth; ++l) {
+            masks[l] = __ballot(d <= l && l <= ll);
+            if (lane == 0) wc[wid][l] = __popcll(masks[l]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l <= kDepth; ++l) {
+            if (d <= l && l <= ll) {
+                uint32_t off = run[l] + __popcll(masks[l] & lt);
+                for (int w = 0; w < wid; ++w) off += wc[w][l];
+                const int64_t pos = level_off[l] + blkoff[(int64_t)l * nblk + blockIdx.x] + off;
+                nfirst[pos] = (int32_t)i;
+                nlevel[pos] = l;
+            }
+        }
+        __syncthreads();
+        if (tid <= kDepth) {
+            uint32_t add = 0;
+            for (int w = 0; w < kBlock / 64; ++w) add += wc[w][tid];
+            run[tid] += add;
+        }
+    }
 }
 
 __global__ void k_levels(const uint64_t *keys, int64_t n, int leaf_max, int max_depth,
@@ -341,7 +488,14 @@ __global__ void k_nodes(const uint64_t *keys, int64_t n, const uint8_t *llev, in
         const int sh = 3 * (kDepth - l);
         prefix = l == 0 ? 0ull : (keys[i] >> sh);
         const uint64_t next = (prefix + 1ull) << sh;
-        end = lower_bound_u64(keys, i + 1, n, next);
+        // gallop from i: most nodes are small, so the bracket stays near i
+        int64_t lo = i + 1, step = 1, hi = i + 1;
+        while (hi < n && keys[hi] < next) {
+            lo = hi + 1;
+            hi = i + 1 + step;
+            step <<= 1;
+        }
+        end = lower_bound_u64(keys, lo, hi < n ? hi : n, next);
     }
     ncount[v] = (int32_t)(end - i);
     ndigit[v] = l > 0 ? (int32_t)(prefix & 7ull) : 0;
@@ -371,22 +525,30 @@ __global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *lev
     }
 }
 
-__global__ void k_gather3(const float *x, const float *y, const float *z, const int32_t *perm,
-                          int64_t n, float *xs, float *ys, float *zs, int32_t *iperm) {
+__global__ void k_inverse_perm(const int32_t *perm, int64_t n, int32_t *iperm) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t j = perm[i];
-    xs[i] = x[j];
-    ys[i] = y[j];
-    zs[i] = z[j];
-    iperm[j] = (int32_t)i;
+    iperm[perm[i]] = (int32_t)i;
 }
 
 }  // namespace
 
+int ensure_iperm(msp_tree *t, hipStream_t s) {
+    if (t->iperm_valid) return MSP_OK;
+    MSP_TRY(t->iperm.ensure((t->n > 0 ? t->n : 1) * 4));
+    if (t->n > 0) {
+        hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(t->n, kBlock)), dim3(kBlock), 0, s,
+                           t->perm.as<int32_t>(), t->n, t->iperm.as<int32_t>());
+        MSP_CHECK_LAUNCH();
+    }
+    t->iperm_valid = true;
+    return MSP_OK;
+}
+
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
                int max_depth, hipStream_t s) {
     t->built = false;
+    t->iperm_valid = false;
     t->lists_valid = false;
     t->node_moments_level = -1;
     t->n = n;
@@ -407,7 +569,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
             PhaseScope ps(&t->timing, PH_BBOX, s);
             hipLaunchKernelGGL(k_bbox_partial, dim3(parts), dim3(kBlock), 0, s, x, y, z, n, part, bad);
             MSP_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, parts, out);
+            hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, part, parts, out);
             MSP_CHECK_LAUNCH();
         }
         float host[8];
@@ -436,6 +598,8 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     // keys and sort
     MSP_TRY(t->keys.ensure(nb * 8));
     MSP_TRY(t->keys2.ensure(nb * 8));
+    MSP_TRY(t->pin.ensure(nb * 16));
+    MSP_TRY(t->ps.ensure(nb * 16));
     MSP_TRY(t->perm.ensure(nb * 4));
     MSP_TRY(t->perm2.ensure(nb * 4));
     const int nblk = (int)((n + kTile - 1) / kTile) > 0 ? (int)((n + kTile - 1) / kTile) : 1;
@@ -445,7 +609,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         PhaseScope ps(&t->timing, PH_KEYS, s);
         hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
                            g.lo[0], g.lo[1], g.lo[2], g.scale, t->keys.as<uint64_t>(),
-                           t->perm.as<int32_t>());
+                           t->perm.as<int32_t>(), t->pin.as<float4>());
         MSP_CHECK_LAUNCH();
         }
         PhaseScope ps(&t->timing, PH_SORT, s);
@@ -459,8 +623,9 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
             MSP_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
             MSP_CHECK_LAUNCH();
+            const bool last = pass == 7;
             hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift,
-                               hist, total, nblk);
+                               hist, total, nblk, t->pin.as<float4>(), last ? t->ps.as<float4>() : nullptr);
             MSP_CHECK_LAUNCH();
             std::swap(ka, kb);
             std::swap(va, vb);
@@ -483,6 +648,12 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     uint32_t *ltot = blkcnt + (size_t)kMaxLevels * nblk;
     if (n > 0) {
         PhaseScope ps(&t->timing, PH_LEVELS, s);
+        if (leaf_max <= kWinMax) {
+            hipLaunchKernelGGL(k_levels_tile, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
+                               leaf_max, max_depth, t->dlev.as<uint8_t>(), t->llev.as<uint8_t>(),
+                               blkcnt, nblk);
+            MSP_CHECK_LAUNCH();
+        } else {
         if (m > 0) {
             hipLaunchKernelGGL(k_window_L, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s,
                                t->keys.as<uint64_t>(), m, leaf_max, L);
@@ -496,6 +667,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
                            leaf_max, max_depth, pre, suf, m, W, t->dlev.as<uint8_t>(),
                            t->llev.as<uint8_t>(), blkcnt, nblk);
         MSP_CHECK_LAUNCH();
+        }
         hipLaunchKernelGGL(k_level_scan, dim3(kDepth + 1), dim3(kBlock), 0, s, blkcnt, nblk, ltot);
         MSP_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, ltot,
@@ -522,7 +694,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     {
     PhaseScope ps_nodes(&t->timing, PH_NODES, s);
     if (n > 0) {
-        hipLaunchKernelGGL(k_emit, dim3(nblk), dim3(kBlock), 0, s, t->dlev.as<uint8_t>(),
+        hipLaunchKernelGGL(k_emit_tile, dim3(nblk), dim3(kBlock), 0, s, t->dlev.as<uint8_t>(),
                            t->llev.as<uint8_t>(), n, blkcnt, nblk, t->d_level_off.as<int64_t>(),
                            t->nfirst.as<int32_t>(), t->nlevel.as<int32_t>());
         MSP_CHECK_LAUNCH();
@@ -544,18 +716,6 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     MSP_CHECK_LAUNCH();
     }
 
-    // sorted coordinates
-    MSP_TRY(t->xs.ensure(nb * 4));
-    MSP_TRY(t->ys.ensure(nb * 4));
-    MSP_TRY(t->zs.ensure(nb * 4));
-    MSP_TRY(t->iperm.ensure(nb * 4));
-    if (n > 0) {
-        PhaseScope ps(&t->timing, PH_GATHER, s);
-        hipLaunchKernelGGL(k_gather3, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z,
-                           t->perm.as<int32_t>(), n, t->xs.as<float>(), t->ys.as<float>(),
-                           t->zs.as<float>(), t->iperm.as<int32_t>());
-        MSP_CHECK_LAUNCH();
-    }
     t->built = true;
     return MSP_OK;
 }

@@ -195,3 +195,22 @@ def test_edge_cases():
         kw.update(bad)
         with pytest.raises(msp.MspError):
             tree.forward(d["w"], d["tgt"], **kw)
+
+
+@pytest.mark.parametrize("p,level", [(8, 4), (5, 5), (3, 3)])
+def test_m2l_matrix_cores_match_vector_path(p, level):
+    """The MFMA translation passes give the vector-ALU passes' Taylor grid up to
+    float32 rounding (checks the matrix-core lane layout), on ragged grids."""
+    import paper_2301_10570_amd as msp
+    wl = synth.config(3, 0.03)
+    print(f"M2L mfma vs valu p={p} level={level}", flush=True)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"])
+    u_m = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, level=level, route="fgt").cpu().numpy()
+    C_m = tree.debug_buffer(1).cpu().numpy()
+    u_v = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, level=level, route="fgt", m2l="valu").cpu().numpy()
+    C_v = tree.debug_buffer(1).cpu().numpy()
+    scale = np.abs(C_v).max()
+    assert np.abs(C_m - C_v).max() <= 1e-5 * scale
+    tgt = wl.a > 0
+    np.testing.assert_allclose(u_m[tgt], u_v[tgt], rtol=1e-5)
