@@ -65,7 +65,12 @@ enum msp_flags {
     MSP_EXCLUDE_SELF = 1u << 0,
     /* Run the Hermite-to-Taylor translation on the vector ALUs instead of the
      * matrix cores (same result up to float32 rounding; for cross-checks). */
-    MSP_M2L_VALU = 1u << 1
+    MSP_M2L_VALU = 1u << 1,
+    /* Two-level variant of the expansion route: P2M and L2P at the 4x4x4
+     * sub-cells two levels below the expansion level with fewer terms, joined to
+     * it by M2M and L2L shifts (used when p is 6..8 and cells hold >= 512 points;
+     * msp_fgt_info.fine_terms reports it). */
+    MSP_TWO_LEVEL = 1u << 2
 };
 
 typedef struct msp_tree msp_tree; /* opaque handle */
@@ -117,6 +122,8 @@ typedef struct msp_fgt_info {
     double rho;           /* cell half-side / sigma on that level */
     double fgt_cost;      /* cost-model estimates (arbitrary units, same scale) */
     double direct_cost;
+    int32_t fine_terms;   /* > 0: P2M and L2P run at the sub-cells two levels below `level`
+                             with this many terms per axis, joined to `level` by M2M and L2L */
 } msp_fgt_info;
 
 /* Status text for a code (static string). */
@@ -156,7 +163,9 @@ int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info);
  * FGT route: moments (Eq. (7)) of the sources in every cell of one octree level,
  * Hermite-to-Taylor translation between every pair of cells of that level (the
  * transform the paper's Eqs. (6)-(7) combine), and evaluation of each cell's
- * Taylor series (Eq. (6)) at its targets.  Direct route: Eq. (8) summed over all
+ * Taylor series (Eq. (6)) at its targets.  With MSP_TWO_LEVEL, moments and
+ * evaluation move to the sub-cells two levels down with fewer terms, joined to
+ * the expansion level by M2M and L2L shifts (msp_fgt_info.fine_terms).  Direct route: Eq. (8) summed over all
  * source leaves within the cutoff of each target leaf.  The direct route
  * synchronises `stream` once when its interaction lists are (re)built. */
 int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,

@@ -28,6 +28,7 @@ ROUTES = {"auto": 0, "fgt": 1, "direct": 2}
 ROUTE_NAMES = {v: k for k, v in ROUTES.items()}
 EXCLUDE_SELF = 1
 M2L_VALU = 2
+TWO_LEVEL = 4
 
 
 class MspError(RuntimeError):
@@ -59,7 +60,7 @@ class FgtParams(ctypes.Structure):
 class FgtInfo(ctypes.Structure):
     _fields_ = [("route", ctypes.c_int32), ("level", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
                 ("p", ctypes.c_int32), ("rho", ctypes.c_double), ("fgt_cost", ctypes.c_double),
-                ("direct_cost", ctypes.c_double)]
+                ("direct_cost", ctypes.c_double), ("fine_terms", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -121,8 +122,9 @@ def _ptr(t: torch.Tensor | None, dtype: torch.dtype, n: int | None, name: str):
     return t.data_ptr() if t.numel() else None
 
 
-def _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l="mfma") -> FgtParams:
+def _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l="mfma", two_level=False) -> FgtParams:
     flags = (EXCLUDE_SELF if exclude_self else 0) | (M2L_VALU if m2l == "valu" else 0)
+    flags |= TWO_LEVEL if two_level else 0
     if m2l not in ("mfma", "valu"):
         raise ValueError(f"m2l must be 'mfma' or 'valu', got {m2l!r}")
     return FgtParams(int(p), int(level), float(sigma), float(cutoff_sigmas),
@@ -182,15 +184,17 @@ class Tree:
         _check(_lib.msp_tree_export(self._h, ctypes.byref(arr), _stream()), "msp_tree_export")
         return out
 
-    def plan(self, sigma, p=8, level=-1, route="auto", cutoff_sigmas=4.5, exclude_self=False) -> dict:
-        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+    def plan(self, sigma, p=8, level=-1, route="auto", cutoff_sigmas=4.5, exclude_self=False,
+             two_level=False) -> dict:
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, two_level=two_level)
         inf = FgtInfo()
         _check(_lib.msp_fgt_plan(self._h, ctypes.byref(prm), ctypes.byref(inf)), "msp_fgt_plan")
         return {"route": ROUTE_NAMES[inf.route], "level": inf.level, "grid": list(inf.grid), "p": inf.p,
-                "rho": inf.rho, "fgt_cost": inf.fgt_cost, "direct_cost": inf.direct_cost}
+                "rho": inf.rho, "fgt_cost": inf.fgt_cost, "direct_cost": inf.direct_cost,
+                "fine_terms": inf.fine_terms}
 
     def forward(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
-                exclude_self=False, out=None, m2l="mfma"):
+                exclude_self=False, out=None, m2l="mfma", two_level=False):
         """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere."""
         n = self.n
         pw = _ptr(w, torch.float32, n, "w")
@@ -198,7 +202,7 @@ class Tree:
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=w.device)
         po = _ptr(out, torch.float32, n, "out")
-        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l)
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
         _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
         return out
 

@@ -97,7 +97,7 @@ static int check_params(const msp_fgt_params *prm) {
     if (!(prm->sigma > 0.f) || !std::isfinite(prm->sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
     if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
     if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
-    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU))
+    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL))
         return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
     if (std::isnan(prm->cutoff_sigmas)) return fail(MSP_EINVAL, "cutoff_sigmas is NaN");
     return MSP_OK;
@@ -212,6 +212,7 @@ int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info) {
     info->rho = pl.rho;
     info->fgt_cost = pl.fgt_cost;
     info->direct_cost = pl.direct_cost;
+    info->fine_terms = pl.route == MSP_ROUTE_FGT ? pl.pf : 0;
     return MSP_OK;
 }
 

@@ -31,6 +31,26 @@ static const double kRhoMax[kMaxP] = {2e-5, 0.004, 0.025, 0.07, 0.16, 0.25, 0.34
 
 double rho_max_for_p(int p) { return kRhoMax[p - 1]; }
 
+// Terms kept at the sub-cells two levels below the expansion level: the smallest
+// pf whose per-axis tail sum_{b>=pf} (sqrt2 rho_f)^b / sqrt(b!) (the size of the
+// dropped Taylor terms, by Cramer's inequality) is below 1e-5.
+static int fine_terms(int p, double rho_f) {
+    const double x = std::sqrt(2.0) * rho_f;
+    for (int pf = 2; pf < p; ++pf) {
+        double tail = 0.0;
+        for (int b = pf; b < pf + 60; ++b) tail += std::exp(b * std::log(x) - 0.5 * std::lgamma(b + 1.0));
+        if (tail <= 1e-5) return pf;
+    }
+    return p;
+}
+
+static size_t two_level_lds(int p, int pf) {
+    const size_t a = 64 * pf * pf * pf + 16 * pf * pf * p + 4 * pf * p * p + 4 * pf * pf * pf;
+    const size_t b = (size_t)p * p * p + 4 * pf * p * p + 16 * pf * pf * p + 64 * pf * pf * pf;
+    return 4 * (a > b ? a : b);
+}
+
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -331,6 +351,290 @@ __global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n,
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Two-level variant.  Moments are formed at the 4 x 4 x 4 sub-cells two levels
+// below the expansion level with pf < p terms (P2M), shifted to the expansion
+// cell with M2M, translated there (M2L), and shifted back to the sub-cells with
+// L2L truncated to pf terms for L2P.  The sub-cells of a cell are contiguous in
+// key order, and sub-cell s = (d1 << 3) | d2 (two octant digits) sits at offset
+// (k - 1.5) h_f along each axis, k in 0..3, from the cell centre.  Both shifts are
+// done as one separable contraction over the 64 sub-cells, axis by axis:
+//   M2M  A[a] = sum_s sum_{g<=a, g<pf} a_s[g] prod_k d_k^(a_k-g_k)/(a_k-g_k)!
+//   L2L  c_s[b] = sum_{g>=b} C[g] prod_k binom(g_k, b_k) d_k^(g_k-b_k),  b < pf
+// ---------------------------------------------------------------------------------
+
+// Orders LDS accesses among the lanes of one wavefront (the lanes run in lockstep;
+// this keeps the compiler from moving LDS reads above the wave's writes and waits
+// for them to land).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int sub_coord(int s, int axis) {
+    const int d1 = s >> 3, d2 = s & 7, sh = 2 - axis;
+    return (((d1 >> sh) & 1) << 1) | ((d2 >> sh) & 1);
+}
+
+// Shift tables for the four sub-cell offsets along an axis: m2m[k][m] = d_k^m/m!,
+// l2l[k][g][b] = binom(g, b) d_k^(g-b), d_k = (k - 1.5) * hf / sigma.
+template <int P>
+__device__ inline void shift_tables(double hf_over_sigma, float (*m2m)[P], float (*l2l)[P][P]) {
+    for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
+        const int k = e / P, m = e % P;
+        const double d = (k - 1.5) * hf_over_sigma;
+        double v = 1.0;
+        for (int q = 1; q <= m; ++q) v *= d / q;
+        m2m[k][m] = (float)v;
+    }
+    for (int e = threadIdx.x; e < 4 * P * P; e += blockDim.x) {
+        const int k = e / (P * P), g = (e / P) % P, b = e % P;
+        const double d = (k - 1.5) * hf_over_sigma;
+        double v = 0.0;
+        if (g >= b) {
+            double binom = 1.0;
+            for (int q = 1; q <= b; ++q) binom = binom * (g - b + q) / q;
+            v = binom;
+            for (int q = 0; q < g - b; ++q) v *= d;
+        }
+        l2l[k][g][b] = (float)v;
+    }
+}
+
+template <int P, int PF>
+__global__ void __launch_bounds__(kBlock) k_p2m_2lvl(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                     const int32_t *perm, const float *w, int level,
+                                                     int Gx, int Gy, int Gz, double lox, double loy,
+                                                     double loz, double cell, double inv_sigma, float *A) {
+    constexpr int P3 = P * P * P;
+    constexpr int pf = PF, pf2 = PF * PF, pf3 = PF * PF * PF;
+    constexpr int NG = 64 / pf2;                             // point groups per wave
+    __shared__ float As[64 * pf3];                           // [s][gz][gy][gx]
+    __shared__ float B1[16 * pf2 * P];                       // [sy][sz][gz][gy][ax]
+    __shared__ float B2[4 * pf * P * P];                     // [sz][gz][ay][ax]
+    __shared__ float sm2m[4][P];
+    __shared__ float sl2l[4][P][P];
+    __shared__ int64_t bnd[65];
+    __shared__ float4 stage[kBlock / 64][64];
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const double hf = cell * 0.25;
+    {
+        const uint64_t prefix = morton3((uint32_t)kx, (uint32_t)ky, (uint32_t)kz);
+        const int shf = 3 * (kDepth - level - 2);
+        if (tid <= 64) {
+            const uint64_t key = tid < 64 ? ((prefix << 6) | (uint64_t)tid) << shf
+                                          : ((prefix + 1ull) << 6) << shf;
+            bnd[tid] = lower_bound_u64(keys, 0, n, key);
+        }
+    }
+    shift_tables<P>(hf * inv_sigma, sm2m, sl2l);
+    __syncthreads();
+    const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
+    // fine moments: wave w takes sub-cells w, w+4, ...  Each chunk of up to 64
+    // points is first staged by the wave (one point per lane, so the weight
+    // gathers are independent), then lane = (group, gy, gz) keeps the pf moments
+    // along x and walks every NG-th staged point.
+    const int grp = lane / pf2, pair = lane % pf2, gy = pair % pf, gz = pair / pf;
+    const bool active = grp < NG;
+    float4 *stg = stage[wid];
+    for (int s0 = 0; s0 < 64; s0 += 4) {
+        const int s = s0 + wid;
+        const double sx = cx + (sub_coord(s, 0) - 1.5) * hf, sy = cy + (sub_coord(s, 1) - 1.5) * hf,
+                     sz = cz + (sub_coord(s, 2) - 1.5) * hf;
+        float acc[PF];
+#pragma unroll
+        for (int a = 0; a < PF; ++a) acc[a] = 0.f;
+        for (int64_t c0 = bnd[s]; c0 < bnd[s + 1]; c0 += 64) {
+            const int m = bnd[s + 1] - c0 < 64 ? (int)(bnd[s + 1] - c0) : 64;
+            if (lane < m) {
+                const float4 q = ps[c0 + lane];
+                stg[lane] = make_float4((float)(((double)q.x - sx) * inv_sigma),
+                                        (float)(((double)q.y - sy) * inv_sigma),
+                                        (float)(((double)q.z - sz) * inv_sigma), w[perm[c0 + lane]]);
+            }
+            wave_sync();
+            if (active) {
+                for (int j = grp; j < m; j += NG) {
+                    const float4 q = stg[j];
+                    float f = q.w;
+#pragma unroll
+                    for (int k = 1; k < PF; ++k) {
+                        f = k <= gy ? f * q.y : f;
+                        f = k <= gz ? f * q.z : f;
+                    }
+#pragma unroll
+                    for (int a = 0; a < PF; ++a) {
+                        acc[a] += f;
+                        f *= q.x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+        // point groups in order (lanes pf2 apart), then 1/(gx! gy! gz!)
+#pragma unroll
+        for (int a = 0; a < PF; ++a) {
+            float tot = 0.f;
+            for (int q = 0; q < NG; ++q) tot += __shfl(acc[a], pair + q * pf2, 64);
+            acc[a] = tot;
+        }
+        if (grp == 0) {
+            float fy = 1.f, fz = 1.f;
+            for (int k = 2; k <= gy; ++k) fy *= (float)k;
+            for (int k = 2; k <= gz; ++k) fz *= (float)k;
+            float fx = 1.f;
+#pragma unroll
+            for (int a = 0; a < PF; ++a) {
+                if (a > 1) fx *= (float)a;
+                As[s * pf3 + (gz * pf + gy) * pf + a] = acc[a] / (fx * fy * fz);
+            }
+        }
+    }
+    __syncthreads();
+    // x: B1[sy][sz][gz][gy][ax] = sum_sx sum_{gx<=ax} As[s][gz][gy][gx] m2m[sx][ax-gx]
+    for (int e = tid; e < 16 * pf2 * P; e += kBlock) {
+        const int ax = e % P, gy = (e / P) % pf, zz = (e / (P * pf)) % pf, yzs = e / (P * pf2);
+        const int syi = yzs >> 2, szi = yzs & 3;
+        float acc = 0.f;
+        for (int sxi = 0; sxi < 4; ++sxi) {
+            // sub-cell index with coordinates (sxi, syi, szi)
+            const int d1 = ((sxi >> 1) << 2) | ((syi >> 1) << 1) | (szi >> 1);
+            const int d2 = ((sxi & 1) << 2) | ((syi & 1) << 1) | (szi & 1);
+            const float *a_s = As + ((d1 << 3) | d2) * pf3 + (zz * pf + gy) * pf;
+            for (int gx = 0; gx <= ax && gx < pf; ++gx) acc = fmaf(a_s[gx], sm2m[sxi][ax - gx], acc);
+        }
+        B1[e] = acc;
+    }
+    __syncthreads();
+    // y: B2[sz][gz][ay][ax] = sum_sy sum_{gy<=ay} B1[sy][sz][gz][gy][ax] m2m[sy][ay-gy]
+    for (int e = tid; e < 4 * pf * P * P; e += kBlock) {
+        const int ax = e % P, ay = (e / P) % P, zz = (e / (P * P)) % pf, szi = e / (P * P * pf);
+        float acc = 0.f;
+        for (int syi = 0; syi < 4; ++syi) {
+            const float *b1 = B1 + (((syi << 2) | szi) * pf + zz) * pf * P;
+            for (int gy = 0; gy <= ay && gy < pf; ++gy) acc = fmaf(b1[gy * P + ax], sm2m[syi][ay - gy], acc);
+        }
+        B2[e] = acc;
+    }
+    __syncthreads();
+    // z: A[az][ay][ax] = sum_sz sum_{gz<=az} B2[sz][gz][ay][ax] m2m[sz][az-gz]
+    const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    for (int e = tid; e < P3; e += kBlock) {
+        const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
+        float acc = 0.f;
+        for (int szi = 0; szi < 4; ++szi)
+            for (int zz = 0; zz <= az && zz < pf; ++zz)
+                acc = fmaf(B2[((szi * pf + zz) * P + ay) * P + ax], sm2m[szi][az - zz], acc);
+        A[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax] = acc;
+    }
+}
+
+template <int P, int PF>
+__global__ void __launch_bounds__(kBlock) k_l2p_2lvl(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                     const int32_t *perm, const uint8_t *is_target,
+                                                     const float *w, int subtract_self, int level,
+                                                     int Gx, int Gy, int Gz, double lox, double loy,
+                                                     double loz, double cell, double inv_sigma,
+                                                     const float *C, float *u_out) {
+    constexpr int P3 = P * P * P;
+    constexpr int pf = PF, pf2 = PF * PF, pf3 = PF * PF * PF;
+    __shared__ float sC[P3];                 // [az][ay][ax]
+    __shared__ float D1[4 * pf * P * P];     // [sz][bz][ay][ax]
+    __shared__ float D2[16 * pf2 * P];       // [sy][sz][bz][by][ax]
+    __shared__ float cs[16 * pf3];           // [s - s_group][bz][by][bx]
+    __shared__ float sm2m[4][P];
+    __shared__ float sl2l[4][P][P];
+    __shared__ int64_t bnd[65];
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    const int tid = threadIdx.x;
+    const double hf = cell * 0.25;
+    {
+        const uint64_t prefix = morton3((uint32_t)kx, (uint32_t)ky, (uint32_t)kz);
+        const int shf = 3 * (kDepth - level - 2);
+        if (tid <= 64) {
+            const uint64_t key = tid < 64 ? ((prefix << 6) | (uint64_t)tid) << shf
+                                          : ((prefix + 1ull) << 6) << shf;
+            bnd[tid] = lower_bound_u64(keys, 0, n, key);
+        }
+    }
+    shift_tables<P>(hf * inv_sigma, sm2m, sl2l);
+    const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    for (int e = tid; e < P3; e += kBlock) {
+        const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
+        sC[e] = C[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax];
+    }
+    __syncthreads();
+    if (bnd[0] == bnd[64]) return;
+    // z: D1[sz][bz][ay][ax] = sum_{gz>=bz} C[gz][ay][ax] l2l[sz][gz][bz]
+    for (int e = tid; e < 4 * pf * P * P; e += kBlock) {
+        const int axy = e % (P * P), bz = (e / (P * P)) % pf, szi = e / (P * P * pf);
+        float acc = 0.f;
+        for (int gz = bz; gz < P; ++gz) acc = fmaf(sC[gz * P * P + axy], sl2l[szi][gz][bz], acc);
+        D1[e] = acc;
+    }
+    __syncthreads();
+    // y: D2[sy][sz][bz][by][ax] = sum_{gy>=by} D1[sz][bz][gy][ax] l2l[sy][gy][by]
+    for (int e = tid; e < 16 * pf2 * P; e += kBlock) {
+        const int ax = e % P, by = (e / P) % pf, bz = (e / (P * pf)) % pf, yzs = e / (P * pf2);
+        const int syi = yzs >> 2, szi = yzs & 3;
+        const float *d1 = D1 + (szi * pf + bz) * P * P;
+        float acc = 0.f;
+        for (int gy = by; gy < P; ++gy) acc = fmaf(d1[gy * P + ax], sl2l[syi][gy][by], acc);
+        D2[e] = acc;
+    }
+    __syncthreads();
+    // x stage and evaluation in four groups of 16 sub-cells:
+    //   cs[s][bz][by][bx] = sum_{gx>=bx} D2[sy][sz][bz][by][gx] l2l[sx][gx][bx]
+    // then wave w evaluates sub-cells w, w+4, ... of the group at their targets
+    const int lane = tid & 63, wid = tid >> 6;
+    const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
+    for (int sg = 0; sg < 64; sg += 16) {
+        for (int e = tid; e < 16 * pf3; e += kBlock) {
+            const int bx = e % pf, by = (e / pf) % pf, bz = (e / pf2) % pf, sidx = sg + e / pf3;
+            const int sxi = sub_coord(sidx, 0), syi = sub_coord(sidx, 1), szi = sub_coord(sidx, 2);
+            const float *d2 = D2 + ((((syi << 2) | szi) * pf + bz) * pf + by) * P;
+            float acc = 0.f;
+            for (int gx = bx; gx < P; ++gx) acc = fmaf(d2[gx], sl2l[sxi][gx][bx], acc);
+            cs[e] = acc;
+        }
+        __syncthreads();
+        for (int s0 = 0; s0 < 16; s0 += 4) {
+            const int sidx = sg + s0 + wid;
+            const double sx = cx + (sub_coord(sidx, 0) - 1.5) * hf, sy = cy + (sub_coord(sidx, 1) - 1.5) * hf,
+                         sz = cz + (sub_coord(sidx, 2) - 1.5) * hf;
+            const float *c = cs + (s0 + wid) * pf3;
+            for (int64_t i = bnd[sidx] + lane; i < bnd[sidx + 1]; i += 64) {
+                const float4 q = ps[i];
+                const float X = (float)(((double)q.x - sx) * inv_sigma);
+                const float Y = (float)(((double)q.y - sy) * inv_sigma);
+                const float Z = (float)(((double)q.z - sz) * inv_sigma);
+                float uz = 0.f;
+#pragma unroll
+                for (int bz = pf - 1; bz >= 0; --bz) {
+                    float uy = 0.f;
+#pragma unroll
+                    for (int by = pf - 1; by >= 0; --by) {
+                        const float *row = c + (bz * pf + by) * pf;
+                        float ux = row[pf - 1];
+#pragma unroll
+                        for (int bx = pf - 2; bx >= 0; --bx) ux = fmaf(ux, X, row[bx]);
+                        uy = fmaf(uy, Y, ux);
+                    }
+                    uz = fmaf(uz, Z, uy);
+                }
+                const int32_t j = perm[i];
+                const bool tg = !is_target || is_target[j];
+                u_out[j] = tg ? (subtract_self ? uz - w[j] : uz) : 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Weights and target flags into key order (the w slot of the sorted positions).
 __global__ void k_stage(const float *w, const uint8_t *is_target, const int32_t *perm, int64_t n,
                         float4 *ps, uint8_t *tflag) {
@@ -357,10 +661,38 @@ struct GridArgs {
     float *u_out;
 };
 
+template <int P, int PF>
+int launch_2lvl(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, const float *C, float *A,
+                const GridArgs &ga, hipStream_t s) {
+    const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
+    if (!l2p)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m_2lvl<P, PF>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
+                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w,
+                           pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2],
+                           pl.cell, inv_sigma, A);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p_2lvl<P, PF>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
+                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
+                           ga.is_target, ga.w, ga.subtract_self, pl.level, pl.G[0], pl.G[1], pl.G[2],
+                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, ga.u_out);
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+
 template <int P>
 int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, const float *C,
                    float *A, const GridArgs &ga, hipStream_t s) {
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
+    if constexpr (P >= 6 && P <= 8) {
+        if (pl.pf > 0) {
+            switch (pl.pf) {
+                case 3: return launch_2lvl<P, 3>(t, pl, inv_sigma, l2p, C, A, ga, s);
+                case 4: return launch_2lvl<P, 4>(t, pl, inv_sigma, l2p, C, A, ga, s);
+                case 5: return launch_2lvl<P, 5>(t, pl, inv_sigma, l2p, C, A, ga, s);
+                default: return fail(MSP_EINVAL, "two-level terms %d not built", pl.pf);
+            }
+        }
+    }
     if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
@@ -433,6 +765,15 @@ int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *pl) {
         return fail(MSP_ENOSPC, "expansion grid %dx%dx%d at p=%d exceeds %.0f GB", pl->G[0], pl->G[1],
                     pl->G[2], p, kMaxGridBytes / 1e9);
     pl->route = route;
+    // two-level variant (on request): cells must hold many points for the shorter
+    // sub-cell series to pay for the shifts; p 6..8 (LDS budget of the fused kernels)
+    pl->pf = 0;
+    if ((prm->flags & MSP_TWO_LEVEL) && p >= 6 && p <= 8 && level + 2 <= kDepth) {
+        const int pf = fine_terms(p, pl->rho * 0.25);
+        const double per_cell = n / (ncell > 0 ? ncell : 1.0);
+        if (pf >= 3 && pf <= 5 && pf <= p - 2 && per_cell >= 512.0 && two_level_lds(p, pf) <= 60 * 1024)
+            pl->pf = pf;
+    }
     return MSP_OK;
 }
 

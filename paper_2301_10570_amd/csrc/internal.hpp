@@ -147,6 +147,7 @@ struct FgtPlan {
     double rho;
     double cell;      // cell side at `level`
     double fgt_cost, direct_cost;
+    int pf;           // > 0: terms at the sub-cells two levels down (two-level variant)
 };
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
 double rho_max_for_p(int p);

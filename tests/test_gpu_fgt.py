@@ -214,3 +214,28 @@ def test_m2l_matrix_cores_match_vector_path(p, level):
     assert np.abs(C_m - C_v).max() <= 1e-5 * scale
     tgt = wl.a > 0
     np.testing.assert_allclose(u_m[tgt], u_v[tgt], rtol=1e-5)
+
+
+def test_two_level_m2m_l2l(slab):
+    """Moments at sub-cells two levels down with fewer terms, M2M up, M2L, L2L
+    down with truncation: same moment grid as single-level P2M up to the dropped
+    sub-cell terms, and the same accuracy against the oracle."""
+    import paper_2301_10570_amd as msp
+    wl, sel, ref = slab
+    print("two-level (M2M/L2L) vs single-level, full slab p=8", flush=True)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"])
+    plan2 = tree.plan(wl.sigma, p=8, two_level=True)
+    plan1 = tree.plan(wl.sigma, p=8)
+    assert plan2["fine_terms"] > 0 and plan1["fine_terms"] == 0
+    u2 = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=8, two_level=True).cpu().numpy()
+    A2 = tree.debug_buffer(0).cpu().numpy()
+    u1 = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=8).cpu().numpy()
+    A1 = tree.debug_buffer(0).cpu().numpy()
+    assert np.abs(A2 - A1).max() <= 2e-5 * np.abs(A1).max()
+    e2 = rel_err(u2[sel], ref)
+    e1 = rel_err(u1[sel], ref)
+    print(f"  plan={plan2} two-level max rel err {e2.max():.3e}, single-level {e1.max():.3e}")
+    assert e2.max() <= TOL and e1.max() <= TOL
+    tgt = wl.a > 0
+    assert rel_err(u2[tgt], u1[tgt]).max() <= 2e-5
