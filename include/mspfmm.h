@@ -171,6 +171,24 @@ int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info);
 int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
                     const msp_fgt_params *prm, float *u_out, void *stream);
 
+/* Derivatives of L = sum_i g_i u(t_i) over the targets i (the adjoint of
+ * msp_fgt_forward with the same w, is_target and params).  With
+ * K = exp(-|t - s|^2/sigma^2) and v(x) = sum_i g_i K(t_i, x) (the transposed sum,
+ * computed by the same route with weights g at the targets):
+ *   grad_w[j]          = v(x_j)                       (for every point, w_j = 0 included)
+ *   grad_{x,y,z}[k]    = g_k grad u(x_k) + w_k grad v(x_k)
+ *   grad_sigma[0]      = sum_i g_i ((sigma/2) lap u(t_i) + (3/sigma) u(t_i))
+ * The sigma form is the heat equation of the Gaussian, dK/dsigma =
+ * (sigma/2) lap K + (3/sigma) K, applied to the local expansions or the direct
+ * sums.  grad_u: device float32[n] (entries of non-targets are ignored).
+ * grad_w, grad_x, grad_y, grad_z: device float32[n] or NULL (all three position
+ * arrays or none); grad_sigma: device float64[1] or NULL.  Input order throughout.
+ * With MSP_EXCLUDE_SELF the self pair drops out of grad_w (it adds nothing to the
+ * other derivatives). */
+int msp_fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target,
+                     const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                     float *grad_y, float *grad_z, double *grad_sigma, void *stream);
+
 /* All-pairs direct sum on the GPU, Eq. (8), no tree and no cutoff (the baseline
  * that the transform is measured against).  Targets tx,ty,tz: device float32[nt];
  * sources sx,sy,sz,w: device float32[ns]; u: device float32[nt].  The sum over

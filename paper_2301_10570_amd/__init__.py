@@ -4,7 +4,7 @@ Every step of the computation runs in the HIP kernels of the shared library;
 this module checks tensors, passes their device pointers and the current torch
 stream, and turns status codes into exceptions.  PyTorch supplies device memory
 and streams.  The library must have been built (python -m
-paper_2301_10570_amd.build); importing without it raises ImportError.
+paper_2301_10570_amd/build.py); importing without it raises ImportError.
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmspfmm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mspfmm.h")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2301_10570_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python paper_2301_10570_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -78,6 +78,7 @@ _lib.msp_tree_get_info.argtypes = [_vp, ctypes.POINTER(TreeInfo)]
 _lib.msp_tree_export.argtypes = [_vp, ctypes.POINTER(TreeArrays), _vp]
 _lib.msp_fgt_plan.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(FgtInfo)]
 _lib.msp_fgt_forward.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp]
+_lib.msp_fgt_backward.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.msp_direct_sum.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
 _lib.msp_partner_probabilities.argtypes = [_vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _i64, _vp,
                                            _vp, _vp, _vp]
@@ -87,7 +88,7 @@ _lib.msp_tree_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctype
 _lib.msp_phase_name.restype = ctypes.c_char_p
 _lib.msp_phase_name.argtypes = [ctypes.c_int]
 PHASE_COUNT = 24
-for _f in ("msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
+for _f in ("msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_fgt_debug_buffer"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -221,6 +222,32 @@ class Tree:
                 out[_lib.msp_phase_name(k).decode()] = (ms[k], int(cnt[k]))
         return out
 
+    def backward(self, w, grad_u, is_target=None, sigma=100.0, p=8, level=-1, route="auto",
+                 cutoff_sigmas=4.5, exclude_self=False, want=("w", "pos", "sigma")):
+        """Derivatives of sum_i grad_u[i] * u_i (targets only): dict with 'w' [n],
+        'pos' ([n] x, y, z tensors), 'sigma' (float64 [1])."""
+        n = self.n
+        dev = w.device
+        pw = _ptr(w, torch.float32, n, "w")
+        pg = _ptr(grad_u, torch.float32, n, "grad_u")
+        pt = _ptr(is_target, torch.uint8, n, "is_target")
+        out = {}
+        gw = torch.empty(n, dtype=torch.float32, device=dev) if "w" in want else None
+        gpos = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)] if "pos" in want else None
+        gs = torch.zeros(1, dtype=torch.float64, device=dev) if "sigma" in want else None
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+        ptr = lambda x: x.data_ptr() if (x is not None and x.numel()) else None
+        _check(_lib.msp_fgt_backward(self._h, pw, pt, ctypes.byref(prm), pg, ptr(gw),
+                                     *(ptr(g) for g in (gpos or (None, None, None))), ptr(gs), _stream()),
+               "msp_fgt_backward")
+        if gw is not None:
+            out["w"] = gw
+        if gpos is not None:
+            out["pos"] = gpos
+        if gs is not None:
+            out["sigma"] = gs
+        return out
+
     def debug_buffer(self, which: int) -> torch.Tensor:
         """Copy of an internal buffer: 0 moment grid, 1 Taylor grid (last expansion-route
         forward), 2 node moments, 3 node moment flags (last partner call)."""
@@ -267,3 +294,56 @@ def direct_sum(tx, ty, tz, sx, sy, sz, w, sigma, out=None):
     _check(_lib.msp_direct_sum(*ptrs_t, nt, *ptrs_s[:3], ptrs_s[3], ns, float(sigma), po, _stream()),
            "msp_direct_sum")
     return out
+
+
+class _AttractionFn(torch.autograd.Function):
+    """u = msp_fgt_forward(...) with msp_fgt_backward as its adjoint."""
+
+    @staticmethod
+    def forward(ctx, x, y, z, w, sigma, is_target, opts):
+        tree = opts.get("tree") or Tree()
+        tree.build(x, y, z, leaf_max=opts.get("leaf_max", 64))
+        s = float(sigma.item()) if isinstance(sigma, torch.Tensor) else float(sigma)
+        u = tree.forward(w, is_target, sigma=s, p=opts.get("p", 8), route=opts.get("route", "auto"),
+                         cutoff_sigmas=opts.get("cutoff_sigmas", 4.5),
+                         exclude_self=opts.get("exclude_self", False))
+        ctx.tree, ctx.sigma, ctx.opts = tree, s, opts
+        ctx.save_for_backward(w, is_target if is_target is not None else torch.empty(0))
+        ctx.sigma_is_tensor = isinstance(sigma, torch.Tensor)
+        ctx.sigma_dtype = sigma.dtype if ctx.sigma_is_tensor else None
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        w, tg = ctx.saved_tensors
+        tg = tg if tg.numel() else None
+        o = ctx.opts
+        need_pos = any(ctx.needs_input_grad[:3])
+        want = ["w"] if ctx.needs_input_grad[3] else []
+        if need_pos:
+            want.append("pos")
+        if ctx.needs_input_grad[4]:
+            want.append("sigma")
+        if not want:
+            return None, None, None, None, None, None, None
+        g = ctx.tree.backward(w, grad_u.contiguous().float(), tg, sigma=ctx.sigma, p=o.get("p", 8),
+                              route=o.get("route", "auto"), cutoff_sigmas=o.get("cutoff_sigmas", 4.5),
+                              exclude_self=o.get("exclude_self", False), want=tuple(want))
+        gx = gy = gz = None
+        if need_pos:
+            gx, gy, gz = g["pos"]
+        gs = None
+        if "sigma" in g:
+            gs = g["sigma"].to(ctx.sigma_dtype).reshape(())
+        return gx, gy, gz, g.get("w"), gs, None, None
+
+
+def attraction(x, y, z, w, sigma, is_target=None, p=8, route="auto", cutoff_sigmas=4.5,
+               exclude_self=False, leaf_max=64, tree=None):
+    """Differentiable attraction sums u (float32 [n], 0 for non-targets).
+
+    x, y, z, w: CUDA float32 [n]; sigma: float or 0-d CUDA tensor.  Gradients flow
+    to x, y, z, w and sigma through msp_fgt_backward (no autograd tape inside)."""
+    opts = dict(p=p, route=route, cutoff_sigmas=cutoff_sigmas, exclude_self=exclude_self,
+                leaf_max=leaf_max, tree=tree)
+    return _AttractionFn.apply(x, y, z, w, sigma, is_target, opts)

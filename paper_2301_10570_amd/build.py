@@ -1,6 +1,6 @@
 """Compile the HIP sources into the in-tree shared library libmspfmm.so (gfx950).
 
-    python -m paper_2301_10570_amd.build
+    python paper_2301_10570_amd/build.py
 
 Packed FP32 instructions are disabled for device code (-packed-fp32-ops).
 """
@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmspfmm.so")
-SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip"]
+SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip"]
 ARCH = "gfx950"
 
 

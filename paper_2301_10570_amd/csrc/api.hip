@@ -109,7 +109,7 @@ msp_tree::~msp_tree() {
     for (msp::DevBuf *b : {&keys, &perm, &iperm, &ps, &pin, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
                            &nnchild, &ndigit, &nix, &niy, &niz, &d_level_off, &keys2, &perm2, &hist,
                            &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &tflag, &usort,
-                           &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
+                           &bwd, &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
                            &node_nsrc})
         b->release();
 }
@@ -232,6 +232,20 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     return scatter_output(t, u_out, prm->flags, false, s);
 }
 
+int msp_fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target,
+                     const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                     float *grad_y, float *grad_z, double *grad_sigma, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (t->n > 0 && (!w || !grad_u)) return fail(MSP_EINVAL, "NULL weight or upstream gradient");
+    const int npos = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);
+    if (npos != 0 && npos != 3) return fail(MSP_EINVAL, "give all three position gradients or none");
+    return fgt_backward(t, w, is_target, prm, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
+                        (hipStream_t)stream);
+}
+
 int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
                    const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
                    float *u, void *stream) {
@@ -301,7 +315,8 @@ const char *msp_phase_name(int phase) {
     static const char *names[PH_COUNT_] = {"bbox", "morton", "radix_sort", "node_levels", "node_table",
                                            "gather_sorted", "stage", "m2l_operators", "p2m", "m2l_x",
                                            "m2l_y", "m2l_z", "l2p", "interaction_lists", "p2p",
-                                           "scatter", "node_moments", "partner", "direct"};
+                                           "scatter", "node_moments", "partner", "direct",
+                                           "backward_combine"};
     if (phase < 0 || phase >= PH_COUNT_) return "";
     return names[phase];
 }

@@ -635,6 +635,73 @@ __global__ void __launch_bounds__(kBlock) k_l2p_2lvl(const uint64_t *keys, int64
     }
 }
 
+// L2P with derivatives: value, gradient and Laplacian of each cell's Taylor
+// series at its points (in key order).  Nested Horner: along x the row
+// polynomial r and r', r''; along y the row sums of r, r', r'' and the first two
+// y-derivatives of the sum of r; along z the same for the values of that level.
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                     int level, int Gx, int Gy, int Gz, double lox,
+                                                     double loy, double loz, double cell,
+                                                     double inv_sigma, const float *C, float *val,
+                                                     float *gx, float *gy, float *gz, float *lap) {
+    constexpr int P3 = P * P * P;
+    __shared__ float sC[P3];
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
+    if (start == end) return;
+    const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    for (int e = threadIdx.x; e < P3; e += kBlock) {
+        const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
+        sC[e] = C[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax];
+    }
+    __syncthreads();
+    const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
+    const float is = (float)inv_sigma;
+    for (int64_t i = start + threadIdx.x; i < end; i += kBlock) {
+        const float4 q = ps[i];
+        const float X = (float)(((double)q.x - cx) * inv_sigma);
+        const float Y = (float)(((double)q.y - cy) * inv_sigma);
+        const float Z = (float)(((double)q.z - cz) * inv_sigma);
+        // z level accumulators of: v0 (value), v1 (d/dx), v2 (d2/dx2), w1 (d/dy), w2 (d2/dy2)
+        float z0 = 0.f, z1 = 0.f, z2 = 0.f, zy1 = 0.f, zy2 = 0.f, zd1 = 0.f, zd2 = 0.f;
+        for (int az = P - 1; az >= 0; --az) {
+            float y0 = 0.f, y1 = 0.f, y2 = 0.f, yd1 = 0.f, yd2 = 0.f;
+#pragma unroll
+            for (int ay = P - 1; ay >= 0; --ay) {
+                const float *c = sC + (az * P + ay) * P;
+                float r0 = c[P - 1], r1 = 0.f, r2 = 0.f;
+#pragma unroll
+                for (int ax = P - 2; ax >= 0; --ax) {
+                    r2 = fmaf(r2, X, r1);
+                    r1 = fmaf(r1, X, r0);
+                    r0 = fmaf(r0, X, c[ax]);
+                }
+                // Horner in Y for the sums of r0, r1, r2 and derivatives of the r0 sum
+                yd2 = fmaf(yd2, Y, yd1);
+                yd1 = fmaf(yd1, Y, y0);
+                y0 = fmaf(y0, Y, r0);
+                y1 = fmaf(y1, Y, r1);
+                y2 = fmaf(y2, Y, r2);
+            }
+            zd2 = fmaf(zd2, Z, zd1);
+            zd1 = fmaf(zd1, Z, z0);
+            z0 = fmaf(z0, Z, y0);
+            z1 = fmaf(z1, Z, y1);
+            z2 = fmaf(z2, Z, 2.f * y2);
+            zy1 = fmaf(zy1, Z, yd1);
+            zy2 = fmaf(zy2, Z, 2.f * yd2);
+        }
+        val[i] = z0;
+        gx[i] = z1 * is;
+        gy[i] = zy1 * is;
+        gz[i] = zd1 * is;
+        if (lap) lap[i] = (z2 + zy2 + 2.f * zd2) * is * is;
+    }
+}
+
 // Weights and target flags into key order (the w slot of the sorted positions).
 __global__ void k_stage(const float *w, const uint8_t *is_target, const int32_t *perm, int64_t n,
                         float4 *ps, uint8_t *tflag) {
@@ -720,6 +787,40 @@ int dispatch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p,
 }
 
 }  // namespace
+
+namespace {
+template <int P>
+int launch_l2p_grad(msp_tree *t, const FgtPlan &pl, double inv_sigma, const float *C, float *val,
+                    float *gx, float *gy, float *gz, float *lap, hipStream_t s) {
+    const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p_grad<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
+                       t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), pl.level, pl.G[0], pl.G[1],
+                       pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, val, gx,
+                       gy, gz, lap);
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+}  // namespace
+
+int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
+                   float *val, float *gx, float *gy, float *gz, float *lap, hipStream_t s) {
+    // moments of w, all-pairs translation, then value/gradient/Laplacian at every point
+    msp_fgt_params q = *prm;
+    q.flags &= ~(uint32_t)MSP_TWO_LEVEL;
+    FgtPlan p1 = pl;
+    p1.pf = 0;
+    MSP_TRY(fgt_forward_grid(t, p1, &q, w, nullptr, nullptr, s));
+    const double inv_sigma = 1.0 / prm->sigma;
+    const float *C = t->gridB.as<float>();
+    PhaseScope ps(&t->timing, PH_L2P, s);
+    switch (pl.p) {
+#define CASE(P) case P: return launch_l2p_grad<P>(t, pl, inv_sigma, C, val, gx, gy, gz, lap, s);
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    }
+    return fail(MSP_EINVAL, "p out of range");
+}
 
 constexpr double kMaxGridBytes = 48.0e9;   // per expansion grid
 
@@ -838,6 +939,7 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
         }
         MSP_CHECK_LAUNCH();
     }
+    if (!u_out) return MSP_OK;   // callers that evaluate the Taylor grid themselves
     PhaseScope ps(&t->timing, PH_L2P, s);
     return dispatch_p2m_l2p(t, pl, inv_sigma, true, B, nullptr, ga, s);
 }

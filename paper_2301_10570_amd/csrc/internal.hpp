@@ -57,7 +57,7 @@ struct Geometry {
 enum Phase {
     PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
     PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
-    PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_COUNT_
+    PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_COUNT_
 };
 static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 
@@ -116,6 +116,7 @@ struct msp_tree {
 
     // per-call staging
     msp::DevBuf tflag, usort;
+    msp::DevBuf bwd;   // backward scratch: field values, gradients, Laplacians, reductions
     // expansion grids and translation operators
     msp::DevBuf gridA, gridB, ops;
     int64_t grid_bytes_valid = 0;
@@ -155,10 +156,18 @@ int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStrea
 int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, const float *w,
                      const uint8_t *is_target, float *u_out, hipStream_t s);
 int ensure_iperm(msp_tree *t, hipStream_t s);
+int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
+                   float *val, float *gx, float *gy, float *gz, float *lap, hipStream_t s);
+int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *val, float *gx, float *gy,
+                      float *gz, float *lap, hipStream_t s);
+int fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                 const float *grad_u, float *grad_w, float *grad_x, float *grad_y, float *grad_z,
+                 double *grad_sigma, hipStream_t s);
 int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s);
 
 // p2p.hip
 int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
+int direct_route_lists(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
 int direct_all_pairs(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
                      const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
                      float *u, hipStream_t s);

@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(kBlock) k_direct(const float *tx, const float 
 
 }  // namespace
 
-int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+int direct_route_lists(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     const int64_t nn = t->n_nodes;
     if (t->n == 0) return MSP_OK;
     BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
@@ -262,6 +262,14 @@ int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
         t->list_cutoff = prm->cutoff_sigmas;
         t->lists_valid = true;
     }
+    return MSP_OK;
+}
+
+int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+    const int64_t nn = t->n_nodes;
+    if (t->n == 0) return MSP_OK;
+    MSP_TRY(direct_route_lists(t, prm, s));
+    BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
     const float k_scale = (float)(std::sqrt(1.4426950408889634) / (double)prm->sigma);
     PhaseScope ps(&t->timing, PH_P2P, s);
     hipLaunchKernelGGL(k_p2p, dim3((unsigned)nn), dim3(64), 0, s, nn, t->nfirst.as<int32_t>(),

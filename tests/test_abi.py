@@ -19,8 +19,12 @@ def _declared():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_2301_10570_amd import build as b
-        b.build()
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "_mspfmm_build", os.path.join(ROOT, "paper_2301_10570_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     return ctypes.CDLL(LIB)
 
 

@@ -1,0 +1,116 @@
+"""Adjoint of the forward sum vs the oracle's direct-sum derivatives: weights,
+positions (a point may be target and source) and sigma."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _reference(wl, g, sample, full_sigma):
+    """Oracle derivatives of L = sum_targets g_i u_i at the sampled points."""
+    pos = wl.pos64()
+    tgt = np.nonzero(wl.a > 0)[0]
+    allp = np.arange(wl.n)
+    # weights and source-side position terms for the sampled points (all targets summed)
+    d_src = oracle.gauss_grad(pos[tgt], g[tgt], pos[sample], wl.w[sample], wl.sigma, want=("w", "s"))
+    # target-side position terms for the sampled points that are targets (all sources summed)
+    st = sample[wl.a[sample] > 0]
+    d_tgt = oracle.gauss_grad(pos[st], g[st], pos[allp], wl.w, wl.sigma, want=("t",))
+    gpos = d_src["s"].copy()
+    where = {k: i for i, k in enumerate(sample)}
+    for r, k in enumerate(st):
+        gpos[where[k]] += d_tgt["t"][r]
+    out = {"w": d_src["w"], "pos": gpos}
+    if full_sigma:
+        out["sigma"] = oracle.gauss_grad(pos[tgt], g[tgt], pos[allp], wl.w, wl.sigma, want=("sigma",))["sigma"]
+    return out
+
+
+def _check(wl, g, route, sample, full_sigma, p=8):
+    import torch
+    import paper_2301_10570_amd as msp
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    gd = torch.from_numpy(g.astype(np.float32)).to(d["x"].device)
+    res = tree.backward(d["w"], gd, d["tgt"], sigma=wl.sigma, p=p, route=route, cutoff_sigmas=0.0)
+    gw = res["w"].cpu().numpy()[sample]
+    gp = np.stack([t.cpu().numpy()[sample] for t in res["pos"]], axis=1)
+    ref = _reference(wl, g, sample, full_sigma)
+    # weights: positive sums, relative error per entry
+    assert np.max(np.abs(gw - ref["w"]) / np.abs(ref["w"])) <= 1e-4
+    # positions: error against the size of the terms, (2/sigma)(g u + w v) per point
+    u = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, route=route, cutoff_sigmas=0.0).cpu().numpy()
+    scale = 2.0 / wl.sigma * (g[sample] * (wl.a[sample] > 0) * u[sample] + wl.w[sample] * ref["w"])
+    err = np.max(np.abs(gp - ref["pos"]), axis=1)
+    ok = err <= 5e-4 * scale + 1e-12
+    assert np.all(ok), (err[~ok][:5], scale[~ok][:5])
+    if full_sigma:
+        gs = float(res["sigma"].cpu().numpy()[0])
+        assert abs(gs - ref["sigma"]) <= 1e-4 * abs(ref["sigma"]), (gs, ref["sigma"])
+    return tree.plan(wl.sigma, p=p, route=route)
+
+
+@pytest.mark.parametrize("route", ["fgt", "direct"])
+def test_backward_small_full_sigma(route):
+    """1/64 of the gradient workload: 16,384 sources + 16,384 targets, sigma over all pairs."""
+    wl = synth.config(4, 1 / 64)
+    g = wl.extra["g"].astype(np.float64)
+    sample = synth.sample_indices(wl.n, 1024, seed=404)
+    print(f"backward small, route={route}", flush=True)
+    plan = _check(wl, g, route, sample, full_sigma=True)
+    print(f"  plan {plan}")
+
+
+def test_backward_full_size_subset():
+    """1,048,576 sources + 1,048,576 targets; derivatives checked on a 4,096-point subset."""
+    wl = synth.config(4)
+    g = wl.extra["g"].astype(np.float64)
+    sample = synth.sample_indices(wl.n, 4096, seed=405)
+    print("backward 2M points, subset of 4096", flush=True)
+    plan = _check(wl, g, "auto", sample, full_sigma=False)
+    assert plan["route"] == "fgt"
+
+
+def test_backward_signed_g_and_union_points():
+    """Signed upstream gradients and neurons that are both target and source."""
+    wl = synth.uniform_box(6000, extent=(600.0, 600.0, 600.0), sigma=110.0, seed=61)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=wl.n)
+    sample = synth.sample_indices(wl.n, 512, seed=406)
+    import torch
+    import paper_2301_10570_amd as msp
+    d = to_dev(wl)
+    for route in ("fgt", "direct"):
+        print(f"signed g, union set, route={route}", flush=True)
+        tree = msp.build_tree(d["x"], d["y"], d["z"])
+        res = tree.backward(d["w"], torch.from_numpy(g.astype(np.float32)).cuda(), d["tgt"], sigma=wl.sigma,
+                            route=route, cutoff_sigmas=0.0)
+        ref = _reference(wl, g, sample, full_sigma=True)
+        gw = res["w"].cpu().numpy()[sample]
+        # signed sums: error against the sum of |terms| (computed with |g|)
+        absref = _reference(wl, np.abs(g), sample, full_sigma=False)["w"]
+        assert np.max(np.abs(gw - ref["w"]) / absref) <= 1e-4
+        gs = float(res["sigma"].cpu().numpy()[0])
+        abs_sig = _reference(wl, np.abs(g), sample, full_sigma=True)["sigma"]
+        assert abs(gs - ref["sigma"]) <= 1e-4 * abs_sig
+
+
+def test_autograd_function_matches_backward():
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.config(4, 1 / 256)
+    d = to_dev(wl)
+    x, y, z, w = (t.clone().requires_grad_(True) for t in (d["x"], d["y"], d["z"], d["w"]))
+    sig = torch.tensor(wl.sigma, dtype=torch.float64, device=x.device, requires_grad=True)
+    g = torch.from_numpy(wl.extra["g"]).cuda()
+    print("autograd function", flush=True)
+    u = msp.attraction(x, y, z, w, sig, d["tgt"])
+    (u * g).sum().backward()
+    tree = msp.build_tree(d["x"], d["y"], d["z"])
+    ref = tree.backward(d["w"], g, d["tgt"], sigma=wl.sigma)
+    assert torch.allclose(w.grad, ref["w"]) and torch.allclose(x.grad, ref["pos"][0])
+    assert torch.allclose(sig.grad.reshape(1), ref["sigma"])
