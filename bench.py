@@ -5,7 +5,9 @@ A step is one pass of the whole hot path over the 4,194,304-neuron slab
 (10 x 10 x 2 mm, sigma = 750 um, p = 8, leaf <= 64): octree build (root cube,
 Morton keys, radix sort, node table), staging, the forward sum (expansion route
 chosen by the cost model) and the scatter back to input order, plus child
-probabilities for a batch of partner queries.  value = targets evaluated per
+probabilities (Algorithm 2) for 65,536 partner queries in the proportions of
+its descent (one query per inner node visited).
+fwd_bwd_ms times tree build + forward + backward (weights, positions, sigma).  value = targets evaluated per
 second (attraction sums/s), inputs resident in HBM before the timed region.
 
 Prints one JSON line.  Extra keys: per-phase times, the accuracy of this run
@@ -57,6 +59,27 @@ def _algorithmic(phase, ctx):
     return None
 
 
+def _partner_queries(tree, k, seed):
+    """k (target, node) queries in the proportions of the descent of Algorithm 2,
+    which asks one query per (axon box, dendrite node) pair on every level: the
+    node is drawn uniformly from the inner nodes (so levels appear in proportion
+    to their node counts) and the target uniformly from the node's points."""
+    import numpy as np
+    import torch
+    ex = {kk: v.cpu().numpy() for kk, v in tree.export().items()}
+    if k <= 0 or tree.n == 0:
+        e = torch.zeros(0, dtype=torch.int32, device="cuda")
+        return e, e
+    rng = np.random.default_rng(seed)
+    inner = np.nonzero(ex["node_n_children"] > 0)[0]
+    node = inner[rng.integers(0, inner.size, k)]
+    first, count = ex["node_first"][node], ex["node_count"][node]
+    pos = first + (rng.random(k) * count).astype(np.int64)
+    tq = ex["perm"][pos]
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+    return T(tq), T(node)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +92,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the octree "
@@ -93,10 +117,15 @@ def main():
     n_src = int((wl.w > 0).sum())
     u = torch.empty(wl.n, dtype=torch.float32, device=dev)
     tree = msp.Tree()
+    tree.build(x, y, z, leaf_max=wl.leaf_max)
+    tq, nq = _partner_queries(tree, args.queries, seed=781)
+    uni = T(synth.uniforms(tq.numel(), 782))
 
     def step():
         tree.build(x, y, z, leaf_max=wl.leaf_max)
         tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+        if tq.numel():
+            tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni)
 
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -135,6 +164,21 @@ def main():
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / args.steps
 
+    # forward + backward (L = sum u_i over targets, g = 1): gradients w.r.t. the
+    # weights, the positions and sigma; the tree is rebuilt every step
+    gone = torch.ones(wl.n, dtype=torch.float32, device=dev)
+    def fwd_bwd():
+        tree.build(x, y, z, leaf_max=wl.leaf_max)
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+        tree.backward(w, gone, tgt, sigma=wl.sigma, p=wl.p, route=args.route)
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
+
     ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"]}
     per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                  for k, v in phases.items()}
@@ -166,6 +210,8 @@ def main():
         "ms_per_step_without_events": ms_clean,
         "forward_only_ms": ms_fwd,
         "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
+        "fwd_bwd_ms": ms_fb,
+        "partner_queries_per_step": int(tq.numel()),
     }
 
     sample = None
@@ -207,7 +253,9 @@ def main():
         import oracle
         threads = min(16, len(os.sched_getaffinity(0)))
         ti = np.nonzero(wl.a > 0)[0]
-        probe = ti[synth.sample_indices(ti.size, 4, seed=779)]
+        # the probe keeps every thread busy, so its rate is the sample's rate
+        probe = ti[synth.sample_indices(ti.size, 8 * threads, seed=779)]
+        oracle.attraction(wl, probe[:threads], threads=threads)
         t0 = time.perf_counter()
         oracle.attraction(wl, probe, threads=threads)
         per = (time.perf_counter() - t0) / probe.size

@@ -201,9 +201,15 @@ int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt
 /* Child probabilities for proportional partner choice (Algorithm 2).  For query q
  * (target point target_idx[q], an input index, and tree node node_id[q]) the
  * attraction of child c of that node is S_c = sum_{j below c} w_j K(t, s_j), and
- * probs[8*q + octant(c)] = S_c / sum_c' S_c' (0 for absent children).  Children
- * far enough for an expansion to meet the accuracy of `prm->p` are evaluated from
- * their Hermite moments (Eq. (7)), the rest directly (Eq. (8)).  If `uniforms`
+ * probs[8*q + octant(c)] = S_c / sum_c' S_c' (0 for absent children).  Weights
+ * are expected to be >= 0 (they are counts of free elements); with negative
+ * weights the result is unspecified.  The children are walked nearest first.  A
+ * node holding more than 70 sources (Algorithm 2's threshold) carries Hermite
+ * moments (Eq. (7)) and is evaluated from them (Eq. (8)) when the truncation
+ * model of `prm->p` puts the error below 1e-5 of the node's smallest term or
+ * below 1e-7 of the query's running total; it is dropped when even all of its
+ * weight at its nearest point stays below 1e-12 of the running total.  All other
+ * sources are summed directly, in float64.  If `uniforms`
  * (device float32[nq] in [0,1)) is non-NULL, choice[q] receives the node id of
  * the first child, in octant order, whose running sum of S exceeds
  * uniforms[q] * total, or -1 when the total is 0 or the node is a leaf.

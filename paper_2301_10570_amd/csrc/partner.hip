@@ -34,7 +34,28 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kC1 = 70;                    // Algorithm 2's element threshold
 constexpr int kStack = 8 * (kDepth + 2);
-constexpr float kAdmitTol = 1e-5f;
+constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
+constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
+constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
+
+// Sources below the nodes of one level: leaves count their points, inner nodes
+// add up their children (levels are processed from the deepest up).
+__global__ void k_nsrc_level(int64_t v0, int64_t v1, const int32_t *nfirst, const int32_t *ncount,
+                             const int32_t *nfchild, const int32_t *nnchild, const float4 *ps,
+                             int32_t *nsrc) {
+    const int64_t v = v0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= v1) return;
+    const int32_t nc = nnchild[v];
+    int32_t k = 0;
+    if (nc == 0) {
+        const int32_t f = nfirst[v], c = ncount[v];
+        for (int32_t j = f; j < f + c; ++j) k += ps[j].w != 0.f;
+    } else {
+        const int32_t fc = nfchild[v];
+        for (int q = 0; q < nc; ++q) k += nsrc[fc + q];
+    }
+    nsrc[v] = k;
+}
 
 // One block per node of one level (v0 .. v0 + gridDim.x).  Nodes must be
 // processed from the deepest level upward.
@@ -55,31 +76,14 @@ k_node_moments(int64_t v0, int level, int lh, const int32_t *nfirst, const int32
     __shared__ float bufA[P3];
     float *bufB = pts;
     __shared__ float red[NG > 1 ? NG * P2 * P : 1];
-    __shared__ int32_t s_cnt[kBlock / 64];
     __shared__ float shift[3][P];
 
     const int64_t v = v0 + blockIdx.x;
     const int tid = threadIdx.x;
     const int32_t nc = nnchild[v];
     const int32_t f = nfirst[v], cnt = ncount[v];
-    // sources below the node
-    int32_t ns = 0;
-    if (nc == 0) {
-        int32_t c = 0;
-        for (int32_t j = f + tid; j < f + cnt; j += kBlock) c += ps[j].w != 0.f;
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if ((tid & 63) == 0) s_cnt[tid >> 6] = c;
-        __syncthreads();
-        for (int w = 0; w < kBlock / 64; ++w) ns += s_cnt[w];
-    } else {
-        const int32_t fc = nfchild[v];
-        for (int q = 0; q < nc; ++q) ns += nsrc[fc + q];
-    }
-    const bool want = level >= lh && ns > kC1;
-    if (tid == 0) {
-        nsrc[v] = ns;
-        hasA[v] = want ? 1 : 0;
-    }
+    const bool want = level >= lh && nsrc[v] > kC1;
+    if (tid == 0) hasA[v] = want ? 1 : 0;
     if (!want) return;
 
     const double h = side / (double)(1ll << level);
@@ -208,7 +212,14 @@ __device__ inline double exp2_neg(double a) {
     return ldexp((double)__builtin_amdgcn_exp2f(-(float)(a - n)), -(int)fmin(n, 2000.0));
 }
 
-// One wavefront (block of 64) per query.
+// One wavefront (block of 64) per query.  Children of X are taken nearest
+// first, and every walk pushes a node's children so that the nearest is popped
+// first; the running total R of what has been summed so far then bounds every
+// later decision from below:
+//   - a node carrying moments is evaluated by M2P when the truncation model is
+//     within kAdmitTol of its own smallest contribution, or within kRunTol of R;
+//   - a node carrying moments whose largest possible contribution is below
+//     kSkipTol * R is dropped.
 template <int P>
 __global__ void __launch_bounds__(64)
 k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
@@ -216,20 +227,21 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
           const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
           const int32_t *nnchild, const int32_t *ndigit, const int32_t *nix, const int32_t *niy,
           const int32_t *niz, double lox, double loy, double loz, double side, const float4 *ps,
-          const uint8_t *hasA,
-          const float *nodeA, int64_t slot0, int lh, double sigma, float cutoff2, int unlimited,
-          float rho_ref, int exclude_self, float *probs, int32_t *choice) {
+          const uint8_t *hasA, const float *nodeA, int64_t slot0, int lh, double sigma, float cutoff2,
+          int unlimited, float rho_ref, int exclude_self, float *probs, int32_t *choice) {
     constexpr int P3 = P * P * P;
     __shared__ int32_t stk[kStack];
     __shared__ float hfun[3][P];
     __shared__ double S[8];
     __shared__ int32_t cid[8];
+    __shared__ int32_t order[8];
+    __shared__ double dist[8];
     const int64_t q = blockIdx.x;
     const int lane = threadIdx.x;
     if (q >= nq) return;
     const int32_t ti = target_idx[q], X = node_id[q];
     if (lane < 8) { S[lane] = 0.0; cid[lane] = -1; }
-    bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
+    const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
     const int nc = ok ? nnchild[X] : 0;
     __syncthreads();
     if (nc == 0) {
@@ -242,23 +254,39 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     const double tx = qt.x, ty = qt.y, tz = qt.z;
     const double inv_sigma = 1.0 / sigma;
     const double kexp = 1.4426950408889634 / (sigma * sigma);
-    // distance from the target to the box of X
-    double d0sq = 0.0;
-    {
-        const int l = nlevel[X];
+    // squared distance from the target to a node's box
+    auto box_d2 = [&](int32_t u, double &cxo, double &cyo, double &czo, double &half) {
+        const int l = nlevel[u];
         const double h = side / (double)(1ll << l);
-        const double c3[3] = {lox + (nix[X] + 0.5) * h, loy + (niy[X] + 0.5) * h, loz + (niz[X] + 0.5) * h};
-        const double t3[3] = {tx, ty, tz};
-        for (int a = 0; a < 3; ++a) {
-            const double g = fmax(fabs(t3[a] - c3[a]) - 0.5 * h, 0.0);
-            d0sq += g * g;
-        }
-    }
+        cxo = lox + (nix[u] + 0.5) * h;
+        cyo = loy + (niy[u] + 0.5) * h;
+        czo = loz + (niz[u] + 0.5) * h;
+        half = 0.5 * h;
+        const double gx = fmax(fabs(tx - cxo) - half, 0.0), gy = fmax(fabs(ty - cyo) - half, 0.0),
+                     gz = fmax(fabs(tz - czo) - half, 0.0);
+        return gx * gx + gy * gy + gz * gz;
+    };
+    double d0sq, dum0, dum1, dum2, dum3;
+    d0sq = box_d2(X, dum0, dum1, dum2, dum3);
     const double reach = unlimited ? 0.0 : sqrt(d0sq) + sqrt((double)cutoff2);
     const int32_t fc = nfchild[X];
-    for (int c = 0; c < nc; ++c) {
-        const int32_t child = fc + c;
-        double part = 0.0;
+    // children of X nearest first (ties by index)
+    if (lane < nc) {
+        double a, b, c, h;
+        dist[lane] = box_d2(fc + lane, a, b, c, h);
+    }
+    __syncthreads();
+    if (lane < nc) {
+        int rank = 0;
+        for (int k = 0; k < nc; ++k)
+            rank += (dist[k] < dist[lane]) || (dist[k] == dist[lane] && k < lane);
+        order[rank] = lane;
+    }
+    __syncthreads();
+    double run = 0.0;   // wave-uniform running total
+    for (int ci = 0; ci < nc; ++ci) {
+        const int32_t child = fc + order[ci];
+        double csum = 0.0;
         int sp = 0;
         if (lane == 0) stk[0] = child;
         sp = 1;
@@ -267,36 +295,35 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             const int32_t u = stk[sp - 1];
             __syncthreads();
             --sp;
-            const int l = nlevel[u];
-            const double h = side / (double)(1ll << l);
-            const double ux = lox + (nix[u] + 0.5) * h, uy = loy + (niy[u] + 0.5) * h,
-                         uz = loz + (niz[u] + 0.5) * h;
-            const double dx = tx - ux, dy = ty - uy, dz = tz - uz;
-            if (!unlimited) {
-                const double half = 0.5 * h;
-                const double gx = fmax(fabs(dx) - half, 0.0), gy = fmax(fabs(dy) - half, 0.0),
-                             gz = fmax(fabs(dz) - half, 0.0);
-                if (gx * gx + gy * gy + gz * gz > reach * reach) continue;
-            }
+            double ux, uy, uz, half;
+            const double g2 = box_d2(u, ux, uy, uz, half);
+            if (!unlimited && g2 > reach * reach) continue;
             const int32_t uf = nfirst[u], un = ncount[u], unc = nnchild[u];
+            const double dx = tx - ux, dy = ty - uy, dz = tz - uz;
             bool use_m = false;
+            const float *A = nullptr;
             if (hasA[u]) {
-                const double rho = 0.5 * h * inv_sigma;
+                A = nodeA + (int64_t)(u - slot0) * P3;
+                const double wsum = fabs((double)A[0]);
+                // largest possible contribution: every source at the box's nearest point
+                if (wsum * exp2_neg(g2 * kexp) <= kSkipTol * run) continue;
+                const double rho = half * inv_sigma;
                 const double r = sqrt(dx * dx + dy * dy + dz * dz) * inv_sigma;
-                const double e = 2e-5 * pow(rho / rho_ref, (double)P) *
-                                 exp(0.5 * r * r + 2.0 * 1.7320508075688772 * rho * r + 3.0 * rho * rho);
-                use_m = e <= kAdmitTol;
+                const double model = 2e-5 * pow(rho / rho_ref, (double)P);
+                const double rel = model * exp(0.5 * r * r + 2.0 * 1.7320508075688772 * rho * r + 3.0 * rho * rho);
+                const double abs_err = model * wsum * exp(-0.5 * r * r);
+                use_m = rel <= kAdmitTol || abs_err <= kRunTol * run;
             }
+            double part = 0.0;
             if (use_m) {
                 if (lane < 3 * P) {
                     const int axis = lane / P, k = lane % P;
-                    const double y = (axis == 0 ? dx : axis == 1 ? dy : dz) * inv_sigma;
-                    double hm1 = exp(-y * y), hk = hm1;
+                    const double yv = (axis == 0 ? dx : axis == 1 ? dy : dz) * inv_sigma;
+                    double h0 = exp(-yv * yv), hk = h0;
                     if (k >= 1) {
-                        double h0 = hm1;
-                        hk = 2.0 * y * h0;
+                        hk = 2.0 * yv * h0;
                         for (int m = 1; m < k; ++m) {
-                            const double hn = 2.0 * y * hk - 2.0 * m * h0;
+                            const double hn = 2.0 * yv * hk - 2.0 * m * h0;
                             h0 = hk;
                             hk = hn;
                         }
@@ -304,7 +331,6 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                     hfun[axis][k] = (float)hk;
                 }
                 __syncthreads();
-                const float *A = nodeA + (int64_t)(u - slot0) * P3;
                 float mp = 0.f;
                 for (int e = lane; e < P3; e += 64) {
                     const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
@@ -312,29 +338,43 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                 }
                 // the query's own point inside this node contributes w_self * K(0)
                 if (exclude_self && lane == 0 && si >= uf && si < uf + un) mp -= qt.w;
-                part += (double)mp;
+                part = (double)mp;
                 __syncthreads();
             } else if (unc == 0) {
                 for (int32_t j = uf + lane; j < uf + un; j += 64) {
                     const float4 qj = ps[j];
-                    const float wj = qj.w;
-                    if (wj == 0.f || (exclude_self && j == si)) continue;
+                    if (qj.w == 0.f || (exclude_self && j == si)) continue;
                     const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                    const double d2 = ex * ex + ey * ey + ez * ez;
-                    part += (double)wj * exp2_neg(d2 * kexp);
+                    part += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
                 }
             } else {
+                // push the children farthest first so that the nearest is popped first
                 const int32_t f = nfchild[u];
                 if (f > u && f + unc <= n_nodes && sp + unc <= kStack) {
-                    if (lane < unc) stk[sp + lane] = f + unc - 1 - lane;
+                    double cd = 0.0;
+                    if (lane < unc) {
+                        double a, b, c, h;
+                        cd = box_d2(f + lane, a, b, c, h);
+                    }
+                    if (lane < 8) dist[lane] = cd;
+                    __syncthreads();
+                    if (lane < unc) {
+                        int rank = 0;   // number of children farther away (ties: larger index first)
+                        for (int k = 0; k < unc; ++k)
+                            rank += (dist[k] > cd) || (dist[k] == cd && k > lane);
+                        stk[sp + rank] = f + lane;
+                    }
                     sp += unc;
                 }
                 __syncthreads();
+                continue;
             }
+            const double node_sum = wave_sum(part);
+            csum += node_sum;
+            run += node_sum;
         }
-        const double sc = wave_sum(part);
         if (lane == 0) {
-            S[ndigit[child]] = sc;
+            S[ndigit[child]] = csum;
             cid[ndigit[child]] = child;
         }
         __syncthreads();
@@ -346,12 +386,12 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         int32_t pick = -1;
         if (total > 0.0 && uniforms) {
             const double target = (double)uniforms[q] * total;
-            double run = 0.0;
+            double acc = 0.0;
             int32_t last = -1;
             for (int d = 0; d < 8; ++d) {
                 if (S[d] > 0.0) last = cid[d];
-                run += S[d];
-                if (run > target && S[d] > 0.0) { pick = cid[d]; break; }
+                acc += S[d];
+                if (acc > target && S[d] > 0.0) { pick = cid[d]; break; }
             }
             if (pick < 0) pick = last;
         }
@@ -377,10 +417,20 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
     MSP_HIP(hipMemsetAsync(t->node_hasA.p, 0, nn, s));
     {
         PhaseScope ps(&t->timing, PH_NODE_MOMENTS, s);
+        for (int l = t->depth; l >= lh && l >= 0; --l) {
+            const int64_t a = t->level_off[l], b = t->level_off[l + 1];
+            if (b <= a) continue;
+            hipLaunchKernelGGL(k_nsrc_level, dim3(grid_for(b - a, kBlock)), dim3(kBlock), 0, s, a, b,
+                               t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                               t->nnchild.as<int32_t>(), t->ps.as<float4>(), t->node_nsrc.as<int32_t>());
+            MSP_CHECK_LAUNCH();
+        }
         for (int l = t->depth; l >= 0; --l) {
             const int64_t a = t->level_off[l], b = t->level_off[l + 1];
             if (b <= a) continue;
             if (l < lh) break;
+            // the deepest level holds only leaves, which never exceed leaf_max points
+            if (l == t->depth && t->leaf_max <= kC1 && l < t->max_depth) continue;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_node_moments<P>), dim3((unsigned)(b - a)), dim3(kBlock),
                                0, s, a, l, lh, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(),
                                t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), t->nix.as<int32_t>(),
