@@ -33,7 +33,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kC1 = 70;                    // Algorithm 2's element threshold
-constexpr int kStack = 8 * (kDepth + 2);
+constexpr int kStack = 2048;                 // walk stack of one query (LDS)
+constexpr int kLaneLeaf = 128;               // leaves up to this size are summed by one lane
 constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
@@ -212,39 +213,140 @@ __device__ inline double exp2_neg(double a) {
     return ldexp((double)__builtin_amdgcn_exp2f(-(float)(a - n)), -(int)fmin(n, 2000.0));
 }
 
-// One wavefront (block of 64) per query.  Children of X are taken nearest
-// first, and every walk pushes a node's children so that the nearest is popped
-// first; the running total R of what has been summed so far then bounds every
-// later decision from below:
-//   - a node carrying moments is evaluated by M2P when the truncation model is
-//     within kAdmitTol of its own smallest contribution, or within kRunTol of R;
-//   - a node carrying moments whose largest possible contribution is below
-//     kSkipTol * R is dropped.
+// Rigorous bound, relative to the node's total weight, on the Hermite terms a
+// p-term tensor expansion leaves out: with |A_a| <= W prod rho^a_k / a_k! (every
+// source within rho sigma of the centre per axis) and Cramer's inequality
+// |h_n(x)| <= K 2^(n/2) sqrt(n!) exp(-x^2/2), each term is at most
+// W prod_k a(alpha_k) with a(n) = K (sqrt2 rho)^n / sqrt(n!), so the omitted
+// part is at most W (F^3 - F_p^3), F = sum_n a(n), F_p = sum_{n<p} a(n).
+__device__ inline double trunc_bound(double rho, int p) {
+    const double K = 1.086435, x = 1.4142135623730951 * rho;
+    double a = K, fp = 0.0, tail = 0.0;
+    for (int k = 0; k < 400; ++k) {
+        if (k < p) fp += a;
+        else tail += a;
+        a *= x / sqrt((double)(k + 1));
+        if (k >= p && a < 1e-17 * (fp + tail)) break;
+    }
+    const double f = fp + tail;
+    return tail * (f * f + f * fp + fp * fp);
+}
+
+// h_0..h_{P-1} at y: h_0 = exp(-y^2), h_{k+1} = 2y h_k - 2k h_{k-1}.
+template <int P>
+__device__ inline void hermite_row(float y, float (&h)[P]) {
+    h[0] = expf(-y * y);
+    if (P > 1) h[1] = 2.f * y * h[0];
+#pragma unroll
+    for (int k = 1; k + 1 < P; ++k) h[k + 1] = 2.f * y * h[k] - 2.f * (float)k * h[k - 1];
+}
+
+__device__ inline float hermite_at(float y, int k) {
+    float h0 = expf(-y * y);
+    if (k == 0) return h0;
+    float h1 = 2.f * y * h0;
+    for (int m = 1; m < k; ++m) {
+        const float hn = 2.f * y * h1 - 2.f * (float)m * h0;
+        h0 = h1;
+        h1 = hn;
+    }
+    return h1;
+}
+
+// One row of Eq. (7): sum_ax A[ax] h_ax.
+template <int P>
+__device__ inline float m2p_row(const float *__restrict__ row, const float (&hx)[P]) {
+    float sx = 0.f;
+    if constexpr (P % 4 == 0) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+        for (int k = 0; k < P / 4; ++k) {
+            const float4 v = r4[k];
+            sx = fmaf(v.x, hx[4 * k], sx);
+            sx = fmaf(v.y, hx[4 * k + 1], sx);
+            sx = fmaf(v.z, hx[4 * k + 2], sx);
+            sx = fmaf(v.w, hx[4 * k + 3], sx);
+        }
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < P; ++ax) sx = fmaf(row[ax], hx[ax], sx);
+    }
+    return sx;
+}
+
+// Eq. (7) evaluated at y = (t - c)/sigma by one lane: sum_a A_a h_ax h_ay h_az.
+template <int P>
+__device__ inline float m2p_lane(const float *__restrict__ A, float yx, float yy, float yz) {
+    float hx[P], hy[P], hz[P];
+    hermite_row<P>(yx, hx);
+    hermite_row<P>(yy, hy);
+    hermite_row<P>(yz, hz);
+    float acc = 0.f;
+#pragma unroll 1
+    for (int az = 0; az < P; ++az) {
+        float sy = 0.f;
+#pragma unroll
+        for (int ay = 0; ay < P; ++ay) sy = fmaf(m2p_row<P>(A + (az * P + ay) * P, hx), hy[ay], sy);
+        acc = fmaf(sy, hz[az], acc);
+    }
+    return acc;
+}
+
+// The same sum with its rows spread over the lanes; every lane gets the total.
+template <int P>
+__device__ inline double m2p_wave(const float *__restrict__ A, float yx, float yy, float yz, int lane) {
+    float hx[P];
+    hermite_row<P>(yx, hx);
+    float part = 0.f;
+    for (int r = lane; r < P * P; r += 64) {
+        const float sx = m2p_row<P>(A + r * P, hx);
+        part = fmaf(sx, hermite_at(yy, r % P) * hermite_at(yz, r / P), part);
+    }
+    return wave_sum((double)part);
+}
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// One wavefront per query (t, X).  The sums over the children of X come from a
+// walk below X that evaluates up to 64 nodes at a time, one per lane, taken
+// from the top of a stack on which every node's children are pushed so that
+// the nearest ends on top.  Decisions compare against R = max(lower bound,
+// total summed so far), which never exceeds the final total; the lower bound
+// comes first, from the chain of nearest nodes below X (each node with moments
+// gives its M2P value minus the rigorous truncation bound, the leaf at the end
+// of the chain its exact sum).  For a node carrying moments:
+//   - dropped if all of its weight at its nearest point stays below kSkipTol R;
+//   - M2P if the calibrated error model is below kAdmitTol of the node's own
+//     smallest term, or below kRunTol R;
+// otherwise its children are pushed, and a leaf is summed directly (by its
+// lane, or by the whole wave when it holds more than kLaneLeaf points).
+// Every decision and every sum is taken in a fixed order, so the result is
+// the same from run to run.
 template <int P>
 __global__ void __launch_bounds__(64)
 k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
           int64_t n, int64_t n_nodes, const int32_t *iperm, const int32_t *nlevel,
           const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
-          const int32_t *nnchild, const int32_t *ndigit, const int32_t *nix, const int32_t *niy,
-          const int32_t *niz, double lox, double loy, double loz, double side, const float4 *ps,
-          const uint8_t *hasA, const float *nodeA, int64_t slot0, int lh, double sigma, float cutoff2,
-          int unlimited, float rho_ref, int exclude_self, float *probs, int32_t *choice) {
+          const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
+          double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
+          const float *nodeA, int64_t slot0, double sigma, float cutoff2, int unlimited,
+          double rho_ref, int exclude_self, float *probs, int32_t *choice) {
     constexpr int P3 = P * P * P;
     __shared__ int32_t stk[kStack];
-    __shared__ float hfun[3][P];
-    __shared__ double S[8];
-    __shared__ int32_t cid[8];
-    __shared__ int32_t order[8];
-    __shared__ double dist[8];
     const int64_t q = blockIdx.x;
     const int lane = threadIdx.x;
     if (q >= nq) return;
     const int32_t ti = target_idx[q], X = node_id[q];
-    if (lane < 8) { S[lane] = 0.0; cid[lane] = -1; }
     const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
     const int nc = ok ? nnchild[X] : 0;
-    __syncthreads();
-    if (nc == 0) {
+    const int32_t fc = ok ? nfchild[X] : 0;
+    if (nc == 0 || fc <= X || fc + nc > n_nodes) {
         if (lane < 8) probs[q * 8 + lane] = 0.f;
         if (lane == 0 && choice) choice[q] = -1;
         return;
@@ -253,145 +355,248 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     const float4 qt = ps[si];
     const double tx = qt.x, ty = qt.y, tz = qt.z;
     const double inv_sigma = 1.0 / sigma;
-    const double kexp = 1.4426950408889634 / (sigma * sigma);
-    // squared distance from the target to a node's box
-    auto box_d2 = [&](int32_t u, double &cxo, double &cyo, double &czo, double &half) {
-        const int l = nlevel[u];
-        const double h = side / (double)(1ll << l);
-        cxo = lox + (nix[u] + 0.5) * h;
-        cyo = loy + (niy[u] + 0.5) * h;
-        czo = loz + (niz[u] + 0.5) * h;
+    const double inv_s2 = inv_sigma * inv_sigma;
+    const double kexp = 1.4426950408889634 * inv_s2;
+    const int lx = nlevel[X];
+    auto centre = [&](int32_t u, double &cx, double &cy, double &cz, double &half) {
+        const double h = side / (double)(1ll << nlevel[u]);
+        cx = lox + (nix[u] + 0.5) * h;
+        cy = loy + (niy[u] + 0.5) * h;
+        cz = loz + (niz[u] + 0.5) * h;
         half = 0.5 * h;
-        const double gx = fmax(fabs(tx - cxo) - half, 0.0), gy = fmax(fabs(ty - cyo) - half, 0.0),
-                     gz = fmax(fabs(tz - czo) - half, 0.0);
+    };
+    // squared distance from the target to the box (near) and to its farthest corner (far)
+    auto box_d2 = [&](int32_t u, double &far2) {
+        double cx, cy, cz, half;
+        centre(u, cx, cy, cz, half);
+        const double ax = fabs(tx - cx), ay = fabs(ty - cy), az = fabs(tz - cz);
+        const double gx = fmax(ax - half, 0.0), gy = fmax(ay - half, 0.0), gz = fmax(az - half, 0.0);
+        far2 = (ax + half) * (ax + half) + (ay + half) * (ay + half) + (az + half) * (az + half);
         return gx * gx + gy * gy + gz * gz;
     };
-    double d0sq, dum0, dum1, dum2, dum3;
-    d0sq = box_d2(X, dum0, dum1, dum2, dum3);
+    double far0;
+    const double d0sq = box_d2(X, far0);
     const double reach = unlimited ? 0.0 : sqrt(d0sq) + sqrt((double)cutoff2);
-    const int32_t fc = nfchild[X];
-    // children of X nearest first (ties by index)
-    if (lane < nc) {
-        double a, b, c, h;
-        dist[lane] = box_d2(fc + lane, a, b, c, h);
-    }
-    __syncthreads();
-    if (lane < nc) {
-        int rank = 0;
-        for (int k = 0; k < nc; ++k)
-            rank += (dist[k] < dist[lane]) || (dist[k] == dist[lane] && k < lane);
-        order[rank] = lane;
-    }
-    __syncthreads();
-    double run = 0.0;   // wave-uniform running total
-    for (int ci = 0; ci < nc; ++ci) {
-        const int32_t child = fc + order[ci];
-        double csum = 0.0;
-        int sp = 0;
-        if (lane == 0) stk[0] = child;
-        sp = 1;
-        __syncthreads();
-        while (sp > 0) {
-            const int32_t u = stk[sp - 1];
-            __syncthreads();
-            --sp;
-            double ux, uy, uz, half;
-            const double g2 = box_d2(u, ux, uy, uz, half);
-            if (!unlimited && g2 > reach * reach) continue;
+    const double reach2 = reach * reach;
+    // direct sum over one node's points by the whole wave
+    auto wave_direct = [&](int32_t uf, int32_t un) {
+        double part = 0.0;
+        for (int32_t j = uf + lane; j < uf + un; j += 64) {
+            const float4 qj = ps[j];
+            if (qj.w == 0.f || (exclude_self && j == si)) continue;
+            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+            part += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+        }
+        return wave_sum(part);
+    };
+
+    // lower bound of the total from the chain of nearest nodes
+    double lb = 0.0;
+    {
+        int32_t u = X;
+        for (int guard = 0; guard <= kMaxLevels; ++guard) {
+            double far2;
+            (void)box_d2(u, far2);
+            if (!unlimited && far2 > reach2) break;   // not every source of u is counted
             const int32_t uf = nfirst[u], un = ncount[u], unc = nnchild[u];
-            const double dx = tx - ux, dy = ty - uy, dz = tz - uz;
-            bool use_m = false;
-            const float *A = nullptr;
             if (hasA[u]) {
-                A = nodeA + (int64_t)(u - slot0) * P3;
-                const double wsum = fabs((double)A[0]);
-                // largest possible contribution: every source at the box's nearest point
-                if (wsum * exp2_neg(g2 * kexp) <= kSkipTol * run) continue;
-                const double rho = half * inv_sigma;
-                const double r = sqrt(dx * dx + dy * dy + dz * dz) * inv_sigma;
-                const double model = 2e-5 * pow(rho / rho_ref, (double)P);
-                const double rel = model * exp(0.5 * r * r + 2.0 * 1.7320508075688772 * rho * r + 3.0 * rho * rho);
-                const double abs_err = model * wsum * exp(-0.5 * r * r);
-                use_m = rel <= kAdmitTol || abs_err <= kRunTol * run;
+                const float *A = nodeA + (int64_t)(u - slot0) * P3;
+                double cx, cy, cz, half;
+                centre(u, cx, cy, cz, half);
+                double m = m2p_wave<P>(A, (float)((tx - cx) * inv_sigma), (float)((ty - cy) * inv_sigma),
+                                       (float)((tz - cz) * inv_sigma), lane);
+                if (exclude_self && si >= uf && si < uf + un) m -= (double)qt.w;
+                lb = fmax(lb, m - trunc_bound(half * inv_sigma, P) * fabs((double)A[0]));
             }
-            double part = 0.0;
-            if (use_m) {
-                if (lane < 3 * P) {
-                    const int axis = lane / P, k = lane % P;
-                    const double yv = (axis == 0 ? dx : axis == 1 ? dy : dz) * inv_sigma;
-                    double h0 = exp(-yv * yv), hk = h0;
-                    if (k >= 1) {
-                        hk = 2.0 * yv * h0;
-                        for (int m = 1; m < k; ++m) {
-                            const double hn = 2.0 * yv * hk - 2.0 * m * h0;
-                            h0 = hk;
-                            hk = hn;
+            if (unc == 0) {
+                lb = fmax(lb, wave_direct(uf, un));
+                break;
+            }
+            const int32_t f = nfchild[u];
+            if (f <= u || f + unc > n_nodes) break;
+            double bd = 1e300;
+            int bl = 64;
+            if (lane < unc) {
+                double dummy;
+                bd = box_d2(f + lane, dummy);
+                bl = lane;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double od = __shfl_xor(bd, o, 64);
+                const int ol = __shfl_xor(bl, o, 64);
+                if (od < bd || (od == bd && ol < bl)) { bd = od; bl = ol; }
+            }
+            u = f + bl;
+        }
+    }
+
+    // children of X, farthest at the bottom of the stack
+    {
+        double dummy, dl = 0.0;
+        if (lane < nc) dl = box_d2(fc + lane, dummy);
+        int rank = 0;   // children farther away; ties: the larger index counts as farther
+        for (int k = 0; k < nc; ++k) {
+            const double dk = __shfl(dl, k, 64);
+            rank += (dk > dl) || (dk == dl && k > lane);
+        }
+        if (lane < nc) stk[rank] = fc + lane;
+    }
+    int sp = nc;
+    double S[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) S[d] = 0.0;
+    double acc = 0.0;
+    const double log_admit = log(kAdmitTol), log_runtol = log(kRunTol), log_skip = log(kSkipTol);
+    const double log_model0 = log(2e-5);
+    __syncthreads();
+    while (sp > 0) {
+        const double run = fmax(lb, acc);
+        const double lrun = run > 0.0 ? log(run) : -1e300;
+        int B = sp < 64 ? sp : 64;
+        const int room = (kStack - sp) / 7;   // pops B, pushes at most 8 B
+        if (B > room) B = room > 1 ? room : 1;
+        const int base = sp - B;
+        const int32_t u = lane < B ? stk[base + lane] : -1;
+        __syncthreads();
+        double val = 0.0;
+        int digit = 0, npush = 0;
+        bool big = false;
+        int32_t uf = 0, un = 0, f = 0;
+        if (u >= 0) {
+            double cx, cy, cz, half;
+            centre(u, cx, cy, cz, half);
+            const int lu = nlevel[u];
+            const int sh = lu - lx - 1;
+            digit = (((nix[u] >> sh) & 1) << 2) | (((niy[u] >> sh) & 1) << 1) | ((niz[u] >> sh) & 1);
+            double far2;
+            const double g2 = box_d2(u, far2);
+            uf = nfirst[u];
+            un = ncount[u];
+            const int32_t unc = nnchild[u];
+            f = unc > 0 ? nfchild[u] : 0;
+            if (unlimited || g2 <= reach2) {
+                bool descend = unc > 0, direct = unc == 0;
+                if (hasA[u]) {
+                    const float *A = nodeA + (int64_t)(u - slot0) * P3;
+                    const double lw = log(fmax(fabs((double)A[0]), 1e-300));
+                    if (lw - g2 * inv_s2 <= log_skip + lrun) {
+                        descend = direct = false;
+                    } else {
+                        const double dx = tx - cx, dy = ty - cy, dz = tz - cz;
+                        const double rho = half * inv_sigma;
+                        const double r = sqrt(dx * dx + dy * dy + dz * dz) * inv_sigma;
+                        // calibrated error model 2e-5 (rho / rho_max(p))^p of the expansion level
+                        const double lm = log_model0 + P * log(rho / rho_ref);
+                        const bool adm = lm + 0.5 * r * r + 2.0 * 1.7320508075688772 * rho * r + 3.0 * rho * rho <= log_admit ||
+                                         lm + lw - 0.5 * r * r <= log_runtol + lrun;
+                        if (adm) {
+                            float m = m2p_lane<P>(A, (float)(dx * inv_sigma), (float)(dy * inv_sigma),
+                                                  (float)(dz * inv_sigma));
+                            val = (double)m;
+                            if (exclude_self && si >= uf && si < uf + un) val -= (double)qt.w;
+                            descend = direct = false;
                         }
                     }
-                    hfun[axis][k] = (float)hk;
                 }
-                __syncthreads();
-                float mp = 0.f;
-                for (int e = lane; e < P3; e += 64) {
-                    const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
-                    mp = fmaf(A[e], hfun[0][ax] * hfun[1][ay] * hfun[2][az], mp);
-                }
-                // the query's own point inside this node contributes w_self * K(0)
-                if (exclude_self && lane == 0 && si >= uf && si < uf + un) mp -= qt.w;
-                part = (double)mp;
-                __syncthreads();
-            } else if (unc == 0) {
-                for (int32_t j = uf + lane; j < uf + un; j += 64) {
-                    const float4 qj = ps[j];
-                    if (qj.w == 0.f || (exclude_self && j == si)) continue;
-                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                    part += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
-                }
-            } else {
-                // push the children farthest first so that the nearest is popped first
-                const int32_t f = nfchild[u];
-                if (f > u && f + unc <= n_nodes && sp + unc <= kStack) {
-                    double cd = 0.0;
-                    if (lane < unc) {
-                        double a, b, c, h;
-                        cd = box_d2(f + lane, a, b, c, h);
+                if (direct) {
+                    if (un <= kLaneLeaf) {
+                        for (int32_t j = uf; j < uf + un; ++j) {
+                            const float4 qj = ps[j];
+                            if (qj.w == 0.f || (exclude_self && j == si)) continue;
+                            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                            val += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+                        }
+                    } else {
+                        big = true;
                     }
-                    if (lane < 8) dist[lane] = cd;
-                    __syncthreads();
-                    if (lane < unc) {
-                        int rank = 0;   // number of children farther away (ties: larger index first)
-                        for (int k = 0; k < unc; ++k)
-                            rank += (dist[k] > cd) || (dist[k] == cd && k > lane);
-                        stk[sp + rank] = f + lane;
-                    }
-                    sp += unc;
                 }
-                __syncthreads();
-                continue;
+                if (descend) {
+                    if (f > u && f + unc <= n_nodes) npush = unc;
+                    else big = true;   // malformed links: sum the node's points instead
+                }
             }
-            const double node_sum = wave_sum(part);
-            csum += node_sum;
-            run += node_sum;
         }
-        if (lane == 0) {
-            S[ndigit[child]] = csum;
-            cid[ndigit[child]] = child;
+        int incl = wave_incl_scan(npush, lane);
+        if (npush > 0 && base + incl > kStack) {
+            // only reachable when a single node is taken with a nearly full stack
+            big = true;
+            npush = 0;
+            incl = 0;
+        }
+        if (npush > 0) {
+            double cd[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                double fr;
+                cd[k] = k < npush ? box_d2(f + k, fr) : 0.0;
+            }
+            const int pos0 = base + incl - npush;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k >= npush) continue;
+                int rank = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < 8; ++k2)
+                    rank += k2 < npush && ((cd[k2] > cd[k]) || (cd[k2] == cd[k] && k2 > k));
+                stk[pos0 + rank] = f + k;
+            }
+        }
+        sp = base + __shfl(incl, 63, 64);
+        // nodes summed by the whole wave
+        uint64_t bigmask = __ballot(big);
+        while (bigmask) {
+            const int bl = __builtin_ctzll(bigmask);
+            bigmask &= bigmask - 1;
+            const int32_t bf = __shfl(uf, bl, 64), bn = __shfl(un, bl, 64);
+            const int bd = __shfl(digit, bl, 64);
+            const double sbig = wave_direct(bf, bn);
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+                if (d == bd) S[d] += sbig;
+            acc += sbig;
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            if (__ballot(val != 0.0 && digit == d) == 0) continue;
+            const double sd = wave_sum(digit == d ? val : 0.0);
+            S[d] += sd;
+            acc += sd;
         }
         __syncthreads();
     }
     double total = 0.0;
+#pragma unroll
     for (int d = 0; d < 8; ++d) total += S[d];
-    if (lane < 8) probs[q * 8 + lane] = total > 0.0 ? (float)(S[lane] / total) : 0.f;
+    // child node id per octant (absent children: -1)
+    int32_t cid_l = -1;
+    if (lane < 8) {
+        for (int k = 0; k < nc; ++k) {
+            const int32_t c = fc + k;
+            const int sh = nlevel[c] - lx - 1;
+            const int dg = (((nix[c] >> sh) & 1) << 2) | (((niy[c] >> sh) & 1) << 1) | ((niz[c] >> sh) & 1);
+            if (dg == lane) cid_l = c;
+        }
+        double sl = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            if (d == lane) sl = S[d];
+        probs[q * 8 + lane] = total > 0.0 ? (float)(sl / total) : 0.f;
+    }
+    int32_t cids[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) cids[d] = __shfl(cid_l, d, 64);
     if (lane == 0 && choice) {
         int32_t pick = -1;
         if (total > 0.0 && uniforms) {
             const double target = (double)uniforms[q] * total;
-            double acc = 0.0;
+            double accp = 0.0;
             int32_t last = -1;
+#pragma unroll
             for (int d = 0; d < 8; ++d) {
-                if (S[d] > 0.0) last = cid[d];
-                acc += S[d];
-                if (acc > target && S[d] > 0.0) { pick = cid[d]; break; }
+                if (pick >= 0) continue;
+                if (S[d] > 0.0) last = cids[d];
+                accp += S[d];
+                if (accp > target && S[d] > 0.0) pick = cids[d];
             }
             if (pick < 0) pick = last;
         }
@@ -451,11 +656,11 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nq), dim3(64), 0, s, nq, target_idx,
                        node_id, uniforms, t->n, nn, t->iperm.as<int32_t>(), t->nlevel.as<int32_t>(),
                        t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                       t->nnchild.as<int32_t>(), t->ndigit.as<int32_t>(), t->nix.as<int32_t>(),
-                       t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1],
-                       t->geo.lo[2], t->geo.side, t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, lh,
-                       sigma, R * R, unlimited ? 1 : 0, (float)rmax,
-                       (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice);
+                       t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                       t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
+                       t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma,
+                       R * R, unlimited ? 1 : 0, rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs,
+                       choice);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
