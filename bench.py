@@ -28,8 +28,15 @@ sys.path.insert(0, ROOT)
 PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12}
 
 
+# phase -> kernel it times (one kernel per launch of the phase)
+KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "p2m": "k_p2m",
+                   "l2p": "k_l2p", "m2l_x": "k_m2l_pass_mfma", "m2l_y": "k_m2l_pass_mfma",
+                   "m2l_z": "k_m2l_pass_mfma", "morton": "k_morton", "stage": "k_stage",
+                   "partner": "k_partner"}
+
+
 def _algorithmic(phase, ctx):
-    """(bound, unit, amount per launch) for a library phase, or None.
+    """(bound, unit, amount per launch) for a single-kernel phase, or None.
 
     Amounts count what the method must do: flops of the contraction it performs
     (2 per multiply-add) or bytes it must move at least once."""
@@ -44,19 +51,37 @@ def _algorithmic(phase, ctx):
         k = {"m2l_x": 0, "m2l_y": 1, "m2l_z": 2}[phase]
         U = G[k] * p
         R = G[0] * G[1] * G[2] * p3 // U
-        return "alu", "TFLOP/s", 2.0 * R * U * U
-    if phase == "radix_sort":
-        # 8 passes; each must read and write every (key, index) pair once
-        return "hbm", "GB/s", 8 * n * 12 * 2.0
+        return "mfma", "TFLOP/s", 2.0 * R * U * U
+    if phase == "sort_scatter":
+        # each pass reads and writes every (key, index) pair once; the last of the
+        # 8 passes also gathers the float4 positions into sorted order
+        return "hbm", "GB/s", n * (24.0 + 32.0 / 8)
+    if phase == "sort_hist":
+        return "hbm", "GB/s", n * 8.0
     if phase == "morton":
-        return "hbm", "GB/s", n * (12 + 8 + 4.0)
-    if phase == "gather_sorted":
-        return "hbm", "GB/s", n * (4 + 12 + 12.0)
-    if phase in ("stage",):
-        return "hbm", "GB/s", n * (4 + 1 + 4 + 4 + 1.0)
-    if phase == "scatter":
-        return "hbm", "GB/s", n * (4 + 4 + 1 + 4 + 4.0)
+        return "hbm", "GB/s", n * (12 + 8 + 4 + 16.0)
+    if phase == "stage":
+        return "hbm", "GB/s", n * (4 + 1 + 4 + 16 + 1.0)
     return None
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the kernel's source has changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_slab4M.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"source_sha256:\s*(\S+)\s+(\S+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_src and m_val):
+        return None
+    src = os.path.join(ROOT, m_src.group(1))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != m_src.group(2):
+        return None
+    return float(m_val.group(1))
 
 
 def _partner_queries(tree, k, seed):
@@ -93,6 +118,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three copies of 1 GiB (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the octree "
@@ -133,7 +160,19 @@ def main():
     torch.cuda.synchronize()
     plan = tree.plan(wl.sigma, p=wl.p, route=args.route)
 
-    # timed region (phase events recorded live on the library's stream)
+    # timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = n_tgt / (ms_per_step / 1000.0)
+    print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} sums/s", file=sys.stderr, flush=True)
+
+    # the same steps again with HIP events around every library phase and sort
+    # pass, recorded live on the library's stream (per-kernel durations)
     tree.set_timing(True)
     tree.timing(reset=True)
     torch.cuda.synchronize()
@@ -141,20 +180,9 @@ def main():
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    ms_events = 1000.0 * (time.perf_counter() - t0) / args.steps
     phases = tree.timing(reset=True)
     tree.set_timing(False)
-    ms_per_step = 1000.0 * elapsed / args.steps
-    value = n_tgt / (ms_per_step / 1000.0)
-    print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} sums/s", file=sys.stderr, flush=True)
-
-    # same loop without the phase events (overhead check)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_clean = 1000.0 * (time.perf_counter() - t0) / args.steps
 
     # forward only, cached tree
     torch.cuda.synchronize()
@@ -182,19 +210,32 @@ def main():
     ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"]}
     per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                  for k, v in phases.items()}
-    dom = max(phases, key=lambda k: phases[k][0])
+    # dominant kernel: the single-kernel phase with the most time per step
+    cands = [k for k in KERNEL_OF_PHASE if k in phases and phases[k][1] > 0]
+    dom = max(cands, key=lambda k: phases[k][0]) if cands else None
     roof = None
-    info = _algorithmic(dom, ctx)
+    info = _algorithmic(dom, ctx) if dom else None
     if info is not None:
         bound, unit, amount = info
         avg_s = phases[dom][0] / phases[dom][1] / 1000.0
         if unit == "GB/s":
             achieved, peak = amount / avg_s / 1e9, PEAK["hbm"] / 1e9
         else:
-            achieved, peak = amount / avg_s / 1e12, PEAK["fp32_vector"] / 1e12
-        roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None,
+            achieved = amount / avg_s / 1e12
+            peak = (PEAK["fp32_mfma"] if bound == "mfma" else PEAK["fp32_vector"]) / 1e12
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": _traffic(KERNEL_OF_PHASE[dom]),
+                "kernel": KERNEL_OF_PHASE[dom], "phase": dom,
+                "algorithmic_per_launch": amount,
                 "avg_launch_ms": phases[dom][0] / phases[dom][1]}
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling the HBM counters
+        a = torch.empty(256 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"bench: copy calibration 3 x {a.numel() * 4} bytes", file=sys.stderr, flush=True)
 
     result = {
         "metric": "attraction sums/s at rel-err<=1e-4 (FMM forward incl. octree build)",
@@ -207,7 +248,7 @@ def main():
                    "rho": plan["rho"]},
         "roofline": roof,
         "phases": per_phase,
-        "ms_per_step_without_events": ms_clean,
+        "ms_per_step_with_events": ms_events,
         "forward_only_ms": ms_fwd,
         "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
         "fwd_bwd_ms": ms_fb,

@@ -238,7 +238,7 @@ int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes
  * around each phase it launches on the caller's stream; msp_tree_get_timing
  * waits for them and returns, per phase, the summed milliseconds and the number
  * of launches since the last reset.  Phase names come from msp_phase_name. */
-enum { MSP_PHASE_COUNT = 24 };
+enum { MSP_PHASE_COUNT = 32 };
 int msp_tree_set_timing(msp_tree *t, int enable);
 int msp_tree_get_timing(msp_tree *t, double *ms /* host [MSP_PHASE_COUNT] */,
                         int64_t *launches /* host [MSP_PHASE_COUNT] */, int reset);

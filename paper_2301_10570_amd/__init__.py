@@ -87,7 +87,7 @@ _lib.msp_tree_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.msp_tree_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]
 _lib.msp_phase_name.restype = ctypes.c_char_p
 _lib.msp_phase_name.argtypes = [ctypes.c_int]
-PHASE_COUNT = 24
+PHASE_COUNT = 32
 for _f in ("msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_fgt_debug_buffer"):

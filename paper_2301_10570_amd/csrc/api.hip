@@ -105,15 +105,6 @@ static int check_params(const msp_fgt_params *prm) {
 
 }  // namespace msp
 
-msp_tree::~msp_tree() {
-    for (msp::DevBuf *b : {&keys, &perm, &iperm, &ps, &pin, &nlevel, &nfirst, &ncount, &nparent, &nfchild,
-                           &nnchild, &ndigit, &nix, &niy, &niz, &d_level_off, &keys2, &perm2, &hist,
-                           &tmp_a, &tmp_b, &tmp_c, &dlev, &llev, &blkcnt, &bbox, &tflag, &usort,
-                           &bwd, &gridA, &gridB, &ops, &list_off, &list_idx, &list_cnt, &nodeA, &node_hasA,
-                           &node_nsrc})
-        b->release();
-}
-
 using namespace msp;
 
 extern "C" {
@@ -316,7 +307,8 @@ const char *msp_phase_name(int phase) {
                                            "gather_sorted", "stage", "m2l_operators", "p2m", "m2l_x",
                                            "m2l_y", "m2l_z", "l2p", "interaction_lists", "p2p",
                                            "scatter", "node_moments", "partner", "direct",
-                                           "backward_combine"};
+                                           "backward_combine", "sort_hist", "sort_digit_scan",
+                                           "sort_scatter", "node_source_counts", "partner_leafy"};
     if (phase < 0 || phase >= PH_COUNT_) return "";
     return names[phase];
 }

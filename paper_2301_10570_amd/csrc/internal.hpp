@@ -41,6 +41,10 @@ int fail(int code, const char *fmt, ...);
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     int ensure(size_t need);
     void release();
     template <class T> T *as() const { return static_cast<T *>(p); }
@@ -57,7 +61,8 @@ struct Geometry {
 enum Phase {
     PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
     PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
-    PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_COUNT_
+    PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_SORT_HIST, PH_SORT_SCAN, PH_SORT_SCATTER,
+    PH_NODE_COUNTS, PH_PARTNER_LEAFY, PH_COUNT_
 };
 static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 
@@ -126,11 +131,10 @@ struct msp_tree {
     float list_sigma = -1.f, list_cutoff = -2.f;
     bool lists_valid = false;
     // node moments for partner queries
-    msp::DevBuf nodeA, node_hasA, node_nsrc;
+    msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
 
-    ~msp_tree();
 };
 
 namespace msp {

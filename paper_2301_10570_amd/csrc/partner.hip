@@ -58,150 +58,6 @@ __global__ void k_nsrc_level(int64_t v0, int64_t v1, const int32_t *nfirst, cons
     nsrc[v] = k;
 }
 
-// One block per node of one level (v0 .. v0 + gridDim.x).  Nodes must be
-// processed from the deepest level upward.
-template <int P>
-__global__ void __launch_bounds__(kBlock)
-k_node_moments(int64_t v0, int level, int lh, const int32_t *nfirst, const int32_t *ncount,
-               const int32_t *nfchild, const int32_t *nnchild, const int32_t *nix,
-               const int32_t *niy, const int32_t *niz, const int32_t *ndigit, double lox,
-               double loy, double loz, double side, const float4 *ps, double inv_sigma,
-               int32_t *nsrc, uint8_t *hasA,
-               float *nodeA, int64_t slot0) {
-    constexpr int P2 = P * P, P3 = P * P * P;
-    constexpr int NG = kBlock / P2 > 0 ? kBlock / P2 : 1;
-    constexpr int STR = 3 * P + 1;
-    constexpr int CH = P >= 11 ? 64 : kBlock;      // points staged per round (LDS budget)
-    __shared__ float pts[(CH * STR > P3) ? CH * STR : P3];   // reused as bufB for M2M
-    __shared__ float tot[P3];
-    __shared__ float bufA[P3];
-    float *bufB = pts;
-    __shared__ float red[NG > 1 ? NG * P2 * P : 1];
-    __shared__ float shift[3][P];
-
-    const int64_t v = v0 + blockIdx.x;
-    const int tid = threadIdx.x;
-    const int32_t nc = nnchild[v];
-    const int32_t f = nfirst[v], cnt = ncount[v];
-    const bool want = level >= lh && nsrc[v] > kC1;
-    if (tid == 0) hasA[v] = want ? 1 : 0;
-    if (!want) return;
-
-    const double h = side / (double)(1ll << level);
-    const double cx = lox + (nix[v] + 0.5) * h, cy = loy + (niy[v] + 0.5) * h, cz = loz + (niz[v] + 0.5) * h;
-    const int grp = tid / P2, yz = tid % P2, ay = yz % P, az = yz / P;
-    const bool active = grp < NG;
-    float acc[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = 0.f;
-
-    // P2M over the points of children that carry no moments (all points for a leaf)
-    const int nparts = nc == 0 ? 1 : nc;
-    for (int q = 0; q < nparts; ++q) {
-        int32_t pf = f, pn = cnt;
-        if (nc > 0) {
-            const int32_t c = nfchild[v] + q;
-            if (hasA[c]) continue;
-            pf = nfirst[c];
-            pn = ncount[c];
-        }
-        for (int32_t c0 = 0; c0 < pn; c0 += CH) {
-            const int32_t i = pf + c0 + tid;
-            __syncthreads();
-            if (tid < CH && c0 + tid < pn) {
-                const float4 qp = ps[i];
-                const float X = (float)(((double)qp.x - cx) * inv_sigma);
-                const float Y = (float)(((double)qp.y - cy) * inv_sigma);
-                const float Z = (float)(((double)qp.z - cz) * inv_sigma);
-                float *r = pts + tid * STR;
-                float px = qp.w, py = 1.f, pz = 1.f;
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    r[k] = px; r[P + k] = py; r[2 * P + k] = pz;
-                    px *= X; py *= Y; pz *= Z;
-                }
-            }
-            __syncthreads();
-            const int m = pn - c0 < CH ? pn - c0 : CH;
-            if (active)
-                for (int j = grp; j < m; j += NG) {
-                    const float *r = pts + j * STR;
-                    const float fyz = r[P + ay] * r[2 * P + az];
-#pragma unroll
-                    for (int k = 0; k < P; ++k) acc[k] = fmaf(fyz, r[k], acc[k]);
-                }
-        }
-    }
-    __syncthreads();
-    if (NG > 1) {
-        if (active)
-#pragma unroll
-            for (int k = 0; k < P; ++k) red[(grp * P2 + yz) * P + k] = acc[k];
-        __syncthreads();
-    }
-    if (grp == 0) {
-        float fy = 1.f, fz = 1.f;
-        for (int k = 2; k <= ay; ++k) fy *= (float)k;
-        for (int k = 2; k <= az; ++k) fz *= (float)k;
-        float fx = 1.f;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (k > 1) fx *= (float)k;
-            float s = acc[k];
-            if (NG > 1) {
-                s = 0.f;
-                for (int q = 0; q < NG; ++q) s += red[(q * P2 + yz) * P + k];
-            }
-            tot[(az * P + ay) * P + k] = s / (fx * fy * fz);
-        }
-    }
-    __syncthreads();
-
-    // M2M of the children that carry moments
-    if (nc > 0) {
-        const double hc = 0.5 * h;
-        for (int q = 0; q < nc; ++q) {
-            const int32_t c = nfchild[v] + q;
-            if (!hasA[c]) continue;
-            const float *Ac = nodeA + (int64_t)(c - slot0) * P3;
-            for (int e = tid; e < P3; e += kBlock) bufA[e] = Ac[e];
-            if (tid < 3 * P) {
-                const int axis = tid / P, k = tid % P;
-                const int bit = (ndigit[c] >> (2 - axis)) & 1;
-                const double d = (bit - 0.5) * hc * inv_sigma;
-                double val = 1.0;
-                for (int m = 1; m <= k; ++m) val *= d / m;      // d^k / k!
-                shift[axis][k] = (float)val;
-            }
-            __syncthreads();
-            // x: bufB[az][ay][ax] = sum_{g<=ax} bufA[az][ay][g] shift_x[ax-g]
-            for (int e = tid; e < P3; e += kBlock) {
-                const int ax = e % P, rowb = e - ax;
-                float s = 0.f;
-                for (int g = 0; g <= ax; ++g) s = fmaf(bufA[rowb + g], shift[0][ax - g], s);
-                bufB[e] = s;
-            }
-            __syncthreads();
-            for (int e = tid; e < P3; e += kBlock) {
-                const int ax = e % P, ay2 = (e / P) % P, az2 = e / P2;
-                float s = 0.f;
-                for (int g = 0; g <= ay2; ++g) s = fmaf(bufB[(az2 * P + g) * P + ax], shift[1][ay2 - g], s);
-                bufA[e] = s;
-            }
-            __syncthreads();
-            for (int e = tid; e < P3; e += kBlock) {
-                const int rest = e % P2, az2 = e / P2;
-                float s = 0.f;
-                for (int g = 0; g <= az2; ++g) s = fmaf(bufA[g * P2 + rest], shift[2][az2 - g], s);
-                tot[e] += s;
-            }
-            __syncthreads();
-        }
-    }
-    float *dst = nodeA + (v - slot0) * P3;
-    for (int e = tid; e < P3; e += kBlock) dst[e] = tot[e];
-}
-
 __device__ inline double wave_sum(double x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
@@ -313,6 +169,350 @@ __device__ inline int wave_incl_scan(int v, int lane) {
     return v;
 }
 
+// One wavefront per node, striding over the nodes v0 .. v1 of one level.
+// Levels must be processed from the deepest upward.  The children's records are
+// read once, one lane per child; the points of the children that carry no
+// moments (of the node itself for a leaf) are flattened into one list staged 64
+// at a time; the moment blocks of the others are shifted (M2M) G at a time in LDS.
+template <int P>
+__global__ void __launch_bounds__(64)
+k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const int32_t *ncount,
+               const int32_t *nfchild, const int32_t *nnchild, const int32_t *nix,
+               const int32_t *niy, const int32_t *niz, const int32_t *ndigit, double lox,
+               double loy, double loz, double side, const float4 *ps, double inv_sigma,
+               const int32_t *nsrc, uint8_t *hasA, float *nodeA, int64_t slot0) {
+    constexpr int P2 = P * P, P3 = P2 * P;
+    constexpr int RP = (P2 + 63) / 64;                  // (ay, az) rows per lane
+    constexpr int STR = 3 * P + 1;
+    constexpr int PR = P + 1;                           // padded row of a child block
+    constexpr int G0 = 10240 / (P2 * PR * 4);
+    constexpr int G = G0 < 1 ? 1 : (G0 > 8 ? 8 : G0);   // child blocks shifted together
+    __shared__ float pts[64 * STR];
+    __shared__ float tot[P3];
+    __shared__ float cbuf[G * P2 * PR];
+    __shared__ float shift[2][P];                       // d^k / k! for the two child offsets
+    __shared__ int32_t part_first[64], part_end[64];
+    const int lane = threadIdx.x;
+    const double h = side / (double)(1ll << level);
+    if (lane < 2 * P) {
+        const int bit = lane / P, k = lane % P;
+        const double d = (bit - 0.5) * 0.5 * h * inv_sigma;   // child centre - node centre, in sigma
+        double val = 1.0;
+        for (int m = 1; m <= k; ++m) val *= d / m;
+        shift[bit][k] = (float)val;
+    }
+    __syncthreads();
+    for (int64_t v = v0 + blockIdx.x; v < v1; v += gridDim.x) {
+        const bool want = nsrc[v] > kC1;
+        if (lane == 0) hasA[v] = want ? 1 : 0;
+        if (!want) continue;
+        const int32_t nc = nnchild[v];
+        const double cx = lox + (nix[v] + 0.5) * h, cy = loy + (niy[v] + 0.5) * h,
+                     cz = loz + (niz[v] + 0.5) * h;
+        // parts: the children (lanes 0..nc-1), or the node itself when it is a leaf
+        int32_t cf = 0, cn = 0, cdig = 0, cid = -1;
+        bool chas = false;
+        if (nc == 0) {
+            if (lane == 0) {
+                cf = nfirst[v];
+                cn = ncount[v];
+            }
+        } else if (lane < nc) {
+            cid = nfchild[v] + lane;
+            chas = hasA[cid] != 0;
+            cf = nfirst[cid];
+            cn = ncount[cid];
+            cdig = ndigit[cid];
+        }
+        const int take = chas ? 0 : cn;
+        const int incl = wave_incl_scan(take, lane);
+        const int total = __shfl(incl, 63, 64);
+        part_first[lane] = cf - (incl - take);
+        part_end[lane] = take > 0 ? incl : -1;
+        float acc[RP][P];
+#pragma unroll
+        for (int rr = 0; rr < RP; ++rr)
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc[rr][k] = 0.f;
+
+        // P2M (Eq. (7)) over the flattened points
+        int owner = 0;
+        for (int32_t c0 = 0; c0 < total; c0 += 64) {
+            __syncthreads();
+            const int32_t j = c0 + lane;
+            if (j < total) {
+                while (part_end[owner] <= j) ++owner;
+                const float4 qp = ps[part_first[owner] + j];
+                const float X = (float)(((double)qp.x - cx) * inv_sigma);
+                const float Y = (float)(((double)qp.y - cy) * inv_sigma);
+                const float Z = (float)(((double)qp.z - cz) * inv_sigma);
+                float *r = pts + lane * STR;
+                float px = qp.w, py = 1.f, pz = 1.f;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    r[k] = px;
+                    r[P + k] = py;
+                    r[2 * P + k] = pz;
+                    px *= X;
+                    py *= Y;
+                    pz *= Z;
+                }
+            }
+            __syncthreads();
+            const int m = total - c0 < 64 ? total - c0 : 64;
+            for (int jj = 0; jj < m; ++jj) {
+                const float *r = pts + jj * STR;
+#pragma unroll
+                for (int rr = 0; rr < RP; ++rr) {
+                    const int row = lane + 64 * rr;
+                    if (row >= P2) continue;
+                    const float fyz = r[P + row % P] * r[2 * P + row / P];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) acc[rr][k] = fmaf(fyz, r[k], acc[rr][k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RP; ++rr) {
+            const int row = lane + 64 * rr;
+            if (row >= P2) continue;
+            const int ay = row % P, az = row / P;
+            float fyz = 1.f;
+            for (int k = 2; k <= ay; ++k) fyz *= (float)k;
+            for (int k = 2; k <= az; ++k) fyz *= (float)k;
+            float fx = 1.f;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (k > 1) fx *= (float)k;
+                tot[row * P + k] = acc[rr][k] / (fx * fyz);
+            }
+        }
+
+        // M2M of the children that carry moments, G blocks at a time:
+        // A'_a = sum_{g<=a} A_g d^(a-g)/(a-g)! along x, then y, then z
+        uint64_t todo = __ballot(chas);
+        while (todo) {
+            int32_t gid[G];
+            int gdig[G];
+            int ng = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                gid[g] = -1;
+                gdig[g] = 0;
+                if (todo) {
+                    const int q = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    gid[g] = __shfl(cid, q, 64);
+                    gdig[g] = __shfl(cdig, q, 64);
+                    ng = g + 1;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (g >= ng) continue;
+                const float *Ac = nodeA + (int64_t)(gid[g] - slot0) * P3;
+                for (int e = lane; e < P3; e += 64) cbuf[g * P2 * PR + (e / P) * PR + e % P] = Ac[e];
+            }
+            __syncthreads();
+            // x: rows (g, az, ay)
+            for (int i = lane; i < ng * P2; i += 64) {
+                const int g = i / P2;
+                int bx = 0;
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg)
+                    if (gg == g) bx = (gdig[gg] >> 2) & 1;
+                float *row = cbuf + g * P2 * PR + (i % P2) * PR;
+                float a[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) a[k] = row[k];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int m = 0; m <= k; ++m) s = fmaf(a[m], shift[bx][k - m], s);
+                    row[k] = s;
+                }
+            }
+            __syncthreads();
+            // y: columns (g, az, ax)
+            for (int i = lane; i < ng * P2; i += 64) {
+                const int g = i / P2, az = (i % P2) / P, ax = i % P;
+                int by = 0;
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg)
+                    if (gg == g) by = (gdig[gg] >> 1) & 1;
+                float *col = cbuf + g * P2 * PR + az * P * PR + ax;
+                float a[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) a[k] = col[k * PR];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int m = 0; m <= k; ++m) s = fmaf(a[m], shift[by][k - m], s);
+                    col[k * PR] = s;
+                }
+            }
+            __syncthreads();
+            // z: columns (g, ay, ax)
+            for (int i = lane; i < ng * P2; i += 64) {
+                const int g = i / P2, ay = (i % P2) / P, ax = i % P;
+                int bz = 0;
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg)
+                    if (gg == g) bz = gdig[gg] & 1;
+                float *col = cbuf + g * P2 * PR + ay * PR + ax;
+                float a[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) a[k] = col[k * P * PR];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int m = 0; m <= k; ++m) s = fmaf(a[m], shift[bz][k - m], s);
+                    col[k * P * PR] = s;
+                }
+            }
+            __syncthreads();
+            for (int e = lane; e < P3; e += 64) {
+                float s = tot[e];
+                const int off = (e / P) * PR + e % P;
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (g < ng) s += cbuf[g * P2 * PR + off];
+                tot[e] = s;
+            }
+        }
+        __syncthreads();
+        float *dst = nodeA + (v - slot0) * P3;
+        for (int e = lane; e < P3; e += 64) dst[e] = tot[e];
+        __syncthreads();
+    }
+}
+
+
+// Queries whose node X has only leaf children (none carrying moments, each of at
+// most kLaneLeaf points): eight queries per wavefront, one lane per child, each
+// lane summing its leaf directly.  done[q] tells the general walk which queries
+// are finished here.
+__global__ void __launch_bounds__(256)
+k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
+                int64_t n, int64_t n_nodes, const int32_t *iperm, const int32_t *nlevel,
+                const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
+                const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
+                double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
+                double sigma, float cutoff2, int unlimited, int exclude_self, float *probs,
+                int32_t *choice, uint8_t *done) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t q = g >> 3;
+    const int c = (int)(g & 7);
+    const int lane = threadIdx.x & 63, gbase = lane & ~7;
+    bool ok = q < nq;
+    int32_t ti = 0, X = 0, nc = 0, fc = 0;
+    if (ok) {
+        ti = target_idx[q];
+        X = node_id[q];
+        ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
+    }
+    if (ok) {
+        nc = nnchild[X];
+        fc = nfchild[X];
+        ok = nc > 0 && fc > X && fc + nc <= n_nodes;
+    }
+    int32_t child = -1;
+    if (ok && c < nc) {
+        child = fc + c;
+        ok = nnchild[child] == 0 && !hasA[child] && ncount[child] <= kLaneLeaf;
+    }
+    const uint64_t bad = __ballot(!ok);
+    const bool group_ok = ((bad >> gbase) & 0xffull) == 0;
+    if (!group_ok) {
+        if (q < nq && c == 0) done[q] = 0;
+        return;   // the whole group leaves together
+    }
+    const int32_t si = iperm[ti];
+    const float4 qt = ps[si];
+    const double tx = qt.x, ty = qt.y, tz = qt.z;
+    const double kexp = 1.4426950408889634 / (sigma * sigma);
+    auto box_d2 = [&](int32_t u) {
+        const double h = side / (double)(1ll << nlevel[u]);
+        const double half = 0.5 * h;
+        const double gx = fmax(fabs(tx - (lox + (nix[u] + 0.5) * h)) - half, 0.0);
+        const double gy = fmax(fabs(ty - (loy + (niy[u] + 0.5) * h)) - half, 0.0);
+        const double gz = fmax(fabs(tz - (loz + (niz[u] + 0.5) * h)) - half, 0.0);
+        return gx * gx + gy * gy + gz * gz;
+    };
+    double Sl = 0.0;
+    int dg = -1;
+    if (child >= 0) {
+        const int sh = nlevel[child] - nlevel[X] - 1;
+        dg = (((nix[child] >> sh) & 1) << 2) | (((niy[child] >> sh) & 1) << 1) | ((niz[child] >> sh) & 1);
+        bool in = true;
+        if (!unlimited) {
+            const double reach = sqrt(box_d2(X)) + sqrt((double)cutoff2);
+            in = box_d2(child) <= reach * reach;
+        }
+        if (in) {
+            const int32_t uf = nfirst[child], un = ncount[child];
+            for (int32_t j = uf; j < uf + un; ++j) {
+                const float4 qj = ps[j];
+                if (qj.w == 0.f || (exclude_self && j == si)) continue;
+                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                Sl += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+            }
+        }
+    }
+    // sums and child ids by octant, gathered from the group's lanes
+    double S[8];
+    int32_t cid[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        S[d] = 0.0;
+        cid[d] = -1;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double sk = __shfl(Sl, gbase + k, 64);
+        const int dk = __shfl(dg, gbase + k, 64);
+        const int32_t ck = __shfl(child, gbase + k, 64);
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            if (d == dk) {
+                S[d] = sk;
+                cid[d] = ck;
+            }
+    }
+    double total = 0.0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) total += S[d];
+    double mine = 0.0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+        if (d == c) mine = S[d];
+    probs[q * 8 + c] = total > 0.0 ? (float)(mine / total) : 0.f;
+    if (c == 0) {
+        if (choice) {
+            int32_t pick = -1;
+            if (total > 0.0 && uniforms) {
+                const double target = (double)uniforms[q] * total;
+                double accp = 0.0;
+                int32_t last = -1;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    if (pick >= 0) continue;
+                    if (S[d] > 0.0) last = cid[d];
+                    accp += S[d];
+                    if (accp > target && S[d] > 0.0) pick = cid[d];
+                }
+                if (pick < 0) pick = last;
+            }
+            choice[q] = pick;
+        }
+        done[q] = 1;
+    }
+}
+
 // One wavefront per query (t, X).  The sums over the children of X come from a
 // walk below X that evaluates up to 64 nodes at a time, one per lane, taken
 // from the top of a stack on which every node's children are pushed so that
@@ -336,12 +536,12 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
           const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
           double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
           const float *nodeA, int64_t slot0, double sigma, float cutoff2, int unlimited,
-          double rho_ref, int exclude_self, float *probs, int32_t *choice) {
+          double rho_ref, int exclude_self, float *probs, int32_t *choice, const uint8_t *done) {
     constexpr int P3 = P * P * P;
     __shared__ int32_t stk[kStack];
     const int64_t q = blockIdx.x;
     const int lane = threadIdx.x;
-    if (q >= nq) return;
+    if (q >= nq || done[q]) return;
     const int32_t ti = target_idx[q], X = node_id[q];
     const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
     const int nc = ok ? nnchild[X] : 0;
@@ -390,9 +590,9 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         return wave_sum(part);
     };
 
-    // lower bound of the total from the chain of nearest nodes
-    double lb = 0.0;
-    {
+    // lower bound of the total from the chain of nearest nodes (wave-uniform call)
+    auto lower_bound = [&]() {
+        double lb = 0.0;
         int32_t u = X;
         for (int guard = 0; guard <= kMaxLevels; ++guard) {
             double far2;
@@ -428,7 +628,8 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             }
             u = f + bl;
         }
-    }
+        return lb;
+    };
 
     // children of X, farthest at the bottom of the stack
     {
@@ -445,21 +646,30 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     double S[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) S[d] = 0.0;
-    double acc = 0.0;
+    double acc = 0.0, lb = 0.0;
+    bool have_lb = false;
+    __shared__ int32_t c_first[64], c_end[64];
+    __shared__ int8_t c_digit[64];
     const double log_admit = log(kAdmitTol), log_runtol = log(kRunTol), log_skip = log(kSkipTol);
     const double log_model0 = log(2e-5);
     __syncthreads();
     while (sp > 0) {
-        const double run = fmax(lb, acc);
-        const double lrun = run > 0.0 ? log(run) : -1e300;
         int B = sp < 64 ? sp : 64;
         const int room = (kStack - sp) / 7;   // pops B, pushes at most 8 B
         if (B > room) B = room > 1 ? room : 1;
         const int base = sp - B;
         const int32_t u = lane < B ? stk[base + lane] : -1;
+        const bool u_has = u >= 0 && hasA[u];
         __syncthreads();
+        // the bound is needed only once a node carrying moments comes up
+        if (!have_lb && __ballot(u_has)) {
+            lb = lower_bound();
+            have_lb = true;
+        }
+        const double run = fmax(lb, acc);
+        const double lrun = run > 0.0 ? log(run) : -1e300;
         double val = 0.0;
-        int digit = 0, npush = 0;
+        int digit = 0, npush = 0, nleaf = 0;
         bool big = false;
         int32_t uf = 0, un = 0, f = 0;
         if (u >= 0) {
@@ -476,7 +686,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             f = unc > 0 ? nfchild[u] : 0;
             if (unlimited || g2 <= reach2) {
                 bool descend = unc > 0, direct = unc == 0;
-                if (hasA[u]) {
+                if (u_has) {
                     const float *A = nodeA + (int64_t)(u - slot0) * P3;
                     const double lw = log(fmax(fabs((double)A[0]), 1e-300));
                     if (lw - g2 * inv_s2 <= log_skip + lrun) {
@@ -499,16 +709,8 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                     }
                 }
                 if (direct) {
-                    if (un <= kLaneLeaf) {
-                        for (int32_t j = uf; j < uf + un; ++j) {
-                            const float4 qj = ps[j];
-                            if (qj.w == 0.f || (exclude_self && j == si)) continue;
-                            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                            val += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
-                        }
-                    } else {
-                        big = true;
-                    }
+                    if (un <= kLaneLeaf) nleaf = un;
+                    else big = true;
                 }
                 if (descend) {
                     if (f > u && f + unc <= n_nodes) npush = unc;
@@ -555,10 +757,35 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                 if (d == bd) S[d] += sbig;
             acc += sbig;
         }
+        // the small leaves of the batch, their points spread over the lanes
+        double pd[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) pd[d] = (digit == d) ? val : 0.0;
+        const int lincl = wave_incl_scan(nleaf, lane);
+        const int ltotal = __shfl(lincl, 63, 64);
+        if (ltotal > 0) {
+            c_first[lane] = uf - (lincl - nleaf);   // point index = c_first + flattened index
+            c_end[lane] = nleaf > 0 ? lincl : -1;
+            c_digit[lane] = (int8_t)digit;
+            __syncthreads();
+            int owner = 0;
+            for (int j = lane; j < ltotal; j += 64) {
+                while (c_end[owner] <= j) ++owner;   // lanes in order, flattened indices increase
+                const int32_t pj = c_first[owner] + j;
+                const float4 qj = ps[pj];
+                if (qj.w == 0.f || (exclude_self && pj == si)) continue;
+                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+                const int dg = c_digit[owner];
+#pragma unroll
+                for (int d = 0; d < 8; ++d)
+                    if (d == dg) pd[d] += e;
+            }
+        }
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
-            if (__ballot(val != 0.0 && digit == d) == 0) continue;
-            const double sd = wave_sum(digit == d ? val : 0.0);
+            if (__ballot(pd[d] != 0.0) == 0) continue;
+            const double sd = wave_sum(pd[d]);
             S[d] += sd;
             acc += sd;
         }
@@ -622,13 +849,16 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
     MSP_HIP(hipMemsetAsync(t->node_hasA.p, 0, nn, s));
     {
         PhaseScope ps(&t->timing, PH_NODE_MOMENTS, s);
-        for (int l = t->depth; l >= lh && l >= 0; --l) {
-            const int64_t a = t->level_off[l], b = t->level_off[l + 1];
-            if (b <= a) continue;
-            hipLaunchKernelGGL(k_nsrc_level, dim3(grid_for(b - a, kBlock)), dim3(kBlock), 0, s, a, b,
-                               t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                               t->nnchild.as<int32_t>(), t->ps.as<float4>(), t->node_nsrc.as<int32_t>());
-            MSP_CHECK_LAUNCH();
+        {
+            PhaseScope ps_counts(&t->timing, PH_NODE_COUNTS, s);
+            for (int l = t->depth; l >= lh && l >= 0; --l) {
+                const int64_t a = t->level_off[l], b = t->level_off[l + 1];
+                if (b <= a) continue;
+                hipLaunchKernelGGL(k_nsrc_level, dim3(grid_for(b - a, kBlock)), dim3(kBlock), 0, s, a, b,
+                                   t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                                   t->nnchild.as<int32_t>(), t->ps.as<float4>(), t->node_nsrc.as<int32_t>());
+                MSP_CHECK_LAUNCH();
+            }
         }
         for (int l = t->depth; l >= 0; --l) {
             const int64_t a = t->level_off[l], b = t->level_off[l + 1];
@@ -636,13 +866,14 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
             if (l < lh) break;
             // the deepest level holds only leaves, which never exceed leaf_max points
             if (l == t->depth && t->leaf_max <= kC1 && l < t->max_depth) continue;
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_node_moments<P>), dim3((unsigned)(b - a)), dim3(kBlock),
-                               0, s, a, l, lh, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(),
-                               t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), t->nix.as<int32_t>(),
-                               t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->ndigit.as<int32_t>(),
-                               t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(), 1.0 / sigma,
-                               t->node_nsrc.as<int32_t>(), t->node_hasA.as<uint8_t>(),
-                               t->nodeA.as<float>(), slot0);
+            const int64_t nb = b - a < 8192 ? b - a : 8192;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_node_moments<P>), dim3((unsigned)nb), dim3(64), 0, s, a, b,
+                               l, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                               t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                               t->niz.as<int32_t>(), t->ndigit.as<int32_t>(), t->geo.lo[0], t->geo.lo[1],
+                               t->geo.lo[2], t->geo.side, t->ps.as<float4>(), 1.0 / sigma,
+                               t->node_nsrc.as<int32_t>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(),
+                               slot0);
             MSP_CHECK_LAUNCH();
         }
     }
@@ -652,6 +883,19 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
     if (nq == 0) return MSP_OK;
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * sigma);
+    MSP_TRY(t->partner_done.ensure((size_t)nq));
+    {
+        PhaseScope pl(&t->timing, PH_PARTNER_LEAFY, s);
+        hipLaunchKernelGGL(k_partner_leafy, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, target_idx,
+                           node_id, uniforms, t->n, nn, t->iperm.as<int32_t>(), t->nlevel.as<int32_t>(),
+                           t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                           t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                           t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
+                           t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), sigma, R * R, unlimited ? 1 : 0,
+                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice,
+                           t->partner_done.as<uint8_t>());
+        MSP_CHECK_LAUNCH();
+    }
     PhaseScope ps(&t->timing, PH_PARTNER, s);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nq), dim3(64), 0, s, nq, target_idx,
                        node_id, uniforms, t->n, nn, t->iperm.as<int32_t>(), t->nlevel.as<int32_t>(),
@@ -660,7 +904,7 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                        t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
                        t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma,
                        R * R, unlimited ? 1 : 0, rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs,
-                       choice);
+                       choice, t->partner_done.as<uint8_t>());
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }

@@ -619,11 +619,18 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         uint32_t *total = hist + (size_t)256 * nblk;
         for (int pass = 0; pass < 8; ++pass) {
             const int shift = pass * 8;
-            hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
-            MSP_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
-            MSP_CHECK_LAUNCH();
+            {
+                PhaseScope k1(&t->timing, PH_SORT_HIST, s);
+                hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
+                MSP_CHECK_LAUNCH();
+            }
+            {
+                PhaseScope k2(&t->timing, PH_SORT_SCAN, s);
+                hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
+                MSP_CHECK_LAUNCH();
+            }
             const bool last = pass == 7;
+            PhaseScope k3(&t->timing, PH_SORT_SCATTER, s);
             hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift,
                                hist, total, nblk, t->pin.as<float4>(), last ? t->ps.as<float4>() : nullptr);
             MSP_CHECK_LAUNCH();

@@ -1,0 +1,109 @@
+#!/usr/bin/env python3
+"""Short text summaries of rocprofv3 CSV output, for the files under profiles/.
+
+    python paper_2301_10570_amd/rocprof_summary.py stats KERNEL_STATS_CSV --command CMD
+    python paper_2301_10570_amd/rocprof_summary.py traffic --fetch FETCH_CSV --write WRITE_CSV \\
+        --kernel NAME --source FILE --copy-bytes B --command CMD
+
+`stats` lists every kernel of a `--kernel-trace --stats` run (calls, total and
+average duration).  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters
+(KiB per dispatch, one `--pmc` run each) of one kernel into HBM bytes per
+launch, scaled by what the same counters read for the largest device copy of
+the run (`__amd_rocclr_copyBuffer` of --copy-bytes bytes read and written),
+and records the SHA-256 of the kernel's source file so that a reader can tell
+whether the kernel has changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import sys
+
+
+def short_name(name: str) -> str:
+    m = re.search(r"(k_[A-Za-z0-9_]+(<\d+>)?|__amd_rocclr_\w+|\w*elementwise_kernel\w*)", name)
+    return m.group(1) if m else name[:48]
+
+
+def stats(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["# rocprofv3 kernel statistics", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+           "    " + command, "",
+           f"Total kernel time {total / 1e6:.3f} ms over the whole run.", "",
+           "| kernel | calls | total ms | avg us | min us | max us | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| {} | {} | {:.3f} | {:.1f} | {:.1f} | {:.1f} | {:.2f} |".format(
+            short_name(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def _counter(path: str, counter: str):
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        per.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return per
+
+
+def traffic(fetch: str, write: str, kernel: str, source: str, copy_bytes: float, command: str) -> str:
+    f = _counter(fetch, "FETCH_SIZE")
+    w = _counter(write, "WRITE_SIZE")
+    if kernel not in f or kernel not in w:
+        raise SystemExit(f"kernel {kernel} not found in the counter files")
+    copy_f = max(f.get("__amd_rocclr_copyBuffer", [0.0]))
+    copy_w = max(w.get("__amd_rocclr_copyBuffer", [0.0]))
+    if copy_f <= 0 or copy_w <= 0:
+        raise SystemExit("no copy kernel in the counter files")
+    sf = copy_bytes / (copy_f * 1024.0)
+    sw = copy_bytes / (copy_w * 1024.0)
+    kf = sum(f[kernel]) / len(f[kernel])
+    kw = sum(w[kernel]) / len(w[kernel])
+    bytes_per_launch = kf * 1024.0 * sf + kw * 1024.0 * sw
+    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    out = ["# HBM traffic of " + kernel, "",
+           "Commands (from /tmp, TMPDIR=/tmp), one counter per run:", "",
+           "    " + command.replace("COUNTER", "FETCH_SIZE"),
+           "    " + command.replace("COUNTER", "WRITE_SIZE"), "",
+           "| counter | dispatches | mean KiB/dispatch | min | max |", "|---|---:|---:|---:|---:|",
+           f"| FETCH_SIZE | {len(f[kernel])} | {kf:.1f} | {min(f[kernel]):.1f} | {max(f[kernel]):.1f} |",
+           f"| WRITE_SIZE | {len(w[kernel])} | {kw:.1f} | {min(w[kernel]):.1f} | {max(w[kernel]):.1f} |",
+           "",
+           f"Calibration: a device copy of {copy_bytes:.0f} bytes (read and written once) reads "
+           f"FETCH_SIZE {copy_f:.1f} KiB and WRITE_SIZE {copy_w:.1f} KiB, so the counters are scaled by "
+           f"{sf:.4f} (fetch) and {sw:.4f} (write).", "",
+           f"traffic_bytes_per_launch: {bytes_per_launch:.6e}",
+           f"source_sha256: {os.path.relpath(source)} {sha}", ""]
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--command", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--source", required=True)
+    b.add_argument("--copy-bytes", type=float, required=True)
+    b.add_argument("--command", required=True)
+    args = ap.parse_args()
+    if args.what == "stats":
+        sys.stdout.write(stats(args.csv, args.command))
+    else:
+        sys.stdout.write(traffic(args.fetch, args.write, args.kernel, args.source, args.copy_bytes,
+                                 args.command))
+
+
+if __name__ == "__main__":
+    main()
