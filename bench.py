@@ -192,6 +192,26 @@ def main():
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / args.steps
 
+    # forward only with the translation (M2L) as split-bfloat16 matrix-core
+    # products, against the float32 matrix-core passes
+    ub = torch.empty_like(u)
+    tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l="bf16x3")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l="bf16x3")
+    torch.cuda.synchronize()
+    ms_fwd_b = 1000.0 * (time.perf_counter() - t0) / args.steps
+    m2l_ms = {}
+    for mode in ("mfma", "bf16x3"):
+        tree.set_timing(True)
+        tree.timing(reset=True)
+        for _ in range(args.steps):
+            tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l=mode)
+        ph = tree.timing(reset=True)
+        tree.set_timing(False)
+        m2l_ms[mode] = sum(ph[k][0] for k in ("m2l_x", "m2l_y", "m2l_z") if k in ph) / args.steps
+
     # forward + backward (L = sum u_i over targets, g = 1): gradients w.r.t. the
     # weights, the positions and sigma; the tree is rebuilt every step
     gone = torch.ones(wl.n, dtype=torch.float32, device=dev)
@@ -253,6 +273,8 @@ def main():
         "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
         "fwd_bwd_ms": ms_fb,
         "partner_queries_per_step": int(tq.numel()),
+        "m2l_bf16x3": {"forward_only_ms": ms_fwd_b, "m2l_ms": m2l_ms["bf16x3"],
+                       "m2l_fp32_mfma_ms": m2l_ms["mfma"]},
     }
 
     sample = None
@@ -269,6 +291,10 @@ def main():
         result["accuracy"] = {"targets_checked": int(sample.size), "max_rel_err": float(rel.max()),
                               "p50_rel_err": float(np.median(rel)), "bar": 1e-4,
                               "pass": bool(rel.max() <= 1e-4)}
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l="bf16x3")
+        relb = np.abs(ub.cpu().numpy()[sample].astype(np.float64) - ref) / ref
+        result["m2l_bf16x3"].update({"max_rel_err": float(relb.max()),
+                                     "p50_rel_err": float(np.median(relb))})
 
     if not args.no_direct:
         print("bench: all-pairs GPU direct sum on sampled targets", file=sys.stderr, flush=True)

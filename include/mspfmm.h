@@ -70,7 +70,12 @@ enum msp_flags {
      * sub-cells two levels below the expansion level with fewer terms, joined to
      * it by M2M and L2L shifts (used when p is 6..8 and cells hold >= 512 points;
      * msp_fgt_info.fine_terms reports it). */
-    MSP_TWO_LEVEL = 1u << 2
+    MSP_TWO_LEVEL = 1u << 2,
+    /* Run the Hermite-to-Taylor translation as split bfloat16 products on the
+     * matrix cores: every float32 operand x becomes hi = bf16(x) plus
+     * lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi is accumulated in float32
+     * (about 2^-16 of each product is lost).  Exclusive with MSP_M2L_VALU. */
+    MSP_M2L_BF16X3 = 1u << 3
 };
 
 typedef struct msp_tree msp_tree; /* opaque handle */

@@ -29,6 +29,7 @@ ROUTE_NAMES = {v: k for k, v in ROUTES.items()}
 EXCLUDE_SELF = 1
 M2L_VALU = 2
 TWO_LEVEL = 4
+M2L_BF16X3 = 8
 
 
 class MspError(RuntimeError):
@@ -125,9 +126,9 @@ def _ptr(t: torch.Tensor | None, dtype: torch.dtype, n: int | None, name: str):
 
 def _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l="mfma", two_level=False) -> FgtParams:
     flags = (EXCLUDE_SELF if exclude_self else 0) | (M2L_VALU if m2l == "valu" else 0)
-    flags |= TWO_LEVEL if two_level else 0
-    if m2l not in ("mfma", "valu"):
-        raise ValueError(f"m2l must be 'mfma' or 'valu', got {m2l!r}")
+    flags |= (M2L_BF16X3 if m2l == "bf16x3" else 0) | (TWO_LEVEL if two_level else 0)
+    if m2l not in ("mfma", "valu", "bf16x3"):
+        raise ValueError(f"m2l must be 'mfma', 'valu' or 'bf16x3', got {m2l!r}")
     return FgtParams(int(p), int(level), float(sigma), float(cutoff_sigmas),
                      ROUTES[route] if isinstance(route, str) else int(route), flags)
 
@@ -223,7 +224,7 @@ class Tree:
         return out
 
     def backward(self, w, grad_u, is_target=None, sigma=100.0, p=8, level=-1, route="auto",
-                 cutoff_sigmas=4.5, exclude_self=False, want=("w", "pos", "sigma")):
+                 cutoff_sigmas=4.5, exclude_self=False, want=("w", "pos", "sigma"), m2l="mfma"):
         """Derivatives of sum_i grad_u[i] * u_i (targets only): dict with 'w' [n],
         'pos' ([n] x, y, z tensors), 'sigma' (float64 [1])."""
         n = self.n
@@ -235,7 +236,7 @@ class Tree:
         gw = torch.empty(n, dtype=torch.float32, device=dev) if "w" in want else None
         gpos = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)] if "pos" in want else None
         gs = torch.zeros(1, dtype=torch.float64, device=dev) if "sigma" in want else None
-        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self)
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l)
         ptr = lambda x: x.data_ptr() if (x is not None and x.numel()) else None
         _check(_lib.msp_fgt_backward(self._h, pw, pt, ctypes.byref(prm), pg, ptr(gw),
                                      *(ptr(g) for g in (gpos or (None, None, None))), ptr(gs), _stream()),
@@ -306,7 +307,7 @@ class _AttractionFn(torch.autograd.Function):
         s = float(sigma.item()) if isinstance(sigma, torch.Tensor) else float(sigma)
         u = tree.forward(w, is_target, sigma=s, p=opts.get("p", 8), route=opts.get("route", "auto"),
                          cutoff_sigmas=opts.get("cutoff_sigmas", 4.5),
-                         exclude_self=opts.get("exclude_self", False))
+                         exclude_self=opts.get("exclude_self", False), m2l=opts.get("m2l", "mfma"))
         ctx.tree, ctx.sigma, ctx.opts = tree, s, opts
         ctx.save_for_backward(w, is_target if is_target is not None else torch.empty(0))
         ctx.sigma_is_tensor = isinstance(sigma, torch.Tensor)
@@ -328,7 +329,8 @@ class _AttractionFn(torch.autograd.Function):
             return None, None, None, None, None, None, None
         g = ctx.tree.backward(w, grad_u.contiguous().float(), tg, sigma=ctx.sigma, p=o.get("p", 8),
                               route=o.get("route", "auto"), cutoff_sigmas=o.get("cutoff_sigmas", 4.5),
-                              exclude_self=o.get("exclude_self", False), want=tuple(want))
+                              exclude_self=o.get("exclude_self", False), want=tuple(want),
+                              m2l=o.get("m2l", "mfma"))
         gx = gy = gz = None
         if need_pos:
             gx, gy, gz = g["pos"]
@@ -339,11 +341,11 @@ class _AttractionFn(torch.autograd.Function):
 
 
 def attraction(x, y, z, w, sigma, is_target=None, p=8, route="auto", cutoff_sigmas=4.5,
-               exclude_self=False, leaf_max=64, tree=None):
+               exclude_self=False, leaf_max=64, tree=None, m2l="mfma"):
     """Differentiable attraction sums u (float32 [n], 0 for non-targets).
 
     x, y, z, w: CUDA float32 [n]; sigma: float or 0-d CUDA tensor.  Gradients flow
     to x, y, z, w and sigma through msp_fgt_backward (no autograd tape inside)."""
     opts = dict(p=p, route=route, cutoff_sigmas=cutoff_sigmas, exclude_self=exclude_self,
-                leaf_max=leaf_max, tree=tree)
+                leaf_max=leaf_max, tree=tree, m2l=m2l)
     return _AttractionFn.apply(x, y, z, w, sigma, is_target, opts)

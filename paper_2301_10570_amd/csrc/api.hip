@@ -97,8 +97,10 @@ static int check_params(const msp_fgt_params *prm) {
     if (!(prm->sigma > 0.f) || !std::isfinite(prm->sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
     if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
     if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
-    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL))
+    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL | MSP_M2L_BF16X3))
         return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
+    if ((prm->flags & MSP_M2L_VALU) && (prm->flags & MSP_M2L_BF16X3))
+        return fail(MSP_EINVAL, "MSP_M2L_VALU and MSP_M2L_BF16X3 exclude each other");
     if (std::isnan(prm->cutoff_sigmas)) return fail(MSP_EINVAL, "cutoff_sigmas is NaN");
     return MSP_OK;
 }

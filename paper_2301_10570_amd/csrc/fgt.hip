@@ -288,6 +288,92 @@ __global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Ou
             }
 }
 
+// The same pass with split bfloat16 products (v_mfma_f32_16x16x32_bf16): each
+// FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi), and
+// hi*hi + hi*lo + lo*hi is accumulated in FP32.  The dropped lo*lo term and the
+// rounding of lo leave about 2^-16 of each product.  A lane supplies eight
+// consecutive k of its row of A and of its column of B (the same k for both).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+constexpr int MK2 = 32;
+
+__device__ inline unsigned short bf16_bits(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline void split_bf16(const float *src, int stride, bf16x8 &hi, bf16x8 &lo) {
+    u16x8 h, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float x = src[j * stride];
+        const unsigned short hb = bf16_bits(x);
+        h[j] = hb;
+        l[j] = bf16_bits(x - __uint_as_float((uint32_t)hb << 16));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+__global__ void __launch_bounds__(64) k_m2l_pass_bf16x3(const float *In, float *Out, int64_t R, int p,
+                                                        int G, const float *T) {
+    __shared__ float sA[MT][MK2 + 1];   // operator rows v, columns u
+    __shared__ float sB[MT][MK2 + 1];   // input rows r, columns u
+    const int U = G * p;
+    const int64_t r0 = (int64_t)blockIdx.x * MT;
+    const int v0 = blockIdx.y * MT;
+    const int lane = threadIdx.x;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int u0 = 0; u0 < U; u0 += MK2) {
+#pragma unroll
+        for (int e = lane; e < MT * MK2; e += 64) {
+            const int row = e / MK2, kk = e % MK2;
+            const int u = u0 + kk;
+            const int v = v0 + row;
+            float m = 0.f;
+            if (v < U && u < U) {
+                const int t = v / p, b = v % p, sI = u / p, a = u % p;
+                m = T[((size_t)(t - sI + G - 1) * p + b) * p + a];
+            }
+            sA[row][kk] = m;
+            const int64_t r = r0 + row;
+            sB[row][kk] = (r < R && u < U) ? In[r * U + u] : 0.f;
+        }
+        __syncthreads();
+        const int k8 = 8 * (lane >> 4), rr = lane & 15;
+        bf16x8 a0h, a0l, a1h, a1l, b0h, b0l, b1h, b1l;
+        split_bf16(&sA[rr][k8], 1, a0h, a0l);
+        split_bf16(&sA[16 + rr][k8], 1, a1h, a1l);
+        split_bf16(&sB[rr][k8], 1, b0h, b0l);
+        split_bf16(&sB[16 + rr][k8], 1, b1h, b1l);
+#define MSP_BF16X3(ACC, AH, AL, BH, BL)                                              \
+    ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, BH, ACC, 0, 0, 0);             \
+    ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BL, ACC, 0, 0, 0);             \
+    ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BH, ACC, 0, 0, 0);
+        MSP_BF16X3(acc[0][0], a0h, a0l, b0h, b0l)
+        MSP_BF16X3(acc[0][1], a0h, a0l, b1h, b1l)
+        MSP_BF16X3(acc[1][0], a1h, a1l, b0h, b0l)
+        MSP_BF16X3(acc[1][1], a1h, a1l, b1h, b1l)
+#undef MSP_BF16X3
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = v0 + 16 * a + 4 * (lane >> 4) + i;
+                const int64_t r = r0 + 16 * b + (lane & 15);
+                if (v < U && r < R) Out[(int64_t)v * R + r] = acc[a][b][i];
+            }
+}
+
 // One block per cell: evaluate the cell's Taylor series at its targets (Horner
 // in x, then y, then z), two targets per thread so that every coefficient read
 // from LDS feeds two multiply-adds.
@@ -927,12 +1013,16 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
                             {B, Tmp, Ux * Uz, pl.G[1], opsy, Uy},
                             {Tmp, B, Uy * Ux, pl.G[2], opsz, Uz}};
     const bool valu = (prm->flags & MSP_M2L_VALU) != 0;
+    const bool bf16x3 = (prm->flags & MSP_M2L_BF16X3) != 0;
     for (int k = 0; k < 3; ++k) {
         const Pass &ps = passes[k];
         PhaseScope sc(&t->timing, PH_M2L_X + k, s);
         if (valu) {
             dim3 grid((unsigned)((ps.R + TR - 1) / TR), (unsigned)((ps.U + TV - 1) / TV));
             hipLaunchKernelGGL(k_m2l_pass, grid, dim3(kBlock), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+        } else if (bf16x3) {
+            dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
+            hipLaunchKernelGGL(k_m2l_pass_bf16x3, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
         } else {
             dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
             hipLaunchKernelGGL(k_m2l_pass_mfma, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);

@@ -216,6 +216,43 @@ def test_m2l_matrix_cores_match_vector_path(p, level):
     np.testing.assert_allclose(u_m[tgt], u_v[tgt], rtol=1e-5)
 
 
+@pytest.mark.parametrize("p,level", [(8, 4), (5, 5), (10, 3)])
+def test_m2l_bf16x3_matches_fp32(p, level):
+    """Split-bfloat16 translation passes: Taylor grid within the split's rounding
+    (about 2^-16 per product) of the float32 vector-ALU grid, on ragged grids."""
+    import paper_2301_10570_amd as msp
+    wl = synth.config(3, 0.03)
+    print(f"M2L bf16x3 vs valu p={p} level={level}", flush=True)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"])
+    u_b = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, level=level, route="fgt", m2l="bf16x3").cpu().numpy()
+    C_b = tree.debug_buffer(1).cpu().numpy()
+    u_v = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, level=level, route="fgt", m2l="valu").cpu().numpy()
+    C_v = tree.debug_buffer(1).cpu().numpy()
+    scale = np.abs(C_v).max()
+    dC = np.abs(C_b - C_v).max() / scale
+    tgt = wl.a > 0
+    du = np.abs(u_b[tgt] - u_v[tgt]) / np.abs(u_v[tgt])
+    print(f"  grid max |dC|/max|C| {dC:.2e}, u max rel diff {du.max():.2e}")
+    assert dC <= 2e-4
+    assert du.max() <= 5e-5
+
+
+@pytest.mark.parametrize("p", [4, 6, 8, 10])
+def test_config3_bf16x3_vs_oracle(slab, p):
+    """Full slab with the split-bfloat16 translation: error against the FP64
+    oracle per p, within the 1e-4 bar."""
+    import paper_2301_10570_amd as msp
+    wl, sel, ref = slab
+    print(f"config 3 full slab p={p} m2l=bf16x3", flush=True)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"])
+    u = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, route="fgt", m2l="bf16x3").cpu().numpy()
+    err = rel_err(u[sel], ref)
+    print(f"  max rel err {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= TOL
+
+
 def test_two_level_m2m_l2l(slab):
     """Moments at sub-cells two levels down with fewer terms, M2M up, M2L, L2L
     down with truncation: same moment grid as single-level P2M up to the dropped
