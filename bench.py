@@ -116,7 +116,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+                    help="budget for the oracle sample, from a short probe (which overestimates)")
     ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three copies of 1 GiB (counter calibration runs)")

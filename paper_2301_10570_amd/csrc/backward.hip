@@ -16,6 +16,7 @@ namespace msp {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRec = 16;   // floats per point record of the backward pass (64 bytes)
 
 __global__ void k_target_weights(const float *g, const uint8_t *is_target, int64_t n, float *gt) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -43,8 +44,7 @@ __global__ void __launch_bounds__(64) k_p2p_grad(int64_t n_nodes, const int32_t 
                                                  const int32_t *niy, const int32_t *niz, BoxGeo geo,
                                                  const int64_t *off, const int32_t *lst,
                                                  const float4 *ps, float kexp, float inv_s2,
-                                                 float *val, float *gx, float *gy, float *gz,
-                                                 float *lap) {
+                                                 float *out, int stride, int want_lap) {
     const int64_t v = blockIdx.x;
     if (v >= n_nodes || nnchild[v] != 0) return;
     __shared__ float4 src[64];
@@ -96,34 +96,39 @@ __global__ void __launch_bounds__(64) k_p2p_grad(int64_t n_nodes, const int32_t 
             float r[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
             for (int q = 0; q < G; ++q)
                 for (int k = 0; k < 5; ++k) r[k] += red[k][q * tp + a];
-            val[ti] = r[0];
-            gx[ti] = -2.f * inv_s2 * r[1];
-            gy[ti] = -2.f * inv_s2 * r[2];
-            gz[ti] = -2.f * inv_s2 * r[3];
-            if (lap) lap[ti] = 4.f * inv_s2 * inv_s2 * r[4] - 6.f * inv_s2 * r[0];
+            float *o = out + (int64_t)ti * stride;   // value, gradient x y z, Laplacian
+            o[0] = r[0];
+            o[1] = -2.f * inv_s2 * r[1];
+            o[2] = -2.f * inv_s2 * r[2];
+            o[3] = -2.f * inv_s2 * r[3];
+            if (want_lap) o[4] = 4.f * inv_s2 * inv_s2 * r[4] - 6.f * inv_s2 * r[0];
         }
     }
 }
 
-// Back to input order; per-block partial sums of the sigma derivative.
-__global__ void k_combine(int64_t n, const int32_t *perm, const float *gt, const float *w,
-                          const float *Av, const float *Agx, const float *Agy, const float *Agz,
-                          const float *Alap, const float *Bv, const float *Bgx, const float *Bgy,
-                          const float *Bgz, double sigma, int exclude_self, float *grad_w,
-                          float *grad_x, float *grad_y, float *grad_z, double *partial) {
+// Per point of the input order j: the key-order record of its point (64 bytes,
+// one aligned segment: A value, gradient, Laplacian, then B value, gradient)
+// combined into the gradients; per-block partial sums of the sigma derivative.
+__global__ void k_combine(int64_t n, const int32_t *iperm, const float *gt, const float *w,
+                          const float *rec, int want_w, int want_pos, int want_sigma, double sigma,
+                          int exclude_self, float *grad_w, float *grad_x, float *grad_y, float *grad_z,
+                          double *partial) {
     __shared__ double red[kBlock];
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     double ds = 0.0;
-    if (i < n) {
-        const int32_t j = perm[i];
-        const float g = gt[j], wj = w[j];
-        if (grad_w) grad_w[j] = exclude_self ? Bv[i] - g : Bv[i];
-        if (grad_x) {
-            grad_x[j] = g * Agx[i] + wj * Bgx[i];
-            grad_y[j] = g * Agy[i] + wj * Bgy[i];
-            grad_z[j] = g * Agz[i] + wj * Bgz[i];
+    if (j < n) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(rec + (int64_t)iperm[j] * kRec);
+        const float4 a = r4[0], b = r4[1], c = r4[2];
+        // a = (Av, Agx, Agy, Agz), b = (Alap, Bv, Bgx, Bgy), c = (Bgz, -, -, -)
+        const float g = gt[j];
+        if (want_w) grad_w[j] = exclude_self ? b.y - g : b.y;
+        if (want_pos) {
+            const float wj = w[j];
+            grad_x[j] = g * a.y + wj * b.z;
+            grad_y[j] = g * a.z + wj * b.w;
+            grad_z[j] = g * a.w + wj * c.x;
         }
-        if (Alap) ds = (double)g * (0.5 * sigma * (double)Alap[i] + 3.0 / sigma * (double)Av[i]);
+        if (want_sigma) ds = (double)g * (0.5 * sigma * (double)b.x + 3.0 / sigma * (double)a.x);
     }
     red[threadIdx.x] = ds;
     __syncthreads();
@@ -149,8 +154,8 @@ __global__ void k_sum_partials(const double *partial, int64_t m, double *out) {
 
 }  // namespace
 
-int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *val, float *gx, float *gy,
-                      float *gz, float *lap, hipStream_t s) {
+int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *out, int stride, int want_lap,
+                      hipStream_t s) {
     // the leaf lists of the direct route are built (or reused) by direct_route's
     // list pass; ps.w holds the staged weights of this evaluation
     const int64_t nn = t->n_nodes;
@@ -163,7 +168,7 @@ int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *val, float 
                        t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(), t->nlevel.as<int32_t>(),
                        t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), geo,
                        t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(), kexp,
-                       inv_s2, val, gx, gy, gz, lap);
+                       inv_s2, out, stride, want_lap);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
@@ -176,44 +181,45 @@ int fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target, const ms
     MSP_TRY(plan_fgt(t, prm, &pl));
     const int64_t nb = n > 0 ? n : 1;
     const int64_t nblk = (nb + kBlock - 1) / kBlock;
-    // scratch: gt (input order), A: val gx gy gz lap, B: val gx gy gz (key order), partials
-    MSP_TRY(t->bwd.ensure((size_t)nb * 4 * 10 + (size_t)nblk * 8 + 64));
-    float *gt = t->bwd.as<float>();
-    float *Av = gt + nb, *Agx = Av + nb, *Agy = Agx + nb, *Agz = Agy + nb, *Alap = Agz + nb;
-    float *Bv = Alap + nb, *Bgx = Bv + nb, *Bgy = Bgx + nb, *Bgz = Bgy + nb;
-    double *partial = reinterpret_cast<double *>(Bgz + nb);   // 10*nb floats in: 8-byte aligned
+    // scratch: one 64-byte record per point in key order (A: value, gradient,
+    // Laplacian; B: value, gradient), gt in input order, block partials
+    MSP_TRY(t->bwd.ensure((size_t)nb * kRec * 4 + (size_t)nb * 4 + (size_t)nblk * 8 + 64));
+    float *rec = t->bwd.as<float>();
+    float *gt = rec + (size_t)nb * kRec;
+    double *partial = reinterpret_cast<double *>(gt + nb + (nb & 1));
     if (n == 0) {
         if (grad_sigma) MSP_HIP(hipMemsetAsync(grad_sigma, 0, sizeof(double), s));
         return MSP_OK;
     }
     const bool needA = grad_x || grad_sigma;
     const bool needB = grad_w || grad_x;
+    MSP_TRY(ensure_iperm(t, s));
     hipLaunchKernelGGL(k_target_weights, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, grad_u, is_target,
                        n, gt);
     MSP_CHECK_LAUNCH();
     if (pl.route == MSP_ROUTE_FGT) {
-        if (needA) MSP_TRY(fgt_field_grad(t, pl, prm, w, Av, Agx, Agy, Agz, Alap, s));
-        if (needB) MSP_TRY(fgt_field_grad(t, pl, prm, gt, Bv, Bgx, Bgy, Bgz, nullptr, s));
+        if (needA) MSP_TRY(fgt_field_grad(t, pl, prm, w, rec, kRec, grad_sigma ? 1 : 0, s));
+        if (needB) MSP_TRY(fgt_field_grad(t, pl, prm, gt, rec + 5, kRec, 0, s));
     } else {
         msp_fgt_params q = *prm;
         q.flags &= ~(uint32_t)MSP_EXCLUDE_SELF;
         if (needA) {
             MSP_TRY(stage_inputs(t, w, nullptr, s));
             MSP_TRY(direct_route_lists(t, &q, s));
-            MSP_TRY(direct_field_grad(t, &q, Av, Agx, Agy, Agz, Alap, s));
+            MSP_TRY(direct_field_grad(t, &q, rec, kRec, grad_sigma ? 1 : 0, s));
         }
         if (needB) {
             MSP_TRY(stage_inputs(t, gt, nullptr, s));
             MSP_TRY(direct_route_lists(t, &q, s));
-            MSP_TRY(direct_field_grad(t, &q, Bv, Bgx, Bgy, Bgz, nullptr, s));
+            MSP_TRY(direct_field_grad(t, &q, rec + 5, kRec, 0, s));
         }
     }
     {
         PhaseScope ps(&t->timing, PH_BACKWARD, s);
-        hipLaunchKernelGGL(k_combine, dim3((unsigned)nblk), dim3(kBlock), 0, s, n, t->perm.as<int32_t>(), gt,
-                           w, Av, Agx, Agy, Agz, grad_sigma ? Alap : nullptr, Bv, Bgx, Bgy, Bgz,
-                           (double)prm->sigma, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0,
-                           needB ? grad_w : nullptr, grad_x, grad_y, grad_z, partial);
+        hipLaunchKernelGGL(k_combine, dim3((unsigned)nblk), dim3(kBlock), 0, s, n, t->iperm.as<int32_t>(), gt,
+                           w, rec, grad_w && needB ? 1 : 0, grad_x ? 1 : 0, grad_sigma ? 1 : 0,
+                           (double)prm->sigma, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, grad_w, grad_x,
+                           grad_y, grad_z, partial);
         MSP_CHECK_LAUNCH();
         if (grad_sigma) {
             hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, nblk, grad_sigma);

@@ -729,8 +729,8 @@ template <int P>
 __global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64_t n, const float4 *ps,
                                                      int level, int Gx, int Gy, int Gz, double lox,
                                                      double loy, double loz, double cell,
-                                                     double inv_sigma, const float *C, float *val,
-                                                     float *gx, float *gy, float *gz, float *lap) {
+                                                     double inv_sigma, const float *C, float *out,
+                                                     int stride, int want_lap) {
     constexpr int P3 = P * P * P;
     __shared__ float sC[P3];
     const int64_t g = blockIdx.x;
@@ -780,11 +780,12 @@ __global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64
             zy1 = fmaf(zy1, Z, yd1);
             zy2 = fmaf(zy2, Z, 2.f * yd2);
         }
-        val[i] = z0;
-        gx[i] = z1 * is;
-        gy[i] = zy1 * is;
-        gz[i] = zd1 * is;
-        if (lap) lap[i] = (z2 + zy2 + 2.f * zd2) * is * is;
+        float *o = out + i * stride;   // value, gradient x y z, Laplacian
+        o[0] = z0;
+        o[1] = z1 * is;
+        o[2] = zy1 * is;
+        o[3] = zd1 * is;
+        if (want_lap) o[4] = (z2 + zy2 + 2.f * zd2) * is * is;
     }
 }
 
@@ -876,20 +877,20 @@ int dispatch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p,
 
 namespace {
 template <int P>
-int launch_l2p_grad(msp_tree *t, const FgtPlan &pl, double inv_sigma, const float *C, float *val,
-                    float *gx, float *gy, float *gz, float *lap, hipStream_t s) {
+int launch_l2p_grad(msp_tree *t, const FgtPlan &pl, double inv_sigma, const float *C, float *out,
+                    int stride, int want_lap, hipStream_t s) {
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p_grad<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                        t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), pl.level, pl.G[0], pl.G[1],
-                       pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, val, gx,
-                       gy, gz, lap);
+                       pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, out,
+                       stride, want_lap);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
 }  // namespace
 
 int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
-                   float *val, float *gx, float *gy, float *gz, float *lap, hipStream_t s) {
+                   float *out, int stride, int want_lap, hipStream_t s) {
     // moments of w, all-pairs translation, then value/gradient/Laplacian at every point
     msp_fgt_params q = *prm;
     q.flags &= ~(uint32_t)MSP_TWO_LEVEL;
@@ -900,7 +901,7 @@ int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, co
     const float *C = t->gridB.as<float>();
     PhaseScope ps(&t->timing, PH_L2P, s);
     switch (pl.p) {
-#define CASE(P) case P: return launch_l2p_grad<P>(t, pl, inv_sigma, C, val, gx, gy, gz, lap, s);
+#define CASE(P) case P: return launch_l2p_grad<P>(t, pl, inv_sigma, C, out, stride, want_lap, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE

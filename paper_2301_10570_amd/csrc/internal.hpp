@@ -160,10 +160,12 @@ int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStrea
 int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, const float *w,
                      const uint8_t *is_target, float *u_out, hipStream_t s);
 int ensure_iperm(msp_tree *t, hipStream_t s);
+// Value, gradient (x, y, z) and, with want_lap, Laplacian of the field of weights w
+// at every point, in key order: point i writes out[i * stride + 0 .. 4].
 int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
-                   float *val, float *gx, float *gy, float *gz, float *lap, hipStream_t s);
-int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *val, float *gx, float *gy,
-                      float *gz, float *lap, hipStream_t s);
+                   float *out, int stride, int want_lap, hipStream_t s);
+int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *out, int stride, int want_lap,
+                      hipStream_t s);
 int fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
                  const float *grad_u, float *grad_w, float *grad_x, float *grad_y, float *grad_z,
                  double *grad_sigma, hipStream_t s);
