@@ -105,6 +105,77 @@ def _partner_queries(tree, k, seed):
     return T(tq), T(node)
 
 
+def _batch_bench(args, dev, oracle_threads):
+    """256 independent populations (sizes log-uniform in [1024, 65536], sigma
+    log-uniform in [50, 300] um, each in its own 1 mm cube): autotuned leaf size
+    and route per population, the forward as one captured hipGraph (all
+    direct-route populations in one persistent launch), per-population latency
+    from device timestamps, forward + backward, and accuracy on sampled targets."""
+    import numpy as np
+    import torch
+
+    import paper_2301_10570_amd as msp
+    import synth
+    pops = synth.populations()
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.concatenate(a))).to(dev)
+    x, y, z, w = (T([getattr(p, k) for p in pops]) for k in ("x", "y", "z", "w"))
+    tg = T([(p.a > 0).astype(np.uint8) for p in pops])
+    off = np.concatenate([[0], np.cumsum([p.n for p in pops])]).astype(np.int64)
+    sig = np.array([p.sigma for p in pops], dtype=np.float32)
+    n_tgt = int(sum(int((p.a > 0).sum()) for p in pops))
+    b = msp.Batch()
+    t0 = time.perf_counter()
+    leaf, routes = b.autotune(x, y, z, off, w, sig, is_target=tg, p=args.p, candidates=(32, 64, 128))
+    tune_s = time.perf_counter() - t0
+    u = torch.empty(int(off[-1]), dtype=torch.float32, device=dev)
+    b.forward(w, sig, is_target=tg, p=args.p, out=u)        # eager, then captured
+    launches = b.info()["launches_last_eager_forward"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.forward(w, sig, is_target=tg, p=args.p, out=u)    # graph replay
+    torch.cuda.synchronize()
+    ms_graph = 1000.0 * (time.perf_counter() - t0) / args.steps
+    inst = b.instance_ms()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.forward(w, sig, is_target=tg, p=args.p, out=u, use_graph=False)
+    torch.cuda.synchronize()
+    ms_eager = 1000.0 * (time.perf_counter() - t0) / args.steps
+    gone = torch.ones(int(off[-1]), dtype=torch.float32, device=dev)
+    b.backward(w, gone, sig, is_target=tg, p=args.p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.forward(w, sig, is_target=tg, p=args.p, out=u)
+        b.backward(w, gone, sig, is_target=tg, p=args.p)
+    torch.cuda.synchronize()
+    ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
+    res = {"workload": "256 populations, n log-uniform 1024-65536, sigma log-uniform 50-300 um, 1 mm cubes",
+           "points": int(off[-1]), "targets": n_tgt, "autotune_s": tune_s,
+           "routes": {"fgt": routes.count("fgt"), "direct": routes.count("direct")},
+           "leaf_sizes": {str(k): int((leaf == k).sum()) for k in (32, 64, 128)},
+           "forward_ms_graph": ms_graph, "forward_ms_eager": ms_eager,
+           "sums_per_s": n_tgt / (ms_graph / 1000.0), "launches_per_forward_eager": launches,
+           "instance_ms_p50": float(np.percentile(inst, 50)), "instance_ms_p99": float(np.percentile(inst, 99)),
+           "fwd_bwd_ms": ms_fb}
+    if not args.no_check:
+        import oracle
+        u_h = u.cpu().numpy()
+        errs = []
+        for k in synth.sample_indices(len(pops), 32, seed=783):
+            wl = pops[k]
+            tgt = np.nonzero(wl.a > 0)[0]
+            sel = tgt[synth.sample_indices(tgt.size, 8, seed=784 + int(k))]
+            ref = oracle.attraction(wl, sel, threads=oracle_threads)
+            errs.append(np.abs(u_h[off[k]:off[k + 1]][sel].astype(np.float64) - ref) / ref)
+        e = np.concatenate(errs)
+        res["accuracy"] = {"targets_checked": int(e.size), "max_rel_err": float(e.max()), "bar": 1e-4,
+                           "pass": bool(e.max() <= 1e-4)}
+    b.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +190,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="budget for the oracle sample, from a short probe (which overestimates)")
     ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-population batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three copies of 1 GiB (counter calibration runs)")
     args = ap.parse_args()
@@ -337,6 +409,9 @@ def main():
                                   "sample": f"{k} seeded targets of the slab, each summed over all "
                                             f"{n_src} sources in FP64 ({dt:.1f} s)"}
     tree.close()
+    if not args.no_batch:
+        print("bench: 256-population batch", file=sys.stderr, flush=True)
+        result["batch"] = _batch_bench(args, dev, min(16, len(os.sched_getaffinity(0))))
     print(json.dumps(result), flush=True)
 
 

@@ -239,6 +239,63 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
                          void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent populations (many uneven-size networks, each with its
+ * own sigma).  The caller concatenates the populations: population k owns the
+ * indices offsets[k] .. offsets[k+1]-1 of every per-point array (x, y, z, w,
+ * is_target, u_out, gradients).  Every population gets its own octree; the
+ * kernels of a forward call cover all of them: populations on the expansion
+ * route run their own short sequence, and all populations on the direct route
+ * share one persistent launch that takes (population, node) work items from a
+ * device counter.  The first forward call with a given argument set runs
+ * eagerly and captures the sequence into a hipGraph; later calls with the same
+ * pointers, sigmas and parameters replay it on `stream`.  Calls on one batch
+ * must not overlap (they share the work counter and scratch).
+ * ------------------------------------------------------------------------- */
+typedef struct msp_batch msp_batch; /* opaque handle */
+
+int msp_batch_create(msp_batch **out);
+void msp_batch_destroy(msp_batch *b);
+
+/* Build the octrees.  offsets: host int64[npop + 1], offsets[0] = 0, non-decreasing;
+ * leaf_max: host int32[npop] or NULL (64 for all); max_depth as msp_octree_build.
+ * Synchronises `stream`.  Invalidates a captured graph. */
+int msp_batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                    int32_t npop, const int32_t *leaf_max, int32_t max_depth, void *stream);
+
+/* Autotuner: for every population, build its tree at each candidate leaf size
+ * (host int32[ncand]), time three forward calls on each route whose grid fits,
+ * keep the fastest (leaf size, route) pair, and build the batch with the choices
+ * (later forward calls with prm->route == MSP_ROUTE_AUTO use the chosen routes).
+ * scratch_u: device float32[offsets[npop]] written during the trials.  leaf_out,
+ * route_out: host int32[npop] or NULL.  Synchronises `stream`. */
+int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float *z,
+                       const int64_t *offsets, int32_t npop, const float *w, const uint8_t *is_target,
+                       const float *sigma, const msp_fgt_params *prm, const int32_t *cand, int32_t ncand,
+                       int32_t max_depth, float *scratch_u, int32_t *leaf_out, int32_t *route_out,
+                       void *stream);
+
+/* Forward of every population (as msp_fgt_forward on its slice).  sigma: host
+ * float32[npop] (prm->sigma is ignored); the other fields of prm apply to all.
+ * use_graph = 0 runs eagerly every time. */
+int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                      const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream);
+
+/* Backward of every population (as msp_fgt_backward on its slice); grad_sigma:
+ * device float64[npop] or NULL. */
+int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                       const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                       float *grad_y, float *grad_z, double *grad_sigma, void *stream);
+
+/* Per-population latency of the last forward call, from device timestamps
+ * (host double[npop], milliseconds; 0 for empty populations).  Waits for the
+ * device.  For direct-route populations it spans the first to the last work
+ * item of the population inside the shared persistent launch. */
+int msp_batch_instance_ms(msp_batch *b, double *ms);
+
+/* Number of populations; launches of the last eager forward call. */
+int msp_batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
+
 /* Per-phase GPU timing.  When enabled, the library records a pair of HIP events
  * around each phase it launches on the caller's stream; msp_tree_get_timing
  * waits for them and returns, per phase, the summed milliseconds and the number

@@ -88,10 +88,22 @@ _lib.msp_tree_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.msp_tree_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]
 _lib.msp_phase_name.restype = ctypes.c_char_p
 _lib.msp_phase_name.argtypes = [ctypes.c_int]
+_lib.msp_batch_create.argtypes = [ctypes.POINTER(_vp)]
+_lib.msp_batch_destroy.argtypes = [_vp]
+_lib.msp_batch_destroy.restype = None
+_lib.msp_batch_build.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _vp]
+_lib.msp_batch_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, ctypes.POINTER(FgtParams),
+                                    _vp, _i32, _i32, _vp, _vp, _vp, _vp]
+_lib.msp_batch_forward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _i32, _vp]
+_lib.msp_batch_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _vp]
+_lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
+_lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
 for _f in ("msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
-           "msp_fgt_debug_buffer"):
+           "msp_fgt_debug_buffer", "msp_batch_create", "msp_batch_build", "msp_batch_autotune",
+           "msp_batch_forward", "msp_batch_backward", "msp_batch_instance_ms", "msp_batch_info"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -278,6 +290,125 @@ class Tree:
                                               choice.data_ptr() if nq else None, _stream()),
                "msp_partner_probabilities")
         return probs.view(nq, 8), choice
+
+
+def _host_array(values, ctype, n, name):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(values), dtype={ctypes.c_int64: np.int64, ctypes.c_int32: np.int32,
+                                                        ctypes.c_float: np.float32}[ctype])
+    if a.ndim != 1 or a.size != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Batch:
+    """Independent populations in one batch (msp_batch_*): population k owns the
+    indices offsets[k] .. offsets[k+1]-1 of every per-point tensor."""
+
+    def __init__(self):
+        h = _vp()
+        _check(_lib.msp_batch_create(ctypes.byref(h)), "msp_batch_create")
+        self._h = h
+        self.offsets = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.msp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _set_offsets(self, offsets):
+        import numpy as np
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.offsets = off
+        self.npop = off.size - 1
+        self.n = int(off[-1])
+        return off
+
+    def build(self, x, y, z, offsets, leaf_max=None, max_depth=21):
+        off = self._set_offsets(offsets)
+        ptrs = [_ptr(v, torch.float32, self.n, nm) for v, nm in ((x, "x"), (y, "y"), (z, "z"))]
+        lm = _host_array(leaf_max, ctypes.c_int32, self.npop, "leaf_max") if leaf_max is not None else (None, None)
+        _check(_lib.msp_batch_build(self._h, *ptrs, off.ctypes.data_as(_vp), self.npop, lm[1], max_depth,
+                                    _stream()), "msp_batch_build")
+        return self
+
+    def autotune(self, x, y, z, offsets, w, sigmas, is_target=None, p=8, candidates=(32, 64, 128),
+                 cutoff_sigmas=4.5, exclude_self=False, max_depth=21):
+        """Pick (leaf size, route) per population by timing, and build with them.
+        Returns (leaf sizes, route names)."""
+        import numpy as np
+        off = self._set_offsets(offsets)
+        ptrs = [_ptr(v, torch.float32, self.n, nm) for v, nm in ((x, "x"), (y, "y"), (z, "z"))]
+        pw = _ptr(w, torch.float32, self.n, "w")
+        pt = _ptr(is_target, torch.uint8, self.n, "is_target")
+        sg = _host_array(sigmas, ctypes.c_float, self.npop, "sigmas")
+        cand = _host_array(candidates, ctypes.c_int32, len(candidates), "candidates")
+        scratch = torch.empty(max(self.n, 1), dtype=torch.float32, device=w.device)
+        leaf = np.zeros(self.npop, dtype=np.int32)
+        route = np.zeros(self.npop, dtype=np.int32)
+        prm = _params(1.0, p, -1, "auto", cutoff_sigmas, exclude_self)
+        _check(_lib.msp_batch_autotune(self._h, *ptrs, off.ctypes.data_as(_vp), self.npop, pw, pt, sg[1],
+                                       ctypes.byref(prm), cand[1], len(candidates), max_depth,
+                                       scratch.data_ptr(), leaf.ctypes.data_as(_vp),
+                                       route.ctypes.data_as(_vp), _stream()), "msp_batch_autotune")
+        return leaf, [ROUTE_NAMES[int(r)] for r in route]
+
+    def forward(self, w, sigmas, is_target=None, p=8, route="auto", cutoff_sigmas=4.5, exclude_self=False,
+                out=None, m2l="mfma", use_graph=True):
+        pw = _ptr(w, torch.float32, self.n, "w")
+        pt = _ptr(is_target, torch.uint8, self.n, "is_target")
+        sg = _host_array(sigmas, ctypes.c_float, self.npop, "sigmas")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device=w.device)
+        po = _ptr(out, torch.float32, self.n, "out")
+        prm = _params(1.0, p, -1, route, cutoff_sigmas, exclude_self, m2l)
+        _check(_lib.msp_batch_forward(self._h, pw, pt, sg[1], ctypes.byref(prm), po, 1 if use_graph else 0,
+                                      _stream()), "msp_batch_forward")
+        return out
+
+    def backward(self, w, grad_u, sigmas, is_target=None, p=8, route="auto", cutoff_sigmas=4.5,
+                 exclude_self=False, want=("w", "pos", "sigma"), m2l="mfma"):
+        """Per-population derivatives as Tree.backward; 'sigma' is float64 [npop]."""
+        n = self.n
+        dev = w.device
+        pw = _ptr(w, torch.float32, n, "w")
+        pg = _ptr(grad_u, torch.float32, n, "grad_u")
+        pt = _ptr(is_target, torch.uint8, n, "is_target")
+        sg = _host_array(sigmas, ctypes.c_float, self.npop, "sigmas")
+        gw = torch.empty(n, dtype=torch.float32, device=dev) if "w" in want else None
+        gpos = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)] if "pos" in want else None
+        gs = torch.zeros(max(self.npop, 1), dtype=torch.float64, device=dev) if "sigma" in want else None
+        prm = _params(1.0, p, -1, route, cutoff_sigmas, exclude_self, m2l)
+        ptr = lambda x: x.data_ptr() if (x is not None and x.numel()) else None
+        _check(_lib.msp_batch_backward(self._h, pw, pt, sg[1], ctypes.byref(prm), pg, ptr(gw),
+                                       *(ptr(g) for g in (gpos or (None, None, None))), ptr(gs), _stream()),
+               "msp_batch_backward")
+        out = {}
+        if gw is not None:
+            out["w"] = gw
+        if gpos is not None:
+            out["pos"] = gpos
+        if gs is not None:
+            out["sigma"] = gs[:self.npop]
+        return out
+
+    def instance_ms(self):
+        """Per-population latency (ms) of the last forward, from device timestamps."""
+        import numpy as np
+        ms = np.zeros(max(self.npop, 1), dtype=np.float64)
+        _check(_lib.msp_batch_instance_ms(self._h, ms.ctypes.data_as(_vp)), "msp_batch_instance_ms")
+        return ms[:self.npop]
+
+    def info(self) -> dict:
+        npop, launches = _i32(), _i64()
+        _check(_lib.msp_batch_info(self._h, ctypes.byref(npop), ctypes.byref(launches)), "msp_batch_info")
+        return {"populations": npop.value, "launches_last_eager_forward": launches.value}
 
 
 def build_tree(x, y, z, leaf_max=64, max_depth=21) -> Tree:

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmspfmm.so")
-SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip"]
+SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip", "batch.hip"]
 ARCH = "gfx950"
 
 

@@ -304,6 +304,100 @@ int msp_tree_get_timing(msp_tree *t, double *ms, int64_t *launches, int reset) {
     return MSP_OK;
 }
 
+int msp_batch_create(msp_batch **out) {
+    if (!out) return fail(MSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    MSP_TRY(check_device());
+    msp_batch *b = new (std::nothrow) msp_batch();
+    if (!b) return fail(MSP_ENOSPC, "host allocation failed");
+    (void)hipGetDevice(&b->device);
+    *out = b;
+    return MSP_OK;
+}
+
+void msp_batch_destroy(msp_batch *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    delete b;
+}
+
+static int check_offsets(const int64_t *offsets, int32_t npop) {
+    if (npop < 0) return fail(MSP_EINVAL, "npop = %d < 0", npop);
+    if (!offsets) return fail(MSP_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(MSP_EINVAL, "offsets[0] must be 0");
+    for (int32_t k = 0; k < npop; ++k) {
+        if (offsets[k + 1] < offsets[k]) return fail(MSP_EINVAL, "offsets decrease at %d", k);
+        if (offsets[k + 1] - offsets[k] > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "population %d too large", k);
+    }
+    return MSP_OK;
+}
+
+int msp_batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                    int32_t npop, const int32_t *leaf_max, int32_t max_depth, void *stream) {
+    g_err[0] = 0;
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    MSP_TRY(check_offsets(offsets, npop));
+    if (offsets[npop] > 0 && (!x || !y || !z)) return fail(MSP_EINVAL, "NULL coordinate array");
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    if (leaf_max)
+        for (int32_t k = 0; k < npop; ++k)
+            if (leaf_max[k] < 1) return fail(MSP_EINVAL, "leaf_max[%d] < 1", k);
+    return batch_build(b, x, y, z, offsets, npop, leaf_max, max_depth, (hipStream_t)stream);
+}
+
+int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float *z,
+                       const int64_t *offsets, int32_t npop, const float *w, const uint8_t *is_target,
+                       const float *sigma, const msp_fgt_params *prm, const int32_t *cand, int32_t ncand,
+                       int32_t max_depth, float *scratch_u, int32_t *leaf_out, int32_t *route_out,
+                       void *stream) {
+    g_err[0] = 0;
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    MSP_TRY(check_offsets(offsets, npop));
+    MSP_TRY(check_params(prm));
+    if (offsets[npop] > 0 && (!x || !y || !z || !w || !scratch_u)) return fail(MSP_EINVAL, "NULL array");
+    if (npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
+    if (!cand || ncand < 1) return fail(MSP_EINVAL, "no candidate leaf sizes");
+    for (int32_t c = 0; c < ncand; ++c)
+        if (cand[c] < 1) return fail(MSP_EINVAL, "candidate leaf size %d < 1", cand[c]);
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    return batch_autotune(b, x, y, z, offsets, npop, w, is_target, sigma, prm, cand, ncand, max_depth,
+                          scratch_u, leaf_out, route_out, (hipStream_t)stream);
+}
+
+int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                      const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream) {
+    g_err[0] = 0;
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    MSP_TRY(check_params(prm));
+    if (b->npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
+    if (b->npop > 0 && b->off[b->npop] > 0 && (!w || !u_out)) return fail(MSP_EINVAL, "NULL weight or output array");
+    return batch_forward(b, w, is_target, sigma, prm, u_out, use_graph, (hipStream_t)stream);
+}
+
+int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                       const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                       float *grad_y, float *grad_z, double *grad_sigma, void *stream) {
+    g_err[0] = 0;
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    MSP_TRY(check_params(prm));
+    if (b->npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
+    if (b->npop > 0 && b->off[b->npop] > 0 && (!w || !grad_u)) return fail(MSP_EINVAL, "NULL weight or upstream gradient");
+    const int npos = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);
+    if (npos != 0 && npos != 3) return fail(MSP_EINVAL, "give all three position gradients or none");
+    return batch_backward(b, w, is_target, sigma, prm, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
+                          (hipStream_t)stream);
+}
+
+int msp_batch_instance_ms(msp_batch *b, double *ms) {
+    if (!b || (b->npop > 0 && !ms)) return fail(MSP_EINVAL, "NULL argument");
+    return batch_instance_ms(b, ms);
+}
+
+int msp_batch_info(const msp_batch *b, int32_t *npop, int64_t *launches) {
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    return batch_info(b, npop, launches);
+}
+
 const char *msp_phase_name(int phase) {
     static const char *names[PH_COUNT_] = {"bbox", "morton", "radix_sort", "node_levels", "node_table",
                                            "gather_sorted", "stage", "m2l_operators", "p2m", "m2l_x",

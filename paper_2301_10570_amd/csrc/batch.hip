@@ -1,0 +1,411 @@
+// Many independent populations in one batch.
+//
+// Every population keeps its own octree (built from its slice of the caller's
+// concatenated arrays) and its own sigma.  A forward call evaluates all of them:
+//   - populations on the expansion route run their own short kernel sequence
+//     (translation operators, P2M, three M2L passes, L2P straight into the
+//     output slice), bracketed by two one-thread kernels that record device
+//     timestamps, spread round-robin over eight branch streams that fork from
+//     the caller's stream and join it again;
+//   - all populations on the direct route share ONE persistent P2P launch: a
+//     grid sized to the chip takes work items (population, node) from a global
+//     counter until the queue is empty, so small populations do not each pay
+//     for a launch and the chip stays busy across the uneven sizes.  One staging
+//     launch before it and one scatter launch after it also cover all of them.
+// After a first eager call the sequence is captured into a hipGraph on a
+// private stream and later calls with the same arguments replay the graph on
+// the caller's stream.  The capture holds no memset nodes: the work counter and
+// the timestamps are cleared by a kernel.
+//
+// The autotuner times every population at each candidate leaf size on both
+// routes and keeps the fastest pair.
+#include "internal.hpp"
+#include "p2p_leaf.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+namespace msp {
+namespace {
+
+constexpr int kBlock = 256;
+
+// One direct-route population as the batched kernels read it.
+struct PopDesc {
+    LeafSet ls;            // tree arrays, staged weights (ls.ps.w), flags, output in key order
+    const int32_t *perm;   // key order -> index inside the population
+    int64_t base;          // first index of the population in the caller's arrays
+    int64_t n;
+    int32_t pop;
+};
+
+__device__ inline int find_segment(const int64_t *off, int nseg, int64_t x) {
+    int lo = 0, hi = nseg;   // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_stamp(uint64_t *slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+
+__global__ void k_batch_reset(const PopDesc *desc, int nd, unsigned long long *counter,
+                              unsigned long long *stamps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0ull;
+    if (i < nd) {
+        stamps[2 * desc[i].pop] = ~0ull;
+        stamps[2 * desc[i].pop + 1] = 0ull;
+    }
+}
+
+__global__ void k_batch_stage(const PopDesc *desc, const int64_t *pt_off, int nd, const float *w,
+                              const uint8_t *is_target) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= pt_off[nd]) return;
+    const int d = find_segment(pt_off, nd, g);
+    const PopDesc &D = desc[d];
+    const int64_t i = g - pt_off[d];
+    const int64_t j = D.base + D.perm[i];
+    float4 *ps = const_cast<float4 *>(D.ls.ps);
+    ps[i].w = w[j];
+    const_cast<uint8_t *>(D.ls.tflag)[i] = is_target ? (is_target[j] != 0) : (uint8_t)1;
+}
+
+// Persistent P2P over the nodes of every direct-route population.  Every wave
+// leaves the loop once the counter passes the last item.
+__global__ void __launch_bounds__(64) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
+                                                  unsigned long long *counter,
+                                                  unsigned long long *stamps) {
+    __shared__ P2PShared sh;
+    __shared__ long long s_item;
+    const int64_t total = item_off[nd];
+    // a block can take at most `total` items before the counter passes the end
+    for (int64_t it = 0; it <= total; ++it) {
+        if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int d = find_segment(item_off, nd, item);
+        const PopDesc &D = desc[d];
+        const int64_t v = item - item_off[d];
+        const unsigned long long t0 = wall_clock64();
+        p2p_leaf(D.ls, v, sh);
+        if (threadIdx.x == 0) {
+            atomicMin(&stamps[2 * D.pop], t0);
+            atomicMax(&stamps[2 * D.pop + 1], (unsigned long long)wall_clock64());
+        }
+    }
+}
+
+__global__ void k_batch_scatter(const PopDesc *desc, const int64_t *pt_off, int nd, float *u_out) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= pt_off[nd]) return;
+    const int d = find_segment(pt_off, nd, g);
+    const PopDesc &D = desc[d];
+    const int64_t i = g - pt_off[d];
+    u_out[D.base + D.perm[i]] = D.ls.usort[i];
+}
+
+}  // namespace
+}  // namespace msp
+
+namespace msp {
+
+namespace {
+
+struct PopPlan {
+    msp_fgt_params prm;
+    FgtPlan pl;
+};
+
+int plan_batch(msp_batch *b, const float *sigma, const msp_fgt_params *prm, std::vector<PopPlan> &plans) {
+    plans.resize(b->npop);
+    for (int k = 0; k < b->npop; ++k) {
+        PopPlan &pp = plans[k];
+        pp.prm = *prm;
+        pp.prm.sigma = sigma[k];
+        if (!(sigma[k] > 0.f) || !std::isfinite(sigma[k]))
+            return fail(MSP_EINVAL, "sigma[%d] must be finite and > 0", k);
+        if (prm->route == MSP_ROUTE_AUTO && b->route[k] != MSP_ROUTE_AUTO) pp.prm.route = b->route[k];
+        MSP_TRY(plan_fgt(b->pops[k].get(), &pp.prm, &pp.pl));
+    }
+    return MSP_OK;
+}
+
+// Allocations, interaction lists and the descriptors of the direct-route
+// populations (host synchronisations allowed: never under capture).
+int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, hipStream_t s) {
+    std::vector<PopDesc> d;
+    std::vector<int64_t> poff{0}, ioff{0};
+    for (int k = 0; k < b->npop; ++k) {
+        msp_tree *t = b->pops[k].get();
+        const PopPlan &pp = plans[k];
+        if (pp.pl.route == MSP_ROUTE_FGT || t->n == 0) continue;
+        const int64_t nb = t->n > 0 ? t->n : 1;
+        MSP_TRY(t->tflag.ensure(nb));
+        MSP_TRY(t->usort.ensure(nb * 4));
+        MSP_TRY(direct_route_lists(t, &pp.prm, s));
+        PopDesc q;
+        q.ls = LeafSet{t->n_nodes, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(),
+                       t->nlevel.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                       BoxGeo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side},
+                       t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(),
+                       t->tflag.as<uint8_t>(), (float)(std::sqrt(1.4426950408889634) / (double)pp.prm.sigma),
+                       (pp.prm.flags & MSP_EXCLUDE_SELF) ? 1 : 0, t->usort.as<float>()};
+        q.perm = t->perm.as<int32_t>();
+        q.base = b->off[k];
+        q.n = t->n;
+        q.pop = k;
+        d.push_back(q);
+        poff.push_back(poff.back() + t->n);
+        ioff.push_back(ioff.back() + t->n_nodes);
+    }
+    if (!b->fork) {
+        MSP_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (int r = 0; r < msp_batch::kBranches; ++r) {
+            MSP_HIP(hipStreamCreateWithFlags(&b->side[r], hipStreamNonBlocking));
+            MSP_HIP(hipEventCreateWithFlags(&b->join[r], hipEventDisableTiming));
+        }
+    }
+    b->n_direct = (int32_t)d.size();
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->direct_points = poff.back();
+    b->direct_items = ioff.back();
+    MSP_TRY(b->desc.ensure((d.size() + 1) * sizeof(PopDesc)));
+    MSP_TRY(b->pt_off.ensure(poff.size() * 8));
+    MSP_TRY(b->item_off.ensure(ioff.size() * 8));
+    MSP_TRY(b->counter.ensure(8));
+    MSP_TRY(b->stamps.ensure((size_t)(b->npop > 0 ? b->npop : 1) * 16));
+    MSP_HIP(hipStreamSynchronize(s));
+    if (!d.empty()) MSP_HIP(hipMemcpy(b->desc.p, d.data(), d.size() * sizeof(PopDesc), hipMemcpyHostToDevice));
+    MSP_HIP(hipMemcpy(b->pt_off.p, poff.data(), poff.size() * 8, hipMemcpyHostToDevice));
+    MSP_HIP(hipMemcpy(b->item_off.p, ioff.data(), ioff.size() * 8, hipMemcpyHostToDevice));
+    std::vector<uint64_t> zero((size_t)(b->npop > 0 ? b->npop : 1) * 2, 0);
+    MSP_HIP(hipMemcpy(b->stamps.p, zero.data(), zero.size() * 8, hipMemcpyHostToDevice));
+    return MSP_OK;
+}
+
+// The whole forward as a launch sequence on s (no synchronisation, no allocation
+// once prepare_batch has run for the same plans).
+int enqueue_forward(msp_batch *b, const std::vector<PopPlan> &plans, const float *w,
+                    const uint8_t *is_target, float *u_out, hipStream_t s) {
+    int64_t launches = 0;
+    uint64_t *stamps = b->stamps.as<uint64_t>();
+    // expansion-route populations round-robin on the branch streams, which fork
+    // from s here and join it at the end (also under capture)
+    constexpr int NB = msp_batch::kBranches;
+    MSP_HIP(hipEventRecord(b->fork, s));
+    for (int r = 0; r < NB; ++r) MSP_HIP(hipStreamWaitEvent(b->side[r], b->fork, 0));
+    int next = 0;
+    for (int k = 0; k < b->npop; ++k) {
+        msp_tree *t = b->pops[k].get();
+        const PopPlan &pp = plans[k];
+        if (pp.pl.route != MSP_ROUTE_FGT || t->n == 0) continue;
+        hipStream_t bs = b->side[next];
+        next = (next + 1) % NB;
+        const int64_t o = b->off[k];
+        hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, bs, stamps + 2 * k);
+        MSP_CHECK_LAUNCH();
+        MSP_TRY(fgt_forward_grid(t, pp.pl, &pp.prm, w + o, is_target ? is_target + o : nullptr, u_out + o, bs));
+        hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, bs, stamps + 2 * k + 1);
+        MSP_CHECK_LAUNCH();
+        launches += 8;
+    }
+    const int nd = b->n_direct;
+    if (nd > 0) {
+        const PopDesc *desc = b->desc.as<PopDesc>();
+        auto *counter = b->counter.as<unsigned long long>();
+        auto *st = b->stamps.as<unsigned long long>();
+        hipLaunchKernelGGL(k_batch_reset, dim3(grid_for(nd, 64)), dim3(64), 0, s, desc, nd, counter, st);
+        MSP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_batch_stage, dim3(grid_for(b->direct_points, kBlock)), dim3(kBlock), 0, s, desc,
+                           b->pt_off.as<int64_t>(), nd, w, is_target);
+        MSP_CHECK_LAUNCH();
+        const int64_t waves = (int64_t)b->cus * 16;
+        const int64_t grid = b->direct_items < waves ? b->direct_items : waves;
+        if (grid > 0) {
+            hipLaunchKernelGGL(k_batch_p2p, dim3((unsigned)grid), dim3(64), 0, s, desc,
+                               b->item_off.as<int64_t>(), nd, counter, st);
+            MSP_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(b->direct_points, kBlock)), dim3(kBlock), 0, s, desc,
+                           b->pt_off.as<int64_t>(), nd, u_out);
+        MSP_CHECK_LAUNCH();
+        launches += 4;
+    }
+    for (int r = 0; r < NB; ++r) {
+        MSP_HIP(hipEventRecord(b->join[r], b->side[r]));
+        MSP_HIP(hipStreamWaitEvent(s, b->join[r], 0));
+    }
+    b->launches = launches;
+    return MSP_OK;
+}
+
+void append_bytes(std::vector<unsigned char> &k, const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    k.insert(k.end(), c, c + n);
+}
+
+}  // namespace
+
+int batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                int32_t npop, const int32_t *leaf_max, int32_t max_depth, hipStream_t s) {
+    b->drop_graph();
+    b->pops.clear();
+    b->npop = npop;
+    b->off.assign(offsets, offsets + npop + 1);
+    b->leaf_max.resize(npop);
+    b->route.assign(npop, MSP_ROUTE_AUTO);
+    MSP_HIP(hipGetDevice(&b->device));
+    for (int k = 0; k < npop; ++k) {
+        b->leaf_max[k] = leaf_max ? leaf_max[k] : 64;
+        auto t = std::make_unique<msp_tree>();
+        t->device = b->device;
+        const int64_t o = offsets[k], n = offsets[k + 1] - offsets[k];
+        MSP_TRY(build_tree(t.get(), x + o, y + o, z + o, n, b->leaf_max[k], max_depth, s));
+        b->pops.push_back(std::move(t));
+    }
+    ++b->generation;
+    return MSP_OK;
+}
+
+int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                  const msp_fgt_params *prm, float *u_out, int use_graph, hipStream_t s) {
+    std::vector<PopPlan> plans;
+    MSP_TRY(plan_batch(b, sigma, prm, plans));
+    std::vector<unsigned char> key;
+    append_bytes(key, &b->generation, sizeof(b->generation));
+    append_bytes(key, &w, sizeof(w));
+    append_bytes(key, &is_target, sizeof(is_target));
+    append_bytes(key, &u_out, sizeof(u_out));
+    append_bytes(key, prm, sizeof(*prm));
+    append_bytes(key, sigma, sizeof(float) * b->npop);
+    append_bytes(key, b->route.data(), sizeof(int32_t) * b->route.size());
+    if (use_graph && b->exec && key == b->key) {
+        MSP_HIP(hipGraphLaunch(b->exec, s));
+        return MSP_OK;
+    }
+    b->drop_graph();
+    MSP_TRY(prepare_batch(b, plans, s));
+    MSP_TRY(enqueue_forward(b, plans, w, is_target, u_out, s));
+    if (!use_graph) return MSP_OK;
+    // capture the same sequence for later calls
+    if (!b->cap) MSP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    MSP_HIP(hipStreamSynchronize(s));
+    MSP_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_forward(b, plans, w, is_target, u_out, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != MSP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) return fail(MSP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = g;
+    MSP_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->key = key;
+    return MSP_OK;
+}
+
+int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                   const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                   float *grad_y, float *grad_z, double *grad_sigma, hipStream_t s) {
+    std::vector<PopPlan> plans;
+    MSP_TRY(plan_batch(b, sigma, prm, plans));
+    for (int k = 0; k < b->npop; ++k) {
+        const int64_t o = b->off[k];
+        msp_fgt_params q = plans[k].prm;
+        q.route = plans[k].pl.route;
+        MSP_TRY(fgt_backward(b->pops[k].get(), w + o, is_target ? is_target + o : nullptr, &q, grad_u + o,
+                             grad_w ? grad_w + o : nullptr, grad_x ? grad_x + o : nullptr,
+                             grad_y ? grad_y + o : nullptr, grad_z ? grad_z + o : nullptr,
+                             grad_sigma ? grad_sigma + k : nullptr, s));
+    }
+    return MSP_OK;
+}
+
+int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                   int32_t npop, const float *w, const uint8_t *is_target, const float *sigma,
+                   const msp_fgt_params *prm, const int32_t *cand, int32_t ncand, int32_t max_depth,
+                   float *scratch_u, int32_t *leaf_out, int32_t *route_out, hipStream_t s) {
+    std::vector<int32_t> best_leaf(npop, 64), best_route(npop, MSP_ROUTE_AUTO);
+    hipEvent_t e0, e1;
+    MSP_HIP(hipEventCreate(&e0));
+    MSP_HIP(hipEventCreate(&e1));
+    int rc = MSP_OK;
+    for (int k = 0; k < npop && rc == MSP_OK; ++k) {
+        const int64_t o = offsets[k], n = offsets[k + 1] - offsets[k];
+        double best = 1e300;
+        for (int c = 0; c < ncand && rc == MSP_OK; ++c) {
+            msp_tree t;
+            (void)hipGetDevice(&t.device);
+            rc = build_tree(&t, x + o, y + o, z + o, n, cand[c], max_depth, s);
+            if (rc != MSP_OK) break;
+            for (int r : {MSP_ROUTE_FGT, MSP_ROUTE_DIRECT}) {
+                msp_fgt_params q = *prm;
+                q.sigma = sigma[k];
+                q.route = r;
+                FgtPlan pl;
+                if (plan_fgt(&t, &q, &pl) != MSP_OK) continue;   // grid too large for this route
+                auto run = [&]() -> int {
+                    if (pl.route == MSP_ROUTE_FGT)
+                        return fgt_forward_grid(&t, pl, &q, w + o, is_target ? is_target + o : nullptr,
+                                                scratch_u + o, s);
+                    MSP_TRY(stage_inputs(&t, w + o, is_target ? is_target + o : nullptr, s));
+                    MSP_TRY(direct_route(&t, &q, s));
+                    return scatter_output(&t, scratch_u + o, q.flags, false, s);
+                };
+                rc = run();   // first call: allocations and lists
+                if (rc != MSP_OK) break;
+                (void)hipEventRecord(e0, s);
+                for (int rep = 0; rep < 3 && rc == MSP_OK; ++rep) rc = run();
+                (void)hipEventRecord(e1, s);
+                if (rc != MSP_OK) break;
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    best_leaf[k] = cand[c];
+                    best_route[k] = r;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MSP_OK) return rc;
+    MSP_TRY(batch_build(b, x, y, z, offsets, npop, best_leaf.data(), max_depth, s));
+    b->route = best_route;
+    if (leaf_out) std::memcpy(leaf_out, best_leaf.data(), sizeof(int32_t) * npop);
+    if (route_out) std::memcpy(route_out, best_route.data(), sizeof(int32_t) * npop);
+    return MSP_OK;
+}
+
+int batch_info(const msp_batch *b, int32_t *npop, int64_t *launches) {
+    if (npop) *npop = b->npop;
+    if (launches) *launches = b->launches;
+    return MSP_OK;
+}
+
+int batch_instance_ms(msp_batch *b, double *ms) {
+    std::vector<uint64_t> st((size_t)b->npop * 2, 0);
+    if (b->npop > 0) MSP_HIP(hipMemcpy(st.data(), b->stamps.p, st.size() * 8, hipMemcpyDeviceToHost));
+    int khz = 100000;
+    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device);
+    for (int k = 0; k < b->npop; ++k) {
+        const uint64_t a = st[2 * k], c = st[2 * k + 1];
+        ms[k] = (c > a && a != ~0ull) ? (double)(c - a) / (double)khz : 0.0;
+    }
+    return MSP_OK;
+}
+
+}  // namespace msp

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -134,10 +135,65 @@ struct msp_tree {
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
+};
 
+// A batch of independent populations (batch.hip).
+struct msp_batch {
+    int device = -1;
+    int32_t npop = 0;
+    int64_t generation = 0;
+    std::vector<int64_t> off;
+    std::vector<std::unique_ptr<msp_tree>> pops;
+    std::vector<int32_t> leaf_max, route;
+    // batched direct route
+    msp::DevBuf desc, pt_off, item_off, counter, stamps;
+    int32_t n_direct = 0;
+    int cus = 256;
+    int64_t direct_points = 0, direct_items = 0;
+    // branches for the expansion-route populations (forked from the caller's stream)
+    static constexpr int kBranches = 8;
+    hipStream_t side[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
+    // graph of the last forward signature
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> key;
+    int64_t launches = 0;   // kernel launches issued by the last eager forward
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+    ~msp_batch() {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
+        for (int k = 0; k < kBranches; ++k) {
+            if (side[k]) (void)hipStreamDestroy(side[k]);
+            if (join[k]) (void)hipEventDestroy(join[k]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace msp {
+
+// batch.hip
+int batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                int32_t npop, const int32_t *leaf_max, int32_t max_depth, hipStream_t s);
+int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                  const msp_fgt_params *prm, float *u_out, int use_graph, hipStream_t s);
+int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                   const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                   float *grad_y, float *grad_z, double *grad_sigma, hipStream_t s);
+int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
+                   int32_t npop, const float *w, const uint8_t *is_target, const float *sigma,
+                   const msp_fgt_params *prm, const int32_t *cand, int32_t ncand, int32_t max_depth,
+                   float *scratch_u, int32_t *leaf_out, int32_t *route_out, hipStream_t s);
+int batch_instance_ms(msp_batch *b, double *ms);
+int batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
 
 // tree.hip
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,

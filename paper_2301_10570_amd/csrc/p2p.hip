@@ -10,6 +10,7 @@
 //
 // exp(-d^2/sigma^2) is evaluated as exp2(-(k d)^2) with k^2 = log2(e)/sigma^2.
 #include "internal.hpp"
+#include "p2p_leaf.hpp"
 
 #include <cmath>
 
@@ -18,20 +19,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kStack = 8 * (kDepth + 2);
-
-struct BoxGeo {
-    double lo[3];
-    double side;
-};
-
-__device__ inline void node_box(const BoxGeo &g, int level, int ix, int iy, int iz, float c[3],
-                                float &half) {
-    const double h = g.side / (double)(1ll << level);
-    c[0] = (float)(g.lo[0] + (ix + 0.5) * h);
-    c[1] = (float)(g.lo[1] + (iy + 0.5) * h);
-    c[2] = (float)(g.lo[2] + (iz + 0.5) * h);
-    half = (float)(0.5 * h);
-}
 
 // Count (fill == nullptr) or write the source leaves within reach of each leaf.
 __global__ void k_lists(int64_t n_nodes, const int32_t *nlevel, const int32_t *nix,
@@ -105,9 +92,7 @@ __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
         }
 }
 
-// One wavefront per target leaf.  Lanes are split into G = 64 / tp groups for
-// leaves with tp <= 32 targets; each group takes every G-th source of a staged
-// chunk, and the group partials are added in group order at the end.
+// One wavefront per target leaf (non-leaf nodes return at once).
 __global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfirst,
                                             const int32_t *ncount, const int32_t *nnchild,
                                             const int32_t *nlevel, const int32_t *nix,
@@ -115,69 +100,10 @@ __global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfir
                                             const int64_t *off, const int32_t *lst, const float4 *ps,
                                             const uint8_t *tflag, float k_scale, int exclude_self,
                                             float *usort) {
-    const int64_t v = blockIdx.x;
-    if (v >= n_nodes || nnchild[v] != 0) return;
-    __shared__ float sx[64], sy[64], sz[64], sw[64];
-    __shared__ int32_t sid[64];
-    __shared__ float red[64];
-    const int lane = threadIdx.x;
-    float ct[3], ht;
-    node_box(geo, nlevel[v], nix[v], niy[v], niz[v], ct, ht);
-    const int32_t tf = nfirst[v], tn = ncount[v];
-    const int64_t l0 = off[v], l1 = off[v + 1];
-    for (int t0 = 0; t0 < tn; t0 += 64) {
-        const int nt = tn - t0 < 64 ? tn - t0 : 64;
-        int tp = 1;
-        while (tp < nt) tp <<= 1;
-        const int G = 64 / tp;
-        const int a = lane % tp, grp = lane / tp;
-        const int32_t ti = tf + t0 + (a < nt ? a : 0);
-        const float4 qt = ps[ti];
-        const float tx = (qt.x - ct[0]) * k_scale;
-        const float ty = (qt.y - ct[1]) * k_scale;
-        const float tz = (qt.z - ct[2]) * k_scale;
-        float total = 0.f, comp = 0.f;
-        for (int64_t q = l0; q < l1; ++q) {
-            const int32_t u = lst[q];
-            if (u < 0 || u >= n_nodes) continue;
-            const int32_t sf = nfirst[u], sn = ncount[u];
-            for (int s0 = 0; s0 < sn; s0 += 64) {
-                const int ns = sn - s0 < 64 ? sn - s0 : 64;
-                __syncthreads();
-                if (lane < ns) {
-                    const int32_t j = sf + s0 + lane;
-                    const float4 qs = ps[j];
-                    sx[lane] = (qs.x - ct[0]) * k_scale;
-                    sy[lane] = (qs.y - ct[1]) * k_scale;
-                    sz[lane] = (qs.z - ct[2]) * k_scale;
-                    sw[lane] = qs.w;
-                    sid[lane] = j;
-                }
-                __syncthreads();
-                float part = 0.f;
-                for (int j = grp; j < ns; j += G) {
-                    const float dx = tx - sx[j], dy = ty - sy[j], dz = tz - sz[j];
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    float e = sw[j] * __builtin_amdgcn_exp2f(-d2);
-                    if (exclude_self && sid[j] == ti) e = 0.f;
-                    part += e;
-                }
-                // compensated addition of the chunk partial
-                const float y = part - comp;
-                const float tt = total + y;
-                comp = (tt - total) - y;
-                total = tt;
-            }
-        }
-        __syncthreads();
-        red[lane] = total;
-        __syncthreads();
-        if (grp == 0 && a < nt) {
-            float s = 0.f;
-            for (int q = 0; q < G; ++q) s += red[q * tp + a];
-            usort[ti] = tflag[ti] ? s : 0.f;
-        }
-    }
+    __shared__ P2PShared sh;
+    const LeafSet ls{n_nodes, nfirst, ncount, nnchild, nlevel, nix, niy, niz, geo, off, lst, ps, tflag,
+                     k_scale, exclude_self, usort};
+    p2p_leaf(ls, (int64_t)blockIdx.x, sh);
 }
 
 // All-pairs baseline: one target per thread, 1024 sources per LDS tile.

@@ -1,0 +1,114 @@
+// P2P of one target leaf against its interaction list (Eq. (8)); shared by the
+// single-tree direct route and the batched persistent kernel.
+//
+// One wavefront per target leaf.  Lanes are split into G = 64 / tp groups for
+// leaves with tp <= 32 targets; each group takes every G-th source of a staged
+// chunk, and the group partials are added in group order at the end.  Chunk
+// partials are added with compensation.  exp(-d^2/sigma^2) is evaluated as
+// exp2(-(k d)^2) with k^2 = log2(e)/sigma^2 (k = k_scale).
+#pragma once
+#include "internal.hpp"
+
+namespace msp {
+namespace {
+
+struct BoxGeo {
+    double lo[3];
+    double side;
+};
+
+__device__ inline void node_box(const BoxGeo &g, int level, int ix, int iy, int iz, float c[3],
+                                float &half) {
+    const double h = g.side / (double)(1ll << level);
+    c[0] = (float)(g.lo[0] + (ix + 0.5) * h);
+    c[1] = (float)(g.lo[1] + (iy + 0.5) * h);
+    c[2] = (float)(g.lo[2] + (iz + 0.5) * h);
+    half = (float)(0.5 * h);
+}
+
+// One tree's arrays as the P2P pass reads them.
+struct LeafSet {
+    int64_t n_nodes;
+    const int32_t *nfirst, *ncount, *nnchild, *nlevel, *nix, *niy, *niz;
+    BoxGeo geo;
+    const int64_t *off;
+    const int32_t *lst;
+    const float4 *ps;
+    const uint8_t *tflag;
+    float k_scale;
+    int exclude_self;
+    float *usort;
+};
+
+struct P2PShared {
+    float sx[64], sy[64], sz[64], sw[64];
+    int32_t sid[64];
+    float red[64];
+};
+
+__device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
+    if (v >= L.n_nodes || L.nnchild[v] != 0) return;
+    const int lane = threadIdx.x;
+    float ct[3], ht;
+    node_box(L.geo, L.nlevel[v], L.nix[v], L.niy[v], L.niz[v], ct, ht);
+    const int32_t tf = L.nfirst[v], tn = L.ncount[v];
+    const int64_t l0 = L.off[v];
+    int64_t l1 = L.off[v + 1];
+    if (l1 - l0 > L.n_nodes) l1 = l0 + L.n_nodes;   // a list names each node at most once
+    for (int t0 = 0; t0 < tn; t0 += 64) {
+        const int nt = tn - t0 < 64 ? tn - t0 : 64;
+        int tp = 1;
+        while (tp < nt) tp <<= 1;
+        const int G = 64 / tp;
+        const int a = lane % tp, grp = lane / tp;
+        const int32_t ti = tf + t0 + (a < nt ? a : 0);
+        const float4 qt = L.ps[ti];
+        const float tx = (qt.x - ct[0]) * L.k_scale;
+        const float ty = (qt.y - ct[1]) * L.k_scale;
+        const float tz = (qt.z - ct[2]) * L.k_scale;
+        float total = 0.f, comp = 0.f;
+        for (int64_t q = l0; q < l1; ++q) {
+            const int32_t u = L.lst[q];
+            if (u < 0 || u >= L.n_nodes) continue;
+            const int32_t sf = L.nfirst[u], sn = L.ncount[u];
+            for (int s0 = 0; s0 < sn; s0 += 64) {
+                const int ns = sn - s0 < 64 ? sn - s0 : 64;
+                __syncthreads();
+                if (lane < ns) {
+                    const int32_t j = sf + s0 + lane;
+                    const float4 qs = L.ps[j];
+                    sh.sx[lane] = (qs.x - ct[0]) * L.k_scale;
+                    sh.sy[lane] = (qs.y - ct[1]) * L.k_scale;
+                    sh.sz[lane] = (qs.z - ct[2]) * L.k_scale;
+                    sh.sw[lane] = qs.w;
+                    sh.sid[lane] = j;
+                }
+                __syncthreads();
+                float part = 0.f;
+                for (int j = grp; j < ns; j += G) {
+                    const float dx = tx - sh.sx[j], dy = ty - sh.sy[j], dz = tz - sh.sz[j];
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    float e = sh.sw[j] * __builtin_amdgcn_exp2f(-d2);
+                    if (L.exclude_self && sh.sid[j] == ti) e = 0.f;
+                    part += e;
+                }
+                // compensated addition of the chunk partial
+                const float y = part - comp;
+                const float tt = total + y;
+                comp = (tt - total) - y;
+                total = tt;
+            }
+        }
+        __syncthreads();
+        sh.red[lane] = total;
+        __syncthreads();
+        if (grp == 0 && a < nt) {
+            float s = 0.f;
+            for (int q = 0; q < G; ++q) s += sh.red[q * tp + a];
+            L.usort[ti] = L.tflag[ti] ? s : 0.f;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace msp

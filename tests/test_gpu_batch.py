@@ -1,0 +1,132 @@
+"""Batches of independent populations (config 5 shape, half size): the batched
+forward and backward equal the single-tree calls on every population, agree
+with the FP64 oracle, and replays of the captured graph equal the eager result."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _concat(pops, empty_at=None):
+    import torch
+    xs, ys, zs, ws, ts, offs = [], [], [], [], [], [0]
+    sig = []
+    for k, wl in enumerate(pops):
+        if empty_at is not None and k == empty_at:
+            offs.append(offs[-1])
+            sig.append(100.0)
+        xs.append(wl.x); ys.append(wl.y); zs.append(wl.z); ws.append(wl.w)
+        ts.append((wl.a > 0).astype(np.uint8))
+        offs.append(offs[-1] + wl.n)
+        sig.append(wl.sigma)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.concatenate(a))).cuda()
+    return (T(xs), T(ys), T(zs), T(ws), T(ts), np.array(offs, dtype=np.int64),
+            np.array(sig, dtype=np.float32))
+
+
+def _single(wl, p=8, leaf_max=64, route="auto"):
+    import torch
+    import paper_2301_10570_amd as msp
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tree = msp.build_tree(T(wl.x), T(wl.y), T(wl.z), leaf_max=leaf_max)
+    tgt = T((wl.a > 0).astype(np.uint8))
+    u = tree.forward(T(wl.w), tgt, sigma=float(np.float32(wl.sigma)), p=p, route=route)
+    return tree, u.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pops():
+    return synth.populations(count=20, scale=0.5)
+
+
+def test_batch_forward_equals_single_trees_and_oracle(pops):
+    import paper_2301_10570_amd as msp
+    print("batch forward vs single trees, 20 populations + 1 empty", flush=True)
+    x, y, z, w, tg, off, sig = _concat(pops, empty_at=7)
+    b = msp.Batch().build(x, y, z, off)
+    u = b.forward(w, sig, is_target=tg, use_graph=False).cpu().numpy()
+    routes = []
+    k = 0
+    for i in range(len(off) - 1):
+        lo, hi = off[i], off[i + 1]
+        if hi == lo:
+            continue
+        wl = pops[k]
+        k += 1
+        tree, us = _single(wl)
+        routes.append(tree.plan(float(np.float32(wl.sigma)), p=8)["route"])
+        np.testing.assert_array_equal(u[lo:hi], us)
+        tgt = np.nonzero(wl.a > 0)[0]
+        sel = tgt[synth.sample_indices(tgt.size, 24, seed=900 + i)]
+        ref = oracle.attraction(wl, sel)
+        assert rel_err(u[lo:hi][sel], ref).max() <= TOL
+    print(f"  routes: {routes}")
+    assert "fgt" in routes and "direct" in routes   # both paths of the batch are exercised
+    ms = b.instance_ms()
+    assert ms[7] == 0.0 and (np.delete(ms, 7) > 0).all()
+    b.close()
+
+
+def test_batch_graph_replays_match_eager(pops):
+    import torch
+    import paper_2301_10570_amd as msp
+    print("batch graph replay x3 with eager work between", flush=True)
+    x, y, z, w, tg, off, sig = _concat(pops[:12])
+    b = msp.Batch().build(x, y, z, off)
+    out = torch.empty(x.numel(), dtype=torch.float32, device="cuda")
+    ref = b.forward(w, sig, is_target=tg, out=out).cpu().numpy().copy()   # eager + capture
+    assert b.info()["launches_last_eager_forward"] > 0
+    for rep in range(3):
+        a = torch.randn(512, 512, device="cuda")
+        (a @ a).sum().item()           # unrelated eager work and a synchronisation
+        out.zero_()
+        torch.cuda.synchronize()
+        got = b.forward(w, sig, is_target=tg, out=out).cpu().numpy()   # graph replay
+        np.testing.assert_array_equal(got, ref)
+    b.close()
+
+
+def test_batch_backward_equals_single_trees(pops):
+    import torch
+    import paper_2301_10570_amd as msp
+    print("batch backward vs single trees", flush=True)
+    sub = pops[:6]
+    x, y, z, w, tg, off, sig = _concat(sub)
+    b = msp.Batch().build(x, y, z, off)
+    g = torch.from_numpy(synth.uniforms(x.numel(), 901) + np.float32(0.5)).cuda()
+    got = b.backward(w, g, sig, is_target=tg)
+    for k, wl in enumerate(sub):
+        lo, hi = off[k], off[k + 1]
+        tree, _ = _single(wl)
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        ref = tree.backward(T(wl.w), g[lo:hi].contiguous(), T((wl.a > 0).astype(np.uint8)),
+                            sigma=float(np.float32(wl.sigma)), p=8)
+        np.testing.assert_array_equal(got["w"][lo:hi].cpu().numpy(), ref["w"].cpu().numpy())
+        for a in range(3):
+            np.testing.assert_array_equal(got["pos"][a][lo:hi].cpu().numpy(), ref["pos"][a].cpu().numpy())
+        assert got["sigma"][k].item() == ref["sigma"].item()
+    b.close()
+
+
+def test_batch_autotune(pops):
+    import paper_2301_10570_amd as msp
+    print("batch autotune over leaf sizes 16/32/64 and both routes", flush=True)
+    sub = pops[:8]
+    x, y, z, w, tg, off, sig = _concat(sub)
+    b = msp.Batch()
+    leaf, routes = b.autotune(x, y, z, off, w, sig, is_target=tg, candidates=(16, 32, 64))
+    print(f"  leaf {leaf.tolist()} routes {routes}")
+    assert set(leaf.tolist()) <= {16, 32, 64} and set(routes) <= {"fgt", "direct"}
+    u = b.forward(w, sig, is_target=tg).cpu().numpy()
+    for k, wl in enumerate(sub):
+        lo = off[k]
+        tgt = np.nonzero(wl.a > 0)[0]
+        sel = tgt[synth.sample_indices(tgt.size, 16, seed=950 + k)]
+        assert rel_err(u[lo:lo + wl.n][sel], oracle.attraction(wl, sel)).max() <= TOL
+    b.close()
