@@ -29,10 +29,11 @@ PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12}
 
 
 # phase -> kernel it times (one kernel per launch of the phase)
-KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "p2m": "k_p2m",
+KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "sort_runs": "k_seg_sort",
+                   "p2m": "k_p2m",
                    "l2p": "k_l2p", "m2l_x": "k_m2l_pass_mfma", "m2l_y": "k_m2l_pass_mfma",
                    "m2l_z": "k_m2l_pass_mfma", "morton": "k_morton", "stage": "k_stage",
-                   "partner": "k_partner"}
+                   "partner": "k_partner", "partner_leafy": "k_partner_leafy"}
 
 
 def _algorithmic(phase, ctx):
@@ -53,9 +54,14 @@ def _algorithmic(phase, ctx):
         R = G[0] * G[1] * G[2] * p3 // U
         return "mfma", "TFLOP/s", 2.0 * R * U * U
     if phase == "sort_scatter":
-        # each pass reads and writes every (key, index) pair once; the last of the
-        # 8 passes also gathers the float4 positions into sorted order
-        return "hbm", "GB/s", n * (24.0 + 32.0 / 8)
+        # each pass reads and writes every (key, index) pair once
+        return "hbm", "GB/s", n * 24.0
+    if phase == "sort_runs":
+        # (key, index) read and written once, positions gathered into key order
+        return "hbm", "GB/s", n * (24.0 + 32.0)
+    if phase in ("partner", "partner_leafy"):
+        # per query: target, node and uniform in, 8 probabilities and the choice out
+        return "hbm", "GB/s", ctx["queries"] * (12.0 + 36.0)
     if phase == "sort_hist":
         return "hbm", "GB/s", n * 8.0
     if phase == "morton":
@@ -300,27 +306,33 @@ def main():
     torch.cuda.synchronize()
     ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
 
-    ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"]}
+    ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"],
+           "queries": int(tq.numel())}
     per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                  for k, v in phases.items()}
     # dominant kernel: the single-kernel phase with the most time per step
-    cands = [k for k in KERNEL_OF_PHASE if k in phases and phases[k][1] > 0]
-    dom = max(cands, key=lambda k: phases[k][0]) if cands else None
-    roof = None
-    info = _algorithmic(dom, ctx) if dom else None
-    if info is not None:
+    def _roof(ph):
+        info = _algorithmic(ph, ctx)
+        if info is None:
+            return None
         bound, unit, amount = info
-        avg_s = phases[dom][0] / phases[dom][1] / 1000.0
+        avg_s = phases[ph][0] / phases[ph][1] / 1000.0
         if unit == "GB/s":
             achieved, peak = amount / avg_s / 1e9, PEAK["hbm"] / 1e9
         else:
             achieved = amount / avg_s / 1e12
             peak = (PEAK["fp32_mfma"] if bound == "mfma" else PEAK["fp32_vector"]) / 1e12
-        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": _traffic(KERNEL_OF_PHASE[dom]),
-                "kernel": KERNEL_OF_PHASE[dom], "phase": dom,
-                "algorithmic_per_launch": amount,
-                "avg_launch_ms": phases[dom][0] / phases[dom][1]}
+        return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": _traffic(KERNEL_OF_PHASE[ph]),
+                "kernel": KERNEL_OF_PHASE[ph], "phase": ph, "algorithmic_per_launch": amount,
+                "avg_launch_ms": phases[ph][0] / phases[ph][1],
+                "ms_per_step": phases[ph][0] / args.steps}
+
+    # dominant kernel: the single-kernel phase with the most time per step
+    cands = [k for k in KERNEL_OF_PHASE if k in phases and phases[k][1] > 0]
+    dom = max(cands, key=lambda k: phases[k][0]) if cands else None
+    roof = _roof(dom) if dom else None
+    kernels = {k: _roof(k) for k in sorted(cands, key=lambda k: -phases[k][0])}
     if args.copy_calibration:
         # a plain device copy of known size, for scaling the HBM counters
         a = torch.empty(256 << 20, dtype=torch.float32, device=dev)
@@ -340,6 +352,7 @@ def main():
                    "route": plan["route"], "level": plan["level"], "grid": plan["grid"],
                    "rho": plan["rho"]},
         "roofline": roof,
+        "kernel_rooflines": kernels,
         "phases": per_phase,
         "ms_per_step_with_events": ms_events,
         "forward_only_ms": ms_fwd,

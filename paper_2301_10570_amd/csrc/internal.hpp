@@ -63,7 +63,7 @@ enum Phase {
     PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
     PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
     PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_SORT_HIST, PH_SORT_SCAN, PH_SORT_SCATTER,
-    PH_NODE_COUNTS, PH_PARTNER_LEAFY, PH_COUNT_
+    PH_NODE_COUNTS, PH_PARTNER_LEAFY, PH_SORT_RUNS, PH_COUNT_
 };
 static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 

@@ -525,6 +525,46 @@ __global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *lev
     }
 }
 
+// Final ordering inside runs of equal 24-bit key prefix (level-8 cells).  The
+// input is stably sorted by the prefix, so within a run the points are in index
+// order; each point's place in the run is the number of run members with a
+// smaller (key, index), which reproduces the stable sort by the full key.  Runs
+// longer than kSegMax raise *overflow (the caller then sorts all 63 bits).
+constexpr int kSegShift = 39;
+constexpr int kSegMax = 256;
+__global__ void k_seg_sort(const uint64_t *kin, const int32_t *vin, int64_t n, uint64_t *kout,
+                           int32_t *vout, const float4 *pin, float4 *ps, int *overflow) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = kin[i];
+    const int32_t val = vin[i];
+    const uint64_t pre = key >> kSegShift;
+    int64_t st = i, en = i + 1;
+    int steps = 0;
+    while (st > 0 && (kin[st - 1] >> kSegShift) == pre) {
+        --st;
+        if (++steps > kSegMax) {
+            atomicOr(overflow, 1);
+            return;
+        }
+    }
+    while (en < n && (kin[en] >> kSegShift) == pre) {
+        ++en;
+        if (++steps > kSegMax) {
+            atomicOr(overflow, 1);
+            return;
+        }
+    }
+    int64_t o = st;
+    for (int64_t j = st; j < en; ++j) {
+        const uint64_t kj = kin[j];
+        o += (kj < key) || (kj == key && vin[j] < val);
+    }
+    kout[o] = key;
+    vout[o] = val;
+    ps[o] = pin[val];
+}
+
 __global__ void k_inverse_perm(const int32_t *perm, int64_t n, int32_t *iperm) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -545,6 +585,60 @@ int ensure_iperm(msp_tree *t, hipStream_t s) {
     return MSP_OK;
 }
 
+namespace {
+
+// bbox scratch: per-part minima/maxima (kBboxParts x 6 floats), the reduced 8
+// floats, then two flags: non-finite input, and a sort run too long for k_seg_sort
+constexpr int kBboxParts = 512;
+inline int *bbox_flags(msp_tree *t) {
+    return reinterpret_cast<int *>(t->bbox.as<float>() + kBboxParts * 6 + 8);
+}
+
+// Stable sort of (key, index), and the positions gathered into key order.
+// fast: three 8-bit LSD passes over the top 24 key bits (the level-8 cell), then
+// k_seg_sort inside the runs of equal prefix; it leaves a flag in the bbox
+// scratch when a run is too long.  Otherwise: eight LSD passes over all bits.
+int sort_keys(msp_tree *t, int64_t n, int nblk, bool full, hipStream_t s) {
+    PhaseScope ps(&t->timing, PH_SORT, s);
+    uint64_t *ka = t->keys.as<uint64_t>(), *kb = t->keys2.as<uint64_t>();
+    int32_t *va = t->perm.as<int32_t>(), *vb = t->perm2.as<int32_t>();
+    uint32_t *hist = t->hist.as<uint32_t>();
+    uint32_t *total = hist + (size_t)256 * nblk;
+    const int first = full ? 0 : kSegShift, npass = full ? 8 : 3;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int shift = first + pass * 8;
+        {
+            PhaseScope k1(&t->timing, PH_SORT_HIST, s);
+            hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
+            MSP_CHECK_LAUNCH();
+        }
+        {
+            PhaseScope k2(&t->timing, PH_SORT_SCAN, s);
+            hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
+            MSP_CHECK_LAUNCH();
+        }
+        const bool gather = full && pass == npass - 1;
+        PhaseScope k3(&t->timing, PH_SORT_SCATTER, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift, hist,
+                           total, nblk, t->pin.as<float4>(), gather ? t->ps.as<float4>() : nullptr);
+        MSP_CHECK_LAUNCH();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (!full) {
+        // three passes leave the data in keys2/perm2; the run sort writes keys/perm
+        PhaseScope k4(&t->timing, PH_SORT_RUNS, s);
+        int *overflow = bbox_flags(t) + 1;
+        hipLaunchKernelGGL(k_seg_sort, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, ka, va, n,
+                           t->keys.as<uint64_t>(), t->perm.as<int32_t>(), t->pin.as<float4>(),
+                           t->ps.as<float4>(), overflow);
+        MSP_CHECK_LAUNCH();
+    }
+    return MSP_OK;
+}
+
+}  // namespace
+
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
                int max_depth, hipStream_t s) {
     t->built = false;
@@ -559,12 +653,12 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     // root cube
     float box[6] = {0, 0, 0, 0, 0, 0};
     if (n > 0) {
-        const int parts = 512;
-        MSP_TRY(t->bbox.ensure(parts * 6 * sizeof(float) + 8 * sizeof(float) + sizeof(int)));
+        const int parts = kBboxParts;
+        MSP_TRY(t->bbox.ensure(parts * 6 * sizeof(float) + 8 * sizeof(float) + 2 * sizeof(int)));
         float *part = t->bbox.as<float>();
         float *out = part + parts * 6;
-        int *bad = reinterpret_cast<int *>(out + 8);
-        MSP_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+        int *bad = bbox_flags(t);
+        MSP_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));   // non-finite flag, sort-run overflow
         {
             PhaseScope ps(&t->timing, PH_BBOX, s);
             hipLaunchKernelGGL(k_bbox_partial, dim3(parts), dim3(kBlock), 0, s, x, y, z, n, part, bad);
@@ -604,43 +698,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     MSP_TRY(t->perm2.ensure(nb * 4));
     const int nblk = (int)((n + kTile - 1) / kTile) > 0 ? (int)((n + kTile - 1) / kTile) : 1;
     MSP_TRY(t->hist.ensure((size_t)256 * nblk * 4 + 256 * 4));
-    if (n > 0) {
-        {
-        PhaseScope ps(&t->timing, PH_KEYS, s);
-        hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
-                           g.lo[0], g.lo[1], g.lo[2], g.scale, t->keys.as<uint64_t>(),
-                           t->perm.as<int32_t>(), t->pin.as<float4>());
-        MSP_CHECK_LAUNCH();
-        }
-        PhaseScope ps(&t->timing, PH_SORT, s);
-        uint64_t *ka = t->keys.as<uint64_t>(), *kb = t->keys2.as<uint64_t>();
-        int32_t *va = t->perm.as<int32_t>(), *vb = t->perm2.as<int32_t>();
-        uint32_t *hist = t->hist.as<uint32_t>();
-        uint32_t *total = hist + (size_t)256 * nblk;
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = pass * 8;
-            {
-                PhaseScope k1(&t->timing, PH_SORT_HIST, s);
-                hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
-                MSP_CHECK_LAUNCH();
-            }
-            {
-                PhaseScope k2(&t->timing, PH_SORT_SCAN, s);
-                hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, nblk, total);
-                MSP_CHECK_LAUNCH();
-            }
-            const bool last = pass == 7;
-            PhaseScope k3(&t->timing, PH_SORT_SCATTER, s);
-            hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift,
-                               hist, total, nblk, t->pin.as<float4>(), last ? t->ps.as<float4>() : nullptr);
-            MSP_CHECK_LAUNCH();
-            std::swap(ka, kb);
-            std::swap(va, vb);
-        }
-        // after an even number of passes the result is back in keys/perm
-    }
-
-    // per-point levels and node counts per level
+    // per-point levels and node counts per level (scratch)
     MSP_TRY(t->dlev.ensure(nb));
     MSP_TRY(t->llev.ensure(nb));
     MSP_TRY(t->blkcnt.ensure((size_t)kMaxLevels * nblk * 4 + kMaxLevels * 4));
@@ -653,7 +711,17 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     int8_t *L = t->tmp_a.as<int8_t>(), *pre = t->tmp_b.as<int8_t>(), *suf = t->tmp_c.as<int8_t>();
     uint32_t *blkcnt = t->blkcnt.as<uint32_t>();
     uint32_t *ltot = blkcnt + (size_t)kMaxLevels * nblk;
-    if (n > 0) {
+    auto keys_and_sort = [&](bool full) -> int {
+        {
+            PhaseScope ps(&t->timing, PH_KEYS, s);
+            hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
+                               g.lo[0], g.lo[1], g.lo[2], g.scale, t->keys.as<uint64_t>(),
+                               t->perm.as<int32_t>(), t->pin.as<float4>());
+            MSP_CHECK_LAUNCH();
+        }
+        return sort_keys(t, n, nblk, full, s);
+    };
+    auto levels = [&]() -> int {
         PhaseScope ps(&t->timing, PH_LEVELS, s);
         if (leaf_max <= kWinMax) {
             hipLaunchKernelGGL(k_levels_tile, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
@@ -661,27 +729,40 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
                                blkcnt, nblk);
             MSP_CHECK_LAUNCH();
         } else {
-        if (m > 0) {
-            hipLaunchKernelGGL(k_window_L, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s,
-                               t->keys.as<uint64_t>(), m, leaf_max, L);
+            if (m > 0) {
+                hipLaunchKernelGGL(k_window_L, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s,
+                                   t->keys.as<uint64_t>(), m, leaf_max, L);
+                MSP_CHECK_LAUNCH();
+                const int64_t nwb = (m + W - 1) / W;
+                hipLaunchKernelGGL(k_window_presuf, dim3(grid_for(nwb, kBlock)), dim3(kBlock), 0, s, L,
+                                   m, W, pre, suf);
+                MSP_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_levels, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
+                               leaf_max, max_depth, pre, suf, m, W, t->dlev.as<uint8_t>(),
+                               t->llev.as<uint8_t>(), blkcnt, nblk);
             MSP_CHECK_LAUNCH();
-            const int64_t nwb = (m + W - 1) / W;
-            hipLaunchKernelGGL(k_window_presuf, dim3(grid_for(nwb, kBlock)), dim3(kBlock), 0, s, L, m,
-                               W, pre, suf);
-            MSP_CHECK_LAUNCH();
-        }
-        hipLaunchKernelGGL(k_levels, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
-                           leaf_max, max_depth, pre, suf, m, W, t->dlev.as<uint8_t>(),
-                           t->llev.as<uint8_t>(), blkcnt, nblk);
-        MSP_CHECK_LAUNCH();
         }
         hipLaunchKernelGGL(k_level_scan, dim3(kDepth + 1), dim3(kBlock), 0, s, blkcnt, nblk, ltot);
         MSP_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, ltot,
-                           t->d_level_off.as<int64_t>());
+        hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, ltot, t->d_level_off.as<int64_t>());
         MSP_CHECK_LAUNCH();
         MSP_HIP(hipMemcpyAsync(t->level_off, t->d_level_off.p, kMaxLevels * 8, hipMemcpyDeviceToHost, s));
+        return MSP_OK;
+    };
+    if (n > 0) {
+        MSP_TRY(keys_and_sort(false));
+        MSP_TRY(levels());
+        int over = 0;
+        const int *overflow = bbox_flags(t) + 1;
+        MSP_HIP(hipMemcpyAsync(&over, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
         MSP_HIP(hipStreamSynchronize(s));
+        if (over) {
+            // a run of equal 24-bit prefix was too long for the run sort: sort all bits
+            MSP_TRY(keys_and_sort(true));
+            MSP_TRY(levels());
+            MSP_HIP(hipStreamSynchronize(s));
+        }
     } else {
         // empty input: a single empty root leaf
         t->level_off[0] = 0;
