@@ -119,28 +119,45 @@ __global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n,
     for (int a = 0; a < P; ++a)
 #pragma unroll
         for (int b = 0; b < P; ++b) acc[a][b] = 0.f;
-    if (active) {
-        for (int64_t j = start + wid * PL + pl; j < end; j += NW * PL) {
+    // the cell's points pass through LDS in chunks of kBlock, one point per thread:
+    // while a chunk is being accumulated, the threads already hold the next one
+    // (position and the weight gathered through the permutation) in registers
+    __shared__ float4 chunk[kBlock];
+    float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto fetch = [&](int64_t c0) {
+        const int64_t j = c0 + tid;
+        if (j < end) {
             const float4 q = ps[j];
-            const float X = (float)(((double)q.x - cx) * inv_sigma);
-            const float Y = (float)(((double)q.y - cy) * inv_sigma);
-            const float Z = (float)(((double)q.z - cz) * inv_sigma);
-            float zw = w[perm[j]];
-#pragma unroll
-            for (int k = 1; k < P; ++k) zw = k <= az ? zw * Z : zw;
-            float px[P], yz[P];
-            px[0] = 1.f;
-            yz[0] = zw;
-#pragma unroll
-            for (int k = 1; k < P; ++k) {
-                px[k] = px[k - 1] * X;
-                yz[k] = yz[k - 1] * Y;
-            }
-#pragma unroll
-            for (int a = 0; a < P; ++a)
-#pragma unroll
-                for (int b = 0; b < P; ++b) acc[a][b] = fmaf(px[a], yz[b], acc[a][b]);
+            nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
+                              (float)(((double)q.z - cz) * inv_sigma), w[perm[j]]);
         }
+    };
+    fetch(start);
+    for (int64_t c0 = start; c0 < end; c0 += kBlock) {
+        __syncthreads();
+        chunk[tid] = nxt;
+        __syncthreads();
+        if (c0 + kBlock < end) fetch(c0 + kBlock);
+        const int m = end - c0 < kBlock ? (int)(end - c0) : kBlock;
+        if (active)
+            for (int jj = wid * PL + pl; jj < m; jj += NW * PL) {
+                const float4 q = chunk[jj];
+                float zw = q.w;
+#pragma unroll
+                for (int k = 1; k < P; ++k) zw = k <= az ? zw * q.z : zw;
+                float px[P], yz[P];
+                px[0] = 1.f;
+                yz[0] = zw;
+#pragma unroll
+                for (int k = 1; k < P; ++k) {
+                    px[k] = px[k - 1] * q.x;
+                    yz[k] = yz[k - 1] * q.y;
+                }
+#pragma unroll
+                for (int a = 0; a < P; ++a)
+#pragma unroll
+                    for (int b = 0; b < P; ++b) acc[a][b] = fmaf(px[a], yz[b], acc[a][b]);
+            }
     }
     // lanes with the same az in point-lane order (per wave, or waves in turn)
     for (int e = tid; e < NB * P3; e += kBlock) (&red[0][0])[e] = 0.f;
@@ -406,6 +423,12 @@ __global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n,
         const float X0 = (float)(((double)q0.x - cx) * inv_sigma), X1 = (float)(((double)q1.x - cx) * inv_sigma);
         const float Y0 = (float)(((double)q0.y - cy) * inv_sigma), Y1 = (float)(((double)q1.y - cy) * inv_sigma);
         const float Z0 = (float)(((double)q0.z - cz) * inv_sigma), Z1 = (float)(((double)q1.z - cz) * inv_sigma);
+        // the scattered reads of the output step are issued before the evaluation
+        const int32_t j0 = perm[i0];
+        const int32_t j1 = has1 ? perm[i1] : j0;
+        const bool t0 = !is_target || is_target[j0];
+        const bool t1 = !is_target || is_target[j1];
+        const float w0 = subtract_self ? w[j0] : 0.f, w1 = subtract_self ? w[j1] : 0.f;
         float uz0 = 0.f, uz1 = 0.f;
         for (int az = P - 1; az >= 0; --az) {
             float uy0 = 0.f, uy1 = 0.f;
@@ -426,14 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n,
             uz1 = fmaf(uz1, Z1, uy1);
         }
         // back to input order; non-targets get 0
-        const int32_t j0 = perm[i0];
-        const bool t0 = !is_target || is_target[j0];
-        u_out[j0] = t0 ? (subtract_self ? uz0 - w[j0] : uz0) : 0.f;
-        if (has1) {
-            const int32_t j1 = perm[i1];
-            const bool t1 = !is_target || is_target[j1];
-            u_out[j1] = t1 ? (subtract_self ? uz1 - w[j1] : uz1) : 0.f;
-        }
+        u_out[j0] = t0 ? uz0 - w0 : 0.f;
+        if (has1) u_out[j1] = t1 ? uz1 - w1 : 0.f;
     }
 }
 

@@ -187,7 +187,7 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
     constexpr int PR = P + 1;                           // padded row of a child block
     constexpr int G0 = 10240 / (P2 * PR * 4);
     constexpr int G = G0 < 1 ? 1 : (G0 > 8 ? 8 : G0);   // child blocks shifted together
-    __shared__ float pts[64 * STR];
+    __shared__ __align__(16) float pts[64 * STR];
     __shared__ float tot[P3];
     __shared__ float cbuf[G * P2 * PR];
     __shared__ float shift[2][P];                       // d^k / k! for the two child offsets
@@ -236,55 +236,120 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
             for (int k = 0; k < P; ++k) acc[rr][k] = 0.f;
 
         // P2M (Eq. (7)) over the flattened points
-        int owner = 0;
-        for (int32_t c0 = 0; c0 < total; c0 += 64) {
-            __syncthreads();
-            const int32_t j = c0 + lane;
-            if (j < total) {
-                while (part_end[owner] <= j) ++owner;
-                const float4 qp = ps[part_first[owner] + j];
-                const float X = (float)(((double)qp.x - cx) * inv_sigma);
-                const float Y = (float)(((double)qp.y - cy) * inv_sigma);
-                const float Z = (float)(((double)qp.z - cz) * inv_sigma);
-                float *r = pts + lane * STR;
-                float px = qp.w, py = 1.f, pz = 1.f;
+        if constexpr (P == 1 || P == 2 || P == 4 || P == 8) {
+            // lane = (point group, az): each lane accumulates the (ay, ax) block of its
+            // az over every NG-th staged point; the groups are added by butterfly shuffles
+            constexpr int NG = 64 / P;
+            const int az = lane % P, grp = lane / P;
+            float a2[P][P];
 #pragma unroll
+            for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+                for (int ax = 0; ax < P; ++ax) a2[ay][ax] = 0.f;
+            float4 *pt4 = reinterpret_cast<float4 *>(pts);
+            int owner = 0;
+            for (int32_t c0 = 0; c0 < total; c0 += 64) {
+                __syncthreads();
+                const int32_t j = c0 + lane;
+                if (j < total) {
+                    while (part_end[owner] <= j) ++owner;
+                    const float4 qp = ps[part_first[owner] + j];
+                    pt4[lane] = make_float4((float)(((double)qp.x - cx) * inv_sigma),
+                                            (float)(((double)qp.y - cy) * inv_sigma),
+                                            (float)(((double)qp.z - cz) * inv_sigma), qp.w);
+                }
+                __syncthreads();
+                const int m = total - c0 < 64 ? total - c0 : 64;
+                for (int jj = grp; jj < m; jj += NG) {
+                    const float4 q = pt4[jj];
+                    float wz = q.w;
+                    for (int k = 0; k < az; ++k) wz *= q.z;
+                    float yp[P], xp[P];
+                    yp[0] = wz;
+                    xp[0] = 1.f;
+#pragma unroll
+                    for (int k = 1; k < P; ++k) {
+                        yp[k] = yp[k - 1] * q.y;
+                        xp[k] = xp[k - 1] * q.x;
+                    }
+#pragma unroll
+                    for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+                        for (int ax = 0; ax < P; ++ax) a2[ay][ax] = fmaf(yp[ay], xp[ax], a2[ay][ax]);
+                }
+            }
+#pragma unroll
+            for (int o = P; o < 64; o <<= 1)
+#pragma unroll
+                for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) a2[ay][ax] += __shfl_xor(a2[ay][ax], o, 64);
+            if (grp == 0) {
+                float fz = 1.f;
+                for (int k = 2; k <= az; ++k) fz *= (float)k;
+                float fy = 1.f;
+#pragma unroll
+                for (int ay = 0; ay < P; ++ay) {
+                    if (ay > 1) fy *= (float)ay;
+                    float fx = 1.f;
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) {
+                        if (ax > 1) fx *= (float)ax;
+                        tot[(az * P + ay) * P + ax] = a2[ay][ax] / (fx * fy * fz);
+                    }
+                }
+            }
+        } else {
+            int owner = 0;
+            for (int32_t c0 = 0; c0 < total; c0 += 64) {
+                __syncthreads();
+                const int32_t j = c0 + lane;
+                if (j < total) {
+                    while (part_end[owner] <= j) ++owner;
+                    const float4 qp = ps[part_first[owner] + j];
+                    const float X = (float)(((double)qp.x - cx) * inv_sigma);
+                    const float Y = (float)(((double)qp.y - cy) * inv_sigma);
+                    const float Z = (float)(((double)qp.z - cz) * inv_sigma);
+                    float *r = pts + lane * STR;
+                    float px = qp.w, py = 1.f, pz = 1.f;
+    #pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        r[k] = px;
+                        r[P + k] = py;
+                        r[2 * P + k] = pz;
+                        px *= X;
+                        py *= Y;
+                        pz *= Z;
+                    }
+                }
+                __syncthreads();
+                const int m = total - c0 < 64 ? total - c0 : 64;
+                for (int jj = 0; jj < m; ++jj) {
+                    const float *r = pts + jj * STR;
+    #pragma unroll
+                    for (int rr = 0; rr < RP; ++rr) {
+                        const int row = lane + 64 * rr;
+                        if (row >= P2) continue;
+                        const float fyz = r[P + row % P] * r[2 * P + row / P];
+    #pragma unroll
+                        for (int k = 0; k < P; ++k) acc[rr][k] = fmaf(fyz, r[k], acc[rr][k]);
+                    }
+                }
+            }
+    #pragma unroll
+            for (int rr = 0; rr < RP; ++rr) {
+                const int row = lane + 64 * rr;
+                if (row >= P2) continue;
+                const int ay = row % P, az = row / P;
+                float fyz = 1.f;
+                for (int k = 2; k <= ay; ++k) fyz *= (float)k;
+                for (int k = 2; k <= az; ++k) fyz *= (float)k;
+                float fx = 1.f;
+    #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    r[k] = px;
-                    r[P + k] = py;
-                    r[2 * P + k] = pz;
-                    px *= X;
-                    py *= Y;
-                    pz *= Z;
+                    if (k > 1) fx *= (float)k;
+                    tot[row * P + k] = acc[rr][k] / (fx * fyz);
                 }
-            }
-            __syncthreads();
-            const int m = total - c0 < 64 ? total - c0 : 64;
-            for (int jj = 0; jj < m; ++jj) {
-                const float *r = pts + jj * STR;
-#pragma unroll
-                for (int rr = 0; rr < RP; ++rr) {
-                    const int row = lane + 64 * rr;
-                    if (row >= P2) continue;
-                    const float fyz = r[P + row % P] * r[2 * P + row / P];
-#pragma unroll
-                    for (int k = 0; k < P; ++k) acc[rr][k] = fmaf(fyz, r[k], acc[rr][k]);
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RP; ++rr) {
-            const int row = lane + 64 * rr;
-            if (row >= P2) continue;
-            const int ay = row % P, az = row / P;
-            float fyz = 1.f;
-            for (int k = 2; k <= ay; ++k) fyz *= (float)k;
-            for (int k = 2; k <= az; ++k) fyz *= (float)k;
-            float fx = 1.f;
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                if (k > 1) fx *= (float)k;
-                tot[row * P + k] = acc[rr][k] / (fx * fyz);
             }
         }
 

@@ -45,11 +45,13 @@ def stats(path: str, command: str) -> str:
 
 
 def _counter(path: str, counter: str):
+    """Counter values per kernel, keyed by the short name without template arguments."""
     per = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        per.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        name = re.sub(r"<.*>$", "", short_name(r["Kernel_Name"]))
+        per.setdefault(name, []).append(float(r["Counter_Value"]))
     return per
 
 
