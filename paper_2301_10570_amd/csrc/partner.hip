@@ -174,8 +174,10 @@ __device__ inline int wave_incl_scan(int v, int lane) {
 // read once, one lane per child; the points of the children that carry no
 // moments (of the node itself for a leaf) are flattened into one list staged 64
 // at a time; the moment blocks of the others are shifted (M2M) G at a time in LDS.
-template <int P>
-__global__ void __launch_bounds__(64)
+// M2M = false: no child of the level can carry moments (the children are leaves
+// of at most leaf_max <= 70 points), so no shift buffers are needed.
+template <int P, bool M2M>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const int32_t *ncount,
                const int32_t *nfchild, const int32_t *nnchild, const int32_t *nix,
                const int32_t *niy, const int32_t *niz, const int32_t *ndigit, double lox,
@@ -183,13 +185,14 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
                const int32_t *nsrc, uint8_t *hasA, float *nodeA, int64_t slot0) {
     constexpr int P2 = P * P, P3 = P2 * P;
     constexpr int RP = (P2 + 63) / 64;                  // (ay, az) rows per lane
-    constexpr int STR = 3 * P + 1;
+    constexpr bool ILP = P == 1 || P == 2 || P == 4 || P == 8;
+    constexpr int STR = ILP ? 4 : 3 * P + 1;            // staged floats per point
     constexpr int PR = P + 1;                           // padded row of a child block
     constexpr int G0 = 10240 / (P2 * PR * 4);
-    constexpr int G = G0 < 1 ? 1 : (G0 > 8 ? 8 : G0);   // child blocks shifted together
+    constexpr int G = !M2M ? 1 : (G0 < 1 ? 1 : (G0 > 8 ? 8 : G0));   // child blocks shifted together
     __shared__ __align__(16) float pts[64 * STR];
     __shared__ float tot[P3];
-    __shared__ float cbuf[G * P2 * PR];
+    __shared__ float cbuf[M2M ? G * P2 * PR : 1];
     __shared__ float shift[2][P];                       // d^k / k! for the two child offsets
     __shared__ int32_t part_first[64], part_end[64];
     const int lane = threadIdx.x;
@@ -236,66 +239,79 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
             for (int k = 0; k < P; ++k) acc[rr][k] = 0.f;
 
         // P2M (Eq. (7)) over the flattened points
-        if constexpr (P == 1 || P == 2 || P == 4 || P == 8) {
-            // lane = (point group, az): each lane accumulates the (ay, ax) block of its
-            // az over every NG-th staged point; the groups are added by butterfly shuffles
-            constexpr int NG = 64 / P;
-            const int az = lane % P, grp = lane / P;
-            float a2[P][P];
+        if constexpr (ILP) {
+            // lane = (point group, ay half, az): each lane accumulates the (ay, ax) block
+            // of its az and half of the ay range over every NG-th staged point; the
+            // groups are added by butterfly shuffles
+            constexpr int H = P == 8 ? 2 : 1;     // ay halves (keeps 32 accumulators at P = 8)
+            constexpr int AY = P / H;
+            constexpr int NG = 64 / (P * H);
+            const int az = lane % P, ah = (lane / P) % H, grp = lane / (P * H);
+            float a2[AY][P];
 #pragma unroll
-            for (int ay = 0; ay < P; ++ay)
+            for (int ay = 0; ay < AY; ++ay)
 #pragma unroll
                 for (int ax = 0; ax < P; ++ax) a2[ay][ax] = 0.f;
             float4 *pt4 = reinterpret_cast<float4 *>(pts);
             int owner = 0;
-            for (int32_t c0 = 0; c0 < total; c0 += 64) {
-                __syncthreads();
+            // each lane holds the point of the next chunk while the current one is used
+            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            auto fetch = [&](int32_t c0) {
                 const int32_t j = c0 + lane;
                 if (j < total) {
                     while (part_end[owner] <= j) ++owner;
-                    const float4 qp = ps[part_first[owner] + j];
-                    pt4[lane] = make_float4((float)(((double)qp.x - cx) * inv_sigma),
-                                            (float)(((double)qp.y - cy) * inv_sigma),
-                                            (float)(((double)qp.z - cz) * inv_sigma), qp.w);
+                    nxt = ps[part_first[owner] + j];
                 }
+            };
+            __syncthreads();   // part_first / part_end written above
+            fetch(0);
+            for (int32_t c0 = 0; c0 < total; c0 += 64) {
                 __syncthreads();
+                if (c0 + lane < total)
+                    pt4[lane] = make_float4((float)(((double)nxt.x - cx) * inv_sigma),
+                                            (float)(((double)nxt.y - cy) * inv_sigma),
+                                            (float)(((double)nxt.z - cz) * inv_sigma), nxt.w);
+                __syncthreads();
+                if (c0 + 64 < total) fetch(c0 + 64);
                 const int m = total - c0 < 64 ? total - c0 : 64;
                 for (int jj = grp; jj < m; jj += NG) {
                     const float4 q = pt4[jj];
                     float wz = q.w;
                     for (int k = 0; k < az; ++k) wz *= q.z;
-                    float yp[P], xp[P];
+                    for (int k = 0; k < ah * AY; ++k) wz *= q.y;   // y^(first ay of the half)
+                    float yp[AY], xp[P];
                     yp[0] = wz;
                     xp[0] = 1.f;
 #pragma unroll
-                    for (int k = 1; k < P; ++k) {
-                        yp[k] = yp[k - 1] * q.y;
-                        xp[k] = xp[k - 1] * q.x;
-                    }
+                    for (int k = 1; k < AY; ++k) yp[k] = yp[k - 1] * q.y;
 #pragma unroll
-                    for (int ay = 0; ay < P; ++ay)
+                    for (int k = 1; k < P; ++k) xp[k] = xp[k - 1] * q.x;
+#pragma unroll
+                    for (int ay = 0; ay < AY; ++ay)
 #pragma unroll
                         for (int ax = 0; ax < P; ++ax) a2[ay][ax] = fmaf(yp[ay], xp[ax], a2[ay][ax]);
                 }
             }
 #pragma unroll
-            for (int o = P; o < 64; o <<= 1)
+            for (int o = P * H; o < 64; o <<= 1)
 #pragma unroll
-                for (int ay = 0; ay < P; ++ay)
+                for (int ay = 0; ay < AY; ++ay)
 #pragma unroll
                     for (int ax = 0; ax < P; ++ax) a2[ay][ax] += __shfl_xor(a2[ay][ax], o, 64);
             if (grp == 0) {
                 float fz = 1.f;
                 for (int k = 2; k <= az; ++k) fz *= (float)k;
                 float fy = 1.f;
+                for (int k = 2; k <= ah * AY - 1; ++k) fy *= (float)k;   // (first ay - 1)!
 #pragma unroll
-                for (int ay = 0; ay < P; ++ay) {
+                for (int i = 0; i < AY; ++i) {
+                    const int ay = ah * AY + i;
                     if (ay > 1) fy *= (float)ay;
                     float fx = 1.f;
 #pragma unroll
                     for (int ax = 0; ax < P; ++ax) {
                         if (ax > 1) fx *= (float)ax;
-                        tot[(az * P + ay) * P + ax] = a2[ay][ax] / (fx * fy * fz);
+                        tot[(az * P + ay) * P + ax] = a2[i][ax] / (fx * fy * fz);
                     }
                 }
             }
@@ -355,8 +371,8 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
 
         // M2M of the children that carry moments, G blocks at a time:
         // A'_a = sum_{g<=a} A_g d^(a-g)/(a-g)! along x, then y, then z
-        uint64_t todo = __ballot(chas);
-        while (todo) {
+        uint64_t todo = M2M ? __ballot(chas) : 0ull;
+        while (M2M && todo) {
             int32_t gid[G];
             int gdig[G];
             int ng = 0;
@@ -932,7 +948,10 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
             // the deepest level holds only leaves, which never exceed leaf_max points
             if (l == t->depth && t->leaf_max <= kC1 && l < t->max_depth) continue;
             const int64_t nb = b - a < 8192 ? b - a : 8192;
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_node_moments<P>), dim3((unsigned)nb), dim3(64), 0, s, a, b,
+            // children at the deepest level are leaves of at most leaf_max points: no moments
+            const bool leaf_children = l + 1 == t->depth && t->leaf_max <= kC1 && l + 1 < t->max_depth;
+            auto kern = leaf_children ? k_node_moments<P, false> : k_node_moments<P, true>;
+            hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, a, b,
                                l, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                                t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
                                t->niz.as<int32_t>(), t->ndigit.as<int32_t>(), t->geo.lo[0], t->geo.lo[1],
