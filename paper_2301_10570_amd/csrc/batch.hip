@@ -142,9 +142,45 @@ int plan_batch(msp_batch *b, const float *sigma, const msp_fgt_params *prm, std:
 
 // Allocations, interaction lists and the descriptors of the direct-route
 // populations (host synchronisations allowed: never under capture).
-int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, hipStream_t s) {
+int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
+                  float *u_out, hipStream_t s) {
     std::vector<PopDesc> d;
     std::vector<int64_t> poff{0}, ioff{0};
+    // expansion-route populations: descriptors and prefix sums for the batched passes
+    std::vector<FgtPop> fp;
+    std::vector<int64_t> ops_off{0}, node_off{0}, grid_off{0}, tile_off[3] = {{0}, {0}, {0}};
+    int p = 0;
+    for (int k = 0; k < b->npop; ++k) {
+        msp_tree *t = b->pops[k].get();
+        const PopPlan &pp = plans[k];
+        if (pp.pl.route != MSP_ROUTE_FGT || t->n == 0) continue;
+        FgtPop f;
+        MSP_TRY(fgt_pop_prepare(t, pp.pl, &pp.prm, &f));
+        const int64_t o = b->off[k];
+        f.w = w + o;
+        f.is_target = is_target ? is_target + o : nullptr;
+        f.u_out = u_out + o;
+        f.pop = k;
+        p = pp.pl.p;
+        fp.push_back(f);
+        ops_off.push_back(ops_off.back() + 2 * (f.G[0] + f.G[1] + f.G[2]) - 3);
+        node_off.push_back(node_off.back() + t->n_nodes);
+        grid_off.push_back(grid_off.back() + (int64_t)f.G[0] * f.G[1] * f.G[2] * p * p * p);
+    }
+    // M2L as whole-K GEMM tiles when every population's operator and tile fit in LDS
+    size_t gemm_lds = 0;
+    for (const FgtPop &f : fp) {
+        const size_t l = fgt_pop_gemm_lds(f, p);
+        gemm_lds = l > gemm_lds ? l : gemm_lds;
+    }
+    const bool gemm = gemm_lds <= 64 * 1024;
+    for (const FgtPop &f : fp)
+        for (int pass = 0; pass < 3; ++pass)
+            tile_off[pass].push_back(tile_off[pass].back() + fgt_pop_tiles(f, p, pass, gemm));
+    const int nf = (int)fp.size();
+    MSP_TRY(b->fdesc.ensure((fp.size() + 1) * sizeof(FgtPop)));
+    MSP_TRY(b->foff.ensure((size_t)6 * (nf + 1) * 8));
+    MSP_TRY(b->franges.ensure((size_t)(node_off.back() + 1) * sizeof(int4) + 16));
     for (int k = 0; k < b->npop; ++k) {
         msp_tree *t = b->pops[k].get();
         const PopPlan &pp = plans[k];
@@ -190,6 +226,34 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, hipStream_t s
     MSP_HIP(hipMemcpy(b->item_off.p, ioff.data(), ioff.size() * 8, hipMemcpyHostToDevice));
     std::vector<uint64_t> zero((size_t)(b->npop > 0 ? b->npop : 1) * 2, 0);
     MSP_HIP(hipMemcpy(b->stamps.p, zero.data(), zero.size() * 8, hipMemcpyHostToDevice));
+    FgtBatchPlan &bp = b->fplan;
+    bp = FgtBatchPlan{};
+    bp.npop = nf;
+    bp.p = p;
+    bp.cus = b->cus;
+    bp.gemm = gemm ? 1 : 0;
+    bp.gemm_lds = gemm_lds;
+    if (nf > 0) {
+        MSP_HIP(hipMemcpy(b->fdesc.p, fp.data(), fp.size() * sizeof(FgtPop), hipMemcpyHostToDevice));
+        int64_t *off = b->foff.as<int64_t>();
+        const std::vector<int64_t> *arrs[6] = {&ops_off, &node_off, &grid_off, &tile_off[0], &tile_off[1], &tile_off[2]};
+        for (int a = 0; a < 6; ++a)
+            MSP_HIP(hipMemcpy(off + (size_t)a * (nf + 1), arrs[a]->data(), (size_t)(nf + 1) * 8, hipMemcpyHostToDevice));
+        bp.pops = b->fdesc.as<FgtPop>();
+        bp.ops_off = off;
+        bp.node_off = off + (nf + 1);
+        bp.grid_off = off + 2 * (nf + 1);
+        for (int pass = 0; pass < 3; ++pass) {
+            bp.tile_off[pass] = off + (size_t)(3 + pass) * (nf + 1);
+            bp.n_tiles[pass] = tile_off[pass].back();
+        }
+        bp.n_ops = ops_off.back();
+        bp.n_nodes = node_off.back();
+        bp.n_grid = grid_off.back();
+        bp.nranges = reinterpret_cast<int32_t *>(b->franges.as<int4>() + node_off.back());
+        bp.ranges = b->franges.as<int4>();
+        bp.stamps = b->stamps.as<unsigned long long>();
+    }
     return MSP_OK;
 }
 
@@ -199,26 +263,13 @@ int enqueue_forward(msp_batch *b, const std::vector<PopPlan> &plans, const float
                     const uint8_t *is_target, float *u_out, hipStream_t s) {
     int64_t launches = 0;
     uint64_t *stamps = b->stamps.as<uint64_t>();
-    // expansion-route populations round-robin on the branch streams, which fork
-    // from s here and join it at the end (also under capture)
-    constexpr int NB = msp_batch::kBranches;
+    // all expansion-route populations on a branch stream that forks from s here and
+    // joins it at the end (also under capture), beside the direct-route launch
     MSP_HIP(hipEventRecord(b->fork, s));
-    for (int r = 0; r < NB; ++r) MSP_HIP(hipStreamWaitEvent(b->side[r], b->fork, 0));
-    int next = 0;
-    for (int k = 0; k < b->npop; ++k) {
-        msp_tree *t = b->pops[k].get();
-        const PopPlan &pp = plans[k];
-        if (pp.pl.route != MSP_ROUTE_FGT || t->n == 0) continue;
-        hipStream_t bs = b->side[next];
-        next = (next + 1) % NB;
-        const int64_t o = b->off[k];
-        hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, bs, stamps + 2 * k);
-        MSP_CHECK_LAUNCH();
-        MSP_TRY(fgt_forward_grid(t, pp.pl, &pp.prm, w + o, is_target ? is_target + o : nullptr, u_out + o, bs));
-        hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, bs, stamps + 2 * k + 1);
-        MSP_CHECK_LAUNCH();
-        launches += 8;
-    }
+    MSP_HIP(hipStreamWaitEvent(b->side[0], b->fork, 0));
+    MSP_TRY(fgt_batch_forward(b->fplan, b->side[0]));
+    if (b->fplan.npop > 0) launches += 8;
+    (void)stamps;
     const int nd = b->n_direct;
     if (nd > 0) {
         const PopDesc *desc = b->desc.as<PopDesc>();
@@ -241,10 +292,8 @@ int enqueue_forward(msp_batch *b, const std::vector<PopPlan> &plans, const float
         MSP_CHECK_LAUNCH();
         launches += 4;
     }
-    for (int r = 0; r < NB; ++r) {
-        MSP_HIP(hipEventRecord(b->join[r], b->side[r]));
-        MSP_HIP(hipStreamWaitEvent(s, b->join[r], 0));
-    }
+    MSP_HIP(hipEventRecord(b->join[0], b->side[0]));
+    MSP_HIP(hipStreamWaitEvent(s, b->join[0], 0));
     b->launches = launches;
     return MSP_OK;
 }
@@ -294,7 +343,7 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
         return MSP_OK;
     }
     b->drop_graph();
-    MSP_TRY(prepare_batch(b, plans, s));
+    MSP_TRY(prepare_batch(b, plans, w, is_target, u_out, s));
     MSP_TRY(enqueue_forward(b, plans, w, is_target, u_out, s));
     if (!use_graph) return MSP_OK;
     // capture the same sequence for later calls

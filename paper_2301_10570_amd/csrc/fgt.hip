@@ -57,8 +57,7 @@ constexpr int kBlock = 256;
 
 // T_k[o][b][a] = (-1)^b / b! * h_{a+b}(o * step), o = -(G_k-1) .. G_k-1, for the three
 // axes in one launch (thread -> axis, offset); computed in float64, stored as float32.
-__global__ void k_m2l_ops(int p, int Gx, int Gy, int Gz, double step, float *ox, float *oy, float *oz) {
-    int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__device__ void m2l_ops_one(int p, int Gx, int Gy, int Gz, double step, float *ox, float *oy, float *oz, int t) {
     const int nx = 2 * Gx - 1, ny = 2 * Gy - 1, nz = 2 * Gz - 1;
     int G;
     float *out;
@@ -81,6 +80,10 @@ __global__ void k_m2l_ops(int p, int Gx, int Gy, int Gz, double step, float *ox,
     }
 }
 
+__global__ void k_m2l_ops(int p, int Gx, int Gy, int Gz, double step, float *ox, float *oy, float *oz) {
+    m2l_ops_one(p, Gx, Gy, Gz, step, ox, oy, oz, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+}
+
 // Point range of a grid cell: the points whose level-`level` key prefix is the
 // cell's Morton code (contiguous in key order).
 __device__ inline void cell_range(const uint64_t *keys, int64_t n, int level, int kx, int ky, int kz,
@@ -95,21 +98,16 @@ __device__ inline void cell_range(const uint64_t *keys, int64_t n, int level, in
 // [kz][az][ky][ay][kx][ax].  Lane l of a wave owns az = l % P and handles every
 // (64/P)-th point of the wave's share; it keeps the P x P moments (ax, ay) of its
 // az in registers.  Partial moments are added in a fixed order (lanes, then waves).
+// Moments of the points [start, end) of cell (kx, ky, kz) (block-wide).
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n, const float4 *ps,
-                                                const int32_t *perm, const float *w,
-                                                int level, int Gx, int Gy, int Gz, double lox,
-                                                double loy, double loz, double cell,
-                                                double inv_sigma, float *A) {
+__device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, int Gx, int Gy,
+                         double lox, double loy, double loz, double cell, double inv_sigma, float *A,
+                         int kx, int ky, int kz, int64_t start, int64_t end) {
     constexpr int P3 = P * P * P;
     constexpr int PL = 64 / P;            // point lanes per wave
     constexpr int NW = kBlock / 64;
     constexpr int NB = P <= 12 ? NW : 1;  // partial buffers (LDS budget for large P)
     __shared__ float red[NB][P3];
-    const int64_t g = blockIdx.x;
-    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
-    int64_t start, end;
-    cell_range(keys, n, level, kx, ky, kz, start, end);
     const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int az = lane % P, pl = lane / P;
@@ -189,6 +187,21 @@ __global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n,
     }
 }
 
+// One block per cell of the grid; moments written in the grid layout
+// [kz][az][ky][ay][kx][ax] (empty cells get zeros).
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                const int32_t *perm, const float *w,
+                                                int level, int Gx, int Gy, int Gz, double lox,
+                                                double loy, double loz, double cell,
+                                                double inv_sigma, float *A) {
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
+    p2m_cell<P>(ps, perm, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, A, kx, ky, kz, start, end);
+}
+
 // Out[v][r] = sum_u In[r][u] * T[(v/p) - (u/p) + G - 1][v%p][u%p], u, v in [0, G*p).
 constexpr int TR = 64, TV = 64, TK = 16;
 __global__ void __launch_bounds__(kBlock) k_m2l_pass(const float *In, float *Out, int64_t R, int p,
@@ -252,13 +265,11 @@ __global__ void __launch_bounds__(kBlock) k_m2l_pass(const float *In, float *Out
 // B[l/16][l%16] and receives D[4*(l/16) + i][l%16], i = 0..3.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 32, MK = 16;
-__global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Out, int64_t R, int p,
-                                                      int G, const float *T) {
+__device__ void m2l_tile_mfma(const float *In, float *Out, int64_t R, int p, int G, const float *T, int64_t r0,
+                              int v0) {
     __shared__ float sA[MT][MK + 1];   // operator rows v, columns u
     __shared__ float sB[MT][MK + 1];   // input rows r, columns u
     const int U = G * p;
-    const int64_t r0 = (int64_t)blockIdx.x * MT;
-    const int v0 = blockIdx.y * MT;
     const int lane = threadIdx.x;
     f32x4 acc[2][2];
 #pragma unroll
@@ -303,6 +314,91 @@ __global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Ou
                 const int64_t r = r0 + 16 * b + (lane & 15);
                 if (v < U && r < R) Out[(int64_t)v * R + r] = acc[a][b][i];
             }
+}
+
+__global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Out, int64_t R, int p,
+                                                      int G, const float *T) {
+    m2l_tile_mfma(In, Out, R, p, G, T, (int64_t)blockIdx.x * MT, (int)blockIdx.y * MT);
+}
+
+// The same pass with the whole contraction in LDS: a block of four waves takes RT
+// rows r of In (all U columns, staged once) and the operator table T of the axis,
+// and produces Out[v][r] for every v.  Each wave owns 16-row slices of v: it keeps
+// its slice's operator entries for all K steps in registers (generated from T by
+// offset, row and column) and sweeps the r columns in 16-wide MFMA tiles
+// (v_mfma_f32_16x16x4f32, same lane layout as above).  LDS: RT x (U + 1) floats of
+// In and (2G - 1) p^2 floats of T (dynamic).
+__host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
+    return ((size_t)RT * (U + 1) + (size_t)(2 * G - 1) * p * p) * 4;
+}
+
+template <int RT>
+__device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int G, const float *T, int64_t r0,
+                              float *sm) {
+    constexpr int NR = RT / 16;   // 16-wide column tiles per block
+    constexpr int KC = 8;         // K steps (of 4) per operator chunk in registers
+    const int U = G * p;
+    const int UP = U + 1;
+    float *sIn = sm;
+    float *sT = sm + (size_t)RT * UP;
+    const int nT = (2 * G - 1) * p * p;
+    for (int e = threadIdx.x; e < nT; e += 256) sT[e] = T[e];
+    for (int e = threadIdx.x; e < RT * U; e += 256) {
+        const int rr = e / U, u = e % U;
+        const int64_t r = r0 + rr;
+        sIn[rr * UP + u] = r < R ? In[r * U + u] : 0.f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nk = (U + 3) / 4;
+    const int nv = (U + 15) / 16;
+    for (int vc = wave; vc < nv; vc += 4) {
+        const int v = vc * 16 + (lane & 15);
+        const int tv = v / p, b = v % p;
+        f32x4 acc[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        int s = (lane >> 4) / p, ai = (lane >> 4) % p;   // column u = 4 k + lane / 16 as (cell, term)
+        for (int k0 = 0; k0 < nk; k0 += KC) {
+            // this lane's operator entries M[v][u] for KC steps
+            float a[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const int u = 4 * (k0 + k) + (lane >> 4);
+                a[k] = (v < U && u < U) ? sT[((tv - s + G - 1) * p + b) * p + ai] : 0.f;
+                ai += 4;
+                while (ai >= p) {
+                    ai -= p;
+                    ++s;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const float *bcol = sIn + (16 * j + (lane & 15)) * UP + (lane >> 4);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int u = 4 * (k0 + k) + (lane >> 4);
+                    const float bv = u < U ? bcol[4 * (k0 + k)] : 0.f;
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bv, acc[j], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int vo = vc * 16 + 4 * (lane >> 4) + i;
+                const int64_t r = r0 + 16 * j + (lane & 15);
+                if (vo < U && r < R) Out[(int64_t)vo * R + r] = acc[j][i];
+            }
+    }
+}
+
+template <int RT>
+__global__ void __launch_bounds__(256) k_m2l_gemm(const float *In, float *Out, int64_t R, int p, int G,
+                                                  const float *T) {
+    extern __shared__ float sm[];
+    m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
 }
 
 // The same pass with split bfloat16 products (v_mfma_f32_16x16x32_bf16): each
@@ -394,20 +490,14 @@ __global__ void __launch_bounds__(64) k_m2l_pass_bf16x3(const float *In, float *
 // One block per cell: evaluate the cell's Taylor series at its targets (Horner
 // in x, then y, then z), two targets per thread so that every coefficient read
 // from LDS feeds two multiply-adds.
+// Taylor series of cell (kx, ky, kz) at its points [start, end) (block-wide).
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n, const float4 *ps,
-                                                const int32_t *perm, const uint8_t *is_target,
-                                                const float *w, int subtract_self, int level, int Gx,
-                                                int Gy, int Gz, double lox, double loy, double loz,
-                                                double cell, double inv_sigma, const float *C,
-                                                float *u_out) {
+__device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *is_target, const float *w,
+                         int subtract_self, int Gx, int Gy, double lox, double loy, double loz,
+                         double cell, double inv_sigma, const float *C, float *u_out, int kx, int ky,
+                         int kz, int64_t start, int64_t end) {
     constexpr int P3 = P * P * P;
     __shared__ float sC[P3];
-    const int64_t g = blockIdx.x;
-    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
-    int64_t start, end;
-    cell_range(keys, n, level, kx, ky, kz, start, end);
-    if (start == end) return;
     const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
     for (int e = threadIdx.x; e < P3; e += kBlock) {
         const int ax = e % P, ay = (e / P) % P, az = e / (P * P);
@@ -452,6 +542,22 @@ __global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n,
         u_out[j0] = t0 ? uz0 - w0 : 0.f;
         if (has1) u_out[j1] = t1 ? uz1 - w1 : 0.f;
     }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_l2p(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                const int32_t *perm, const uint8_t *is_target,
+                                                const float *w, int subtract_self, int level, int Gx,
+                                                int Gy, int Gz, double lox, double loy, double loz,
+                                                double cell, double inv_sigma, const float *C,
+                                                float *u_out) {
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
+    if (start == end) return;
+    l2p_cell<P>(ps, perm, is_target, w, subtract_self, Gx, Gy, lox, loy, loz, cell, inv_sigma, C, u_out,
+                kx, ky, kz, start, end);
 }
 
 // ---------------------------------------------------------------------------------
@@ -926,6 +1032,226 @@ int fgt_field_grad(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, co
     return fail(MSP_EINVAL, "p out of range");
 }
 
+// ---------------------------------------------------------------------------------
+// Batches of expansion-route populations: one launch per pass covers all of them.
+// Work units are (population, operator), (population, grid float), (population,
+// node) and (population, M2L tile), located by binary search in prefix sums.
+// P2M and L2P run over "ranges": the nodes at the expansion level and the leaves
+// above it, each holding whole cells of that level (split by key prefix).
+namespace {
+
+__device__ inline int find_pop(const int64_t *off, int npop, int64_t x) {
+    int lo = 0, hi = npop;   // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bops(FgtBatchPlan bp) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= bp.n_ops) return;
+    const int k = find_pop(bp.ops_off, bp.npop, g);
+    const FgtPop &f = bp.pops[k];
+    m2l_ops_one(bp.p, f.G[0], f.G[1], f.G[2], f.step, f.opsx, f.opsy, f.opsz, (int)(g - bp.ops_off[k]));
+}
+
+// zero moment grids (cells without points are never written by the range P2M),
+// clear the range counter and the timestamps
+__global__ void k_bclear(FgtBatchPlan bp) {
+    const int64_t g0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g0 == 0) *bp.nranges = 0;
+    if (g0 < bp.npop) {
+        bp.stamps[2 * bp.pops[g0].pop] = ~0ull;
+        bp.stamps[2 * bp.pops[g0].pop + 1] = 0ull;
+    }
+    for (int64_t g = g0; g < bp.n_grid; g += (int64_t)gridDim.x * blockDim.x) {
+        const int k = find_pop(bp.grid_off, bp.npop, g);
+        bp.pops[k].A[g - bp.grid_off[k]] = 0.f;
+    }
+}
+
+__global__ void k_branges(FgtBatchPlan bp) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= bp.n_nodes) return;
+    const int k = find_pop(bp.node_off, bp.npop, g);
+    const FgtPop &f = bp.pops[k];
+    const int64_t v = g - bp.node_off[k];
+    const int l = f.nlevel[v];
+    if (l == f.level || (l < f.level && f.nnchild[v] == 0)) {
+        const int32_t c = f.ncount[v];
+        if (c > 0) bp.ranges[atomicAdd(bp.nranges, 1)] = make_int4(k, f.nfirst[v], c, 0);
+    }
+}
+
+// walk the cells of one range: [s, e) of equal level prefix, then the next
+template <typename F>
+__device__ inline void for_cells(const FgtPop &f, int64_t first, int64_t last, F &&fn) {
+    const int sh = 3 * (kDepth - f.level);
+    int64_t s0 = first;
+    while (s0 < last) {
+        const uint64_t pre = f.keys[s0] >> sh;
+        const int64_t e = lower_bound_u64(f.keys, s0, last, (pre + 1ull) << sh);
+        fn((int)compact3(pre >> 2), (int)compact3(pre >> 1), (int)compact3(pre), s0, e);
+        __syncthreads();
+        s0 = e;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_bp2m(FgtBatchPlan bp) {
+    const int64_t m = *bp.nranges;
+    for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+        const int4 rg = bp.ranges[r];
+        const FgtPop &f = bp.pops[rg.x];
+        if (threadIdx.x == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
+        for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
+            p2m_cell<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo[0], f.lo[1], f.lo[2], f.cell, f.inv_sigma,
+                        f.A, kx, ky, kz, s0, e);
+        });
+    }
+}
+
+__global__ void __launch_bounds__(64) k_bm2l(FgtBatchPlan bp, int pass) {
+    const int64_t g = blockIdx.x;
+    const int k = find_pop(bp.tile_off[pass], bp.npop, g);
+    const FgtPop &f = bp.pops[k];
+    const int p = bp.p;
+    const int64_t Ux = (int64_t)f.G[0] * p, Uy = (int64_t)f.G[1] * p, Uz = (int64_t)f.G[2] * p;
+    const float *In = pass == 0 ? f.A : (pass == 1 ? f.B : f.Tmp);
+    float *Out = pass == 1 ? f.Tmp : f.B;
+    const int64_t R = pass == 0 ? Uz * Uy : (pass == 1 ? Ux * Uz : Uy * Ux);
+    const int G = f.G[pass];
+    const float *T = pass == 0 ? f.opsx : (pass == 1 ? f.opsy : f.opsz);
+    const int64_t nr = (R + MT - 1) / MT;
+    const int64_t t = g - bp.tile_off[pass][k];
+    m2l_tile_mfma(In, Out, R, p, G, T, (t % nr) * MT, (int)(t / nr) * MT);
+}
+
+__global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp, int pass) {
+    extern __shared__ float sm[];
+    const int64_t g = blockIdx.x;
+    const int k = find_pop(bp.tile_off[pass], bp.npop, g);
+    const FgtPop &f = bp.pops[k];
+    const int p = bp.p;
+    const int64_t Ux = (int64_t)f.G[0] * p, Uy = (int64_t)f.G[1] * p, Uz = (int64_t)f.G[2] * p;
+    const float *In = pass == 0 ? f.A : (pass == 1 ? f.B : f.Tmp);
+    float *Out = pass == 1 ? f.Tmp : f.B;
+    const int64_t R = pass == 0 ? Uz * Uy : (pass == 1 ? Ux * Uz : Uy * Ux);
+    const float *T = pass == 0 ? f.opsx : (pass == 1 ? f.opsy : f.opsz);
+    m2l_gemm_tile<32>(In, Out, R, p, f.G[pass], T, (g - bp.tile_off[pass][k]) * 32, sm);
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_bl2p(FgtBatchPlan bp) {
+    const int64_t m = *bp.nranges;
+    for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+        const int4 rg = bp.ranges[r];
+        const FgtPop &f = bp.pops[rg.x];
+        for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
+            l2p_cell<P>(f.ps, f.perm, f.is_target, f.w, f.subtract_self, f.G[0], f.G[1], f.lo[0], f.lo[1],
+                        f.lo[2], f.cell, f.inv_sigma, f.B, f.u_out, kx, ky, kz, s0, e);
+        });
+        if (threadIdx.x == 0) atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
+    }
+}
+
+template <int P>
+int batch_p2m_l2p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
+    const unsigned grid = (unsigned)(bp.cus * 8);
+    if (!l2p) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bp2m<P>), dim3(grid), dim3(kBlock), 0, s, bp);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bl2p<P>), dim3(grid), dim3(kBlock), 0, s, bp);
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+
+int batch_p2m_l2p_p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
+    switch (bp.p) {
+#define CASE(P) case P: return batch_p2m_l2p<P>(bp, l2p, s);
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    }
+    return fail(MSP_EINVAL, "p out of range");
+}
+
+}  // namespace
+
+int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
+    if (bp.npop == 0) return MSP_OK;
+    hipLaunchKernelGGL(k_bops, dim3(grid_for(bp.n_ops, 64)), dim3(64), 0, s, bp);
+    MSP_CHECK_LAUNCH();
+    const int64_t fill_threads = bp.n_grid < (int64_t)bp.cus * 2048 ? bp.n_grid : (int64_t)bp.cus * 2048;
+    hipLaunchKernelGGL(k_bclear, dim3(grid_for(fill_threads > bp.npop ? fill_threads : bp.npop, kBlock)),
+                       dim3(kBlock), 0, s, bp);
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_branges, dim3(grid_for(bp.n_nodes, kBlock)), dim3(kBlock), 0, s, bp);
+    MSP_CHECK_LAUNCH();
+    MSP_TRY(batch_p2m_l2p_p(bp, false, s));
+    for (int pass = 0; pass < 3; ++pass) {
+        if (bp.n_tiles[pass] == 0) continue;
+        if (bp.gemm)
+            hipLaunchKernelGGL(k_bm2l_gemm, dim3((unsigned)bp.n_tiles[pass]), dim3(256), bp.gemm_lds, s, bp, pass);
+        else
+            hipLaunchKernelGGL(k_bm2l, dim3((unsigned)bp.n_tiles[pass]), dim3(64), 0, s, bp, pass);
+        MSP_CHECK_LAUNCH();
+    }
+    return batch_p2m_l2p_p(bp, true, s);
+}
+
+int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, FgtPop *f) {
+    const int p = pl.p;
+    const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
+    const size_t gbytes = (size_t)ncell * p * p * p * 4;
+    MSP_TRY(t->gridA.ensure(gbytes));
+    MSP_TRY(t->gridB.ensure(gbytes));
+    MSP_TRY(t->ops.ensure(gbytes + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4));
+    t->grid_bytes_valid = (int64_t)gbytes;
+    f->keys = t->keys.as<uint64_t>();
+    f->ps = t->ps.as<float4>();
+    f->perm = t->perm.as<int32_t>();
+    f->n = t->n;
+    f->nlevel = t->nlevel.as<int32_t>();
+    f->nfirst = t->nfirst.as<int32_t>();
+    f->ncount = t->ncount.as<int32_t>();
+    f->nnchild = t->nnchild.as<int32_t>();
+    f->n_nodes = t->n_nodes;
+    f->subtract_self = (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0;
+    f->A = t->gridA.as<float>();
+    f->B = t->gridB.as<float>();
+    f->Tmp = t->ops.as<float>();
+    f->opsx = f->Tmp + (size_t)ncell * p * p * p;
+    f->opsy = f->opsx + (size_t)(2 * pl.G[0] - 1) * p * p;
+    f->opsz = f->opsy + (size_t)(2 * pl.G[1] - 1) * p * p;
+    f->level = pl.level;
+    for (int k = 0; k < 3; ++k) {
+        f->G[k] = pl.G[k];
+        f->lo[k] = t->geo.lo[k];
+    }
+    f->cell = pl.cell;
+    f->inv_sigma = 1.0 / prm->sigma;
+    f->step = pl.cell / prm->sigma;
+    return MSP_OK;
+}
+
+int64_t fgt_pop_tiles(const FgtPop &f, int p, int pass, bool gemm) {
+    const int64_t U[3] = {(int64_t)f.G[0] * p, (int64_t)f.G[1] * p, (int64_t)f.G[2] * p};
+    const int64_t R = pass == 0 ? U[2] * U[1] : (pass == 1 ? U[0] * U[2] : U[1] * U[0]);
+    if (gemm) return (R + 31) / 32;
+    return ((R + MT - 1) / MT) * ((U[pass] + MT - 1) / MT);
+}
+
+size_t fgt_pop_gemm_lds(const FgtPop &f, int p) {
+    size_t m = 0;
+    for (int k = 0; k < 3; ++k) {
+        const size_t l = m2l_gemm_lds(f.G[k] * p, f.G[k], p, 32);
+        m = l > m ? l : m;
+    }
+    return m;
+}
+
 constexpr double kMaxGridBytes = 48.0e9;   // per expansion grid
 
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *pl) {
@@ -1042,8 +1368,22 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
             dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
             hipLaunchKernelGGL(k_m2l_pass_bf16x3, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
         } else {
-            dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
-            hipLaunchKernelGGL(k_m2l_pass_mfma, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+            // rows per block: enough blocks to fill the chip, at most 64
+            int RT = 64;
+            while (RT > 16 && (ps.R + RT - 1) / RT < 1024) RT >>= 1;
+            const size_t lds = m2l_gemm_lds((int)ps.U, ps.G, p, RT);
+            if (lds <= 64 * 1024) {
+                const dim3 grid((unsigned)((ps.R + RT - 1) / RT));
+                if (RT == 64)
+                    hipLaunchKernelGGL(k_m2l_gemm<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+                else if (RT == 32)
+                    hipLaunchKernelGGL(k_m2l_gemm<32>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+                else
+                    hipLaunchKernelGGL(k_m2l_gemm<16>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+            } else {
+                dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
+                hipLaunchKernelGGL(k_m2l_pass_mfma, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+            }
         }
         MSP_CHECK_LAUNCH();
     }

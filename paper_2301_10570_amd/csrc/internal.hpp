@@ -137,6 +137,42 @@ struct msp_tree {
     int64_t node_moments_bytes = 0;
 };
 
+namespace msp {
+
+// One expansion-route population of a batch, as the batched kernels read it.
+struct FgtPop {
+    const uint64_t *keys;
+    const float4 *ps;
+    const int32_t *perm;
+    int64_t n;
+    const int32_t *nlevel, *nfirst, *ncount, *nnchild;
+    int64_t n_nodes;
+    const float *w;
+    const uint8_t *is_target;
+    float *u_out;
+    int subtract_self;
+    float *A, *B, *Tmp, *opsx, *opsy, *opsz;
+    int level, G[3];
+    double lo[3], cell, inv_sigma, step;
+    int pop;
+};
+// Device-side offsets of a batch of expansion-route populations (prefix sums over
+// the populations of their operator counts, nodes, grid floats and M2L tiles).
+struct FgtBatchPlan {
+    const FgtPop *pops;
+    int npop, p;
+    const int64_t *ops_off, *node_off, *grid_off, *tile_off[3];
+    int64_t n_ops, n_nodes, n_grid, n_tiles[3];
+    int4 *ranges;
+    int32_t *nranges;
+    unsigned long long *stamps;
+    int cus;
+    int gemm;          // M2L passes as whole-K GEMM tiles of 32 rows (else 32 x 32 tiles)
+    size_t gemm_lds;   // dynamic LDS of the GEMM tiles (largest population)
+};
+
+}  // namespace msp
+
 // A batch of independent populations (batch.hip).
 struct msp_batch {
     int device = -1;
@@ -150,8 +186,11 @@ struct msp_batch {
     int32_t n_direct = 0;
     int cus = 256;
     int64_t direct_points = 0, direct_items = 0;
-    // branches for the expansion-route populations (forked from the caller's stream)
-    static constexpr int kBranches = 8;
+    // expansion-route populations: descriptors, offsets, range list, launch plan
+    msp::DevBuf fdesc, foff, franges;
+    msp::FgtBatchPlan fplan{};
+    // branch stream for the expansion-route populations (forked from the caller's stream)
+    static constexpr int kBranches = 1;
     hipStream_t side[kBranches] = {};
     hipEvent_t fork = nullptr, join[kBranches] = {};
     // graph of the last forward signature
@@ -179,6 +218,7 @@ struct msp_batch {
 };
 
 namespace msp {
+
 
 // batch.hip
 int batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
@@ -210,6 +250,12 @@ struct FgtPlan {
     double fgt_cost, direct_cost;
     int pf;           // > 0: terms at the sub-cells two levels down (two-level variant)
 };
+
+// fgt.hip: grid buffers of a population (allocated here) and the batched forward
+int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, FgtPop *out);
+int64_t fgt_pop_tiles(const FgtPop &f, int p, int pass, bool gemm);
+size_t fgt_pop_gemm_lds(const FgtPop &f, int p);
+int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s);
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
 double rho_max_for_p(int p);
 int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s);
