@@ -1100,16 +1100,153 @@ __device__ inline void for_cells(const FgtPop &f, int64_t first, int64_t last, F
     }
 }
 
+// Moments of the points [s0, e) of one cell by one wavefront, written into the
+// grid (same layout and normalisation as p2m_cell).  Points pass through LDS 64 at a
+// time.  For p = 1, 2, 4, 8 a lane (point group, ay half, az) accumulates its (ay, ax)
+// block over every NG-th point and the groups are added by butterfly shuffles;
+// otherwise a lane owns whole (ay, az) rows and visits every point.
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_bp2m(FgtBatchPlan bp) {
+__device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float *w, int Gx, int Gy,
+                              const double *lo, double cell, double inv_sigma, float *A, int kx, int ky,
+                              int kz, int64_t s0, int64_t e, float4 *stage) {
+    constexpr bool ILP = P == 1 || P == 2 || P == 4 || P == 8;
+    const int lane = threadIdx.x;
+    const double cx = lo[0] + (kx + 0.5) * cell, cy = lo[1] + (ky + 0.5) * cell, cz = lo[2] + (kz + 0.5) * cell;
+    const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    auto out = [&](int ax, int ay, int az, float v) {
+        A[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax] = v;
+    };
+    auto stage_chunk = [&](int64_t c0) {
+        const int64_t j = c0 + lane;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < e) {
+            const float4 t = ps[j];
+            q = make_float4((float)(((double)t.x - cx) * inv_sigma), (float)(((double)t.y - cy) * inv_sigma),
+                            (float)(((double)t.z - cz) * inv_sigma), w[perm[j]]);
+        }
+        return q;
+    };
+    if constexpr (ILP) {
+        constexpr int H = P == 8 ? 2 : 1;
+        constexpr int AY = P / H;
+        constexpr int NG = 64 / (P * H);
+        const int az = lane % P, ah = (lane / P) % H, grp = lane / (P * H);
+        float a2[AY][P];
+#pragma unroll
+        for (int i = 0; i < AY; ++i)
+#pragma unroll
+            for (int ax = 0; ax < P; ++ax) a2[i][ax] = 0.f;
+        float4 nxt = stage_chunk(s0);
+        for (int64_t c0 = s0; c0 < e; c0 += 64) {
+            __syncthreads();
+            stage[lane] = nxt;
+            __syncthreads();
+            if (c0 + 64 < e) nxt = stage_chunk(c0 + 64);
+            const int m = e - c0 < 64 ? (int)(e - c0) : 64;
+            for (int jj = grp; jj < m; jj += NG) {
+                const float4 q = stage[jj];
+                float wz = q.w;
+                for (int k = 0; k < az; ++k) wz *= q.z;
+                for (int k = 0; k < ah * AY; ++k) wz *= q.y;
+                float yp[AY], xp[P];
+                yp[0] = wz;
+                xp[0] = 1.f;
+#pragma unroll
+                for (int k = 1; k < AY; ++k) yp[k] = yp[k - 1] * q.y;
+#pragma unroll
+                for (int k = 1; k < P; ++k) xp[k] = xp[k - 1] * q.x;
+#pragma unroll
+                for (int i = 0; i < AY; ++i)
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) a2[i][ax] = fmaf(yp[i], xp[ax], a2[i][ax]);
+            }
+        }
+#pragma unroll
+        for (int o = P * H; o < 64; o <<= 1)
+#pragma unroll
+            for (int i = 0; i < AY; ++i)
+#pragma unroll
+                for (int ax = 0; ax < P; ++ax) a2[i][ax] += __shfl_xor(a2[i][ax], o, 64);
+        if (grp == 0) {
+            float fz = 1.f;
+            for (int k = 2; k <= az; ++k) fz *= (float)k;
+            float fy = 1.f;
+            for (int k = 2; k <= ah * AY - 1; ++k) fy *= (float)k;
+#pragma unroll
+            for (int i = 0; i < AY; ++i) {
+                const int ay = ah * AY + i;
+                if (ay > 1) fy *= (float)ay;
+                float fx = 1.f;
+#pragma unroll
+                for (int ax = 0; ax < P; ++ax) {
+                    if (ax > 1) fx *= (float)ax;
+                    out(ax, ay, az, a2[i][ax] / (fx * fy * fz));
+                }
+            }
+        }
+    } else {
+        constexpr int P2 = P * P;
+        constexpr int RP = (P2 + 63) / 64;
+        float acc[RP][P];
+#pragma unroll
+        for (int rr = 0; rr < RP; ++rr)
+#pragma unroll
+            for (int ax = 0; ax < P; ++ax) acc[rr][ax] = 0.f;
+        float4 nxt = stage_chunk(s0);
+        for (int64_t c0 = s0; c0 < e; c0 += 64) {
+            __syncthreads();
+            stage[lane] = nxt;
+            __syncthreads();
+            if (c0 + 64 < e) nxt = stage_chunk(c0 + 64);
+            const int m = e - c0 < 64 ? (int)(e - c0) : 64;
+            for (int jj = 0; jj < m; ++jj) {
+                const float4 q = stage[jj];
+                float xp[P];
+                xp[0] = 1.f;
+#pragma unroll
+                for (int k = 1; k < P; ++k) xp[k] = xp[k - 1] * q.x;
+#pragma unroll
+                for (int rr = 0; rr < RP; ++rr) {
+                    const int row = lane + 64 * rr;
+                    if (row >= P2) continue;
+                    float f = q.w;
+                    for (int k = 0; k < row % P; ++k) f *= q.y;
+                    for (int k = 0; k < row / P; ++k) f *= q.z;
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) acc[rr][ax] = fmaf(f, xp[ax], acc[rr][ax]);
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RP; ++rr) {
+            const int row = lane + 64 * rr;
+            if (row >= P2) continue;
+            const int ay = row % P, az = row / P;
+            float fyz = 1.f;
+            for (int k = 2; k <= ay; ++k) fyz *= (float)k;
+            for (int k = 2; k <= az; ++k) fyz *= (float)k;
+            float fx = 1.f;
+#pragma unroll
+            for (int ax = 0; ax < P; ++ax) {
+                if (ax > 1) fx *= (float)ax;
+                out(ax, ay, az, acc[rr][ax] / (fx * fyz));
+            }
+        }
+    }
+}
+
+// one wavefront per range
+template <int P>
+__global__ void __launch_bounds__(64) k_bp2m(FgtBatchPlan bp) {
+    __shared__ float4 stage[64];
     const int64_t m = *bp.nranges;
     for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
         const int4 rg = bp.ranges[r];
         const FgtPop &f = bp.pops[rg.x];
         if (threadIdx.x == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
         for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
-            p2m_cell<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo[0], f.lo[1], f.lo[2], f.cell, f.inv_sigma,
-                        f.A, kx, ky, kz, s0, e);
+            p2m_cell_wave<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo, f.cell, f.inv_sigma, f.A, kx, ky, kz, s0, e,
+                             stage);
         });
     }
 }
@@ -1161,7 +1298,7 @@ __global__ void __launch_bounds__(kBlock) k_bl2p(FgtBatchPlan bp) {
 template <int P>
 int batch_p2m_l2p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
     const unsigned grid = (unsigned)(bp.cus * 8);
-    if (!l2p) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bp2m<P>), dim3(grid), dim3(kBlock), 0, s, bp);
+    if (!l2p) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bp2m<P>), dim3(grid * 4), dim3(64), 0, s, bp);
     else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bl2p<P>), dim3(grid), dim3(kBlock), 0, s, bp);
     MSP_CHECK_LAUNCH();
     return MSP_OK;

@@ -1,6 +1,8 @@
 """Batches of independent populations (config 5 shape, half size): the batched
-forward and backward equal the single-tree calls on every population, agree
-with the FP64 oracle, and replays of the captured graph equal the eager result."""
+forward matches the single-tree calls on every population (bit for bit on the
+direct route, to float32 rounding on the expansion route), the batched backward
+equals them, both agree with the FP64 oracle, and replays of the captured graph
+equal the eager result."""
 import numpy as np
 import pytest
 
@@ -60,8 +62,13 @@ def test_batch_forward_equals_single_trees_and_oracle(pops):
         wl = pops[k]
         k += 1
         tree, us = _single(wl)
-        routes.append(tree.plan(float(np.float32(wl.sigma)), p=8)["route"])
-        np.testing.assert_array_equal(u[lo:hi], us)
+        route = tree.plan(float(np.float32(wl.sigma)), p=8)["route"]
+        routes.append(route)
+        if route == "direct":
+            np.testing.assert_array_equal(u[lo:hi], us)   # same P2P kernel body
+        else:
+            # the batched moments are summed in another order (one wavefront per cell)
+            np.testing.assert_allclose(u[lo:hi], us, rtol=2e-5, atol=1e-6 * np.abs(us).max())
         tgt = np.nonzero(wl.a > 0)[0]
         sel = tgt[synth.sample_indices(tgt.size, 24, seed=900 + i)]
         ref = oracle.attraction(wl, sel)
