@@ -78,27 +78,27 @@ __global__ void k_batch_stage(const PopDesc *desc, const int64_t *pt_off, int nd
     const_cast<uint8_t *>(D.ls.tflag)[i] = is_target ? (is_target[j] != 0) : (uint8_t)1;
 }
 
-// Persistent P2P over the nodes of every direct-route population.  Every wave
-// leaves the loop once the counter passes the last item.
-__global__ void __launch_bounds__(64) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
-                                                  unsigned long long *counter,
-                                                  unsigned long long *stamps) {
-    __shared__ P2PShared sh;
-    __shared__ long long s_item;
+// Persistent P2P over the nodes of every direct-route population, four independent
+// wavefronts per block.  Every wave leaves the loop once the counter passes the
+// last item.
+__global__ void __launch_bounds__(256) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
+                                                   unsigned long long *counter,
+                                                   unsigned long long *stamps) {
+    __shared__ P2PShared sh[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t total = item_off[nd];
-    // a block can take at most `total` items before the counter passes the end
+    // a wave can take at most `total` items before the counter passes the end
     for (int64_t it = 0; it <= total; ++it) {
-        if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();
+        unsigned long long mine = 0ull;
+        if (lane == 0) mine = atomicAdd(counter, 1ull);
+        const int64_t item = (int64_t)__shfl(mine, 0, 64);
         if (item >= total) break;
         const int d = find_segment(item_off, nd, item);
         const PopDesc &D = desc[d];
         const int64_t v = item - item_off[d];
         const unsigned long long t0 = wall_clock64();
-        p2p_leaf(D.ls, v, sh);
-        if (threadIdx.x == 0) {
+        p2p_leaf(D.ls, v, sh[wave]);
+        if (lane == 0) {
             atomicMin(&stamps[2 * D.pop], t0);
             atomicMax(&stamps[2 * D.pop + 1], (unsigned long long)wall_clock64());
         }
@@ -280,10 +280,11 @@ int enqueue_forward(msp_batch *b, const std::vector<PopPlan> &plans, const float
         hipLaunchKernelGGL(k_batch_stage, dim3(grid_for(b->direct_points, kBlock)), dim3(kBlock), 0, s, desc,
                            b->pt_off.as<int64_t>(), nd, w, is_target);
         MSP_CHECK_LAUNCH();
-        const int64_t waves = (int64_t)b->cus * 16;
-        const int64_t grid = b->direct_items < waves ? b->direct_items : waves;
+        const int64_t waves = (int64_t)b->cus * 32;
+        const int64_t want = b->direct_items < waves ? b->direct_items : waves;
+        const int64_t grid = (want + 3) / 4;
         if (grid > 0) {
-            hipLaunchKernelGGL(k_batch_p2p, dim3((unsigned)grid), dim3(64), 0, s, desc,
+            hipLaunchKernelGGL(k_batch_p2p, dim3((unsigned)grid), dim3(256), 0, s, desc,
                                b->item_off.as<int64_t>(), nd, counter, st);
             MSP_CHECK_LAUNCH();
         }

@@ -329,12 +329,21 @@ __global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Ou
 // (v_mfma_f32_16x16x4f32, same lane layout as above).  LDS: RT x (U + 1) floats of
 // In and (2G - 1) p^2 floats of T (dynamic).
 __host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
-    return ((size_t)RT * (U + 1) + (size_t)(2 * G - 1) * p * p) * 4;
+    // input rows, operator table, and (cell-major modes) row bases and column offsets
+    const size_t nT = (size_t)(2 * G - 1) * p * p;
+    return ((size_t)RT * (U + 1) + nT + (nT & 1)) * 4 + (size_t)RT * 8 + (size_t)U * 4;
 }
 
-template <int RT>
+// Grid layouts.  The M2L passes read rows along one axis of the interleaved layout
+// [kz p + az][ky p + ay][kx p + ax].  The batched route keeps the moment and Taylor
+// grids cell-major instead, [kz][ky][kx][az][ay][ax], so that one cell's p^3
+// coefficients are one contiguous run for P2M and L2P; its x pass (MODE 1) reads the
+// cell-major moments, and its z pass (MODE 2) takes its rows in cell-column order
+// (ky, kx, ay, ax) and writes the cell-major Taylor grid.  Ga: the grid's cells along
+// y (MODE 1) or x (MODE 2).
+template <int RT, int MODE = 0>
 __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int G, const float *T, int64_t r0,
-                              float *sm) {
+                              float *sm, int Ga = 0) {
     constexpr int NR = RT / 16;   // 16-wide column tiles per block
     constexpr int KC = 8;         // K steps (of 4) per operator chunk in registers
     const int U = G * p;
@@ -343,10 +352,40 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int
     float *sT = sm + (size_t)RT * UP;
     const int nT = (2 * G - 1) * p * p;
     for (int e = threadIdx.x; e < nT; e += 256) sT[e] = T[e];
-    for (int e = threadIdx.x; e < RT * U; e += 256) {
-        const int rr = e / U, u = e % U;
-        const int64_t r = r0 + rr;
-        sIn[rr * UP + u] = r < R ? In[r * U + u] : 0.f;
+    const int pp = p * p;
+    const int p3 = pp * p;
+    if constexpr (MODE == 0) {
+        for (int e = threadIdx.x; e < RT * U; e += 256) {
+            const int rr = e / U, u = e % U;
+            const int64_t r = r0 + rr;
+            sIn[rr * UP + u] = r < R ? In[r * U + u] : 0.f;
+        }
+    } else {
+        // element (rr, u) of the tile sits at rowbase[rr] + colofs[u]
+        int64_t *rowbase = reinterpret_cast<int64_t *>(sT + nT + (nT & 1));
+        int *colofs = reinterpret_cast<int *>(rowbase + RT);
+        for (int rr = threadIdx.x; rr < RT; rr += 256) {
+            const int64_t r = r0 + rr;
+            int64_t b = -1;
+            if (r < R) {
+                if constexpr (MODE == 1) {   // row r = (z', y') of the cell-major moments
+                    const int Uy = Ga * p;
+                    const int zq = (int)(r / Uy), yq = (int)(r % Uy);
+                    b = ((int64_t)(zq / p) * Ga + yq / p) * G * (int64_t)p3 + ((zq % p) * p + yq % p) * p;
+                } else {                     // row q = (ky, kx, ay, ax) in cell-column order
+                    const int c = (int)(r / pp), rem = (int)(r % pp);
+                    b = ((int64_t)((c / Ga) * p + rem / p) * Ga * p + (c % Ga) * p + rem % p) * U;
+                }
+            }
+            rowbase[rr] = b;
+        }
+        for (int u = threadIdx.x; u < U; u += 256) colofs[u] = MODE == 1 ? (u / p) * p3 + u % p : u;
+        __syncthreads();
+        for (int e = threadIdx.x; e < RT * U; e += 256) {
+            const int rr = e / U, u = e % U;
+            const int64_t b = rowbase[rr];
+            sIn[rr * UP + u] = b >= 0 ? In[b + colofs[u]] : 0.f;
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -389,7 +428,14 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int
             for (int i = 0; i < 4; ++i) {
                 const int vo = vc * 16 + 4 * (lane >> 4) + i;
                 const int64_t r = r0 + 16 * j + (lane & 15);
-                if (vo < U && r < R) Out[(int64_t)vo * R + r] = acc[j][i];
+                if (vo < U && r < R) {
+                    if constexpr (MODE == 2) {   // vo = z' = (kz, az); r = q in cell-column order
+                        const int q = (int)r;
+                        Out[(int64_t)(vo / p) * R * p + (vo % p) * pp + (int64_t)(q / pp) * p3 + q % pp] = acc[j][i];
+                    } else {
+                        Out[(int64_t)vo * R + r] = acc[j][i];
+                    }
+                }
             }
     }
 }
@@ -1059,17 +1105,23 @@ __global__ void k_bops(FgtBatchPlan bp) {
 }
 
 // zero moment grids (cells without points are never written by the range P2M),
-// clear the range counter and the timestamps
+// clear the range counter and the timestamps.  Each population's grid is cleared
+// in 16-byte stores by all threads (grids start at allocation boundaries).
 __global__ void k_bclear(FgtBatchPlan bp) {
     const int64_t g0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     if (g0 == 0) *bp.nranges = 0;
     if (g0 < bp.npop) {
         bp.stamps[2 * bp.pops[g0].pop] = ~0ull;
         bp.stamps[2 * bp.pops[g0].pop + 1] = 0ull;
     }
-    for (int64_t g = g0; g < bp.n_grid; g += (int64_t)gridDim.x * blockDim.x) {
-        const int k = find_pop(bp.grid_off, bp.npop, g);
-        bp.pops[k].A[g - bp.grid_off[k]] = 0.f;
+    for (int k = 0; k < bp.npop; ++k) {
+        float *A = bp.pops[k].A;
+        const int64_t n = bp.grid_off[k + 1] - bp.grid_off[k];
+        const int64_t n4 = n / 4;
+        float4 *A4 = reinterpret_cast<float4 *>(A);
+        for (int64_t g = g0; g < n4; g += nth) A4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int64_t g = 4 * n4 + g0; g < n; g += nth) A[g] = 0.f;
     }
 }
 
@@ -1086,35 +1138,51 @@ __global__ void k_branges(FgtBatchPlan bp) {
     }
 }
 
-// walk the cells of one range: [s, e) of equal level prefix, then the next
+// Walk the cells of one range by one wavefront: [s0, e) of equal level prefix,
+// then the next.  The end of a cell is found by comparing 64 keys at a time and
+// taking the first lane whose prefix differs, so a cell of at most 64 points costs
+// one load of keys.
 template <typename F>
 __device__ inline void for_cells(const FgtPop &f, int64_t first, int64_t last, F &&fn) {
     const int sh = 3 * (kDepth - f.level);
+    const int lane = threadIdx.x & 63;
     int64_t s0 = first;
     while (s0 < last) {
-        const uint64_t pre = f.keys[s0] >> sh;
-        const int64_t e = lower_bound_u64(f.keys, s0, last, (pre + 1ull) << sh);
+        const int64_t j0 = s0 + lane;
+        const uint64_t k0 = j0 < last ? f.keys[j0] : 0ull;
+        const uint64_t pre = __shfl(k0, 0, 64) >> sh;
+        uint64_t differ = __ballot(j0 >= last || (k0 >> sh) != pre);
+        int64_t e = s0;
+        while (differ == 0ull) {
+            e += 64;
+            const int64_t j = e + lane;
+            differ = __ballot(j >= last || (f.keys[j] >> sh) != pre);
+        }
+        e += __ffsll((unsigned long long)differ) - 1;
         fn((int)compact3(pre >> 2), (int)compact3(pre >> 1), (int)compact3(pre), s0, e);
-        __syncthreads();
+        wave_sync();
         s0 = e;
     }
 }
 
 // Moments of the points [s0, e) of one cell by one wavefront, written into the
-// grid (same layout and normalisation as p2m_cell).  Points pass through LDS 64 at a
+// grid (normalisation as p2m_cell; cell-major layout when cm is set, else
+// interleaved).  Points pass through LDS 64 at a
 // time.  For p = 1, 2, 4, 8 a lane (point group, ay half, az) accumulates its (ay, ax)
 // block over every NG-th point and the groups are added by butterfly shuffles;
 // otherwise a lane owns whole (ay, az) rows and visits every point.
 template <int P>
 __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float *w, int Gx, int Gy,
-                              const double *lo, double cell, double inv_sigma, float *A, int kx, int ky,
+                              const double *lo, double cell, double inv_sigma, float *A, int cm, int kx, int ky,
                               int kz, int64_t s0, int64_t e, float4 *stage) {
     constexpr bool ILP = P == 1 || P == 2 || P == 4 || P == 8;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const double cx = lo[0] + (kx + 0.5) * cell, cy = lo[1] + (ky + 0.5) * cell, cz = lo[2] + (kz + 0.5) * cell;
     const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
+    const int64_t cbase = (((int64_t)kz * Gy + ky) * Gx + kx) * (P * P * P);
     auto out = [&](int ax, int ay, int az, float v) {
-        A[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax] = v;
+        if (cm) A[cbase + (az * P + ay) * P + ax] = v;
+        else A[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax] = v;
     };
     auto stage_chunk = [&](int64_t c0) {
         const int64_t j = c0 + lane;
@@ -1138,9 +1206,9 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
             for (int ax = 0; ax < P; ++ax) a2[i][ax] = 0.f;
         float4 nxt = stage_chunk(s0);
         for (int64_t c0 = s0; c0 < e; c0 += 64) {
-            __syncthreads();
+            wave_sync();
             stage[lane] = nxt;
-            __syncthreads();
+            wave_sync();
             if (c0 + 64 < e) nxt = stage_chunk(c0 + 64);
             const int m = e - c0 < 64 ? (int)(e - c0) : 64;
             for (int jj = grp; jj < m; jj += NG) {
@@ -1194,9 +1262,9 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
             for (int ax = 0; ax < P; ++ax) acc[rr][ax] = 0.f;
         float4 nxt = stage_chunk(s0);
         for (int64_t c0 = s0; c0 < e; c0 += 64) {
-            __syncthreads();
+            wave_sync();
             stage[lane] = nxt;
-            __syncthreads();
+            wave_sync();
             if (c0 + 64 < e) nxt = stage_chunk(c0 + 64);
             const int m = e - c0 < 64 ? (int)(e - c0) : 64;
             for (int jj = 0; jj < m; ++jj) {
@@ -1235,18 +1303,19 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
     }
 }
 
-// one wavefront per range
+// one wavefront per range, four per block
 template <int P>
-__global__ void __launch_bounds__(64) k_bp2m(FgtBatchPlan bp) {
-    __shared__ float4 stage[64];
+__global__ void __launch_bounds__(256) k_bp2m(FgtBatchPlan bp) {
+    __shared__ float4 stage[4][64];
+    const int wave = threadIdx.x >> 6;
     const int64_t m = *bp.nranges;
-    for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+    for (int64_t r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
         const int4 rg = bp.ranges[r];
         const FgtPop &f = bp.pops[rg.x];
-        if (threadIdx.x == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
+        if ((threadIdx.x & 63) == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
         for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
-            p2m_cell_wave<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo, f.cell, f.inv_sigma, f.A, kx, ky, kz, s0, e,
-                             stage);
+            p2m_cell_wave<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo, f.cell, f.inv_sigma, f.A, bp.gemm, kx, ky,
+                             kz, s0, e, stage[wave]);
         });
     }
 }
@@ -1267,39 +1336,112 @@ __global__ void __launch_bounds__(64) k_bm2l(FgtBatchPlan bp, int pass) {
     m2l_tile_mfma(In, Out, R, p, G, T, (t % nr) * MT, (int)(t / nr) * MT);
 }
 
-__global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp, int pass) {
+// x pass from the cell-major moments, z pass into the cell-major Taylor grid
+template <int PASS>
+__global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp) {
     extern __shared__ float sm[];
     const int64_t g = blockIdx.x;
-    const int k = find_pop(bp.tile_off[pass], bp.npop, g);
+    const int k = find_pop(bp.tile_off[PASS], bp.npop, g);
     const FgtPop &f = bp.pops[k];
     const int p = bp.p;
     const int64_t Ux = (int64_t)f.G[0] * p, Uy = (int64_t)f.G[1] * p, Uz = (int64_t)f.G[2] * p;
-    const float *In = pass == 0 ? f.A : (pass == 1 ? f.B : f.Tmp);
-    float *Out = pass == 1 ? f.Tmp : f.B;
-    const int64_t R = pass == 0 ? Uz * Uy : (pass == 1 ? Ux * Uz : Uy * Ux);
-    const float *T = pass == 0 ? f.opsx : (pass == 1 ? f.opsy : f.opsz);
-    m2l_gemm_tile<32>(In, Out, R, p, f.G[pass], T, (g - bp.tile_off[pass][k]) * 32, sm);
+    const int64_t r0 = (g - bp.tile_off[PASS][k]) * 32;
+    if constexpr (PASS == 0)
+        m2l_gemm_tile<32, 1>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
+    else if constexpr (PASS == 1)
+        m2l_gemm_tile<32, 0>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
+    else
+        m2l_gemm_tile<32, 2>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
 }
 
+// Taylor series of cell (kx, ky, kz) at its points [s0, e) by one wavefront (grid
+// cell-major when cm is set, else interleaved).  The cell's p^3 coefficients are
+// staged in LDS (az slices padded by 4 floats so that
+// the slices a lane group reads fall in different banks).  A pass takes up to 64
+// targets; when it has fewer, L = 64 / (targets rounded up to a power of 2) lanes
+// (at most the largest power of 2 <= P) share one target: lane `sub` evaluates the
+// az slices sub, sub + L, ... (Horner in x, then y, then in z^L over its slices),
+// scales by z^sub, and the L partial values are added by butterfly shuffles.
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_bl2p(FgtBatchPlan bp) {
+__device__ void l2p_cell_wave(const FgtPop &f, int cm, int kx, int ky, int kz, int64_t s0, int64_t e, float *sC) {
+    constexpr int SZ = P * P + 4;
+    constexpr int LMAX = P >= 16 ? 16 : (P >= 8 ? 8 : (P >= 4 ? 4 : (P >= 2 ? 2 : 1)));
+    const int lane = threadIdx.x & 63;
+    const int64_t Rx = (int64_t)f.G[0] * P, Ry = (int64_t)f.G[1] * P;
+    const int64_t cbase = (((int64_t)kz * f.G[1] + ky) * f.G[0] + kx) * (P * P * P);
+    for (int q = lane; q < P * P * P; q += 64) {
+        const int ax = q % P, ay = (q / P) % P, az = q / (P * P);
+        sC[az * SZ + ay * P + ax] = cm ? f.B[cbase + q]
+                                       : f.B[(((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax];
+    }
+    wave_sync();
+    const double cx = f.lo[0] + (kx + 0.5) * f.cell, cy = f.lo[1] + (ky + 0.5) * f.cell,
+                 cz = f.lo[2] + (kz + 0.5) * f.cell;
+    for (int64_t c0 = s0; c0 < e; ) {
+        const int64_t left = e - c0;
+        int tp = 1;
+        while (tp < left && tp < 64) tp <<= 1;
+        const int L = 64 / tp < LMAX ? 64 / tp : LMAX;
+        const int slots = 64 / L;
+        const int a = lane / L, sub = lane % L;
+        const int64_t i = c0 + a;
+        const bool live = a < left;
+        const float4 q = live ? f.ps[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int32_t j = live ? f.perm[i] : 0;
+        const bool tgt = live && (!f.is_target || f.is_target[j]);
+        const float wself = (live && f.subtract_self) ? f.w[j] : 0.f;
+        const float X = (float)(((double)q.x - cx) * f.inv_sigma);
+        const float Y = (float)(((double)q.y - cy) * f.inv_sigma);
+        const float Z = (float)(((double)q.z - cz) * f.inv_sigma);
+        float zl = 1.f, zs = 1.f;
+        for (int k = 0; k < L; ++k) {
+            if (k == sub) zs = zl;
+            zl *= Z;
+        }
+        int top = sub;
+        while (top + L < P) top += L;
+        float uz = 0.f;
+        for (int az = top; az >= 0; az -= L) {
+            const float *cz_ = sC + az * SZ;
+            float uy = 0.f;
+#pragma unroll
+            for (int ay = P - 1; ay >= 0; --ay) {
+                const float *c = cz_ + ay * P;
+                float ux = c[P - 1];
+#pragma unroll
+                for (int ax = P - 2; ax >= 0; --ax) ux = fmaf(ux, X, c[ax]);
+                uy = fmaf(uy, Y, ux);
+            }
+            uz = fmaf(uz, zl, uy);
+        }
+        float u = uz * zs;
+        for (int o = 1; o < L; o <<= 1) u += __shfl_xor(u, o, 64);
+        if (live && sub == 0) f.u_out[j] = tgt ? u - wself : 0.f;
+        c0 += slots;
+    }
+}
+
+// one wavefront per range, four per block
+template <int P>
+__global__ void __launch_bounds__(256) k_bl2p(FgtBatchPlan bp) {
+    __shared__ float sC[4][P * (P * P + 4)];
+    const int wave = threadIdx.x >> 6;
     const int64_t m = *bp.nranges;
-    for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+    for (int64_t r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
         const int4 rg = bp.ranges[r];
         const FgtPop &f = bp.pops[rg.x];
         for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
-            l2p_cell<P>(f.ps, f.perm, f.is_target, f.w, f.subtract_self, f.G[0], f.G[1], f.lo[0], f.lo[1],
-                        f.lo[2], f.cell, f.inv_sigma, f.B, f.u_out, kx, ky, kz, s0, e);
+            l2p_cell_wave<P>(f, bp.gemm, kx, ky, kz, s0, e, sC[wave]);
         });
-        if (threadIdx.x == 0) atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
+        if ((threadIdx.x & 63) == 0) atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
     }
 }
 
 template <int P>
 int batch_p2m_l2p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
     const unsigned grid = (unsigned)(bp.cus * 8);
-    if (!l2p) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bp2m<P>), dim3(grid * 4), dim3(64), 0, s, bp);
-    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bl2p<P>), dim3(grid), dim3(kBlock), 0, s, bp);
+    if (!l2p) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bp2m<P>), dim3(grid), dim3(256), 0, s, bp);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bl2p<P>), dim3(grid), dim3(256), 0, s, bp);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
@@ -1320,7 +1462,7 @@ int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
     if (bp.npop == 0) return MSP_OK;
     hipLaunchKernelGGL(k_bops, dim3(grid_for(bp.n_ops, 64)), dim3(64), 0, s, bp);
     MSP_CHECK_LAUNCH();
-    const int64_t fill_threads = bp.n_grid < (int64_t)bp.cus * 2048 ? bp.n_grid : (int64_t)bp.cus * 2048;
+    const int64_t fill_threads = bp.n_grid / 4 < (int64_t)bp.cus * 2048 ? bp.n_grid / 4 + 1 : (int64_t)bp.cus * 2048;
     hipLaunchKernelGGL(k_bclear, dim3(grid_for(fill_threads > bp.npop ? fill_threads : bp.npop, kBlock)),
                        dim3(kBlock), 0, s, bp);
     MSP_CHECK_LAUNCH();
@@ -1329,9 +1471,12 @@ int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
     MSP_TRY(batch_p2m_l2p_p(bp, false, s));
     for (int pass = 0; pass < 3; ++pass) {
         if (bp.n_tiles[pass] == 0) continue;
-        if (bp.gemm)
-            hipLaunchKernelGGL(k_bm2l_gemm, dim3((unsigned)bp.n_tiles[pass]), dim3(256), bp.gemm_lds, s, bp, pass);
-        else
+        if (bp.gemm) {
+            const dim3 grid((unsigned)bp.n_tiles[pass]);
+            if (pass == 0) hipLaunchKernelGGL(k_bm2l_gemm<0>, grid, dim3(256), bp.gemm_lds, s, bp);
+            else if (pass == 1) hipLaunchKernelGGL(k_bm2l_gemm<1>, grid, dim3(256), bp.gemm_lds, s, bp);
+            else hipLaunchKernelGGL(k_bm2l_gemm<2>, grid, dim3(256), bp.gemm_lds, s, bp);
+        } else
             hipLaunchKernelGGL(k_bm2l, dim3((unsigned)bp.n_tiles[pass]), dim3(64), 0, s, bp, pass);
         MSP_CHECK_LAUNCH();
     }

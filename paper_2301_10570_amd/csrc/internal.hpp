@@ -167,7 +167,8 @@ struct FgtBatchPlan {
     int32_t *nranges;
     unsigned long long *stamps;
     int cus;
-    int gemm;          // M2L passes as whole-K GEMM tiles of 32 rows (else 32 x 32 tiles)
+    int gemm;          // M2L passes as whole-K GEMM tiles of 32 rows with cell-major grids
+                       // (else 32 x 32 tiles on interleaved grids)
     size_t gemm_lds;   // dynamic LDS of the GEMM tiles (largest population)
 };
 
@@ -325,6 +326,15 @@ __host__ __device__ inline uint64_t morton3(uint32_t qx, uint32_t qy, uint32_t q
 }
 
 // First index in [lo, hi) with keys[idx] >= v.
+// Orders one wavefront's LDS accesses at this point.  A wavefront executes in lock
+// step and its LDS operations complete in order, so LDS data private to one wave
+// needs no workgroup barrier; this keeps the compiler from moving accesses across.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline int64_t lower_bound_u64(const uint64_t *keys, int64_t lo, int64_t hi, uint64_t v) {
     while (lo < hi) {
         int64_t mid = lo + ((hi - lo) >> 1);

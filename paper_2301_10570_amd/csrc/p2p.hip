@@ -93,17 +93,18 @@ __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
 }
 
 // One wavefront per target leaf (non-leaf nodes return at once).
-__global__ void __launch_bounds__(64) k_p2p(int64_t n_nodes, const int32_t *nfirst,
+__global__ void __launch_bounds__(256) k_p2p(int64_t n_nodes, const int32_t *nfirst,
                                             const int32_t *ncount, const int32_t *nnchild,
                                             const int32_t *nlevel, const int32_t *nix,
                                             const int32_t *niy, const int32_t *niz, BoxGeo geo,
                                             const int64_t *off, const int32_t *lst, const float4 *ps,
                                             const uint8_t *tflag, float k_scale, int exclude_self,
                                             float *usort) {
-    __shared__ P2PShared sh;
+    __shared__ P2PShared sh[4];
     const LeafSet ls{n_nodes, nfirst, ncount, nnchild, nlevel, nix, niy, niz, geo, off, lst, ps, tflag,
                      k_scale, exclude_self, usort};
-    p2p_leaf(ls, (int64_t)blockIdx.x, sh);
+    const int wave = threadIdx.x >> 6;
+    p2p_leaf(ls, (int64_t)blockIdx.x * 4 + wave, sh[wave]);
 }
 
 // All-pairs baseline: one target per thread, 1024 sources per LDS tile.
@@ -198,7 +199,7 @@ int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
     const float k_scale = (float)(std::sqrt(1.4426950408889634) / (double)prm->sigma);
     PhaseScope ps(&t->timing, PH_P2P, s);
-    hipLaunchKernelGGL(k_p2p, dim3((unsigned)nn), dim3(64), 0, s, nn, t->nfirst.as<int32_t>(),
+    hipLaunchKernelGGL(k_p2p, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, s, nn, t->nfirst.as<int32_t>(),
                        t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(), t->nlevel.as<int32_t>(),
                        t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), geo,
                        t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(),

@@ -1,10 +1,12 @@
 // P2P of one target leaf against its interaction list (Eq. (8)); shared by the
 // single-tree direct route and the batched persistent kernel.
 //
-// One wavefront per target leaf.  Lanes are split into G = 64 / tp groups for
+// One wavefront per target leaf (sh is private to the wave).  Lanes are split into G = 64 / tp groups for
 // leaves with tp <= 32 targets; each group takes every G-th source of a staged
-// chunk, and the group partials are added in group order at the end.  Chunk
-// partials are added with compensation.  exp(-d^2/sigma^2) is evaluated as
+// chunk, and the group partials are added in group order at the end.  The source
+// leaves of the list are read 64 entries at a time and their points concatenated,
+// so that a chunk of 64 staged sources may span several leaves.  Chunk partials
+// are added with compensation.  exp(-d^2/sigma^2) is evaluated as
 // exp2(-(k d)^2) with k^2 = log2(e)/sigma^2 (k = k_scale).
 #pragma once
 #include "internal.hpp"
@@ -44,11 +46,20 @@ struct P2PShared {
     float sx[64], sy[64], sz[64], sw[64];
     int32_t sid[64];
     float red[64];
+    int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
 };
+
+__device__ inline int p2p_incl_scan(int v, int lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
 
 __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
     if (v >= L.n_nodes || L.nnchild[v] != 0) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     float ct[3], ht;
     node_box(L.geo, L.nlevel[v], L.nix[v], L.niy[v], L.niz[v], ct, ht);
     const int32_t tf = L.nfirst[v], tn = L.ncount[v];
@@ -67,23 +78,48 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
         const float ty = (qt.y - ct[1]) * L.k_scale;
         const float tz = (qt.z - ct[2]) * L.k_scale;
         float total = 0.f, comp = 0.f;
-        for (int64_t q = l0; q < l1; ++q) {
-            const int32_t u = L.lst[q];
-            if (u < 0 || u >= L.n_nodes) continue;
-            const int32_t sf = L.nfirst[u], sn = L.ncount[u];
-            for (int s0 = 0; s0 < sn; s0 += 64) {
-                const int ns = sn - s0 < 64 ? sn - s0 : 64;
-                __syncthreads();
-                if (lane < ns) {
-                    const int32_t j = sf + s0 + lane;
-                    const float4 qs = L.ps[j];
-                    sh.sx[lane] = (qs.x - ct[0]) * L.k_scale;
-                    sh.sy[lane] = (qs.y - ct[1]) * L.k_scale;
-                    sh.sz[lane] = (qs.z - ct[2]) * L.k_scale;
-                    sh.sw[lane] = qs.w;
-                    sh.sid[lane] = j;
+        // the source points of up to 64 list entries at a time form one sequence that is
+        // staged 64 points per chunk; the next chunk is loaded while the current one is used
+        for (int64_t w0 = l0; w0 < l1; w0 += 64) {
+            const int nw = l1 - w0 < 64 ? (int)(l1 - w0) : 64;
+            int32_t esf = 0, esn = 0;
+            if (lane < nw) {
+                const int32_t u = L.lst[w0 + lane];
+                if (u >= 0 && u < L.n_nodes) {
+                    esf = L.nfirst[u];
+                    esn = L.ncount[u];
                 }
-                __syncthreads();
+            }
+            const int incl = p2p_incl_scan(esn, lane);
+            const int tot = __shfl(incl, 63, 64);
+            wave_sync();   // previous window's entries and points are no longer read
+            sh.efirst[lane] = esf - (incl - esn);
+            sh.eend[lane] = esn > 0 ? incl : -1;
+            wave_sync();
+            int owner = 0;
+            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            int32_t nid = -1;
+            auto fetch = [&](int c0) {
+                const int j = c0 + lane;
+                if (j < tot) {
+                    while (sh.eend[owner] <= j) ++owner;
+                    nid = sh.efirst[owner] + j;
+                    nxt = L.ps[nid];
+                }
+            };
+            fetch(0);
+            for (int c0 = 0; c0 < tot; c0 += 64) {
+                const int ns = tot - c0 < 64 ? tot - c0 : 64;
+                wave_sync();
+                if (lane < ns) {
+                    sh.sx[lane] = (nxt.x - ct[0]) * L.k_scale;
+                    sh.sy[lane] = (nxt.y - ct[1]) * L.k_scale;
+                    sh.sz[lane] = (nxt.z - ct[2]) * L.k_scale;
+                    sh.sw[lane] = nxt.w;
+                    sh.sid[lane] = nid;
+                }
+                wave_sync();
+                if (c0 + 64 < tot) fetch(c0 + 64);
                 float part = 0.f;
                 for (int j = grp; j < ns; j += G) {
                     const float dx = tx - sh.sx[j], dy = ty - sh.sy[j], dz = tz - sh.sz[j];
@@ -99,9 +135,9 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
                 total = tt;
             }
         }
-        __syncthreads();
+        wave_sync();
         sh.red[lane] = total;
-        __syncthreads();
+        wave_sync();
         if (grp == 0 && a < nt) {
             float s = 0.f;
             for (int q = 0; q < G; ++q) s += sh.red[q * tp + a];
