@@ -79,28 +79,43 @@ __global__ void k_batch_stage(const PopDesc *desc, const int64_t *pt_off, int nd
 }
 
 // Persistent P2P over the nodes of every direct-route population, four independent
-// wavefronts per block.  Every wave leaves the loop once the counter passes the
-// last item.
+// wavefronts per block.  A wave takes kP2PTake consecutive items per atomic addition
+// on the shared counter (one item balances the load best: leaves differ widely in
+// work) and leaves the loop once the counter passes the last item; population
+// timestamps are recorded once per run of items of one population.
+constexpr int kP2PTake = 1;
 __global__ void __launch_bounds__(256) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
                                                    unsigned long long *counter,
                                                    unsigned long long *stamps) {
     __shared__ P2PShared sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t total = item_off[nd];
-    // a wave can take at most `total` items before the counter passes the end
+    // a wave can take at most `total` batches before the counter passes the end
     for (int64_t it = 0; it <= total; ++it) {
         unsigned long long mine = 0ull;
-        if (lane == 0) mine = atomicAdd(counter, 1ull);
-        const int64_t item = (int64_t)__shfl(mine, 0, 64);
-        if (item >= total) break;
-        const int d = find_segment(item_off, nd, item);
-        const PopDesc &D = desc[d];
-        const int64_t v = item - item_off[d];
-        const unsigned long long t0 = wall_clock64();
-        p2p_leaf(D.ls, v, sh[wave]);
+        if (lane == 0) mine = atomicAdd(counter, (unsigned long long)kP2PTake);
+        const int64_t first = (int64_t)__shfl(mine, 0, 64);
+        if (first >= total) break;
+        const int64_t last = first + kP2PTake < total ? first + kP2PTake : total;
+        int pop = -1;
+        unsigned long long t_first = 0ull;
+        for (int64_t item = first; item < last; ++item) {
+            const int d = find_segment(item_off, nd, item);
+            const PopDesc &D = desc[d];
+            const unsigned long long t0 = wall_clock64();
+            if (D.pop != pop) {
+                if (pop >= 0 && lane == 0) {
+                    atomicMin(&stamps[2 * pop], t_first);
+                    atomicMax(&stamps[2 * pop + 1], (unsigned long long)wall_clock64());
+                }
+                pop = D.pop;
+                t_first = t0;
+            }
+            p2p_leaf(D.ls, item - item_off[d], sh[wave]);
+        }
         if (lane == 0) {
-            atomicMin(&stamps[2 * D.pop], t0);
-            atomicMax(&stamps[2 * D.pop + 1], (unsigned long long)wall_clock64());
+            atomicMin(&stamps[2 * pop], t_first);
+            atomicMax(&stamps[2 * pop + 1], (unsigned long long)wall_clock64());
         }
     }
 }
@@ -148,7 +163,8 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
     std::vector<int64_t> poff{0}, ioff{0};
     // expansion-route populations: descriptors and prefix sums for the batched passes
     std::vector<FgtPop> fp;
-    std::vector<int64_t> ops_off{0}, node_off{0}, grid_off{0}, tile_off[3] = {{0}, {0}, {0}};
+    std::vector<int64_t> ops_off{0}, pw_off{0}, grid_off{0}, tile_off[3] = {{0}, {0}, {0}};
+    int64_t n_pts = 0;
     int p = 0;
     for (int k = 0; k < b->npop; ++k) {
         msp_tree *t = b->pops[k].get();
@@ -164,7 +180,8 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
         p = pp.pl.p;
         fp.push_back(f);
         ops_off.push_back(ops_off.back() + 2 * (f.G[0] + f.G[1] + f.G[2]) - 3);
-        node_off.push_back(node_off.back() + t->n_nodes);
+        pw_off.push_back(pw_off.back() + (t->n + 63) / 64);
+        n_pts += t->n;
         grid_off.push_back(grid_off.back() + (int64_t)f.G[0] * f.G[1] * f.G[2] * p * p * p);
     }
     // M2L as whole-K GEMM tiles when every population's operator and tile fit in LDS
@@ -180,7 +197,7 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
     const int nf = (int)fp.size();
     MSP_TRY(b->fdesc.ensure((fp.size() + 1) * sizeof(FgtPop)));
     MSP_TRY(b->foff.ensure((size_t)6 * (nf + 1) * 8));
-    MSP_TRY(b->franges.ensure((size_t)(node_off.back() + 1) * sizeof(int4) + 16));
+    MSP_TRY(b->franges.ensure((size_t)(n_pts + 1) * sizeof(int4) + 16));
     for (int k = 0; k < b->npop; ++k) {
         msp_tree *t = b->pops[k].get();
         const PopPlan &pp = plans[k];
@@ -236,22 +253,23 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
     if (nf > 0) {
         MSP_HIP(hipMemcpy(b->fdesc.p, fp.data(), fp.size() * sizeof(FgtPop), hipMemcpyHostToDevice));
         int64_t *off = b->foff.as<int64_t>();
-        const std::vector<int64_t> *arrs[6] = {&ops_off, &node_off, &grid_off, &tile_off[0], &tile_off[1], &tile_off[2]};
+        const std::vector<int64_t> *arrs[6] = {&ops_off, &pw_off, &grid_off, &tile_off[0], &tile_off[1], &tile_off[2]};
         for (int a = 0; a < 6; ++a)
             MSP_HIP(hipMemcpy(off + (size_t)a * (nf + 1), arrs[a]->data(), (size_t)(nf + 1) * 8, hipMemcpyHostToDevice));
         bp.pops = b->fdesc.as<FgtPop>();
         bp.ops_off = off;
-        bp.node_off = off + (nf + 1);
+        bp.pw_off = off + (nf + 1);
         bp.grid_off = off + 2 * (nf + 1);
         for (int pass = 0; pass < 3; ++pass) {
             bp.tile_off[pass] = off + (size_t)(3 + pass) * (nf + 1);
             bp.n_tiles[pass] = tile_off[pass].back();
         }
         bp.n_ops = ops_off.back();
-        bp.n_nodes = node_off.back();
+        bp.n_pw = pw_off.back();
         bp.n_grid = grid_off.back();
-        bp.nranges = reinterpret_cast<int32_t *>(b->franges.as<int4>() + node_off.back());
-        bp.ranges = b->franges.as<int4>();
+        bp.cap = n_pts + 1;   // a cell holds at least one point
+        bp.cells = b->franges.as<int4>();
+        bp.ncells = reinterpret_cast<int32_t *>(b->franges.as<int4>() + bp.cap);
         bp.stamps = b->stamps.as<unsigned long long>();
     }
     return MSP_OK;

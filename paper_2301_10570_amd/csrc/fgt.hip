@@ -54,6 +54,9 @@ static size_t two_level_lds(int p, int pf) {
 namespace {
 
 constexpr int kBlock = 256;
+// batched expansion route: cells of at most this many points are processed eight
+// to a wavefront (p <= 8)
+constexpr int kSmallCell = 32;
 
 // T_k[o][b][a] = (-1)^b / b! * h_{a+b}(o * step), o = -(G_k-1) .. G_k-1, for the three
 // axes in one launch (thread -> axis, offset); computed in float64, stored as float32.
@@ -1104,13 +1107,16 @@ __global__ void k_bops(FgtBatchPlan bp) {
     m2l_ops_one(bp.p, f.G[0], f.G[1], f.G[2], f.step, f.opsx, f.opsy, f.opsz, (int)(g - bp.ops_off[k]));
 }
 
-// zero moment grids (cells without points are never written by the range P2M),
-// clear the range counter and the timestamps.  Each population's grid is cleared
+// zero moment grids (cells without points are never written by the P2M), clear
+// the cell counters and the timestamps.  Each population's grid is cleared
 // in 16-byte stores by all threads (grids start at allocation boundaries).
 __global__ void k_bclear(FgtBatchPlan bp) {
     const int64_t g0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    if (g0 == 0) *bp.nranges = 0;
+    if (g0 == 0) {
+        bp.ncells[0] = 0;
+        bp.ncells[1] = 0;
+    }
     if (g0 < bp.npop) {
         bp.stamps[2 * bp.pops[g0].pop] = ~0ull;
         bp.stamps[2 * bp.pops[g0].pop + 1] = 0ull;
@@ -1125,44 +1131,102 @@ __global__ void k_bclear(FgtBatchPlan bp) {
     }
 }
 
-__global__ void k_branges(FgtBatchPlan bp) {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= bp.n_nodes) return;
-    const int k = find_pop(bp.node_off, bp.npop, g);
-    const FgtPop &f = bp.pops[k];
-    const int64_t v = g - bp.node_off[k];
-    const int l = f.nlevel[v];
-    if (l == f.level || (l < f.level && f.nnchild[v] == 0)) {
-        const int32_t c = f.ncount[v];
-        if (c > 0) bp.ranges[atomicAdd(bp.nranges, 1)] = make_int4(k, f.nfirst[v], c, 0);
+// Occupied cells of every population.  A window is 64 consecutive points (key
+// order) of one population, one point per lane: a lane whose point starts a cell
+// (its level prefix differs from the previous point's) ends it at the next lane that
+// starts a cell or lies past the population; the cell that runs past the window is
+// followed 64 keys at a time.  Cells of at most cmax points go to the front of the
+// list, larger ones to the back, as (population, first point, points, cell index).
+// A wavefront takes kCellWin consecutive windows and makes one atomic addition per
+// list for all of them (additions on one address are serialised by the memory
+// system).
+constexpr int kCellWin = 16;
+__global__ void __launch_bounds__(256) k_bcells(FgtBatchPlan bp, int cmax) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCellWin;
+    if (w0 >= bp.n_pw) return;   // whole wavefronts
+    int4 cw[kCellWin];
+    uint64_t msw[kCellWin], mbw[kCellWin];
+    int ns = 0, nb = 0;
+#pragma unroll
+    for (int q = 0; q < kCellWin; ++q) {
+        const int64_t wv = w0 + q;
+        bool emit = false, small = false;
+        cw[q] = make_int4(0, 0, 0, 0);
+        if (wv < bp.n_pw) {
+            const int k = find_pop(bp.pw_off, bp.npop, wv);
+            const FgtPop &f = bp.pops[k];
+            const int sh = 3 * (kDepth - f.level);
+            const int64_t base = (wv - bp.pw_off[k]) * 64, i = base + lane;
+            const bool in = i < f.n;
+            const uint64_t pre = in ? f.keys[i] >> sh : 0ull;
+            uint64_t prev = __shfl_up(pre, 1, 64);
+            if (lane == 0) prev = base > 0 ? f.keys[base - 1] >> sh : ~0ull;
+            const bool start = in && (i == 0 || prev != pre);
+            const uint64_t bound = __ballot(start || !in);
+            const uint64_t starts = __ballot(start);
+            if (starts) {
+                // end of the cell of the last starting lane, when it runs past the window
+                const int last = 63 - __clzll(starts);
+                const uint64_t after = last < 63 ? (bound >> (last + 1)) : 0ull;
+                int64_t tail = -1;
+                if (after == 0ull) {
+                    const uint64_t lp = __shfl(pre, last, 64);
+                    int64_t e0 = base + 64;
+                    for (;;) {
+                        const int64_t j = e0 + lane;
+                        const uint64_t m = __ballot(j >= f.n || (f.keys[j] >> sh) != lp);
+                        if (m) {
+                            tail = e0 + __ffsll((unsigned long long)m) - 1;
+                            break;
+                        }
+                        e0 += 64;
+                    }
+                }
+                if (start) {
+                    const uint64_t nxb = lane < 63 ? (bound >> (lane + 1)) : 0ull;
+                    const int64_t e = nxb ? i + __ffsll((unsigned long long)nxb) : tail;
+                    const int kx = (int)compact3(pre >> 2), ky = (int)compact3(pre >> 1), kz = (int)compact3(pre);
+                    cw[q] = make_int4(k, (int)i, (int)(e - i), (kz * f.G[1] + ky) * f.G[0] + kx);
+                    emit = true;
+                    small = e - i <= cmax;
+                }
+            }
+        }
+        msw[q] = __ballot(emit && small);
+        mbw[q] = __ballot(emit && !small);
+        ns += (int)__popcll(msw[q]);
+        nb += (int)__popcll(mbw[q]);
+    }
+    int bs = 0, bb = 0;
+    if (lane == 0) {
+        if (ns) bs = atomicAdd(&bp.ncells[0], ns);
+        if (nb) bb = atomicAdd(&bp.ncells[1], nb);
+    }
+    bs = __shfl(bs, 0, 64);
+    bb = __shfl(bb, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < kCellWin; ++q) {
+        if ((msw[q] >> lane) & 1ull) bp.cells[bs + __popcll(msw[q] & below)] = cw[q];
+        if ((mbw[q] >> lane) & 1ull) bp.cells[bp.cap - 1 - (bb + __popcll(mbw[q] & below))] = cw[q];
+        bs += (int)__popcll(msw[q]);
+        bb += (int)__popcll(mbw[q]);
     }
 }
 
-// Walk the cells of one range by one wavefront: [s0, e) of equal level prefix,
-// then the next.  The end of a cell is found by comparing 64 keys at a time and
-// taking the first lane whose prefix differs, so a cell of at most 64 points costs
-// one load of keys.
-template <typename F>
-__device__ inline void for_cells(const FgtPop &f, int64_t first, int64_t last, F &&fn) {
-    const int sh = 3 * (kDepth - f.level);
-    const int lane = threadIdx.x & 63;
-    int64_t s0 = first;
-    while (s0 < last) {
-        const int64_t j0 = s0 + lane;
-        const uint64_t k0 = j0 < last ? f.keys[j0] : 0ull;
-        const uint64_t pre = __shfl(k0, 0, 64) >> sh;
-        uint64_t differ = __ballot(j0 >= last || (k0 >> sh) != pre);
-        int64_t e = s0;
-        while (differ == 0ull) {
-            e += 64;
-            const int64_t j = e + lane;
-            differ = __ballot(j >= last || (f.keys[j] >> sh) != pre);
-        }
-        e += __ffsll((unsigned long long)differ) - 1;
-        fn((int)compact3(pre >> 2), (int)compact3(pre >> 1), (int)compact3(pre), s0, e);
-        wave_sync();
-        s0 = e;
-    }
+__device__ inline void cell_coords(const FgtPop &f, int cidx, int &kx, int &ky, int &kz) {
+    kx = cidx % f.G[0];
+    ky = (cidx / f.G[0]) % f.G[1];
+    kz = cidx / (f.G[0] * f.G[1]);
+}
+
+// index of coefficient (ax, ay, az) of cell (kx, ky, kz): cell-major or interleaved
+template <int P>
+__device__ inline int64_t grid_index(const FgtPop &f, int cm, int kx, int ky, int kz, int ax, int ay, int az) {
+    if (cm) return ((((int64_t)kz * f.G[1] + ky) * f.G[0] + kx) * P + az) * (P * P) + ay * P + ax;
+    const int64_t Rx = (int64_t)f.G[0] * P, Ry = (int64_t)f.G[1] * P;
+    return (((int64_t)kz * P + az) * Ry + (int64_t)ky * P + ay) * Rx + (int64_t)kx * P + ax;
 }
 
 // Moments of the points [s0, e) of one cell by one wavefront, written into the
@@ -1248,8 +1312,21 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
 #pragma unroll
                 for (int ax = 0; ax < P; ++ax) {
                     if (ax > 1) fx *= (float)ax;
-                    out(ax, ay, az, a2[i][ax] / (fx * fy * fz));
+                    a2[i][ax] = a2[i][ax] / (fx * fy * fz);
                 }
+            }
+            if (P == 8 && cm) {   // this lane's (ay, ax) block is 32 consecutive floats
+                float4 *o = reinterpret_cast<float4 *>(A + cbase + az * 64 + ah * 32);
+#pragma unroll
+                for (int i = 0; i < AY; ++i)
+#pragma unroll
+                    for (int h = 0; h < P / 4; ++h)
+                        o[i * (P / 4) + h] = make_float4(a2[i][4 * h], a2[i][4 * h + 1], a2[i][4 * h + 2], a2[i][4 * h + 3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < AY; ++i)
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) out(ax, ah * AY + i, az, a2[i][ax]);
             }
         }
     } else {
@@ -1303,20 +1380,149 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
     }
 }
 
-// one wavefront per range, four per block
+// Small cells, eight per wavefront: lane group grp = lane / 8 takes cell r0 + grp,
+// whose points pass through LDS eight at a time (zero weight past the end of the
+// cell, which adds exact zeros; the next eight are loaded while the current ones
+// are used), and each of its eight lanes accumulates a share of the p^3 moments over
+// the cell's points in order.  For p = 8 the share of lane sub is the set of 16-byte
+// chunks k * 8 + sub (k = 0 .. 15) of the cell-major coefficient block (az = k / 2,
+// ay = 4 (k % 2) + sub / 2, ax = 4 (sub % 2) + e), so that every store of the group
+// covers one whole 128-byte line; otherwise lane sub takes slice az = sub.  P <= 8.
+template <int P>
+__device__ void p2m_cells_group(const FgtBatchPlan &bp, int64_t r0, int64_t nsmall, float4 *stage) {
+    const int lane = threadIdx.x & 63, grp = lane >> 3, sub = lane & 7;
+    const int64_t r = r0 + grp;
+    const bool has = r < nsmall;
+    const int4 c = has ? bp.cells[r] : make_int4(0, 0, 0, 0);
+    const FgtPop &f = bp.pops[c.x];
+    if (has && sub == 0 && c.y == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
+    int kx = 0, ky = 0, kz = 0;
+    if (has) cell_coords(f, c.w, kx, ky, kz);
+    const double cx = f.lo[0] + (kx + 0.5) * f.cell, cy = f.lo[1] + (ky + 0.5) * f.cell,
+                 cz = f.lo[2] + (kz + 0.5) * f.cell;
+    const int cnt = has ? c.z : 0;
+    int mx = cnt;
+    for (int o = 8; o < 64; o <<= 1) {
+        const int t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    auto fetch = [&](int c0) {
+        const int j = c0 + sub;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < cnt) {
+            const float4 t = f.ps[c.y + j];
+            q = make_float4((float)(((double)t.x - cx) * f.inv_sigma), (float)(((double)t.y - cy) * f.inv_sigma),
+                            (float)(((double)t.z - cz) * f.inv_sigma), f.w[f.perm[c.y + j]]);
+        }
+        return q;
+    };
+    constexpr bool CH = P == 8;
+    constexpr int NA = CH ? 16 : P, NB = CH ? 4 : P;
+    float acc[NA][NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = 0.f;
+    const int ya = sub >> 1, xodd = sub & 1;
+    float4 nxt = fetch(0);
+    for (int c0 = 0; c0 < mx; c0 += 8) {
+        wave_sync();
+        stage[lane] = nxt;
+        wave_sync();
+        if (c0 + 8 < mx) nxt = fetch(c0 + 8);
+#pragma unroll 2
+        for (int t = 0; t < 8; ++t) {
+            const float4 q = stage[grp * 8 + t];
+            if constexpr (CH) {
+                const float x2 = q.x * q.x, y2 = q.y * q.y;
+                const float x0 = xodd ? x2 * x2 : 1.f;
+                float y0 = 1.f;
+                for (int k = 0; k < ya; ++k) y0 *= q.y;
+                const float y1 = y0 * (y2 * y2);
+                const float xp[4] = {x0, x0 * q.x, x0 * x2, x0 * x2 * q.x};
+                float zp = q.w;
+#pragma unroll
+                for (int az = 0; az < 8; ++az) {
+                    const float f0 = zp * y0, f1 = zp * y1;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        acc[2 * az][e] = fmaf(f0, xp[e], acc[2 * az][e]);
+                        acc[2 * az + 1][e] = fmaf(f1, xp[e], acc[2 * az + 1][e]);
+                    }
+                    zp *= q.z;
+                }
+            } else {
+                float wz = q.w;
+                for (int k = 0; k < sub; ++k) wz *= q.z;
+                float yp[P], xp[P];
+                yp[0] = wz;
+                xp[0] = 1.f;
+#pragma unroll
+                for (int k = 1; k < P; ++k) {
+                    yp[k] = yp[k - 1] * q.y;
+                    xp[k] = xp[k - 1] * q.x;
+                }
+#pragma unroll
+                for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+                    for (int ax = 0; ax < P; ++ax) acc[ay][ax] = fmaf(yp[ay], xp[ax], acc[ay][ax]);
+            }
+        }
+    }
+    if (!has) return;
+    auto fact = [](int m) {
+        float v = 1.f;
+        for (int k = 2; k <= m; ++k) v *= (float)k;
+        return v;
+    };
+    if constexpr (CH) {
+        const float fx[4] = {fact(4 * xodd), fact(4 * xodd + 1), fact(4 * xodd + 2), fact(4 * xodd + 3)};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int az = k >> 1, ay = 4 * (k & 1) + ya;
+            const float fyz = fact(ay) * fact(az);
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = acc[k][e] / (fx[e] * fyz);
+            if (bp.gemm) {
+                *reinterpret_cast<float4 *>(f.A + (int64_t)c.w * 512 + (k * 8 + sub) * 4) =
+                    make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) f.A[grid_index<P>(f, 0, kx, ky, kz, 4 * xodd + e, ay, az)] = v[e];
+            }
+        }
+    } else {
+        if (sub >= P) return;
+        const float fz = fact(sub);
+#pragma unroll
+        for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < P; ++ax)
+                f.A[grid_index<P>(f, bp.gemm, kx, ky, kz, ax, ay, sub)] = acc[ay][ax] / (fact(ax) * fact(ay) * fz);
+    }
+}
+
+// P2M over the cell list: large cells one per wavefront, then small cells eight per
+// wavefront (four wavefronts per block, each on its own cells).
 template <int P>
 __global__ void __launch_bounds__(256) k_bp2m(FgtBatchPlan bp) {
     __shared__ float4 stage[4][64];
-    const int wave = threadIdx.x >> 6;
-    const int64_t m = *bp.nranges;
-    for (int64_t r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
-        const int4 rg = bp.ranges[r];
-        const FgtPop &f = bp.pops[rg.x];
-        if ((threadIdx.x & 63) == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
-        for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
-            p2m_cell_wave<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo, f.cell, f.inv_sigma, f.A, bp.gemm, kx, ky,
-                             kz, s0, e, stage[wave]);
-        });
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + wave, nw = (int64_t)gridDim.x * 4;
+    const int64_t nsmall = bp.ncells[0], nbig = bp.ncells[1];
+    for (int64_t r = wid; r < nbig; r += nw) {
+        const int4 c = bp.cells[bp.cap - 1 - r];
+        const FgtPop &f = bp.pops[c.x];
+        if (lane == 0 && c.y == 0) atomicMin(&bp.stamps[2 * f.pop], (unsigned long long)wall_clock64());
+        int kx, ky, kz;
+        cell_coords(f, c.w, kx, ky, kz);
+        p2m_cell_wave<P>(f.ps, f.perm, f.w, f.G[0], f.G[1], f.lo, f.cell, f.inv_sigma, f.A, bp.gemm, kx, ky, kz,
+                         c.y, (int64_t)c.y + c.z, stage[wave]);
+        wave_sync();
+    }
+    if constexpr (P <= 8) {
+        for (int64_t r0 = wid * 8; r0 < nsmall; r0 += nw * 8) p2m_cells_group<P>(bp, r0, nsmall, stage[wave]);
     }
 }
 
@@ -1421,19 +1627,152 @@ __device__ void l2p_cell_wave(const FgtPop &f, int cm, int kx, int ky, int kz, i
     }
 }
 
-// one wavefront per range, four per block
+// Small cells, eight per wavefront: lane group grp = lane / 8 takes cell r0 + grp;
+// its eight lanes hold shares of the cell's Taylor coefficients in registers (the
+// same shares as the grouped P2M: for p = 8 the 16-byte chunks k * 8 + sub, read
+// one 128-byte line per group and load; otherwise slice az = sub), each evaluates
+// its share at every target of the cell (Horner in x within a chunk, then over az
+// in z), and the eight values are added by butterfly shuffles.  Targets pass
+// through LDS eight per group at a time; the lane that loaded a target also holds
+// its output index, flag and self weight and writes its value.  P <= 8.
+template <int P>
+__device__ void l2p_cells_group(const FgtBatchPlan &bp, int64_t r0, int64_t nsmall, float4 *stage) {
+    const int lane = threadIdx.x & 63, grp = lane >> 3, sub = lane & 7;
+    const int64_t r = r0 + grp;
+    const bool has = r < nsmall;
+    const int4 c = has ? bp.cells[r] : make_int4(0, 0, 0, 0);
+    const FgtPop &f = bp.pops[c.x];
+    int kx = 0, ky = 0, kz = 0;
+    if (has) cell_coords(f, c.w, kx, ky, kz);
+    constexpr bool CH = P == 8;
+    constexpr int NA = CH ? 16 : P, NB = CH ? 4 : P;
+    const int ya = sub >> 1, xodd = sub & 1;
+    float cf[NA][NB];
+    if constexpr (CH) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (has && bp.gemm) {
+                v = *reinterpret_cast<const float4 *>(f.B + (int64_t)c.w * 512 + (k * 8 + sub) * 4);
+            } else if (has) {
+                const int az = k >> 1, ay = 4 * (k & 1) + ya;
+                v = make_float4(f.B[grid_index<P>(f, 0, kx, ky, kz, 4 * xodd, ay, az)],
+                                f.B[grid_index<P>(f, 0, kx, ky, kz, 4 * xodd + 1, ay, az)],
+                                f.B[grid_index<P>(f, 0, kx, ky, kz, 4 * xodd + 2, ay, az)],
+                                f.B[grid_index<P>(f, 0, kx, ky, kz, 4 * xodd + 3, ay, az)]);
+            }
+            cf[k][0] = v.x;
+            cf[k][1] = v.y;
+            cf[k][2] = v.z;
+            cf[k][3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int ay = 0; ay < P; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < P; ++ax)
+                cf[ay][ax] = (has && sub < P) ? f.B[grid_index<P>(f, bp.gemm, kx, ky, kz, ax, ay, sub)] : 0.f;
+    }
+    const double cx = f.lo[0] + (kx + 0.5) * f.cell, cy = f.lo[1] + (ky + 0.5) * f.cell,
+                 cz = f.lo[2] + (kz + 0.5) * f.cell;
+    const int cnt = has ? c.z : 0;
+    int mx = cnt;
+    for (int o = 8; o < 64; o <<= 1) {
+        const int t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    // this lane's target of a chunk: position (in sigma, from the centre), output
+    // index (-1: none), flag and self weight
+    struct Tgt {
+        float4 q;
+        int32_t j;
+        bool t;
+        float ws;
+    };
+    auto fetch = [&](int c0) {
+        Tgt g{make_float4(0.f, 0.f, 0.f, 0.f), -1, false, 0.f};
+        const int jj = c0 + sub;
+        if (jj < cnt) {
+            const float4 t = f.ps[c.y + jj];
+            g.q = make_float4((float)(((double)t.x - cx) * f.inv_sigma), (float)(((double)t.y - cy) * f.inv_sigma),
+                              (float)(((double)t.z - cz) * f.inv_sigma), 0.f);
+            g.j = f.perm[c.y + jj];
+            g.t = !f.is_target || f.is_target[g.j];
+            g.ws = f.subtract_self ? f.w[g.j] : 0.f;
+        }
+        return g;
+    };
+    Tgt cur, nxt = fetch(0);
+    for (int c0 = 0; c0 < mx; c0 += 8) {
+        cur = nxt;
+        wave_sync();
+        stage[lane] = cur.q;
+        wave_sync();
+        if (c0 + 8 < mx) nxt = fetch(c0 + 8);
+#pragma unroll 2
+        for (int t = 0; t < 8; ++t) {
+            const float4 q = stage[grp * 8 + t];
+            float v;
+            if constexpr (CH) {
+                const float x2 = q.x * q.x, y2 = q.y * q.y;
+                const float y4 = y2 * y2;
+                float s = 0.f;
+#pragma unroll
+                for (int az = 7; az >= 0; --az) {
+                    const float *c0p = cf[2 * az], *c1p = cf[2 * az + 1];
+                    const float h0 = fmaf(fmaf(fmaf(c0p[3], q.x, c0p[2]), q.x, c0p[1]), q.x, c0p[0]);
+                    const float h1 = fmaf(fmaf(fmaf(c1p[3], q.x, c1p[2]), q.x, c1p[1]), q.x, c1p[0]);
+                    s = fmaf(s, q.z, fmaf(y4, h1, h0));
+                }
+                float hy = 1.f;
+                for (int k = 0; k < ya; ++k) hy *= q.y;
+                v = s * hy * (xodd ? x2 * x2 : 1.f);
+            } else {
+                float uy = 0.f;
+#pragma unroll
+                for (int ay = P - 1; ay >= 0; --ay) {
+                    float ux = cf[ay][P - 1];
+#pragma unroll
+                    for (int ax = P - 2; ax >= 0; --ax) ux = fmaf(ux, q.x, cf[ay][ax]);
+                    uy = fmaf(uy, q.y, ux);
+                }
+                float zs = 1.f;
+                for (int k = 0; k < sub; ++k) zs *= q.z;
+                v = uy * zs;
+            }
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            if (sub == t && cur.j >= 0) f.u_out[cur.j] = cur.t ? v - cur.ws : 0.f;
+        }
+    }
+    // end stamp once per run of consecutive groups of one population
+    const int prev_pop = __shfl(has ? f.pop : -1, lane - 8 < 0 ? lane : lane - 8, 64);
+    if (has && sub == 0 && (grp == 0 || prev_pop != f.pop))
+        atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
+}
+
+// L2P over the cell list: large cells one per wavefront, then small cells eight per
+// wavefront (four wavefronts per block, each on its own cells).
 template <int P>
 __global__ void __launch_bounds__(256) k_bl2p(FgtBatchPlan bp) {
-    __shared__ float sC[4][P * (P * P + 4)];
-    const int wave = threadIdx.x >> 6;
-    const int64_t m = *bp.nranges;
-    for (int64_t r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
-        const int4 rg = bp.ranges[r];
-        const FgtPop &f = bp.pops[rg.x];
-        for_cells(f, rg.y, (int64_t)rg.y + rg.z, [&](int kx, int ky, int kz, int64_t s0, int64_t e) {
-            l2p_cell_wave<P>(f, bp.gemm, kx, ky, kz, s0, e, sC[wave]);
-        });
-        if ((threadIdx.x & 63) == 0) atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
+    constexpr int SC = P * (P * P + 4) > 256 ? P * (P * P + 4) : 256;   // slice buffer, or 64 float4
+    __shared__ __align__(16) float sC[4][SC];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + wave, nw = (int64_t)gridDim.x * 4;
+    const int64_t nsmall = bp.ncells[0], nbig = bp.ncells[1];
+    for (int64_t r = wid; r < nbig; r += nw) {
+        const int4 c = bp.cells[bp.cap - 1 - r];
+        const FgtPop &f = bp.pops[c.x];
+        int kx, ky, kz;
+        cell_coords(f, c.w, kx, ky, kz);
+        l2p_cell_wave<P>(f, bp.gemm, kx, ky, kz, c.y, (int64_t)c.y + c.z, sC[wave]);
+        wave_sync();
+        if (lane == 0) atomicMax(&bp.stamps[2 * f.pop + 1], (unsigned long long)wall_clock64());
+    }
+    if constexpr (P <= 8) {
+        float4 *stage = reinterpret_cast<float4 *>(sC[wave]);
+        for (int64_t r0 = wid * 8; r0 < nsmall; r0 += nw * 8) l2p_cells_group<P>(bp, r0, nsmall, stage);
     }
 }
 
@@ -1466,7 +1805,9 @@ int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
     hipLaunchKernelGGL(k_bclear, dim3(grid_for(fill_threads > bp.npop ? fill_threads : bp.npop, kBlock)),
                        dim3(kBlock), 0, s, bp);
     MSP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_branges, dim3(grid_for(bp.n_nodes, kBlock)), dim3(kBlock), 0, s, bp);
+    const int64_t cell_waves = (bp.n_pw + kCellWin - 1) / kCellWin;
+    hipLaunchKernelGGL(k_bcells, dim3((unsigned)((cell_waves + 3) / 4)), dim3(256), 0, s, bp,
+                       bp.p <= 8 ? kSmallCell : 0);
     MSP_CHECK_LAUNCH();
     MSP_TRY(batch_p2m_l2p_p(bp, false, s));
     for (int pass = 0; pass < 3; ++pass) {

@@ -157,14 +157,19 @@ struct FgtPop {
     int pop;
 };
 // Device-side offsets of a batch of expansion-route populations (prefix sums over
-// the populations of their operator counts, nodes, grid floats and M2L tiles).
+// the populations of their operator counts, wavefronts of 64 points, grid floats
+// and M2L tiles).
+// cells: the occupied grid cells (population, first point, points, cell index),
+// small ones from the front (count ncells[0]), large ones from the back (ncells[1]);
+// cap entries.
 struct FgtBatchPlan {
     const FgtPop *pops;
     int npop, p;
-    const int64_t *ops_off, *node_off, *grid_off, *tile_off[3];
-    int64_t n_ops, n_nodes, n_grid, n_tiles[3];
-    int4 *ranges;
-    int32_t *nranges;
+    const int64_t *ops_off, *pw_off, *grid_off, *tile_off[3];
+    int64_t n_ops, n_pw, n_grid, n_tiles[3];
+    int4 *cells;
+    int32_t *ncells;
+    int64_t cap;
     unsigned long long *stamps;
     int cus;
     int gemm;          // M2L passes as whole-K GEMM tiles of 32 rows with cell-major grids

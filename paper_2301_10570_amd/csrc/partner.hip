@@ -188,7 +188,9 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
     constexpr bool ILP = P == 1 || P == 2 || P == 4 || P == 8;
     constexpr int STR = ILP ? 4 : 3 * P + 1;            // staged floats per point
     constexpr int PR = P + 1;                           // padded row of a child block
-    constexpr int G0 = 10240 / (P2 * PR * 4);
+    // about 4.5 KB of shift buffers, so that the wave's LDS stays near 8 KB and four
+    // waves fit on each SIMD
+    constexpr int G0 = 4608 / (P2 * PR * 4);
     constexpr int G = !M2M ? 1 : (G0 < 1 ? 1 : (G0 > 8 ? 8 : G0));   // child blocks shifted together
     __shared__ __align__(16) float pts[64 * STR];
     __shared__ float tot[P3];
