@@ -282,7 +282,9 @@ int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, co
                       const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream);
 
 /* Backward of every population (as msp_fgt_backward on its slice); grad_sigma:
- * device float64[npop] or NULL. */
+ * device float64[npop] or NULL.  The populations run on eight internal streams
+ * that wait for the work already on `stream` and that `stream` waits for before
+ * its later work; the call returns once everything is enqueued. */
 int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                        const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
                        float *grad_y, float *grad_z, double *grad_sigma, void *stream);

@@ -388,16 +388,34 @@ int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const
                    float *grad_y, float *grad_z, double *grad_sigma, hipStream_t s) {
     std::vector<PopPlan> plans;
     MSP_TRY(plan_batch(b, sigma, prm, plans));
-    for (int k = 0; k < b->npop; ++k) {
+    // the populations are independent (own trees and buffers, disjoint outputs): their
+    // sequences run on kBwdStreams streams forked from s and joined back into it
+    constexpr int NS = msp_batch::kBwdStreams;
+    if (!b->bfork) {
+        MSP_HIP(hipEventCreateWithFlags(&b->bfork, hipEventDisableTiming));
+        for (int r = 0; r < NS; ++r) {
+            MSP_HIP(hipStreamCreateWithFlags(&b->bside[r], hipStreamNonBlocking));
+            MSP_HIP(hipEventCreateWithFlags(&b->bjoin[r], hipEventDisableTiming));
+        }
+    }
+    MSP_HIP(hipEventRecord(b->bfork, s));
+    for (int r = 0; r < NS; ++r) MSP_HIP(hipStreamWaitEvent(b->bside[r], b->bfork, 0));
+    int rc = MSP_OK;
+    for (int k = 0; k < b->npop && rc == MSP_OK; ++k) {
         const int64_t o = b->off[k];
         msp_fgt_params q = plans[k].prm;
         q.route = plans[k].pl.route;
-        MSP_TRY(fgt_backward(b->pops[k].get(), w + o, is_target ? is_target + o : nullptr, &q, grad_u + o,
-                             grad_w ? grad_w + o : nullptr, grad_x ? grad_x + o : nullptr,
-                             grad_y ? grad_y + o : nullptr, grad_z ? grad_z + o : nullptr,
-                             grad_sigma ? grad_sigma + k : nullptr, s));
+        rc = fgt_backward(b->pops[k].get(), w + o, is_target ? is_target + o : nullptr, &q, grad_u + o,
+                          grad_w ? grad_w + o : nullptr, grad_x ? grad_x + o : nullptr,
+                          grad_y ? grad_y + o : nullptr, grad_z ? grad_z + o : nullptr,
+                          grad_sigma ? grad_sigma + k : nullptr, b->bside[k % NS]);
     }
-    return MSP_OK;
+    // join even after an error, so that s stays ordered after whatever was enqueued
+    for (int r = 0; r < NS; ++r) {
+        MSP_HIP(hipEventRecord(b->bjoin[r], b->bside[r]));
+        MSP_HIP(hipStreamWaitEvent(s, b->bjoin[r], 0));
+    }
+    return rc;
 }
 
 int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,

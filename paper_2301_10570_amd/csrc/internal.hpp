@@ -199,6 +199,10 @@ struct msp_batch {
     static constexpr int kBranches = 1;
     hipStream_t side[kBranches] = {};
     hipEvent_t fork = nullptr, join[kBranches] = {};
+    // streams of the backward, populations spread round-robin (forked from the caller's stream)
+    static constexpr int kBwdStreams = 8;
+    hipStream_t bside[kBwdStreams] = {};
+    hipEvent_t bfork = nullptr, bjoin[kBwdStreams] = {};
     // graph of the last forward signature
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -220,6 +224,11 @@ struct msp_batch {
             if (join[k]) (void)hipEventDestroy(join[k]);
         }
         if (fork) (void)hipEventDestroy(fork);
+        for (int k = 0; k < kBwdStreams; ++k) {
+            if (bside[k]) (void)hipStreamDestroy(bside[k]);
+            if (bjoin[k]) (void)hipEventDestroy(bjoin[k]);
+        }
+        if (bfork) (void)hipEventDestroy(bfork);
     }
 };
 
