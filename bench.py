@@ -149,12 +149,12 @@ def _batch_bench(args, dev, oracle_threads):
     torch.cuda.synchronize()
     ms_eager = 1000.0 * (time.perf_counter() - t0) / args.steps
     gone = torch.ones(int(off[-1]), dtype=torch.float32, device=dev)
-    b.backward(w, gone, sig, is_target=tg, p=args.p)
+    grads = b.backward(w, gone, sig, is_target=tg, p=args.p, use_graph=True)   # eager + capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         b.forward(w, sig, is_target=tg, p=args.p, out=u)
-        b.backward(w, gone, sig, is_target=tg, p=args.p)
+        grads = b.backward(w, gone, sig, is_target=tg, p=args.p, out=grads, use_graph=True)
     torch.cuda.synchronize()
     ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
     res = {"workload": "256 populations, n log-uniform 1024-65536, sigma log-uniform 50-300 um, 1 mm cubes",

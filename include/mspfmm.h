@@ -284,10 +284,14 @@ int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, co
 /* Backward of every population (as msp_fgt_backward on its slice); grad_sigma:
  * device float64[npop] or NULL.  The populations run on eight internal streams
  * that wait for the work already on `stream` and that `stream` waits for before
- * its later work; the call returns once everything is enqueued. */
+ * its later work; the call returns once everything is enqueued.  use_graph = 1:
+ * the first call with given pointers, sigma and parameters runs eagerly (it may
+ * synchronise) and records the same work into a hipGraph; later calls with the
+ * same arguments launch that graph on `stream`.  use_graph = 0 runs eagerly every
+ * time (outputs at new addresses on every call gain nothing from a graph). */
 int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                        const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
-                       float *grad_y, float *grad_z, double *grad_sigma, void *stream);
+                       float *grad_y, float *grad_z, double *grad_sigma, int32_t use_graph, void *stream);
 
 /* Per-population latency of the last forward call, from device timestamps
  * (host double[npop], milliseconds; 0 for empty populations).  Waits for the

@@ -96,7 +96,7 @@ _lib.msp_batch_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp
                                     _vp, _i32, _i32, _vp, _vp, _vp, _vp]
 _lib.msp_batch_forward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _i32, _vp]
 _lib.msp_batch_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _vp, _vp, _vp,
-                                    _vp, _vp]
+                                    _vp, ctypes.c_int32, _vp]
 _lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
 _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
@@ -373,30 +373,46 @@ class Batch:
         return out
 
     def backward(self, w, grad_u, sigmas, is_target=None, p=8, route="auto", cutoff_sigmas=4.5,
-                 exclude_self=False, want=("w", "pos", "sigma"), m2l="mfma"):
-        """Per-population derivatives as Tree.backward; 'sigma' is float64 [npop]."""
+                 exclude_self=False, want=("w", "pos", "sigma"), m2l="mfma", out=None, use_graph=False):
+        """Per-population derivatives as Tree.backward; 'sigma' is float64 [npop].
+
+        out: a dict returned by an earlier call, to be filled again (same addresses);
+        use_graph replays a captured graph when the arguments repeat, so it pays only
+        together with out."""
         n = self.n
         dev = w.device
         pw = _ptr(w, torch.float32, n, "w")
         pg = _ptr(grad_u, torch.float32, n, "grad_u")
         pt = _ptr(is_target, torch.uint8, n, "is_target")
         sg = _host_array(sigmas, ctypes.c_float, self.npop, "sigmas")
-        gw = torch.empty(n, dtype=torch.float32, device=dev) if "w" in want else None
-        gpos = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)] if "pos" in want else None
-        gs = torch.zeros(max(self.npop, 1), dtype=torch.float64, device=dev) if "sigma" in want else None
+        if out is not None:
+            gw = out.get("w")
+            gpos = out.get("pos")
+            gs = out.get("sigma_full")
+            for x, nm in ((gw, "w"), *(((g, "pos") for g in gpos) if gpos else ())):
+                if x is not None:
+                    _ptr(x, torch.float32, n, nm)
+            if gs is not None:
+                _ptr(gs, torch.float64, max(self.npop, 1), "sigma")
+        else:
+            gw = torch.empty(n, dtype=torch.float32, device=dev) if "w" in want else None
+            gpos = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)] if "pos" in want else None
+            gs = torch.zeros(max(self.npop, 1), dtype=torch.float64, device=dev) if "sigma" in want else None
         prm = _params(1.0, p, -1, route, cutoff_sigmas, exclude_self, m2l)
         ptr = lambda x: x.data_ptr() if (x is not None and x.numel()) else None
         _check(_lib.msp_batch_backward(self._h, pw, pt, sg[1], ctypes.byref(prm), pg, ptr(gw),
-                                       *(ptr(g) for g in (gpos or (None, None, None))), ptr(gs), _stream()),
+                                       *(ptr(g) for g in (gpos or (None, None, None))), ptr(gs),
+                                       1 if use_graph else 0, _stream()),
                "msp_batch_backward")
-        out = {}
+        res = {}
         if gw is not None:
-            out["w"] = gw
+            res["w"] = gw
         if gpos is not None:
-            out["pos"] = gpos
+            res["pos"] = gpos
         if gs is not None:
-            out["sigma"] = gs[:self.npop]
-        return out
+            res["sigma"] = gs[:self.npop]
+            res["sigma_full"] = gs
+        return res
 
     def instance_ms(self):
         """Per-population latency (ms) of the last forward, from device timestamps."""

@@ -376,7 +376,7 @@ int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, co
 
 int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                        const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
-                       float *grad_y, float *grad_z, double *grad_sigma, void *stream) {
+                       float *grad_y, float *grad_z, double *grad_sigma, int32_t use_graph, void *stream) {
     g_err[0] = 0;
     if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     MSP_TRY(check_params(prm));
@@ -385,7 +385,7 @@ int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, c
     const int npos = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);
     if (npos != 0 && npos != 3) return fail(MSP_EINVAL, "give all three position gradients or none");
     return batch_backward(b, w, is_target, sigma, prm, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
-                          (hipStream_t)stream);
+                          use_graph, (hipStream_t)stream);
 }
 
 int msp_batch_instance_ms(msp_batch *b, double *ms) {

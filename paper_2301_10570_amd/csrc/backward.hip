@@ -188,7 +188,11 @@ int fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target, const ms
     float *gt = rec + (size_t)nb * kRec;
     double *partial = reinterpret_cast<double *>(gt + nb + (nb & 1));
     if (n == 0) {
-        if (grad_sigma) MSP_HIP(hipMemsetAsync(grad_sigma, 0, sizeof(double), s));
+        // a kernel rather than a memset, so that the sequence can be captured into a graph
+        if (grad_sigma) {
+            hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, (int64_t)0, grad_sigma);
+            MSP_CHECK_LAUNCH();
+        }
         return MSP_OK;
     }
     const bool needA = grad_x || grad_sigma;

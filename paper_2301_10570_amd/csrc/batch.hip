@@ -383,21 +383,15 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
     return MSP_OK;
 }
 
-int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
-                   const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
-                   float *grad_y, float *grad_z, double *grad_sigma, hipStream_t s) {
-    std::vector<PopPlan> plans;
-    MSP_TRY(plan_batch(b, sigma, prm, plans));
-    // the populations are independent (own trees and buffers, disjoint outputs): their
-    // sequences run on kBwdStreams streams forked from s and joined back into it
+namespace {
+
+// The backward of every population, spread round-robin over kBwdStreams streams
+// forked from s and joined back into it (the populations are independent: own
+// trees and buffers, disjoint outputs).
+int enqueue_backward(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
+                     const float *grad_u, float *grad_w, float *grad_x, float *grad_y, float *grad_z,
+                     double *grad_sigma, hipStream_t s) {
     constexpr int NS = msp_batch::kBwdStreams;
-    if (!b->bfork) {
-        MSP_HIP(hipEventCreateWithFlags(&b->bfork, hipEventDisableTiming));
-        for (int r = 0; r < NS; ++r) {
-            MSP_HIP(hipStreamCreateWithFlags(&b->bside[r], hipStreamNonBlocking));
-            MSP_HIP(hipEventCreateWithFlags(&b->bjoin[r], hipEventDisableTiming));
-        }
-    }
     MSP_HIP(hipEventRecord(b->bfork, s));
     for (int r = 0; r < NS; ++r) MSP_HIP(hipStreamWaitEvent(b->bside[r], b->bfork, 0));
     int rc = MSP_OK;
@@ -416,6 +410,60 @@ int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const
         MSP_HIP(hipStreamWaitEvent(s, b->bjoin[r], 0));
     }
     return rc;
+}
+
+}  // namespace
+
+// With use_graph, the first call with given arguments runs eagerly (allocations,
+// lists, inverse permutations) and the same sequence is captured into a hipGraph;
+// later calls replay it.
+int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
+                   const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
+                   float *grad_y, float *grad_z, double *grad_sigma, int use_graph, hipStream_t s) {
+    std::vector<PopPlan> plans;
+    MSP_TRY(plan_batch(b, sigma, prm, plans));
+    std::vector<unsigned char> key;
+    append_bytes(key, &b->generation, sizeof(b->generation));
+    const void *ptrs[9] = {w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma, nullptr};
+    append_bytes(key, ptrs, sizeof(ptrs));
+    append_bytes(key, prm, sizeof(*prm));
+    append_bytes(key, sigma, sizeof(float) * b->npop);
+    append_bytes(key, b->route.data(), sizeof(int32_t) * b->route.size());
+    if (use_graph && b->bexec && key == b->bkey) {
+        MSP_HIP(hipGraphLaunch(b->bexec, s));
+        return MSP_OK;
+    }
+    if (b->bexec) (void)hipGraphExecDestroy(b->bexec);
+    if (b->bgraph) (void)hipGraphDestroy(b->bgraph);
+    b->bexec = nullptr;
+    b->bgraph = nullptr;
+    b->bkey.clear();
+    constexpr int NS = msp_batch::kBwdStreams;
+    if (!b->bfork) {
+        MSP_HIP(hipEventCreateWithFlags(&b->bfork, hipEventDisableTiming));
+        for (int r = 0; r < NS; ++r) {
+            MSP_HIP(hipStreamCreateWithFlags(&b->bside[r], hipStreamNonBlocking));
+            MSP_HIP(hipEventCreateWithFlags(&b->bjoin[r], hipEventDisableTiming));
+        }
+    }
+    MSP_TRY(enqueue_backward(b, plans, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma, s));
+    if (!use_graph) return MSP_OK;
+    if (!b->cap) MSP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    MSP_HIP(hipStreamSynchronize(s));
+    MSP_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_backward(b, plans, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
+                                    b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc != MSP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) return fail(MSP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->bgraph = g;
+    MSP_HIP(hipGraphInstantiate(&b->bexec, b->bgraph, nullptr, nullptr, 0));
+    b->bkey = key;
+    return MSP_OK;
 }
 
 int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,

@@ -209,12 +209,21 @@ struct msp_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> key;
     int64_t launches = 0;   // kernel launches issued by the last eager forward
+    // graph of the last backward signature
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    std::vector<unsigned char> bkey;
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         key.clear();
+        if (bexec) (void)hipGraphExecDestroy(bexec);
+        if (bgraph) (void)hipGraphDestroy(bgraph);
+        bexec = nullptr;
+        bgraph = nullptr;
+        bkey.clear();
     }
     ~msp_batch() {
         drop_graph();
@@ -242,7 +251,7 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
                   const msp_fgt_params *prm, float *u_out, int use_graph, hipStream_t s);
 int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                    const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
-                   float *grad_y, float *grad_z, double *grad_sigma, hipStream_t s);
+                   float *grad_y, float *grad_z, double *grad_sigma, int use_graph, hipStream_t s);
 int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
                    int32_t npop, const float *w, const uint8_t *is_target, const float *sigma,
                    const msp_fgt_params *prm, const int32_t *cand, int32_t ncand, int32_t max_depth,

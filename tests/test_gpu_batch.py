@@ -118,6 +118,21 @@ def test_batch_backward_equals_single_trees(pops):
         for a in range(3):
             np.testing.assert_array_equal(got["pos"][a][lo:hi].cpu().numpy(), ref["pos"][a].cpu().numpy())
         assert got["sigma"][k].item() == ref["sigma"].item()
+    # the second call with the same arguments replays the captured graph
+    keep = {"w": got["w"].cpu().numpy().copy(), "sigma": got["sigma"].cpu().numpy().copy(),
+            "pos": [a.cpu().numpy().copy() for a in got["pos"]]}
+    again = b.backward(w, g, sig, is_target=tg, use_graph=True)      # eager, then captured
+    for rep in range(3):
+        g.sum().item()                                                  # eager work and a synchronisation
+        for k_ in ("w", "sigma_full"):
+            again[k_].zero_()
+        for a in again["pos"]:
+            a.zero_()
+        again = b.backward(w, g, sig, is_target=tg, out=again, use_graph=True)   # graph replay
+        np.testing.assert_array_equal(again["w"].cpu().numpy(), keep["w"])
+        np.testing.assert_array_equal(again["sigma"].cpu().numpy(), keep["sigma"])
+        for a in range(3):
+            np.testing.assert_array_equal(again["pos"][a].cpu().numpy(), keep["pos"][a])
     b.close()
 
 
