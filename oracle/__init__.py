@@ -14,6 +14,10 @@ Contents
                                      translation operators (Eqs. (6)-(7)), truncation bounds
   partner.py                         child probabilities and proportional choice
                                      (Algorithm 2)
+  descent.py                         the partner descent over pairs of items
+                                     (Algorithm 1 with Algorithm 2's choice), the
+                                     counter-based generator it draws from, and the
+                                     acceptance of requests at the dendrites
 """
 from __future__ import annotations
 
