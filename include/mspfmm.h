@@ -224,6 +224,47 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
                               const int32_t *target_idx, const int32_t *node_id, int64_t nq,
                               const float *uniforms, float *probs, int32_t *choice, void *stream);
 
+/* Partner descent: Algorithm 1 over pairs of (axon item, dendrite item), driven by
+ * the proportional choice of Algorithm 2, then the acceptance of the requests at
+ * the dendrites.  Items: a tree node v (v >= 0) or one neuron with input index i,
+ * encoded -(i + 1).  A neuron is the paper's leaf; the children of an inner node
+ * are its child nodes in octant order, those of a leaf node its neurons in key
+ * order.  Every choice compares Att(S, C) = sum_{i in S} sum_{j in C, j != i}
+ * a_i w_j exp(-|t_i - s_j|^2 / sigma^2) over the candidates C:
+ *   S, T neurons       request S -> T
+ *   S neuron, T node   choose a child C of T by Att(S, C)
+ *   S node, T neuron   choose a child S' of S by Att(S', T); the other children drop out
+ *   S, T nodes         each child S_c of S holding axons chooses a child C of T by Att(S_c, C)
+ * A choice takes the first candidate whose running sum exceeds r times the total,
+ * r = (mix(mix(seed ^ ((step + 1) * 0x9E3779B97F4A7C15)) ^ item) >> 11) * 2^-53 with
+ * mix the SplitMix64 output for a state and item the choosing item (two's
+ * complement); all-zero values drop the pair.  Att over the children of an inner
+ * node is accumulated from partner queries (the accuracy contract of
+ * msp_partner_probabilities, prm->cutoff_sigmas applies); over neurons it is
+ * summed directly in float64.  w: vacant dendritic elements, a: vacant axonal
+ * elements, both device float32[n] in input order (>= 0).  prm: sigma, p and
+ * cutoff; self pairs are always skipped.  Synchronises `stream` (the frontier is
+ * kept on the host). */
+
+/* One step on the host frontier (S_in[k], T_in[k]), k < m: the next frontier goes
+ * to S_out/T_out (host int64[cap]; *m_out pairs), the requests to req_axon /
+ * req_dendrite (host int32[req_cap], input indices; *n_req).  MSP_ENOSPC when a
+ * capacity is exceeded (the counts are still set). */
+int msp_descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                     int32_t step, const int64_t *S_in, const int64_t *T_in, int64_t m, int64_t *S_out,
+                     int64_t *T_out, int64_t cap, int64_t *m_out, int32_t *req_axon, int32_t *req_dendrite,
+                     int64_t req_cap, int64_t *n_req, void *stream);
+
+/* The whole descent from (root, root) until the frontier is empty (steps numbered
+ * from 0), then acceptance: dendrite neuron j takes at most floor(w_j) requests,
+ * those with the smallest priority mix(mix(seed ^ 0xD1B54A32D192ED03) ^ i) of the
+ * axon's input index i, ties by i.  req_axon, req_dendrite: device int32[n]
+ * (input indices; at most one request per neuron with axons); accepted: device
+ * uint8[n]; *n_req, *n_steps: host. */
+int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                        int32_t *req_axon, int32_t *req_dendrite, uint8_t *accepted, int64_t *n_req,
+                        int32_t *n_steps, void *stream);
+
 /* Copy an internal buffer, for pass-level checks.
  *   which 0: Hermite moment grid after P2M of the last expansion-route forward call
  *   which 1: Taylor grid after M2L of that call

@@ -81,6 +81,11 @@ _lib.msp_fgt_plan.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(Fgt
 _lib.msp_fgt_forward.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp]
 _lib.msp_fgt_backward.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.msp_direct_sum.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp]
+_lib.msp_descent_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), ctypes.c_uint64, ctypes.c_int32,
+                                  _vp, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _i64,
+                                  ctypes.POINTER(_i64), _vp]
+_lib.msp_partner_descent.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), ctypes.c_uint64, _vp, _vp, _vp,
+                                     ctypes.POINTER(_i64), ctypes.POINTER(_i32), _vp]
 _lib.msp_partner_probabilities.argtypes = [_vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _i64, _vp,
                                            _vp, _vp, _vp]
 _lib.msp_fgt_debug_buffer.argtypes = [_vp, _i32, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), _vp]
@@ -102,6 +107,7 @@ _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
 for _f in ("msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
+           "msp_descent_step", "msp_partner_descent",
            "msp_fgt_debug_buffer", "msp_batch_create", "msp_batch_build", "msp_batch_autotune",
            "msp_batch_forward", "msp_batch_backward", "msp_batch_instance_ms", "msp_batch_info"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -290,6 +296,58 @@ class Tree:
                                               choice.data_ptr() if nq else None, _stream()),
                "msp_partner_probabilities")
         return probs.view(nq, 8), choice
+
+    def descent_step(self, w, a, S, T, step, seed, sigma, p=8, cutoff_sigmas=0.0):
+        """One step of the partner descent (msp_descent_step) on host int64 arrays
+        S, T of items (node id, or -(input index + 1) for a neuron).  Returns
+        (S', T', requests as an int array [k, 2] of (axon, dendrite) input indices)."""
+        import numpy as np
+        S = np.ascontiguousarray(np.asarray(S, np.int64))
+        T = np.ascontiguousarray(np.asarray(T, np.int64))
+        m = S.size
+        if T.size != m:
+            raise ValueError("S and T must have the same length")
+        pw = _ptr(w, torch.float32, self.n, "w")
+        pa = _ptr(a, torch.float32, self.n, "a")
+        cap = max(8 * m + 8, 64)
+        while True:
+            S2 = np.empty(cap, np.int64)
+            T2 = np.empty(cap, np.int64)
+            ra = np.empty(max(m, 1), np.int32)
+            rd = np.empty(max(m, 1), np.int32)
+            m2, nr = _i64(), _i64()
+            prm = _params(sigma, p, -1, "auto", cutoff_sigmas, True)
+            rc = _lib.msp_descent_step(self._h, pw, pa, ctypes.byref(prm), ctypes.c_uint64(int(seed)),
+                                       int(step), S.ctypes.data_as(_vp), T.ctypes.data_as(_vp), m,
+                                       S2.ctypes.data_as(_vp), T2.ctypes.data_as(_vp), cap, ctypes.byref(m2),
+                                       ra.ctypes.data_as(_vp), rd.ctypes.data_as(_vp), ra.size, ctypes.byref(nr),
+                                       _stream())
+            if rc == MSP_ENOSPC and m2.value > cap:
+                cap = m2.value
+                continue
+            _check(rc, "msp_descent_step")
+            break
+        req = np.stack([ra[:nr.value], rd[:nr.value]], 1).astype(np.int64)
+        return S2[:m2.value].copy(), T2[:m2.value].copy(), req
+
+    def partner_descent(self, w, a, sigma, seed, p=8, cutoff_sigmas=0.0):
+        """The whole partner descent and the acceptance (msp_partner_descent).
+        Returns a dict: 'axon', 'dendrite' (int32, input indices), 'accepted'
+        (uint8) device tensors of the requests, and 'steps'."""
+        pw = _ptr(w, torch.float32, self.n, "w")
+        pa = _ptr(a, torch.float32, self.n, "a")
+        dev = w.device
+        n = max(self.n, 1)
+        ra = torch.empty(n, dtype=torch.int32, device=dev)
+        rd = torch.empty(n, dtype=torch.int32, device=dev)
+        acc = torch.empty(n, dtype=torch.uint8, device=dev)
+        nr, steps = _i64(), _i32()
+        prm = _params(sigma, p, -1, "auto", cutoff_sigmas, True)
+        _check(_lib.msp_partner_descent(self._h, pw, pa, ctypes.byref(prm), ctypes.c_uint64(int(seed)),
+                                        ra.data_ptr(), rd.data_ptr(), acc.data_ptr(), ctypes.byref(nr),
+                                        ctypes.byref(steps), _stream()), "msp_partner_descent")
+        k = nr.value
+        return {"axon": ra[:k], "dendrite": rd[:k], "accepted": acc[:k], "steps": steps.value}
 
 
 def _host_array(values, ctype, n, name):

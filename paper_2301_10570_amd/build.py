@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmspfmm.so")
-SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip", "batch.hip"]
+SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip", "batch.hip",
+           "descent.hip"]
 ARCH = "gfx950"
 
 

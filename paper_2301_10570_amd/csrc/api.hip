@@ -266,6 +266,48 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
                                  (hipStream_t)stream);
 }
 
+int msp_descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                     int32_t step, const int64_t *S_in, const int64_t *T_in, int64_t m, int64_t *S_out,
+                     int64_t *T_out, int64_t cap, int64_t *m_out, int32_t *req_axon, int32_t *req_dendrite,
+                     int64_t req_cap, int64_t *n_req, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (m < 0 || cap < 0 || req_cap < 0 || step < 0) return fail(MSP_EINVAL, "negative size or step");
+    if (!m_out || !n_req) return fail(MSP_EINVAL, "NULL count output");
+    if (m > 0 && (!S_in || !T_in)) return fail(MSP_EINVAL, "NULL frontier");
+    if ((cap > 0 && (!S_out || !T_out)) || (req_cap > 0 && (!req_axon || !req_dendrite)))
+        return fail(MSP_EINVAL, "NULL output array");
+    if (t->n > 0 && (!w || !a)) return fail(MSP_EINVAL, "NULL weight array");
+    if (t->n == 0) {
+        if (m > 0) return fail(MSP_EINVAL, "descent on an empty tree");
+        *m_out = 0;
+        *n_req = 0;
+        return MSP_OK;
+    }
+    return descent_step(t, w, a, prm, seed, step, S_in, T_in, m, S_out, T_out, cap, m_out, req_axon,
+                        req_dendrite, req_cap, n_req, (hipStream_t)stream);
+}
+
+int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                        int32_t *req_axon, int32_t *req_dendrite, uint8_t *accepted, int64_t *n_req,
+                        int32_t *n_steps, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (!n_req) return fail(MSP_EINVAL, "NULL count output");
+    if (t->n > 0 && (!w || !a || !req_axon || !req_dendrite || !accepted)) return fail(MSP_EINVAL, "NULL array");
+    if (t->n == 0) {
+        *n_req = 0;
+        if (n_steps) *n_steps = 0;
+        return MSP_OK;
+    }
+    return partner_descent(t, w, a, prm, seed, req_axon, req_dendrite, accepted, n_req, n_steps,
+                           (hipStream_t)stream);
+}
+
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,
                          void *stream) {
     if (!t || !bytes) return fail(MSP_EINVAL, "NULL argument");

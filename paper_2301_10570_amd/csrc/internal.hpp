@@ -308,6 +308,20 @@ int direct_all_pairs(const float *tx, const float *ty, const float *tz, int64_t 
 int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
                           const int32_t *target_idx, const int32_t *node_id, int64_t nq,
                           const float *uniforms, float *probs, int32_t *choice, hipStream_t s);
+// stage the weights, inverse permutation and node moments once; then any number
+// of query batches with the unnormalised per-octant sums (raw: double[nq * 8])
+int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s);
+int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+                      const int32_t *node_id, int64_t nq, float *probs, double *raw, hipStream_t s);
+
+// descent.hip
+int descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                 int32_t step, const int64_t *S_in, const int64_t *T_in, int64_t m, int64_t *S_out,
+                 int64_t *T_out, int64_t cap, int64_t *m_out, int32_t *req_axon, int32_t *req_dendrite,
+                 int64_t req_cap, int64_t *n_req, hipStream_t s);
+int partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
+                    int32_t *req_axon, int32_t *req_dendrite, uint8_t *accepted, int64_t *n_req,
+                    int32_t *n_steps, hipStream_t s);
 
 // helpers
 inline unsigned grid_for(int64_t n, int block) {

@@ -486,7 +486,7 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
                 const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
                 double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
                 double sigma, float cutoff2, int unlimited, int exclude_self, float *probs,
-                int32_t *choice, uint8_t *done) {
+                int32_t *choice, uint8_t *done, double *raw) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t q = g >> 3;
     const int c = (int)(g & 7);
@@ -574,6 +574,7 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
     for (int d = 0; d < 8; ++d)
         if (d == c) mine = S[d];
     probs[q * 8 + c] = total > 0.0 ? (float)(mine / total) : 0.f;
+    if (raw) raw[q * 8 + c] = mine;
     if (c == 0) {
         if (choice) {
             int32_t pick = -1;
@@ -619,7 +620,8 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
           const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
           double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
           const float *nodeA, int64_t slot0, double sigma, float cutoff2, int unlimited,
-          double rho_ref, int exclude_self, float *probs, int32_t *choice, const uint8_t *done) {
+          double rho_ref, int exclude_self, float *probs, int32_t *choice, const uint8_t *done,
+          double *raw) {
     constexpr int P3 = P * P * P;
     __shared__ int32_t stk[kStack];
     const int64_t q = blockIdx.x;
@@ -631,6 +633,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     const int32_t fc = ok ? nfchild[X] : 0;
     if (nc == 0 || fc <= X || fc + nc > n_nodes) {
         if (lane < 8) probs[q * 8 + lane] = 0.f;
+        if (lane < 8 && raw) raw[q * 8 + lane] = 0.0;
         if (lane == 0 && choice) choice[q] = -1;
         return;
     }
@@ -891,6 +894,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         for (int d = 0; d < 8; ++d)
             if (d == lane) sl = S[d];
         probs[q * 8 + lane] = total > 0.0 ? (float)(sl / total) : 0.f;
+        if (raw) raw[q * 8 + lane] = sl;
     }
     int32_t cids[8];
 #pragma unroll
@@ -914,15 +918,20 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     }
 }
 
-template <int P>
-int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
-                const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
-                int32_t *choice, hipStream_t s) {
-    const double sigma = prm->sigma;
-    const double rmax = rho_max_for_p(P);
-    int lh = kDepth;
+// coarsest level whose half-side is within rho_max(p) sigma: the moment level
+int moment_level(const msp_tree *t, double sigma, int p) {
+    const double rmax = rho_max_for_p(p);
     for (int l = 0; l <= kDepth; ++l)
-        if (t->geo.side / std::ldexp(1.0, l + 1) / sigma <= rmax) { lh = l; break; }
+        if (t->geo.side / std::ldexp(1.0, l + 1) / sigma <= rmax) return l;
+    return kDepth;
+}
+
+// node moment pyramid (Eq. (7) and M2M) of the staged weights, from the deepest
+// level up to the moment level
+template <int P>
+int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+    const double sigma = prm->sigma;
+    const int lh = moment_level(t, sigma, P);
     const int64_t nn = t->n_nodes;
     const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
     const int64_t nslots = nn - slot0;
@@ -966,7 +975,21 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
     t->node_moments_level = lh;
     t->node_moments_p = P;
     t->node_moments_bytes = (int64_t)(nslots > 0 ? nslots : 0) * P * P * P * 4;
+    return MSP_OK;
+}
+
+// queries against the node moments of the last partner_moments call; raw (or
+// NULL): the unnormalised per-octant sums
+template <int P>
+int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+                    const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
+                    int32_t *choice, double *raw, hipStream_t s) {
     if (nq == 0) return MSP_OK;
+    const double sigma = prm->sigma;
+    const double rmax = rho_max_for_p(P);
+    const int lh = moment_level(t, sigma, P);
+    const int64_t nn = t->n_nodes;
+    const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * sigma);
     MSP_TRY(t->partner_done.ensure((size_t)nq));
@@ -979,7 +1002,7 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                            t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
                            t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), sigma, R * R, unlimited ? 1 : 0,
                            (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice,
-                           t->partner_done.as<uint8_t>());
+                           t->partner_done.as<uint8_t>(), raw);
         MSP_CHECK_LAUNCH();
     }
     PhaseScope ps(&t->timing, PH_PARTNER, s);
@@ -990,12 +1013,20 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                        t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
                        t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma,
                        R * R, unlimited ? 1 : 0, rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs,
-                       choice, t->partner_done.as<uint8_t>());
+                       choice, t->partner_done.as<uint8_t>(), raw);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
 
 }  // namespace
+
+template <int P>
+int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+                const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
+                int32_t *choice, hipStream_t s) {
+    MSP_TRY(partner_moments<P>(t, prm, s));
+    return partner_queries<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, nullptr, s);
+}
 
 int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
                           const int32_t *target_idx, const int32_t *node_id, int64_t nq,
@@ -1008,6 +1039,30 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
     MSP_TRY(ensure_iperm(t, s));
     switch (prm->p) {
 #define CASE(P) case P: return run_partner<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, s);
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    }
+    return fail(MSP_EINVAL, "p out of range");
+}
+
+
+int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s) {
+    MSP_TRY(stage_inputs(t, w, nullptr, s));
+    MSP_TRY(ensure_iperm(t, s));
+    switch (prm->p) {
+#define CASE(P) case P: return partner_moments<P>(t, prm, s);
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    }
+    return fail(MSP_EINVAL, "p out of range");
+}
+
+int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+                      const int32_t *node_id, int64_t nq, float *probs, double *raw, hipStream_t s) {
+    switch (prm->p) {
+#define CASE(P) case P: return partner_queries<P>(t, prm, target_idx, node_id, nq, nullptr, probs, nullptr, raw, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE

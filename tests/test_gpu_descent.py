@@ -1,0 +1,130 @@
+"""Partner descent on the GPU (Algorithm 1 with Algorithm 2's proportional choice,
+and the acceptance at the dendrites) against the FP64 oracle: step by step on
+the same frontier, whole descents, the landing distribution of a single axon,
+and the invariants of a larger run."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import descent, octree
+
+pytestmark = pytest.mark.gpu
+
+TIE = 1e-4   # a choice closer than this (relative to the total) to a boundary may flip
+
+
+def _setup(wl, leaf_max):
+    import torch
+    import paper_2301_10570_amd as msp
+    T = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    tree = msp.build_tree(T(wl.x), T(wl.y), T(wl.z), leaf_max=leaf_max)
+    ot = octree.build(wl.x, wl.y, wl.z, leaf_max=leaf_max)
+    od = descent.Descent(ot, wl.pos64(), wl.a, wl.w, wl.sigma)
+    return tree, od, T(wl.w), T(wl.a)
+
+
+def _pairs(S, T):
+    return sorted(zip((int(x) for x in S), (int(y) for y in T)))
+
+
+@pytest.mark.parametrize("leaf_max", [8, 32])
+def test_steps_match_oracle(leaf_max):
+    wl = synth.uniform_box(1500, extent=(400.0, 400.0, 400.0), sigma=90.0, seed=31)
+    print(f"descent steps, 1500 neurons, leaf_max {leaf_max}", flush=True)
+    tree, od, w, a = _setup(wl, leaf_max)
+    S, T = np.array([0]), np.array([0])
+    seed, total_req, flips = 77, 0, 0
+    for step in range(60):
+        if S.size == 0:
+            break
+        S2, T2, req = tree.descent_step(w, a, S, T, step, seed, wl.sigma, cutoff_sigmas=0.0)
+        onxt, oreq, dec = od.step(list(zip(S.tolist(), T.tolist())), step, seed)
+        assert sorted(map(tuple, req.tolist())) == sorted(oreq)
+        g, o = set(_pairs(S2, T2)), set(onxt)
+        if g != o:
+            diff = len(g ^ o) // 2
+            near = sum(1 for _, _, m in dec if m < TIE)
+            assert diff <= near, (step, diff, near)
+            flips += diff
+        total_req += len(oreq)
+        S, T = S2, T2
+    assert S.size == 0
+    assert total_req > 50
+    print(f"  requests {total_req}, near-tie flips {flips}")
+
+
+def _oracle_run(od, seed):
+    frontier, req, mmin = [(0, 0)], [], np.inf
+    for step in range(200):
+        if not frontier:
+            break
+        frontier, r, dec = od.step(frontier, step, seed)
+        req += r
+        if dec:
+            mmin = min(mmin, min(m for _, _, m in dec))
+    return sorted(req), mmin
+
+
+def test_whole_descent_and_acceptance_match_oracle():
+    wl = synth.uniform_box(900, extent=(300.0, 300.0, 300.0), sigma=70.0, seed=32)
+    print("whole descent, 900 neurons", flush=True)
+    tree, od, w, a = _setup(wl, 16)
+    # a seed whose oracle choices all stay clear of the boundaries (decided by the oracle)
+    for seed in range(20):
+        oreq, mmin = _oracle_run(od, seed)
+        if mmin >= TIE:
+            break
+    assert mmin >= TIE
+    got = tree.partner_descent(w, a, wl.sigma, seed, cutoff_sigmas=0.0)
+    ga = got["axon"].cpu().numpy()
+    gd = got["dendrite"].cpu().numpy()
+    gacc = got["accepted"].cpu().numpy().astype(bool)
+    assert sorted(zip(ga.tolist(), gd.tolist())) == oreq
+    oacc = descent.accept(list(zip(ga.tolist(), gd.tolist())), wl.w, seed)
+    np.testing.assert_array_equal(gacc, oacc)
+    print(f"  seed {seed}: {len(oreq)} requests, {int(gacc.sum())} accepted, {got['steps']} steps")
+
+
+def test_single_axon_landing_distribution():
+    wl = synth.uniform_box(40, extent=(200.0, 200.0, 200.0), sigma=90.0, seed=13)
+    print("single-axon landing distribution, 600 seeds", flush=True)
+    av = np.zeros(wl.n, np.float32)
+    av[7] = 2.0
+    wv = np.where(np.arange(wl.n) == 7, 0.0, 1.0 + (np.arange(wl.n) % 3)).astype(np.float32)
+    wl.a, wl.w = av, wv
+    tree, od, w, a = _setup(wl, 4)
+    pos = wl.pos64()
+    k = wv * np.exp(-np.sum((pos - pos[7]) ** 2, 1) / wl.sigma ** 2)
+    p = k / k.sum()
+    n = 600
+    hits = np.zeros(wl.n)
+    for seed in range(n):
+        got = tree.partner_descent(w, a, wl.sigma, seed, cutoff_sigmas=0.0)
+        ax = got["axon"].cpu().numpy()
+        dd = got["dendrite"].cpu().numpy()
+        assert ax.tolist() == [7]
+        hits[dd[0]] += 1
+    m = p > 0
+    chi2 = float(np.sum((hits[m] - n * p[m]) ** 2 / (n * p[m])))
+    assert hits[7] == 0 and chi2 < 85.0     # 38 degrees of freedom
+
+
+def test_larger_run_invariants():
+    wl = synth.blobs(16, 2048, extent=2000.0, std=60.0, sigma=120.0, seed=33)
+    print(f"descent invariants, {wl.n} neurons", flush=True)
+    tree, od, w, a = _setup(wl, 64)
+    r1 = tree.partner_descent(w, a, wl.sigma, 5)
+    r2 = tree.partner_descent(w, a, wl.sigma, 5)
+    ax = r1["axon"].cpu().numpy()
+    dd = r1["dendrite"].cpu().numpy()
+    acc = r1["accepted"].cpu().numpy().astype(bool)
+    for key in ("axon", "dendrite", "accepted"):
+        np.testing.assert_array_equal(r1[key].cpu().numpy(), r2[key].cpu().numpy())
+    assert ax.size > 0.5 * np.count_nonzero(wl.a > 0)
+    assert np.unique(ax).size == ax.size
+    assert np.all(wl.a[ax] > 0) and np.all(wl.w[dd] > 0) and np.all(ax != dd)
+    oacc = descent.accept(list(zip(ax.tolist(), dd.tolist())), wl.w, 5)
+    np.testing.assert_array_equal(acc, oacc)
+    cnt = np.bincount(dd[acc], minlength=wl.n)
+    assert np.all(cnt <= np.floor(wl.w))
+    print(f"  {ax.size} requests, {int(acc.sum())} accepted, {r1['steps']} steps")
