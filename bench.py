@@ -12,7 +12,8 @@ second (attraction sums/s), inputs resident in HBM before the timed region.
 
 Prints one JSON line.  Extra keys: per-phase times, the accuracy of this run
 against the FP64 oracle on sampled targets, the all-pairs GPU direct sum on a
-sample of targets (for the speedup), and the oracle timed on host cores.
+sample of targets (for the speedup), the oracle timed on host cores, the batch
+of 256 populations and the partner descent.
 """
 from __future__ import annotations
 
@@ -111,6 +112,41 @@ def _partner_queries(tree, k, seed):
     return T(tq), T(node)
 
 
+def _descent_bench(args, dev):
+    """The partner descent (Algorithm 1 with Algorithm 2's proportional choice, then
+    the acceptance at the dendrites) over the 262,144 neurons in 64 Gaussian blobs
+    (sigma 200 um, p 8): whole descents from (root, root) timed with the device
+    synchronised, plus validity checks of the result."""
+    import numpy as np
+    import torch
+    import paper_2301_10570_amd as msp
+    import synth
+    wl = synth.config(2)
+    T = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+    tree = msp.Tree()
+    tree.build(T(wl.x), T(wl.y), T(wl.z), leaf_max=wl.leaf_max)
+    w, a = T(wl.w), T(wl.a)
+    r = tree.partner_descent(w, a, wl.sigma, 11, p=wl.p)            # first call: allocations
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for rep in range(reps):
+        r = tree.partner_descent(w, a, wl.sigma, 11 + rep, p=wl.p)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    ax = r["axon"].cpu().numpy()
+    dd = r["dendrite"].cpu().numpy()
+    acc = r["accepted"].cpu().numpy().astype(bool)
+    ok = bool(np.unique(ax).size == ax.size and np.all(wl.a[ax] > 0) and np.all(wl.w[dd] > 0)
+              and np.all(ax != dd) and np.all(np.bincount(dd[acc], minlength=wl.n) <= np.floor(wl.w)))
+    tree.close()
+    return {"workload": "262,144 neurons in 64 Gaussian blobs (4 mm cube, std 50 um), sigma 200 um, p 8, "
+                        "leaf <= 64, cutoff 4.5 sigma",
+            "axon_neurons": int(np.count_nonzero(wl.a > 0)), "requests": int(ax.size),
+            "accepted": int(acc.sum()), "steps": int(r["steps"]), "ms_per_descent": ms,
+            "requests_per_s": ax.size / (ms / 1000.0), "valid": ok}
+
+
 def _batch_bench(args, dev, oracle_threads):
     """256 independent populations (sizes log-uniform in [1024, 65536], sigma
     log-uniform in [50, 300] um, each in its own 1 mm cube): autotuned leaf size
@@ -197,6 +233,7 @@ def main():
                     help="budget for the oracle sample, from a short probe (which overestimates)")
     ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-population batch")
+    ap.add_argument("--no-descent", action="store_true", help="skip the partner descent")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three copies of 1 GiB (counter calibration runs)")
     args = ap.parse_args()
@@ -425,6 +462,9 @@ def main():
     if not args.no_batch:
         print("bench: 256-population batch", file=sys.stderr, flush=True)
         result["batch"] = _batch_bench(args, dev, min(16, len(os.sched_getaffinity(0))))
+    if not args.no_descent:
+        print("bench: partner descent", file=sys.stderr, flush=True)
+        result["descent"] = _descent_bench(args, dev)
     print(json.dumps(result), flush=True)
 
 

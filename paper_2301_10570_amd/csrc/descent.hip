@@ -86,13 +86,11 @@ __global__ void __launch_bounds__(256) k_desc_direct(int64_t ntask, const int32_
     }
 }
 
-// value of candidate k of unit U (FP64, fixed summation order)
+// value of candidate k of a K_LEAF or K_SRC unit (FP64, fixed summation order)
 __device__ inline double unit_value(const UnitDesc &U, int k, const double *raw, const float *qa,
                                     const double *dv, const int64_t *toff, const float *ta, const int64_t *crng) {
     double v = 0.0;
-    if (U.kind == K_OCT) {
-        for (int64_t q = U.r0; q < U.r1; ++q) v += (double)qa[q] * raw[q * 8 + k];
-    } else if (U.kind == K_LEAF) {
+    if (U.kind == K_LEAF) {
         for (int64_t t = U.r0; t < U.r1; ++t) v += (double)ta[t] * dv[toff[t] + k];
     } else {
         const int64_t b = crng[2 * (U.c0 + k)], e = crng[2 * (U.c0 + k) + 1];
@@ -101,8 +99,9 @@ __device__ inline double unit_value(const UnitDesc &U, int k, const double *raw,
     return v;
 }
 
-// one wavefront per unit: candidate values 64 at a time (lane per candidate),
-// total and running sums in candidate order by lane 0
+// one wavefront per unit.  K_OCT: the lanes split the queries; otherwise candidate
+// values 64 at a time (lane per candidate), total and running sums in candidate
+// order by lane 0
 __global__ void __launch_bounds__(256) k_desc_choose(int64_t nunit, const UnitDesc *units, const double *raw,
                                                      const float *qa, const double *dv, const int64_t *toff,
                                                      const float *ta, const int64_t *crng, uint64_t seed,
@@ -112,7 +111,42 @@ __global__ void __launch_bounds__(256) k_desc_choose(int64_t nunit, const UnitDe
     const int64_t u = (int64_t)blockIdx.x * 4 + wave;
     if (u >= nunit) return;
     const UnitDesc U = units[u];
-    const int nc = U.kind == K_OCT ? 8 : U.ncand;
+    if (U.kind == K_OCT) {
+        // octant values: the lanes split the queries, then a butterfly sum (every lane
+        // ends with all eight values)
+        double acc[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) acc[d] = 0.0;
+        for (int64_t q = U.r0 + lane; q < U.r1; q += 64) {
+            const double aq = (double)qa[q];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) acc[d] = fma(aq, raw[q * 8 + d], acc[d]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) acc[d] += __shfl_xor(acc[d], o, 64);
+        double tot = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) tot += acc[d];
+        int pk = -1;
+        if (tot > 0.0) {
+            const double target = desc_uniform(seed, step, U.item) * tot;
+            double run = 0.0;
+            int last = -1;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                if (pk >= 0) continue;
+                if (acc[d] > 0.0) last = d;
+                run += acc[d];
+                if (run > target && acc[d] > 0.0) pk = d;
+            }
+            if (pk < 0) pk = last;
+        }
+        if (lane == 0) out[u] = pk;
+        return;
+    }
+    const int nc = U.ncand;
     double total = 0.0;
     for (int k0 = 0; k0 < nc; k0 += 64) {
         const int k = k0 + lane;
