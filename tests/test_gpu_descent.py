@@ -128,3 +128,37 @@ def test_larger_run_invariants():
     cnt = np.bincount(dd[acc], minlength=wl.n)
     assert np.all(cnt <= np.floor(wl.w))
     print(f"  {ax.size} requests, {int(acc.sum())} accepted, {r1['steps']} steps")
+
+
+def test_degenerate_descents():
+    import torch
+    import paper_2301_10570_amd as msp
+    print("descent edge cases: no axons, no dendrites, one neuron, coincident points", flush=True)
+    T = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    wl = synth.uniform_box(300, extent=(200.0, 200.0, 200.0), sigma=60.0, seed=34)
+    tree = msp.build_tree(T(wl.x), T(wl.y), T(wl.z), leaf_max=16)
+    zero = np.zeros(wl.n, np.float32)
+    for a, w in ((zero, wl.w), (wl.a, zero)):
+        r = tree.partner_descent(T(w), T(a), wl.sigma, 3)
+        assert r["axon"].numel() == 0
+    # one neuron: no partner but itself, which is excluded
+    one = msp.build_tree(T(wl.x[:1]), T(wl.y[:1]), T(wl.z[:1]), leaf_max=16)
+    r = one.partner_descent(T(np.ones(1, np.float32)), T(np.ones(1, np.float32)), wl.sigma, 3)
+    assert r["axon"].numel() == 0
+    # coincident points: one depth-21 leaf holding all of them; every choice is by weight
+    n = 200
+    x = np.full(n, 5.0, np.float32)
+    av = np.ones(n, np.float32)
+    wv = (np.arange(n) % 3).astype(np.float32)
+    ct = msp.build_tree(T(x), T(x), T(x), leaf_max=16)
+    ot = octree.build(x, x, x, leaf_max=16)
+    od = descent.Descent(ot, np.stack([x, x, x], 1).astype(np.float64), av, wv, 50.0)
+    got = ct.partner_descent(T(wv), T(av), 50.0, 8, cutoff_sigmas=0.0)
+    g = sorted(zip(got["axon"].cpu().numpy().tolist(), got["dendrite"].cpu().numpy().tolist()))
+    oreq, mmin = _oracle_run(od, 8)
+    if mmin >= TIE:
+        assert g == oreq
+    assert len(g) == n and all(wv[j] > 0 and i != j for i, j in g)
+    acc = got["accepted"].cpu().numpy().astype(bool)
+    dd = got["dendrite"].cpu().numpy()
+    assert np.all(np.bincount(dd[acc], minlength=n) <= np.floor(wv))
