@@ -51,10 +51,6 @@ __device__ inline int find_segment(const int64_t *off, int nseg, int64_t x) {
     return lo;
 }
 
-__global__ void k_stamp(uint64_t *slot) {
-    if (threadIdx.x == 0) *slot = wall_clock64();
-}
-
 __global__ void k_batch_reset(const PopDesc *desc, int nd, unsigned long long *counter,
                               unsigned long long *stamps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -446,35 +446,6 @@ __global__ void k_level_offsets(const uint32_t *total, int64_t *level_off) {
     level_off[kDepth + 1] = run;
 }
 
-__global__ void k_emit(const uint8_t *dlev, const uint8_t *llev, int64_t n, const uint32_t *blkoff,
-                       int nblk, const int64_t *level_off, int32_t *nfirst, int32_t *nlevel) {
-    __shared__ uint32_t lds[kBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-    uint8_t d[kItems], ll[kItems];
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t i = base + k;
-        d[k] = i < n ? dlev[i] : (uint8_t)255;
-        ll[k] = i < n ? llev[i] : (uint8_t)0;
-    }
-    for (int l = 0; l <= kDepth; ++l) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) c += (d[k] <= l && l <= ll[k]) ? 1u : 0u;
-        uint32_t tot;
-        uint32_t r = block_exclusive_scan(c, lds, tot);
-        if (tot == 0) continue;
-        int64_t pos = level_off[l] + blkoff[(int64_t)l * nblk + blockIdx.x] + r;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            if (d[k] <= l && l <= ll[k]) {
-                nfirst[pos] = (int32_t)(base + k);
-                nlevel[pos] = l;
-                ++pos;
-            }
-    }
-}
-
 __global__ void k_nodes(const uint64_t *keys, int64_t n, const uint8_t *llev, int64_t n_nodes,
                         const int32_t *nlevel, const int32_t *nfirst, int32_t *ncount,
                         int32_t *ndigit, int32_t *nix, int32_t *niy, int32_t *niz) {
