@@ -344,11 +344,14 @@ __host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
 // cell-major moments, and its z pass (MODE 2) takes its rows in cell-column order
 // (ky, kx, ay, ax) and writes the cell-major Taylor grid.  Ga: the grid's cells along
 // y (MODE 1) or x (MODE 2).
-template <int RT, int MODE = 0>
-__device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int G, const float *T, int64_t r0,
+template <int RT, int MODE = 0, int PT = 0>
+__device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, int G, const float *T, int64_t r0,
                               float *sm, int Ga = 0) {
+    // PT = 8: the term count is a compile-time 8, so the tile's index arithmetic
+    // folds into constants and rows are read 16 bytes at a time; PT = 0: any p
     constexpr int NR = RT / 16;   // 16-wide column tiles per block
     constexpr int KC = 8;         // K steps (of 4) per operator chunk in registers
+    const int p = PT ? PT : p_rt;
     const int U = G * p;
     const int UP = U + 1;
     float *sIn = sm;
@@ -357,7 +360,54 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int
     for (int e = threadIdx.x; e < nT; e += 256) sT[e] = T[e];
     const int pp = p * p;
     const int p3 = pp * p;
-    if constexpr (MODE == 0) {
+    if constexpr (PT == 8) {
+        // U = 8 G: rows in 16-byte chunks, which never straddle a cell
+        const int U4 = U / 4;
+        if constexpr (MODE == 0) {
+            for (int e = threadIdx.x; e < RT * U4; e += 256) {
+                const int rr = e / U4, c4 = e - rr * U4;
+                const int64_t r = r0 + rr;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r < R) v = *reinterpret_cast<const float4 *>(In + r * U + 4 * c4);
+                float *d = sIn + rr * UP + 4 * c4;
+                d[0] = v.x;
+                d[1] = v.y;
+                d[2] = v.z;
+                d[3] = v.w;
+            }
+        } else {
+            int64_t *rowbase = reinterpret_cast<int64_t *>(sT + nT + (nT & 1));
+            for (int rr = threadIdx.x; rr < RT; rr += 256) {
+                const int64_t r = r0 + rr;
+                int64_t b = -1;
+                if (r < R) {
+                    if constexpr (MODE == 1) {
+                        const int Uy = Ga * 8;
+                        const int zq = (int)(r / Uy), yq = (int)(r % Uy);
+                        b = ((int64_t)(zq >> 3) * Ga + (yq >> 3)) * G * 512 + ((zq & 7) * 8 + (yq & 7)) * 8;
+                    } else {
+                        const int c = (int)(r >> 6), rem = (int)(r & 63);
+                        b = ((int64_t)((c / Ga) * 8 + (rem >> 3)) * Ga * 8 + (c % Ga) * 8 + (rem & 7)) * U;
+                    }
+                }
+                rowbase[rr] = b;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < RT * U4; e += 256) {
+                const int rr = e / U4, c4 = e - rr * U4;
+                const int64_t b = rowbase[rr];
+                // MODE 1: column u = 4 c4 is (cell u / 8, term u % 8), 512 floats per cell
+                const int64_t col = MODE == 1 ? (int64_t)(c4 >> 1) * 512 + (c4 & 1) * 4 : 4 * c4;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (b >= 0) v = *reinterpret_cast<const float4 *>(In + b + col);
+                float *d = sIn + rr * UP + 4 * c4;
+                d[0] = v.x;
+                d[1] = v.y;
+                d[2] = v.z;
+                d[3] = v.w;
+            }
+        }
+    } else if constexpr (MODE == 0) {
         for (int e = threadIdx.x; e < RT * U; e += 256) {
             const int rr = e / U, u = e % U;
             const int64_t r = r0 + rr;
@@ -401,17 +451,24 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int
 #pragma unroll
         for (int j = 0; j < NR; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
         int s = (lane >> 4) / p, ai = (lane >> 4) % p;   // column u = 4 k + lane / 16 as (cell, term)
+        // p = 8: entry of step k at base8 - 64 (k / 2) + 4 (k % 2)
+        const int base8 = ((tv + G - 1) * 8 + b) * 8 + (lane >> 4);
         for (int k0 = 0; k0 < nk; k0 += KC) {
             // this lane's operator entries M[v][u] for KC steps
             float a[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                const int u = 4 * (k0 + k) + (lane >> 4);
-                a[k] = (v < U && u < U) ? sT[((tv - s + G - 1) * p + b) * p + ai] : 0.f;
-                ai += 4;
-                while (ai >= p) {
-                    ai -= p;
-                    ++s;
+                if constexpr (PT == 8) {
+                    const int kk = k0 + k;
+                    a[k] = (v < U && kk < nk) ? sT[base8 - 64 * (kk >> 1) + 4 * (kk & 1)] : 0.f;
+                } else {
+                    const int u = 4 * (k0 + k) + (lane >> 4);
+                    a[k] = (v < U && u < U) ? sT[((tv - s + G - 1) * p + b) * p + ai] : 0.f;
+                    ai += 4;
+                    while (ai >= p) {
+                        ai -= p;
+                        ++s;
+                    }
                 }
             }
 #pragma unroll
@@ -419,8 +476,13 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p, int
                 const float *bcol = sIn + (16 * j + (lane & 15)) * UP + (lane >> 4);
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
-                    const int u = 4 * (k0 + k) + (lane >> 4);
-                    const float bv = u < U ? bcol[4 * (k0 + k)] : 0.f;
+                    float bv;
+                    if constexpr (PT == 8) {
+                        bv = k0 + k < nk ? bcol[4 * (k0 + k)] : 0.f;
+                    } else {
+                        const int u = 4 * (k0 + k) + (lane >> 4);
+                        bv = u < U ? bcol[4 * (k0 + k)] : 0.f;
+                    }
                     acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bv, acc[j], 0, 0, 0);
                 }
             }
@@ -447,7 +509,8 @@ template <int RT>
 __global__ void __launch_bounds__(256) k_m2l_gemm(const float *In, float *Out, int64_t R, int p, int G,
                                                   const float *T) {
     extern __shared__ float sm[];
-    m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
+    if (p == 8) m2l_gemm_tile<RT, 0, 8>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
+    else m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
 }
 
 // The same pass with split bfloat16 products (v_mfma_f32_16x16x32_bf16): each
@@ -1552,12 +1615,21 @@ __global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp) {
     const int p = bp.p;
     const int64_t Ux = (int64_t)f.G[0] * p, Uy = (int64_t)f.G[1] * p, Uz = (int64_t)f.G[2] * p;
     const int64_t r0 = (g - bp.tile_off[PASS][k]) * 32;
-    if constexpr (PASS == 0)
-        m2l_gemm_tile<32, 1>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
-    else if constexpr (PASS == 1)
-        m2l_gemm_tile<32, 0>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
-    else
-        m2l_gemm_tile<32, 2>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
+    if (p == 8) {
+        if constexpr (PASS == 0)
+            m2l_gemm_tile<32, 1, 8>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
+        else if constexpr (PASS == 1)
+            m2l_gemm_tile<32, 0, 8>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
+        else
+            m2l_gemm_tile<32, 2, 8>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
+    } else {
+        if constexpr (PASS == 0)
+            m2l_gemm_tile<32, 1>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
+        else if constexpr (PASS == 1)
+            m2l_gemm_tile<32, 0>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
+        else
+            m2l_gemm_tile<32, 2>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
+    }
 }
 
 // Taylor series of cell (kx, ky, kz) at its points [s0, e) by one wavefront (grid

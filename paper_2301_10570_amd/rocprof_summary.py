@@ -4,6 +4,7 @@
     python paper_2301_10570_amd/rocprof_summary.py stats KERNEL_STATS_CSV --command CMD
     python paper_2301_10570_amd/rocprof_summary.py traffic --fetch FETCH_CSV --write WRITE_CSV \\
         --kernel NAME --source FILE --copy-bytes B --command CMD
+    python paper_2301_10570_amd/rocprof_summary.py util COUNTER_CSV --command CMD --kernels K1,K2
 
 `stats` lists every kernel of a `--kernel-trace --stats` run (calls, total and
 average duration).  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters
@@ -86,6 +87,34 @@ def traffic(fetch: str, write: str, kernel: str, source: str, copy_bytes: float,
     return "\n".join(out)
 
 
+def util(path: str, command: str, kernels) -> str:
+    """Mean of each derived counter per kernel (percent or flops per dispatch)."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        name = re.sub(r"<.*>$", "", short_name(r["Kernel_Name"]))
+        per.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for d in per.values() for c in d})
+    out = ["# Matrix-core and vector-ALU utilisation per kernel", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+           "    " + command, "",
+           "MfmaUtil: percent of the time the matrix units are busy (sum of busy cycles over all",
+           "SIMDs / (GPU active cycles x SIMDs)); VALUBusy: percent of the time vector instructions",
+           "are processed; MfmaFlopsF32: FP32 matrix flops per dispatch.  Kernels run one at a time",
+           "under counter collection.", "",
+           "| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---:|" + "---:|" * len(names)]
+    for k in kernels:
+        if k not in per:
+            continue
+        d = per[k]
+        n = max(len(v) for v in d.values())
+        cells = []
+        for c in names:
+            v = d.get(c)
+            cells.append("-" if not v else (f"{sum(v) / len(v):.3e}" if "Flops" in c else f"{sum(v) / len(v):.1f}"))
+        out.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -99,7 +128,14 @@ def main():
     b.add_argument("--source", required=True)
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--command", required=True)
+    c = sub.add_parser("util")
+    c.add_argument("csv")
+    c.add_argument("--command", required=True)
+    c.add_argument("--kernels", required=True, help="comma-separated short kernel names")
     args = ap.parse_args()
+    if args.what == "util":
+        sys.stdout.write(util(args.csv, args.command, args.kernels.split(",")))
+        return
     if args.what == "stats":
         sys.stdout.write(stats(args.csv, args.command))
     else:
