@@ -7,7 +7,8 @@
 // leaves of the list are read 64 entries at a time and their points concatenated,
 // so that a chunk of 64 staged sources may span several leaves.  Chunk partials
 // are added with compensation.  exp(-d^2/sigma^2) is evaluated as
-// exp2(-(k d)^2) with k^2 = log2(e)/sigma^2 (k = k_scale).
+// exp2(-(k d)^2) with k^2 = log2(e)/sigma^2 (k = k_scale); the sources of a chunk
+// sit in LDS as one 16-byte record each.
 #pragma once
 #include "internal.hpp"
 
@@ -43,7 +44,7 @@ struct LeafSet {
 };
 
 struct P2PShared {
-    float sx[64], sy[64], sz[64], sw[64];
+    float4 sp[64];   // staged sources: scaled offsets from the leaf centre, weight
     int32_t sid[64];
     float red[64];
     int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
@@ -112,21 +113,28 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
                 const int ns = tot - c0 < 64 ? tot - c0 : 64;
                 wave_sync();
                 if (lane < ns) {
-                    sh.sx[lane] = (nxt.x - ct[0]) * L.k_scale;
-                    sh.sy[lane] = (nxt.y - ct[1]) * L.k_scale;
-                    sh.sz[lane] = (nxt.z - ct[2]) * L.k_scale;
-                    sh.sw[lane] = nxt.w;
+                    sh.sp[lane] = make_float4((nxt.x - ct[0]) * L.k_scale, (nxt.y - ct[1]) * L.k_scale,
+                                              (nxt.z - ct[2]) * L.k_scale, nxt.w);
                     sh.sid[lane] = nid;
                 }
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
                 float part = 0.f;
-                for (int j = grp; j < ns; j += G) {
-                    const float dx = tx - sh.sx[j], dy = ty - sh.sy[j], dz = tz - sh.sz[j];
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    float e = sh.sw[j] * __builtin_amdgcn_exp2f(-d2);
-                    if (L.exclude_self && sh.sid[j] == ti) e = 0.f;
-                    part += e;
+                if (L.exclude_self) {
+                    for (int j = grp; j < ns; j += G) {
+                        const float4 q = sh.sp[j];
+                        const float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float e = q.w * __builtin_amdgcn_exp2f(-d2);
+                        part += sh.sid[j] == ti ? 0.f : e;
+                    }
+                } else {
+                    for (int j = grp; j < ns; j += G) {
+                        const float4 q = sh.sp[j];
+                        const float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        part = fmaf(q.w, __builtin_amdgcn_exp2f(-d2), part);
+                    }
                 }
                 // compensated addition of the chunk partial
                 const float y = part - comp;
