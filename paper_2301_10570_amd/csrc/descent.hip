@@ -273,10 +273,11 @@ int ctx_init(DescentCtx &c, msp_tree *t, const float *w, const float *a, const m
     c.t = t;
     c.n = t->n;
     c.nn = t->n_nodes;
-    MSP_TRY(partner_prepare(t, w, prm, s));   // staged w, inverse permutation, node moments
+    MSP_TRY(partner_prepare(t, w, prm, s));   // staged w, node moments
     MSP_HIP(hipStreamSynchronize(s));
     MSP_TRY(to_host(c.perm, t->perm.p, c.n));
-    MSP_TRY(to_host(c.iperm, t->iperm.p, c.n));
+    c.iperm.resize((size_t)c.n);
+    for (int64_t p = 0; p < c.n; ++p) c.iperm[c.perm[p]] = (int32_t)p;
     MSP_TRY(to_host(c.nfirst, t->nfirst.p, c.nn));
     MSP_TRY(to_host(c.ncount, t->ncount.p, c.nn));
     MSP_TRY(to_host(c.nfchild, t->nfchild.p, c.nn));
@@ -322,7 +323,7 @@ void range_of(const DescentCtx &c, int64_t item, int64_t &first, int64_t &count)
 }
 
 struct StepBufs {
-    DevBuf qt, qn, qa, raw, probs, ti, tcf, tnc, toff, ta, dv, crng, units, choice;
+    DevBuf qt, qs, qn, qa, raw, probs, ti, tcf, tnc, toff, ta, dv, crng, units, choice;
 };
 
 template <class T>
@@ -338,7 +339,7 @@ int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t se
               std::vector<int64_t> &T2, std::vector<int32_t> &ra, std::vector<int32_t> &rd, hipStream_t s) {
     S2.clear();
     T2.clear();
-    std::vector<int32_t> qt, qn, ti, tcf, tnc;
+    std::vector<int32_t> qt, qs, qn, ti, tcf, tnc;
     std::vector<float> qa, ta;
     std::vector<int64_t> toff, crng;
     std::vector<UnitDesc> units;
@@ -365,6 +366,7 @@ int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t se
             for (int64_t p = xf; p < xf + xc; ++p)
                 if (c.as[p] > 0.f) {
                     qt.push_back(c.perm[p]);
+                    qs.push_back((int32_t)p);
                     qn.push_back((int32_t)Tn);
                     qa.push_back(c.as[p]);
                 }
@@ -427,6 +429,7 @@ int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t se
     const int64_t nq = (int64_t)qt.size(), ntask = (int64_t)ti.size(), nu = (int64_t)units.size();
     if (nu == 0) return MSP_OK;
     MSP_TRY(upload(B.qt, qt));
+    MSP_TRY(upload(B.qs, qs));
     MSP_TRY(upload(B.qn, qn));
     MSP_TRY(upload(B.qa, qa));
     MSP_TRY(upload(B.ti, ti));
@@ -442,7 +445,7 @@ int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t se
     MSP_TRY(B.choice.ensure((size_t)nu * sizeof(int32_t)));
     if (nq > 0)
         MSP_TRY(partner_query_raw(c.t, prm, B.qt.as<int32_t>(), B.qn.as<int32_t>(), nq, B.probs.as<float>(),
-                                  B.raw.as<double>(), s));
+                                  B.raw.as<double>(), B.qs.as<int32_t>(), s));
     if (ntask > 0) {
         hipLaunchKernelGGL(k_desc_direct, dim3(grid_for(ntask, 4)), dim3(256), 0, s, ntask, B.ti.as<int32_t>(),
                            B.tcf.as<int32_t>(), B.tnc.as<int32_t>(), B.toff.as<int64_t>(), c.t->ps.as<float4>(),

@@ -133,6 +133,8 @@ struct msp_tree {
     bool lists_valid = false;
     // node moments for partner queries
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
+    msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
+    msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
 };
@@ -308,11 +310,13 @@ int direct_all_pairs(const float *tx, const float *ty, const float *tz, int64_t 
 int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
                           const int32_t *target_idx, const int32_t *node_id, int64_t nq,
                           const float *uniforms, float *probs, int32_t *choice, hipStream_t s);
-// stage the weights, inverse permutation and node moments once; then any number
-// of query batches with the unnormalised per-octant sums (raw: double[nq * 8])
+// stage the weights and node moments once; then any number of query batches with
+// the unnormalised per-octant sums (raw: double[nq * 8]); qpos: key-order positions
+// of the targets, or NULL to look them up
 int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s);
 int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
-                      const int32_t *node_id, int64_t nq, float *probs, double *raw, hipStream_t s);
+                      const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
+                      hipStream_t s);
 
 // descent.hip
 int descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
@@ -356,6 +360,13 @@ __host__ __device__ inline uint32_t compact3(uint64_t v) {
     v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
     v = (v ^ (v >> 32)) & 0x1fffffull;
     return (uint32_t)v;
+}
+
+// q = min(floor((x - lo) * scale), 2^21 - 1) in float64: a subtraction, then a
+// multiplication, each rounded once (no contraction is possible in this form).
+__device__ inline uint32_t quantise(float v, double lo, double scale) {
+    double q = floor(((double)v - lo) * scale);
+    return q >= (double)kQMax ? kQMax : (uint32_t)q;
 }
 
 __host__ __device__ inline uint64_t morton3(uint32_t qx, uint32_t qy, uint32_t qz) {

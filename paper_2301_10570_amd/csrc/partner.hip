@@ -39,23 +39,110 @@ constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest con
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
 
-// Sources below the nodes of one level: leaves count their points, inner nodes
-// add up their children (levels are processed from the deepest up).
-__global__ void k_nsrc_level(int64_t v0, int64_t v1, const int32_t *nfirst, const int32_t *ncount,
-                             const int32_t *nfchild, const int32_t *nnchild, const float4 *ps,
-                             int32_t *nsrc) {
-    const int64_t v = v0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= v1) return;
-    const int32_t nc = nnchild[v];
-    int32_t k = 0;
-    if (nc == 0) {
-        const int32_t f = nfirst[v], c = ncount[v];
-        for (int32_t j = f; j < f + c; ++j) k += ps[j].w != 0.f;
-    } else {
-        const int32_t fc = nfchild[v];
-        for (int q = 0; q < nc; ++q) k += nsrc[fc + q];
+// Sources (staged weight != 0) below every node, from an exclusive prefix count
+// S over the points in key order: nsrc(v) = S[first + count] - S[first].
+// Tiles of kSrcTile points, point k * 256 + t of a tile to thread t.
+constexpr int kSrcItems = 16;
+constexpr int kSrcTile = 256 * kSrcItems;
+
+__device__ inline int32_t block_sum_256(int32_t v, int32_t *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    return lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+__global__ void __launch_bounds__(256) k_src_tiles(int64_t n, const float4 *ps, int32_t *tile_sum) {
+    __shared__ int32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kSrcTile;
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kSrcItems; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < n) c += ps[i].w != 0.f ? 1 : 0;
     }
-    nsrc[v] = k;
+    const int32_t tot = block_sum_256(c, lds);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// exclusive scan of the tile sums in place (one block, chunks of 1024)
+__global__ void __launch_bounds__(1024) k_src_tile_scan(int64_t nt, int32_t *tile) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nt; c0 += 1024) {
+        const int64_t g = c0 + threadIdx.x;
+        const int32_t v = g < nt ? tile[g] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (g < nt) tile[g] = carry + part[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+// S[i] for the points of one tile (S[n] = total from the tile holding point n - 1)
+__global__ void __launch_bounds__(256) k_src_prefix(int64_t n, const float4 *ps, const int32_t *tile_off,
+                                                    int32_t *S) {
+    __shared__ int32_t wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSrcTile;
+    int32_t run = tile_off[blockIdx.x];
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int k = 0; k < kSrcItems; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        const bool f = i < n && ps[i].w != 0.f;
+        const uint64_t m = __ballot(f);
+        __syncthreads();
+        if (lane == 0) wsum[wave] = (int32_t)__popcll(m);
+        __syncthreads();
+        int32_t before = run;
+        for (int q = 0; q < wave; ++q) before += wsum[q];
+        before += (int32_t)__popcll(m & below);
+        if (i < n) S[i] = before;
+        if (i == n - 1) S[n] = before + (f ? 1 : 0);
+        run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    }
+}
+
+__global__ void k_nsrc_nodes(int64_t nn, const int32_t *nfirst, const int32_t *ncount, const int32_t *S,
+                             int32_t *nsrc) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= nn) return;
+    const int32_t f = nfirst[v];
+    nsrc[v] = S[f + ncount[v]] - S[f];
+}
+
+// Key-order position of each query's target: its Morton key (as the tree build
+// computes it) is searched among the sorted keys, then the run of equal keys is
+// scanned for the point itself.  -1 for an index out of range.
+__global__ void k_query_pos(int64_t nq, const int32_t *target_idx, int64_t n, const float4 *pin,
+                            const uint64_t *keys, const int32_t *perm, double lx, double ly, double lz,
+                            double scale, int32_t *qpos) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int32_t t = target_idx[q];
+    int32_t pos = -1;
+    if (t >= 0 && t < n) {
+        const float4 a = pin[t];
+        const uint64_t key = morton3(quantise(a.x, lx, scale), quantise(a.y, ly, scale), quantise(a.z, lz, scale));
+        for (int64_t p = lower_bound_u64(keys, 0, n, key); p < n && keys[p] == key; ++p)
+            if (perm[p] == t) {
+                pos = (int32_t)p;
+                break;
+            }
+    }
+    qpos[q] = pos;
 }
 
 __device__ inline double wave_sum(double x) {
@@ -481,7 +568,7 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
 // are finished here.
 __global__ void __launch_bounds__(256)
 k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
-                int64_t n, int64_t n_nodes, const int32_t *iperm, const int32_t *nlevel,
+                int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
                 const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
                 const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
                 double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
@@ -496,7 +583,7 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
     if (ok) {
         ti = target_idx[q];
         X = node_id[q];
-        ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
+        ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
     }
     if (ok) {
         nc = nnchild[X];
@@ -514,7 +601,7 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
         if (q < nq && c == 0) done[q] = 0;
         return;   // the whole group leaves together
     }
-    const int32_t si = iperm[ti];
+    const int32_t si = qpos[q];
     const float4 qt = ps[si];
     const double tx = qt.x, ty = qt.y, tz = qt.z;
     const double kexp = 1.4426950408889634 / (sigma * sigma);
@@ -615,7 +702,7 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
 template <int P>
 __global__ void __launch_bounds__(64)
 k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
-          int64_t n, int64_t n_nodes, const int32_t *iperm, const int32_t *nlevel,
+          int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
           const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
           const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
           double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
@@ -628,7 +715,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     const int lane = threadIdx.x;
     if (q >= nq || done[q]) return;
     const int32_t ti = target_idx[q], X = node_id[q];
-    const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes;
+    const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
     const int nc = ok ? nnchild[X] : 0;
     const int32_t fc = ok ? nfchild[X] : 0;
     if (nc == 0 || fc <= X || fc + nc > n_nodes) {
@@ -637,7 +724,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         if (lane == 0 && choice) choice[q] = -1;
         return;
     }
-    const int32_t si = iperm[ti];
+    const int32_t si = qpos[q];
     const float4 qt = ps[si];
     const double tx = qt.x, ty = qt.y, tz = qt.z;
     const double inv_sigma = 1.0 / sigma;
@@ -943,14 +1030,21 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
         PhaseScope ps(&t->timing, PH_NODE_MOMENTS, s);
         {
             PhaseScope ps_counts(&t->timing, PH_NODE_COUNTS, s);
-            for (int l = t->depth; l >= lh && l >= 0; --l) {
-                const int64_t a = t->level_off[l], b = t->level_off[l + 1];
-                if (b <= a) continue;
-                hipLaunchKernelGGL(k_nsrc_level, dim3(grid_for(b - a, kBlock)), dim3(kBlock), 0, s, a, b,
-                                   t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                                   t->nnchild.as<int32_t>(), t->ps.as<float4>(), t->node_nsrc.as<int32_t>());
-                MSP_CHECK_LAUNCH();
-            }
+            const int64_t n = t->n;
+            const int64_t ntile = (n + kSrcTile - 1) / kSrcTile;
+            MSP_TRY(t->src_prefix.ensure((size_t)(n + 1 + ntile) * 4));
+            int32_t *S = t->src_prefix.as<int32_t>();
+            int32_t *tile = S + n + 1;
+            if (n == 0) return fail(MSP_EINVAL, "node moments of an empty tree");
+            hipLaunchKernelGGL(k_src_tiles, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_src_tile_scan, dim3(1), dim3(1024), 0, s, ntile, tile);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_src_prefix, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile, S);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_nsrc_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn,
+                               t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), S, t->node_nsrc.as<int32_t>());
+            MSP_CHECK_LAUNCH();
         }
         for (int l = t->depth; l >= 0; --l) {
             const int64_t a = t->level_off[l], b = t->level_off[l + 1];
@@ -983,8 +1077,16 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
 template <int P>
 int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                     const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
-                    int32_t *choice, double *raw, hipStream_t s) {
+                    int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s) {
     if (nq == 0) return MSP_OK;
+    if (!qpos) {   // key-order positions of the targets
+        MSP_TRY(t->partner_qpos.ensure((size_t)nq * 4));
+        hipLaunchKernelGGL(k_query_pos, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, target_idx, t->n,
+                           t->pin.as<float4>(), t->keys.as<uint64_t>(), t->perm.as<int32_t>(), t->geo.lo[0],
+                           t->geo.lo[1], t->geo.lo[2], t->geo.scale, t->partner_qpos.as<int32_t>());
+        MSP_CHECK_LAUNCH();
+        qpos = t->partner_qpos.as<int32_t>();
+    }
     const double sigma = prm->sigma;
     const double rmax = rho_max_for_p(P);
     const int lh = moment_level(t, sigma, P);
@@ -996,7 +1098,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     {
         PhaseScope pl(&t->timing, PH_PARTNER_LEAFY, s);
         hipLaunchKernelGGL(k_partner_leafy, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, target_idx,
-                           node_id, uniforms, t->n, nn, t->iperm.as<int32_t>(), t->nlevel.as<int32_t>(),
+                           node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
                            t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                            t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
                            t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
@@ -1007,7 +1109,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     }
     PhaseScope ps(&t->timing, PH_PARTNER, s);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nq), dim3(64), 0, s, nq, target_idx,
-                       node_id, uniforms, t->n, nn, t->iperm.as<int32_t>(), t->nlevel.as<int32_t>(),
+                       node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
                        t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                        t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
                        t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
@@ -1025,7 +1127,7 @@ int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_id
                 const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
                 int32_t *choice, hipStream_t s) {
     MSP_TRY(partner_moments<P>(t, prm, s));
-    return partner_queries<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, nullptr, s);
+    return partner_queries<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, nullptr, nullptr, s);
 }
 
 int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,
@@ -1036,7 +1138,6 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
         return MSP_OK;
     }
     MSP_TRY(stage_inputs(t, w, nullptr, s));
-    MSP_TRY(ensure_iperm(t, s));
     switch (prm->p) {
 #define CASE(P) case P: return run_partner<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -1049,7 +1150,6 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
 
 int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s) {
     MSP_TRY(stage_inputs(t, w, nullptr, s));
-    MSP_TRY(ensure_iperm(t, s));
     switch (prm->p) {
 #define CASE(P) case P: return partner_moments<P>(t, prm, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -1060,9 +1160,10 @@ int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipS
 }
 
 int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
-                      const int32_t *node_id, int64_t nq, float *probs, double *raw, hipStream_t s) {
+                      const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
+                      hipStream_t s) {
     switch (prm->p) {
-#define CASE(P) case P: return partner_queries<P>(t, prm, target_idx, node_id, nq, nullptr, probs, nullptr, raw, s);
+#define CASE(P) case P: return partner_queries<P>(t, prm, target_idx, node_id, nq, nullptr, probs, nullptr, raw, qpos, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE

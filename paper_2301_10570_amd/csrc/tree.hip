@@ -103,13 +103,6 @@ __global__ void k_bbox_final(const float *part, int nparts, float *out) {
 
 // ---- keys ----------------------------------------------------------------------------------
 
-// q = min(floor((x - lo) * scale), 2^21 - 1) in float64: a subtraction, then a
-// multiplication, each rounded once (no contraction is possible in this form).
-__device__ inline uint32_t quantise(float v, double lo, double scale) {
-    double q = floor(((double)v - lo) * scale);
-    return q >= (double)kQMax ? kQMax : (uint32_t)q;
-}
-
 __global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, double lx,
                          double ly, double lz, double scale, uint64_t *key, int32_t *idx,
                          float4 *pin) {
