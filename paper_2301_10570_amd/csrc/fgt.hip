@@ -18,6 +18,9 @@
 // included (no cutoff); operator entries for far offsets underflow to zero.
 #include "internal.hpp"
 
+#include <algorithm>
+#include <cstring>
+
 #include <cmath>
 
 namespace msp {
@@ -1903,6 +1906,7 @@ int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, F
     MSP_TRY(t->gridA.ensure(gbytes));
     MSP_TRY(t->gridB.ensure(gbytes));
     MSP_TRY(t->ops.ensure(gbytes + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4));
+    t->ops_valid = false;   // the batched pass writes the tables itself
     t->grid_bytes_valid = (int64_t)gbytes;
     f->keys = t->keys.as<uint64_t>();
     f->ps = t->ps.as<float4>();
@@ -2023,7 +2027,9 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
     const size_t gbytes = (size_t)ncell * p * p * p * 4;
     MSP_TRY(t->gridA.ensure(gbytes));
     MSP_TRY(t->gridB.ensure(gbytes));
+    const size_t ops_bytes_before = t->ops.bytes;
     MSP_TRY(t->ops.ensure(gbytes + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4));
+    if (t->ops.bytes != ops_bytes_before) t->ops_valid = false;   // reallocated
     t->grid_bytes_valid = (int64_t)gbytes;
     if (t->n == 0) return MSP_OK;
     float *A = t->gridA.as<float>();
@@ -2033,12 +2039,18 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
     float *opsy = opsx + (size_t)(2 * pl.G[0] - 1) * p * p;
     float *opsz = opsy + (size_t)(2 * pl.G[1] - 1) * p * p;
     const double step = pl.cell / prm->sigma;
-    {
+    // the operator tables depend on (p, grid, cell / sigma) only: kept from the last
+    // call when those are unchanged
+    uint64_t sig[5] = {(uint64_t)p, (uint64_t)pl.G[0], (uint64_t)pl.G[1], (uint64_t)pl.G[2], 0};
+    std::memcpy(&sig[4], &step, sizeof(double));
+    if (!t->ops_valid || !std::equal(sig, sig + 5, t->ops_sig)) {
         PhaseScope ps(&t->timing, PH_OPS, s);
         const int nops = 2 * (pl.G[0] + pl.G[1] + pl.G[2]) - 3;
         hipLaunchKernelGGL(k_m2l_ops, dim3(grid_for(nops, 64)), dim3(64), 0, s, p, pl.G[0], pl.G[1],
                            pl.G[2], step, opsx, opsy, opsz);
         MSP_CHECK_LAUNCH();
+        std::copy(sig, sig + 5, t->ops_sig);
+        t->ops_valid = true;
     }
     const double inv_sigma = 1.0 / prm->sigma;
     {

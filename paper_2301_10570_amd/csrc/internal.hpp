@@ -125,6 +125,8 @@ struct msp_tree {
     msp::DevBuf bwd;   // backward scratch: field values, gradients, Laplacians, reductions
     // expansion grids and translation operators
     msp::DevBuf gridA, gridB, ops;
+    bool ops_valid = false;     // M2L operator tables in ops match ops_sig (p, grid, cell / sigma)
+    uint64_t ops_sig[5] = {};
     int64_t grid_bytes_valid = 0;
     // direct-route interaction lists (cached per sigma/cutoff)
     msp::DevBuf list_off, list_idx, list_cnt;
