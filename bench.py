@@ -31,9 +31,9 @@ PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12}
 
 # phase -> kernel it times (one kernel per launch of the phase)
 KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "sort_runs": "k_seg_sort",
-                   "p2m": "k_p2m",
-                   "l2p": "k_l2p", "m2l_x": "k_m2l_pass_mfma", "m2l_y": "k_m2l_pass_mfma",
-                   "m2l_z": "k_m2l_pass_mfma", "morton": "k_morton", "stage": "k_stage",
+                   "p2m": "k_p2m_mfma8",
+                   "l2p": "k_l2p", "m2l_x": "k_m2l_gemm", "m2l_y": "k_m2l_gemm",
+                   "m2l_z": "k_m2l_gemm", "morton": "k_morton", "stage": "k_stage",
                    "partner": "k_partner", "partner_leafy": "k_partner_leafy"}
 
 
@@ -45,7 +45,8 @@ def _algorithmic(phase, ctx):
     n, ns, nt, p = ctx["n"], ctx["n_src"], ctx["n_tgt"], ctx["p"]
     p3 = p ** 3
     if phase == "p2m":
-        return "alu", "TFLOP/s", 2.0 * p3 * ns
+        # p = 8: moments as a matrix-core product (k_p2m_mfma8)
+        return ("mfma" if p == 8 else "alu"), "TFLOP/s", 2.0 * p3 * ns
     if phase == "l2p":
         return "alu", "TFLOP/s", 2.0 * p3 * nt
     if phase in ("m2l_x", "m2l_y", "m2l_z"):

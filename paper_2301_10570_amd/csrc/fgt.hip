@@ -208,6 +208,97 @@ __global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n,
     p2m_cell<P>(ps, perm, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, A, kx, ky, kz, start, end);
 }
 
+// P2M of one grid cell for p = 8 on the matrix cores.  With ay = 2 ay_hi + ay_lo the
+// moments form a 16 x 32 matrix product over the cell's points,
+//   M[(ax, ay_lo)][(ay_hi, az)] = sum_j X_j^ax Y_j^ay_lo * w_j Y_j^(2 ay_hi) Z_j^az,
+// taken four points at a time by v_mfma_f32_16x16x4f32 (two 16-column tiles).  The
+// cell's points pass through LDS 256 at a time with their powers (X^k, Y^k and
+// w Z^k, k < 8), one point per thread, the next chunk held in registers; each wave
+// takes 64 of them, and the four waves' products are added in wave order at the end.
+// One block per cell; output in the grid layout [kz][az][ky][ay][kx][ax].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kPowStr = 25;   // floats per staged point (24 powers, padded)
+__global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int64_t n, const float4 *ps,
+                                                      const int32_t *perm, const float *w, int level, int Gx,
+                                                      int Gy, int Gz, double lox, double loy, double loz,
+                                                      double cell, double inv_sigma, float *A) {
+    __shared__ float pw[kBlock * kPowStr];
+    __shared__ float red[kBlock / 64][512];
+    const int64_t g = blockIdx.x;
+    const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
+    int64_t start, end;
+    cell_range(keys, n, level, kx, ky, kz, start, end);
+    const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto fetch = [&](int64_t c0) {
+        const int64_t j = c0 + tid;
+        nxt = make_float4(0.f, 0.f, 0.f, 0.f);   // past the cell: zero weight
+        if (j < end) {
+            const float4 q = ps[j];
+            nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
+                              (float)(((double)q.z - cz) * inv_sigma), w[perm[j]]);
+        }
+    };
+    // this lane's operand slots: row m = (ax, ay_lo), column n = (ay_hi within the tile, az)
+    const int m = lane & 15, kq = lane >> 4;
+    const int ax = m >> 1, aylo = m & 1;
+    const int n16 = lane & 15, azc = n16 & 7, ayh0 = n16 >> 3;
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+    fetch(start);
+    for (int64_t c0 = start; c0 < end; c0 += kBlock) {
+        __syncthreads();
+        {
+            float *r = pw + tid * kPowStr;
+            float xp = 1.f, yp = 1.f, wz = nxt.w;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                r[k] = xp;
+                r[8 + k] = yp;
+                r[16 + k] = wz;
+                xp *= nxt.x;
+                yp *= nxt.y;
+                wz *= nxt.z;
+            }
+        }
+        __syncthreads();
+        if (c0 + kBlock < end) fetch(c0 + kBlock);
+        const int cnt = end - c0 < kBlock ? (int)(end - c0) : kBlock;
+        const int w0 = wid * 64;
+        if (w0 < cnt) {
+            const int steps = ((cnt - w0 < 64 ? cnt - w0 : 64) + 3) / 4;   // rows past the cell weigh 0
+            for (int st = 0; st < steps; ++st) {
+                const float *r = pw + (w0 + 4 * st + kq) * kPowStr;
+                const float a = r[ax] * r[8 + aylo];
+                const float b0 = r[8 + 2 * ayh0] * r[16 + azc];
+                const float b1 = r[8 + 2 * (ayh0 + 2)] * r[16 + azc];
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
+            }
+        }
+    }
+    // D[4 kq + i][n16] of both tiles -> red[wave][(az * 8 + ay) * 8 + ax]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int mm = 4 * kq + i, axo = mm >> 1, aylo_o = mm & 1;
+        red[wid][(azc * 8 + 2 * ayh0 + aylo_o) * 8 + axo] = acc0[i];
+        red[wid][(azc * 8 + 2 * (ayh0 + 2) + aylo_o) * 8 + axo] = acc1[i];
+    }
+    __syncthreads();
+    const int64_t Rx = (int64_t)Gx * 8, Ry = (int64_t)Gy * 8;
+    for (int e = tid; e < 512; e += kBlock) {
+        float sum = 0.f;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) sum += red[q][e];
+        const int ex = e & 7, ey = (e >> 3) & 7, ez = e >> 6;
+        float f = 1.f;
+        for (int k = 2; k <= ex; ++k) f *= (float)k;
+        for (int k = 2; k <= ey; ++k) f *= (float)k;
+        for (int k = 2; k <= ez; ++k) f *= (float)k;
+        A[(((int64_t)kz * 8 + ez) * Ry + (int64_t)ky * 8 + ey) * Rx + (int64_t)kx * 8 + ex] = sum / f;
+    }
+}
+
 // Out[v][r] = sum_u In[r][u] * T[(v/p) - (u/p) + G - 1][v%p][u%p], u, v in [0, G*p).
 constexpr int TR = 64, TV = 64, TK = 16;
 __global__ void __launch_bounds__(kBlock) k_m2l_pass(const float *In, float *Out, int64_t R, int p,
@@ -269,7 +360,6 @@ __global__ void __launch_bounds__(kBlock) k_m2l_pass(const float *In, float *Out
 // One wavefront per 32 x 32 tile of D, built from 2 x 2 MFMA tiles; K steps of 16.
 // Lane layout of the 16x16x4 instruction: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and receives D[4*(l/16) + i][l%16], i = 0..3.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 32, MK = 16;
 __device__ void m2l_tile_mfma(const float *In, float *Out, int64_t R, int p, int G, const float *T, int64_t r0,
                               int v0) {
@@ -1085,7 +1175,11 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
             }
         }
     }
-    if (!l2p) {
+    if (!l2p && P == 8) {
+        hipLaunchKernelGGL(k_p2m_mfma8, dim3((unsigned)ncell), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), t->n,
+                           t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2],
+                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A);
+    } else if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
                            ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
