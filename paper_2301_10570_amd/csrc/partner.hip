@@ -31,6 +31,7 @@ double rho_max_for_p(int p);
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBlock = 256;
 constexpr int kC1 = 70;                    // Algorithm 2's element threshold
 constexpr int kStack = 2048;                 // walk stack of one query (LDS)
@@ -272,18 +273,26 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
                const int32_t *nsrc, uint8_t *hasA, float *nodeA, int64_t slot0) {
     constexpr int P2 = P * P, P3 = P2 * P;
     constexpr int RP = (P2 + 63) / 64;                  // (ay, az) rows per lane
-    constexpr bool ILP = P == 1 || P == 2 || P == 4 || P == 8;
-    constexpr int STR = ILP ? 4 : 3 * P + 1;            // staged floats per point
+    constexpr bool MX = P == 8;                         // P2M on the matrix cores
+    constexpr bool ILP = P == 1 || P == 2 || P == 4;
+    constexpr int STR = MX ? 24 : ILP ? 4 : 3 * P + 1;  // staged floats per point
     constexpr int PR = P + 1;                           // padded row of a child block
     // about 4.5 KB of shift buffers, so that the wave's LDS stays near 8 KB and four
     // waves fit on each SIMD
     constexpr int G0 = 4608 / (P2 * PR * 4);
     constexpr int G = !M2M ? 1 : (G0 < 1 ? 1 : (G0 > 8 ? 8 : G0));   // child blocks shifted together
-    __shared__ __align__(16) float pts[64 * STR];
+    // P <= 8: the eight child octants are shifted as a reduction tree (x-shifted
+    // pairs summed, then y, then z), with four blocks in LDS; larger P: G child
+    // blocks at a time, each shifted along x, y and z
+    constexpr bool TREE = P <= 8;
+    // the staged points and the shift buffers are used one after the other
+    constexpr int NPTS = 64 * STR, NCB = !M2M ? 1 : TREE ? 4 * P2 * PR : G * P2 * PR;
+    __shared__ __align__(16) float pts[NPTS > NCB ? NPTS : NCB];
     __shared__ float tot[P3];
-    __shared__ float cbuf[M2M ? G * P2 * PR : 1];
+    float *cbuf = pts;
     __shared__ float shift[2][P];                       // d^k / k! for the two child offsets
     __shared__ int32_t part_first[64], part_end[64];
+    __shared__ int32_t och[8];                          // child of each octant digit with moments
     const int lane = threadIdx.x;
     const double h = side / (double)(1ll << level);
     if (lane < 2 * P) {
@@ -328,11 +337,73 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
             for (int k = 0; k < P; ++k) acc[rr][k] = 0.f;
 
         // P2M (Eq. (7)) over the flattened points
-        if constexpr (ILP) {
+        if constexpr (MX) {
+            // with ay = 2 ay_hi + ay_lo the moments are the 16 x 32 product
+            //   M[(ax, ay_lo)][(ay_hi, az)] = sum_j X_j^ax Y_j^ay_lo * w_j Y_j^(2 ay_hi) Z_j^az,
+            // four points per v_mfma_f32_16x16x4f32 (two 16-column tiles); the points
+            // pass through LDS 64 at a time as their powers X^k, Y^k and w Z^k (k < 8),
+            // the next chunk held in registers
+            const int mr = lane & 15, kq = lane >> 4;
+            const int ax = mr >> 1, aylo = mr & 1, azc = mr & 7, ayh = mr >> 3;
+            f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+            int owner = 0;
+            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            auto fetch = [&](int32_t c0) {
+                const int32_t j = c0 + lane;
+                nxt = make_float4(0.f, 0.f, 0.f, 0.f);   // past the list: weight 0
+                if (j < total) {
+                    while (part_end[owner] <= j) ++owner;
+                    const float4 q = ps[part_first[owner] + j];
+                    nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
+                                      (float)(((double)q.z - cz) * inv_sigma), q.w);
+                }
+            };
+            __syncthreads();   // part_first / part_end written above
+            fetch(0);
+            for (int32_t c0 = 0; c0 < total; c0 += 64) {
+                __syncthreads();
+                {
+                    float *r = pts + lane * STR;
+                    float xp = 1.f, yp = 1.f, wz = nxt.w;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        r[k] = xp;
+                        r[8 + k] = yp;
+                        r[16 + k] = wz;
+                        xp *= nxt.x;
+                        yp *= nxt.y;
+                        wz *= nxt.z;
+                    }
+                }
+                __syncthreads();
+                if (c0 + 64 < total) fetch(c0 + 64);
+                const int m = total - c0 < 64 ? total - c0 : 64;
+                for (int st = 0; st < (m + 3) / 4; ++st) {
+                    const float *r = pts + (4 * st + kq) * STR;
+                    const float a = r[ax] * r[8 + aylo];
+                    const float wzv = r[16 + azc];
+                    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[8 + 2 * ayh] * wzv, d0, 0, 0, 0);
+                    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[8 + 2 * ayh + 4] * wzv, d1, 0, 0, 0);
+                }
+            }
+            // D[4 kq + i][n] of the two tiles, times 1 / (ax! ay! az!)
+            float fz = 1.f;
+            for (int k = 2; k <= azc; ++k) fz *= (float)k;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mm = 4 * kq + i, axo = mm >> 1, ay0 = 2 * ayh + (mm & 1), ay1 = ay0 + 4;
+                float fx = 1.f, f0 = 1.f, f1 = 1.f;
+                for (int k = 2; k <= axo; ++k) fx *= (float)k;
+                for (int k = 2; k <= ay0; ++k) f0 *= (float)k;
+                for (int k = 2; k <= ay1; ++k) f1 *= (float)k;
+                tot[(azc * 8 + ay0) * 8 + axo] = d0[i] / (fx * f0 * fz);
+                tot[(azc * 8 + ay1) * 8 + axo] = d1[i] / (fx * f1 * fz);
+            }
+        } else if constexpr (ILP) {
             // lane = (point group, ay half, az): each lane accumulates the (ay, ax) block
             // of its az and half of the ay range over every NG-th staged point; the
             // groups are added by butterfly shuffles
-            constexpr int H = P == 8 ? 2 : 1;     // ay halves (keeps 32 accumulators at P = 8)
+            constexpr int H = 1;                  // ay halves per lane group
             constexpr int AY = P / H;
             constexpr int NG = 64 / (P * H);
             const int az = lane % P, ah = (lane / P) % H, grp = lane / (P * H);
@@ -458,10 +529,88 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
             }
         }
 
-        // M2M of the children that carry moments, G blocks at a time:
+        // M2M of the children that carry moments:
         // A'_a = sum_{g<=a} A_g d^(a-g)/(a-g)! along x, then y, then z
         uint64_t todo = M2M ? __ballot(chas) : 0ull;
-        while (M2M && todo) {
+        if constexpr (M2M && TREE) {
+            if (todo) {
+                // octant digit 4 bx + 2 by + bz; pairs q = 2 by + bz
+                if (lane < 8) och[lane] = -1;
+                __syncthreads();
+                if (chas) och[cdig] = cid;
+                __syncthreads();
+                // x: row (az, ay) of the two children of each pair, shifted and summed
+                for (int r = lane; r < P2; r += 64) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float o[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) o[k] = 0.f;
+#pragma unroll
+                        for (int bx = 0; bx < 2; ++bx) {
+                            const int32_t c = och[4 * bx + q];
+                            if (c < 0) continue;
+                            const float *row = nodeA + (int64_t)(c - slot0) * P3 + r * P;
+                            float a[P];
+#pragma unroll
+                            for (int k = 0; k < P; ++k) a[k] = row[k];
+#pragma unroll
+                            for (int k = 0; k < P; ++k)
+#pragma unroll
+                                for (int m = 0; m <= k; ++m) o[k] = fmaf(a[m], shift[bx][k - m], o[k]);
+                        }
+                        float *dst = cbuf + (q * P2 + r) * PR;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) dst[k] = o[k];
+                    }
+                }
+                __syncthreads();
+                // y: column (az, ax) of the pairs by = 0, 1 of each bz, into the by = 0 block
+                for (int i = lane; i < 2 * P2; i += 64) {
+                    const int bz = i / P2, az = (i % P2) / P, ax = i % P;
+                    float o[P];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) o[k] = 0.f;
+#pragma unroll
+                    for (int by = 0; by < 2; ++by) {
+                        const float *col = cbuf + ((2 * by + bz) * P2 + az * P) * PR + ax;
+                        float a[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) a[k] = col[k * PR];
+#pragma unroll
+                        for (int k = 0; k < P; ++k)
+#pragma unroll
+                            for (int m = 0; m <= k; ++m) o[k] = fmaf(a[m], shift[by][k - m], o[k]);
+                    }
+                    float *col0 = cbuf + (bz * P2 + az * P) * PR + ax;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) col0[k * PR] = o[k];
+                }
+                __syncthreads();
+                // z: column (ay, ax) of the blocks bz = 0, 1, added to the node's moments
+                for (int i = lane; i < P2; i += 64) {
+                    const int ay = i / P, ax = i % P;
+                    float o[P];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) o[k] = 0.f;
+#pragma unroll
+                    for (int bz = 0; bz < 2; ++bz) {
+                        const float *col = cbuf + (bz * P2 + ay) * PR + ax;
+                        float a[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) a[k] = col[k * P * PR];
+#pragma unroll
+                        for (int k = 0; k < P; ++k)
+#pragma unroll
+                            for (int m = 0; m <= k; ++m) o[k] = fmaf(a[m], shift[bz][k - m], o[k]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < P; ++k) tot[(k * P + ay) * P + ax] += o[k];
+                }
+            }
+            todo = 0;
+        }
+        while (M2M && !TREE && todo) {
             int32_t gid[G];
             int gdig[G];
             int ng = 0;
