@@ -323,13 +323,20 @@ int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, co
                       const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream);
 
 /* Backward of every population (as msp_fgt_backward on its slice); grad_sigma:
- * device float64[npop] or NULL.  The populations run on eight internal streams
- * that wait for the work already on `stream` and that `stream` waits for before
- * its later work; the call returns once everything is enqueued.  use_graph = 1:
- * the first call with given pointers, sigma and parameters runs eagerly (it may
- * synchronise) and records the same work into a hipGraph; later calls with the
- * same arguments launch that graph on `stream`.  use_graph = 0 runs eagerly every
- * time (outputs at new addresses on every call gain nothing from a graph). */
+ * device float64[npop] or NULL.  One fixed launch sequence covers all populations:
+ * the two fields (weights w, and the upstream gradient at the targets) of the
+ * expansion-route populations as batched P2M / M2L / L2P-with-derivatives passes
+ * on an internal stream that forks from `stream` and joins it again, beside one
+ * persistent P2P-with-derivatives launch per field for the direct-route
+ * populations, then one combination launch and one sigma-reduction launch.  The
+ * direct route gives the bits of msp_fgt_backward; the expansion route agrees with
+ * it to float32 rounding (moments and translations summed in another order).  The
+ * call returns once everything is enqueued.  use_graph = 1: the first call with
+ * given pointers, sigma and parameters runs eagerly (it may synchronise) and
+ * records the same work into a hipGraph; later calls with the same arguments, while
+ * the populations' buffers stay where they were, launch that graph on `stream`.
+ * use_graph = 0 runs eagerly every time (outputs at new addresses on every call
+ * gain nothing from a graph). */
 int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                        const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
                        float *grad_y, float *grad_z, double *grad_sigma, int32_t use_graph, void *stream);

@@ -8,7 +8,7 @@
 // Laplacian (weights w), and v with gradient (weights g at the targets), both by
 // the expansion route (L2P with derivatives) or the direct route (P2P with
 // derivatives).
-#include "internal.hpp"
+#include "grad_common.hpp"
 
 #include <cmath>
 
@@ -16,7 +16,6 @@ namespace msp {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRec = 16;   // floats per point record of the backward pass (64 bytes)
 
 __global__ void k_target_weights(const float *g, const uint8_t *is_target, int64_t n, float *gt) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -24,86 +23,10 @@ __global__ void k_target_weights(const float *g, const uint8_t *is_target, int64
     gt[i] = (!is_target || is_target[i]) ? g[i] : 0.f;
 }
 
-struct BoxGeo {
-    double lo[3];
-    double side;
-};
-
-__device__ inline void node_box(const BoxGeo &g, int level, int ix, int iy, int iz, float c[3]) {
-    const double h = g.side / (double)(1ll << level);
-    c[0] = (float)(g.lo[0] + (ix + 0.5) * h);
-    c[1] = (float)(g.lo[1] + (iy + 0.5) * h);
-    c[2] = (float)(g.lo[2] + (iz + 0.5) * h);
-}
-
-// P2P with derivatives: for every point of every leaf (key order), the sums over
-// the source leaves of its list of e = w exp(-r^2/sigma^2), e*(x-s) and e*r^2.
-__global__ void __launch_bounds__(64) k_p2p_grad(int64_t n_nodes, const int32_t *nfirst,
-                                                 const int32_t *ncount, const int32_t *nnchild,
-                                                 const int32_t *nlevel, const int32_t *nix,
-                                                 const int32_t *niy, const int32_t *niz, BoxGeo geo,
-                                                 const int64_t *off, const int32_t *lst,
-                                                 const float4 *ps, float kexp, float inv_s2,
-                                                 float *out, int stride, int want_lap) {
-    const int64_t v = blockIdx.x;
-    if (v >= n_nodes || nnchild[v] != 0) return;
-    __shared__ float4 src[64];
-    __shared__ float red[5][64];
-    const int lane = threadIdx.x;
-    float ct[3];
-    node_box(geo, nlevel[v], nix[v], niy[v], niz[v], ct);
-    const int32_t tf = nfirst[v], tn = ncount[v];
-    const int64_t l0 = off[v], l1 = off[v + 1];
-    for (int t0 = 0; t0 < tn; t0 += 64) {
-        const int nt = tn - t0 < 64 ? tn - t0 : 64;
-        int tp = 1;
-        while (tp < nt) tp <<= 1;
-        const int G = 64 / tp;
-        const int a = lane % tp, grp = lane / tp;
-        const int32_t ti = tf + t0 + (a < nt ? a : 0);
-        const float4 qt = ps[ti];
-        const float tx = qt.x - ct[0], ty = qt.y - ct[1], tz = qt.z - ct[2];
-        float su = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, sr = 0.f;
-        for (int64_t q = l0; q < l1; ++q) {
-            const int32_t u = lst[q];
-            if (u < 0 || u >= n_nodes) continue;
-            const int32_t sf = nfirst[u], sn = ncount[u];
-            for (int s0 = 0; s0 < sn; s0 += 64) {
-                const int ns = sn - s0 < 64 ? sn - s0 : 64;
-                __syncthreads();
-                if (lane < ns) {
-                    const float4 qs = ps[sf + s0 + lane];
-                    src[lane] = make_float4(qs.x - ct[0], qs.y - ct[1], qs.z - ct[2], qs.w);
-                }
-                __syncthreads();
-                for (int j = grp; j < ns; j += G) {
-                    const float4 s4 = src[j];
-                    const float dx = tx - s4.x, dy = ty - s4.y, dz = tz - s4.z;
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float e = s4.w * __builtin_amdgcn_exp2f(r2 * kexp);
-                    su += e;
-                    sx = fmaf(e, dx, sx);
-                    sy = fmaf(e, dy, sy);
-                    sz = fmaf(e, dz, sz);
-                    sr = fmaf(e, r2, sr);
-                }
-            }
-        }
-        __syncthreads();
-        red[0][lane] = su; red[1][lane] = sx; red[2][lane] = sy; red[3][lane] = sz; red[4][lane] = sr;
-        __syncthreads();
-        if (grp == 0 && a < nt) {
-            float r[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int q = 0; q < G; ++q)
-                for (int k = 0; k < 5; ++k) r[k] += red[k][q * tp + a];
-            float *o = out + (int64_t)ti * stride;   // value, gradient x y z, Laplacian
-            o[0] = r[0];
-            o[1] = -2.f * inv_s2 * r[1];
-            o[2] = -2.f * inv_s2 * r[2];
-            o[3] = -2.f * inv_s2 * r[3];
-            if (want_lap) o[4] = 4.f * inv_s2 * inv_s2 * r[4] - 6.f * inv_s2 * r[0];
-        }
-    }
+// P2P with derivatives, one target leaf per block of one wavefront.
+__global__ void __launch_bounds__(64) k_p2p_grad(GradLeafSet L, int stride, int want_lap) {
+    __shared__ GradShared sh;
+    p2p_grad_leaf(L, blockIdx.x, stride, want_lap, sh);
 }
 
 // Per point of the input order j: the key-order record of its point (64 bytes,
@@ -116,20 +39,11 @@ __global__ void k_combine(int64_t n, const int32_t *iperm, const float *gt, cons
     __shared__ double red[kBlock];
     const int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     double ds = 0.0;
-    if (j < n) {
-        const float4 *r4 = reinterpret_cast<const float4 *>(rec + (int64_t)iperm[j] * kRec);
-        const float4 a = r4[0], b = r4[1], c = r4[2];
-        // a = (Av, Agx, Agy, Agz), b = (Alap, Bv, Bgx, Bgy), c = (Bgz, -, -, -)
-        const float g = gt[j];
-        if (want_w) grad_w[j] = exclude_self ? b.y - g : b.y;
-        if (want_pos) {
-            const float wj = w[j];
-            grad_x[j] = g * a.y + wj * b.z;
-            grad_y[j] = g * a.z + wj * b.w;
-            grad_z[j] = g * a.w + wj * c.x;
-        }
-        if (want_sigma) ds = (double)g * (0.5 * sigma * (double)b.x + 3.0 / sigma * (double)a.x);
-    }
+    if (j < n)
+        ds = combine_point(reinterpret_cast<const float4 *>(rec + (int64_t)iperm[j] * kRec), gt[j],
+                           want_pos ? w[j] : 0.f, want_w, want_pos, want_sigma, sigma, exclude_self,
+                           want_w ? grad_w + j : nullptr, want_pos ? grad_x + j : nullptr,
+                           want_pos ? grad_y + j : nullptr, want_pos ? grad_z + j : nullptr);
     red[threadIdx.x] = ds;
     __syncthreads();
     for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -163,12 +77,12 @@ int direct_field_grad(msp_tree *t, const msp_fgt_params *prm, float *out, int st
     const double sig = prm->sigma;
     const float kexp = (float)(-1.4426950408889634 / (sig * sig));
     const float inv_s2 = (float)(1.0 / (sig * sig));
+    const GradLeafSet L{nn, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(),
+                        t->nlevel.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                        geo, t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(), kexp,
+                        inv_s2, out};
     PhaseScope ps(&t->timing, PH_P2P, s);
-    hipLaunchKernelGGL(k_p2p_grad, dim3((unsigned)nn), dim3(64), 0, s, nn, t->nfirst.as<int32_t>(),
-                       t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(), t->nlevel.as<int32_t>(),
-                       t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), geo,
-                       t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(), kexp,
-                       inv_s2, out, stride, want_lap);
+    hipLaunchKernelGGL(k_p2p_grad, dim3((unsigned)nn), dim3(64), 0, s, L, stride, want_lap);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }

@@ -1,17 +1,23 @@
 // Many independent populations in one batch.
 //
 // Every population keeps its own octree (built from its slice of the caller's
-// concatenated arrays) and its own sigma.  A forward call evaluates all of them:
-//   - populations on the expansion route run their own short kernel sequence
-//     (translation operators, P2M, three M2L passes, L2P straight into the
-//     output slice), bracketed by two one-thread kernels that record device
-//     timestamps, spread round-robin over eight branch streams that fork from
-//     the caller's stream and join it again;
+// concatenated arrays) and its own sigma.  A forward call evaluates all of them
+// with a fixed, short launch sequence whatever the number of populations:
+//   - the expansion-route populations share one launch per pass (translation
+//     operators, grid clearing, the occupied-cell list, P2M, three M2L passes,
+//     L2P straight into the output slices), each pass locating its work units
+//     (population, cell / tile / operator) in prefix sums; they run on a branch
+//     stream that forks from the caller's stream and joins it again;
 //   - all populations on the direct route share ONE persistent P2P launch: a
 //     grid sized to the chip takes work items (population, node) from a global
 //     counter until the queue is empty, so small populations do not each pay
 //     for a launch and the chip stays busy across the uneven sizes.  One staging
 //     launch before it and one scatter launch after it also cover all of them.
+// The backward has the same shape: the two fields it needs (weights w, and the
+// upstream gradient at the targets) by the batched expansion passes with an L2P
+// that also gives gradient and Laplacian, or by one persistent P2P-with-derivatives
+// launch per field, then one launch that combines every point's records into its
+// gradients and one that reduces the sigma derivative of each population.
 // After a first eager call the sequence is captured into a hipGraph on a
 // private stream and later calls with the same arguments replay the graph on
 // the caller's stream.  The capture holds no memset nodes: the work counter and
@@ -19,8 +25,7 @@
 //
 // The autotuner times every population at each candidate leaf size on both
 // routes and keeps the fastest pair.
-#include "internal.hpp"
-#include "p2p_leaf.hpp"
+#include "grad_common.hpp"
 
 #include <cmath>
 #include <cstring>
@@ -125,6 +130,103 @@ __global__ void k_batch_scatter(const PopDesc *desc, const int64_t *pt_off, int 
     u_out[D.base + D.perm[i]] = D.ls.usort[i];
 }
 
+// ---------------------------------------------------------------------------------
+// Batched backward.  One direct-route population as its kernels read it.
+struct GradDesc {
+    GradLeafSet L;          // tree arrays, staged weights (L.ps.w), records L.out
+    const int32_t *perm;    // key order -> index inside the population
+    int64_t base, n;
+};
+
+// One population as the combination reads it.
+struct CombDesc {
+    const int32_t *iperm;   // index inside the population -> key order
+    const float *rec;       // records in key order
+    int64_t base, n;
+    double sigma;
+    int exclude_self;
+};
+
+// Weights of every direct-route population into key order (the w slot of ps).
+__global__ void k_bw_stage(const GradDesc *desc, const int64_t *pt_off, int nd, const float *w) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= pt_off[nd]) return;
+    const int d = find_segment(pt_off, nd, g);
+    const GradDesc &D = desc[d];
+    const int64_t i = g - pt_off[d];
+    const_cast<float4 *>(D.L.ps)[i].w = w[D.base + D.perm[i]];
+}
+
+__global__ void k_bw_reset(unsigned long long *counter) { *counter = 0ull; }
+
+// Persistent P2P with derivatives over the nodes of every direct-route population
+// (four independent wavefronts per block, one item per counter addition).
+__global__ void __launch_bounds__(256) k_batch_p2p_grad(const GradDesc *desc, const int64_t *item_off, int nd,
+                                                        unsigned long long *counter, int slot, int want_lap) {
+    __shared__ GradShared sh[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t total = item_off[nd];
+    for (int64_t it = 0; it <= total; ++it) {
+        unsigned long long mine = 0ull;
+        if (lane == 0) mine = atomicAdd(counter, 1ull);
+        const int64_t item = (int64_t)__shfl(mine, 0, 64);
+        if (item >= total) break;
+        const int d = find_segment(item_off, nd, item);
+        GradLeafSet L = desc[d].L;
+        L.out += slot;
+        p2p_grad_leaf(L, item - item_off[d], kRec, want_lap, sh[wave]);
+    }
+}
+
+// Gradients of every point of every population (blocks of 256 points, each within
+// one population) and per-block partial sums of the sigma derivative.
+__global__ void __launch_bounds__(256) k_batch_combine(const CombDesc *desc, const int64_t *blk_off, int np,
+                                                       const float *gt, const float *w, int want_w, int want_pos,
+                                                       int want_sigma, float *grad_w, float *grad_x,
+                                                       float *grad_y, float *grad_z, double *partial) {
+    __shared__ double red[kBlock];
+    const int d = find_segment(blk_off, np, (int64_t)blockIdx.x);
+    const CombDesc &D = desc[d];
+    const int64_t j = (blockIdx.x - blk_off[d]) * (int64_t)kBlock + threadIdx.x;
+    double ds = 0.0;
+    if (j < D.n) {
+        const int64_t o = D.base + j;
+        ds = combine_point(reinterpret_cast<const float4 *>(D.rec + (int64_t)D.iperm[j] * kRec), gt[o],
+                           want_pos ? w[o] : 0.f, want_w, want_pos, want_sigma, D.sigma, D.exclude_self,
+                           want_w ? grad_w + o : nullptr, want_pos ? grad_x + o : nullptr,
+                           want_pos ? grad_y + o : nullptr, want_pos ? grad_z + o : nullptr);
+    }
+    red[threadIdx.x] = ds;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && partial) partial[blockIdx.x] = red[0];
+}
+
+// Sigma derivative of population blockIdx.x: its block partials in order.
+__global__ void __launch_bounds__(256) k_batch_sigma(const int64_t *blk_off, const double *partial,
+                                                     double *grad_sigma) {
+    __shared__ double red[kBlock];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = blk_off[k] + threadIdx.x; b < blk_off[k + 1]; b += kBlock) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad_sigma[k] = red[0];
+}
+
+__global__ void k_bw_target_weights(const float *g, const uint8_t *is_target, int64_t n, float *gt) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    gt[i] = (!is_target || is_target[i]) ? g[i] : 0.f;
+}
+
 }  // namespace
 }  // namespace msp
 
@@ -151,14 +253,13 @@ int plan_batch(msp_batch *b, const float *sigma, const msp_fgt_params *prm, std:
     return MSP_OK;
 }
 
-// Allocations, interaction lists and the descriptors of the direct-route
-// populations (host synchronisations allowed: never under capture).
-int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
-                  float *u_out, hipStream_t s) {
-    std::vector<PopDesc> d;
-    std::vector<int64_t> poff{0}, ioff{0};
-    // expansion-route populations: descriptors and prefix sums for the batched passes
-    std::vector<FgtPop> fp;
+// Expansion-route populations: their descriptors (weights w, flags, outputs u_out)
+// into fp, and the device offsets of the batched passes uploaded into foff; bp
+// gets everything but its descriptor pointer.  Host synchronisations allowed.
+int prepare_fgt(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
+                float *u_out, std::vector<FgtPop> &fp, DevBuf &foff, DevBuf &franges, DevBuf &stamps,
+                FgtBatchPlan &bp) {
+    fp.clear();
     std::vector<int64_t> ops_off{0}, pw_off{0}, grid_off{0}, tile_off[3] = {{0}, {0}, {0}};
     int64_t n_pts = 0;
     int p = 0;
@@ -171,7 +272,7 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
         const int64_t o = b->off[k];
         f.w = w + o;
         f.is_target = is_target ? is_target + o : nullptr;
-        f.u_out = u_out + o;
+        f.u_out = u_out ? u_out + o : nullptr;
         f.pop = k;
         p = pp.pl.p;
         fp.push_back(f);
@@ -191,9 +292,54 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
         for (int pass = 0; pass < 3; ++pass)
             tile_off[pass].push_back(tile_off[pass].back() + fgt_pop_tiles(f, p, pass, gemm));
     const int nf = (int)fp.size();
+    MSP_TRY(foff.ensure((size_t)6 * (nf + 1) * 8));
+    MSP_TRY(franges.ensure((size_t)(n_pts + 1) * sizeof(int4) + 16));
+    MSP_TRY(stamps.ensure((size_t)(b->npop > 0 ? b->npop : 1) * 16));
+    bp = FgtBatchPlan{};
+    bp.npop = nf;
+    bp.p = p;
+    bp.cus = b->cus;
+    bp.gemm = gemm ? 1 : 0;
+    bp.gemm_lds = gemm_lds;
+    if (nf > 0) {
+        int64_t *off = foff.as<int64_t>();
+        const std::vector<int64_t> *arrs[6] = {&ops_off, &pw_off, &grid_off, &tile_off[0], &tile_off[1], &tile_off[2]};
+        for (int a = 0; a < 6; ++a)
+            MSP_HIP(hipMemcpy(off + (size_t)a * (nf + 1), arrs[a]->data(), (size_t)(nf + 1) * 8, hipMemcpyHostToDevice));
+        bp.ops_off = off;
+        bp.pw_off = off + (nf + 1);
+        bp.grid_off = off + 2 * (nf + 1);
+        for (int pass = 0; pass < 3; ++pass) {
+            bp.tile_off[pass] = off + (size_t)(3 + pass) * (nf + 1);
+            bp.n_tiles[pass] = tile_off[pass].back();
+        }
+        bp.n_ops = ops_off.back();
+        bp.n_pw = pw_off.back();
+        bp.n_grid = grid_off.back();
+        bp.cap = n_pts + 1;   // a cell holds at least one point
+        bp.cells = franges.as<int4>();
+        bp.ncells = reinterpret_cast<int32_t *>(franges.as<int4>() + bp.cap);
+        bp.stamps = stamps.as<unsigned long long>();
+    }
+    return MSP_OK;
+}
+
+// Allocations, interaction lists and the descriptors of the direct-route
+// populations (host synchronisations allowed: never under capture).
+int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
+                  float *u_out, hipStream_t s) {
+    std::vector<PopDesc> d;
+    std::vector<int64_t> poff{0}, ioff{0};
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    // earlier work on s may still read the descriptors about to be replaced
+    MSP_HIP(hipStreamSynchronize(s));
+    std::vector<FgtPop> fp;
+    MSP_TRY(prepare_fgt(b, plans, w, is_target, u_out, fp, b->foff, b->franges, b->stamps, b->fplan));
     MSP_TRY(b->fdesc.ensure((fp.size() + 1) * sizeof(FgtPop)));
-    MSP_TRY(b->foff.ensure((size_t)6 * (nf + 1) * 8));
-    MSP_TRY(b->franges.ensure((size_t)(n_pts + 1) * sizeof(int4) + 16));
+    if (!fp.empty()) {
+        MSP_HIP(hipMemcpy(b->fdesc.p, fp.data(), fp.size() * sizeof(FgtPop), hipMemcpyHostToDevice));
+        b->fplan.pops = b->fdesc.as<FgtPop>();
+    }
     for (int k = 0; k < b->npop; ++k) {
         msp_tree *t = b->pops[k].get();
         const PopPlan &pp = plans[k];
@@ -225,49 +371,18 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
         }
     }
     b->n_direct = (int32_t)d.size();
-    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
     b->direct_points = poff.back();
     b->direct_items = ioff.back();
     MSP_TRY(b->desc.ensure((d.size() + 1) * sizeof(PopDesc)));
     MSP_TRY(b->pt_off.ensure(poff.size() * 8));
     MSP_TRY(b->item_off.ensure(ioff.size() * 8));
     MSP_TRY(b->counter.ensure(8));
-    MSP_TRY(b->stamps.ensure((size_t)(b->npop > 0 ? b->npop : 1) * 16));
     MSP_HIP(hipStreamSynchronize(s));
     if (!d.empty()) MSP_HIP(hipMemcpy(b->desc.p, d.data(), d.size() * sizeof(PopDesc), hipMemcpyHostToDevice));
     MSP_HIP(hipMemcpy(b->pt_off.p, poff.data(), poff.size() * 8, hipMemcpyHostToDevice));
     MSP_HIP(hipMemcpy(b->item_off.p, ioff.data(), ioff.size() * 8, hipMemcpyHostToDevice));
     std::vector<uint64_t> zero((size_t)(b->npop > 0 ? b->npop : 1) * 2, 0);
     MSP_HIP(hipMemcpy(b->stamps.p, zero.data(), zero.size() * 8, hipMemcpyHostToDevice));
-    FgtBatchPlan &bp = b->fplan;
-    bp = FgtBatchPlan{};
-    bp.npop = nf;
-    bp.p = p;
-    bp.cus = b->cus;
-    bp.gemm = gemm ? 1 : 0;
-    bp.gemm_lds = gemm_lds;
-    if (nf > 0) {
-        MSP_HIP(hipMemcpy(b->fdesc.p, fp.data(), fp.size() * sizeof(FgtPop), hipMemcpyHostToDevice));
-        int64_t *off = b->foff.as<int64_t>();
-        const std::vector<int64_t> *arrs[6] = {&ops_off, &pw_off, &grid_off, &tile_off[0], &tile_off[1], &tile_off[2]};
-        for (int a = 0; a < 6; ++a)
-            MSP_HIP(hipMemcpy(off + (size_t)a * (nf + 1), arrs[a]->data(), (size_t)(nf + 1) * 8, hipMemcpyHostToDevice));
-        bp.pops = b->fdesc.as<FgtPop>();
-        bp.ops_off = off;
-        bp.pw_off = off + (nf + 1);
-        bp.grid_off = off + 2 * (nf + 1);
-        for (int pass = 0; pass < 3; ++pass) {
-            bp.tile_off[pass] = off + (size_t)(3 + pass) * (nf + 1);
-            bp.n_tiles[pass] = tile_off[pass].back();
-        }
-        bp.n_ops = ops_off.back();
-        bp.n_pw = pw_off.back();
-        bp.n_grid = grid_off.back();
-        bp.cap = n_pts + 1;   // a cell holds at least one point
-        bp.cells = b->franges.as<int4>();
-        bp.ncells = reinterpret_cast<int32_t *>(b->franges.as<int4>() + bp.cap);
-        bp.stamps = b->stamps.as<unsigned long long>();
-    }
     return MSP_OK;
 }
 
@@ -318,6 +433,27 @@ void append_bytes(std::vector<unsigned char> &k, const void *p, size_t n) {
     k.insert(k.end(), c, c + n);
 }
 
+// What a captured graph takes from the populations' trees: the addresses of their
+// buffers and the parameters of their interaction lists.  A graph is replayed only
+// while this is unchanged (the other call's preparation may reallocate or rebuild).
+std::vector<uintptr_t> state_signature(const msp_batch *b) {
+    std::vector<uintptr_t> sig;
+    sig.reserve(b->pops.size() * 24);
+    for (const auto &tp : b->pops) {
+        const msp_tree *t = tp.get();
+        const msp::DevBuf *bufs[] = {&t->keys, &t->ps, &t->perm, &t->iperm, &t->nfirst, &t->ncount, &t->nnchild,
+                                     &t->nlevel, &t->nix, &t->niy, &t->niz, &t->gridA, &t->gridB, &t->ops,
+                                     &t->list_off, &t->list_idx, &t->tflag, &t->usort, &t->bwd};
+        for (const msp::DevBuf *d : bufs) sig.push_back(reinterpret_cast<uintptr_t>(d->p));
+        uint32_t ls, lc;
+        std::memcpy(&ls, &t->list_sigma, 4);
+        std::memcpy(&lc, &t->list_cutoff, 4);
+        sig.push_back(((uintptr_t)ls << 32) | lc);
+        sig.push_back((uintptr_t)t->lists_valid | ((uintptr_t)t->iperm_valid << 1));
+    }
+    return sig;
+}
+
 }  // namespace
 
 int batch_build(msp_batch *b, const float *x, const float *y, const float *z, const int64_t *offsets,
@@ -353,11 +489,11 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
     append_bytes(key, prm, sizeof(*prm));
     append_bytes(key, sigma, sizeof(float) * b->npop);
     append_bytes(key, b->route.data(), sizeof(int32_t) * b->route.size());
-    if (use_graph && b->exec && key == b->key) {
+    if (use_graph && b->exec && key == b->key && state_signature(b) == b->fsig) {
         MSP_HIP(hipGraphLaunch(b->exec, s));
         return MSP_OK;
     }
-    b->drop_graph();
+    b->drop_fwd_graph();
     MSP_TRY(prepare_batch(b, plans, w, is_target, u_out, s));
     MSP_TRY(enqueue_forward(b, plans, w, is_target, u_out, s));
     if (!use_graph) return MSP_OK;
@@ -376,43 +512,166 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
     b->graph = g;
     MSP_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->key = key;
+    b->fsig = state_signature(b);
     return MSP_OK;
 }
 
 namespace {
 
-// The backward of every population, spread round-robin over kBwdStreams streams
-// forked from s and joined back into it (the populations are independent: own
-// trees and buffers, disjoint outputs).
-int enqueue_backward(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, const uint8_t *is_target,
-                     const float *grad_u, float *grad_w, float *grad_x, float *grad_y, float *grad_z,
-                     double *grad_sigma, hipStream_t s) {
-    constexpr int NS = msp_batch::kBwdStreams;
+// Backward descriptors in the batch's own buffers (the forward's graph keeps
+// reading the forward's): expansion-route populations twice (weights w, then the
+// target weights g), direct-route populations once, every population for the
+// combination.  Interaction lists, inverse permutations and record buffers are
+// made here.  Host synchronisations allowed: never under capture.
+int prepare_backward(msp_batch *b, const std::vector<PopPlan> &plans, const float *w, hipStream_t s) {
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    MSP_HIP(hipStreamSynchronize(s));
+    const int64_t N = b->npop > 0 ? b->off[b->npop] : 0;
+    MSP_TRY(b->bw_gt.ensure((size_t)(N > 0 ? N : 1) * 4));
+    const float *gt = b->bw_gt.as<float>();
+    std::vector<CombDesc> cd;
+    std::vector<int64_t> boff{0};
+    for (int k = 0; k < b->npop; ++k) {
+        msp_tree *t = b->pops[k].get();
+        CombDesc c{nullptr, nullptr, b->off[k], t->n, (double)plans[k].prm.sigma,
+                   (plans[k].prm.flags & MSP_EXCLUDE_SELF) ? 1 : 0};
+        if (t->n > 0) {
+            MSP_TRY(t->bwd.ensure((size_t)t->n * kRec * 4));
+            MSP_TRY(ensure_iperm(t, s));
+            c.iperm = t->iperm.as<int32_t>();
+            c.rec = t->bwd.as<float>();
+        }
+        cd.push_back(c);
+        boff.push_back(boff.back() + (t->n + kBlock - 1) / kBlock);
+    }
+    // expansion route: one plan, two descriptor sets
+    std::vector<FgtPop> fp;
+    MSP_TRY(prepare_fgt(b, plans, w, nullptr, nullptr, fp, b->bw_foff, b->bw_franges, b->bw_stamps, b->bw_plan[0]));
+    const size_t nf = fp.size();
+    for (FgtPop &f : fp) f.rec = b->pops[f.pop]->bwd.as<float>();
+    std::vector<FgtPop> both(fp);
+    for (FgtPop f : fp) {
+        f.w = gt + b->off[f.pop];
+        both.push_back(f);
+    }
+    MSP_TRY(b->bw_fdesc.ensure((both.size() + 1) * sizeof(FgtPop)));
+    b->bw_plan[1] = b->bw_plan[0];
+    if (nf > 0) {
+        MSP_HIP(hipMemcpy(b->bw_fdesc.p, both.data(), both.size() * sizeof(FgtPop), hipMemcpyHostToDevice));
+        b->bw_plan[0].pops = b->bw_fdesc.as<FgtPop>();
+        b->bw_plan[1].pops = b->bw_fdesc.as<FgtPop>() + nf;
+    }
+    // direct route
+    std::vector<GradDesc> gd;
+    std::vector<int64_t> poff{0}, ioff{0};
+    for (int k = 0; k < b->npop; ++k) {
+        msp_tree *t = b->pops[k].get();
+        const PopPlan &pp = plans[k];
+        if (pp.pl.route == MSP_ROUTE_FGT || t->n == 0) continue;
+        MSP_TRY(direct_route_lists(t, &pp.prm, s));
+        const double sig = pp.prm.sigma;
+        GradDesc g;
+        g.L = GradLeafSet{t->n_nodes, t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nnchild.as<int32_t>(),
+                          t->nlevel.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                          BoxGeo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side},
+                          t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(),
+                          (float)(-1.4426950408889634 / (sig * sig)), (float)(1.0 / (sig * sig)),
+                          t->bwd.as<float>()};
+        g.perm = t->perm.as<int32_t>();
+        g.base = b->off[k];
+        g.n = t->n;
+        gd.push_back(g);
+        poff.push_back(poff.back() + t->n);
+        ioff.push_back(ioff.back() + t->n_nodes);
+    }
+    b->bw_nd = (int32_t)gd.size();
+    b->bw_points = poff.back();
+    b->bw_items = ioff.back();
+    b->bw_nblk = boff.back();
+    MSP_TRY(b->bw_desc.ensure((gd.size() + 1) * sizeof(GradDesc)));
+    MSP_TRY(b->bw_pt_off.ensure(poff.size() * 8));
+    MSP_TRY(b->bw_item_off.ensure(ioff.size() * 8));
+    MSP_TRY(b->bw_counter.ensure(8));
+    MSP_TRY(b->bw_comb.ensure((cd.size() + 1) * sizeof(CombDesc)));
+    MSP_TRY(b->bw_boff.ensure(boff.size() * 8));
+    MSP_TRY(b->bw_partial.ensure((size_t)(b->bw_nblk > 0 ? b->bw_nblk : 1) * 8));
+    MSP_HIP(hipStreamSynchronize(s));
+    if (!gd.empty()) MSP_HIP(hipMemcpy(b->bw_desc.p, gd.data(), gd.size() * sizeof(GradDesc), hipMemcpyHostToDevice));
+    MSP_HIP(hipMemcpy(b->bw_pt_off.p, poff.data(), poff.size() * 8, hipMemcpyHostToDevice));
+    MSP_HIP(hipMemcpy(b->bw_item_off.p, ioff.data(), ioff.size() * 8, hipMemcpyHostToDevice));
+    if (!cd.empty()) MSP_HIP(hipMemcpy(b->bw_comb.p, cd.data(), cd.size() * sizeof(CombDesc), hipMemcpyHostToDevice));
+    MSP_HIP(hipMemcpy(b->bw_boff.p, boff.data(), boff.size() * 8, hipMemcpyHostToDevice));
+    if (!b->bfork) {
+        MSP_HIP(hipEventCreateWithFlags(&b->bfork, hipEventDisableTiming));
+        MSP_HIP(hipStreamCreateWithFlags(&b->bside, hipStreamNonBlocking));
+        MSP_HIP(hipEventCreateWithFlags(&b->bjoin, hipEventDisableTiming));
+    }
+    return MSP_OK;
+}
+
+// The whole backward as a launch sequence on s (no synchronisation, no allocation
+// once prepare_backward has run for the same plans): the target weights, the two
+// fields of the expansion-route populations on a branch stream beside those of
+// the direct-route populations, then the combination.
+int enqueue_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *grad_u,
+                     float *grad_w, float *grad_x, float *grad_y, float *grad_z, double *grad_sigma,
+                     hipStream_t s) {
+    const int64_t N = b->npop > 0 ? b->off[b->npop] : 0;
+    const bool needA = grad_x || grad_sigma;
+    const bool needB = grad_w || grad_x;
+    float *gt = b->bw_gt.as<float>();
+    if (N > 0) {
+        hipLaunchKernelGGL(k_bw_target_weights, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, grad_u, is_target, N,
+                           gt);
+        MSP_CHECK_LAUNCH();
+    }
     MSP_HIP(hipEventRecord(b->bfork, s));
-    for (int r = 0; r < NS; ++r) MSP_HIP(hipStreamWaitEvent(b->bside[r], b->bfork, 0));
-    int rc = MSP_OK;
-    for (int k = 0; k < b->npop && rc == MSP_OK; ++k) {
-        const int64_t o = b->off[k];
-        msp_fgt_params q = plans[k].prm;
-        q.route = plans[k].pl.route;
-        rc = fgt_backward(b->pops[k].get(), w + o, is_target ? is_target + o : nullptr, &q, grad_u + o,
-                          grad_w ? grad_w + o : nullptr, grad_x ? grad_x + o : nullptr,
-                          grad_y ? grad_y + o : nullptr, grad_z ? grad_z + o : nullptr,
-                          grad_sigma ? grad_sigma + k : nullptr, b->bside[k % NS]);
+    MSP_HIP(hipStreamWaitEvent(b->bside, b->bfork, 0));
+    if (needA) MSP_TRY(fgt_batch_field_grad(b->bw_plan[0], kRec, 0, grad_sigma ? 1 : 0, b->bside));
+    if (needB) MSP_TRY(fgt_batch_field_grad(b->bw_plan[1], kRec, 5, 0, b->bside));
+    const int nd = b->bw_nd;
+    if (nd > 0) {
+        const GradDesc *desc = b->bw_desc.as<GradDesc>();
+        auto *counter = b->bw_counter.as<unsigned long long>();
+        const int64_t waves = (int64_t)b->cus * 32;
+        const int64_t want = b->bw_items < waves ? b->bw_items : waves;
+        const unsigned grid = (unsigned)((want + 3) / 4);
+        for (int f = 0; f < 2; ++f) {
+            if (!(f == 0 ? needA : needB)) continue;
+            hipLaunchKernelGGL(k_bw_stage, dim3(grid_for(b->bw_points, kBlock)), dim3(kBlock), 0, s, desc,
+                               b->bw_pt_off.as<int64_t>(), nd, f == 0 ? w : gt);
+            MSP_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_bw_reset, dim3(1), dim3(1), 0, s, counter);
+            MSP_CHECK_LAUNCH();
+            if (grid > 0) {
+                hipLaunchKernelGGL(k_batch_p2p_grad, dim3(grid), dim3(256), 0, s, desc, b->bw_item_off.as<int64_t>(),
+                                   nd, counter, f == 0 ? 0 : 5, f == 0 && grad_sigma ? 1 : 0);
+                MSP_CHECK_LAUNCH();
+            }
+        }
     }
-    // join even after an error, so that s stays ordered after whatever was enqueued
-    for (int r = 0; r < NS; ++r) {
-        MSP_HIP(hipEventRecord(b->bjoin[r], b->bside[r]));
-        MSP_HIP(hipStreamWaitEvent(s, b->bjoin[r], 0));
+    MSP_HIP(hipEventRecord(b->bjoin, b->bside));
+    MSP_HIP(hipStreamWaitEvent(s, b->bjoin, 0));
+    if (b->npop > 0 && b->bw_nblk > 0) {
+        hipLaunchKernelGGL(k_batch_combine, dim3((unsigned)b->bw_nblk), dim3(kBlock), 0, s,
+                           b->bw_comb.as<CombDesc>(), b->bw_boff.as<int64_t>(), b->npop, gt, w,
+                           grad_w && needB ? 1 : 0, grad_x ? 1 : 0, grad_sigma ? 1 : 0, grad_w, grad_x, grad_y,
+                           grad_z, b->bw_partial.as<double>());
+        MSP_CHECK_LAUNCH();
     }
-    return rc;
+    if (grad_sigma && b->npop > 0) {
+        hipLaunchKernelGGL(k_batch_sigma, dim3((unsigned)b->npop), dim3(kBlock), 0, s, b->bw_boff.as<int64_t>(),
+                           b->bw_partial.as<double>(), grad_sigma);
+        MSP_CHECK_LAUNCH();
+    }
+    return MSP_OK;
 }
 
 }  // namespace
 
 // With use_graph, the first call with given arguments runs eagerly (allocations,
 // lists, inverse permutations) and the same sequence is captured into a hipGraph;
-// later calls replay it.
+// later calls replay it while the arguments and the populations' buffers are unchanged.
 int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                    const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
                    float *grad_y, float *grad_z, double *grad_sigma, int use_graph, hipStream_t s) {
@@ -425,30 +684,18 @@ int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const
     append_bytes(key, prm, sizeof(*prm));
     append_bytes(key, sigma, sizeof(float) * b->npop);
     append_bytes(key, b->route.data(), sizeof(int32_t) * b->route.size());
-    if (use_graph && b->bexec && key == b->bkey) {
+    if (use_graph && b->bexec && key == b->bkey && state_signature(b) == b->bsig) {
         MSP_HIP(hipGraphLaunch(b->bexec, s));
         return MSP_OK;
     }
-    if (b->bexec) (void)hipGraphExecDestroy(b->bexec);
-    if (b->bgraph) (void)hipGraphDestroy(b->bgraph);
-    b->bexec = nullptr;
-    b->bgraph = nullptr;
-    b->bkey.clear();
-    constexpr int NS = msp_batch::kBwdStreams;
-    if (!b->bfork) {
-        MSP_HIP(hipEventCreateWithFlags(&b->bfork, hipEventDisableTiming));
-        for (int r = 0; r < NS; ++r) {
-            MSP_HIP(hipStreamCreateWithFlags(&b->bside[r], hipStreamNonBlocking));
-            MSP_HIP(hipEventCreateWithFlags(&b->bjoin[r], hipEventDisableTiming));
-        }
-    }
-    MSP_TRY(enqueue_backward(b, plans, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma, s));
+    b->drop_bwd_graph();
+    MSP_TRY(prepare_backward(b, plans, w, s));
+    MSP_TRY(enqueue_backward(b, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma, s));
     if (!use_graph) return MSP_OK;
     if (!b->cap) MSP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     MSP_HIP(hipStreamSynchronize(s));
     MSP_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_backward(b, plans, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
-                                    b->cap);
+    const int rc = enqueue_backward(b, w, is_target, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma, b->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (rc != MSP_OK) {
@@ -459,6 +706,7 @@ int batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, const
     b->bgraph = g;
     MSP_HIP(hipGraphInstantiate(&b->bexec, b->bgraph, nullptr, nullptr, 0));
     b->bkey = key;
+    b->bsig = state_signature(b);
     return MSP_OK;
 }
 

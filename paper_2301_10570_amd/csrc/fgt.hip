@@ -1049,10 +1049,50 @@ __global__ void __launch_bounds__(kBlock) k_l2p_2lvl(const uint64_t *keys, int64
     }
 }
 
-// L2P with derivatives: value, gradient and Laplacian of each cell's Taylor
-// series at its points (in key order).  Nested Horner: along x the row
-// polynomial r and r', r''; along y the row sums of r, r', r'' and the first two
-// y-derivatives of the sum of r; along z the same for the values of that level.
+// Value, gradient and Laplacian of a cell's Taylor series (coefficients sC in the
+// order [az][ay][ax]) at the offset (X, Y, Z) from its centre, in sigma; is = 1/sigma.
+// Nested Horner: along x the row polynomial r and r', r''; along y the row sums of
+// r, r', r'' and the first two y-derivatives of the sum of r; along z the same for
+// the values of that level.
+template <int P>
+__device__ inline void l2p_grad_point(const float *sC, float X, float Y, float Z, float is, int want_lap, float *o) {
+    // z level accumulators of: v0 (value), v1 (d/dx), v2 (d2/dx2), w1 (d/dy), w2 (d2/dy2)
+    float z0 = 0.f, z1 = 0.f, z2 = 0.f, zy1 = 0.f, zy2 = 0.f, zd1 = 0.f, zd2 = 0.f;
+    for (int az = P - 1; az >= 0; --az) {
+        float y0 = 0.f, y1 = 0.f, y2 = 0.f, yd1 = 0.f, yd2 = 0.f;
+#pragma unroll
+        for (int ay = P - 1; ay >= 0; --ay) {
+            const float *c = sC + (az * P + ay) * P;
+            float r0 = c[P - 1], r1 = 0.f, r2 = 0.f;
+#pragma unroll
+            for (int ax = P - 2; ax >= 0; --ax) {
+                r2 = fmaf(r2, X, r1);
+                r1 = fmaf(r1, X, r0);
+                r0 = fmaf(r0, X, c[ax]);
+            }
+            // Horner in Y for the sums of r0, r1, r2 and derivatives of the r0 sum
+            yd2 = fmaf(yd2, Y, yd1);
+            yd1 = fmaf(yd1, Y, y0);
+            y0 = fmaf(y0, Y, r0);
+            y1 = fmaf(y1, Y, r1);
+            y2 = fmaf(y2, Y, r2);
+        }
+        zd2 = fmaf(zd2, Z, zd1);
+        zd1 = fmaf(zd1, Z, z0);
+        z0 = fmaf(z0, Z, y0);
+        z1 = fmaf(z1, Z, y1);
+        z2 = fmaf(z2, Z, 2.f * y2);
+        zy1 = fmaf(zy1, Z, yd1);
+        zy2 = fmaf(zy2, Z, 2.f * yd2);
+    }
+    o[0] = z0;   // value, gradient x y z, Laplacian
+    o[1] = z1 * is;
+    o[2] = zy1 * is;
+    o[3] = zd1 * is;
+    if (want_lap) o[4] = (z2 + zy2 + 2.f * zd2) * is * is;
+}
+
+// L2P with derivatives at every point of each cell (in key order), one block per cell.
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64_t n, const float4 *ps,
                                                      int level, int Gx, int Gy, int Gz, double lox,
@@ -1079,41 +1119,7 @@ __global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64
         const float X = (float)(((double)q.x - cx) * inv_sigma);
         const float Y = (float)(((double)q.y - cy) * inv_sigma);
         const float Z = (float)(((double)q.z - cz) * inv_sigma);
-        // z level accumulators of: v0 (value), v1 (d/dx), v2 (d2/dx2), w1 (d/dy), w2 (d2/dy2)
-        float z0 = 0.f, z1 = 0.f, z2 = 0.f, zy1 = 0.f, zy2 = 0.f, zd1 = 0.f, zd2 = 0.f;
-        for (int az = P - 1; az >= 0; --az) {
-            float y0 = 0.f, y1 = 0.f, y2 = 0.f, yd1 = 0.f, yd2 = 0.f;
-#pragma unroll
-            for (int ay = P - 1; ay >= 0; --ay) {
-                const float *c = sC + (az * P + ay) * P;
-                float r0 = c[P - 1], r1 = 0.f, r2 = 0.f;
-#pragma unroll
-                for (int ax = P - 2; ax >= 0; --ax) {
-                    r2 = fmaf(r2, X, r1);
-                    r1 = fmaf(r1, X, r0);
-                    r0 = fmaf(r0, X, c[ax]);
-                }
-                // Horner in Y for the sums of r0, r1, r2 and derivatives of the r0 sum
-                yd2 = fmaf(yd2, Y, yd1);
-                yd1 = fmaf(yd1, Y, y0);
-                y0 = fmaf(y0, Y, r0);
-                y1 = fmaf(y1, Y, r1);
-                y2 = fmaf(y2, Y, r2);
-            }
-            zd2 = fmaf(zd2, Z, zd1);
-            zd1 = fmaf(zd1, Z, z0);
-            z0 = fmaf(z0, Z, y0);
-            z1 = fmaf(z1, Z, y1);
-            z2 = fmaf(z2, Z, 2.f * y2);
-            zy1 = fmaf(zy1, Z, yd1);
-            zy2 = fmaf(zy2, Z, 2.f * yd2);
-        }
-        float *o = out + i * stride;   // value, gradient x y z, Laplacian
-        o[0] = z0;
-        o[1] = z1 * is;
-        o[2] = zy1 * is;
-        o[3] = zd1 * is;
-        if (want_lap) o[4] = (z2 + zy2 + 2.f * zd2) * is * is;
+        l2p_grad_point<P>(sC, X, Y, Z, is, want_lap, out + i * stride);
     }
 }
 
@@ -1945,6 +1951,39 @@ __global__ void __launch_bounds__(256) k_bl2p(FgtBatchPlan bp) {
     }
 }
 
+// L2P with derivatives over the cell list (one wavefront per cell): value,
+// gradient and (want_lap) Laplacian at every point of the cell, into the
+// population's records f.rec + i * stride + slot (key order i).
+template <int P>
+__global__ void __launch_bounds__(64) k_bl2p_grad(FgtBatchPlan bp, int stride, int slot, int want_lap) {
+    constexpr int P3 = P * P * P;
+    __shared__ float sC[P3];
+    const int lane = threadIdx.x;
+    const int64_t nsmall = bp.ncells[0], nbig = bp.ncells[1];
+    for (int64_t r = blockIdx.x; r < nsmall + nbig; r += gridDim.x) {
+        const int4 c = r < nbig ? bp.cells[bp.cap - 1 - r] : bp.cells[r - nbig];
+        const FgtPop &f = bp.pops[c.x];
+        int kx, ky, kz;
+        cell_coords(f, c.w, kx, ky, kz);
+        wave_sync();   // the previous cell's coefficients are no longer read
+        for (int q = lane; q < P3; q += 64) {
+            const int ax = q % P, ay = (q / P) % P, az = q / (P * P);
+            sC[q] = f.B[grid_index<P>(f, bp.gemm, kx, ky, kz, ax, ay, az)];
+        }
+        wave_sync();
+        const double cx = f.lo[0] + (kx + 0.5) * f.cell, cy = f.lo[1] + (ky + 0.5) * f.cell,
+                     cz = f.lo[2] + (kz + 0.5) * f.cell;
+        const float is = (float)f.inv_sigma;
+        for (int64_t i = (int64_t)c.y + lane; i < (int64_t)c.y + c.z; i += 64) {
+            const float4 q = f.ps[i];
+            const float X = (float)(((double)q.x - cx) * f.inv_sigma);
+            const float Y = (float)(((double)q.y - cy) * f.inv_sigma);
+            const float Z = (float)(((double)q.z - cz) * f.inv_sigma);
+            l2p_grad_point<P>(sC, X, Y, Z, is, want_lap, f.rec + i * stride + slot);
+        }
+    }
+}
+
 template <int P>
 int batch_p2m_l2p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
     const unsigned grid = (unsigned)(bp.cus * 8);
@@ -1966,8 +2005,9 @@ int batch_p2m_l2p_p(const FgtBatchPlan &bp, bool l2p, hipStream_t s) {
 
 }  // namespace
 
-int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
-    if (bp.npop == 0) return MSP_OK;
+namespace {
+// operator tables, cleared grids, the cell list, P2M and the three M2L passes
+int fgt_batch_expand(const FgtBatchPlan &bp, hipStream_t s) {
     hipLaunchKernelGGL(k_bops, dim3(grid_for(bp.n_ops, 64)), dim3(64), 0, s, bp);
     MSP_CHECK_LAUNCH();
     const int64_t fill_threads = bp.n_grid / 4 < (int64_t)bp.cus * 2048 ? bp.n_grid / 4 + 1 : (int64_t)bp.cus * 2048;
@@ -1990,7 +2030,34 @@ int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
             hipLaunchKernelGGL(k_bm2l, dim3((unsigned)bp.n_tiles[pass]), dim3(64), 0, s, bp, pass);
         MSP_CHECK_LAUNCH();
     }
+    return MSP_OK;
+}
+
+template <int P>
+int launch_bl2p_grad(const FgtBatchPlan &bp, int stride, int slot, int want_lap, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bl2p_grad<P>), dim3((unsigned)(bp.cus * 16)), dim3(64), 0, s, bp,
+                       stride, slot, want_lap);
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+}  // namespace
+
+int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s) {
+    if (bp.npop == 0) return MSP_OK;
+    MSP_TRY(fgt_batch_expand(bp, s));
     return batch_p2m_l2p_p(bp, true, s);
+}
+
+int fgt_batch_field_grad(const FgtBatchPlan &bp, int stride, int slot, int want_lap, hipStream_t s) {
+    if (bp.npop == 0) return MSP_OK;
+    MSP_TRY(fgt_batch_expand(bp, s));
+    switch (bp.p) {
+#define CASE(P) case P: return launch_bl2p_grad<P>(bp, stride, slot, want_lap, s);
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+    }
+    return fail(MSP_EINVAL, "p out of range");
 }
 
 int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, FgtPop *f) {
@@ -2012,6 +2079,7 @@ int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, F
     f->nnchild = t->nnchild.as<int32_t>();
     f->n_nodes = t->n_nodes;
     f->subtract_self = (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0;
+    f->rec = nullptr;
     f->A = t->gridA.as<float>();
     f->B = t->gridB.as<float>();
     f->Tmp = t->ops.as<float>();

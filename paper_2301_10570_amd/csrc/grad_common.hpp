@@ -1,0 +1,119 @@
+// Pieces of the backward pass that the single-tree and the batched kernels share,
+// so that both give the same bits: the direct sums with derivatives over the
+// interaction list of one target leaf, the evaluation of a cell's Taylor series
+// with derivatives at one point, and the combination of a point's two field
+// records into its gradients.
+//
+// Record of a point (kRec floats, key order): the field A of the weights w
+// (value, gradient x y z, Laplacian) at offset 0, the field B of the target
+// weights g (value, gradient x y z) at offset 5.
+#pragma once
+#include "p2p_leaf.hpp"
+
+namespace msp {
+namespace {
+
+constexpr int kRec = 16;   // floats per point record (64 bytes, one aligned segment)
+
+// One tree's arrays as the direct sums with derivatives read them; the staged
+// weights sit in ps.w, records go to out + i * stride (key order i).
+struct GradLeafSet {
+    int64_t n_nodes;
+    const int32_t *nfirst, *ncount, *nnchild, *nlevel, *nix, *niy, *niz;
+    BoxGeo geo;
+    const int64_t *off;
+    const int32_t *lst;
+    const float4 *ps;
+    float kexp, inv_s2;   // -log2(e) / sigma^2, 1 / sigma^2
+    float *out;
+};
+
+struct GradShared {
+    float4 src[64];
+    float red[5][64];
+};
+
+// For every point of target leaf v (one wavefront; sh private to it): the sums
+// over the source leaves of its list of e = w exp(-r^2/sigma^2), e (x - s) and
+// e r^2, written as value, gradient and Laplacian of the field.
+__device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride, int want_lap, GradShared &sh) {
+    if (v >= L.n_nodes || L.nnchild[v] != 0) return;
+    const int lane = threadIdx.x & 63;
+    float ct[3], half;
+    node_box(L.geo, L.nlevel[v], L.nix[v], L.niy[v], L.niz[v], ct, half);
+    const int32_t tf = L.nfirst[v], tn = L.ncount[v];
+    const int64_t l0 = L.off[v], l1 = L.off[v + 1];
+    for (int t0 = 0; t0 < tn; t0 += 64) {
+        const int nt = tn - t0 < 64 ? tn - t0 : 64;
+        int tp = 1;
+        while (tp < nt) tp <<= 1;
+        const int G = 64 / tp;
+        const int a = lane % tp, grp = lane / tp;
+        const int32_t ti = tf + t0 + (a < nt ? a : 0);
+        const float4 qt = L.ps[ti];
+        const float tx = qt.x - ct[0], ty = qt.y - ct[1], tz = qt.z - ct[2];
+        float su = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, sr = 0.f;
+        for (int64_t q = l0; q < l1; ++q) {
+            const int32_t u = L.lst[q];
+            if (u < 0 || u >= L.n_nodes) continue;
+            const int32_t sf = L.nfirst[u], sn = L.ncount[u];
+            for (int s0 = 0; s0 < sn; s0 += 64) {
+                const int ns = sn - s0 < 64 ? sn - s0 : 64;
+                wave_sync();
+                if (lane < ns) {
+                    const float4 qs = L.ps[sf + s0 + lane];
+                    sh.src[lane] = make_float4(qs.x - ct[0], qs.y - ct[1], qs.z - ct[2], qs.w);
+                }
+                wave_sync();
+                for (int j = grp; j < ns; j += G) {
+                    const float4 s4 = sh.src[j];
+                    const float dx = tx - s4.x, dy = ty - s4.y, dz = tz - s4.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float e = s4.w * __builtin_amdgcn_exp2f(r2 * L.kexp);
+                    su += e;
+                    sx = fmaf(e, dx, sx);
+                    sy = fmaf(e, dy, sy);
+                    sz = fmaf(e, dz, sz);
+                    sr = fmaf(e, r2, sr);
+                }
+            }
+        }
+        wave_sync();
+        sh.red[0][lane] = su;
+        sh.red[1][lane] = sx;
+        sh.red[2][lane] = sy;
+        sh.red[3][lane] = sz;
+        sh.red[4][lane] = sr;
+        wave_sync();
+        if (grp == 0 && a < nt) {
+            float r[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < G; ++q)
+                for (int k = 0; k < 5; ++k) r[k] += sh.red[k][q * tp + a];
+            float *o = L.out + (int64_t)ti * stride;   // value, gradient x y z, Laplacian
+            o[0] = r[0];
+            o[1] = -2.f * L.inv_s2 * r[1];
+            o[2] = -2.f * L.inv_s2 * r[2];
+            o[3] = -2.f * L.inv_s2 * r[3];
+            if (want_lap) o[4] = 4.f * L.inv_s2 * L.inv_s2 * r[4] - 6.f * L.inv_s2 * r[0];
+        }
+    }
+}
+
+// The gradients of input point j from its record (rec4: the record as float4),
+// its target weight g and weight wj; returns its term of the sigma derivative.
+__device__ inline double combine_point(const float4 *rec4, float g, float wj, int want_w, int want_pos,
+                                       int want_sigma, double sigma, int exclude_self, float *gw, float *gx,
+                                       float *gy, float *gz) {
+    const float4 a = rec4[0], b = rec4[1], c = rec4[2];
+    // a = (Av, Agx, Agy, Agz), b = (Alap, Bv, Bgx, Bgy), c = (Bgz, -, -, -)
+    if (want_w) *gw = exclude_self ? b.y - g : b.y;
+    if (want_pos) {
+        *gx = g * a.y + wj * b.z;
+        *gy = g * a.z + wj * b.w;
+        *gz = g * a.w + wj * c.x;
+    }
+    return want_sigma ? (double)g * (0.5 * sigma * (double)b.x + 3.0 / sigma * (double)a.x) : 0.0;
+}
+
+}  // namespace
+}  // namespace msp

@@ -154,6 +154,7 @@ struct FgtPop {
     const float *w;
     const uint8_t *is_target;
     float *u_out;
+    float *rec;          // backward records in key order (batched backward only)
     int subtract_self;
     float *A, *B, *Tmp, *opsx, *opsy, *opsz;
     int level, G[3];
@@ -203,31 +204,47 @@ struct msp_batch {
     static constexpr int kBranches = 1;
     hipStream_t side[kBranches] = {};
     hipEvent_t fork = nullptr, join[kBranches] = {};
-    // streams of the backward, populations spread round-robin (forked from the caller's stream)
-    static constexpr int kBwdStreams = 8;
-    hipStream_t bside[kBwdStreams] = {};
-    hipEvent_t bfork = nullptr, bjoin[kBwdStreams] = {};
-    // graph of the last forward signature
+    // batched backward: its own descriptors, offsets and scratch (target weights gt,
+    // block partials of the sigma derivative), and one plan per field (weights w, g)
+    msp::DevBuf bw_fdesc, bw_foff, bw_franges, bw_stamps, bw_desc, bw_pt_off, bw_item_off, bw_counter,
+        bw_comb, bw_boff, bw_partial, bw_gt;
+    msp::FgtBatchPlan bw_plan[2]{};
+    int32_t bw_nd = 0;
+    int64_t bw_points = 0, bw_items = 0, bw_nblk = 0;
+    // branch stream of the backward's expansion-route populations
+    hipStream_t bside = nullptr;
+    hipEvent_t bfork = nullptr, bjoin = nullptr;
+    // graph of the last forward signature, and the populations' state it was captured with
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> key;
+    std::vector<uintptr_t> fsig;
     int64_t launches = 0;   // kernel launches issued by the last eager forward
     // graph of the last backward signature
     hipGraph_t bgraph = nullptr;
     hipGraphExec_t bexec = nullptr;
     std::vector<unsigned char> bkey;
-    void drop_graph() {
+    std::vector<uintptr_t> bsig;
+    void drop_fwd_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         key.clear();
+        fsig.clear();
+    }
+    void drop_bwd_graph() {
         if (bexec) (void)hipGraphExecDestroy(bexec);
         if (bgraph) (void)hipGraphDestroy(bgraph);
         bexec = nullptr;
         bgraph = nullptr;
         bkey.clear();
+        bsig.clear();
+    }
+    void drop_graph() {
+        drop_fwd_graph();
+        drop_bwd_graph();
     }
     ~msp_batch() {
         drop_graph();
@@ -237,10 +254,8 @@ struct msp_batch {
             if (join[k]) (void)hipEventDestroy(join[k]);
         }
         if (fork) (void)hipEventDestroy(fork);
-        for (int k = 0; k < kBwdStreams; ++k) {
-            if (bside[k]) (void)hipStreamDestroy(bside[k]);
-            if (bjoin[k]) (void)hipEventDestroy(bjoin[k]);
-        }
+        if (bside) (void)hipStreamDestroy(bside);
+        if (bjoin) (void)hipEventDestroy(bjoin);
         if (bfork) (void)hipEventDestroy(bfork);
     }
 };
@@ -284,6 +299,9 @@ int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, F
 int64_t fgt_pop_tiles(const FgtPop &f, int p, int pass, bool gemm);
 size_t fgt_pop_gemm_lds(const FgtPop &f, int p);
 int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s);
+// value, gradient and (want_lap) Laplacian of every population's field at all its
+// points, into f.rec + i * stride + slot (key order i)
+int fgt_batch_field_grad(const FgtBatchPlan &bp, int stride, int slot, int want_lap, hipStream_t s);
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
 double rho_max_for_p(int p);
 int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s);

@@ -29,7 +29,7 @@ def _forward(wl, **kw):
 @pytest.mark.parametrize("route,cutoff", [("fgt", 4.5), ("direct", 4.5), ("direct", 0.0), ("auto", 4.5)])
 def test_config1_all_targets(route, cutoff):
     wl = synth.config(1)
-    print(f"config 1 route={route} cutoff={cutoff}", flush=True)
+    print(f"4,096-point cube route={route} cutoff={cutoff}", flush=True)
     tree, u = _forward(wl, route=route, cutoff_sigmas=cutoff)
     tgt = np.nonzero(wl.a > 0)[0]
     ref = oracle.attraction(wl, tgt)
@@ -43,7 +43,7 @@ def test_config1_all_targets(route, cutoff):
 @pytest.mark.parametrize("route", ["fgt", "direct"])
 def test_config2_blobs(route):
     wl = synth.config(2)
-    print(f"config 2 route={route}", flush=True)
+    print(f"262,144-point blobs route={route}", flush=True)
     tree, u = _forward(wl, route=route)
     tgt = np.nonzero(wl.a > 0)[0]
     sel = tgt[synth.sample_indices(tgt.size, 4096, seed=202)]
@@ -64,7 +64,7 @@ def slab():
 
 def test_config3_full_slab_p8(slab):
     wl, sel, ref = slab
-    print("config 3 full slab p=8 auto", flush=True)
+    print("4M-point slab p=8 auto", flush=True)
     tree, u = _forward(wl, p=8)
     plan = tree.plan(wl.sigma, p=8)
     assert plan["route"] == "fgt"
@@ -76,7 +76,7 @@ def test_config3_full_slab_p8(slab):
 @pytest.mark.parametrize("p", [4, 6, 10])
 def test_config3_p_sweep(slab, p):
     wl, sel, ref = slab
-    print(f"config 3 full slab p={p}", flush=True)
+    print(f"4M-point slab p={p}", flush=True)
     tree, u = _forward(wl, p=p, route="fgt")
     err = rel_err(u[sel], ref)
     print(f"  plan={tree.plan(wl.sigma, p=p, route='fgt')} max rel err {err.max():.3e}")
@@ -244,7 +244,7 @@ def test_config3_bf16x3_vs_oracle(slab, p):
     oracle per p, within the 1e-4 bar."""
     import paper_2301_10570_amd as msp
     wl, sel, ref = slab
-    print(f"config 3 full slab p={p} m2l=bf16x3", flush=True)
+    print(f"4M-point slab p={p} m2l=bf16x3", flush=True)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"])
     u = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, route="fgt", m2l="bf16x3").cpu().numpy()

@@ -72,7 +72,7 @@ def test_partner_config1():
     wl = synth.config(1)
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     tq, nq = _queries(tr, wl.n, 300, seed=5)
-    print("partner config 1, 300 queries", flush=True)
+    print("partner, 4,096-point cube, 300 queries", flush=True)
     e = _check(wl, tq, nq, seed=6)
     print(f"  max |dP| {e:.2e}")
 
