@@ -29,20 +29,27 @@ struct GradLeafSet {
 };
 
 struct GradShared {
-    float4 src[64];
+    float4 src[64];                 // staged sources: offsets from the leaf centre, weight
     float red[5][64];
+    int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
 };
 
 // For every point of target leaf v (one wavefront; sh private to it): the sums
 // over the source leaves of its list of e = w exp(-r^2/sigma^2), e (x - s) and
-// e r^2, written as value, gradient and Laplacian of the field.
+// e r^2, written as value, gradient and Laplacian of the field.  Lanes are split
+// into G = 64 / tp groups for leaves with tp <= 32 targets, each group taking
+// every G-th source of a staged chunk; the source points of up to 64 list entries
+// at a time form one sequence staged 64 per chunk, the next chunk loaded while
+// the current one is used; group partials are added in group order.
 __device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride, int want_lap, GradShared &sh) {
     if (v >= L.n_nodes || L.nnchild[v] != 0) return;
     const int lane = threadIdx.x & 63;
     float ct[3], half;
     node_box(L.geo, L.nlevel[v], L.nix[v], L.niy[v], L.niz[v], ct, half);
     const int32_t tf = L.nfirst[v], tn = L.ncount[v];
-    const int64_t l0 = L.off[v], l1 = L.off[v + 1];
+    const int64_t l0 = L.off[v];
+    int64_t l1 = L.off[v + 1];
+    if (l1 - l0 > L.n_nodes) l1 = l0 + L.n_nodes;   // a list names each node at most once
     for (int t0 = 0; t0 < tn; t0 += 64) {
         const int nt = tn - t0 < 64 ? tn - t0 : 64;
         int tp = 1;
@@ -53,18 +60,38 @@ __device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride
         const float4 qt = L.ps[ti];
         const float tx = qt.x - ct[0], ty = qt.y - ct[1], tz = qt.z - ct[2];
         float su = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, sr = 0.f;
-        for (int64_t q = l0; q < l1; ++q) {
-            const int32_t u = L.lst[q];
-            if (u < 0 || u >= L.n_nodes) continue;
-            const int32_t sf = L.nfirst[u], sn = L.ncount[u];
-            for (int s0 = 0; s0 < sn; s0 += 64) {
-                const int ns = sn - s0 < 64 ? sn - s0 : 64;
-                wave_sync();
-                if (lane < ns) {
-                    const float4 qs = L.ps[sf + s0 + lane];
-                    sh.src[lane] = make_float4(qs.x - ct[0], qs.y - ct[1], qs.z - ct[2], qs.w);
+        for (int64_t w0 = l0; w0 < l1; w0 += 64) {
+            const int nw = l1 - w0 < 64 ? (int)(l1 - w0) : 64;
+            int32_t esf = 0, esn = 0;
+            if (lane < nw) {
+                const int32_t u = L.lst[w0 + lane];
+                if (u >= 0 && u < L.n_nodes) {
+                    esf = L.nfirst[u];
+                    esn = L.ncount[u];
                 }
+            }
+            const int incl = p2p_incl_scan(esn, lane);
+            const int tot = __shfl(incl, 63, 64);
+            wave_sync();   // previous window's entries and points are no longer read
+            sh.efirst[lane] = esf - (incl - esn);
+            sh.eend[lane] = esn > 0 ? incl : -1;
+            wave_sync();
+            int owner = 0;
+            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            auto fetch = [&](int c0) {
+                const int j = c0 + lane;
+                if (j < tot) {
+                    while (sh.eend[owner] <= j) ++owner;
+                    nxt = L.ps[sh.efirst[owner] + j];
+                }
+            };
+            fetch(0);
+            for (int c0 = 0; c0 < tot; c0 += 64) {
+                const int ns = tot - c0 < 64 ? tot - c0 : 64;
                 wave_sync();
+                if (lane < ns) sh.src[lane] = make_float4(nxt.x - ct[0], nxt.y - ct[1], nxt.z - ct[2], nxt.w);
+                wave_sync();
+                if (c0 + 64 < tot) fetch(c0 + 64);
                 for (int j = grp; j < ns; j += G) {
                     const float4 s4 = sh.src[j];
                     const float dx = tx - s4.x, dy = ty - s4.y, dz = tz - s4.z;
