@@ -133,7 +133,8 @@ __global__ void k_batch_scatter(const PopDesc *desc, const int64_t *pt_off, int 
 // ---------------------------------------------------------------------------------
 // Batched backward.  One direct-route population as its kernels read it.
 struct GradDesc {
-    GradLeafSet L;          // tree arrays, staged weights (L.ps.w), records L.out
+    GradLeafSet L;          // tree arrays, staged weights w (L.ps.w), records L.out
+    float *g2;              // staged target weights g in key order
     const int32_t *perm;    // key order -> index inside the population
     int64_t base, n;
 };
@@ -147,22 +148,26 @@ struct CombDesc {
     int exclude_self;
 };
 
-// Weights of every direct-route population into key order (the w slot of ps).
-__global__ void k_bw_stage(const GradDesc *desc, const int64_t *pt_off, int nd, const float *w) {
+// Both fields' weights of every direct-route population into key order (w into
+// the w slot of ps, the target weights g into g2).
+__global__ void k_bw_stage(const GradDesc *desc, const int64_t *pt_off, int nd, const float *w, const float *gt) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= pt_off[nd]) return;
     const int d = find_segment(pt_off, nd, g);
     const GradDesc &D = desc[d];
     const int64_t i = g - pt_off[d];
-    const_cast<float4 *>(D.L.ps)[i].w = w[D.base + D.perm[i]];
+    const int64_t j = D.base + D.perm[i];
+    const_cast<float4 *>(D.L.ps)[i].w = w[j];
+    D.g2[i] = gt[j];
 }
 
 __global__ void k_bw_reset(unsigned long long *counter) { *counter = 0ull; }
 
-// Persistent P2P with derivatives over the nodes of every direct-route population
-// (four independent wavefronts per block, one item per counter addition).
+// Persistent P2P with derivatives of both fields over the nodes of every
+// direct-route population (four independent wavefronts per block, one item per
+// counter addition).
 __global__ void __launch_bounds__(256) k_batch_p2p_grad(const GradDesc *desc, const int64_t *item_off, int nd,
-                                                        unsigned long long *counter, int slot, int want_lap) {
+                                                        unsigned long long *counter, int want_lap) {
     __shared__ GradShared sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t total = item_off[nd];
@@ -172,9 +177,7 @@ __global__ void __launch_bounds__(256) k_batch_p2p_grad(const GradDesc *desc, co
         const int64_t item = (int64_t)__shfl(mine, 0, 64);
         if (item >= total) break;
         const int d = find_segment(item_off, nd, item);
-        GradLeafSet L = desc[d].L;
-        L.out += slot;
-        p2p_grad_leaf(L, item - item_off[d], kRec, want_lap, sh[wave]);
+        p2p_grad_leaf_t<true>(desc[d].L, desc[d].g2, item - item_off[d], kRec, want_lap, sh[wave]);
     }
 }
 
@@ -536,7 +539,7 @@ int prepare_backward(msp_batch *b, const std::vector<PopPlan> &plans, const floa
         CombDesc c{nullptr, nullptr, b->off[k], t->n, (double)plans[k].prm.sigma,
                    (plans[k].prm.flags & MSP_EXCLUDE_SELF) ? 1 : 0};
         if (t->n > 0) {
-            MSP_TRY(t->bwd.ensure((size_t)t->n * kRec * 4));
+            MSP_TRY(t->bwd.ensure((size_t)t->n * (kRec + 1) * 4));   // records, then g in key order
             MSP_TRY(ensure_iperm(t, s));
             c.iperm = t->iperm.as<int32_t>();
             c.rec = t->bwd.as<float>();
@@ -577,6 +580,7 @@ int prepare_backward(msp_batch *b, const std::vector<PopPlan> &plans, const floa
                           t->list_off.as<int64_t>(), t->list_idx.as<int32_t>(), t->ps.as<float4>(),
                           (float)(-1.4426950408889634 / (sig * sig)), (float)(1.0 / (sig * sig)),
                           t->bwd.as<float>()};
+        g.g2 = t->bwd.as<float>() + (size_t)t->n * kRec;
         g.perm = t->perm.as<int32_t>();
         g.base = b->off[k];
         g.n = t->n;
@@ -636,18 +640,16 @@ int enqueue_backward(msp_batch *b, const float *w, const uint8_t *is_target, con
         const int64_t waves = (int64_t)b->cus * 32;
         const int64_t want = b->bw_items < waves ? b->bw_items : waves;
         const unsigned grid = (unsigned)((want + 3) / 4);
-        for (int f = 0; f < 2; ++f) {
-            if (!(f == 0 ? needA : needB)) continue;
-            hipLaunchKernelGGL(k_bw_stage, dim3(grid_for(b->bw_points, kBlock)), dim3(kBlock), 0, s, desc,
-                               b->bw_pt_off.as<int64_t>(), nd, f == 0 ? w : gt);
+        // both fields in one pass: one exponential per pair serves both
+        hipLaunchKernelGGL(k_bw_stage, dim3(grid_for(b->bw_points, kBlock)), dim3(kBlock), 0, s, desc,
+                           b->bw_pt_off.as<int64_t>(), nd, w, gt);
+        MSP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_bw_reset, dim3(1), dim3(1), 0, s, counter);
+        MSP_CHECK_LAUNCH();
+        if (grid > 0) {
+            hipLaunchKernelGGL(k_batch_p2p_grad, dim3(grid), dim3(256), 0, s, desc, b->bw_item_off.as<int64_t>(),
+                               nd, counter, grad_sigma ? 1 : 0);
             MSP_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_bw_reset, dim3(1), dim3(1), 0, s, counter);
-            MSP_CHECK_LAUNCH();
-            if (grid > 0) {
-                hipLaunchKernelGGL(k_batch_p2p_grad, dim3(grid), dim3(256), 0, s, desc, b->bw_item_off.as<int64_t>(),
-                                   nd, counter, f == 0 ? 0 : 5, f == 0 && grad_sigma ? 1 : 0);
-                MSP_CHECK_LAUNCH();
-            }
         }
     }
     MSP_HIP(hipEventRecord(b->bjoin, b->bside));

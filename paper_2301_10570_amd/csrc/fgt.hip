@@ -1049,13 +1049,13 @@ __global__ void __launch_bounds__(kBlock) k_l2p_2lvl(const uint64_t *keys, int64
     }
 }
 
-// Value, gradient and Laplacian of a cell's Taylor series (coefficients sC in the
-// order [az][ay][ax]) at the offset (X, Y, Z) from its centre, in sigma; is = 1/sigma.
-// Nested Horner: along x the row polynomial r and r', r''; along y the row sums of
-// r, r', r'' and the first two y-derivatives of the sum of r; along z the same for
-// the values of that level.
-template <int P>
-__device__ inline void l2p_grad_point(const float *sC, float X, float Y, float Z, float is, int want_lap, float *o) {
+// Value, gradient and (LAP) Laplacian of a cell's Taylor series (coefficients sC in
+// the order [az][ay][ax]) at the offset (X, Y, Z) from its centre, in sigma;
+// is = 1/sigma.  Nested Horner: along x the row polynomial r and r' (and r''); along
+// y the row sums of r, r' (r'') and the first (two) y-derivatives of the sum of r;
+// along z the same for the values of that level.
+template <int P, bool LAP>
+__device__ inline void l2p_grad_point_t(const float *sC, float X, float Y, float Z, float is, float *o) {
     // z level accumulators of: v0 (value), v1 (d/dx), v2 (d2/dx2), w1 (d/dy), w2 (d2/dy2)
     float z0 = 0.f, z1 = 0.f, z2 = 0.f, zy1 = 0.f, zy2 = 0.f, zd1 = 0.f, zd2 = 0.f;
     for (int az = P - 1; az >= 0; --az) {
@@ -1066,30 +1066,36 @@ __device__ inline void l2p_grad_point(const float *sC, float X, float Y, float Z
             float r0 = c[P - 1], r1 = 0.f, r2 = 0.f;
 #pragma unroll
             for (int ax = P - 2; ax >= 0; --ax) {
-                r2 = fmaf(r2, X, r1);
+                if (LAP) r2 = fmaf(r2, X, r1);
                 r1 = fmaf(r1, X, r0);
                 r0 = fmaf(r0, X, c[ax]);
             }
             // Horner in Y for the sums of r0, r1, r2 and derivatives of the r0 sum
-            yd2 = fmaf(yd2, Y, yd1);
+            if (LAP) yd2 = fmaf(yd2, Y, yd1);
             yd1 = fmaf(yd1, Y, y0);
             y0 = fmaf(y0, Y, r0);
             y1 = fmaf(y1, Y, r1);
-            y2 = fmaf(y2, Y, r2);
+            if (LAP) y2 = fmaf(y2, Y, r2);
         }
-        zd2 = fmaf(zd2, Z, zd1);
+        if (LAP) zd2 = fmaf(zd2, Z, zd1);
         zd1 = fmaf(zd1, Z, z0);
         z0 = fmaf(z0, Z, y0);
         z1 = fmaf(z1, Z, y1);
-        z2 = fmaf(z2, Z, 2.f * y2);
+        if (LAP) z2 = fmaf(z2, Z, 2.f * y2);
         zy1 = fmaf(zy1, Z, yd1);
-        zy2 = fmaf(zy2, Z, 2.f * yd2);
+        if (LAP) zy2 = fmaf(zy2, Z, 2.f * yd2);
     }
     o[0] = z0;   // value, gradient x y z, Laplacian
     o[1] = z1 * is;
     o[2] = zy1 * is;
     o[3] = zd1 * is;
-    if (want_lap) o[4] = (z2 + zy2 + 2.f * zd2) * is * is;
+    if (LAP) o[4] = (z2 + zy2 + 2.f * zd2) * is * is;
+}
+
+template <int P>
+__device__ inline void l2p_grad_point(const float *sC, float X, float Y, float Z, float is, int want_lap, float *o) {
+    if (want_lap) l2p_grad_point_t<P, true>(sC, X, Y, Z, is, o);
+    else l2p_grad_point_t<P, false>(sC, X, Y, Z, is, o);
 }
 
 // L2P with derivatives at every point of each cell (in key order), one block per cell.

@@ -30,7 +30,8 @@ struct GradLeafSet {
 
 struct GradShared {
     float4 src[64];                 // staged sources: offsets from the leaf centre, weight
-    float red[5][64];
+    float sg[64];                   // their second weights (two fields at once)
+    float red[9][64];
     int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
 };
 
@@ -41,7 +42,12 @@ struct GradShared {
 // every G-th source of a staged chunk; the source points of up to 64 list entries
 // at a time form one sequence staged 64 per chunk, the next chunk loaded while
 // the current one is used; group partials are added in group order.
-__device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride, int want_lap, GradShared &sh) {
+// TWO: a second field at once, with the key-order weights g2 of the sources (value
+// and gradient, into out + 5): one exponential serves both, and each field's sums
+// are formed exactly as a pass of its own would form them.
+template <bool TWO>
+__device__ inline void p2p_grad_leaf_t(const GradLeafSet &L, const float *g2, int64_t v, int stride, int want_lap,
+                                       GradShared &sh) {
     if (v >= L.n_nodes || L.nnchild[v] != 0) return;
     const int lane = threadIdx.x & 63;
     float ct[3], half;
@@ -60,6 +66,7 @@ __device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride
         const float4 qt = L.ps[ti];
         const float tx = qt.x - ct[0], ty = qt.y - ct[1], tz = qt.z - ct[2];
         float su = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, sr = 0.f;
+        float gu = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         for (int64_t w0 = l0; w0 < l1; w0 += 64) {
             const int nw = l1 - w0 < 64 ? (int)(l1 - w0) : 64;
             int32_t esf = 0, esn = 0;
@@ -78,30 +85,45 @@ __device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride
             wave_sync();
             int owner = 0;
             float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+            float ngw = 0.f;
             auto fetch = [&](int c0) {
                 const int j = c0 + lane;
                 if (j < tot) {
                     while (sh.eend[owner] <= j) ++owner;
-                    nxt = L.ps[sh.efirst[owner] + j];
+                    const int32_t pj = sh.efirst[owner] + j;
+                    nxt = L.ps[pj];
+                    if (TWO) ngw = g2[pj];
                 }
             };
             fetch(0);
             for (int c0 = 0; c0 < tot; c0 += 64) {
                 const int ns = tot - c0 < 64 ? tot - c0 : 64;
                 wave_sync();
-                if (lane < ns) sh.src[lane] = make_float4(nxt.x - ct[0], nxt.y - ct[1], nxt.z - ct[2], nxt.w);
+                if (lane < ns) {
+                    sh.src[lane] = make_float4(nxt.x - ct[0], nxt.y - ct[1], nxt.z - ct[2], nxt.w);
+                    if (TWO) sh.sg[lane] = ngw;
+                }
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
                 for (int j = grp; j < ns; j += G) {
                     const float4 s4 = sh.src[j];
                     const float dx = tx - s4.x, dy = ty - s4.y, dz = tz - s4.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float e = s4.w * __builtin_amdgcn_exp2f(r2 * L.kexp);
-                    su += e;
+                    const float k = __builtin_amdgcn_exp2f(r2 * L.kexp);
+                    // no contraction: either field's sums carry the same bits as a pass of its own
+                    const float e = __fmul_rn(s4.w, k);
+                    su = __fadd_rn(su, e);
                     sx = fmaf(e, dx, sx);
                     sy = fmaf(e, dy, sy);
                     sz = fmaf(e, dz, sz);
                     sr = fmaf(e, r2, sr);
+                    if (TWO) {
+                        const float eg = __fmul_rn(sh.sg[j], k);
+                        gu = __fadd_rn(gu, eg);
+                        gx = fmaf(eg, dx, gx);
+                        gy = fmaf(eg, dy, gy);
+                        gz = fmaf(eg, dz, gz);
+                    }
                 }
             }
         }
@@ -111,19 +133,39 @@ __device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride
         sh.red[2][lane] = sy;
         sh.red[3][lane] = sz;
         sh.red[4][lane] = sr;
+        if (TWO) {
+            sh.red[5][lane] = gu;
+            sh.red[6][lane] = gx;
+            sh.red[7][lane] = gy;
+            sh.red[8][lane] = gz;
+        }
         wave_sync();
         if (grp == 0 && a < nt) {
-            float r[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            constexpr int NR = TWO ? 9 : 5;
+            float r[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) r[k] = 0.f;
             for (int q = 0; q < G; ++q)
-                for (int k = 0; k < 5; ++k) r[k] += sh.red[k][q * tp + a];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) r[k] += sh.red[k][q * tp + a];
             float *o = L.out + (int64_t)ti * stride;   // value, gradient x y z, Laplacian
             o[0] = r[0];
             o[1] = -2.f * L.inv_s2 * r[1];
             o[2] = -2.f * L.inv_s2 * r[2];
             o[3] = -2.f * L.inv_s2 * r[3];
             if (want_lap) o[4] = 4.f * L.inv_s2 * L.inv_s2 * r[4] - 6.f * L.inv_s2 * r[0];
+            if (TWO) {
+                o[5] = r[5];
+                o[6] = -2.f * L.inv_s2 * r[6];
+                o[7] = -2.f * L.inv_s2 * r[7];
+                o[8] = -2.f * L.inv_s2 * r[8];
+            }
         }
     }
+}
+
+__device__ inline void p2p_grad_leaf(const GradLeafSet &L, int64_t v, int stride, int want_lap, GradShared &sh) {
+    p2p_grad_leaf_t<false>(L, nullptr, v, stride, want_lap, sh);
 }
 
 // The gradients of input point j from its record (rec4: the record as float4),
