@@ -371,6 +371,21 @@ def main():
     dom = max(cands, key=lambda k: phases[k][0]) if cands else None
     roof = _roof(dom) if dom else None
     kernels = {k: _roof(k) for k in sorted(cands, key=lambda k: -phases[k][0])}
+    # the step as a whole: T_ideal = sum over the phases with a work model of
+    # (launches x algorithmic amount / peak), against the measured step time
+    t_ideal, modelled, unmodelled_ms = 0.0, [], 0.0
+    for ph, (tot_ms, launches) in phases.items():
+        info = _algorithmic(ph, ctx) if launches > 0 else None
+        if info is None:
+            unmodelled_ms += tot_ms / args.steps
+            continue
+        bound, unit, amount = info
+        pk = PEAK["hbm"] if unit == "GB/s" else (PEAK["fp32_mfma"] if bound == "mfma" else PEAK["fp32_vector"])
+        t_ideal += (launches / args.steps) * amount / pk
+        modelled.append(ph)
+    step_roof = {"t_ideal_ms": 1000.0 * t_ideal, "t_measured_ms": ms_per_step,
+                 "frac": 1000.0 * t_ideal / ms_per_step, "phases_modelled": sorted(modelled),
+                 "unmodelled_phase_ms": unmodelled_ms}
     if args.copy_calibration:
         # a plain device copy of known size, for scaling the HBM counters
         a = torch.empty(256 << 20, dtype=torch.float32, device=dev)
@@ -391,6 +406,7 @@ def main():
                    "rho": plan["rho"]},
         "roofline": roof,
         "kernel_rooflines": kernels,
+        "step_roofline": step_roof,
         "phases": per_phase,
         "ms_per_step_with_events": ms_events,
         "forward_only_ms": ms_fwd,
