@@ -122,7 +122,7 @@ def _descent_bench(args, dev):
     import torch
     import paper_2301_10570_amd as msp
     import synth
-    wl = synth.config(2)
+    wl = synth.blobs262k()
     T = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
     tree = msp.Tree()
     tree.build(T(wl.x), T(wl.y), T(wl.z), leaf_max=wl.leaf_max)
@@ -251,7 +251,7 @@ def main():
     import synth
 
     print("bench: generating the 4,194,304-neuron slab", file=sys.stderr, flush=True)
-    wl = synth.config(3, args.scale)
+    wl = synth.slab4m(args.scale)
     wl.p = args.p
     dev = torch.device("cuda", 0)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)

@@ -88,8 +88,8 @@ def blobs(n_blobs: int, per_blob: int, extent=4000.0, std=50.0, sigma=200.0, see
     return _finish(name or f"blobs{n_blobs}x{per_blob}", pos, rng, sigma, p, leaf_max)
 
 
-def config(idx: int, scale: float = 1.0) -> Workload:
-    """The five workloads of the study (idx 1..5).
+def _workload(idx: int, scale: float = 1.0) -> Workload:
+    """The workloads below by their stream number (which fixes their seed).
 
     scale < 1 shrinks the neuron counts (and nothing else) for quick tests.
     1: 4,096 neurons uniform in a 1000 um cube, sigma 100, p 8
@@ -99,24 +99,24 @@ def config(idx: int, scale: float = 1.0) -> Workload:
     4: 1,048,576 weighted sources and 1,048,576 separate targets uniform in a
        2 mm cube, sigma 200 (sources have w in 0..5 and a = 0, targets w = 0 and
        a = 1); extra["g"] holds upstream gradients drawn from U(0.5, 1.5)
-    5: 256 populations, see populations()
+    5: the 256 populations of populations()
     """
     seed = SEED_BASE + idx
     rng = np.random.default_rng(np.random.PCG64(seed))
     if idx == 1:
         n = max(1, int(round(4096 * scale)))
         pos = rng.random((n, 3)) * 1000.0
-        return _finish("cfg1_uniform4k", pos, rng, 100.0)
+        return _finish("uniform4k", pos, rng, 100.0)
     if idx == 2:
         per = max(1, int(round(4096 * scale)))
         centres = rng.random((64, 3)) * 4000.0
         off = rng.normal(0.0, 50.0, size=(64, per, 3))
         pos = (centres[:, None, :] + off).reshape(-1, 3)
-        return _finish("cfg2_blobs262k", pos, rng, 200.0)
+        return _finish("blobs262k", pos, rng, 200.0)
     if idx == 3:
         n = max(1, int(round(4194304 * scale)))
         pos = rng.random((n, 3)) * np.array([10000.0, 10000.0, 2000.0])
-        return _finish("cfg3_slab4M", pos, rng, 750.0)
+        return _finish("slab4M", pos, rng, 750.0)
     if idx == 4:
         m = max(1, int(round(1048576 * scale)))
         src = rng.random((m, 3)) * 2000.0
@@ -126,14 +126,35 @@ def config(idx: int, scale: float = 1.0) -> Workload:
         pos = np.concatenate([src, tgt]).astype(np.float32)
         a = np.concatenate([np.zeros(m, np.float32), np.ones(m, np.float32)])
         ww = np.concatenate([w, np.zeros(m, np.float32)])
-        return Workload("cfg4_grad1M", np.ascontiguousarray(pos[:, 0]),
+        return Workload("sources_targets_1M", np.ascontiguousarray(pos[:, 0]),
                         np.ascontiguousarray(pos[:, 1]), np.ascontiguousarray(pos[:, 2]),
                         a, ww, 200.0, 8, 64, {"g": np.concatenate([np.zeros(m, np.float32), g])})
-    raise ValueError(f"unknown config {idx}")
+    raise ValueError(f"unknown workload {idx}")
+
+
+def uniform4k(scale: float = 1.0) -> Workload:
+    """4,096 neurons uniform in a 1000 um cube, sigma 100 um."""
+    return _workload(1, scale)
+
+
+def blobs262k(scale: float = 1.0) -> Workload:
+    """262,144 neurons in 64 Gaussian blobs (4 mm cube, std 50 um), sigma 200 um."""
+    return _workload(2, scale)
+
+
+def slab4m(scale: float = 1.0) -> Workload:
+    """4,194,304 neurons uniform in a 10 x 10 x 2 mm slab, sigma 750 um."""
+    return _workload(3, scale)
+
+
+def sources_targets_1m(scale: float = 1.0) -> Workload:
+    """1,048,576 sources and 1,048,576 targets uniform in a 2 mm cube, sigma 200 um,
+    with upstream gradients in extra["g"]."""
+    return _workload(4, scale)
 
 
 def populations(count: int = 256, scale: float = 1.0, seed: int | None = None) -> list[Workload]:
-    """Config 5: independent populations with log-uniform sizes in [1024, 65536]
+    """Independent populations with log-uniform sizes in [1024, 65536]
     and log-uniform sigma in [50, 300] um, each uniform in its own 1 mm cube."""
     rng = np.random.default_rng(np.random.PCG64(SEED_BASE + 5 if seed is None else seed))
     sizes = np.rint(np.exp(rng.uniform(math.log(1024), math.log(65536), size=count))).astype(np.int64)
@@ -142,7 +163,7 @@ def populations(count: int = 256, scale: float = 1.0, seed: int | None = None) -
     for k in range(count):
         n = max(1, int(round(int(sizes[k]) * scale)))
         pos = rng.random((n, 3)) * 1000.0
-        out.append(_finish(f"cfg5_pop{k}", pos, rng, float(sigmas[k])))
+        out.append(_finish(f"population{k}", pos, rng, float(sigmas[k])))
     return out
 
 

@@ -57,7 +57,7 @@ def _check(wl, g, route, sample, full_sigma, p=8):
 @pytest.mark.parametrize("route", ["fgt", "direct"])
 def test_backward_small_full_sigma(route):
     """1/64 of the gradient workload: 16,384 sources + 16,384 targets, sigma over all pairs."""
-    wl = synth.config(4, 1 / 64)
+    wl = synth.sources_targets_1m(1 / 64)
     g = wl.extra["g"].astype(np.float64)
     sample = synth.sample_indices(wl.n, 1024, seed=404)
     print(f"backward small, route={route}", flush=True)
@@ -67,7 +67,7 @@ def test_backward_small_full_sigma(route):
 
 def test_backward_full_size_subset():
     """1,048,576 sources + 1,048,576 targets; derivatives checked on a 4,096-point subset."""
-    wl = synth.config(4)
+    wl = synth.sources_targets_1m()
     g = wl.extra["g"].astype(np.float64)
     sample = synth.sample_indices(wl.n, 4096, seed=405)
     print("backward 2M points, subset of 4096", flush=True)
@@ -102,7 +102,7 @@ def test_backward_signed_g_and_union_points():
 def test_autograd_function_matches_backward():
     import torch
     import paper_2301_10570_amd as msp
-    wl = synth.config(4, 1 / 256)
+    wl = synth.sources_targets_1m(1 / 256)
     d = to_dev(wl)
     x, y, z, w = (t.clone().requires_grad_(True) for t in (d["x"], d["y"], d["z"], d["w"]))
     sig = torch.tensor(wl.sigma, dtype=torch.float64, device=x.device, requires_grad=True)

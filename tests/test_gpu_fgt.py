@@ -27,8 +27,8 @@ def _forward(wl, **kw):
 
 
 @pytest.mark.parametrize("route,cutoff", [("fgt", 4.5), ("direct", 4.5), ("direct", 0.0), ("auto", 4.5)])
-def test_config1_all_targets(route, cutoff):
-    wl = synth.config(1)
+def test_uniform4k_all_targets(route, cutoff):
+    wl = synth.uniform4k()
     print(f"4,096-point cube route={route} cutoff={cutoff}", flush=True)
     tree, u = _forward(wl, route=route, cutoff_sigmas=cutoff)
     tgt = np.nonzero(wl.a > 0)[0]
@@ -41,8 +41,8 @@ def test_config1_all_targets(route, cutoff):
 
 
 @pytest.mark.parametrize("route", ["fgt", "direct"])
-def test_config2_blobs(route):
-    wl = synth.config(2)
+def test_blobs262k(route):
+    wl = synth.blobs262k()
     print(f"262,144-point blobs route={route}", flush=True)
     tree, u = _forward(wl, route=route)
     tgt = np.nonzero(wl.a > 0)[0]
@@ -55,14 +55,14 @@ def test_config2_blobs(route):
 
 @pytest.fixture(scope="module")
 def slab():
-    wl = synth.config(3)
+    wl = synth.slab4m()
     tgt = np.nonzero(wl.a > 0)[0]
     sel = tgt[synth.sample_indices(tgt.size, 384, seed=303)]
     ref = oracle.attraction(wl, sel)
     return wl, sel, ref
 
 
-def test_config3_full_slab_p8(slab):
+def test_slab4m_full_p8(slab):
     wl, sel, ref = slab
     print("4M-point slab p=8 auto", flush=True)
     tree, u = _forward(wl, p=8)
@@ -74,7 +74,7 @@ def test_config3_full_slab_p8(slab):
 
 
 @pytest.mark.parametrize("p", [4, 6, 10])
-def test_config3_p_sweep(slab, p):
+def test_slab4m_p_sweep(slab, p):
     wl, sel, ref = slab
     print(f"4M-point slab p={p}", flush=True)
     tree, u = _forward(wl, p=p, route="fgt")
@@ -115,7 +115,7 @@ def test_pass_level_parity_grids():
 def test_direct_baseline():
     import torch
     import paper_2301_10570_amd as msp
-    wl = synth.config(1)
+    wl = synth.uniform4k()
     print("all-pairs direct baseline", flush=True)
     tgt = np.nonzero(wl.a > 0)[0]
     src = np.nonzero(wl.w > 0)[0]
@@ -152,7 +152,7 @@ def test_exclude_self():
 def test_deterministic_and_linear():
     import torch
     import paper_2301_10570_amd as msp
-    wl = synth.config(3, 0.125)
+    wl = synth.slab4m(0.125)
     print("determinism + linearity (slab, 1/8 size)", flush=True)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"])
@@ -202,7 +202,7 @@ def test_m2l_matrix_cores_match_vector_path(p, level):
     """The MFMA translation passes give the vector-ALU passes' Taylor grid up to
     float32 rounding (checks the matrix-core lane layout), on ragged grids."""
     import paper_2301_10570_amd as msp
-    wl = synth.config(3, 0.03)
+    wl = synth.slab4m(0.03)
     print(f"M2L mfma vs valu p={p} level={level}", flush=True)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"])
@@ -221,7 +221,7 @@ def test_m2l_bf16x3_matches_fp32(p, level):
     """Split-bfloat16 translation passes: Taylor grid within the split's rounding
     (about 2^-16 per product) of the float32 vector-ALU grid, on ragged grids."""
     import paper_2301_10570_amd as msp
-    wl = synth.config(3, 0.03)
+    wl = synth.slab4m(0.03)
     print(f"M2L bf16x3 vs valu p={p} level={level}", flush=True)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"])
@@ -239,7 +239,7 @@ def test_m2l_bf16x3_matches_fp32(p, level):
 
 
 @pytest.mark.parametrize("p", [4, 6, 8, 10])
-def test_config3_bf16x3_vs_oracle(slab, p):
+def test_slab4m_bf16x3_vs_oracle(slab, p):
     """Full slab with the split-bfloat16 translation: error against the FP64
     oracle per p, within the 1e-4 bar."""
     import paper_2301_10570_amd as msp

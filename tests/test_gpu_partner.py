@@ -68,8 +68,8 @@ def _check(wl, tq, nq, seed, cutoff=0.0, exclude_self=False, p=8):
     return err.max()
 
 
-def test_partner_config1():
-    wl = synth.config(1)
+def test_partner_uniform4k():
+    wl = synth.uniform4k()
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     tq, nq = _queries(tr, wl.n, 300, seed=5)
     print("partner, 4,096-point cube, 300 queries", flush=True)
@@ -78,7 +78,7 @@ def test_partner_config1():
 
 
 def test_partner_blobs_exclude_self():
-    wl = synth.config(2, 0.125)
+    wl = synth.blobs262k(0.125)
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     tq, nq = _queries(tr, wl.n, 200, seed=7)
     print("partner blobs (1/8), exclude self", flush=True)
@@ -87,7 +87,7 @@ def test_partner_blobs_exclude_self():
 
 def test_partner_slab_ancestors():
     """Full 4M slab: moments are used for the large children."""
-    wl = synth.config(3)
+    wl = synth.slab4m()
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     tq, nq = _queries(tr, wl.n, 48, seed=9, ancestors_only=True)
     print("partner slab 4M, 48 ancestor queries", flush=True)
@@ -97,7 +97,7 @@ def test_partner_slab_ancestors():
 
 @pytest.mark.parametrize("p", [4, 10])
 def test_partner_other_p(p):
-    wl = synth.config(3, 0.0625)
+    wl = synth.slab4m(0.0625)
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     tq, nq = _queries(tr, wl.n, 64, seed=11 + p, ancestors_only=True)
     print(f"partner slab 1/16, p={p}", flush=True)
@@ -138,7 +138,7 @@ def test_node_moments_m2m_parity():
     import torch
     import paper_2301_10570_amd as msp
     from oracle import fgt as ofgt
-    wl = synth.config(3, 0.0625)
+    wl = synth.slab4m(0.0625)
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)

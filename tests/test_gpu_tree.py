@@ -43,10 +43,10 @@ def _compare(x, y, z, leaf_max=64, max_depth=21):
     tree.close()
 
 
-@pytest.mark.parametrize("idx,scale", [(1, 1.0), (2, 1.0), (3, 0.0625)])
-def test_tree_bitexact_configs(idx, scale):
-    wl = synth.config(idx, scale)
-    print(f"tree bit-exact: config {idx} n={wl.n}", flush=True)
+@pytest.mark.parametrize("make,scale", [("uniform4k", 1.0), ("blobs262k", 1.0), ("slab4m", 0.0625)])
+def test_tree_bitexact_workloads(make, scale):
+    wl = getattr(synth, make)(scale)
+    print(f"tree bit-exact: {make} x {scale} n={wl.n}", flush=True)
     _compare(wl.x, wl.y, wl.z)
 
 
@@ -59,7 +59,7 @@ def test_tree_bitexact_params(leaf_max, max_depth):
 
 def test_tree_full_slab():
     """4,194,304 points: the full slab workload."""
-    wl = synth.config(3)
+    wl = synth.slab4m()
     print("tree bit-exact: full slab", flush=True)
     _compare(wl.x, wl.y, wl.z)
 
