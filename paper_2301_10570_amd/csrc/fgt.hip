@@ -90,6 +90,40 @@ __global__ void k_m2l_ops(int p, int Gx, int Gy, int Gz, double step, float *ox,
     m2l_ops_one(p, Gx, Gy, Gz, step, ox, oy, oz, (int)(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
+// Largest cell offset along an axis whose translation can matter: the entries
+// (-1)^b/b! h_{a+b}(o step) of offset o, weighted by the largest moment and Taylor
+// scales rho^a/a! and rho^b of a cell (rho = step/2, so that |A_a| <= W rho^a / a!),
+// stay below 1e-9 of the zero-offset term for every larger offset.  The M2L
+// contractions skip the blocks beyond it.
+int m2l_band(int p, double step, int G) {
+    const double rho = 0.5 * step;
+    int band = 0;
+    for (int o = 1; o < G; ++o) {
+        const double x = o * step;
+        double h[2 * kMaxP];
+        h[0] = std::exp(-x * x);
+        if (2 * p - 1 > 1) h[1] = 2.0 * x * h[0];
+        for (int n = 1; n + 1 < 2 * p - 1; ++n) h[n + 1] = 2.0 * x * h[n] - 2.0 * n * h[n - 1];
+        double worst = 0.0, fa = 1.0, ra = 1.0;
+        for (int a = 0; a < p; ++a) {
+            if (a > 0) {
+                fa *= a;
+                ra *= rho;
+            }
+            double fb = 1.0, rb = 1.0;
+            for (int b = 0; b < p; ++b) {
+                if (b > 0) {
+                    fb *= b;
+                    rb *= rho;
+                }
+                worst = std::fmax(worst, std::fabs(h[a + b]) * ra * rb / (fa * fb));
+            }
+        }
+        if (worst >= 1e-9) band = o;
+    }
+    return band;
+}
+
 // Point range of a grid cell: the points whose level-`level` key prefix is the
 // cell's Morton code (contiguous in key order).
 __device__ inline void cell_range(const uint64_t *keys, int64_t n, int level, int kx, int ky, int kz,
@@ -439,7 +473,7 @@ __host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
 // y (MODE 1) or x (MODE 2).
 template <int RT, int MODE = 0, int PT = 0>
 __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, int G, const float *T, int64_t r0,
-                              float *sm, int Ga = 0) {
+                              float *sm, int Ga = 0, int band = 1 << 30) {
     // PT = 8: the term count is a compile-time 8, so the tile's index arithmetic
     // folds into constants and rows are read 16 bytes at a time; PT = 0: any p
     constexpr int NR = RT / 16;   // 16-wide column tiles per block
@@ -543,20 +577,31 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, 
         f32x4 acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        int s = (lane >> 4) / p, ai = (lane >> 4) % p;   // column u = 4 k + lane / 16 as (cell, term)
+        // K steps [kb, ke) that meet an operator block within `band` cells of this
+        // column block's cells (the blocks beyond it are negligible and skipped)
+        int kb = 0, ke = nk;
+        if (band < G - 1) {
+            const int vlast = vc * 16 + 15 < U ? vc * 16 + 15 : U - 1;
+            const int c_lo = (vc * 16) / p - band, c_hi = vlast / p + band;
+            kb = (c_lo > 0 ? c_lo : 0) * p / 4;
+            const int u_end = (c_hi + 1 < G ? c_hi + 1 : G) * p;
+            ke = (u_end + 3) / 4 < nk ? (u_end + 3) / 4 : nk;
+        }
+        const int u0 = 4 * kb + (lane >> 4);
+        int s = u0 / p, ai = u0 % p;   // column u = 4 k + lane / 16 as (cell, term)
         // p = 8: entry of step k at base8 - 64 (k / 2) + 4 (k % 2)
         const int base8 = ((tv + G - 1) * 8 + b) * 8 + (lane >> 4);
-        for (int k0 = 0; k0 < nk; k0 += KC) {
+        for (int k0 = kb; k0 < ke; k0 += KC) {
             // this lane's operator entries M[v][u] for KC steps
             float a[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 if constexpr (PT == 8) {
                     const int kk = k0 + k;
-                    a[k] = (v < U && kk < nk) ? sT[base8 - 64 * (kk >> 1) + 4 * (kk & 1)] : 0.f;
+                    a[k] = (v < U && kk < ke) ? sT[base8 - 64 * (kk >> 1) + 4 * (kk & 1)] : 0.f;
                 } else {
                     const int u = 4 * (k0 + k) + (lane >> 4);
-                    a[k] = (v < U && u < U) ? sT[((tv - s + G - 1) * p + b) * p + ai] : 0.f;
+                    a[k] = (v < U && u < U && k0 + k < ke) ? sT[((tv - s + G - 1) * p + b) * p + ai] : 0.f;
                     ai += 4;
                     while (ai >= p) {
                         ai -= p;
@@ -571,10 +616,10 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, 
                 for (int k = 0; k < KC; ++k) {
                     float bv;
                     if constexpr (PT == 8) {
-                        bv = k0 + k < nk ? bcol[4 * (k0 + k)] : 0.f;
+                        bv = k0 + k < ke ? bcol[4 * (k0 + k)] : 0.f;
                     } else {
                         const int u = 4 * (k0 + k) + (lane >> 4);
-                        bv = u < U ? bcol[4 * (k0 + k)] : 0.f;
+                        bv = (u < U && k0 + k < ke) ? bcol[4 * (k0 + k)] : 0.f;
                     }
                     acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bv, acc[j], 0, 0, 0);
                 }
@@ -600,10 +645,10 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, 
 
 template <int RT>
 __global__ void __launch_bounds__(256) k_m2l_gemm(const float *In, float *Out, int64_t R, int p, int G,
-                                                  const float *T) {
+                                                  const float *T, int band) {
     extern __shared__ float sm[];
-    if (p == 8) m2l_gemm_tile<RT, 0, 8>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
-    else m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm);
+    if (p == 8) m2l_gemm_tile<RT, 0, 8>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm, 0, band);
+    else m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm, 0, band);
 }
 
 // The same pass with split bfloat16 products (v_mfma_f32_16x16x32_bf16): each
@@ -1726,18 +1771,18 @@ __global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp) {
     const int64_t r0 = (g - bp.tile_off[PASS][k]) * 32;
     if (p == 8) {
         if constexpr (PASS == 0)
-            m2l_gemm_tile<32, 1, 8>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
+            m2l_gemm_tile<32, 1, 8>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1], f.band[0]);
         else if constexpr (PASS == 1)
-            m2l_gemm_tile<32, 0, 8>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
+            m2l_gemm_tile<32, 0, 8>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm, 0, f.band[1]);
         else
-            m2l_gemm_tile<32, 2, 8>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
+            m2l_gemm_tile<32, 2, 8>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0], f.band[2]);
     } else {
         if constexpr (PASS == 0)
-            m2l_gemm_tile<32, 1>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1]);
+            m2l_gemm_tile<32, 1>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1], f.band[0]);
         else if constexpr (PASS == 1)
-            m2l_gemm_tile<32, 0>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm);
+            m2l_gemm_tile<32, 0>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm, 0, f.band[1]);
         else
-            m2l_gemm_tile<32, 2>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0]);
+            m2l_gemm_tile<32, 2>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0], f.band[2]);
     }
 }
 
@@ -2100,6 +2145,7 @@ int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, F
     f->cell = pl.cell;
     f->inv_sigma = 1.0 / prm->sigma;
     f->step = pl.cell / prm->sigma;
+    for (int k = 0; k < 3; ++k) f->band[k] = m2l_band(p, f->step, pl.G[k]);
     return MSP_OK;
 }
 
@@ -2249,12 +2295,13 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
             const size_t lds = m2l_gemm_lds((int)ps.U, ps.G, p, RT);
             if (lds <= 64 * 1024) {
                 const dim3 grid((unsigned)((ps.R + RT - 1) / RT));
+                const int band = m2l_band(p, step, ps.G);
                 if (RT == 64)
-                    hipLaunchKernelGGL(k_m2l_gemm<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+                    hipLaunchKernelGGL(k_m2l_gemm<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T, band);
                 else if (RT == 32)
-                    hipLaunchKernelGGL(k_m2l_gemm<32>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+                    hipLaunchKernelGGL(k_m2l_gemm<32>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T, band);
                 else
-                    hipLaunchKernelGGL(k_m2l_gemm<16>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+                    hipLaunchKernelGGL(k_m2l_gemm<16>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T, band);
             } else {
                 dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
                 hipLaunchKernelGGL(k_m2l_pass_mfma, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);

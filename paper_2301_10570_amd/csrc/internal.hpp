@@ -158,6 +158,7 @@ struct FgtPop {
     int subtract_self;
     float *A, *B, *Tmp, *opsx, *opsy, *opsz;
     int level, G[3];
+    int band[3];         // largest cell offset per axis whose translation is not negligible
     double lo[3], cell, inv_sigma, step;
     int pop;
 };
