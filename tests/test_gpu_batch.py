@@ -166,3 +166,84 @@ def test_batch_autotune(pops):
         sel = tgt[synth.sample_indices(tgt.size, 16, seed=950 + k)]
         assert rel_err(u[lo:lo + wl.n][sel], oracle.attraction(wl, sel)).max() <= TOL
     b.close()
+
+
+def _single_backward(wl, g, want):
+    import torch
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tree, _ = _single(wl)
+    ref = tree.backward(T(wl.w), g.contiguous(), T((wl.a > 0).astype(np.uint8)),
+                        sigma=float(np.float32(wl.sigma)), p=8, want=want)
+    route = tree.plan(float(np.float32(wl.sigma)), p=8)["route"]
+    tree.close()
+    return ref, route
+
+
+def test_batch_backward_subsets_and_empty_population(pops):
+    import torch
+    import paper_2301_10570_amd as msp
+    print("batch backward: one empty population, gradient subsets", flush=True)
+    sub = pops[8:14]
+    x, y, z, w, tg, off, sig = _concat(sub, empty_at=2)
+    b = msp.Batch().build(x, y, z, off)
+    g = torch.from_numpy(synth.uniforms(x.numel(), 902) + np.float32(0.5)).cuda()
+    for want in (("w",), ("sigma",), ("pos", "sigma")):
+        got = b.backward(w, g, sig, is_target=tg, want=want)
+        if "sigma" in want:
+            assert got["sigma"][2].item() == 0.0          # the empty population
+        k = 0
+        for i in range(len(off) - 1):
+            lo, hi = off[i], off[i + 1]
+            if hi == lo:
+                continue
+            ref, route = _single_backward(sub[k], g[lo:hi], want)
+            k += 1
+            for key in want:
+                if key == "sigma":
+                    gs, rs = got["sigma"][i].item(), ref["sigma"].item()
+                    if route == "direct":
+                        assert gs == rs
+                    else:
+                        assert abs(gs - rs) <= 1e-4 * abs(rs) + 1e-30
+                    continue
+                gv = [got[key]] if key == "w" else got[key]
+                rv = [ref[key]] if key == "w" else ref[key]
+                for a_, b_ in zip(gv, rv):
+                    a_, b_ = a_[lo:hi].cpu().numpy(), b_.cpu().numpy()
+                    if route == "direct":
+                        np.testing.assert_array_equal(a_, b_)
+                    else:
+                        np.testing.assert_allclose(a_, b_, rtol=1e-4, atol=1e-5 * np.abs(b_).max())
+    b.close()
+
+
+def test_batch_forward_and_backward_graphs_alternate(pops):
+    import torch
+    import paper_2301_10570_amd as msp
+    print("batch forward and backward graphs, alternating, against eager results", flush=True)
+    sub = pops[:5]
+    x, y, z, w, tg, off, sig = _concat(sub)
+    b = msp.Batch().build(x, y, z, off)
+    g = torch.from_numpy(synth.uniforms(x.numel(), 903) + np.float32(0.5)).cuda()
+    u_ref = b.forward(w, sig, is_target=tg, use_graph=False).cpu().numpy()
+    gr = b.backward(w, g, sig, is_target=tg)
+    g_ref = {"w": gr["w"].cpu().numpy(), "sigma": gr["sigma"].cpu().numpy(),
+             "pos": [a.cpu().numpy() for a in gr["pos"]]}
+    u = torch.empty(x.numel(), dtype=torch.float32, device="cuda")
+    out = None
+    for rep in range(3):
+        u.zero_()
+        b.forward(w, sig, is_target=tg, out=u, use_graph=True)     # eager + capture, then replays
+        np.testing.assert_array_equal(u.cpu().numpy(), u_ref)
+        if out is not None:
+            for k_ in ("w", "sigma_full"):
+                out[k_].zero_()
+            for a in out["pos"]:
+                a.zero_()
+        out = b.backward(w, g, sig, is_target=tg, out=out, use_graph=True)
+        np.testing.assert_array_equal(out["w"].cpu().numpy(), g_ref["w"])
+        np.testing.assert_array_equal(out["sigma"].cpu().numpy(), g_ref["sigma"])
+        for a in range(3):
+            np.testing.assert_array_equal(out["pos"][a].cpu().numpy(), g_ref["pos"][a])
+        torch.cuda.synchronize()
+    b.close()
