@@ -1200,6 +1200,16 @@ struct GridArgs {
     float *u_out;
 };
 
+// Target flags and the self term applied in input order after an L2P that wrote
+// every point's sum: reading the flags and weights here is coalesced, where the
+// L2P would have gathered them through the permutation.
+__global__ void k_finish_u(int64_t n, const uint8_t *is_target, const float *w, int subtract_self, float *u) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const bool tg = !is_target || is_target[j];
+    u[j] = tg ? (subtract_self ? u[j] - w[j] : u[j]) : 0.f;
+}
+
 template <int P, int PF>
 int launch_2lvl(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, const float *C, float *A,
                 const GridArgs &ga, hipStream_t s) {
@@ -1242,10 +1252,15 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
                            ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
                            t->geo.lo[2], pl.cell, inv_sigma, A);
     } else {
+        // every point's sum straight to input order, flags and self term afterwards
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
-                           ga.is_target, ga.w, ga.subtract_self, pl.level, pl.G[0], pl.G[1], pl.G[2],
+                           (const uint8_t *)nullptr, ga.w, 0, pl.level, pl.G[0], pl.G[1], pl.G[2],
                            t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, ga.u_out);
+        MSP_CHECK_LAUNCH();
+        if (ga.is_target || ga.subtract_self)
+            hipLaunchKernelGGL(k_finish_u, dim3(grid_for(t->n, kBlock)), dim3(kBlock), 0, s, t->n, ga.is_target,
+                               ga.w, ga.subtract_self, ga.u_out);
     }
     MSP_CHECK_LAUNCH();
     return MSP_OK;
