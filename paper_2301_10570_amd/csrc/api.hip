@@ -51,6 +51,26 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+int HostBuf::ensure(size_t need) {
+    if (need == 0) need = 1;
+    if (need <= bytes) return MSP_OK;
+    release();
+    hipError_t e = hipHostMalloc(&p, need, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(MSP_EHIP, "hipHostMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+    }
+    bytes = need;
+    return MSP_OK;
+}
+
+void HostBuf::release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
 hipEvent_t Timing::get() {
     if (!pool.empty()) {
         hipEvent_t e = pool.back();

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace msp {
@@ -322,32 +323,88 @@ void range_of(const DescentCtx &c, int64_t item, int64_t &first, int64_t &count)
     }
 }
 
+// Device arrays of one step (the tree's, kept between descents): the host lists
+// travel in one copy from a page-locked staging buffer into `lists` (each array
+// at a 256-byte aligned offset).
 struct StepBufs {
-    DevBuf qt, qs, qn, qa, raw, probs, ti, tcf, tnc, toff, ta, dv, crng, units, choice;
+    DevBuf &lists, &raw, &probs, &dv, &choice;
+    HostBuf &stage;
+    const int32_t *qt = nullptr, *qs = nullptr, *qn = nullptr, *ti = nullptr, *tcf = nullptr, *tnc = nullptr;
+    const float *qa = nullptr, *ta = nullptr;
+    const int64_t *toff = nullptr, *crng = nullptr;
+    const UnitDesc *units = nullptr;
 };
 
-template <class T>
-int upload(DevBuf &b, const std::vector<T> &v) {
-    MSP_TRY(b.ensure((v.size() > 0 ? v.size() : 1) * sizeof(T)));
-    if (!v.empty()) MSP_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return MSP_OK;
-}
-
-// one step on the host frontier (pairs S[k], T[k]) -> next frontier and requests
-int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t seed, int step,
-              const std::vector<int64_t> &S, const std::vector<int64_t> &T, std::vector<int64_t> &S2,
-              std::vector<int64_t> &T2, std::vector<int32_t> &ra, std::vector<int32_t> &rd, hipStream_t s) {
-    S2.clear();
-    T2.clear();
+// The host lists of one step, kept across steps so that their storage is reused.
+struct StepHost {
     std::vector<int32_t> qt, qs, qn, ti, tcf, tnc;
     std::vector<float> qa, ta;
     std::vector<int64_t> toff, crng;
     std::vector<UnitDesc> units;
+    std::vector<int64_t> keep, cand_off, cand;
+    std::vector<int32_t> side, pick;
+    std::vector<int64_t> chS;
+    void clear() {
+        qt.clear(); qs.clear(); qn.clear(); ti.clear(); tcf.clear(); tnc.clear();
+        qa.clear(); ta.clear(); toff.clear(); crng.clear(); units.clear();
+        keep.clear(); cand_off.assign(1, 0); cand.clear(); side.clear(); chS.clear();
+    }
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// all lists of the step in one host-to-device copy
+int upload_lists(StepBufs &B, StepHost &H, hipStream_t s) {
+    struct Item { const void *src; size_t bytes; size_t off; };
+    Item it[11] = {{H.qt.data(), H.qt.size() * 4, 0}, {H.qs.data(), H.qs.size() * 4, 0},
+                   {H.qn.data(), H.qn.size() * 4, 0}, {H.qa.data(), H.qa.size() * 4, 0},
+                   {H.ti.data(), H.ti.size() * 4, 0}, {H.tcf.data(), H.tcf.size() * 4, 0},
+                   {H.tnc.data(), H.tnc.size() * 4, 0}, {H.toff.data(), H.toff.size() * 8, 0},
+                   {H.ta.data(), H.ta.size() * 4, 0}, {H.crng.data(), H.crng.size() * 8, 0},
+                   {H.units.data(), H.units.size() * sizeof(UnitDesc), 0}};
+    size_t total = 0;
+    for (Item &x : it) {
+        x.off = total;
+        total += align_up(x.bytes > 0 ? x.bytes : 1);
+    }
+    MSP_TRY(B.stage.ensure(total));
+    MSP_TRY(B.lists.ensure(total));
+    char *h = static_cast<char *>(B.stage.p);
+    for (const Item &x : it)
+        if (x.bytes) std::memcpy(h + x.off, x.src, x.bytes);
+    MSP_HIP(hipMemcpyAsync(B.lists.p, B.stage.p, total, hipMemcpyHostToDevice, s));
+    const char *d = B.lists.as<char>();
+    B.qt = reinterpret_cast<const int32_t *>(d + it[0].off);
+    B.qs = reinterpret_cast<const int32_t *>(d + it[1].off);
+    B.qn = reinterpret_cast<const int32_t *>(d + it[2].off);
+    B.qa = reinterpret_cast<const float *>(d + it[3].off);
+    B.ti = reinterpret_cast<const int32_t *>(d + it[4].off);
+    B.tcf = reinterpret_cast<const int32_t *>(d + it[5].off);
+    B.tnc = reinterpret_cast<const int32_t *>(d + it[6].off);
+    B.toff = reinterpret_cast<const int64_t *>(d + it[7].off);
+    B.ta = reinterpret_cast<const float *>(d + it[8].off);
+    B.crng = reinterpret_cast<const int64_t *>(d + it[9].off);
+    B.units = reinterpret_cast<const UnitDesc *>(d + it[10].off);
+    return MSP_OK;
+}
+
+// one step on the host frontier (pairs S[k], T[k]) -> next frontier and requests
+int step_once(DescentCtx &c, StepBufs &B, StepHost &H, const msp_fgt_params *prm, uint64_t seed, int step,
+              const std::vector<int64_t> &S, const std::vector<int64_t> &T, std::vector<int64_t> &S2,
+              std::vector<int64_t> &T2, std::vector<int32_t> &ra, std::vector<int32_t> &rd, hipStream_t s) {
+    S2.clear();
+    T2.clear();
+    H.clear();
+    auto &qt = H.qt, &qs = H.qs, &qn = H.qn, &ti = H.ti, &tcf = H.tcf, &tnc = H.tnc;
+    auto &qa = H.qa, &ta = H.ta;
+    auto &toff = H.toff, &crng = H.crng;
+    auto &units = H.units;
     // per unit: the other item of the next pair and the candidate items
-    std::vector<int64_t> keep, cand_off{0}, cand;
-    std::vector<int32_t> side;   // 0: next pair (keep, cand); 1: (cand, keep)
+    auto &keep = H.keep, &cand_off = H.cand_off, &cand = H.cand;
+    auto &side = H.side;   // 0: next pair (keep, cand); 1: (cand, keep)
     int64_t dvn = 0;
-    std::vector<int64_t> chS, chT;
+    auto &chS = H.chS;
     auto add_task = [&](int64_t p_axon, int64_t cf, int64_t nc) {
         ti.push_back((int32_t)p_axon);
         tcf.push_back((int32_t)cf);
@@ -428,35 +485,24 @@ int step_once(DescentCtx &c, StepBufs &B, const msp_fgt_params *prm, uint64_t se
     }
     const int64_t nq = (int64_t)qt.size(), ntask = (int64_t)ti.size(), nu = (int64_t)units.size();
     if (nu == 0) return MSP_OK;
-    MSP_TRY(upload(B.qt, qt));
-    MSP_TRY(upload(B.qs, qs));
-    MSP_TRY(upload(B.qn, qn));
-    MSP_TRY(upload(B.qa, qa));
-    MSP_TRY(upload(B.ti, ti));
-    MSP_TRY(upload(B.tcf, tcf));
-    MSP_TRY(upload(B.tnc, tnc));
-    MSP_TRY(upload(B.toff, toff));
-    MSP_TRY(upload(B.ta, ta));
-    MSP_TRY(upload(B.crng, crng));
-    MSP_TRY(upload(B.units, units));
+    MSP_TRY(upload_lists(B, H, s));
     MSP_TRY(B.raw.ensure((size_t)(nq > 0 ? nq : 1) * 8 * sizeof(double)));
     MSP_TRY(B.probs.ensure((size_t)(nq > 0 ? nq : 1) * 8 * sizeof(float)));
     MSP_TRY(B.dv.ensure((size_t)(dvn > 0 ? dvn : 1) * sizeof(double)));
     MSP_TRY(B.choice.ensure((size_t)nu * sizeof(int32_t)));
     if (nq > 0)
-        MSP_TRY(partner_query_raw(c.t, prm, B.qt.as<int32_t>(), B.qn.as<int32_t>(), nq, B.probs.as<float>(),
-                                  B.raw.as<double>(), B.qs.as<int32_t>(), s));
+        MSP_TRY(partner_query_raw(c.t, prm, B.qt, B.qn, nq, B.probs.as<float>(), B.raw.as<double>(), B.qs, s));
     if (ntask > 0) {
-        hipLaunchKernelGGL(k_desc_direct, dim3(grid_for(ntask, 4)), dim3(256), 0, s, ntask, B.ti.as<int32_t>(),
-                           B.tcf.as<int32_t>(), B.tnc.as<int32_t>(), B.toff.as<int64_t>(), c.t->ps.as<float4>(),
+        hipLaunchKernelGGL(k_desc_direct, dim3(grid_for(ntask, 4)), dim3(256), 0, s, ntask, B.ti, B.tcf, B.tnc,
+                           B.toff, c.t->ps.as<float4>(),
                            1.0 / ((double)prm->sigma * prm->sigma), B.dv.as<double>());
         MSP_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_desc_choose, dim3(grid_for(nu, 4)), dim3(256), 0, s, nu, B.units.as<UnitDesc>(),
-                       B.raw.as<double>(), B.qa.as<float>(), B.dv.as<double>(), B.toff.as<int64_t>(),
-                       B.ta.as<float>(), B.crng.as<int64_t>(), seed, step, B.choice.as<int32_t>());
+    hipLaunchKernelGGL(k_desc_choose, dim3(grid_for(nu, 4)), dim3(256), 0, s, nu, B.units, B.raw.as<double>(),
+                       B.qa, B.dv.as<double>(), B.toff, B.ta, B.crng, seed, step, B.choice.as<int32_t>());
     MSP_CHECK_LAUNCH();
-    std::vector<int32_t> pick((size_t)nu);
+    auto &pick = H.pick;
+    pick.resize((size_t)nu);
     MSP_HIP(hipMemcpyAsync(pick.data(), B.choice.p, (size_t)nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MSP_HIP(hipStreamSynchronize(s));
     for (int64_t u = 0; u < nu; ++u) {
@@ -493,10 +539,11 @@ int descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_para
     MSP_TRY(ctx_init(c, t, w, a, &q, s));
     MSP_TRY(check_items(c, S_in, m));
     MSP_TRY(check_items(c, T_in, m));
-    StepBufs B;
+    StepBufs B{t->desc_lists, t->desc_raw, t->desc_probs, t->desc_dv, t->desc_choice, t->desc_stage};
+    StepHost H;
     std::vector<int64_t> S(S_in, S_in + m), T(T_in, T_in + m), S2, T2;
     std::vector<int32_t> ra, rd;
-    MSP_TRY(step_once(c, B, &q, seed, step, S, T, S2, T2, ra, rd, s));
+    MSP_TRY(step_once(c, B, H, &q, seed, step, S, T, S2, T2, ra, rd, s));
     *m_out = (int64_t)S2.size();
     *n_req = (int64_t)ra.size();
     if ((int64_t)S2.size() > cap) return fail(MSP_ENOSPC, "next frontier has %lld pairs, capacity %lld",
@@ -517,7 +564,8 @@ int partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_p
     q.flags |= MSP_EXCLUDE_SELF;
     DescentCtx c;
     MSP_TRY(ctx_init(c, t, w, a, &q, s));
-    StepBufs B;
+    StepBufs B{t->desc_lists, t->desc_raw, t->desc_probs, t->desc_dv, t->desc_choice, t->desc_stage};
+    StepHost H;
     std::vector<int64_t> S, T, S2, T2;
     std::vector<int32_t> ra, rd;
     if (c.nn > 0 && c.axc[c.n] > 0) {
@@ -529,7 +577,7 @@ int partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_p
     const int max_steps = 2 * (t->depth + 2) + 2;
     int step = 0;
     for (; step < max_steps && !S.empty(); ++step) {
-        MSP_TRY(step_once(c, B, &q, seed, step, S, T, S2, T2, ra, rd, s));
+        MSP_TRY(step_once(c, B, H, &q, seed, step, S, T, S2, T2, ra, rd, s));
         S.swap(S2);
         T.swap(T2);
     }

@@ -51,6 +51,18 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// A grow-only page-locked host allocation owned by a handle (staging of uploads).
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { release(); }
+    int ensure(size_t need);
+    void release();
+};
+
 // Parameters that kernels need about the tree's geometry.
 struct Geometry {
     double lo[3];
@@ -137,6 +149,10 @@ struct msp_tree {
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
     msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
+    // partner descent: one step's lists (staged in page-locked memory, then one
+    // copy), query sums, direct sums and choices; kept for the next descent
+    msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_choice;
+    msp::HostBuf desc_stage;
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
 };
