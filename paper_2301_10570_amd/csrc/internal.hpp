@@ -149,6 +149,7 @@ struct msp_tree {
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
     msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
+    msp::DevBuf partner_order; // walk queries by level of the query node (segments), then tallies
     // partner descent: one step's lists (staged in page-locked memory, then one
     // copy), query sums, direct sums and choices; kept for the next descent
     msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_choice;

@@ -857,10 +857,23 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
           double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
           const float *nodeA, int64_t slot0, double sigma, float cutoff2, int unlimited,
           double rho_ref, int exclude_self, float *probs, int32_t *choice, const uint8_t *done,
-          double *raw) {
+          double *raw, const int32_t *qorder) {
     constexpr int P3 = P * P * P;
     __shared__ int32_t stk[kStack];
-    const int64_t q = blockIdx.x;
+    // blocks take the queries left by the leaf-children pass, coarsest query nodes
+    // first (their walks are the longest, so they start early), then exit
+    int64_t q = nq;
+    {
+        const int32_t *tally = qorder + (size_t)kMaxLevels * nq;
+        int64_t b = blockIdx.x;
+        for (int l = 0; l < kMaxLevels; ++l) {
+            if (b < tally[l]) {
+                q = qorder[(size_t)l * nq + b];
+                break;
+            }
+            b -= tally[l];
+        }
+    }
     const int lane = threadIdx.x;
     if (q >= nq || done[q]) return;
     const int32_t ti = target_idx[q], X = node_id[q];
@@ -1154,6 +1167,37 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     }
 }
 
+// Order of the walk's queries, coarsest query node first, without contention on
+// a few counters: a block tallies its queries per level in LDS, reserves room for
+// each level with one atomic addition, and places them in that level's segment
+// order[l * nq ...]; the per-level tallies (after the segments) give the walk its
+// mapping from block to query.  The order inside a level does not matter: every
+// query writes only its own outputs.
+__global__ void k_order_clear(int32_t *tally) {
+    if (threadIdx.x < kMaxLevels) tally[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_order_place(int64_t nq, const uint8_t *done, const int32_t *node_id,
+                                                     int64_t n_nodes, const int32_t *nlevel, int32_t *order) {
+    __shared__ int32_t cnt[kMaxLevels], base[kMaxLevels];
+    int32_t *tally = order + (size_t)kMaxLevels * nq;
+    if (threadIdx.x < kMaxLevels) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int l = -1, slot = 0;
+    if (q < nq && !done[q]) {
+        const int32_t X = node_id[q];
+        l = (X >= 0 && X < n_nodes) ? nlevel[X] : 0;
+        l = l < kMaxLevels ? l : kMaxLevels - 1;
+        slot = atomicAdd(&cnt[l], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLevels && cnt[threadIdx.x] > 0)
+        base[threadIdx.x] = atomicAdd(&tally[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (l >= 0) order[(size_t)l * nq + base[l] + slot] = (int32_t)q;
+}
+
 // coarsest level whose half-side is within rho_max(p) sigma: the moment level
 int moment_level(const msp_tree *t, double sigma, int p) {
     const double rmax = rho_max_for_p(p);
@@ -1256,6 +1300,13 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                            t->partner_done.as<uint8_t>(), raw);
         MSP_CHECK_LAUNCH();
     }
+    MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
+    int32_t *order = t->partner_order.as<int32_t>();
+    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, order + (size_t)kMaxLevels * nq);
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq,
+                       t->partner_done.as<uint8_t>(), node_id, nn, t->nlevel.as<int32_t>(), order);
+    MSP_CHECK_LAUNCH();
     PhaseScope ps(&t->timing, PH_PARTNER, s);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nq), dim3(64), 0, s, nq, target_idx,
                        node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
@@ -1264,7 +1315,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                        t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
                        t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma,
                        R * R, unlimited ? 1 : 0, rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs,
-                       choice, t->partner_done.as<uint8_t>(), raw);
+                       choice, t->partner_done.as<uint8_t>(), raw, order);
     MSP_CHECK_LAUNCH();
     return MSP_OK;
 }
