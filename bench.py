@@ -269,7 +269,8 @@ def main():
         tree.build(x, y, z, leaf_max=wl.leaf_max)
         tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
         if tq.numel():
-            tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni)
+            # the same counts as the forward: its P2M already gathered w into key order
+            tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
 
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):

@@ -75,7 +75,16 @@ enum msp_flags {
      * matrix cores: every float32 operand x becomes hi = bf16(x) plus
      * lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi is accumulated in float32
      * (about 2^-16 of each product is lost).  Exclusive with MSP_M2L_VALU. */
-    MSP_M2L_BF16X3 = 1u << 3
+    MSP_M2L_BF16X3 = 1u << 3,
+    /* For msp_partner_probabilities: `w` is the weight array of the last
+     * msp_fgt_forward, msp_partner_probabilities or msp_partner_descent call on
+     * this tree, unchanged since (an MSP step evaluates the sums and then the
+     * partner probabilities with the same vacant element counts).  The weights
+     * that call gathered into key order are used again instead of being gathered
+     * a second time.  MSP_ESTATE if no such call has gathered weights since the
+     * tree was built or since a backward call (which gathers other weights);
+     * the contents of `w` are not checked. */
+    MSP_WEIGHTS_STAGED = 1u << 4
 };
 
 typedef struct msp_tree msp_tree; /* opaque handle */

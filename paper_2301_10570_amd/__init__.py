@@ -30,6 +30,7 @@ EXCLUDE_SELF = 1
 M2L_VALU = 2
 TWO_LEVEL = 4
 M2L_BF16X3 = 8
+WEIGHTS_STAGED = 16
 
 
 class MspError(RuntimeError):
@@ -282,7 +283,11 @@ class Tree:
         return out
 
     def partner_probabilities(self, w, target_idx, node_id, sigma, p=8, uniforms=None,
-                              exclude_self=False, level=-1, cutoff_sigmas=4.5):
+                              exclude_self=False, level=-1, cutoff_sigmas=4.5, weights_staged=False):
+        """Child probabilities (msp_partner_probabilities): probs [nq, 8] and choice [nq].
+        weights_staged: w is the weight array of the last forward, partner or descent
+        call on this tree, unchanged since, and the weights that call gathered into
+        key order are used again (MSP_WEIGHTS_STAGED)."""
         nq = target_idx.numel()
         pw = _ptr(w, torch.float32, self.n, "w")
         pti = _ptr(target_idx, torch.int32, nq, "target_idx")
@@ -291,6 +296,8 @@ class Tree:
         probs = torch.empty(nq * 8, dtype=torch.float32, device=w.device)
         choice = torch.empty(nq, dtype=torch.int32, device=w.device)
         prm = _params(sigma, p, level, "auto", cutoff_sigmas, exclude_self)
+        if weights_staged:
+            prm.flags |= WEIGHTS_STAGED
         _check(_lib.msp_partner_probabilities(self._h, pw, ctypes.byref(prm), pti, pni, nq, pu,
                                               probs.data_ptr() if nq else None,
                                               choice.data_ptr() if nq else None, _stream()),

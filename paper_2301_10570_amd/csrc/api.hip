@@ -117,7 +117,8 @@ static int check_params(const msp_fgt_params *prm) {
     if (!(prm->sigma > 0.f) || !std::isfinite(prm->sigma)) return fail(MSP_EINVAL, "sigma must be finite and > 0");
     if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
     if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
-    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL | MSP_M2L_BF16X3))
+    if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL | MSP_M2L_BF16X3 |
+                                 MSP_WEIGHTS_STAGED))
         return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
     if ((prm->flags & MSP_M2L_VALU) && (prm->flags & MSP_M2L_BF16X3))
         return fail(MSP_EINVAL, "MSP_M2L_VALU and MSP_M2L_BF16X3 exclude each other");
@@ -239,8 +240,14 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     hipStream_t s = (hipStream_t)stream;
     FgtPlan pl;
     MSP_TRY(plan_fgt(t, prm, &pl));
-    if (pl.route == MSP_ROUTE_FGT) return fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
+    t->w_staged = false;   // set again by the paths that gather w into ps.w
+    if (pl.route == MSP_ROUTE_FGT) {
+        const int rc = fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
+        t->w_staged = rc == MSP_OK && pl.pf == 0;   // the single-level P2M gathers w into ps.w
+        return rc;
+    }
     MSP_TRY(stage_inputs(t, w, is_target, s));
+    t->w_staged = true;
     MSP_TRY(direct_route(t, prm, s));
     return scatter_output(t, u_out, prm->flags, false, s);
 }
@@ -255,6 +262,7 @@ int msp_fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target,
     if (t->n > 0 && (!w || !grad_u)) return fail(MSP_EINVAL, "NULL weight or upstream gradient");
     const int npos = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);
     if (npos != 0 && npos != 3) return fail(MSP_EINVAL, "give all three position gradients or none");
+    t->w_staged = false;   // the backward gathers the upstream gradient into ps.w too
     return fgt_backward(t, w, is_target, prm, grad_u, grad_w, grad_x, grad_y, grad_z, grad_sigma,
                         (hipStream_t)stream);
 }
@@ -282,8 +290,12 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
     if (nq < 0) return fail(MSP_EINVAL, "nq < 0");
     if (nq > 0 && (!w || !target_idx || !node_id || !probs)) return fail(MSP_EINVAL, "NULL array");
     if (nq > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "nq exceeds 2^31-1");
-    return partner_probabilities(t, w, prm, target_idx, node_id, nq, uniforms, probs, choice,
-                                 (hipStream_t)stream);
+    if ((prm->flags & MSP_WEIGHTS_STAGED) && !t->w_staged)
+        return fail(MSP_ESTATE, "MSP_WEIGHTS_STAGED: no weights gathered since the tree was built or since a backward call");
+    const int rc = partner_probabilities(t, w, prm, target_idx, node_id, nq, uniforms, probs, choice,
+                                         (hipStream_t)stream);
+    t->w_staged = rc == MSP_OK;
+    return rc;
 }
 
 int msp_descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
@@ -306,8 +318,10 @@ int msp_descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_
         *n_req = 0;
         return MSP_OK;
     }
-    return descent_step(t, w, a, prm, seed, step, S_in, T_in, m, S_out, T_out, cap, m_out, req_axon,
-                        req_dendrite, req_cap, n_req, (hipStream_t)stream);
+    const int rc = descent_step(t, w, a, prm, seed, step, S_in, T_in, m, S_out, T_out, cap, m_out, req_axon,
+                                req_dendrite, req_cap, n_req, (hipStream_t)stream);
+    t->w_staged = rc == MSP_OK;
+    return rc;
 }
 
 int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
@@ -324,8 +338,10 @@ int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_f
         if (n_steps) *n_steps = 0;
         return MSP_OK;
     }
-    return partner_descent(t, w, a, prm, seed, req_axon, req_dendrite, accepted, n_req, n_steps,
-                           (hipStream_t)stream);
+    const int rc = partner_descent(t, w, a, prm, seed, req_axon, req_dendrite, accepted, n_req, n_steps,
+                                   (hipStream_t)stream);
+    t->w_staged = rc == MSP_OK;
+    return rc;
 }
 
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,

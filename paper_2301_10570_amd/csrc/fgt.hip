@@ -142,7 +142,7 @@ __device__ inline void cell_range(const uint64_t *keys, int64_t n, int level, in
 template <int P>
 __device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, int Gx, int Gy,
                          double lox, double loy, double loz, double cell, double inv_sigma, float *A,
-                         int kx, int ky, int kz, int64_t start, int64_t end) {
+                         int kx, int ky, int kz, int64_t start, int64_t end, float4 *stage) {
     constexpr int P3 = P * P * P;
     constexpr int PL = 64 / P;            // point lanes per wave
     constexpr int NW = kBlock / 64;
@@ -166,8 +166,10 @@ __device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, 
         const int64_t j = c0 + tid;
         if (j < end) {
             const float4 q = ps[j];
+            const float wv = w[perm[j]];
+            if (stage) stage[j].w = wv;   // the weight in key order, for later calls
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
-                              (float)(((double)q.z - cz) * inv_sigma), w[perm[j]]);
+                              (float)(((double)q.z - cz) * inv_sigma), wv);
         }
     };
     fetch(start);
@@ -234,12 +236,12 @@ __global__ void __launch_bounds__(kBlock) k_p2m(const uint64_t *keys, int64_t n,
                                                 const int32_t *perm, const float *w,
                                                 int level, int Gx, int Gy, int Gz, double lox,
                                                 double loy, double loz, double cell,
-                                                double inv_sigma, float *A) {
+                                                double inv_sigma, float *A, float4 *stage) {
     const int64_t g = blockIdx.x;
     const int kx = (int)(g % Gx), ky = (int)((g / Gx) % Gy), kz = (int)(g / ((int64_t)Gx * Gy));
     int64_t start, end;
     cell_range(keys, n, level, kx, ky, kz, start, end);
-    p2m_cell<P>(ps, perm, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, A, kx, ky, kz, start, end);
+    p2m_cell<P>(ps, perm, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, A, kx, ky, kz, start, end, stage);
 }
 
 // P2M of one grid cell for p = 8 on the matrix cores.  With ay = 2 ay_hi + ay_lo the
@@ -255,7 +257,7 @@ constexpr int kPowStr = 25;   // floats per staged point (24 powers, padded)
 __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int64_t n, const float4 *ps,
                                                       const int32_t *perm, const float *w, int level, int Gx,
                                                       int Gy, int Gz, double lox, double loy, double loz,
-                                                      double cell, double inv_sigma, float *A) {
+                                                      double cell, double inv_sigma, float *A, float4 *stage) {
     __shared__ float pw[kBlock * kPowStr];
     __shared__ float red[kBlock / 64][512];
     const int64_t g = blockIdx.x;
@@ -270,8 +272,10 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
         nxt = make_float4(0.f, 0.f, 0.f, 0.f);   // past the cell: zero weight
         if (j < end) {
             const float4 q = ps[j];
+            const float wv = w[perm[j]];
+            if (stage) stage[j].w = wv;   // the weight in key order, for later calls
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
-                              (float)(((double)q.z - cz) * inv_sigma), w[perm[j]]);
+                              (float)(((double)q.z - cz) * inv_sigma), wv);
         }
     };
     // this lane's operand slots: row m = (ax, ay_lo), column n = (ay_hi within the tile, az)
@@ -1245,12 +1249,12 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
     if (!l2p && P == 8) {
         hipLaunchKernelGGL(k_p2m_mfma8, dim3((unsigned)ncell), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), t->n,
                            t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2],
-                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A);
+                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A, t->ps.as<float4>());
     } else if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
                            ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
-                           t->geo.lo[2], pl.cell, inv_sigma, A);
+                           t->geo.lo[2], pl.cell, inv_sigma, A, t->ps.as<float4>());
     } else {
         // every point's sum straight to input order, flags and self term afterwards
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,

@@ -125,6 +125,7 @@ struct msp_tree {
     // points in key order
     msp::DevBuf keys, perm, iperm, ps;
     bool iperm_valid = false;   // ps: float4 (x, y, z, staged weight) in key order
+    bool w_staged = false;      // ps.w holds the weights of the last weight-taking call
     // node table (SoA, int32)
     msp::DevBuf nlevel, nfirst, ncount, nparent, nfchild, nnchild, ndigit, nix, niy, niz;
     msp::DevBuf d_level_off;  // int64[kMaxLevels] on the device

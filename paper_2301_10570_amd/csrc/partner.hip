@@ -1337,7 +1337,8 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
         if (nq > 0) return fail(MSP_EINVAL, "partner queries on an empty tree");
         return MSP_OK;
     }
-    MSP_TRY(stage_inputs(t, w, nullptr, s));
+    // MSP_WEIGHTS_STAGED: ps.w already holds w (gathered by the last call on the tree)
+    if (!(prm->flags & MSP_WEIGHTS_STAGED)) MSP_TRY(stage_inputs(t, w, nullptr, s));
     switch (prm->p) {
 #define CASE(P) case P: return run_partner<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, s);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)

@@ -608,6 +608,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     t->built = false;
     t->iperm_valid = false;
     t->lists_valid = false;
+    t->w_staged = false;
     t->node_moments_level = -1;
     t->n = n;
     t->leaf_max = leaf_max;

@@ -160,3 +160,38 @@ def test_node_moments_m2m_parity():
         ref = ofgt.p2m(pos[ids], wl.w[ids], c, wl.sigma, p)   # [ax, ay, az]
         got = A[v - slot0].transpose(2, 1, 0)
         assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max(), v
+
+
+def test_staged_weights_reused_after_forward():
+    """MSP_WEIGHTS_STAGED: after a forward on the same tree (whose P2M gathers w into
+    key order, or whose direct route stages it) the partner probabilities reuse the
+    gathered weights and equal those of a call that gathers them itself; without
+    such a forward, or after a backward, the flag is refused."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.slab4m(0.0625)
+    print(f"partner with staged weights, slab {wl.n} points", flush=True)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 400, seed=41)
+    d = to_dev(wl)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(d["x"].device)
+    tqd, nqd = T(tq, np.int32), T(nq, np.int32)
+    u = T(synth.uniforms(len(tq), 42), np.float32)
+    tgt = T((wl.a > 0).astype(np.uint8), np.uint8)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    with pytest.raises(RuntimeError):
+        tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
+    P0, c0 = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u)
+    for route in ("fgt", "direct"):
+        tree.forward(d["w"] * 0.5, tgt, sigma=wl.sigma, route="direct")   # other weights in between
+        tree.forward(d["w"], tgt, sigma=wl.sigma, route=route)
+        P1, c1 = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
+        np.testing.assert_array_equal(P1.cpu().numpy(), P0.cpu().numpy())
+        np.testing.assert_array_equal(c1.cpu().numpy(), c0.cpu().numpy())
+    # a second partner call may reuse the weights of the first
+    P2, _ = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
+    np.testing.assert_array_equal(P2.cpu().numpy(), P0.cpu().numpy())
+    tree.backward(d["w"], torch.ones_like(d["w"]), tgt, sigma=wl.sigma)
+    with pytest.raises(RuntimeError):
+        tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
+    tree.close()
