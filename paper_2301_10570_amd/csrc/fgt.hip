@@ -167,7 +167,8 @@ __device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, 
         if (j < end) {
             const float4 q = ps[j];
             const float wv = w[perm[j]];
-            if (stage) stage[j].w = wv;   // the weight in key order, for later calls
+            // the weight in key order, for later calls (whole records: full-line writes)
+            if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
                               (float)(((double)q.z - cz) * inv_sigma), wv);
         }
@@ -273,7 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
         if (j < end) {
             const float4 q = ps[j];
             const float wv = w[perm[j]];
-            if (stage) stage[j].w = wv;   // the weight in key order, for later calls
+            // the weight in key order, for later calls (whole records: full-line writes)
+            if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
                               (float)(((double)q.z - cz) * inv_sigma), wv);
         }
