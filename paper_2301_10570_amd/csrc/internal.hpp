@@ -149,6 +149,7 @@ struct msp_tree {
     // node moments for partner queries
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
+    msp::HostBuf build_stage;  // page-locked readback of the build: level offsets, box, flags
     msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
     msp::DevBuf partner_order; // walk queries by level of the query node (segments), then tallies
     // partner descent: one step's lists (staged in page-locked memory, then one
@@ -403,6 +404,20 @@ __host__ __device__ inline uint32_t compact3(uint64_t v) {
 
 // q = min(floor((x - lo) * scale), 2^21 - 1) in float64: a subtraction, then a
 // multiplication, each rounded once (no contraction is possible in this form).
+// The root cube from the bounding box (min x, y, z, max x, y, z): lower corner,
+// side (the largest extent, 1 for a single point) and the 21-bit quantisation
+// scale.  Host and device compute it alike, so keys and geometry agree.
+__host__ __device__ inline void root_cube(const float *box, double lo[3], double &side, double &scale) {
+    side = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = (double)box[k];
+        const double ext = (double)box[3 + k] - lo[k];
+        if (ext > side) side = ext;
+    }
+    if (side == 0.0) side = 1.0;
+    scale = 2097152.0 / side;
+}
+
 __device__ inline uint32_t quantise(float v, double lo, double scale) {
     double q = floor(((double)v - lo) * scale);
     return q >= (double)kQMax ? kQMax : (uint32_t)q;

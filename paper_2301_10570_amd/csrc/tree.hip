@@ -17,6 +17,7 @@
 #include "internal.hpp"
 
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace msp {
@@ -103,13 +104,16 @@ __global__ void k_bbox_final(const float *part, int nparts, float *out) {
 
 // ---- keys ----------------------------------------------------------------------------------
 
-__global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, double lx,
-                         double ly, double lz, double scale, uint64_t *key, int32_t *idx,
-                         float4 *pin) {
+// The root cube comes from the bounding box in device memory, so that the build
+// needs no host round trip before the keys.
+__global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, const float *box,
+                         uint64_t *key, int32_t *idx, float4 *pin) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double lo[3], side, scale;
+    root_cube(box, lo, side, scale);
     const float a = x[i], b = y[i], c = z[i];
-    key[i] = morton3(quantise(a, lx, scale), quantise(b, ly, scale), quantise(c, lz, scale));
+    key[i] = morton3(quantise(a, lo[0], scale), quantise(b, lo[1], scale), quantise(c, lo[2], scale));
     idx[i] = (int32_t)i;
     pin[i] = make_float4(a, b, c, 0.f);   // packed so that the sorted gather reads one line per point
 }
@@ -631,28 +635,20 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
             hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, part, parts, out);
             MSP_CHECK_LAUNCH();
         }
-        float host[8];
-        int hbad = 0;
-        MSP_HIP(hipMemcpyAsync(host, out, 6 * sizeof(float), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-        if (hbad) return fail(MSP_EINVAL, "msp_octree_build: non-finite coordinate in input");
-        for (int k = 0; k < 6; ++k) box[k] = host[k];
+        // read back together with the level offsets once the keys are sorted
     }
     Geometry &g = t->geo;
-    double side = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        g.lo[k] = (double)box[k];
-        const double ext = (double)box[3 + k] - g.lo[k];
-        if (ext > side) side = ext;
-    }
-    if (side == 0.0) side = 1.0;
-    g.side = side;
-    g.scale = 2097152.0 / side;
-    for (int k = 0; k < 3; ++k) {
-        const double q = std::floor(((double)box[3 + k] - g.lo[k]) * g.scale);
-        g.qmax[k] = q >= (double)kQMax ? (int32_t)kQMax : (int32_t)q;
-    }
+    // the host geometry from the box (after the readback for n > 0)
+    auto set_geometry = [&]() {
+        double side = 0.0;
+        root_cube(box, g.lo, side, g.scale);
+        g.side = side;
+        for (int k = 0; k < 3; ++k) {
+            const double q = std::floor(((double)box[3 + k] - g.lo[k]) * g.scale);
+            g.qmax[k] = q >= (double)kQMax ? (int32_t)kQMax : (int32_t)q;
+        }
+    };
+    if (n == 0) set_geometry();
 
     // keys and sort
     MSP_TRY(t->keys.ensure(nb * 8));
@@ -680,7 +676,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         {
             PhaseScope ps(&t->timing, PH_KEYS, s);
             hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
-                               g.lo[0], g.lo[1], g.lo[2], g.scale, t->keys.as<uint64_t>(),
+                               t->bbox.as<float>() + kBboxParts * 6, t->keys.as<uint64_t>(),
                                t->perm.as<int32_t>(), t->pin.as<float4>());
             MSP_CHECK_LAUNCH();
         }
@@ -712,21 +708,36 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         MSP_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, ltot, t->d_level_off.as<int64_t>());
         MSP_CHECK_LAUNCH();
-        MSP_HIP(hipMemcpyAsync(t->level_off, t->d_level_off.p, kMaxLevels * 8, hipMemcpyDeviceToHost, s));
+        return MSP_OK;
+    };
+    // one readback per build: level offsets, then the box and the two flags
+    // (non-finite input, sort run overflow), into page-locked memory
+    constexpr size_t kRbBox = kMaxLevels * 8;
+    auto readback = [&]() -> int {
+        MSP_TRY(t->build_stage.ensure(kRbBox + 8 * sizeof(float) + 2 * sizeof(int)));
+        char *h = static_cast<char *>(t->build_stage.p);
+        MSP_HIP(hipMemcpyAsync(h, t->d_level_off.p, kMaxLevels * 8, hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipMemcpyAsync(h + kRbBox, t->bbox.as<float>() + kBboxParts * 6, 8 * sizeof(float) + 2 * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+        std::memcpy(t->level_off, h, kMaxLevels * 8);
         return MSP_OK;
     };
     if (n > 0) {
         MSP_TRY(keys_and_sort(false));
         MSP_TRY(levels());
-        int over = 0;
-        const int *overflow = bbox_flags(t) + 1;
-        MSP_HIP(hipMemcpyAsync(&over, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-        if (over) {
+        MSP_TRY(readback());
+        const char *h = static_cast<const char *>(t->build_stage.p);
+        int flags[2];
+        std::memcpy(box, h + kRbBox, 6 * sizeof(float));
+        std::memcpy(flags, h + kRbBox + 8 * sizeof(float), sizeof(flags));
+        if (flags[0]) return fail(MSP_EINVAL, "msp_octree_build: non-finite coordinate in input");
+        set_geometry();
+        if (flags[1]) {
             // a run of equal 24-bit prefix was too long for the run sort: sort all bits
             MSP_TRY(keys_and_sort(true));
             MSP_TRY(levels());
-            MSP_HIP(hipStreamSynchronize(s));
+            MSP_TRY(readback());
         }
     } else {
         // empty input: a single empty root leaf
