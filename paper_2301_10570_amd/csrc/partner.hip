@@ -762,46 +762,80 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
         const double gz = fmax(fabs(tz - (loz + (niz[u] + 0.5) * h)) - half, 0.0);
         return gx * gx + gy * gy + gz * gz;
     };
-    double Sl = 0.0;
-    int dg = -1;
+    int dg = -1, in = 0;
+    int32_t uend = 0;
     if (child >= 0) {
         const int sh = nlevel[child] - nlevel[X] - 1;
         dg = (((nix[child] >> sh) & 1) << 2) | (((niy[child] >> sh) & 1) << 1) | ((niz[child] >> sh) & 1);
-        bool in = true;
+        in = 1;
         if (!unlimited) {
             const double reach = sqrt(box_d2(X)) + sqrt((double)cutoff2);
             in = box_d2(child) <= reach * reach;
         }
-        if (in) {
-            const int32_t uf = nfirst[child], un = ncount[child];
-            for (int32_t j = uf; j < uf + un; ++j) {
-                const float4 qj = ps[j];
-                if (qj.w == 0.f || (exclude_self && j == si)) continue;
-                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                Sl += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+        uend = nfirst[child] + ncount[child];
+    }
+    // the group's children by lane: point range end, cutoff flag, octant, node id
+    // (their point ranges are consecutive in key order and cover the node's)
+    int32_t ce[8], cd[8], cn[8];
+    int ci[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ce[k] = __shfl(uend, gbase + k, 64);
+        ci[k] = __shfl(in, gbase + k, 64);
+        cd[k] = __shfl(dg, gbase + k, 64);
+        cn[k] = __shfl(child, gbase + k, 64);
+    }
+    auto pick = [](const int32_t(&a)[8], int k) {
+        int32_t v = a[0];
+#pragma unroll
+        for (int kk = 1; kk < 8; ++kk) v = k == kk ? a[kk] : v;
+        return v;
+    };
+    // the group's eight lanes sum the node's points together, lane c taking every
+    // eighth one (consecutive lanes read consecutive records); per octant partials
+    double Sd[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
+    {
+        const int32_t lo = __shfl(child >= 0 ? nfirst[child] : 0, gbase, 64);   // child 0
+        const int32_t hi = pick(ce, nc - 1);
+        int cur = 0;
+        int32_t cur_end = ce[0];
+        int cur_in = ci[0], cur_dg = cd[0];
+        for (int32_t j = lo + c; j < hi; j += 8) {
+            while (j >= cur_end && cur + 1 < nc) {
+                ++cur;
+                cur_end = pick(ce, cur);
+                cur_in = pick(ci, cur);
+                cur_dg = pick(cd, cur);
             }
+            if (!cur_in) continue;
+            const float4 qj = ps[j];
+            if (qj.w == 0.f || (exclude_self && j == si)) continue;
+            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+            const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+                if (d == cur_dg) Sd[d] += e;
         }
     }
-    // sums and child ids by octant, gathered from the group's lanes
+    // sums over the group's lanes, and child ids by octant
     double S[8];
     int32_t cid[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        S[d] = 0.0;
+        double v = Sd[d];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        S[d] = v;
         cid[d] = -1;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double sk = __shfl(Sl, gbase + k, 64);
-        const int dk = __shfl(dg, gbase + k, 64);
-        const int32_t ck = __shfl(child, gbase + k, 64);
+    for (int k = 0; k < 8; ++k)
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            if (d == dk) {
-                S[d] = sk;
-                cid[d] = ck;
-            }
-    }
+            if (d == cd[k] && cn[k] >= 0) cid[d] = cn[k];
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < 8; ++d) total += S[d];
