@@ -300,16 +300,37 @@ __global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, in
                                                         int max_depth, uint8_t *dlev, uint8_t *llev,
                                                         uint32_t *blkcnt, int nblk) {
     __shared__ int8_t Ls[kTile + kWinMax];
+    // window maxima by prefix and suffix maxima over blocks of W = leaf_max + 1
+    // values (van Herk / Gil-Werman): the window [a, a + W - 1] is max(suf[a], pre[a + W - 1])
+    __shared__ int8_t pre[kTile + kWinMax], suf[kTile + kWinMax];
     __shared__ uint32_t wc[kBlock / 64][kDepth + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kTile;
     const int64_t m = n - leaf_max;
-    for (int idx = tid; idx < kTile + leaf_max; idx += kBlock) {
+    const int NL = kTile + leaf_max, W = leaf_max + 1, NB = (NL + W - 1) / W;
+    for (int idx = tid; idx < NL; idx += kBlock) {
         const int64_t j = tile - leaf_max + idx;
         Ls[idx] = (j >= 0 && j < m) ? (int8_t)common_level(keys[j], keys[j + leaf_max]) : (int8_t)-1;
     }
     if (tid <= kDepth)
         for (int w = 0; w < kBlock / 64; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    for (int b = tid; b < 2 * NB; b += kBlock) {
+        const int blk = b < NB ? b : b - NB;
+        const int p0 = blk * W, p1 = p0 + W < NL ? p0 + W : NL;
+        int mx = -1;
+        if (b < NB) {
+            for (int p = p0; p < p1; ++p) {
+                mx = Ls[p] > mx ? Ls[p] : mx;
+                pre[p] = (int8_t)mx;
+            }
+        } else {
+            for (int p = p1 - 1; p >= p0; --p) {
+                mx = Ls[p] > mx ? Ls[p] : mx;
+                suf[p] = (int8_t)mx;
+            }
+        }
+    }
     __syncthreads();
     uint32_t mycnt[kDepth + 1];
 #pragma unroll
@@ -324,11 +345,8 @@ __global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, in
                 const uint64_t x = keys[i] ^ keys[i - 1];
                 d = (x == 0) ? kDepth + 1 : kDepth - (63 - __clzll((long long)x)) / 3;
             }
-            int lam = -1;
-            for (int k = 0; k <= leaf_max; ++k) {
-                const int v = Ls[off + k];
-                lam = v > lam ? v : lam;
-            }
+            const int s0 = suf[off], p1 = pre[off + leaf_max];
+            const int lam = s0 > p1 ? s0 : p1;   // max of Ls[off .. off + leaf_max]
             ll = lam + 1 < max_depth ? lam + 1 : max_depth;
             dlev[i] = (uint8_t)d;
             llev[i] = (uint8_t)ll;
