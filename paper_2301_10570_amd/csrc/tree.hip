@@ -372,27 +372,38 @@ __global__ void __launch_bounds__(kBlock) k_emit_tile(const uint8_t *dlev, const
                                                       int64_t n, const uint32_t *blkoff, int nblk,
                                                       const int64_t *level_off, int32_t *nfirst,
                                                       int32_t *nlevel) {
-    __shared__ uint32_t wc[kBlock / 64][kDepth + 1];
+    // per-wave counts, double-buffered by item: the running totals of item r read
+    // them after the second barrier while waves may already count item r + 1
+    __shared__ uint32_t wcb[2][kBlock / 64][kDepth + 1];
     __shared__ uint32_t run[kDepth + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     if (tid <= kDepth) run[tid] = 0;
     for (int r = 0; r < kItems; ++r) {
+        uint32_t(*wc)[kDepth + 1] = wcb[r & 1];
         const int64_t i = tile + r * kBlock + tid;
         const int d = i < n ? dlev[i] : 255;
         const int ll = i < n ? llev[i] : 0;
-        uint64_t masks[kDepth + 1];
-#pragma unroll
-        for (int l = 0; l <= kDepth; ++l) {
-            masks[l] = __ballot(d <= l && l <= ll);
-            if (lane == 0) wc[wid][l] = __popcll(masks[l]);
+        // the levels at which some point of this wave starts a node (most points start
+        // none: they continue their predecessor's cell below their leaf level)
+        int lo = d <= ll ? d : kDepth + 1, hi = d <= ll ? ll : -1;
+        for (int o = 32; o > 0; o >>= 1) {
+            const int lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+            lo = lo2 < lo ? lo2 : lo;
+            hi = hi2 > hi ? hi2 : hi;
+        }
+        if (lane <= kDepth) wc[wid][lane] = 0;
+        wave_sync();
+        for (int l = lo; l <= hi; ++l) {
+            const uint64_t mk = __ballot(d <= l && l <= ll);
+            if (lane == 0) wc[wid][l] = __popcll(mk);
         }
         __syncthreads();
-#pragma unroll
-        for (int l = 0; l <= kDepth; ++l) {
+        for (int l = lo; l <= hi; ++l) {
+            const uint64_t mk = __ballot(d <= l && l <= ll);
             if (d <= l && l <= ll) {
-                uint32_t off = run[l] + __popcll(masks[l] & lt);
+                uint32_t off = run[l] + __popcll(mk & lt);
                 for (int w = 0; w < wid; ++w) off += wc[w][l];
                 const int64_t pos = level_off[l] + blkoff[(int64_t)l * nblk + blockIdx.x] + off;
                 nfirst[pos] = (int32_t)i;
