@@ -267,7 +267,7 @@ def main():
 
     def step():
         tree.build(x, y, z, leaf_max=wl.leaf_max)
-        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u, stage_weights=True)
         if tq.numel():
             # the same counts as the forward: its P2M already gathered w into key order
             tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)

@@ -77,14 +77,19 @@ enum msp_flags {
      * (about 2^-16 of each product is lost).  Exclusive with MSP_M2L_VALU. */
     MSP_M2L_BF16X3 = 1u << 3,
     /* For msp_partner_probabilities: `w` is the weight array of the last
-     * msp_fgt_forward, msp_partner_probabilities or msp_partner_descent call on
-     * this tree, unchanged since (an MSP step evaluates the sums and then the
-     * partner probabilities with the same vacant element counts).  The weights
-     * that call gathered into key order are used again instead of being gathered
-     * a second time.  MSP_ESTATE if no such call has gathered weights since the
-     * tree was built or since a backward call (which gathers other weights);
-     * the contents of `w` are not checked. */
-    MSP_WEIGHTS_STAGED = 1u << 4
+     * msp_fgt_forward (on the direct route, or with MSP_STAGE_WEIGHTS),
+     * msp_partner_probabilities or msp_partner_descent call on this tree,
+     * unchanged since (an MSP step evaluates the sums and then the partner
+     * probabilities with the same vacant element counts).  The weights that call
+     * gathered into key order are used again instead of being gathered a second
+     * time.  MSP_ESTATE if no such call has gathered weights since the tree was
+     * built or since a backward call (which gathers other weights), or if the
+     * last forward did not keep them; the contents of `w` are not checked. */
+    MSP_WEIGHTS_STAGED = 1u << 4,
+    /* For msp_fgt_forward on the expansion route: keep the weights its P2M
+     * gathers into key order for a following MSP_WEIGHTS_STAGED call (the extra
+     * writes cost a little; a forward on its own does without). */
+    MSP_STAGE_WEIGHTS = 1u << 5
 };
 
 typedef struct msp_tree msp_tree; /* opaque handle */

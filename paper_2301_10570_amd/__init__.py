@@ -31,6 +31,7 @@ M2L_VALU = 2
 TWO_LEVEL = 4
 M2L_BF16X3 = 8
 WEIGHTS_STAGED = 16
+STAGE_WEIGHTS = 32
 
 
 class MspError(RuntimeError):
@@ -215,8 +216,10 @@ class Tree:
                 "fine_terms": inf.fine_terms}
 
     def forward(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
-                exclude_self=False, out=None, m2l="mfma", two_level=False):
-        """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere."""
+                exclude_self=False, out=None, m2l="mfma", two_level=False, stage_weights=False):
+        """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere.
+        stage_weights: keep the weights gathered into key order for a following
+        partner_probabilities(..., weights_staged=True) (MSP_STAGE_WEIGHTS)."""
         n = self.n
         pw = _ptr(w, torch.float32, n, "w")
         pt = _ptr(is_target, torch.uint8, n, "is_target")
@@ -224,6 +227,8 @@ class Tree:
             out = torch.empty(n, dtype=torch.float32, device=w.device)
         po = _ptr(out, torch.float32, n, "out")
         prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
+        if stage_weights:
+            prm.flags |= STAGE_WEIGHTS
         _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
         return out
 

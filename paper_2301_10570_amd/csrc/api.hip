@@ -118,7 +118,7 @@ static int check_params(const msp_fgt_params *prm) {
     if (prm->level < -1 || prm->level > kDepth) return fail(MSP_EINVAL, "level = %d outside -1..21", prm->level);
     if (prm->route < MSP_ROUTE_AUTO || prm->route > MSP_ROUTE_DIRECT) return fail(MSP_EINVAL, "bad route %d", prm->route);
     if (prm->flags & ~(uint32_t)(MSP_EXCLUDE_SELF | MSP_M2L_VALU | MSP_TWO_LEVEL | MSP_M2L_BF16X3 |
-                                 MSP_WEIGHTS_STAGED))
+                                 MSP_WEIGHTS_STAGED | MSP_STAGE_WEIGHTS))
         return fail(MSP_EINVAL, "unknown flags 0x%x", prm->flags);
     if ((prm->flags & MSP_M2L_VALU) && (prm->flags & MSP_M2L_BF16X3))
         return fail(MSP_EINVAL, "MSP_M2L_VALU and MSP_M2L_BF16X3 exclude each other");
@@ -243,7 +243,8 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     t->w_staged = false;   // set again by the paths that gather w into ps.w
     if (pl.route == MSP_ROUTE_FGT) {
         const int rc = fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
-        t->w_staged = rc == MSP_OK && pl.pf == 0;   // the single-level P2M gathers w into ps.w
+        // the single-level P2M gathers w into ps.w when asked to keep it
+        t->w_staged = rc == MSP_OK && pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS);
         return rc;
     }
     MSP_TRY(stage_inputs(t, w, is_target, s));

@@ -1204,6 +1204,7 @@ struct GridArgs {
     const uint8_t *is_target;
     int subtract_self;
     float *u_out;
+    bool stage;   // P2M writes the gathered weights into the sorted records (MSP_STAGE_WEIGHTS)
 };
 
 // Target flags and the self term applied in input order after an L2P that wrote
@@ -1251,12 +1252,13 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
     if (!l2p && P == 8) {
         hipLaunchKernelGGL(k_p2m_mfma8, dim3((unsigned)ncell), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), t->n,
                            t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2],
-                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A, t->ps.as<float4>());
+                           t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A,
+                           ga.stage ? t->ps.as<float4>() : nullptr);
     } else if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
                            ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
-                           t->geo.lo[2], pl.cell, inv_sigma, A, t->ps.as<float4>());
+                           t->geo.lo[2], pl.cell, inv_sigma, A, ga.stage ? t->ps.as<float4>() : nullptr);
     } else {
         // every point's sum straight to input order, flags and self term afterwards
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_l2p<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
@@ -2256,7 +2258,8 @@ int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStrea
 
 int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
                      const uint8_t *is_target, float *u_out, hipStream_t s) {
-    const GridArgs ga{w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out};
+    const GridArgs ga{w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out,
+                      (prm->flags & MSP_STAGE_WEIGHTS) != 0};
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     const size_t gbytes = (size_t)ncell * p * p * p * 4;

@@ -182,9 +182,13 @@ def test_staged_weights_reused_after_forward():
     with pytest.raises(RuntimeError):
         tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
     P0, c0 = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u)
+    # a forward on the expansion route keeps its gathered weights only when asked to
+    tree.forward(d["w"], tgt, sigma=wl.sigma, route="fgt")
+    with pytest.raises(RuntimeError):
+        tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
     for route in ("fgt", "direct"):
         tree.forward(d["w"] * 0.5, tgt, sigma=wl.sigma, route="direct")   # other weights in between
-        tree.forward(d["w"], tgt, sigma=wl.sigma, route=route)
+        tree.forward(d["w"], tgt, sigma=wl.sigma, route=route, stage_weights=True)
         P1, c1 = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
         np.testing.assert_array_equal(P1.cpu().numpy(), P0.cpu().numpy())
         np.testing.assert_array_equal(c1.cpu().numpy(), c0.cpu().numpy())
