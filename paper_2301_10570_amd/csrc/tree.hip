@@ -156,48 +156,48 @@ __global__ void k_rs_digit_scan(uint32_t *hist, int nblk, uint32_t *total) {
 
 // Stable scatter of one 8-bit digit.  The tile is first ordered by digit in LDS
 // (stable: ranks follow item order), then written out so that consecutive
-// threads store consecutive positions of each digit's output run.
+// threads store consecutive positions of each digit's output run.  Each
+// wavefront ranks a contiguous quarter of the tile on its own, with a digit
+// counter of its own in LDS (lanes of one digit found by eight ballots, the
+// last of them advancing the counter), so the ranking needs no block barrier;
+// one scan over (digit, wavefront) then places the quarters in item order.
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t *kin, const int32_t *vin,
                                                        uint64_t *kout, int32_t *vout, int64_t n,
                                                        int shift, const uint32_t *hist,
                                                        const uint32_t *total, int nblk,
                                                        const float4 *pin, float4 *ps) {
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kPerWave = kTile / kWaves;   // items of one wavefront, contiguous
     __shared__ uint64_t sk[kTile];
     __shared__ int32_t sv[kTile];
-    __shared__ uint32_t lds[kBlock / 64];
+    __shared__ uint32_t lds[kWaves];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t toff[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t wcnt[kWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kTile;
     const int cnt = n - tile < kTile ? (int)(n - tile) : kTile;
     uint32_t tot;
     const uint32_t dbase = block_exclusive_scan(total[tid], lds, tot);
     gbase[tid] = dbase + hist[(int64_t)tid * nblk + blockIdx.x];
-    run[tid] = 0;
-    toff[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     uint64_t k[kItems];
     int32_t v[kItems];
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int idx = j * kBlock + tid;
-        k[j] = idx < cnt ? kin[tile + idx] : 0ull;
-        v[j] = idx < cnt ? vin[tile + idx] : 0;
-        if (idx < cnt) atomicAdd(&toff[(uint32_t)(k[j] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    const uint32_t c = toff[tid];
-    __syncthreads();
-    toff[tid] = block_exclusive_scan(c, lds, tot);
+    uint32_t r[kItems];   // rank among the wavefront's items of the same digit
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
+        const int idx = wid * kPerWave + j * 64 + lane;
+        const bool valid = idx < cnt;
+        k[j] = valid ? kin[tile + idx] : 0ull;
+        v[j] = valid ? vin[tile + idx] : 0;
+    }
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        const bool valid = j * kBlock + tid < cnt;
+    for (int j = 0; j < kItems; ++j) {
+        const int idx = wid * kPerWave + j * 64 + lane;
+        const bool valid = idx < cnt;
         const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -206,19 +206,34 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t *kin, cons
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t off = toff[d] + run[d] + __popcll(peers & lt);
-            for (int w = 0; w < wid; ++w) off += wcnt[w][d];
+        // every lane reads the counter before the digit's last lane writes it (one
+        // wavefront's LDS accesses take effect in program order)
+        const uint32_t before = wcnt[wid][d];
+        r[j] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers >> lane) == 1ull) wcnt[wid][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += wcnt[w][tid];
+    const uint32_t ex = block_exclusive_scan(c, lds, tot);
+    toff[tid] = ex;
+    uint32_t o = ex;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = wcnt[w][tid];
+        wcnt[w][tid] = o;   // now: where wavefront w's items of digit tid start in the tile
+        o += t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (wid * kPerWave + j * 64 + lane < cnt) {
+            const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+            const uint32_t off = wcnt[wid][d] + r[j];
             sk[off] = k[j];
             sv[off] = v[j];
         }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
-        run[tid] += add;
     }
     __syncthreads();
 #pragma unroll
