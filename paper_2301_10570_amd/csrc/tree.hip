@@ -540,37 +540,67 @@ __global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *lev
 // Final ordering inside runs of equal 24-bit key prefix (level-8 cells).  The
 // input is stably sorted by the prefix, so within a run the points are in index
 // order; each point's place in the run is the number of run members with a
-// smaller (key, index), which reproduces the stable sort by the full key.  Runs
-// longer than kSegMax raise *overflow (the caller then sorts all 63 bits).
+// smaller (key, index), which reproduces the stable sort by the full key.  A run
+// that lies inside one wavefront's 64 entries is ranked from LDS; a run that
+// crosses a wavefront boundary is found by scanning the neighbours in memory.
+// Runs longer than kSegMax raise *overflow (the caller then sorts all 63 bits).
 constexpr int kSegShift = 39;
 constexpr int kSegMax = 256;
-__global__ void k_seg_sort(const uint64_t *kin, const int32_t *vin, int64_t n, uint64_t *kout,
-                           int32_t *vout, const float4 *pin, float4 *ps, int *overflow) {
+__global__ void __launch_bounds__(kBlock) k_seg_sort(const uint64_t *kin, const int32_t *vin, int64_t n,
+                                                     uint64_t *kout, int32_t *vout, const float4 *pin,
+                                                     float4 *ps, int *overflow) {
+    __shared__ uint64_t sk[kBlock];
+    __shared__ int32_t sv[kBlock];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t key = kin[i];
-    const int32_t val = vin[i];
+    const int lane = threadIdx.x & 63, w0 = threadIdx.x - lane;
+    const bool live = i < n;
+    const uint64_t key = live ? kin[i] : ~0ull;
+    const int32_t val = live ? vin[i] : 0;
     const uint64_t pre = key >> kSegShift;
-    int64_t st = i, en = i + 1;
-    int steps = 0;
-    while (st > 0 && (kin[st - 1] >> kSegShift) == pre) {
-        --st;
-        if (++steps > kSegMax) {
-            atomicOr(overflow, 1);
-            return;
+    sk[threadIdx.x] = key;
+    sv[threadIdx.x] = val;
+    // run boundaries inside the wavefront (entries past n form runs of their own)
+    const uint64_t pre_up = __shfl_up(pre, 1, 64), pre_dn = __shfl_down(pre, 1, 64);
+    const bool starts = lane == 0 || pre_up != pre;
+    const bool ends = lane == 63 || pre_dn != pre;
+    const uint64_t smask = __ballot(starts), emask = __ballot(ends);
+    __syncthreads();
+    if (!live) return;
+    const int s = 63 - __clzll((long long)(smask & ((lane == 63) ? ~0ull : ((2ull << lane) - 1))));
+    const int e = __builtin_ctzll(emask & (~0ull << lane));
+    // does the run continue into the previous or the next wavefront?
+    const int64_t gs = i - lane + s, ge = i - lane + e;   // first and last entry inside this wavefront
+    const bool open_lo = s == 0 && gs > 0 && (kin[gs - 1] >> kSegShift) == pre;
+    const bool open_hi = e == 63 && ge + 1 < n && (kin[ge + 1] >> kSegShift) == pre;
+    int64_t o;
+    if (!open_lo && !open_hi) {
+        o = gs;
+        for (int j = s; j <= e; ++j) {
+            const uint64_t kj = sk[w0 + j];
+            o += (kj < key) || (kj == key && sv[w0 + j] < val);
         }
-    }
-    while (en < n && (kin[en] >> kSegShift) == pre) {
-        ++en;
-        if (++steps > kSegMax) {
-            atomicOr(overflow, 1);
-            return;
+    } else {
+        int64_t st = i, en = i + 1;
+        int steps = 0;
+        while (st > 0 && (kin[st - 1] >> kSegShift) == pre) {
+            --st;
+            if (++steps > kSegMax) {
+                atomicOr(overflow, 1);
+                return;
+            }
         }
-    }
-    int64_t o = st;
-    for (int64_t j = st; j < en; ++j) {
-        const uint64_t kj = kin[j];
-        o += (kj < key) || (kj == key && vin[j] < val);
+        while (en < n && (kin[en] >> kSegShift) == pre) {
+            ++en;
+            if (++steps > kSegMax) {
+                atomicOr(overflow, 1);
+                return;
+            }
+        }
+        o = st;
+        for (int64_t j = st; j < en; ++j) {
+            const uint64_t kj = kin[j];
+            o += (kj < key) || (kj == key && vin[j] < val);
+        }
     }
     kout[o] = key;
     vout[o] = val;

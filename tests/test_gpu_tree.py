@@ -82,6 +82,12 @@ def test_tree_edge_cases():
     wl = synth.uniform_box(65, seed=5)
     _compare(wl.x[:64], wl.y[:64], wl.z[:64], 64)
     _compare(wl.x, wl.y, wl.z, 64)
+    print("tree edge: runs of ~100 points in one level-8 cell, across wavefront boundaries", flush=True)
+    rng = np.random.default_rng(21)
+    ctr = rng.random((40, 3)) * 1000.0
+    pts = (np.repeat(ctr, 100, axis=0) + rng.random((4000, 3)) * 0.5).astype(np.float32)
+    pts = pts[rng.permutation(4000)]
+    _compare(pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), 16)
     print("tree edge: ragged sizes around the 4096-point tile", flush=True)
     for n in (4095, 4096, 4097, 12289):
         wl = synth.uniform_box(n, seed=n)
