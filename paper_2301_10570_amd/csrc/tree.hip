@@ -164,11 +164,16 @@ __global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
-#pragma unroll 4
+    // every load of the thread in flight before the counting
+    uint64_t k[kItems];
+#pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        int64_t i = base + r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        k[r] = i < n ? keys[i] : 0ull;
     }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if (base + r * kBlock + threadIdx.x < n) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
