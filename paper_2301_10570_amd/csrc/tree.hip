@@ -531,51 +531,57 @@ __global__ void k_level_offsets(const uint32_t *total, int64_t *level_off) {
     level_off[kDepth + 1] = run;
 }
 
-__global__ void k_nodes(const uint64_t *keys, int64_t n, const uint8_t *llev, int64_t n_nodes,
-                        const int32_t *nlevel, const int32_t *nfirst, int32_t *ncount,
-                        int32_t *ndigit, int32_t *nix, int32_t *niy, int32_t *niz) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Parent of every node: the last node one level up whose first point is at or
+// before the node's own (binary search in the level's sorted firsts).
+__global__ void k_parents(int64_t n_nodes, const int64_t *level_off, const int32_t *nlevel,
+                          const int32_t *nfirst, int32_t *nparent) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n_nodes) return;
     const int l = nlevel[v];
-    const int64_t i = nfirst[v];
+    nparent[v] = l == 0 ? -1
+                        : (int32_t)(upper_bound_i32(nfirst, level_off[l - 1], level_off[l], nfirst[v]) - 1);
+}
+
+// Count, cell coordinates and children of every node.  The nodes of a level are
+// in key order and the children of one node are consecutive among them, so a
+// node ends where its next sibling starts; the last child of a node ends where
+// its parent ends, which the chain of last children up to the first ancestor
+// with a next sibling (or to the root, which ends at n) gives.  The children of
+// an inner node are the nodes one level down from its first point to its end.
+__global__ void k_nodes(const uint64_t *keys, int64_t n, const uint8_t *llev, int64_t n_nodes,
+                        const int64_t *level_off, const int32_t *nlevel, const int32_t *nfirst,
+                        const int32_t *nparent, int32_t *ncount, int32_t *ndigit, int32_t *nix, int32_t *niy,
+                        int32_t *niz, int32_t *nfchild, int32_t *nnchild) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n_nodes) return;
+    const int l = nlevel[v];
+    const int32_t f = nfirst[v];
     int64_t end = n;
-    uint64_t prefix = 0;
-    if (n > 0) {
-        const int sh = 3 * (kDepth - l);
-        prefix = l == 0 ? 0ull : (keys[i] >> sh);
-        const uint64_t next = (prefix + 1ull) << sh;
-        // gallop from i: most nodes are small, so the bracket stays near i
-        int64_t lo = i + 1, step = 1, hi = i + 1;
-        while (hi < n && keys[hi] < next) {
-            lo = hi + 1;
-            hi = i + 1 + step;
-            step <<= 1;
+    int64_t w = v;
+    for (int guard = 0; guard <= kDepth + 1 && w > 0; ++guard) {
+        const int64_t nx = w + 1;
+        const int32_t pw = nparent[w];
+        if (nx < level_off[nlevel[w] + 1] && nparent[nx] == pw) {
+            end = nfirst[nx];
+            break;
         }
-        end = lower_bound_u64(keys, lo, hi < n ? hi : n, next);
+        w = pw;
     }
-    ncount[v] = (int32_t)(end - i);
+    ncount[v] = (int32_t)(end - f);
+    uint64_t prefix = 0;
+    if (n > 0 && l > 0) prefix = keys[f] >> (3 * (kDepth - l));
     ndigit[v] = l > 0 ? (int32_t)(prefix & 7ull) : 0;
     nix[v] = (int32_t)compact3(prefix >> 2);
     niy[v] = (int32_t)compact3(prefix >> 1);
     niz[v] = (int32_t)compact3(prefix);
-}
-
-__global__ void k_links(const uint8_t *llev, int64_t n_nodes, const int64_t *level_off,
-                        const int32_t *nlevel, const int32_t *nfirst, const int32_t *ncount,
-                        int32_t *nparent, int32_t *nfchild, int32_t *nnchild, int n_points) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= n_nodes) return;
-    const int l = nlevel[v];
-    const int32_t f = nfirst[v];
-    nparent[v] = l == 0 ? -1
-                        : (int32_t)(upper_bound_i32(nfirst, level_off[l - 1], level_off[l], f) - 1);
-    const bool leaf = n_points == 0 || (int)llev[f] == l;
+    const bool leaf = n == 0 || (int)llev[f] == l;
     if (leaf) {
         nfchild[v] = -1;
         nnchild[v] = 0;
     } else {
         const int64_t a = lower_bound_i32(nfirst, level_off[l + 1], level_off[l + 2], f);
-        const int64_t b = lower_bound_i32(nfirst, level_off[l + 1], level_off[l + 2], f + ncount[v]);
+        int64_t b = a;
+        while (b < level_off[l + 2] && nfirst[b] < end && b - a < 8) ++b;
         nfchild[v] = (int32_t)a;
         nnchild[v] = (int32_t)(b - a);
     }
@@ -886,15 +892,15 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         MSP_HIP(hipMemcpyAsync(t->nlevel.p, &zero, 4, hipMemcpyHostToDevice, s));
         MSP_HIP(hipStreamSynchronize(s));
     }
-    hipLaunchKernelGGL(k_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, t->keys.as<uint64_t>(),
-                       n, t->llev.as<uint8_t>(), nn, t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
-                       t->ncount.as<int32_t>(), t->ndigit.as<int32_t>(), t->nix.as<int32_t>(),
-                       t->niy.as<int32_t>(), t->niz.as<int32_t>());
+    hipLaunchKernelGGL(k_parents, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn,
+                       t->d_level_off.as<int64_t>(), t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
+                       t->nparent.as<int32_t>());
     MSP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_links, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, t->llev.as<uint8_t>(),
-                       nn, t->d_level_off.as<int64_t>(), t->nlevel.as<int32_t>(),
-                       t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nparent.as<int32_t>(),
-                       t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), (int)n);
+    hipLaunchKernelGGL(k_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, t->keys.as<uint64_t>(),
+                       n, t->llev.as<uint8_t>(), nn, t->d_level_off.as<int64_t>(), t->nlevel.as<int32_t>(),
+                       t->nfirst.as<int32_t>(), t->nparent.as<int32_t>(), t->ncount.as<int32_t>(),
+                       t->ndigit.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                       t->niz.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>());
     MSP_CHECK_LAUNCH();
     }
 
