@@ -150,7 +150,13 @@ def test_node_moments_m2m_parity():
     A = tree.debug_buffer(2).cpu().numpy()
     nodes = np.nonzero(has)[0]
     assert nodes.size > 50
-    slot0 = tr.level_offset[tree.plan(wl.sigma, p=p)["level"]]
+    lh = tree.plan(wl.sigma, p=p)["level"]
+    # exactly the nodes at or below the moment level with more than 70 sources
+    # (points of nonzero weight) carry moments
+    S = np.concatenate([[0], np.cumsum(wl.w[tr.perm] != 0)])
+    nsrc = S[tr.first + tr.count] - S[tr.first]
+    np.testing.assert_array_equal(has != 0, (tr.level >= lh) & (nsrc > 70))
+    slot0 = tr.level_offset[lh]
     A = A.reshape(-1, p, p, p)   # [slot][az][ay][ax]
     pos = wl.pos64()
     rng = np.random.default_rng(1)
