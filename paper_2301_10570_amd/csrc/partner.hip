@@ -802,21 +802,33 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
         int cur = 0;
         int32_t cur_end = ce[0];
         int cur_in = ci[0], cur_dg = cd[0];
-        for (int32_t j = lo + c; j < hi; j += 8) {
-            while (j >= cur_end && cur + 1 < nc) {
-                ++cur;
-                cur_end = pick(ce, cur);
-                cur_in = pick(ci, cur);
-                cur_dg = pick(cd, cur);
-            }
-            if (!cur_in) continue;
-            const float4 qj = ps[j];
-            if (qj.w == 0.f || (exclude_self && j == si)) continue;
-            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-            const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+        // four records of the lane in flight at a time, used in order
+        for (int32_t j0 = lo + c; j0 < hi; j0 += 32) {
+            float4 qv[4];
 #pragma unroll
-            for (int d = 0; d < 8; ++d)
-                if (d == cur_dg) Sd[d] += e;
+            for (int u = 0; u < 4; ++u) {
+                const int32_t j = j0 + 8 * u;
+                qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t j = j0 + 8 * u;
+                if (j >= hi) continue;
+                while (j >= cur_end && cur + 1 < nc) {
+                    ++cur;
+                    cur_end = pick(ce, cur);
+                    cur_in = pick(ci, cur);
+                    cur_dg = pick(cd, cur);
+                }
+                if (!cur_in) continue;
+                const float4 qj = qv[u];
+                if (qj.w == 0.f || (exclude_self && j == si)) continue;
+                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+#pragma unroll
+                for (int d = 0; d < 8; ++d)
+                    if (d == cur_dg) Sd[d] += e;
+            }
         }
     }
     // sums over the group's lanes, and child ids by octant
