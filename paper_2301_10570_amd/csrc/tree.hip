@@ -144,17 +144,32 @@ __global__ void k_bbox_final(const float *part, int nparts, float *out) {
 // ---- keys ----------------------------------------------------------------------------------
 
 // The root cube comes from the bounding box in device memory, so that the build
-// needs no host round trip before the keys.
-__global__ void k_morton(const float *x, const float *y, const float *z, int64_t n, const float *box,
-                         uint64_t *key, int32_t *idx, float4 *pin) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// needs no host round trip before the keys.  One block per tile of the sort
+// (kTile points, point r * kBlock + t of the tile to thread t), which also counts
+// the tile's digits for the sort's first pass (bits shift .. shift + 7), in the
+// layout k_rs_hist writes.
+__global__ void __launch_bounds__(kBlock) k_morton(const float *x, const float *y, const float *z, int64_t n,
+                                                   const float *box, uint64_t *key, int32_t *idx, float4 *pin,
+                                                   int shift, uint32_t *hist, int nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
     double lo[3], side, scale;
     root_cube(box, lo, side, scale);
-    const float a = x[i], b = y[i], c = z[i];
-    key[i] = morton3(quantise(a, lo[0], scale), quantise(b, lo[1], scale), quantise(c, lo[2], scale));
-    idx[i] = (int32_t)i;
-    pin[i] = make_float4(a, b, c, 0.f);   // packed so that the sorted gather reads one line per point
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        const float a = x[i], b = y[i], c = z[i];
+        const uint64_t k = morton3(quantise(a, lo[0], scale), quantise(b, lo[1], scale), quantise(c, lo[2], scale));
+        key[i] = k;
+        idx[i] = (int32_t)i;
+        pin[i] = make_float4(a, b, c, 0.f);   // packed so that the sorted gather reads one line per point
+        atomicAdd(&h[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 // ---- stable LSD radix sort of (key, index), 8 bits per pass ----------------------------------
@@ -690,6 +705,7 @@ inline int *bbox_flags(msp_tree *t) {
 // fast: three 8-bit LSD passes over the top 24 key bits (the level-8 cell), then
 // k_seg_sort inside the runs of equal prefix; it leaves a flag in the bbox
 // scratch when a run is too long.  Otherwise: eight LSD passes over all bits.
+// The digits of the first pass were counted by k_morton.
 int sort_keys(msp_tree *t, int64_t n, int nblk, bool full, hipStream_t s) {
     PhaseScope ps(&t->timing, PH_SORT, s);
     uint64_t *ka = t->keys.as<uint64_t>(), *kb = t->keys2.as<uint64_t>();
@@ -699,7 +715,7 @@ int sort_keys(msp_tree *t, int64_t n, int nblk, bool full, hipStream_t s) {
     const int first = full ? 0 : kSegShift, npass = full ? 8 : 3;
     for (int pass = 0; pass < npass; ++pass) {
         const int shift = first + pass * 8;
-        {
+        if (pass > 0) {
             PhaseScope k1(&t->timing, PH_SORT_HIST, s);
             hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, ka, n, shift, hist, nblk);
             MSP_CHECK_LAUNCH();
@@ -799,9 +815,10 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     auto keys_and_sort = [&](bool full) -> int {
         {
             PhaseScope ps(&t->timing, PH_KEYS, s);
-            hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, y, z, n,
+            hipLaunchKernelGGL(k_morton, dim3(nblk), dim3(kBlock), 0, s, x, y, z, n,
                                t->bbox.as<float>() + kBboxParts * 6, t->keys.as<uint64_t>(),
-                               t->perm.as<int32_t>(), t->pin.as<float4>());
+                               t->perm.as<int32_t>(), t->pin.as<float4>(), full ? 0 : kSegShift,
+                               t->hist.as<uint32_t>(), nblk);
             MSP_CHECK_LAUNCH();
         }
         return sort_keys(t, n, nblk, full, s);
