@@ -5,7 +5,7 @@ import pytest
 
 import synth
 from oracle import octree, partner
-from tests.helpers import to_dev
+from tests.helpers import paper_parameters, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -151,11 +151,12 @@ def test_node_moments_m2m_parity():
     nodes = np.nonzero(has)[0]
     assert nodes.size > 50
     lh = tree.plan(wl.sigma, p=p)["level"]
-    # exactly the nodes at or below the moment level with more than 70 sources
-    # (points of nonzero weight) carry moments
+    # exactly the nodes at or below the moment level with more than c1 = 70 sources
+    # (points of nonzero weight; Algorithm 2's threshold) carry moments
     S = np.concatenate([[0], np.cumsum(wl.w[tr.perm] != 0)])
     nsrc = S[tr.first + tr.count] - S[tr.first]
-    np.testing.assert_array_equal(has != 0, (tr.level >= lh) & (nsrc > 70))
+    c1 = paper_parameters()["c1"]
+    np.testing.assert_array_equal(has != 0, (tr.level >= lh) & (nsrc > c1))
     slot0 = tr.level_offset[lh]
     A = A.reshape(-1, p, p, p)   # [slot][az][ay][ax]
     pos = wl.pos64()
