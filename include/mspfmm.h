@@ -26,6 +26,10 @@
  *     reused by later calls, released by msp_tree_destroy.  A handle must not be
  *     used from two host threads at once, and two calls on one handle must use
  *     the same stream (or be ordered by the caller).
+ *   - Callers that own all device memory use the *_query / *_ws pairs instead:
+ *     msp_octree_build_ws keeps the tree's arrays in a caller buffer and builds
+ *     in a caller workspace, msp_fgt_forward_ws evaluates in a caller workspace;
+ *     neither allocates device memory.
  *   - Return value: MSP_OK (0) or a negative MSP_E* code; msp_last_error()
  *     then gives a human-readable reason (thread-local).  No C++ exception
  *     crosses this interface.
@@ -45,7 +49,8 @@ extern "C" {
 enum msp_status {
     MSP_OK = 0,
     MSP_EINVAL = -1,    /* bad argument: NULL pointer, size, sigma, p, flags, non-finite position */
-    MSP_ENOSPC = -2,    /* a required buffer would exceed the library's size limits */
+    MSP_ENOSPC = -2,    /* a required buffer would exceed the library's size limits, or a
+                           caller-supplied buffer is too small */
     MSP_EOVERFLOW = -3, /* more than 2^31-1 points or nodes */
     MSP_EHIP = -4,      /* HIP runtime error (allocation, launch, copy) */
     MSP_ENOTSUP = -5,   /* unsupported device or option combination */
@@ -161,10 +166,40 @@ void msp_tree_destroy(msp_tree *t);
  * min(floor((x - lo) * (2^21 / side)), 2^21 - 1) in float64 and the three are
  * interleaved (x highest within each 3-bit digit) into a 63-bit key; points are
  * stably sorted by key.  x, y, z: device float32[n], input order.  leaf_max >= 1,
- * 0 <= max_depth <= 21, 0 <= n < 2^31.  Synchronises `stream` twice (root cube,
- * node count).  Replaces any tree held by the handle. */
+ * 0 <= max_depth <= 21, 0 <= n < 2^31.  Synchronises `stream` once: the level
+ * offsets, the root cube and the input checks come back in one page-locked
+ * readback (a second build pass, with its own readback, runs only when more
+ * points than the run sort takes share one 24-bit key prefix).  MSP_EINVAL for a
+ * non-finite coordinate.  Replaces any tree held by the handle. */
 int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
                      int32_t leaf_max, int32_t max_depth, void *stream);
+
+/* Sizes (host outputs, bytes) of the caller buffers of msp_octree_build_ws for n
+ * points: tree_bytes for the arrays the tree keeps (sorted keys, permutation,
+ * packed positions in key and in input order, inverse permutation, level offsets,
+ * node table and the direct route's per-leaf list lengths), sized for the largest
+ * node count such a tree can have (1 + the sum over levels l >= 1 of
+ * min(8^l, n, 8 floor(n / (leaf_max + 1))): every node below the root has a parent
+ * with more than leaf_max points, and the nodes of one level are disjoint);
+ * ws_bytes for the build's scratch (sort buffers, per-point levels, block
+ * counts).  Argument rules as msp_octree_build.  No device work. */
+int msp_octree_build_query(int64_t n, int32_t leaf_max, int32_t max_depth, size_t *tree_bytes,
+                           size_t *ws_bytes);
+
+/* msp_octree_build with caller-owned device memory: the tree's arrays are placed
+ * in tree_buf, which the tree uses until it is rebuilt or destroyed (the caller
+ * keeps it alive and unmodified meanwhile), and the build's scratch in ws, which
+ * the caller may reuse for work enqueued on `stream` after this call.  Both are
+ * device pointers aligned to 256 bytes.  tree_bytes may be smaller than the
+ * query's bound: MSP_ENOSPC (the message names the bytes needed) only if the tree
+ * actually built does not fit; ws_bytes must reach the query's figure.  Device
+ * memory that the handle owned from an earlier build is released.  The other
+ * entry points use a tree built this way like any other (those that need more
+ * memory than the tree still allocate it in the handle).  Synchronises `stream`
+ * as msp_octree_build. */
+int msp_octree_build_ws(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
+                        int32_t leaf_max, int32_t max_depth, void *tree_buf, size_t tree_bytes, void *ws,
+                        size_t ws_bytes, void *stream);
 
 /* Host copy of the tree's geometry and shape. */
 int msp_tree_get_info(const msp_tree *t, msp_tree_info *info);
@@ -189,6 +224,25 @@ int msp_fgt_plan(msp_tree *t, const msp_fgt_params *prm, msp_fgt_info *info);
  * synchronises `stream` once when its interaction lists are (re)built. */
 int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
                     const msp_fgt_params *prm, float *u_out, void *stream);
+
+/* Bytes of the workspace that msp_fgt_forward_ws needs for this tree and params
+ * (host output): on the expansion route two expansion grids (cells * p^3 floats
+ * each) and a third with the per-axis translation tables; on the direct
+ * route per-point target flags and key-order sums and the leaf interaction lists.
+ * The direct route's list lengths are counted on the device first when sigma or
+ * the cutoff changed since they were last counted (this synchronises `stream`). */
+int msp_fgt_forward_query(msp_tree *t, const msp_fgt_params *prm, size_t *ws_bytes, void *stream);
+
+/* msp_fgt_forward with every per-call buffer in the caller's workspace ws (device,
+ * 256-byte aligned, ws_bytes >= the query's figure, else MSP_ENOSPC).  Allocates
+ * no device memory.  The result has the bits of msp_fgt_forward with the same
+ * arguments.  The workspace holds nothing between calls: the translation tables
+ * and the direct route's lists are rebuilt in it on every call, and the debug
+ * buffers of msp_fgt_debug_buffer are not kept.  The direct route synchronises
+ * `stream` as msp_fgt_forward_query does when the list lengths must be
+ * recounted. */
+int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                       float *u_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Derivatives of L = sum_i g_i u(t_i) over the targets i (the adjoint of
  * msp_fgt_forward with the same w, is_target and params).  With
@@ -332,7 +386,10 @@ int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float
 
 /* Forward of every population (as msp_fgt_forward on its slice).  sigma: host
  * float32[npop] (prm->sigma is ignored); the other fields of prm apply to all.
- * use_graph = 0 runs eagerly every time. */
+ * use_graph = 0 runs eagerly every time.  The batched translation runs on the
+ * fp32 matrix cores on one level: MSP_M2L_VALU, MSP_M2L_BF16X3, MSP_TWO_LEVEL and
+ * the partner flags give MSP_ENOTSUP here and in msp_batch_backward and
+ * msp_batch_autotune. */
 int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                       const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream);
 

@@ -77,6 +77,11 @@ _lib.msp_tree_create.argtypes = [ctypes.POINTER(_vp)]
 _lib.msp_tree_destroy.argtypes = [_vp]
 _lib.msp_tree_destroy.restype = None
 _lib.msp_octree_build.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp]
+_sz = ctypes.c_size_t
+_lib.msp_octree_build_query.argtypes = [_i64, _i32, _i32, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]
+_lib.msp_octree_build_ws.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz, _vp, _sz, _vp]
+_lib.msp_fgt_forward_query.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(_sz), _vp]
+_lib.msp_fgt_forward_ws.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _sz, _vp]
 _lib.msp_tree_get_info.argtypes = [_vp, ctypes.POINTER(TreeInfo)]
 _lib.msp_tree_export.argtypes = [_vp, ctypes.POINTER(TreeArrays), _vp]
 _lib.msp_fgt_plan.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(FgtInfo)]
@@ -107,7 +112,8 @@ _lib.msp_batch_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams
 _lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
 _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
-for _f in ("msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
+for _f in ("msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
+           "msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_descent_step", "msp_partner_descent",
            "msp_fgt_debug_buffer", "msp_batch_create", "msp_batch_build", "msp_batch_autotune",
@@ -185,6 +191,47 @@ class Tree:
         self.n = n
         self._keep = (x, y, z)
         return self
+
+    def build_ws(self, x, y, z, tree_buf, ws, leaf_max=64, max_depth=21):
+        """msp_octree_build_ws: the tree's arrays in tree_buf, the build scratch in ws
+        (CUDA uint8 tensors of at least the sizes build_query gives; tree_buf is kept
+        referenced by this object for as long as the tree uses it)."""
+        n = x.numel()
+        px, py, pz = (_ptr(v, torch.float32, n, nm) for v, nm in ((x, "x"), (y, "y"), (z, "z")))
+        pt = _ptr(tree_buf, torch.uint8, None, "tree_buf")
+        pw = _ptr(ws, torch.uint8, None, "ws")
+        _check(_lib.msp_octree_build_ws(self._h, px, py, pz, n, int(leaf_max), int(max_depth), pt,
+                                        tree_buf.numel(), pw, ws.numel(), _stream()), "msp_octree_build_ws")
+        self.n = n
+        self._keep = (x, y, z, tree_buf)
+        return self
+
+    def forward_query(self, sigma, p=8, level=-1, route="auto", cutoff_sigmas=4.5, exclude_self=False,
+                      m2l="mfma", two_level=False) -> int:
+        """Workspace bytes of forward_ws for these parameters (msp_fgt_forward_query)."""
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
+        nbytes = _sz()
+        _check(_lib.msp_fgt_forward_query(self._h, ctypes.byref(prm), ctypes.byref(nbytes), _stream()),
+               "msp_fgt_forward_query")
+        return nbytes.value
+
+    def forward_ws(self, w, ws, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
+                   exclude_self=False, out=None, m2l="mfma", two_level=False, stage_weights=False):
+        """forward() with every per-call buffer in ws, a CUDA uint8 tensor of at least
+        forward_query() bytes (msp_fgt_forward_ws)."""
+        n = self.n
+        pw = _ptr(w, torch.float32, n, "w")
+        pt = _ptr(is_target, torch.uint8, n, "is_target")
+        pws = _ptr(ws, torch.uint8, None, "ws")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=w.device)
+        po = _ptr(out, torch.float32, n, "out")
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
+        if stage_weights:
+            prm.flags |= STAGE_WEIGHTS
+        _check(_lib.msp_fgt_forward_ws(self._h, pw, pt, ctypes.byref(prm), po, pws, ws.numel(), _stream()),
+               "msp_fgt_forward_ws")
+        return out
 
     def info(self) -> dict:
         inf = TreeInfo()
@@ -495,6 +542,14 @@ class Batch:
         npop, launches = _i32(), _i64()
         _check(_lib.msp_batch_info(self._h, ctypes.byref(npop), ctypes.byref(launches)), "msp_batch_info")
         return {"populations": npop.value, "launches_last_eager_forward": launches.value}
+
+
+def build_query(n, leaf_max=64, max_depth=21) -> tuple[int, int]:
+    """(tree_bytes, ws_bytes) for Tree.build_ws over n points (msp_octree_build_query)."""
+    tb, wb = _sz(), _sz()
+    _check(_lib.msp_octree_build_query(int(n), int(leaf_max), int(max_depth), ctypes.byref(tb), ctypes.byref(wb)),
+           "msp_octree_build_query")
+    return tb.value, wb.value
 
 
 def build_tree(x, y, z, leaf_max=64, max_depth=21) -> Tree:

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -29,6 +30,8 @@ int fail(int code, const char *fmt, ...) {
 int DevBuf::ensure(size_t need) {
     if (need == 0) need = 1;
     if (need <= bytes) return MSP_OK;
+    if (fixed)
+        return fail(MSP_ENOSPC, "caller buffer region holds %zu bytes, %zu needed", bytes, need);
     if (p) {
         hipError_t e = hipFree(p);
         p = nullptr;
@@ -46,9 +49,10 @@ int DevBuf::ensure(size_t need) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && !fixed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    fixed = false;
 }
 
 int HostBuf::ensure(size_t need) {
@@ -154,6 +158,13 @@ int msp_tree_create(msp_tree **out) {
     msp_tree *t = new (std::nothrow) msp_tree();
     if (!t) return fail(MSP_ENOSPC, "host allocation failed");
     (void)hipGetDevice(&t->device);
+    // page-locked landing area of the build's one readback, made here so that a
+    // build into caller buffers allocates nothing
+    const int rc = t->build_stage.ensure(256);
+    if (rc != MSP_OK) {
+        delete t;
+        return rc;
+    }
     *out = t;
     return MSP_OK;
 }
@@ -174,6 +185,36 @@ int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z
     if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
     if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
     return build_tree(t, x, y, z, n, leaf_max, max_depth, (hipStream_t)stream);
+}
+
+int msp_octree_build_query(int64_t n, int32_t leaf_max, int32_t max_depth, size_t *tree_bytes,
+                           size_t *ws_bytes) {
+    g_err[0] = 0;
+    if (!tree_bytes || !ws_bytes) return fail(MSP_EINVAL, "NULL size output");
+    if (n < 0) return fail(MSP_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "n = %lld exceeds 2^31-1", (long long)n);
+    if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    build_query_bytes(n, leaf_max, max_depth, tree_bytes, ws_bytes);
+    return MSP_OK;
+}
+
+static bool misaligned(const void *p) { return ((uintptr_t)p & 255) != 0; }
+
+int msp_octree_build_ws(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
+                        int32_t leaf_max, int32_t max_depth, void *tree_buf, size_t tree_bytes, void *ws,
+                        size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (n < 0) return fail(MSP_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "n = %lld exceeds 2^31-1", (long long)n);
+    if (n > 0 && (!x || !y || !z)) return fail(MSP_EINVAL, "NULL coordinate array");
+    if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    if (!tree_buf || !ws) return fail(MSP_EINVAL, "NULL tree buffer or workspace");
+    if (misaligned(tree_buf) || misaligned(ws)) return fail(MSP_EINVAL, "buffers must be 256-byte aligned");
+    return build_tree(t, x, y, z, n, leaf_max, max_depth, (hipStream_t)stream, tree_buf, tree_bytes, ws,
+                      ws_bytes);
 }
 
 int msp_tree_get_info(const msp_tree *t, msp_tree_info *info) {
@@ -251,6 +292,98 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     t->w_staged = true;
     MSP_TRY(direct_route(t, prm, s));
     return scatter_output(t, u_out, prm->flags, false, s);
+}
+
+}  // extern "C"
+
+namespace msp {
+namespace {
+// The regions of a forward call's workspace, in order: the expansion route's two
+// grids and the buffer of its third grid and operator tables, or the direct
+// route's target flags, key-order sums and list entries (whose count needs the
+// list lengths).  sw == NULL only counts.
+void forward_layout(msp_tree *t, const FgtPlan &pl, Carve &c, BufSwap *sw) {
+    auto put = [&](DevBuf &b, size_t bytes) {
+        if (sw) sw->bind(b, c, bytes);
+        else c.take(bytes);
+    };
+    if (pl.route == MSP_ROUTE_FGT) {
+        size_t g = 0, o = 0;
+        fgt_grid_bytes(pl, &g, &o);
+        put(t->gridA, g);
+        put(t->gridB, g);
+        put(t->ops, o);
+    } else {
+        const size_t nb = (size_t)(t->n > 0 ? t->n : 1);
+        put(t->tflag, nb);
+        put(t->usort, nb * 4);
+        put(t->list_idx, (size_t)(t->list_total > 0 ? t->list_total : 1) * 4);
+    }
+}
+}  // namespace
+}  // namespace msp
+
+extern "C" {
+
+int msp_fgt_forward_query(msp_tree *t, const msp_fgt_params *prm, size_t *ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!t || !ws_bytes) return fail(MSP_EINVAL, "NULL argument");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    FgtPlan pl;
+    MSP_TRY(plan_fgt(t, prm, &pl));
+    if (pl.route == MSP_ROUTE_DIRECT) MSP_TRY(direct_route_counts(t, prm, (hipStream_t)stream));
+    Carve c(nullptr, 0);
+    forward_layout(t, pl, c, nullptr);
+    *ws_bytes = c.used;
+    return MSP_OK;
+}
+
+int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                       float *u_out, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    if (t->n > 0 && (!w || !u_out)) return fail(MSP_EINVAL, "NULL weight or output array");
+    if (!ws) return fail(MSP_EINVAL, "workspace is NULL");
+    if (misaligned(ws)) return fail(MSP_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    FgtPlan pl;
+    MSP_TRY(plan_fgt(t, prm, &pl));
+    if (pl.route == MSP_ROUTE_DIRECT) MSP_TRY(direct_route_counts(t, prm, s));
+    {
+        Carve probe(nullptr, 0);
+        forward_layout(t, pl, probe, nullptr);
+        if (probe.used > ws_bytes)
+            return fail(MSP_ENOSPC, "workspace holds %zu bytes, the call needs %zu (msp_fgt_forward_query)",
+                        ws_bytes, probe.used);
+    }
+    t->w_staged = false;
+    t->grid_bytes_valid = 0;   // the grids of this call live in the caller's workspace
+    Carve c(ws, ws_bytes);
+    BufSwap sw;
+    forward_layout(t, pl, c, &sw);
+    if (pl.route == MSP_ROUTE_FGT) {
+        // the operator tables are rebuilt in the workspace; the handle's own copy
+        // stays as it was
+        const bool ops_valid = t->ops_valid;
+        uint64_t ops_sig[5];
+        std::copy(t->ops_sig, t->ops_sig + 5, ops_sig);
+        t->ops_valid = false;
+        const int rc = fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
+        t->ops_valid = ops_valid;
+        std::copy(ops_sig, ops_sig + 5, t->ops_sig);
+        t->grid_bytes_valid = 0;
+        t->w_staged = rc == MSP_OK && pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS);
+        return rc;
+    }
+    MSP_TRY(stage_inputs(t, w, is_target, s));
+    MSP_TRY(direct_route_fill(t, prm, s));
+    MSP_TRY(direct_route(t, prm, s, true));
+    MSP_TRY(scatter_output(t, u_out, prm->flags, false, s));
+    t->w_staged = true;
+    return MSP_OK;
 }
 
 int msp_fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target,
@@ -400,6 +533,15 @@ void msp_batch_destroy(msp_batch *b) {
     delete b;
 }
 
+// the batched kernels run the single-level fp32 matrix-core translation only, and
+// partner flags have no meaning for a batch
+static int check_batch_flags(const msp_fgt_params *prm) {
+    const uint32_t bad = prm->flags & (uint32_t)(MSP_M2L_VALU | MSP_M2L_BF16X3 | MSP_TWO_LEVEL |
+                                                 MSP_WEIGHTS_STAGED | MSP_STAGE_WEIGHTS);
+    if (bad) return fail(MSP_ENOTSUP, "flags 0x%x are not supported by the batch entry points", bad);
+    return MSP_OK;
+}
+
 static int check_offsets(const int64_t *offsets, int32_t npop) {
     if (npop < 0) return fail(MSP_EINVAL, "npop = %d < 0", npop);
     if (!offsets) return fail(MSP_EINVAL, "offsets is NULL");
@@ -430,9 +572,10 @@ int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float
                        int32_t max_depth, float *scratch_u, int32_t *leaf_out, int32_t *route_out,
                        void *stream) {
     g_err[0] = 0;
+    MSP_TRY(check_params(prm));
+    MSP_TRY(check_batch_flags(prm));
     if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     MSP_TRY(check_offsets(offsets, npop));
-    MSP_TRY(check_params(prm));
     if (offsets[npop] > 0 && (!x || !y || !z || !w || !scratch_u)) return fail(MSP_EINVAL, "NULL array");
     if (npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
     if (!cand || ncand < 1) return fail(MSP_EINVAL, "no candidate leaf sizes");
@@ -446,8 +589,9 @@ int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float
 int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                       const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream) {
     g_err[0] = 0;
-    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     MSP_TRY(check_params(prm));
+    MSP_TRY(check_batch_flags(prm));
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     if (b->npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
     if (b->npop > 0 && b->off[b->npop] > 0 && (!w || !u_out)) return fail(MSP_EINVAL, "NULL weight or output array");
     return batch_forward(b, w, is_target, sigma, prm, u_out, use_graph, (hipStream_t)stream);
@@ -457,8 +601,9 @@ int msp_batch_backward(msp_batch *b, const float *w, const uint8_t *is_target, c
                        const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,
                        float *grad_y, float *grad_z, double *grad_sigma, int32_t use_graph, void *stream) {
     g_err[0] = 0;
-    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     MSP_TRY(check_params(prm));
+    MSP_TRY(check_batch_flags(prm));
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
     if (b->npop > 0 && !sigma) return fail(MSP_EINVAL, "sigma is NULL");
     if (b->npop > 0 && b->off[b->npop] > 0 && (!w || !grad_u)) return fail(MSP_EINVAL, "NULL weight or upstream gradient");
     const int npos = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);

@@ -2134,13 +2134,22 @@ int fgt_batch_field_grad(const FgtBatchPlan &bp, int stride, int slot, int want_
     return fail(MSP_EINVAL, "p out of range");
 }
 
+void fgt_grid_bytes(const FgtPlan &pl, size_t *grid, size_t *ops) {
+    const size_t p = (size_t)pl.p;
+    const size_t ncell = (size_t)pl.G[0] * pl.G[1] * pl.G[2];
+    *grid = ncell * p * p * p * 4;
+    // a third grid, then the per-axis operator tables
+    *ops = *grid + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4;
+}
+
 int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, FgtPop *f) {
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
-    const size_t gbytes = (size_t)ncell * p * p * p * 4;
+    size_t gbytes = 0, obytes = 0;
+    fgt_grid_bytes(pl, &gbytes, &obytes);
     MSP_TRY(t->gridA.ensure(gbytes));
     MSP_TRY(t->gridB.ensure(gbytes));
-    MSP_TRY(t->ops.ensure(gbytes + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4));
+    MSP_TRY(t->ops.ensure(obytes));
     t->ops_valid = false;   // the batched pass writes the tables itself
     t->grid_bytes_valid = (int64_t)gbytes;
     f->keys = t->keys.as<uint64_t>();
@@ -2262,11 +2271,12 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
                       (prm->flags & MSP_STAGE_WEIGHTS) != 0};
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
-    const size_t gbytes = (size_t)ncell * p * p * p * 4;
+    size_t gbytes = 0, obytes = 0;
+    fgt_grid_bytes(pl, &gbytes, &obytes);
     MSP_TRY(t->gridA.ensure(gbytes));
     MSP_TRY(t->gridB.ensure(gbytes));
     const size_t ops_bytes_before = t->ops.bytes;
-    MSP_TRY(t->ops.ensure(gbytes + (size_t)(2 * (pl.G[0] + pl.G[1] + pl.G[2])) * p * p * 4));
+    MSP_TRY(t->ops.ensure(obytes));
     if (t->ops.bytes != ops_bytes_before) t->ops_valid = false;   // reallocated
     t->grid_bytes_valid = (int64_t)gbytes;
     if (t->n == 0) return MSP_OK;

@@ -38,17 +38,75 @@ int fail(int code, const char *fmt, ...);
         if (rc_ != MSP_OK) return rc_; \
     } while (0)
 
-// A grow-only device allocation owned by a handle.
+// A grow-only device allocation owned by a handle, or a region of caller memory
+// bound to it (fixed: never reallocated or freed; a request beyond its size is
+// MSP_ENOSPC).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     int ensure(size_t need);
     void release();
+    void bind(void *ext, size_t n) {
+        release();
+        p = ext;
+        bytes = n;
+        fixed = true;
+    }
     template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Consecutive 256-byte aligned regions of one caller buffer.  With base == NULL it
+// only counts, so a size query and the call that uses the buffer share one layout.
+struct Carve {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    Carve(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    void *take(size_t n) {
+        used = (used + 255) & ~(size_t)255;
+        void *r = base ? base + used : nullptr;
+        used += n > 0 ? n : 1;
+        return r;
+    }
+    // bind the next n bytes to b
+    void into(DevBuf &b, size_t n) {
+        void *r = take(n);
+        b.bind(r, n > 0 ? n : 1);
+    }
+    bool fits() const { return used <= cap; }
+};
+
+// Replaces some of a handle's buffers by regions of a caller workspace for the
+// length of one call and puts the handle's own buffers back afterwards (nothing
+// is allocated or freed).
+struct BufSwap {
+    static constexpr int kMax = 8;
+    DevBuf *buf[kMax];
+    void *p[kMax];
+    size_t bytes[kMax];
+    bool fixed[kMax];
+    int n = 0;
+    void bind(DevBuf &b, Carve &c, size_t need) {
+        buf[n] = &b;
+        p[n] = b.p;
+        bytes[n] = b.bytes;
+        fixed[n] = b.fixed;
+        ++n;
+        b.p = c.take(need);
+        b.bytes = need > 0 ? need : 1;
+        b.fixed = true;
+    }
+    ~BufSwap() {
+        for (int k = 0; k < n; ++k) {
+            buf[k]->p = p[k];
+            buf[k]->bytes = bytes[k];
+            buf[k]->fixed = fixed[k];
+        }
+    }
 };
 
 // A grow-only page-locked host allocation owned by a handle (staging of uploads).
@@ -145,7 +203,8 @@ struct msp_tree {
     msp::DevBuf list_off, list_idx, list_cnt;
     int64_t list_total = 0;
     float list_sigma = -1.f, list_cutoff = -2.f;
-    bool lists_valid = false;
+    bool counts_valid = false;  // list_cnt / list_off / list_total match list_sigma, list_cutoff
+    bool lists_valid = false;   // list_idx holds those lists too
     // node moments for partner queries
     msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
     msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
@@ -299,8 +358,15 @@ int batch_instance_ms(msp_batch *b, double *ms);
 int batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
 
 // tree.hip
+// tree_buf == NULL: handle-owned memory; otherwise the tree's arrays go to tree_buf
+// and the build scratch to ws (MSP_ENOSPC when they do not fit)
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
-               int max_depth, hipStream_t s);
+               int max_depth, hipStream_t s, void *tree_buf = nullptr, size_t tree_bytes = 0,
+               void *ws = nullptr, size_t ws_bytes = 0);
+// upper bound on the node count of a tree over n points
+int64_t tree_node_bound(int64_t n, int leaf_max, int max_depth);
+// caller buffer sizes of msp_octree_build_ws
+void build_query_bytes(int64_t n, int leaf_max, int max_depth, size_t *tree_bytes, size_t *ws_bytes);
 
 // fgt.hip
 struct FgtPlan {
@@ -323,6 +389,9 @@ int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s);
 // points, into f.rec + i * stride + slot (key order i)
 int fgt_batch_field_grad(const FgtBatchPlan &bp, int stride, int slot, int want_lap, hipStream_t s);
 int plan_fgt(const msp_tree *t, const msp_fgt_params *prm, FgtPlan *plan);
+// bytes of one expansion grid, and of the buffer holding a third grid and the
+// operator tables
+void fgt_grid_bytes(const FgtPlan &pl, size_t *grid, size_t *ops);
 double rho_max_for_p(int p);
 int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStream_t s);
 int fgt_forward_grid(msp_tree *t, const FgtPlan &plan, const msp_fgt_params *prm, const float *w,
@@ -340,8 +409,14 @@ int fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target, const ms
 int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s);
 
 // p2p.hip
-int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
+// lists_ready: t->list_idx already holds the lists of prm (else they are built or
+// taken from the handle's cache)
+int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s, bool lists_ready = false);
 int direct_route_lists(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
+// per-leaf list lengths and offsets for prm's sigma and cutoff (one host
+// synchronisation when they change), and the list entries into t->list_idx
+int direct_route_counts(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
+int direct_route_fill(msp_tree *t, const msp_fgt_params *prm, hipStream_t s);
 int direct_all_pairs(const float *tx, const float *ty, const float *tz, int64_t nt, const float *sx,
                      const float *sy, const float *sz, const float *w, int64_t ns, float sigma,
                      float *u, hipStream_t s);

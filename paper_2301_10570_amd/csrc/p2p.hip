@@ -153,49 +153,69 @@ __global__ void __launch_bounds__(kBlock) k_direct(const float *tx, const float 
 
 }  // namespace
 
-int direct_route_lists(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+int direct_route_counts(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+    const int64_t nn = t->n_nodes;
+    if (t->n == 0) return MSP_OK;
+    if (t->counts_valid && t->list_sigma == prm->sigma && t->list_cutoff == prm->cutoff_sigmas) return MSP_OK;
+    BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
+    const bool unlimited = !(prm->cutoff_sigmas > 0.f);
+    const float R = unlimited ? 0.f : prm->cutoff_sigmas * prm->sigma;
+    PhaseScope ps(&t->timing, PH_LISTS, s);
+    t->lists_valid = false;
+    t->counts_valid = false;
+    MSP_TRY(t->list_cnt.ensure(nn * 4));
+    MSP_TRY(t->list_off.ensure((nn + 1) * 8));
+    hipLaunchKernelGGL(k_lists, dim3(grid_for(nn, 128)), dim3(128), 0, s, nn, t->nlevel.as<int32_t>(),
+                       t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                       t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), geo, R * R, unlimited ? 1 : 0,
+                       nullptr, t->list_cnt.as<int32_t>(), nullptr);
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(kBlock), 0, s, t->list_cnt.as<int32_t>(), nn,
+                       t->list_off.as<int64_t>());
+    MSP_CHECK_LAUNCH();
+    int64_t total = 0;
+    MSP_HIP(hipMemcpyAsync(&total, t->list_off.as<int64_t>() + nn, 8, hipMemcpyDeviceToHost, s));
+    MSP_HIP(hipStreamSynchronize(s));
+    if (total > 0x7fffffffLL)
+        return fail(MSP_ENOSPC, "direct route: %lld leaf pairs within the cutoff exceed the list limit",
+                    (long long)total);
+    t->list_total = total;
+    t->list_sigma = prm->sigma;
+    t->list_cutoff = prm->cutoff_sigmas;
+    t->counts_valid = true;
+    return MSP_OK;
+}
+
+int direct_route_fill(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     const int64_t nn = t->n_nodes;
     if (t->n == 0) return MSP_OK;
     BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : prm->cutoff_sigmas * prm->sigma;
-    if (!t->lists_valid || t->list_sigma != prm->sigma || t->list_cutoff != prm->cutoff_sigmas) {
-        PhaseScope ps(&t->timing, PH_LISTS, s);
-        MSP_TRY(t->list_cnt.ensure(nn * 4));
-        MSP_TRY(t->list_off.ensure((nn + 1) * 8));
-        hipLaunchKernelGGL(k_lists, dim3(grid_for(nn, 128)), dim3(128), 0, s, nn,
-                           t->nlevel.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
-                           t->niz.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
-                           geo, R * R, unlimited ? 1 : 0, nullptr, t->list_cnt.as<int32_t>(), nullptr);
-        MSP_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(kBlock), 0, s, t->list_cnt.as<int32_t>(),
-                           nn, t->list_off.as<int64_t>());
-        MSP_CHECK_LAUNCH();
-        int64_t total = 0;
-        MSP_HIP(hipMemcpyAsync(&total, t->list_off.as<int64_t>() + nn, 8, hipMemcpyDeviceToHost, s));
-        MSP_HIP(hipStreamSynchronize(s));
-        if (total > 0x7fffffffLL)
-            return fail(MSP_ENOSPC, "direct route: %lld leaf pairs within the cutoff exceed the list limit",
-                        (long long)total);
-        MSP_TRY(t->list_idx.ensure((total > 0 ? total : 1) * 4));
-        hipLaunchKernelGGL(k_lists, dim3(grid_for(nn, 128)), dim3(128), 0, s, nn,
-                           t->nlevel.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
-                           t->niz.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
-                           geo, R * R, unlimited ? 1 : 0, t->list_off.as<int64_t>(),
-                           t->list_cnt.as<int32_t>(), t->list_idx.as<int32_t>());
-        MSP_CHECK_LAUNCH();
-        t->list_total = total;
-        t->list_sigma = prm->sigma;
-        t->list_cutoff = prm->cutoff_sigmas;
+    PhaseScope ps(&t->timing, PH_LISTS, s);
+    MSP_TRY(t->list_idx.ensure((t->list_total > 0 ? t->list_total : 1) * 4));
+    hipLaunchKernelGGL(k_lists, dim3(grid_for(nn, 128)), dim3(128), 0, s, nn, t->nlevel.as<int32_t>(),
+                       t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                       t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), geo, R * R, unlimited ? 1 : 0,
+                       t->list_off.as<int64_t>(), t->list_cnt.as<int32_t>(), t->list_idx.as<int32_t>());
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+
+int direct_route_lists(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+    if (t->n == 0) return MSP_OK;
+    MSP_TRY(direct_route_counts(t, prm, s));
+    if (!t->lists_valid) {
+        MSP_TRY(direct_route_fill(t, prm, s));
         t->lists_valid = true;
     }
     return MSP_OK;
 }
 
-int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
+int direct_route(msp_tree *t, const msp_fgt_params *prm, hipStream_t s, bool lists_ready) {
     const int64_t nn = t->n_nodes;
     if (t->n == 0) return MSP_OK;
-    MSP_TRY(direct_route_lists(t, prm, s));
+    if (!lists_ready) MSP_TRY(direct_route_lists(t, prm, s));
     BoxGeo geo{{t->geo.lo[0], t->geo.lo[1], t->geo.lo[2]}, t->geo.side};
     const float k_scale = (float)(std::sqrt(1.4426950408889634) / (double)prm->sigma);
     PhaseScope ps(&t->timing, PH_P2P, s);

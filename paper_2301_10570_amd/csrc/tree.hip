@@ -747,11 +747,115 @@ int sort_keys(msp_tree *t, int64_t n, int nblk, bool full, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------
+// Device memory of a build.  Handle-owned buffers grow on demand; with caller
+// buffers (tree_buf for what the tree keeps, ws for the build scratch) every array
+// is bound to a region of them in the order below, which the size query repeats
+// with counting carves.
+namespace {
+
+inline int build_blocks(int64_t n) {
+    const int64_t b = (n + kTile - 1) / kTile;
+    return b > 0 ? (int)b : 1;
+}
+constexpr size_t kBboxBytes = kBboxParts * 6 * sizeof(float) + 8 * sizeof(float) + 2 * sizeof(int);
+
+// arrays the tree keeps, per point (sorted keys, permutation, sorted and input-order
+// packed positions, inverse permutation) and the level offsets
+void place_point_arrays(msp_tree *t, int64_t n, Carve &c) {
+    const size_t nb = (size_t)(n > 0 ? n : 1);
+    c.into(t->keys, nb * 8);
+    c.into(t->perm, nb * 4);
+    c.into(t->ps, nb * 16);
+    c.into(t->pin, nb * 16);
+    c.into(t->iperm, nb * 4);
+    c.into(t->d_level_off, kMaxLevels * 8);
+}
+
+// the node table and the direct route's per-leaf list counts and offsets
+void place_node_arrays(msp_tree *t, int64_t nn, Carve &c) {
+    const size_t m = (size_t)(nn > 0 ? nn : 1);
+    for (DevBuf *b : {&t->nlevel, &t->nfirst, &t->ncount, &t->nparent, &t->nfchild, &t->nnchild,
+                      &t->ndigit, &t->nix, &t->niy, &t->niz})
+        c.into(*b, m * 4);
+    c.into(t->list_cnt, m * 4);
+    c.into(t->list_off, (m + 1) * 8);
+}
+
+// build scratch
+void place_scratch(msp_tree *t, int64_t n, Carve &c) {
+    const size_t nb = (size_t)(n > 0 ? n : 1);
+    const int nblk = build_blocks(n);
+    c.into(t->bbox, kBboxBytes);
+    c.into(t->keys2, nb * 8);
+    c.into(t->perm2, nb * 4);
+    c.into(t->hist, (size_t)256 * nblk * 4 + 256 * 4);
+    c.into(t->dlev, nb);
+    c.into(t->llev, nb);
+    c.into(t->blkcnt, (size_t)kMaxLevels * nblk * 4 + kMaxLevels * 4);
+    c.into(t->tmp_a, nb);
+    c.into(t->tmp_b, nb);
+    c.into(t->tmp_c, nb);
+}
+
+// drop caller regions left from an earlier build into caller buffers, so that a
+// build into handle memory allocates its own
+void unbind_fixed(msp_tree *t) {
+    for (DevBuf *b : {&t->keys, &t->perm, &t->ps, &t->pin, &t->iperm, &t->d_level_off, &t->nlevel,
+                      &t->nfirst, &t->ncount, &t->nparent, &t->nfchild, &t->nnchild, &t->ndigit, &t->nix,
+                      &t->niy, &t->niz, &t->list_cnt, &t->list_off, &t->bbox, &t->keys2, &t->perm2, &t->hist,
+                      &t->dlev, &t->llev, &t->blkcnt, &t->tmp_a, &t->tmp_b, &t->tmp_c})
+        if (b->fixed) b->release();
+}
+
+}  // namespace
+
+int64_t tree_node_bound(int64_t n, int leaf_max, int max_depth) {
+    if (n <= 0) return 1;
+    // a node below the root has a parent holding more than leaf_max points, and the
+    // nodes of one level are disjoint and non-empty
+    const int64_t inner = n / ((int64_t)leaf_max + 1);
+    int64_t total = 1, pow8 = 1;
+    for (int l = 1; l <= max_depth && inner > 0; ++l) {
+        if (pow8 < n) pow8 *= 8;
+        int64_t c = pow8 < n ? pow8 : n;
+        if (8 * inner < c) c = 8 * inner;
+        total += c;
+    }
+    return total;
+}
+
+void build_query_bytes(int64_t n, int leaf_max, int max_depth, size_t *tree_bytes, size_t *ws_bytes) {
+    msp_tree probe;   // counting carves bind nothing real
+    Carve tc(nullptr, 0), wc(nullptr, 0);
+    place_point_arrays(&probe, n, tc);
+    place_node_arrays(&probe, tree_node_bound(n, leaf_max, max_depth), tc);
+    place_scratch(&probe, n, wc);
+    *tree_bytes = tc.used;
+    *ws_bytes = wc.used;
+}
+
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
-               int max_depth, hipStream_t s) {
+               int max_depth, hipStream_t s, void *tree_buf, size_t tree_bytes, void *ws,
+               size_t ws_bytes) {
     t->built = false;
+    const bool caller_mem = tree_buf != nullptr;
+    Carve tc(tree_buf, tree_bytes);
+    if (caller_mem) {
+        Carve wc(ws, ws_bytes);
+        place_point_arrays(t, n, tc);
+        place_scratch(t, n, wc);
+        if (!tc.fits() || !wc.fits()) {
+            unbind_fixed(t);
+            return fail(MSP_ENOSPC, "msp_octree_build_ws: tree buffer holds %zu bytes (%zu needed before the "
+                        "node table), workspace %zu (%zu needed)", tree_bytes, tc.used, ws_bytes, wc.used);
+        }
+    } else {
+        unbind_fixed(t);
+    }
     t->iperm_valid = false;
     t->lists_valid = false;
+    t->counts_valid = false;
     t->w_staged = false;
     t->node_moments_level = -1;
     t->n = n;
@@ -763,7 +867,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     float box[6] = {0, 0, 0, 0, 0, 0};
     if (n > 0) {
         const int parts = kBboxParts;
-        MSP_TRY(t->bbox.ensure(parts * 6 * sizeof(float) + 8 * sizeof(float) + 2 * sizeof(int)));
+        MSP_TRY(t->bbox.ensure(kBboxBytes));
         float *part = t->bbox.as<float>();
         float *out = part + parts * 6;
         int *bad = bbox_flags(t);
@@ -797,7 +901,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     MSP_TRY(t->ps.ensure(nb * 16));
     MSP_TRY(t->perm.ensure(nb * 4));
     MSP_TRY(t->perm2.ensure(nb * 4));
-    const int nblk = (int)((n + kTile - 1) / kTile) > 0 ? (int)((n + kTile - 1) / kTile) : 1;
+    const int nblk = build_blocks(n);
     MSP_TRY(t->hist.ensure((size_t)256 * nblk * 4 + 256 * 4));
     // per-point levels and node counts per level (scratch)
     MSP_TRY(t->dlev.ensure(nb));
@@ -893,9 +997,19 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         if (t->level_off[l + 1] > t->level_off[l]) t->depth = l;
 
     const int64_t nn = t->n_nodes;
+    if (caller_mem) {
+        place_node_arrays(t, nn, tc);
+        if (!tc.fits())
+            return fail(MSP_ENOSPC, "msp_octree_build_ws: the tree has %lld nodes and needs %zu bytes; the tree "
+                        "buffer holds %zu", (long long)nn, tc.used, tree_bytes);
+    }
     for (DevBuf *b : {&t->nlevel, &t->nfirst, &t->ncount, &t->nparent, &t->nfchild, &t->nnchild,
                       &t->ndigit, &t->nix, &t->niy, &t->niz})
         MSP_TRY(b->ensure(nn * 4));
+    // the direct route's per-leaf list lengths and offsets live with the node table,
+    // so that a forward into a caller workspace needs no allocation for them
+    MSP_TRY(t->list_cnt.ensure(nn * 4));
+    MSP_TRY(t->list_off.ensure((nn + 1) * 8));
     {
     PhaseScope ps_nodes(&t->timing, PH_NODES, s);
     if (n > 0) {
