@@ -148,6 +148,94 @@ def _descent_bench(args, dev):
             "requests_per_s": ax.size / (ms / 1000.0), "valid": ok}
 
 
+def _timed(fn, steps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return 1000.0 * (time.perf_counter() - t0) / steps
+
+
+def _other_configs(args, dev, threads):
+    """The transform against the all-pairs GPU direct sum on the 4,096-neuron cube
+    (sigma 100 um) and on the 262,144 neurons in 64 blobs (sigma 200 um), each with
+    its accuracy against the FP64 oracle; and forward + backward on the gradient
+    workload (1,048,576 sources + 1,048,576 targets in a 2 mm cube, sigma 200 um)."""
+    import numpy as np
+    import torch
+
+    import paper_2301_10570_amd as msp
+    import synth
+    out = {}
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    for name, wl, nchk in (("uniform4k", synth.uniform4k(), None), ("blobs262k", synth.blobs262k(), 4096)):
+        x, y, z, w, tg = T(wl.x), T(wl.y), T(wl.z), T(wl.w), T((wl.a > 0).astype(np.uint8))
+        ti = np.nonzero(wl.a > 0)[0]
+        si = np.nonzero(wl.w > 0)[0]
+        tree = msp.Tree().build(x, y, z, leaf_max=wl.leaf_max)
+        u = torch.empty(wl.n, dtype=torch.float32, device=dev)
+        ms_c = _timed(lambda: tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u), args.steps)
+        ms_b = _timed(lambda: (tree.build(x, y, z, leaf_max=wl.leaf_max),
+                               tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u)), args.steps)
+        plan = tree.plan(wl.sigma, p=wl.p)
+        dtx, dty, dtz = T(wl.x[ti]), T(wl.y[ti]), T(wl.z[ti])
+        dsx, dsy, dsz, dsw = T(wl.x[si]), T(wl.y[si]), T(wl.z[si]), T(wl.w[si])
+        ud = torch.empty(ti.size, dtype=torch.float32, device=dev)
+        ms_d = _timed(lambda: msp.direct_sum(dtx, dty, dtz, dsx, dsy, dsz, dsw, wl.sigma, out=ud), args.steps)
+        row = {"n": wl.n, "targets": int(ti.size), "sources": int(si.size), "route": plan["route"],
+               "level": plan["level"], "fmm_ms_cached_tree": ms_c, "fmm_ms_incl_tree": ms_b,
+               "fmm_sums_per_s_cached_tree": ti.size / (ms_c / 1000.0),
+               "fmm_sums_per_s_incl_tree": ti.size / (ms_b / 1000.0),
+               "direct_gpu_ms": ms_d, "direct_gpu_sums_per_s": ti.size / (ms_d / 1000.0),
+               "speedup_cached_tree": ms_d / ms_c, "speedup_incl_tree": ms_d / ms_b}
+        if not args.no_check:
+            import oracle
+            chk = np.arange(ti.size) if nchk is None else synth.sample_indices(ti.size, nchk, seed=786)
+            ref = oracle.attraction(wl, ti[chk], threads=threads)
+            e_f = np.abs(u.cpu().numpy()[ti[chk]].astype(np.float64) - ref) / ref
+            e_d = np.abs(ud.cpu().numpy()[chk].astype(np.float64) - ref) / ref
+            row.update({"targets_checked": int(chk.size), "fmm_max_rel_err": float(e_f.max()),
+                        "direct_max_rel_err": float(e_d.max()), "pass": bool(max(e_f.max(), e_d.max()) <= 1e-4)})
+        out[name] = row
+        tree.close()
+    wl = synth.sources_targets_1m()
+    x, y, z, w, tg = T(wl.x), T(wl.y), T(wl.z), T(wl.w), T((wl.a > 0).astype(np.uint8))
+    g = T(wl.extra["g"])
+    tree = msp.Tree()
+    u = torch.empty(wl.n, dtype=torch.float32, device=dev)
+    res = {}
+
+    def fb():
+        tree.build(x, y, z, leaf_max=wl.leaf_max)
+        tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u)
+        res.update(tree.backward(w, g, tg, sigma=wl.sigma, p=wl.p))
+    ms_fb = _timed(fb, args.steps)
+    row = {"n": wl.n, "targets": int((wl.a > 0).sum()), "sources": int((wl.w > 0).sum()),
+           "route": tree.plan(wl.sigma, p=wl.p)["route"], "fwd_bwd_ms_incl_tree": ms_fb,
+           "gradients": "weights, positions, sigma"}
+    if not args.no_check:
+        import oracle
+        ti = np.nonzero(wl.a > 0)[0]
+        si = np.nonzero(wl.w > 0)[0]
+        chk = ti[synth.sample_indices(ti.size, 4096, seed=787)]
+        ref = oracle.attraction(wl, chk, threads=threads)
+        e_f = np.abs(u.cpu().numpy()[chk].astype(np.float64) - ref) / ref
+        sw = si[synth.sample_indices(si.size, 256, seed=788)]
+        pos = wl.pos64()
+        gh = wl.extra["g"].astype(np.float64)
+        rw = oracle.gauss_grad(pos[ti], gh[ti], pos[sw], wl.w[sw], wl.sigma, want=("w",), threads=threads)["w"]
+        e_w = np.abs(res["w"].cpu().numpy()[sw].astype(np.float64) - rw) / rw
+        row.update({"forward_targets_checked": int(chk.size), "forward_max_rel_err": float(e_f.max()),
+                    "grad_w_points_checked": int(sw.size), "grad_w_max_rel_err": float(e_w.max()),
+                    "pass": bool(max(e_f.max(), e_w.max()) <= 1e-4)})
+    out["sources_targets_1m"] = row
+    tree.close()
+    return out
+
+
 def _batch_bench(args, dev, oracle_threads):
     """256 independent populations (sizes log-uniform in [1024, 65536], sigma
     log-uniform in [50, 300] um, each in its own 1 mm cube): autotuned leaf size
@@ -230,11 +318,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget for the oracle sample, from a short probe (which overestimates)")
     ap.add_argument("--queries", type=int, default=65536, help="partner queries per step")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-population batch")
     ap.add_argument("--no-descent", action="store_true", help="skip the partner descent")
+    ap.add_argument("--no-configs", action="store_true", help="skip the cube, blob and gradient workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three copies of 1 GiB (counter calibration runs)")
     args = ap.parse_args()
@@ -418,24 +507,98 @@ def main():
                        "m2l_fp32_mfma_ms": m2l_ms["mfma"]},
     }
 
-    sample = None
+    # p sweep of the transform (tree cached), fp32 and split-bf16 translation
+    sweep = {}
+    for p in (4, 6, 8, 10):
+        for mode in ("mfma", "bf16x3"):
+            us = torch.empty_like(u)
+            tree.forward(w, tgt, sigma=wl.sigma, p=p, route="fgt", out=us, m2l=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                tree.forward(w, tgt, sigma=wl.sigma, p=p, route="fgt", out=us, m2l=mode)
+            torch.cuda.synchronize()
+            ms_p = 1000.0 * (time.perf_counter() - t0) / args.steps
+            pl_p = tree.plan(wl.sigma, p=p, route="fgt")
+            sweep[f"p{p}_{mode}"] = {"p": p, "m2l": mode, "level": pl_p["level"], "grid": pl_p["grid"],
+                                     "forward_only_ms": ms_p, "sums_per_s": n_tgt / (ms_p / 1000.0),
+                                     "_u": us.cpu().numpy()}
+    result["p_sweep"] = sweep
+
+    threads = min(16, len(os.sched_getaffinity(0)))
     if not args.no_check or not args.no_cpu:
-        tgt_idx = np.nonzero(wl.a > 0)[0]
-    if not args.no_check:
         import oracle
-        sample = tgt_idx[synth.sample_indices(tgt_idx.size, 256, seed=777)]
-        print("bench: oracle check on 256 sampled targets", file=sys.stderr, flush=True)
-        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
-        got = u.cpu().numpy()[sample].astype(np.float64)
-        ref = oracle.attraction(wl, sample, threads=min(16, len(os.sched_getaffinity(0))))
-        rel = np.abs(got - ref) / ref
-        result["accuracy"] = {"targets_checked": int(sample.size), "max_rel_err": float(rel.max()),
-                              "p50_rel_err": float(np.median(rel)), "bar": 1e-4,
-                              "pass": bool(rel.max() <= 1e-4)}
-        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l="bf16x3")
-        relb = np.abs(ub.cpu().numpy()[sample].astype(np.float64) - ref) / ref
-        result["m2l_bf16x3"].update({"max_rel_err": float(relb.max()),
-                                     "p50_rel_err": float(np.median(relb))})
+        ti = np.nonzero(wl.a > 0)[0]
+        # accuracy sample: 65,536 seeded targets, every target within one p = 8 cell of
+        # a corner of the slab, and 8,192 targets within that reach of an x or y face
+        groups = {"uniform": ti[synth.sample_indices(ti.size, min(65536, ti.size), seed=303)]}
+        reach = float(max(np.ptp(wl.x), np.ptp(wl.y), np.ptp(wl.z))) / 16.0
+        groups.update(synth.boundary_sample(wl, ti, reach, 8192, seed=304))
+        sel = np.unique(np.concatenate(list(groups.values())))
+        order = sel[np.random.default_rng(785).permutation(sel.size)]
+        ref_of = {}
+        if not args.no_cpu:
+            # the oracle as it stands, timed on a seeded part of the accuracy sample with
+            # every host thread, then on one thread
+            probe = order[:4 * threads]
+            t0 = time.perf_counter()
+            oracle.attraction(wl, probe, threads=threads)
+            per = (time.perf_counter() - t0) / probe.size
+            k = int(max(4 * threads, min(sel.size, args.cpu_seconds / max(per, 1e-9))))
+            chunk = order[:k]
+            print(f"bench: oracle on {k} targets x {n_src} sources, {threads} threads", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            r = oracle.attraction(wl, chunk, threads=threads)
+            dt = time.perf_counter() - t0
+            ref_of.update(zip(chunk.tolist(), r.tolist()))
+            k1 = int(max(4, min(k, 0.25 * args.cpu_seconds / max(per * threads, 1e-9))))
+            print(f"bench: oracle on {k1} targets, 1 thread", file=sys.stderr, flush=True)
+            t1 = time.perf_counter()
+            oracle.attraction(wl, order[:k1], threads=1)
+            dt1 = time.perf_counter() - t1
+            model = ""
+            try:
+                for line in open("/proc/cpuinfo"):
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+            except OSError:
+                pass
+            result["cpu_baseline"] = {
+                "value": k / dt, "unit": "sums/s", "cores": threads, "kind": "oracle",
+                "sample": f"{k} seeded targets of the slab (from the accuracy sample), each summed over "
+                          f"all {n_src} sources in FP64 ({dt:.1f} s on {threads} threads)",
+                "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
+                "single_thread": {"value": k1 / dt1, "unit": "sums/s", "cores": 1,
+                                  "sample": f"the first {k1} targets of that sample ({dt1:.1f} s)"}}
+        if not args.no_check:
+            rest = np.array([i for i in order.tolist() if i not in ref_of], dtype=np.int64)
+            print(f"bench: oracle reference at {rest.size} more targets", file=sys.stderr, flush=True)
+            if rest.size:
+                ref_of.update(zip(rest.tolist(), oracle.attraction(wl, rest, threads=threads).tolist()))
+            ref = np.array([ref_of[i] for i in sel.tolist()])
+            where = {g: np.searchsorted(sel, idx) for g, idx in groups.items()}
+
+            def acc(uu):
+                rel = np.abs(uu[sel].astype(np.float64) - ref) / ref
+                out = {"targets_checked": int(sel.size), "max_rel_err": float(rel.max()),
+                       "p99_rel_err": float(np.quantile(rel, 0.99)), "p50_rel_err": float(np.median(rel)),
+                       "bar": 1e-4, "pass": bool(rel.max() <= 1e-4)}
+                for g, ix in where.items():
+                    out[g] = {"targets": int(ix.size), "max_rel_err": float(rel[ix].max()),
+                              "p99_rel_err": float(np.quantile(rel[ix], 0.99))}
+                return out
+            tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u)
+            result["accuracy"] = acc(u.cpu().numpy())
+            result["accuracy"]["sample"] = ("65,536 seeded targets, every target within 625 um of a corner of "
+                                            "the slab, 8,192 seeded targets within 625 um of an x or y face")
+            tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=ub, m2l="bf16x3")
+            result["m2l_bf16x3"]["accuracy"] = acc(ub.cpu().numpy())
+            for key, row in sweep.items():
+                a = acc(row["_u"])
+                row["max_rel_err"], row["p99_rel_err"], row["pass"] = a["max_rel_err"], a["p99_rel_err"], a["pass"]
+    for row in sweep.values():
+        row.pop("_u", None)
 
     if not args.no_direct:
         print("bench: all-pairs GPU direct sum on sampled targets", file=sys.stderr, flush=True)
@@ -457,26 +620,10 @@ def main():
                                 "speedup_fmm_incl_tree": value / dsum,
                                 "speedup_fmm_cached_tree": result["forward_only_sums_per_s"] / dsum}
 
-    if not args.no_cpu:
-        import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
-        ti = np.nonzero(wl.a > 0)[0]
-        # the probe keeps every thread busy, so its rate is the sample's rate
-        probe = ti[synth.sample_indices(ti.size, 8 * threads, seed=779)]
-        oracle.attraction(wl, probe[:threads], threads=threads)
-        t0 = time.perf_counter()
-        oracle.attraction(wl, probe, threads=threads)
-        per = (time.perf_counter() - t0) / probe.size
-        k = int(max(4, min(ti.size, args.cpu_seconds / max(per, 1e-9))))
-        cs = ti[synth.sample_indices(ti.size, k, seed=780)]
-        print(f"bench: oracle on {k} targets x {n_src} sources, {threads} threads", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        oracle.attraction(wl, cs, threads=threads)
-        dt = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": k / dt, "unit": "sums/s", "cores": threads, "kind": "oracle",
-                                  "sample": f"{k} seeded targets of the slab, each summed over all "
-                                            f"{n_src} sources in FP64 ({dt:.1f} s)"}
     tree.close()
+    if not args.no_configs:
+        print("bench: the other workloads (cube 4k, blobs 262k, gradients 1M + 1M)", file=sys.stderr, flush=True)
+        result["other_workloads"] = _other_configs(args, dev, threads)
     if not args.no_batch:
         print("bench: 256-population batch", file=sys.stderr, flush=True)
         result["batch"] = _batch_bench(args, dev, min(16, len(os.sched_getaffinity(0))))

@@ -178,3 +178,22 @@ def uniforms(k: int, seed: int) -> np.ndarray:
     """k float32 draws from [0, 1) for proportional child choice."""
     rng = np.random.default_rng(np.random.PCG64(seed))
     return rng.random(k, dtype=np.float32)
+
+
+def boundary_sample(wl: Workload, targets: np.ndarray, reach: float, k_face: int, seed: int) -> dict:
+    """Targets near the edges of the point cloud's bounding box, where the sums
+    are smallest: every target within `reach` of one of the box's eight corners,
+    and k_face targets (seeded) among the others within `reach` of an x or y face.
+    Returns {"corner": indices, "face": indices} (input indices, sorted)."""
+    pos = np.stack([wl.x, wl.y, wl.z], axis=1).astype(np.float64)[targets]
+    lo = np.array([wl.x.min(), wl.y.min(), wl.z.min()], np.float64)
+    hi = np.array([wl.x.max(), wl.y.max(), wl.z.max()], np.float64)
+    corner = np.zeros(targets.size, bool)
+    for c in range(8):
+        vert = np.where([(c >> 2) & 1, (c >> 1) & 1, c & 1], hi, lo)
+        corner |= np.sum((pos - vert) ** 2, axis=1) <= reach * reach
+    edge = np.minimum(np.minimum(pos[:, 0] - lo[0], hi[0] - pos[:, 0]),
+                      np.minimum(pos[:, 1] - lo[1], hi[1] - pos[:, 1]))
+    face_pool = np.nonzero((edge <= reach) & ~corner)[0]
+    face = face_pool[sample_indices(face_pool.size, k_face, seed)]
+    return {"corner": np.sort(targets[corner]), "face": np.sort(targets[face])}

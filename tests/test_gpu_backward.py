@@ -46,6 +46,8 @@ def _check(wl, g, route, sample, full_sigma, p=8):
     u = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, p=p, route=route, cutoff_sigmas=0.0).cpu().numpy()
     scale = 2.0 / wl.sigma * (g[sample] * (wl.a[sample] > 0) * u[sample] + wl.w[sample] * ref["w"])
     err = np.max(np.abs(gp - ref["pos"]), axis=1)
+    print(f"  weights: max rel err {np.max(np.abs(gw - ref['w']) / np.abs(ref['w'])):.2e}; positions: max "
+          f"err / term scale {np.max(err / np.maximum(scale, 1e-300)):.2e}", flush=True)
     ok = err <= 5e-4 * scale + 1e-12
     assert np.all(ok), (err[~ok][:5], scale[~ok][:5])
     if full_sigma:
@@ -66,13 +68,65 @@ def test_backward_small_full_sigma(route):
 
 
 def test_backward_full_size_subset():
-    """1,048,576 sources + 1,048,576 targets; derivatives checked on a 4,096-point subset."""
+    """1,048,576 sources + 1,048,576 targets; derivatives checked on a 4,096-point
+    subset, and the sigma derivative of L restricted to 4,096 sampled targets (all
+    1,048,576 sources) against the oracle's direct sum."""
+    import torch
+    import paper_2301_10570_amd as msp
     wl = synth.sources_targets_1m()
     g = wl.extra["g"].astype(np.float64)
     sample = synth.sample_indices(wl.n, 4096, seed=405)
     print("backward 2M points, subset of 4096", flush=True)
     plan = _check(wl, g, "auto", sample, full_sigma=False)
     assert plan["route"] == "fgt"
+    tgt = np.nonzero(wl.a > 0)[0]
+    S = tgt[synth.sample_indices(tgt.size, 4096, seed=407)]
+    gS = np.zeros(wl.n)
+    gS[S] = g[S]
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    res = tree.backward(d["w"], torch.from_numpy(gS.astype(np.float32)).cuda(), d["tgt"], sigma=wl.sigma,
+                        cutoff_sigmas=0.0, want=("sigma",))
+    pos = wl.pos64()
+    src = np.nonzero(wl.w > 0)[0]
+    ref = oracle.gauss_grad(pos[S], gS[S], pos[src], wl.w[src], wl.sigma, want=("sigma",))["sigma"]
+    gs = float(res["sigma"].cpu().numpy()[0])
+    print(f"  sigma derivative over 4,096 targets x all sources: rel err {abs(gs - ref) / abs(ref):.2e}")
+    assert abs(gs - ref) <= 1e-4 * abs(ref)
+
+
+@pytest.mark.parametrize("route", ["fgt", "direct"])
+def test_backward_sigma_subproblem(route):
+    """The gradient workload's 4,096 x 4,096 sub-problem (seeded sources and targets
+    of the 2 mm cube, sigma 200 um): every derivative against the oracle, and the
+    sigma derivative also against a central difference of the oracle's whole L."""
+    import torch
+    import paper_2301_10570_amd as msp
+    full = synth.sources_targets_1m()
+    m = full.n // 2
+    si = synth.sample_indices(m, 4096, seed=408)
+    ti = m + synth.sample_indices(m, 4096, seed=409)
+    idx = np.concatenate([si, ti])
+    wl = synth.Workload("sub4096", full.x[idx].copy(), full.y[idx].copy(), full.z[idx].copy(),
+                        full.a[idx].copy(), full.w[idx].copy(), full.sigma)
+    g = full.extra["g"][idx].astype(np.float64)
+    print(f"sigma sub-problem 4,096 x 4,096, route={route}", flush=True)
+    plan = _check(wl, g, route, np.arange(wl.n), full_sigma=True)
+    print(f"  plan {plan}")
+    # central difference of L(sigma) = sum_i g_i u_i(sigma) by the oracle
+    pos = wl.pos64()
+    tg = np.nonzero(wl.a > 0)[0]
+    src = np.nonzero(wl.w > 0)[0]
+    h = 1e-3 * wl.sigma
+    L = lambda s: float(np.dot(g[tg], oracle.gauss_sum(pos[tg], pos[src], wl.w[src], s)))
+    fd = (L(wl.sigma + h) - L(wl.sigma - h)) / (2 * h)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    res = tree.backward(d["w"], torch.from_numpy(g.astype(np.float32)).cuda(), d["tgt"], sigma=wl.sigma,
+                        route=route, cutoff_sigmas=0.0, want=("sigma",))
+    gs = float(res["sigma"].cpu().numpy()[0])
+    print(f"  dL/dsigma {gs:.8e}, central difference {fd:.8e}, rel diff {abs(gs - fd) / abs(fd):.2e}")
+    assert abs(gs - fd) <= 1e-4 * abs(fd)
 
 
 def test_backward_signed_g_and_union_points():

@@ -109,6 +109,7 @@ def test_batch_backward_equals_single_trees(pops):
     b = msp.Batch().build(x, y, z, off)
     g = torch.from_numpy(synth.uniforms(x.numel(), 901) + np.float32(0.5)).cuda()
     got = b.backward(w, g, sig, is_target=tg)
+    u_all = b.forward(w, sig, is_target=tg, use_graph=False).cpu().numpy()
     routes = []
     for k, wl in enumerate(sub):
         lo, hi = off[k], off[k + 1]
@@ -130,6 +131,26 @@ def test_batch_backward_equals_single_trees(pops):
                 r = rv.cpu().numpy()
                 np.testing.assert_allclose(gv.cpu().numpy(), r, rtol=1e-4, atol=1e-5 * np.abs(r).max())
             assert abs(got["sigma"][k].item() - ref["sigma"].item()) <= 1e-4 * abs(ref["sigma"].item())
+        # against the oracle: weight and position derivatives at 64 seeded points of
+        # the population, and its sigma derivative over all pairs
+        smp = synth.sample_indices(wl.n, 64, seed=910 + k)
+        gk = g[lo:hi].cpu().numpy().astype(np.float64)
+        pos = wl.pos64()
+        tgt = np.nonzero(wl.a > 0)[0]
+        d_src = oracle.gauss_grad(pos[tgt], gk[tgt], pos[smp], wl.w[smp], wl.sigma, want=("w", "s"))
+        st = smp[wl.a[smp] > 0]
+        d_tgt = oracle.gauss_grad(pos[st], gk[st], pos, wl.w, wl.sigma, want=("t",))
+        sig_ref = oracle.gauss_grad(pos[tgt], gk[tgt], pos, wl.w, wl.sigma, want=("sigma",))["sigma"]
+        gpos_ref = d_src["s"].copy()
+        gpos_ref[np.searchsorted(smp, st)] += d_tgt["t"]
+        gw_b = got["w"][lo:hi].cpu().numpy()[smp]
+        assert np.max(np.abs(gw_b - d_src["w"]) / d_src["w"]) <= TOL, k
+        gp_b = np.stack([got["pos"][a][lo:hi].cpu().numpy()[smp] for a in range(3)], 1)
+        u_b = u_all[lo:hi][smp]
+        scale = 2.0 / wl.sigma * (gk[smp] * (wl.a[smp] > 0) * u_b + wl.w[smp] * d_src["w"])
+        perr = np.max(np.abs(gp_b - gpos_ref), axis=1)
+        assert np.all(perr <= 5e-4 * scale + 1e-12), k
+        assert abs(got["sigma"][k].item() - sig_ref) <= TOL * abs(sig_ref), k
     print(f"  routes: {routes}")
     assert "fgt" in routes and "direct" in routes   # both paths of the batched backward are exercised
     # the second call with the same arguments replays the captured graph

@@ -58,7 +58,12 @@ def _check(wl, tq, nq, seed, cutoff=0.0, exclude_self=False, p=8):
     # defined probabilities in the oracle; compare the rest
     live = Sr.sum(axis=1) > 0
     err = np.abs(P - Pr)[live]
-    assert np.all(err <= 1e-4 * Pr[live] + 1e-6), (err.max(), np.argmax(err))
+    # 1e-4 relative per child, with an absolute floor of 1e-7 of the query's total
+    # (the accuracy contract of the moments: M2P where its error is below 1e-7 of
+    # the running total)
+    bound = 1e-4 * Pr[live] + 1e-7
+    print(f"  max |dP| {err.max():.2e}, max |dP| / bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound), (err.max(), np.argmax(err))
     # choices agree unless r*total sits within 1e-4*total of a running-sum boundary
     run = np.cumsum(Sr, axis=1)
     tot = run[:, -1:]
