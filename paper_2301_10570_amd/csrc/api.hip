@@ -115,6 +115,8 @@ static int check_device() {
     return MSP_OK;
 }
 
+static bool misaligned(const void *p) { return ((uintptr_t)p & 255) != 0; }
+
 static int check_params(const msp_fgt_params *prm) {
     if (!prm) return fail(MSP_EINVAL, "params is NULL");
     if (prm->p < 1 || prm->p > kMaxP) return fail(MSP_EINVAL, "p = %d outside 1..%d", prm->p, kMaxP);
@@ -198,8 +200,6 @@ int msp_octree_build_query(int64_t n, int32_t leaf_max, int32_t max_depth, size_
     build_query_bytes(n, leaf_max, max_depth, tree_bytes, ws_bytes);
     return MSP_OK;
 }
-
-static bool misaligned(const void *p) { return ((uintptr_t)p & 255) != 0; }
 
 int msp_octree_build_ws(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
                         int32_t leaf_max, int32_t max_depth, void *tree_buf, size_t tree_bytes, void *ws,
@@ -327,28 +327,27 @@ extern "C" {
 
 int msp_fgt_forward_query(msp_tree *t, const msp_fgt_params *prm, size_t *ws_bytes, void *stream) {
     g_err[0] = 0;
-    if (!t || !ws_bytes) return fail(MSP_EINVAL, "NULL argument");
-    if (!t->built) return fail(MSP_ESTATE, "no tree built");
-    MSP_TRY(check_params(prm));
-    FgtPlan pl;
-    MSP_TRY(plan_fgt(t, prm, &pl));
-    if (pl.route == MSP_ROUTE_DIRECT) MSP_TRY(direct_route_counts(t, prm, (hipStream_t)stream));
-    Carve c(nullptr, 0);
-    forward_layout(t, pl, c, nullptr);
-    *ws_bytes = c.used;
-    return MSP_OK;
+    if (!ws_bytes) return fail(MSP_EINVAL, "NULL size output");
+    return forward_workspace_bytes(t, prm, ws_bytes, (hipStream_t)stream);
 }
 
 int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
                        float *u_out, void *ws, size_t ws_bytes, void *stream) {
     g_err[0] = 0;
+    if (!ws) return fail(MSP_EINVAL, "workspace is NULL");
+    return forward_in_workspace(t, w, is_target, prm, u_out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace msp {
+int forward_in_workspace(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                         float *u_out, void *ws, size_t ws_bytes, hipStream_t s) {
     if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
     if (!t->built) return fail(MSP_ESTATE, "no tree built");
     MSP_TRY(check_params(prm));
     if (t->n > 0 && (!w || !u_out)) return fail(MSP_EINVAL, "NULL weight or output array");
-    if (!ws) return fail(MSP_EINVAL, "workspace is NULL");
     if (misaligned(ws)) return fail(MSP_EINVAL, "workspace must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
     FgtPlan pl;
     MSP_TRY(plan_fgt(t, prm, &pl));
     if (pl.route == MSP_ROUTE_DIRECT) MSP_TRY(direct_route_counts(t, prm, s));
@@ -385,6 +384,22 @@ int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, co
     t->w_staged = true;
     return MSP_OK;
 }
+
+int forward_workspace_bytes(msp_tree *t, const msp_fgt_params *prm, size_t *bytes, hipStream_t s) {
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (!t->built) return fail(MSP_ESTATE, "no tree built");
+    MSP_TRY(check_params(prm));
+    FgtPlan pl;
+    MSP_TRY(plan_fgt(t, prm, &pl));
+    if (pl.route == MSP_ROUTE_DIRECT) MSP_TRY(direct_route_counts(t, prm, s));
+    Carve c(nullptr, 0);
+    forward_layout(t, pl, c, nullptr);
+    *bytes = c.used;
+    return MSP_OK;
+}
+}  // namespace msp
+
+extern "C" {
 
 int msp_fgt_backward(msp_tree *t, const float *w, const uint8_t *is_target,
                      const msp_fgt_params *prm, const float *grad_u, float *grad_w, float *grad_x,

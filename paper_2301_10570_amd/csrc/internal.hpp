@@ -433,6 +433,12 @@ int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *tar
                       const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
                       hipStream_t s);
 
+// api.hip: msp_fgt_forward with every per-call buffer in the workspace ws (checked
+// against the call's need, MSP_ENOSPC if short), and that need in bytes
+int forward_in_workspace(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                         float *u_out, void *ws, size_t ws_bytes, hipStream_t s);
+int forward_workspace_bytes(msp_tree *t, const msp_fgt_params *prm, size_t *bytes, hipStream_t s);
+
 // descent.hip
 int descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
                  int32_t step, const int64_t *S_in, const int64_t *T_in, int64_t m, int64_t *S_out,
