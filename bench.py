@@ -177,14 +177,15 @@ def _other_configs(args, dev, threads):
         si = np.nonzero(wl.w > 0)[0]
         tree = msp.Tree().build(x, y, z, leaf_max=wl.leaf_max)
         u = torch.empty(wl.n, dtype=torch.float32, device=dev)
-        ms_c = _timed(lambda: tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u), args.steps)
+        reps = max(args.steps, 100)   # small launches: enough repetitions for a steady clock
+        ms_c = _timed(lambda: tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u), reps)
         ms_b = _timed(lambda: (tree.build(x, y, z, leaf_max=wl.leaf_max),
-                               tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u)), args.steps)
+                               tree.forward(w, tg, sigma=wl.sigma, p=wl.p, out=u)), reps)
         plan = tree.plan(wl.sigma, p=wl.p)
         dtx, dty, dtz = T(wl.x[ti]), T(wl.y[ti]), T(wl.z[ti])
         dsx, dsy, dsz, dsw = T(wl.x[si]), T(wl.y[si]), T(wl.z[si]), T(wl.w[si])
         ud = torch.empty(ti.size, dtype=torch.float32, device=dev)
-        ms_d = _timed(lambda: msp.direct_sum(dtx, dty, dtz, dsx, dsy, dsz, dsw, wl.sigma, out=ud), args.steps)
+        ms_d = _timed(lambda: msp.direct_sum(dtx, dty, dtz, dsx, dsy, dsz, dsw, wl.sigma, out=ud), reps)
         row = {"n": wl.n, "targets": int(ti.size), "sources": int(si.size), "route": plan["route"],
                "level": plan["level"], "fmm_ms_cached_tree": ms_c, "fmm_ms_incl_tree": ms_b,
                "fmm_sums_per_s_cached_tree": ti.size / (ms_c / 1000.0),
@@ -355,10 +356,10 @@ def main():
     uni = T(synth.uniforms(tq.numel(), 782))
 
     def step():
-        tree.build(x, y, z, leaf_max=wl.leaf_max)
-        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u, stage_weights=True)
+        # the vacant element counts ride into key order with the positions
+        tree.build(x, y, z, leaf_max=wl.leaf_max, w=w)
+        tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u, weights_staged=True)
         if tq.numel():
-            # the same counts as the forward: its P2M already gathered w into key order
             tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
 
     print("bench: warmup", file=sys.stderr, flush=True)
@@ -540,11 +541,12 @@ def main():
         if not args.no_cpu:
             # the oracle as it stands, timed on a seeded part of the accuracy sample with
             # every host thread, then on one thread
-            probe = order[:4 * threads]
+            oracle.attraction(wl, order[:threads], threads=threads)   # threads started, pages touched
+            probe = order[:8 * threads]
             t0 = time.perf_counter()
             oracle.attraction(wl, probe, threads=threads)
             per = (time.perf_counter() - t0) / probe.size
-            k = int(max(4 * threads, min(sel.size, args.cpu_seconds / max(per, 1e-9))))
+            k = int(max(8 * threads, min(sel.size, args.cpu_seconds / max(per, 1e-9))))
             chunk = order[:k]
             print(f"bench: oracle on {k} targets x {n_src} sources, {threads} threads", file=sys.stderr, flush=True)
             t0 = time.perf_counter()

@@ -81,15 +81,17 @@ enum msp_flags {
      * lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi is accumulated in float32
      * (about 2^-16 of each product is lost).  Exclusive with MSP_M2L_VALU. */
     MSP_M2L_BF16X3 = 1u << 3,
-    /* For msp_partner_probabilities: `w` is the weight array of the last
-     * msp_fgt_forward (on the direct route, or with MSP_STAGE_WEIGHTS),
-     * msp_partner_probabilities or msp_partner_descent call on this tree,
-     * unchanged since (an MSP step evaluates the sums and then the partner
-     * probabilities with the same vacant element counts).  The weights that call
-     * gathered into key order are used again instead of being gathered a second
-     * time.  MSP_ESTATE if no such call has gathered weights since the tree was
-     * built or since a backward call (which gathers other weights), or if the
-     * last forward did not keep them; the contents of `w` are not checked. */
+    /* For msp_fgt_forward (and msp_fgt_forward_ws) and
+     * msp_partner_probabilities: `w` equals the weights the tree already holds in
+     * key order, from msp_octree_build_weighted or from the last msp_fgt_forward
+     * (on the direct route, or with MSP_STAGE_WEIGHTS), msp_partner_probabilities
+     * or msp_partner_descent call on this tree (an MSP step evaluates the sums and
+     * then the partner probabilities with the same vacant element counts).  Those
+     * weights are used instead of gathering `w` through the permutation again (the
+     * expansion route still reads `w` in input order for MSP_EXCLUDE_SELF).
+     * MSP_ESTATE if the tree holds no such weights (none staged since the build,
+     * or a backward call since, which stages other weights); the contents of `w`
+     * are not checked. */
     MSP_WEIGHTS_STAGED = 1u << 4,
     /* For msp_fgt_forward on the expansion route: keep the weights its P2M
      * gathers into key order for a following MSP_WEIGHTS_STAGED call (the extra
@@ -174,6 +176,15 @@ void msp_tree_destroy(msp_tree *t);
 int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z, int64_t n,
                      int32_t leaf_max, int32_t max_depth, void *stream);
 
+/* msp_octree_build, with the weights w (device float32[n], input order) carried
+ * into key order beside the positions by the same passes (one more coalesced
+ * 4-byte read per point), so that a following msp_fgt_forward or
+ * msp_partner_probabilities with MSP_WEIGHTS_STAGED and the same w needs no
+ * gather of the weights through the permutation: the MSP step when positions and
+ * vacant element counts both changed since the last one. */
+int msp_octree_build_weighted(msp_tree *t, const float *x, const float *y, const float *z, const float *w,
+                              int64_t n, int32_t leaf_max, int32_t max_depth, void *stream);
+
 /* Sizes (host outputs, bytes) of the caller buffers of msp_octree_build_ws for n
  * points: tree_bytes for the arrays the tree keeps (sorted keys, permutation,
  * packed positions in key and in input order, inverse permutation, level offsets,
@@ -243,7 +254,6 @@ int msp_fgt_forward_query(msp_tree *t, const msp_fgt_params *prm, size_t *ws_byt
  * recounted. */
 int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
                        float *u_out, void *ws, size_t ws_bytes, void *stream);
-
 /* Derivatives of L = sum_i g_i u(t_i) over the targets i (the adjoint of
  * msp_fgt_forward with the same w, is_target and params).  With
  * K = exp(-|t - s|^2/sigma^2) and v(x) = sum_i g_i K(t_i, x) (the transposed sum,

@@ -78,6 +78,7 @@ _lib.msp_tree_destroy.argtypes = [_vp]
 _lib.msp_tree_destroy.restype = None
 _lib.msp_octree_build.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp]
 _sz = ctypes.c_size_t
+_lib.msp_octree_build_weighted.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp]
 _lib.msp_octree_build_query.argtypes = [_i64, _i32, _i32, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]
 _lib.msp_octree_build_ws.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz, _vp, _sz, _vp]
 _lib.msp_fgt_forward_query.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(_sz), _vp]
@@ -112,7 +113,7 @@ _lib.msp_batch_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams
 _lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
 _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
-for _f in ("msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
+for _f in ("msp_octree_build_weighted", "msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
            "msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_descent_step", "msp_partner_descent",
@@ -183,11 +184,18 @@ class Tree:
     def handle(self):
         return self._h
 
-    def build(self, x, y, z, leaf_max=64, max_depth=21):
+    def build(self, x, y, z, leaf_max=64, max_depth=21, w=None):
+        """Build the octree; with w, carry the weights into key order as well
+        (msp_octree_build_weighted) for calls with weights_staged=True."""
         n = x.numel()
         px, py, pz = (_ptr(v, torch.float32, n, nm) for v, nm in ((x, "x"), (y, "y"), (z, "z")))
-        _check(_lib.msp_octree_build(self._h, px, py, pz, n, int(leaf_max), int(max_depth), _stream()),
-               "msp_octree_build")
+        if w is None:
+            _check(_lib.msp_octree_build(self._h, px, py, pz, n, int(leaf_max), int(max_depth), _stream()),
+                   "msp_octree_build")
+        else:
+            pw = _ptr(w, torch.float32, n, "w")
+            _check(_lib.msp_octree_build_weighted(self._h, px, py, pz, pw, n, int(leaf_max), int(max_depth),
+                                                  _stream()), "msp_octree_build_weighted")
         self.n = n
         self._keep = (x, y, z)
         return self
@@ -263,10 +271,13 @@ class Tree:
                 "fine_terms": inf.fine_terms}
 
     def forward(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
-                exclude_self=False, out=None, m2l="mfma", two_level=False, stage_weights=False):
+                exclude_self=False, out=None, m2l="mfma", two_level=False, stage_weights=False,
+                weights_staged=False):
         """u[i] = sum_j w[j] exp(-|x_i - x_j|^2/sigma^2) for targets, 0 elsewhere.
         stage_weights: keep the weights gathered into key order for a following
-        partner_probabilities(..., weights_staged=True) (MSP_STAGE_WEIGHTS)."""
+        partner_probabilities(..., weights_staged=True) (MSP_STAGE_WEIGHTS).
+        weights_staged: w equals the weights the tree already holds in key order
+        (build(..., w=w), or an earlier call that kept them; MSP_WEIGHTS_STAGED)."""
         n = self.n
         pw = _ptr(w, torch.float32, n, "w")
         pt = _ptr(is_target, torch.uint8, n, "is_target")
@@ -276,6 +287,8 @@ class Tree:
         prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
         if stage_weights:
             prm.flags |= STAGE_WEIGHTS
+        if weights_staged:
+            prm.flags |= WEIGHTS_STAGED
         _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
         return out
 

@@ -117,6 +117,15 @@ static int check_device() {
 
 static bool misaligned(const void *p) { return ((uintptr_t)p & 255) != 0; }
 
+// MSP_WEIGHTS_STAGED needs weights in the sorted records: from a weighted build,
+// or kept by an earlier call since the build (and no backward since)
+static int check_staged(const msp_tree *t, const msp_fgt_params *prm) {
+    if ((prm->flags & MSP_WEIGHTS_STAGED) && !t->w_staged)
+        return fail(MSP_ESTATE, "MSP_WEIGHTS_STAGED: the tree holds no staged weights (weighted build, or a "
+                    "forward with MSP_STAGE_WEIGHTS, since the build or the last backward)");
+    return MSP_OK;
+}
+
 static int check_params(const msp_fgt_params *prm) {
     if (!prm) return fail(MSP_EINVAL, "params is NULL");
     if (prm->p < 1 || prm->p > kMaxP) return fail(MSP_EINVAL, "p = %d outside 1..%d", prm->p, kMaxP);
@@ -187,6 +196,18 @@ int msp_octree_build(msp_tree *t, const float *x, const float *y, const float *z
     if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
     if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
     return build_tree(t, x, y, z, n, leaf_max, max_depth, (hipStream_t)stream);
+}
+
+int msp_octree_build_weighted(msp_tree *t, const float *x, const float *y, const float *z, const float *w,
+                              int64_t n, int32_t leaf_max, int32_t max_depth, void *stream) {
+    g_err[0] = 0;
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (n < 0) return fail(MSP_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "n = %lld exceeds 2^31-1", (long long)n);
+    if (n > 0 && (!x || !y || !z || !w)) return fail(MSP_EINVAL, "NULL coordinate or weight array");
+    if (leaf_max < 1) return fail(MSP_EINVAL, "leaf_max = %d < 1", leaf_max);
+    if (max_depth < 0 || max_depth > kDepth) return fail(MSP_EINVAL, "max_depth = %d outside 0..21", max_depth);
+    return build_tree(t, x, y, z, n, leaf_max, max_depth, (hipStream_t)stream, nullptr, 0, nullptr, 0, w);
 }
 
 int msp_octree_build_query(int64_t n, int32_t leaf_max, int32_t max_depth, size_t *tree_bytes,
@@ -281,11 +302,14 @@ int msp_fgt_forward(msp_tree *t, const float *w, const uint8_t *is_target,
     hipStream_t s = (hipStream_t)stream;
     FgtPlan pl;
     MSP_TRY(plan_fgt(t, prm, &pl));
+    MSP_TRY(check_staged(t, prm));
     t->w_staged = false;   // set again by the paths that gather w into ps.w
     if (pl.route == MSP_ROUTE_FGT) {
         const int rc = fgt_forward_grid(t, pl, prm, w, is_target, u_out, s);
-        // the single-level P2M gathers w into ps.w when asked to keep it
-        t->w_staged = rc == MSP_OK && pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS);
+        // the records keep staged weights; the single-level P2M gathers w into them
+        // when asked to
+        t->w_staged = rc == MSP_OK && ((prm->flags & MSP_WEIGHTS_STAGED) ||
+                                       (pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS)));
         return rc;
     }
     MSP_TRY(stage_inputs(t, w, is_target, s));
@@ -358,6 +382,7 @@ int forward_in_workspace(msp_tree *t, const float *w, const uint8_t *is_target, 
             return fail(MSP_ENOSPC, "workspace holds %zu bytes, the call needs %zu (msp_fgt_forward_query)",
                         ws_bytes, probe.used);
     }
+    MSP_TRY(check_staged(t, prm));
     t->w_staged = false;
     t->grid_bytes_valid = 0;   // the grids of this call live in the caller's workspace
     Carve c(ws, ws_bytes);
@@ -374,7 +399,8 @@ int forward_in_workspace(msp_tree *t, const float *w, const uint8_t *is_target, 
         t->ops_valid = ops_valid;
         std::copy(ops_sig, ops_sig + 5, t->ops_sig);
         t->grid_bytes_valid = 0;
-        t->w_staged = rc == MSP_OK && pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS);
+        t->w_staged = rc == MSP_OK && ((prm->flags & MSP_WEIGHTS_STAGED) ||
+                                       (pl.pf == 0 && (prm->flags & MSP_STAGE_WEIGHTS)));
         return rc;
     }
     MSP_TRY(stage_inputs(t, w, is_target, s));
@@ -439,8 +465,7 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
     if (nq < 0) return fail(MSP_EINVAL, "nq < 0");
     if (nq > 0 && (!w || !target_idx || !node_id || !probs)) return fail(MSP_EINVAL, "NULL array");
     if (nq > 0x7fffffffLL) return fail(MSP_EOVERFLOW, "nq exceeds 2^31-1");
-    if ((prm->flags & MSP_WEIGHTS_STAGED) && !t->w_staged)
-        return fail(MSP_ESTATE, "MSP_WEIGHTS_STAGED: no weights gathered since the tree was built or since a backward call");
+    MSP_TRY(check_staged(t, prm));
     const int rc = partner_probabilities(t, w, prm, target_idx, node_id, nq, uniforms, probs, choice,
                                          (hipStream_t)stream);
     t->w_staged = rc == MSP_OK;

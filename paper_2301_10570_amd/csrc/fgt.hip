@@ -166,7 +166,7 @@ __device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, 
         const int64_t j = c0 + tid;
         if (j < end) {
             const float4 q = ps[j];
-            const float wv = w[perm[j]];
+            const float wv = w ? w[perm[j]] : q.w;   // NULL: the weights are staged in the records
             // the weight in key order, for later calls (whole records: full-line writes)
             if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
         nxt = make_float4(0.f, 0.f, 0.f, 0.f);   // past the cell: zero weight
         if (j < end) {
             const float4 q = ps[j];
-            const float wv = w[perm[j]];
+            const float wv = w ? w[perm[j]] : q.w;   // NULL: the weights are staged in the records
             // the weight in key order, for later calls (whole records: full-line writes)
             if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
             nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
@@ -918,7 +918,7 @@ __global__ void __launch_bounds__(kBlock) k_p2m_2lvl(const uint64_t *keys, int64
                 const float4 q = ps[c0 + lane];
                 stg[lane] = make_float4((float)(((double)q.x - sx) * inv_sigma),
                                         (float)(((double)q.y - sy) * inv_sigma),
-                                        (float)(((double)q.z - sz) * inv_sigma), w[perm[c0 + lane]]);
+                                        (float)(((double)q.z - sz) * inv_sigma), w ? w[perm[c0 + lane]] : q.w);
             }
             wave_sync();
             if (active) {
@@ -1200,7 +1200,8 @@ __global__ void k_scatter(const float *usort, const float4 *ps, const uint8_t *t
 }
 
 struct GridArgs {
-    const float *w;
+    const float *w;          // input order (self term)
+    const float *w_gather;   // gathered by the P2M through the permutation; NULL: staged in ps.w
     const uint8_t *is_target;
     int subtract_self;
     float *u_out;
@@ -1223,7 +1224,7 @@ int launch_2lvl(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, cons
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     if (!l2p)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m_2lvl<P, PF>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
-                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w,
+                           t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w_gather,
                            pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1], t->geo.lo[2],
                            pl.cell, inv_sigma, A);
     else
@@ -1251,13 +1252,13 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
     }
     if (!l2p && P == 8) {
         hipLaunchKernelGGL(k_p2m_mfma8, dim3((unsigned)ncell), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), t->n,
-                           t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2],
+                           t->ps.as<float4>(), t->perm.as<int32_t>(), ga.w_gather, pl.level, pl.G[0], pl.G[1], pl.G[2],
                            t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, A,
                            ga.stage ? t->ps.as<float4>() : nullptr);
     } else if (!l2p) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_p2m<P>), dim3((unsigned)ncell), dim3(kBlock), 0, s,
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
-                           ga.w, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
+                           ga.w_gather, pl.level, pl.G[0], pl.G[1], pl.G[2], t->geo.lo[0], t->geo.lo[1],
                            t->geo.lo[2], pl.cell, inv_sigma, A, ga.stage ? t->ps.as<float4>() : nullptr);
     } else {
         // every point's sum straight to input order, flags and self term afterwards
@@ -2267,8 +2268,9 @@ int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStrea
 
 int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, const float *w,
                      const uint8_t *is_target, float *u_out, hipStream_t s) {
-    const GridArgs ga{w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out,
-                      (prm->flags & MSP_STAGE_WEIGHTS) != 0};
+    const bool staged = (prm->flags & MSP_WEIGHTS_STAGED) != 0;
+    const GridArgs ga{w, staged ? nullptr : w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out,
+                      !staged && (prm->flags & MSP_STAGE_WEIGHTS) != 0};
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     size_t gbytes = 0, obytes = 0;

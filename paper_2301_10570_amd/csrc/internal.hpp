@@ -360,9 +360,10 @@ int batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
 // tree.hip
 // tree_buf == NULL: handle-owned memory; otherwise the tree's arrays go to tree_buf
 // and the build scratch to ws (MSP_ENOSPC when they do not fit)
+// w (or NULL): weights carried into key order with the positions (ps.w)
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
                int max_depth, hipStream_t s, void *tree_buf = nullptr, size_t tree_bytes = 0,
-               void *ws = nullptr, size_t ws_bytes = 0);
+               void *ws = nullptr, size_t ws_bytes = 0, const float *w = nullptr);
 // upper bound on the node count of a tree over n points
 int64_t tree_node_bound(int64_t n, int leaf_max, int max_depth);
 // caller buffer sizes of msp_octree_build_ws

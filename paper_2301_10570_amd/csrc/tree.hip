@@ -148,9 +148,9 @@ __global__ void k_bbox_final(const float *part, int nparts, float *out) {
 // (kTile points, point r * kBlock + t of the tile to thread t), which also counts
 // the tile's digits for the sort's first pass (bits shift .. shift + 7), in the
 // layout k_rs_hist writes.
-__global__ void __launch_bounds__(kBlock) k_morton(const float *x, const float *y, const float *z, int64_t n,
-                                                   const float *box, uint64_t *key, int32_t *idx, float4 *pin,
-                                                   int shift, uint32_t *hist, int nblk) {
+__global__ void __launch_bounds__(kBlock) k_morton(const float *x, const float *y, const float *z,
+                                                   const float *w, int64_t n, const float *box, uint64_t *key,
+                                                   int32_t *idx, float4 *pin, int shift, uint32_t *hist, int nblk) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     double lo[3], side, scale;
@@ -165,7 +165,9 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float *x, const float *
         const uint64_t k = morton3(quantise(a, lo[0], scale), quantise(b, lo[1], scale), quantise(c, lo[2], scale));
         key[i] = k;
         idx[i] = (int32_t)i;
-        pin[i] = make_float4(a, b, c, 0.f);   // packed so that the sorted gather reads one line per point
+        // packed so that the sorted gather reads one line per point; the weight rides
+        // along into key order when the caller gives one
+        pin[i] = make_float4(a, b, c, w ? w[i] : 0.f);
         atomicAdd(&h[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -837,7 +839,7 @@ void build_query_bytes(int64_t n, int leaf_max, int max_depth, size_t *tree_byte
 
 int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int64_t n, int leaf_max,
                int max_depth, hipStream_t s, void *tree_buf, size_t tree_bytes, void *ws,
-               size_t ws_bytes) {
+               size_t ws_bytes, const float *w) {
     t->built = false;
     const bool caller_mem = tree_buf != nullptr;
     Carve tc(tree_buf, tree_bytes);
@@ -919,7 +921,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     auto keys_and_sort = [&](bool full) -> int {
         {
             PhaseScope ps(&t->timing, PH_KEYS, s);
-            hipLaunchKernelGGL(k_morton, dim3(nblk), dim3(kBlock), 0, s, x, y, z, n,
+            hipLaunchKernelGGL(k_morton, dim3(nblk), dim3(kBlock), 0, s, x, y, z, w, n,
                                t->bbox.as<float>() + kBboxParts * 6, t->keys.as<uint64_t>(),
                                t->perm.as<int32_t>(), t->pin.as<float4>(), full ? 0 : kSegShift,
                                t->hist.as<uint32_t>(), nblk);
@@ -1036,6 +1038,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     }
 
     t->built = true;
+    t->w_staged = w != nullptr && n > 0;   // the sorted records carry the weights
     return MSP_OK;
 }
 

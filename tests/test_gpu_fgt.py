@@ -209,3 +209,34 @@ def test_m2l_bf16x3_matches_fp32(p, level):
     print(f"  grid max |dC|/max|C| {dC:.2e}, u max rel diff {du.max():.2e}")
     assert dC <= 2e-4
     assert du.max() <= 5e-5
+
+
+def test_weighted_build_and_staged_forward():
+    """Weights carried into key order by the build (msp_octree_build_weighted): a
+    forward with MSP_WEIGHTS_STAGED gives the bits of a plain forward on every P2M
+    path (matrix-core p = 8, vector p = 6, two-level), on the direct route, and
+    with the self term; without staged weights the flag is refused."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.slab4m(0.125)
+    print("weighted build + staged forward (slab 1/8)", flush=True)
+    d = to_dev(wl)
+    plain = msp.build_tree(d["x"], d["y"], d["z"])
+    staged = msp.Tree().build(d["x"], d["y"], d["z"], w=d["w"])
+    for kw in (dict(p=8, route="fgt"), dict(p=6, route="fgt"), dict(p=8, route="fgt", two_level=True),
+               dict(p=8, route="direct"), dict(p=8, route="fgt", exclude_self=True)):
+        ref = plain.forward(d["w"], d["tgt"], sigma=wl.sigma, **kw).cpu().numpy()
+        got = staged.forward(d["w"], d["tgt"], sigma=wl.sigma, weights_staged=True, **kw).cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), kw
+    # partner probabilities from the staged weights match the plain call
+    tq = torch.arange(0, 64, dtype=torch.int32, device=d["x"].device) * 997
+    nq = torch.zeros(64, dtype=torch.int32, device=d["x"].device)
+    P0, _ = plain.partner_probabilities(d["w"], tq, nq, wl.sigma)
+    P1, _ = staged.partner_probabilities(d["w"], tq, nq, wl.sigma, weights_staged=True)
+    assert torch.equal(P0, P1)
+    # a backward stages other weights; a plain build stages none
+    staged.backward(d["w"], torch.ones_like(d["w"]), d["tgt"], sigma=wl.sigma, want=("w",))
+    for t in (staged, plain.build(d["x"], d["y"], d["z"])):
+        with pytest.raises(msp.MspError) as e:
+            t.forward(d["w"], d["tgt"], sigma=wl.sigma, weights_staged=True)
+        assert e.value.code == msp.MSP_ESTATE

@@ -103,7 +103,9 @@ def test_two_level_passes_vs_oracle():
     that Taylor series to its sub-cell, truncated to fine_terms terms, evaluated by
     the oracle's L2P."""
     import paper_2301_10570_amd as msp
-    wl = synth.uniform_box(20000, extent=(400.0, 200.0, 200.0), sigma=300.0, seed=33)
+    # the root cube's side is the x extent (just under 400 um): y and z stay below
+    # 190 um, inside the first level-1 cell
+    wl = synth.uniform_box(20000, extent=(400.0, 190.0, 190.0), sigma=300.0, seed=33)
     p, level = 8, 1
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
