@@ -81,7 +81,7 @@ enum msp_flags {
      * lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi is accumulated in float32
      * (about 2^-16 of each product is lost).  Exclusive with MSP_M2L_VALU. */
     MSP_M2L_BF16X3 = 1u << 3,
-    /* For msp_fgt_forward (and msp_fgt_forward_ws) and
+    /* For msp_fgt_forward (and its _ws / _noalloc forms) and
      * msp_partner_probabilities: `w` equals the weights the tree already holds in
      * key order, from msp_octree_build_weighted or from the last msp_fgt_forward
      * (on the direct route, or with MSP_STAGE_WEIGHTS), msp_partner_probabilities
@@ -254,6 +254,22 @@ int msp_fgt_forward_query(msp_tree *t, const msp_fgt_params *prm, size_t *ws_byt
  * recounted. */
 int msp_fgt_forward_ws(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
                        float *u_out, void *ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory at all (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): msp_fgt_forward
+ * with its per-call buffers in a fixed 64 MiB device array that the library holds
+ * on every device it runs a call on, from the first such call until the process
+ * ends (no workspace argument, no allocation).  Same arguments and the same bits
+ * as msp_fgt_forward; the tree must live on the current device.  MSP_ENOSPC when
+ * the call needs more than 64 MiB (msp_fgt_forward_query gives the need).  Calls
+ * on one device share that array: calls that overlap in time on one device (other
+ * streams, other host threads) race and must be ordered by the caller.  The array
+ * holds nothing between calls (tables and lists are rebuilt on every call).  The
+ * direct route synchronises `stream` when its list lengths must be recounted
+ * (new sigma or cutoff on this tree): call msp_fgt_forward_query first, outside
+ * any capture. */
+int msp_fgt_forward_noalloc(msp_tree *t, const float *w, const uint8_t *is_target, const msp_fgt_params *prm,
+                            float *u_out, void *stream);
 /* Derivatives of L = sum_i g_i u(t_i) over the targets i (the adjoint of
  * msp_fgt_forward with the same w, is_target and params).  With
  * K = exp(-|t - s|^2/sigma^2) and v(x) = sum_i g_i K(t_i, x) (the transposed sum,

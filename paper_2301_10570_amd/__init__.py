@@ -83,6 +83,7 @@ _lib.msp_octree_build_query.argtypes = [_i64, _i32, _i32, ctypes.POINTER(_sz), c
 _lib.msp_octree_build_ws.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz, _vp, _sz, _vp]
 _lib.msp_fgt_forward_query.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(_sz), _vp]
 _lib.msp_fgt_forward_ws.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _sz, _vp]
+_lib.msp_fgt_forward_noalloc.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp]
 _lib.msp_tree_get_info.argtypes = [_vp, ctypes.POINTER(TreeInfo)]
 _lib.msp_tree_export.argtypes = [_vp, ctypes.POINTER(TreeArrays), _vp]
 _lib.msp_fgt_plan.argtypes = [_vp, ctypes.POINTER(FgtParams), ctypes.POINTER(FgtInfo)]
@@ -114,6 +115,7 @@ _lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
 _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
 for _f in ("msp_octree_build_weighted", "msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
+           "msp_fgt_forward_noalloc",
            "msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_descent_step", "msp_partner_descent",
@@ -239,6 +241,22 @@ class Tree:
             prm.flags |= STAGE_WEIGHTS
         _check(_lib.msp_fgt_forward_ws(self._h, pw, pt, ctypes.byref(prm), po, pws, ws.numel(), _stream()),
                "msp_fgt_forward_ws")
+        return out
+
+    def forward_noalloc(self, w, is_target=None, sigma=100.0, p=8, level=-1, route="auto", cutoff_sigmas=4.5,
+                        exclude_self=False, out=None, m2l="mfma", two_level=False):
+        """forward() without any device allocation by the library: its buffers are the
+        library's fixed per-device scratch (msp_fgt_forward_noalloc).  `out` must be
+        given when the caller cannot allocate either."""
+        n = self.n
+        pw = _ptr(w, torch.float32, n, "w")
+        pt = _ptr(is_target, torch.uint8, n, "is_target")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=w.device)
+        po = _ptr(out, torch.float32, n, "out")
+        prm = _params(sigma, p, level, route, cutoff_sigmas, exclude_self, m2l, two_level)
+        _check(_lib.msp_fgt_forward_noalloc(self._h, pw, pt, ctypes.byref(prm), po, _stream()),
+               "msp_fgt_forward_noalloc")
         return out
 
     def info(self) -> dict:

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmspfmm.so")
 SOURCES = ["api.hip", "tree.hip", "fgt.hip", "p2p.hip", "partner.hip", "backward.hip", "batch.hip",
-           "descent.hip"]
+           "descent.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 
