@@ -34,7 +34,8 @@ KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "so
                    "p2m": "k_p2m_mfma8",
                    "l2p": "k_l2p", "m2l_x": "k_m2l_gemm", "m2l_y": "k_m2l_gemm",
                    "m2l_z": "k_m2l_gemm", "morton": "k_morton", "stage": "k_stage",
-                   "partner": "k_partner", "partner_leafy": "k_partner_leafy"}
+                   "partner": "k_partner", "partner_direct": "k_partner_direct",
+                   "partner_wave": "k_partner_wave"}
 
 
 def _algorithmic(phase, ctx):
@@ -61,7 +62,7 @@ def _algorithmic(phase, ctx):
     if phase == "sort_runs":
         # (key, index) read and written once, positions gathered into key order
         return "hbm", "GB/s", n * (24.0 + 32.0)
-    if phase in ("partner", "partner_leafy"):
+    if phase in ("partner", "partner_direct", "partner_wave"):
         # per query: target, node and uniform in, 8 probabilities and the choice out
         return "hbm", "GB/s", ctx["queries"] * (12.0 + 36.0)
     if phase == "sort_hist":

@@ -668,8 +668,8 @@ const char *msp_phase_name(int phase) {
                                            "m2l_y", "m2l_z", "l2p", "interaction_lists", "p2p",
                                            "scatter", "node_moments", "partner", "direct",
                                            "backward_combine", "sort_hist", "sort_digit_scan",
-                                           "sort_scatter", "node_source_counts", "partner_leafy",
-                                           "sort_runs"};
+                                           "sort_scatter", "node_source_counts", "partner_direct",
+                                           "sort_runs", "partner_wave"};
     if (phase < 0 || phase >= PH_COUNT_) return "";
     return names[phase];
 }

@@ -133,7 +133,7 @@ enum Phase {
     PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
     PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
     PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_SORT_HIST, PH_SORT_SCAN, PH_SORT_SCATTER,
-    PH_NODE_COUNTS, PH_PARTNER_LEAFY, PH_SORT_RUNS, PH_COUNT_
+    PH_NODE_COUNTS, PH_PARTNER_DIRECT, PH_SORT_RUNS, PH_PARTNER_WAVE, PH_COUNT_
 };
 static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 
@@ -165,6 +165,38 @@ struct PhaseScope {
             (void)hipEventRecord(b, s);
             tm->pending.push_back({phase, a, b});
         }
+    }
+};
+
+// A stream forked from a caller's stream and joined back to it (default priority),
+// created on first use.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    SideStream() = default;
+    SideStream(const SideStream &) = delete;
+    SideStream &operator=(const SideStream &) = delete;
+    ~SideStream() {
+        if (stream) (void)hipStreamDestroy(stream);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
+    }
+    // work enqueued on `stream` from here on follows what `s` holds so far
+    int fork(hipStream_t s) {
+        if (!stream) {
+            MSP_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+            MSP_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+            MSP_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+        }
+        MSP_HIP(hipEventRecord(fork_ev, s));
+        MSP_HIP(hipStreamWaitEvent(stream, fork_ev, 0));
+        return MSP_OK;
+    }
+    // work enqueued on `s` from here on follows what `stream` holds so far
+    int join(hipStream_t s) {
+        MSP_HIP(hipEventRecord(join_ev, stream));
+        MSP_HIP(hipStreamWaitEvent(s, join_ev, 0));
+        return MSP_OK;
     }
 };
 
@@ -206,11 +238,12 @@ struct msp_tree {
     bool counts_valid = false;  // list_cnt / list_off / list_total match list_sigma, list_cutoff
     bool lists_valid = false;   // list_idx holds those lists too
     // node moments for partner queries
-    msp::DevBuf nodeA, node_hasA, node_nsrc, partner_done;
+    msp::DevBuf nodeA, node_hasA, node_nsrc;
     msp::DevBuf src_prefix;   // sources before each point in key order, then per-tile offsets
     msp::HostBuf build_stage;  // page-locked readback of the build: level offsets, box, flags
     msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
     msp::DevBuf partner_order; // walk queries by level of the query node (segments), then tallies
+    msp::SideStream side;      // the partner walk runs here, beside the direct passes
     // partner descent: one step's lists (staged in page-locked memory, then one
     // copy), query sums, direct sums and choices; kept for the next descent
     msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_choice;

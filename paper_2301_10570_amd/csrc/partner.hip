@@ -34,8 +34,9 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBlock = 256;
 constexpr int kC1 = 70;                    // Algorithm 2's element threshold
-constexpr int kStack = 2048;                 // walk stack of one query (LDS)
 constexpr int kLaneLeaf = 128;               // leaves up to this size are summed by one lane
+constexpr int kSmallNode = 512;              // nodes up to this size: eight lanes per query sum them
+constexpr int kDirectPoints = 4096;          // nodes up to this size are summed directly (no walk)
 constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
@@ -711,45 +712,41 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
 }
 
 
-// Queries whose node X has only leaf children (none carrying moments, each of at
-// most kLaneLeaf points): eight queries per wavefront, one lane per child, each
-// lane summing its leaf directly.  done[q] tells the general walk which queries
-// are finished here.
+// Queries whose node X holds at most kSmallNode points: the sums over its
+// children straight from the points, in float64 (exact up to rounding), eight
+// queries per wavefront.  The eight lanes of a query read the node's points
+// together (its children's point ranges are consecutive in key order), each
+// point adding to its child's octant.  With a cutoff, children beyond the reach
+// of the query are left out as in the walk.  Queries without children to choose
+// from (a leaf node, an invalid target or node) get zeros and choice -1 here.
 __global__ void __launch_bounds__(256)
-k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
-                int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
-                const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
-                const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
-                double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
-                double sigma, float cutoff2, int unlimited, int exclude_self, float *probs,
-                int32_t *choice, uint8_t *done, double *raw) {
+k_partner_direct(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
+                 int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
+                 const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
+                 const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
+                 double lox, double loy, double loz, double side, const float4 *ps, double sigma,
+                 float cutoff2, int unlimited, int exclude_self, float *probs, int32_t *choice,
+                 double *raw) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t q = g >> 3;
     const int c = (int)(g & 7);
     const int lane = threadIdx.x & 63, gbase = lane & ~7;
-    bool ok = q < nq;
-    int32_t ti = 0, X = 0, nc = 0, fc = 0;
-    if (ok) {
-        ti = target_idx[q];
-        X = node_id[q];
-        ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
-    }
+    if (q >= nq) return;   // (the eight lanes of a query leave together)
+    int32_t ti = target_idx[q], X = node_id[q], nc = 0, fc = 0;
+    bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
     if (ok) {
         nc = nnchild[X];
         fc = nfchild[X];
         ok = nc > 0 && fc > X && fc + nc <= n_nodes;
     }
-    int32_t child = -1;
-    if (ok && c < nc) {
-        child = fc + c;
-        ok = nnchild[child] == 0 && !hasA[child] && ncount[child] <= kLaneLeaf;
+    if (!ok) {
+        probs[q * 8 + c] = 0.f;
+        if (raw) raw[q * 8 + c] = 0.0;
+        if (c == 0 && choice) choice[q] = -1;
+        return;
     }
-    const uint64_t bad = __ballot(!ok);
-    const bool group_ok = ((bad >> gbase) & 0xffull) == 0;
-    if (!group_ok) {
-        if (q < nq && c == 0) done[q] = 0;
-        return;   // the whole group leaves together
-    }
+    if (ncount[X] > kSmallNode) return;   // the wavefront pass or the walk
+    const int32_t child = c < nc ? fc + c : -1;
     const int32_t si = qpos[q];
     const float4 qt = ps[si];
     const double tx = qt.x, ty = qt.y, tz = qt.z;
@@ -875,75 +872,245 @@ k_partner_leafy(int64_t nq, const int32_t *target_idx, const int32_t *node_id, c
             }
             choice[q] = pick;
         }
-        done[q] = 1;
     }
 }
 
-// One wavefront per query (t, X).  The sums over the children of X come from a
-// walk below X that evaluates up to 64 nodes at a time, one per lane, taken
-// from the top of a stack on which every node's children are pushed so that
-// the nearest ends on top.  Decisions compare against R = max(lower bound,
-// total summed so far), which never exceeds the final total; the lower bound
-// comes first, from the chain of nearest nodes below X (each node with moments
-// gives its M2P value minus the rigorous truncation bound, the leaf at the end
-// of the chain its exact sum).  For a node carrying moments:
+// Queries whose node holds more than kSmallNode and at most kDirectPoints
+// points: one wavefront per query sums the node's points directly in float64,
+// each lane every 64th point with four of its records in flight, the partial
+// sums per octant added by shuffles.  Other queries return at once.
+__global__ void __launch_bounds__(256)
+k_partner_wave(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
+               int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
+               const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
+               const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
+               double lox, double loy, double loz, double side, const float4 *ps, double sigma,
+               float cutoff2, int unlimited, int exclude_self, float *probs, int32_t *choice,
+               double *raw) {
+    const int64_t q = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    const int32_t ti = target_idx[q], X = node_id[q];
+    if (!(ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0)) return;
+    const int nc = nnchild[X];
+    const int32_t fc = nfchild[X];
+    if (!(nc > 0 && fc > X && fc + nc <= n_nodes)) return;
+    const int32_t cnt = ncount[X];
+    if (cnt <= kSmallNode || cnt > kDirectPoints) return;
+    const int32_t si = qpos[q];
+    const float4 qt = ps[si];
+    const double tx = qt.x, ty = qt.y, tz = qt.z;
+    const double kexp = 1.4426950408889634 / (sigma * sigma);
+    const int lx = nlevel[X];
+    auto box_d2 = [&](int32_t u) {
+        const double h = side / (double)(1ll << nlevel[u]);
+        const double half = 0.5 * h;
+        const double gx = fmax(fabs(tx - (lox + (nix[u] + 0.5) * h)) - half, 0.0);
+        const double gy = fmax(fabs(ty - (loy + (niy[u] + 0.5) * h)) - half, 0.0);
+        const double gz = fmax(fabs(tz - (loz + (niz[u] + 0.5) * h)) - half, 0.0);
+        return gx * gx + gy * gy + gz * gz;
+    };
+    // child k of lane k: point range end, octant, within reach, node id
+    int32_t uend = 0, cid = -1;
+    int dg = 0, in = 0;
+    if (lane < nc) {
+        cid = fc + lane;
+        uend = nfirst[cid] + ncount[cid];
+        const int shf = nlevel[cid] - lx - 1;
+        dg = (((nix[cid] >> shf) & 1) << 2) | (((niy[cid] >> shf) & 1) << 1) | ((niz[cid] >> shf) & 1);
+        in = 1;
+        if (!unlimited) {
+            const double reach = sqrt(box_d2(X)) + sqrt((double)cutoff2);
+            in = box_d2(cid) <= reach * reach;
+        }
+    }
+    int32_t ce[8];
+    int cd[8], ci[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ce[k] = __shfl(uend, k, 64);
+        cd[k] = __shfl(dg, k, 64);
+        ci[k] = __shfl(in, k, 64);
+    }
+    const int32_t lo = nfirst[X], hi = lo + cnt;
+    double Sd[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
+    int cur = 0;
+    for (int32_t j0 = lo + lane; j0 < hi; j0 += 256) {
+        float4 qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t j = j0 + 64 * u;
+            qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t j = j0 + 64 * u;
+            if (j >= hi) continue;
+            while (cur + 1 < nc && j >= ce[cur]) ++cur;
+            int cin = 0, cdg = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k == cur) {
+                    cin = ci[k];
+                    cdg = cd[k];
+                }
+            const float4 qj = qv[u];
+            if (!cin || qj.w == 0.f || (exclude_self && j == si)) continue;
+            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+            const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+                if (d == cdg) Sd[d] += e;
+        }
+    }
+    double S[8], total = 0.0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        S[d] = wave_sum(Sd[d]);
+        total += S[d];
+    }
+    int32_t cids[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) cids[d] = -1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int32_t ck = __shfl(cid, k, 64);
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            if (ck >= 0 && d == cd[k]) cids[d] = ck;
+    }
+    if (lane < 8) {
+        double mine = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            if (d == lane) mine = S[d];
+        probs[q * 8 + lane] = total > 0.0 ? (float)(mine / total) : 0.f;
+        if (raw) raw[q * 8 + lane] = mine;
+    }
+    if (lane == 0 && choice) {
+        int32_t pick = -1;
+        if (total > 0.0 && uniforms) {
+            const double target = (double)uniforms[q] * total;
+            double accp = 0.0;
+            int32_t last = -1;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                if (pick >= 0) continue;
+                if (S[d] > 0.0) last = cids[d];
+                accp += S[d];
+                if (accp > target && S[d] > 0.0) pick = cids[d];
+            }
+            if (pick < 0) pick = last;
+        }
+        choice[q] = pick;
+    }
+}
+
+// The queries whose node holds more than kDirectPoints points.  The sums over
+// the children of X come from a walk below X by the kWalkWaves
+// wavefronts of a block, sharing one stack: each step takes up to 64 kWalkWaves
+// nodes from the top of the stack, one per lane, and every node's children are
+// pushed so that the nearest ends on top.  Decisions compare against
+// R = max(lower bound, total summed so far), which never exceeds the final total;
+// the lower bound comes first, from the chain of nearest nodes below X (the
+// first node of the chain within reach carrying moments gives its M2P value
+// minus the rigorous truncation bound, a leaf at the end of the chain its exact
+// sum).  For a node carrying moments:
 //   - dropped if all of its weight at its nearest point stays below kSkipTol R;
 //   - M2P if the calibrated error model is below kAdmitTol of the node's own
 //     smallest term, or below kRunTol R;
 // otherwise its children are pushed, and a leaf is summed directly (by its
 // lane, or by the whole wave when it holds more than kLaneLeaf points).
-// Every decision and every sum is taken in a fixed order, so the result is
-// the same from run to run.
-template <int P>
-__global__ void __launch_bounds__(64)
-k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
-          int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
-          const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
-          const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
-          double lox, double loy, double loz, double side, const float4 *ps, const uint8_t *hasA,
-          const float *nodeA, int64_t slot0, double sigma, float cutoff2, int unlimited,
-          double rho_ref, int exclude_self, float *probs, int32_t *choice, const uint8_t *done,
-          double *raw, const int32_t *qorder) {
-    constexpr int P3 = P * P * P;
-    __shared__ int32_t stk[kStack];
-    // blocks take the queries left by the leaf-children pass, coarsest query nodes
-    // first (their walks are the longest, so they start early), then exit
-    int64_t q = nq;
-    {
-        const int32_t *tally = qorder + (size_t)kMaxLevels * nq;
-        int64_t b = blockIdx.x;
-        for (int l = 0; l < kMaxLevels; ++l) {
-            if (b < tally[l]) {
-                q = qorder[(size_t)l * nq + b];
-                break;
-            }
-            b -= tally[l];
-        }
+// Every decision and every sum is taken in a fixed order (nodes go to waves by
+// their place on the stack, and the waves' partial sums are added in wave
+// order), so the result is the same from run to run.
+constexpr int kWalkWaves = 4;
+constexpr int kStack = 4096;   // stack entries of a query
+
+struct WalkShared {
+    int32_t stk[kStack];
+    int32_t c_first[kWalkWaves][64], c_end[kWalkWaves][64];
+    int32_t m2p_order[kWalkWaves][64];   // lanes whose node is evaluated by expansion, in lane order
+    float m2p_res[kWalkWaves][64];
+    double part[kWalkWaves][8];          // per-wave partial sums of a step
+    int32_t wpush[kWalkWaves];
+    int32_t any_has[kWalkWaves];
+    double lbv;
+    int8_t c_digit[kWalkWaves][64];
+};
+
+// the idx-th query of the walk's order (coarsest query nodes first), or nq
+__device__ inline int64_t walk_query_at(const int32_t *qorder, int64_t nq, int64_t idx) {
+    const int32_t *tally = qorder + (size_t)kMaxLevels * nq;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (idx < tally[l]) return qorder[(size_t)l * nq + idx];
+        idx -= tally[l];
     }
-    const int lane = threadIdx.x;
-    if (q >= nq || done[q]) return;
-    const int32_t ti = target_idx[q], X = node_id[q];
-    const bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
-    const int nc = ok ? nnchild[X] : 0;
-    const int32_t fc = ok ? nfchild[X] : 0;
-    if (nc == 0 || fc <= X || fc + nc > n_nodes) {
-        if (lane < 8) probs[q * 8 + lane] = 0.f;
-        if (lane < 8 && raw) raw[q * 8 + lane] = 0.0;
-        if (lane == 0 && choice) choice[q] = -1;
+    return nq;
+}
+
+struct WalkArgs {
+    int64_t nq;
+    const int32_t *target_idx, *node_id;
+    const float *uniforms;
+    int64_t n, n_nodes;
+    const int32_t *qpos, *nlevel, *nfirst, *ncount, *nfchild, *nnchild, *nix, *niy, *niz;
+    double lox, loy, loz, side;
+    const float4 *ps;
+    const uint8_t *hasA;
+    const float *nodeA;
+    int64_t slot0;
+    double sigma;
+    float cutoff2;
+    int unlimited;
+    double rho_ref;
+    int exclude_self;
+    float *probs;
+    int32_t *choice;
+    double *raw;
+    const int32_t *qorder;
+};
+
+// One query, walked by all kWalkWaves wavefronts of the block (this is wave wv).
+template <int P>
+__device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv) {
+    constexpr int P3 = P * P * P;
+    constexpr int NW = kWalkWaves;
+    constexpr int cap = kStack;
+    int32_t *stk = sh.stk;
+    const int lane = threadIdx.x & 63;
+    const bool lead = wv == 0;   // the wave that writes the query's outputs
+    const int32_t ti = a.target_idx[q], X = a.node_id[q];
+    const bool ok = ti >= 0 && ti < a.n && X >= 0 && X < a.n_nodes && a.qpos[q] >= 0;
+    const int nc = ok ? a.nnchild[X] : 0;
+    const int32_t fc = ok ? a.nfchild[X] : 0;
+    if (nc == 0 || fc <= X || fc + nc > a.n_nodes) {
+        if (lead) {
+            if (lane < 8) a.probs[q * 8 + lane] = 0.f;
+            if (lane < 8 && a.raw) a.raw[q * 8 + lane] = 0.0;
+            if (lane == 0 && a.choice) a.choice[q] = -1;
+        }
         return;
     }
-    const int32_t si = qpos[q];
-    const float4 qt = ps[si];
+    const int32_t si = a.qpos[q];
+    const float4 qt = a.ps[si];
     const double tx = qt.x, ty = qt.y, tz = qt.z;
-    const double inv_sigma = 1.0 / sigma;
+    const double inv_sigma = 1.0 / a.sigma;
     const double inv_s2 = inv_sigma * inv_sigma;
     const double kexp = 1.4426950408889634 * inv_s2;
-    const int lx = nlevel[X];
+    const int lx = a.nlevel[X];
+    const int32_t *nlevel = a.nlevel, *nix = a.nix, *niy = a.niy, *niz = a.niz;
+    const int32_t *nfirst = a.nfirst, *ncount = a.ncount, *nnchild = a.nnchild, *nfchild = a.nfchild;
+    const float4 *ps = a.ps;
+    const int64_t n_nodes = a.n_nodes, slot0 = a.slot0;
+    const int unlimited = a.unlimited, exclude_self = a.exclude_self;
     auto centre = [&](int32_t u, double &cx, double &cy, double &cz, double &half) {
-        const double h = side / (double)(1ll << nlevel[u]);
-        cx = lox + (nix[u] + 0.5) * h;
-        cy = loy + (niy[u] + 0.5) * h;
-        cz = loz + (niz[u] + 0.5) * h;
+        const double h = a.side / (double)(1ll << nlevel[u]);
+        cx = a.lox + (nix[u] + 0.5) * h;
+        cy = a.loy + (niy[u] + 0.5) * h;
+        cz = a.loz + (niz[u] + 0.5) * h;
         half = 0.5 * h;
     };
     // squared distance from the target to the box (near) and to its farthest corner (far)
@@ -957,7 +1124,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     };
     double far0;
     const double d0sq = box_d2(X, far0);
-    const double reach = unlimited ? 0.0 : sqrt(d0sq) + sqrt((double)cutoff2);
+    const double reach = unlimited ? 0.0 : sqrt(d0sq) + sqrt((double)a.cutoff2);
     const double reach2 = reach * reach;
     // direct sum over one node's points by the whole wave
     auto wave_direct = [&](int32_t uf, int32_t un) {
@@ -971,26 +1138,31 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
         return wave_sum(part);
     };
 
-    // lower bound of the total from the chain of nearest nodes (wave-uniform call)
+    // lower bound of the total from the chain of nearest nodes (wave-uniform
+    // call); a node reaching beyond the cutoff counts sources the walk drops, so
+    // only the nodes of the chain that lie within reach contribute.  The first of
+    // those carrying moments ends the chain: the nodes below it hold subsets of
+    // its sources, so their sums cannot raise the bound beyond its own error.
     auto lower_bound = [&]() {
         double lb = 0.0;
         int32_t u = X;
         for (int guard = 0; guard <= kMaxLevels; ++guard) {
             double far2;
             (void)box_d2(u, far2);
-            if (!unlimited && far2 > reach2) break;   // not every source of u is counted
+            const bool inside = unlimited || far2 <= reach2;
             const int32_t uf = nfirst[u], un = ncount[u], unc = nnchild[u];
-            if (hasA[u]) {
-                const float *A = nodeA + (int64_t)(u - slot0) * P3;
+            if (inside && a.hasA[u]) {
+                const float *A = a.nodeA + (int64_t)(u - slot0) * P3;
                 double cx, cy, cz, half;
                 centre(u, cx, cy, cz, half);
                 double m = m2p_wave<P>(A, (float)((tx - cx) * inv_sigma), (float)((ty - cy) * inv_sigma),
                                        (float)((tz - cz) * inv_sigma), lane);
                 if (exclude_self && si >= uf && si < uf + un) m -= (double)qt.w;
                 lb = fmax(lb, m - trunc_bound(half * inv_sigma, P) * fabs((double)A[0]));
+                break;
             }
             if (unc == 0) {
-                lb = fmax(lb, wave_direct(uf, un));
+                if (inside) lb = fmax(lb, wave_direct(uf, un));
                 break;
             }
             const int32_t f = nfchild[u];
@@ -1013,7 +1185,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     };
 
     // children of X, farthest at the bottom of the stack
-    {
+    if (lead) {
         double dummy, dl = 0.0;
         if (lane < nc) dl = box_d2(fc + lane, dummy);
         int rank = 0;   // children farther away; ties: the larger index counts as farther
@@ -1029,36 +1201,51 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     for (int d = 0; d < 8; ++d) S[d] = 0.0;
     double acc = 0.0, lb = 0.0;
     bool have_lb = false;
-    __shared__ int32_t c_first[64], c_end[64];
-    __shared__ int8_t c_digit[64];
+    int32_t *c_first = sh.c_first[wv], *c_end = sh.c_end[wv];
+    int8_t *c_digit = sh.c_digit[wv];
     const double log_admit = log(kAdmitTol), log_runtol = log(kRunTol), log_skip = log(kSkipTol);
     const double log_model0 = log(2e-5);
     __syncthreads();
     while (sp > 0) {
-        int B = sp < 64 ? sp : 64;
-        const int room = (kStack - sp) / 7;   // pops B, pushes at most 8 B
+        int B = sp < 64 * NW ? sp : 64 * NW;
+        const int room = (cap - sp) / 7;   // pops B, pushes at most 8 B
         if (B > room) B = room > 1 ? room : 1;
         const int base = sp - B;
-        const int32_t u = lane < B ? stk[base + lane] : -1;
-        const bool u_has = u >= 0 && hasA[u];
-        __syncthreads();
+        const int slot = wv * 64 + lane;   // this lane's place in the popped batch
+        const int32_t u = slot < B ? stk[base + slot] : -1;
+        const bool u_has = u >= 0 && a.hasA[u];
         // the bound is needed only once a node carrying moments comes up
-        if (!have_lb && __ballot(u_has)) {
-            lb = lower_bound();
-            have_lb = true;
+        if (!have_lb) {
+            const bool mine = __ballot(u_has) != 0;
+            if (lane == 0) sh.any_has[wv] = mine ? 1 : 0;
+            __syncthreads();
+            bool any = false;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) any = any || sh.any_has[w] != 0;
+            if (any) {
+                if (wv == 0) {
+                    const double v = lower_bound();
+                    if (lane == 0) sh.lbv = v;
+                }
+                __syncthreads();
+                lb = sh.lbv;
+                have_lb = true;
+            }
         }
+        __syncthreads();   // every popped entry is read before pushes overwrite them
         const double run = fmax(lb, acc);
         const double lrun = run > 0.0 ? log(run) : -1e300;
         double val = 0.0;
         int digit = 0, npush = 0, nleaf = 0;
-        bool big = false;
+        bool big = false, do_m2p = false;
+        float3 my = make_float3(0.f, 0.f, 0.f);
         int32_t uf = 0, un = 0, f = 0;
         if (u >= 0) {
             double cx, cy, cz, half;
             centre(u, cx, cy, cz, half);
             const int lu = nlevel[u];
-            const int sh = lu - lx - 1;
-            digit = (((nix[u] >> sh) & 1) << 2) | (((niy[u] >> sh) & 1) << 1) | ((niz[u] >> sh) & 1);
+            const int shf = lu - lx - 1;
+            digit = (((nix[u] >> shf) & 1) << 2) | (((niy[u] >> shf) & 1) << 1) | ((niz[u] >> shf) & 1);
             double far2;
             const double g2 = box_d2(u, far2);
             uf = nfirst[u];
@@ -1068,7 +1255,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             if (unlimited || g2 <= reach2) {
                 bool descend = unc > 0, direct = unc == 0;
                 if (u_has) {
-                    const float *A = nodeA + (int64_t)(u - slot0) * P3;
+                    const float *A = a.nodeA + (int64_t)(u - slot0) * P3;
                     const double lw = log(fmax(fabs((double)A[0]), 1e-300));
                     if (lw - g2 * inv_s2 <= log_skip + lrun) {
                         descend = direct = false;
@@ -1077,14 +1264,18 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                         const double rho = half * inv_sigma;
                         const double r = sqrt(dx * dx + dy * dy + dz * dz) * inv_sigma;
                         // calibrated error model 2e-5 (rho / rho_max(p))^p of the expansion level
-                        const double lm = log_model0 + P * log(rho / rho_ref);
+                        const double lm = log_model0 + P * log(rho / a.rho_ref);
                         const bool adm = lm + 0.5 * r * r + 2.0 * 1.7320508075688772 * rho * r + 3.0 * rho * rho <= log_admit ||
                                          lm + lw - 0.5 * r * r <= log_runtol + lrun;
                         if (adm) {
-                            float m = m2p_lane<P>(A, (float)(dx * inv_sigma), (float)(dy * inv_sigma),
-                                                  (float)(dz * inv_sigma));
-                            val = (double)m;
-                            if (exclude_self && si >= uf && si < uf + un) val -= (double)qt.w;
+                            my = make_float3((float)(dx * inv_sigma), (float)(dy * inv_sigma),
+                                             (float)(dz * inv_sigma));
+                            if constexpr (P == 8) {
+                                do_m2p = true;   // evaluated below by a lane group
+                            } else {
+                                val = (double)m2p_lane<P>(A, my.x, my.y, my.z);
+                                if (exclude_self && si >= uf && si < uf + un) val -= (double)qt.w;
+                            }
                             descend = direct = false;
                         }
                     }
@@ -1099,12 +1290,75 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                 }
             }
         }
-        int incl = wave_incl_scan(npush, lane);
-        if (npush > 0 && base + incl > kStack) {
-            // only reachable when a single node is taken with a nearly full stack
+        if constexpr (P == 8) {
+            // Eq. (7) for the nodes taken by expansion, eight nodes at a time: the
+            // 8-lane group g evaluates one node, lane s of the group holding the
+            // 16-byte pieces 8k + s (k < 16) of its 2 KB moment block, so that every
+            // load of the group covers one whole 128-byte line
+            const uint64_t mm = __ballot(do_m2p);
+            if (mm) {
+                int32_t *order = sh.m2p_order[wv];
+                float *res = sh.m2p_res[wv];
+                const int nm = __popcll(mm);
+                const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                if (do_m2p) order[__popcll(mm & below)] = lane;
+                wave_sync();
+                const int g = lane >> 3, sl = lane & 7;
+                const int h = sl & 1, ayb = sl >> 1;
+                for (int r0 = 0; r0 < nm; r0 += 8) {
+                    const int k = r0 + g;
+                    const int src = k < nm ? order[k] : lane;
+                    const int32_t su = __shfl(u, src, 64);
+                    const float yx = __shfl(my.x, src, 64), yy = __shfl(my.y, src, 64),
+                                yz = __shfl(my.z, src, 64);
+                    float part = 0.f;
+                    if (k < nm) {
+                        const float4 *blk = reinterpret_cast<const float4 *>(a.nodeA + (int64_t)(su - slot0) * P3);
+                        float4 av[16];
+#pragma unroll
+                        for (int kk = 0; kk < 16; ++kk) av[kk] = blk[8 * kk + sl];
+                        float hx[8], hy[8], hz[8];
+                        hermite_row<8>(yx, hx);
+                        hermite_row<8>(yy, hy);
+                        hermite_row<8>(yz, hz);
+#pragma unroll
+                        for (int kk = 0; kk < 16; ++kk) {
+                            // piece 8 kk + sl: az = kk / 2, ay = 4 (kk % 2) + sl / 2, ax = 4 (sl % 2) ..
+                            const float4 v = av[kk];
+                            float sx = v.x * hx[4 * h];
+                            sx = fmaf(v.y, hx[4 * h + 1], sx);
+                            sx = fmaf(v.z, hx[4 * h + 2], sx);
+                            sx = fmaf(v.w, hx[4 * h + 3], sx);
+                            part = fmaf(sx, hy[4 * (kk & 1) + ayb] * hz[kk >> 1], part);
+                        }
+                    }
+                    part += __shfl_xor(part, 1, 64);
+                    part += __shfl_xor(part, 2, 64);
+                    part += __shfl_xor(part, 4, 64);
+                    if (k < nm && sl == 0) res[src] = part;
+                }
+                wave_sync();
+                if (do_m2p) {
+                    val = (double)res[lane];
+                    if (exclude_self && si >= uf && si < uf + un) val -= (double)qt.w;
+                }
+            }
+        }
+        // a single node taken with a nearly full stack (B = 1 is the only case
+        // where the pushes can overflow): its points are summed instead
+        if (B == 1 && npush > 0 && base + npush > cap) {
             big = true;
             npush = 0;
-            incl = 0;
+        }
+        // pushes: this wave's lanes in lane order, the waves in wave order
+        int incl = wave_incl_scan(npush, lane);
+        if (lane == 63) sh.wpush[wv] = incl;
+        __syncthreads();
+        int woff = 0, pushed = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (w < wv) woff += sh.wpush[w];
+            pushed += sh.wpush[w];
         }
         if (npush > 0) {
             double cd[8];
@@ -1113,7 +1367,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                 double fr;
                 cd[k] = k < npush ? box_d2(f + k, fr) : 0.0;
             }
-            const int pos0 = base + incl - npush;
+            const int pos0 = base + woff + incl - npush;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 if (k >= npush) continue;
@@ -1124,7 +1378,12 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
                 stk[pos0 + rank] = f + k;
             }
         }
-        sp = base + __shfl(incl, 63, 64);
+        sp = base + pushed;
+        // this wave's sums of the step, per octant
+        if (lane < 8) sh.part[wv][lane] = 0.0;
+        auto add_step = [&](int d, double v) {   // wave-uniform d and v
+            if (lane == 0) sh.part[wv][d] += v;
+        };
         // nodes summed by the whole wave
         uint64_t bigmask = __ballot(big);
         while (bigmask) {
@@ -1132,11 +1391,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             bigmask &= bigmask - 1;
             const int32_t bf = __shfl(uf, bl, 64), bn = __shfl(un, bl, 64);
             const int bd = __shfl(digit, bl, 64);
-            const double sbig = wave_direct(bf, bn);
-#pragma unroll
-            for (int d = 0; d < 8; ++d)
-                if (d == bd) S[d] += sbig;
-            acc += sbig;
+            add_step(bd, wave_direct(bf, bn));
         }
         // the small leaves of the batch, their points spread over the lanes
         double pd[8];
@@ -1148,7 +1403,7 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             c_first[lane] = uf - (lincl - nleaf);   // point index = c_first + flattened index
             c_end[lane] = nleaf > 0 ? lincl : -1;
             c_digit[lane] = (int8_t)digit;
-            __syncthreads();
+            wave_sync();
             int owner = 0;
             for (int j = lane; j < ltotal; j += 64) {
                 while (c_end[owner] <= j) ++owner;   // lanes in order, flattened indices increase
@@ -1166,12 +1421,20 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             if (__ballot(pd[d] != 0.0) == 0) continue;
-            const double sd = wave_sum(pd[d]);
-            S[d] += sd;
-            acc += sd;
+            add_step(d, wave_sum(pd[d]));
         }
         __syncthreads();
+        // every wave adds the waves' sums in wave order: identical totals
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                S[d] += sh.part[w][d];
+                acc += sh.part[w][d];
+            }
+        __syncthreads();
     }
+    if (!lead) return;
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < 8; ++d) total += S[d];
@@ -1180,24 +1443,24 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
     if (lane < 8) {
         for (int k = 0; k < nc; ++k) {
             const int32_t c = fc + k;
-            const int sh = nlevel[c] - lx - 1;
-            const int dg = (((nix[c] >> sh) & 1) << 2) | (((niy[c] >> sh) & 1) << 1) | ((niz[c] >> sh) & 1);
+            const int shf = nlevel[c] - lx - 1;
+            const int dg = (((nix[c] >> shf) & 1) << 2) | (((niy[c] >> shf) & 1) << 1) | ((niz[c] >> shf) & 1);
             if (dg == lane) cid_l = c;
         }
         double sl = 0.0;
 #pragma unroll
         for (int d = 0; d < 8; ++d)
             if (d == lane) sl = S[d];
-        probs[q * 8 + lane] = total > 0.0 ? (float)(sl / total) : 0.f;
-        if (raw) raw[q * 8 + lane] = sl;
+        a.probs[q * 8 + lane] = total > 0.0 ? (float)(sl / total) : 0.f;
+        if (a.raw) a.raw[q * 8 + lane] = sl;
     }
     int32_t cids[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) cids[d] = __shfl(cid_l, d, 64);
-    if (lane == 0 && choice) {
+    if (lane == 0 && a.choice) {
         int32_t pick = -1;
-        if (total > 0.0 && uniforms) {
-            const double target = (double)uniforms[q] * total;
+        if (total > 0.0 && a.uniforms) {
+            const double target = (double)a.uniforms[q] * total;
             double accp = 0.0;
             int32_t last = -1;
 #pragma unroll
@@ -1209,12 +1472,28 @@ k_partner(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const f
             }
             if (pick < 0) pick = last;
         }
-        choice[q] = pick;
+        a.choice[q] = pick;
     }
 }
 
-// Order of the walk's queries, coarsest query node first, without contention on
-// a few counters: a block tallies its queries per level in LDS, reserves room for
+// Blocks take the queries of the walk, coarsest query nodes first (their walks
+// are the longest, so they start early): block b the queries b, b + blocks, ...
+template <int P>
+__global__ void __launch_bounds__(64 * kWalkWaves) k_partner(WalkArgs a) {
+    __shared__ WalkShared sh;
+    const int32_t *tally = a.qorder + (size_t)kMaxLevels * a.nq;
+    int64_t nwalk = 0;
+    for (int l = 0; l < kMaxLevels; ++l) nwalk += tally[l];
+    for (int64_t b = blockIdx.x; b < nwalk; b += gridDim.x) {
+        __syncthreads();   // the previous query's shared state is no longer read
+        walk_query<P>(a, walk_query_at(a.qorder, a.nq, b), sh, threadIdx.x >> 6);
+    }
+}
+
+// The walk's queries (valid ones whose node has children and more than
+// kDirectPoints points; the direct passes take the others), coarsest query node
+// first, without contention on a few counters: a block tallies its queries per
+// level in LDS, reserves room for
 // each level with one atomic addition, and places them in that level's segment
 // order[l * nq ...]; the per-level tallies (after the segments) give the walk its
 // mapping from block to query.  The order inside a level does not matter: every
@@ -1223,19 +1502,30 @@ __global__ void k_order_clear(int32_t *tally) {
     if (threadIdx.x < kMaxLevels) tally[threadIdx.x] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_order_place(int64_t nq, const uint8_t *done, const int32_t *node_id,
-                                                     int64_t n_nodes, const int32_t *nlevel, int32_t *order) {
+__global__ void __launch_bounds__(256) k_order_place(int64_t nq, const int32_t *target_idx, const int32_t *node_id,
+                                                     int64_t n, int64_t n_nodes, const int32_t *qpos,
+                                                     const int32_t *nlevel, const int32_t *ncount,
+                                                     const int32_t *nfchild, const int32_t *nnchild,
+                                                     int32_t *order) {
     __shared__ int32_t cnt[kMaxLevels], base[kMaxLevels];
     int32_t *tally = order + (size_t)kMaxLevels * nq;
     if (threadIdx.x < kMaxLevels) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int l = -1, slot = 0;
-    if (q < nq && !done[q]) {
-        const int32_t X = node_id[q];
-        l = (X >= 0 && X < n_nodes) ? nlevel[X] : 0;
-        l = l < kMaxLevels ? l : kMaxLevels - 1;
-        slot = atomicAdd(&cnt[l], 1);
+    if (q < nq) {
+        const int32_t ti = target_idx[q], X = node_id[q];
+        bool walk = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
+        if (walk) {
+            const int nc = nnchild[X];
+            const int32_t fc = nfchild[X];
+            walk = nc > 0 && fc > X && fc + nc <= n_nodes && ncount[X] > kDirectPoints;
+        }
+        if (walk) {
+            l = nlevel[X];
+            l = l < kMaxLevels ? l : kMaxLevels - 1;
+            slot = atomicAdd(&cnt[l], 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x < kMaxLevels && cnt[threadIdx.x] > 0)
@@ -1333,36 +1623,63 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * sigma);
-    MSP_TRY(t->partner_done.ensure((size_t)nq));
-    {
-        PhaseScope pl(&t->timing, PH_PARTNER_LEAFY, s);
-        hipLaunchKernelGGL(k_partner_leafy, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, target_idx,
-                           node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
-                           t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                           t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
-                           t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
-                           t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), sigma, R * R, unlimited ? 1 : 0,
-                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice,
-                           t->partner_done.as<uint8_t>(), raw);
-        MSP_CHECK_LAUNCH();
-    }
+    // the walk's queries, coarsest first
     MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
     int32_t *order = t->partner_order.as<int32_t>();
     hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, order + (size_t)kMaxLevels * nq);
     MSP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq,
-                       t->partner_done.as<uint8_t>(), node_id, nn, t->nlevel.as<int32_t>(), order);
+    hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, target_idx, node_id,
+                       t->n, nn, qpos, t->nlevel.as<int32_t>(), t->ncount.as<int32_t>(),
+                       t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), order);
     MSP_CHECK_LAUNCH();
-    PhaseScope ps(&t->timing, PH_PARTNER, s);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nq), dim3(64), 0, s, nq, target_idx,
-                       node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
-                       t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                       t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
-                       t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
-                       t->ps.as<float4>(), t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma,
-                       R * R, unlimited ? 1 : 0, rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs,
-                       choice, t->partner_done.as<uint8_t>(), raw, order);
-    MSP_CHECK_LAUNCH();
+    // the walk (few, long queries) on a side stream, beside the direct passes (many
+    // short ones) on the caller's stream
+    MSP_TRY(t->side.fork(s));
+    {
+        PhaseScope ps(&t->timing, PH_PARTNER, t->side.stream);
+        WalkArgs wa{nq, target_idx, node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
+                    t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                    t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                    t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(),
+                    t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma, R * R, unlimited ? 1 : 0,
+                    rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, order};
+        // as many blocks as the device holds at once (at most one per query)
+        static int resident = 0;
+        if (resident == 0) {
+            int per_cu = 0, cus = 0, dev = 0;
+            MSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(k_partner<P>), 64 * kWalkWaves, 0));
+            MSP_HIP(hipGetDevice(&dev));
+            MSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        }
+        const int64_t nblocks = nq < resident ? nq : resident;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nblocks), dim3(64 * kWalkWaves), 0,
+                           t->side.stream, wa);
+        MSP_CHECK_LAUNCH();
+    }
+    {
+        PhaseScope pl(&t->timing, PH_PARTNER_DIRECT, s);
+        hipLaunchKernelGGL(k_partner_direct, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, target_idx,
+                           node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
+                           t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                           t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                           t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
+                           t->ps.as<float4>(), sigma, R * R, unlimited ? 1 : 0,
+                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw);
+        MSP_CHECK_LAUNCH();
+    }
+    {
+        PhaseScope pw(&t->timing, PH_PARTNER_WAVE, s);
+        hipLaunchKernelGGL(k_partner_wave, dim3(grid_for(nq, 4)), dim3(256), 0, s, nq, target_idx, node_id,
+                           uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
+                           t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
+                           t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0],
+                           t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(), sigma, R * R,
+                           unlimited ? 1 : 0, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw);
+        MSP_CHECK_LAUNCH();
+    }
+    MSP_TRY(t->side.join(s));
     return MSP_OK;
 }
 
