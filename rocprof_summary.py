@@ -1,10 +1,10 @@
 #!/usr/bin/env python3
 """Short text summaries of rocprofv3 CSV output, for the files under profiles/.
 
-    python paper_2301_10570_amd/rocprof_summary.py stats KERNEL_STATS_CSV --command CMD
-    python paper_2301_10570_amd/rocprof_summary.py traffic --fetch FETCH_CSV --write WRITE_CSV \\
+    python rocprof_summary.py stats KERNEL_STATS_CSV --command CMD
+    python rocprof_summary.py traffic --fetch FETCH_CSV --write WRITE_CSV \\
         --kernel NAME --source FILE --copy-bytes B --command CMD
-    python paper_2301_10570_amd/rocprof_summary.py util COUNTER_CSV --command CMD --kernels K1,K2
+    python rocprof_summary.py util COUNTER_CSV --command CMD --kernels K1,K2
 
 `stats` lists every kernel of a `--kernel-trace --stats` run (calls, total and
 average duration).  `traffic` turns the FETCH_SIZE and WRITE_SIZE counters
