@@ -169,8 +169,8 @@ __device__ void p2m_cell(const float4 *ps, const int32_t *perm, const float *w, 
             const float wv = w ? w[perm[j]] : q.w;   // NULL: the weights are staged in the records
             // the weight in key order, for later calls (whole records: full-line writes)
             if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
-            nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
-                              (float)(((double)q.z - cz) * inv_sigma), wv);
+            nxt = make_float4(((q.x - (float)cx) * (float)inv_sigma), ((q.y - (float)cy) * (float)inv_sigma),
+                              ((q.z - (float)cz) * (float)inv_sigma), wv);
         }
     };
     fetch(start);
@@ -276,8 +276,8 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
             const float wv = w ? w[perm[j]] : q.w;   // NULL: the weights are staged in the records
             // the weight in key order, for later calls (whole records: full-line writes)
             if (stage) stage[j] = make_float4(q.x, q.y, q.z, wv);
-            nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
-                              (float)(((double)q.z - cz) * inv_sigma), wv);
+            nxt = make_float4(((q.x - (float)cx) * (float)inv_sigma), ((q.y - (float)cy) * (float)inv_sigma),
+                              ((q.z - (float)cz) * (float)inv_sigma), wv);
         }
     };
     // this lane's operand slots: row m = (ax, ay_lo), column n = (ay_hi within the tile, az)
@@ -766,9 +766,9 @@ __device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *i
         const bool has1 = i1 < end;
         const float4 q0 = ps[i0];
         const float4 q1 = has1 ? ps[i1] : q0;
-        const float X0 = (float)(((double)q0.x - cx) * inv_sigma), X1 = (float)(((double)q1.x - cx) * inv_sigma);
-        const float Y0 = (float)(((double)q0.y - cy) * inv_sigma), Y1 = (float)(((double)q1.y - cy) * inv_sigma);
-        const float Z0 = (float)(((double)q0.z - cz) * inv_sigma), Z1 = (float)(((double)q1.z - cz) * inv_sigma);
+        const float X0 = ((q0.x - (float)cx) * (float)inv_sigma), X1 = ((q1.x - (float)cx) * (float)inv_sigma);
+        const float Y0 = ((q0.y - (float)cy) * (float)inv_sigma), Y1 = ((q1.y - (float)cy) * (float)inv_sigma);
+        const float Z0 = ((q0.z - (float)cz) * (float)inv_sigma), Z1 = ((q1.z - (float)cz) * (float)inv_sigma);
         // the scattered reads of the output step are issued before the evaluation
         const int32_t j0 = perm[i0];
         const int32_t j1 = has1 ? perm[i1] : j0;
@@ -916,9 +916,9 @@ __global__ void __launch_bounds__(kBlock) k_p2m_2lvl(const uint64_t *keys, int64
             const int m = bnd[s + 1] - c0 < 64 ? (int)(bnd[s + 1] - c0) : 64;
             if (lane < m) {
                 const float4 q = ps[c0 + lane];
-                stg[lane] = make_float4((float)(((double)q.x - sx) * inv_sigma),
-                                        (float)(((double)q.y - sy) * inv_sigma),
-                                        (float)(((double)q.z - sz) * inv_sigma), w ? w[perm[c0 + lane]] : q.w);
+                stg[lane] = make_float4(((q.x - (float)sx) * (float)inv_sigma),
+                                        ((q.y - (float)sy) * (float)inv_sigma),
+                                        ((q.z - (float)sz) * (float)inv_sigma), w ? w[perm[c0 + lane]] : q.w);
             }
             wave_sync();
             if (active) {
@@ -1074,9 +1074,9 @@ __global__ void __launch_bounds__(kBlock) k_l2p_2lvl(const uint64_t *keys, int64
             const float *c = cs + (s0 + wid) * pf3;
             for (int64_t i = bnd[sidx] + lane; i < bnd[sidx + 1]; i += 64) {
                 const float4 q = ps[i];
-                const float X = (float)(((double)q.x - sx) * inv_sigma);
-                const float Y = (float)(((double)q.y - sy) * inv_sigma);
-                const float Z = (float)(((double)q.z - sz) * inv_sigma);
+                const float X = ((q.x - (float)sx) * (float)inv_sigma);
+                const float Y = ((q.y - (float)sy) * (float)inv_sigma);
+                const float Z = ((q.z - (float)sz) * (float)inv_sigma);
                 float uz = 0.f;
 #pragma unroll
                 for (int bz = pf - 1; bz >= 0; --bz) {
@@ -1173,9 +1173,9 @@ __global__ void __launch_bounds__(kBlock) k_l2p_grad(const uint64_t *keys, int64
     const float is = (float)inv_sigma;
     for (int64_t i = start + threadIdx.x; i < end; i += kBlock) {
         const float4 q = ps[i];
-        const float X = (float)(((double)q.x - cx) * inv_sigma);
-        const float Y = (float)(((double)q.y - cy) * inv_sigma);
-        const float Z = (float)(((double)q.z - cz) * inv_sigma);
+        const float X = ((q.x - (float)cx) * (float)inv_sigma);
+        const float Y = ((q.y - (float)cy) * (float)inv_sigma);
+        const float Z = ((q.z - (float)cz) * (float)inv_sigma);
         l2p_grad_point<P>(sC, X, Y, Z, is, want_lap, out + i * stride);
     }
 }
@@ -1494,8 +1494,8 @@ __device__ void p2m_cell_wave(const float4 *ps, const int32_t *perm, const float
         float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < e) {
             const float4 t = ps[j];
-            q = make_float4((float)(((double)t.x - cx) * inv_sigma), (float)(((double)t.y - cy) * inv_sigma),
-                            (float)(((double)t.z - cz) * inv_sigma), w[perm[j]]);
+            q = make_float4(((t.x - (float)cx) * (float)inv_sigma), ((t.y - (float)cy) * (float)inv_sigma),
+                            ((t.z - (float)cz) * (float)inv_sigma), w[perm[j]]);
         }
         return q;
     };
@@ -1652,8 +1652,8 @@ __device__ void p2m_cells_group(const FgtBatchPlan &bp, int64_t r0, int64_t nsma
         float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < cnt) {
             const float4 t = f.ps[c.y + j];
-            q = make_float4((float)(((double)t.x - cx) * f.inv_sigma), (float)(((double)t.y - cy) * f.inv_sigma),
-                            (float)(((double)t.z - cz) * f.inv_sigma), f.w[f.perm[c.y + j]]);
+            q = make_float4(((t.x - (float)cx) * (float)f.inv_sigma), ((t.y - (float)cy) * (float)f.inv_sigma),
+                            ((t.z - (float)cz) * (float)f.inv_sigma), f.w[f.perm[c.y + j]]);
         }
         return q;
     };
@@ -1846,9 +1846,9 @@ __device__ void l2p_cell_wave(const FgtPop &f, int cm, int kx, int ky, int kz, i
         const int32_t j = live ? f.perm[i] : 0;
         const bool tgt = live && (!f.is_target || f.is_target[j]);
         const float wself = (live && f.subtract_self) ? f.w[j] : 0.f;
-        const float X = (float)(((double)q.x - cx) * f.inv_sigma);
-        const float Y = (float)(((double)q.y - cy) * f.inv_sigma);
-        const float Z = (float)(((double)q.z - cz) * f.inv_sigma);
+        const float X = ((q.x - (float)cx) * (float)f.inv_sigma);
+        const float Y = ((q.y - (float)cy) * (float)f.inv_sigma);
+        const float Z = ((q.z - (float)cz) * (float)f.inv_sigma);
         float zl = 1.f, zs = 1.f;
         for (int k = 0; k < L; ++k) {
             if (k == sub) zs = zl;
@@ -1944,8 +1944,8 @@ __device__ void l2p_cells_group(const FgtBatchPlan &bp, int64_t r0, int64_t nsma
         const int jj = c0 + sub;
         if (jj < cnt) {
             const float4 t = f.ps[c.y + jj];
-            g.q = make_float4((float)(((double)t.x - cx) * f.inv_sigma), (float)(((double)t.y - cy) * f.inv_sigma),
-                              (float)(((double)t.z - cz) * f.inv_sigma), 0.f);
+            g.q = make_float4(((t.x - (float)cx) * (float)f.inv_sigma), ((t.y - (float)cy) * (float)f.inv_sigma),
+                              ((t.z - (float)cz) * (float)f.inv_sigma), 0.f);
             g.j = f.perm[c.y + jj];
             g.t = !f.is_target || f.is_target[g.j];
             g.ws = f.subtract_self ? f.w[g.j] : 0.f;
@@ -2051,9 +2051,9 @@ __global__ void __launch_bounds__(64) k_bl2p_grad(FgtBatchPlan bp, int stride, i
         const float is = (float)f.inv_sigma;
         for (int64_t i = (int64_t)c.y + lane; i < (int64_t)c.y + c.z; i += 64) {
             const float4 q = f.ps[i];
-            const float X = (float)(((double)q.x - cx) * f.inv_sigma);
-            const float Y = (float)(((double)q.y - cy) * f.inv_sigma);
-            const float Z = (float)(((double)q.z - cz) * f.inv_sigma);
+            const float X = ((q.x - (float)cx) * (float)f.inv_sigma);
+            const float Y = ((q.y - (float)cy) * (float)f.inv_sigma);
+            const float Z = ((q.z - (float)cz) * (float)f.inv_sigma);
             l2p_grad_point<P>(sC, X, Y, Z, is, want_lap, f.rec + i * stride + slot);
         }
     }

@@ -181,7 +181,7 @@ __device__ inline double trunc_bound(double rho, int p) {
 template <int P>
 __device__ inline void hermite_row(float y, float (&h)[P]) {
     h[0] = expf(-y * y);
-    if (P > 1) h[1] = 2.f * y * h[0];
+    if constexpr (P > 1) h[1] = 2.f * y * h[0];
 #pragma unroll
     for (int k = 1; k + 1 < P; ++k) h[k + 1] = 2.f * y * h[k] - 2.f * (float)k * h[k - 1];
 }
@@ -355,8 +355,8 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
                 if (j < total) {
                     while (part_end[owner] <= j) ++owner;
                     const float4 q = ps[part_first[owner] + j];
-                    nxt = make_float4((float)(((double)q.x - cx) * inv_sigma), (float)(((double)q.y - cy) * inv_sigma),
-                                      (float)(((double)q.z - cz) * inv_sigma), q.w);
+                    nxt = make_float4(((q.x - (float)cx) * (float)inv_sigma), ((q.y - (float)cy) * (float)inv_sigma),
+                                      ((q.z - (float)cz) * (float)inv_sigma), q.w);
                 }
             };
             __syncthreads();   // part_first / part_end written above
@@ -429,9 +429,9 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
             for (int32_t c0 = 0; c0 < total; c0 += 64) {
                 __syncthreads();
                 if (c0 + lane < total)
-                    pt4[lane] = make_float4((float)(((double)nxt.x - cx) * inv_sigma),
-                                            (float)(((double)nxt.y - cy) * inv_sigma),
-                                            (float)(((double)nxt.z - cz) * inv_sigma), nxt.w);
+                    pt4[lane] = make_float4(((nxt.x - (float)cx) * (float)inv_sigma),
+                                            ((nxt.y - (float)cy) * (float)inv_sigma),
+                                            ((nxt.z - (float)cz) * (float)inv_sigma), nxt.w);
                 __syncthreads();
                 if (c0 + 64 < total) fetch(c0 + 64);
                 const int m = total - c0 < 64 ? total - c0 : 64;
@@ -484,9 +484,9 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
                 if (j < total) {
                     while (part_end[owner] <= j) ++owner;
                     const float4 qp = ps[part_first[owner] + j];
-                    const float X = (float)(((double)qp.x - cx) * inv_sigma);
-                    const float Y = (float)(((double)qp.y - cy) * inv_sigma);
-                    const float Z = (float)(((double)qp.z - cz) * inv_sigma);
+                    const float X = ((qp.x - (float)cx) * (float)inv_sigma);
+                    const float Y = ((qp.y - (float)cy) * (float)inv_sigma);
+                    const float Z = ((qp.z - (float)cz) * (float)inv_sigma);
                     float *r = pts + lane * STR;
                     float px = qp.w, py = 1.f, pz = 1.f;
     #pragma unroll
@@ -1073,15 +1073,21 @@ struct WalkArgs {
     const int32_t *qorder;
 };
 
-// One query, walked by all kWalkWaves wavefronts of the block (this is wave wv).
-template <int P>
+// One query.  SHARED: walked by all kWalkWaves wavefronts of the block (this is
+// wave wv), with the block's whole stack; otherwise wavefront wv walks it alone
+// with its own quarter of the stack space.
+template <int P, bool SHARED>
 __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv) {
     constexpr int P3 = P * P * P;
-    constexpr int NW = kWalkWaves;
-    constexpr int cap = kStack;
-    int32_t *stk = sh.stk;
+    constexpr int NW = SHARED ? kWalkWaves : 1;
+    constexpr int cap = SHARED ? kStack : kStack / kWalkWaves;
+    int32_t *stk = SHARED ? sh.stk : sh.stk + wv * (kStack / kWalkWaves);
+    auto sync = [&]() {
+        if constexpr (SHARED) __syncthreads();
+        else wave_sync();
+    };
     const int lane = threadIdx.x & 63;
-    const bool lead = wv == 0;   // the wave that writes the query's outputs
+    const bool lead = !SHARED || wv == 0;   // the wave that writes the query's outputs
     const int32_t ti = a.target_idx[q], X = a.node_id[q];
     const bool ok = ti >= 0 && ti < a.n && X >= 0 && X < a.n_nodes && a.qpos[q] >= 0;
     const int nc = ok ? a.nnchild[X] : 0;
@@ -1205,34 +1211,40 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
     int8_t *c_digit = sh.c_digit[wv];
     const double log_admit = log(kAdmitTol), log_runtol = log(kRunTol), log_skip = log(kSkipTol);
     const double log_model0 = log(2e-5);
-    __syncthreads();
+    sync();
     while (sp > 0) {
         int B = sp < 64 * NW ? sp : 64 * NW;
         const int room = (cap - sp) / 7;   // pops B, pushes at most 8 B
         if (B > room) B = room > 1 ? room : 1;
         const int base = sp - B;
-        const int slot = wv * 64 + lane;   // this lane's place in the popped batch
+        const int slot = (SHARED ? wv * 64 : 0) + lane;   // this lane's place in the popped batch
         const int32_t u = slot < B ? stk[base + slot] : -1;
         const bool u_has = u >= 0 && a.hasA[u];
         // the bound is needed only once a node carrying moments comes up
         if (!have_lb) {
-            const bool mine = __ballot(u_has) != 0;
-            if (lane == 0) sh.any_has[wv] = mine ? 1 : 0;
-            __syncthreads();
-            bool any = false;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) any = any || sh.any_has[w] != 0;
-            if (any) {
-                if (wv == 0) {
-                    const double v = lower_bound();
-                    if (lane == 0) sh.lbv = v;
-                }
+            bool any = __ballot(u_has) != 0;
+            if constexpr (SHARED) {
+                if (lane == 0) sh.any_has[wv] = any ? 1 : 0;
                 __syncthreads();
-                lb = sh.lbv;
+                any = false;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) any = any || sh.any_has[w] != 0;
+            }
+            if (any) {
+                if constexpr (SHARED) {
+                    if (wv == 0) {
+                        const double v = lower_bound();
+                        if (lane == 0) sh.lbv = v;
+                    }
+                    __syncthreads();
+                    lb = sh.lbv;
+                } else {
+                    lb = lower_bound();
+                }
                 have_lb = true;
             }
         }
-        __syncthreads();   // every popped entry is read before pushes overwrite them
+        sync();   // every popped entry is read before pushes overwrite them
         const double run = fmax(lb, acc);
         const double lrun = run > 0.0 ? log(run) : -1e300;
         double val = 0.0;
@@ -1352,13 +1364,16 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
         }
         // pushes: this wave's lanes in lane order, the waves in wave order
         int incl = wave_incl_scan(npush, lane);
-        if (lane == 63) sh.wpush[wv] = incl;
-        __syncthreads();
-        int woff = 0, pushed = 0;
+        int woff = 0, pushed = __shfl(incl, 63, 64);
+        if constexpr (SHARED) {
+            if (lane == 63) sh.wpush[wv] = incl;
+            __syncthreads();
+            pushed = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            if (w < wv) woff += sh.wpush[w];
-            pushed += sh.wpush[w];
+            for (int w = 0; w < NW; ++w) {
+                if (w < wv) woff += sh.wpush[w];
+                pushed += sh.wpush[w];
+            }
         }
         if (npush > 0) {
             double cd[8];
@@ -1379,10 +1394,20 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
             }
         }
         sp = base + pushed;
-        // this wave's sums of the step, per octant
-        if (lane < 8) sh.part[wv][lane] = 0.0;
+        // this wave's sums of the step, per octant: into the shared partials when
+        // the block walks, into S (and acc) directly when the wave walks alone
+        if constexpr (SHARED) {
+            if (lane < 8) sh.part[wv][lane] = 0.0;
+        }
         auto add_step = [&](int d, double v) {   // wave-uniform d and v
-            if (lane == 0) sh.part[wv][d] += v;
+            if constexpr (SHARED) {
+                if (lane == 0) sh.part[wv][d] += v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (e == d) S[e] += v;
+                acc += v;
+            }
         };
         // nodes summed by the whole wave
         uint64_t bigmask = __ballot(big);
@@ -1423,16 +1448,18 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
             if (__ballot(pd[d] != 0.0) == 0) continue;
             add_step(d, wave_sum(pd[d]));
         }
-        __syncthreads();
-        // every wave adds the waves' sums in wave order: identical totals
+        if constexpr (SHARED) {
+            __syncthreads();
+            // every wave adds the waves' sums in wave order: identical totals
 #pragma unroll
-        for (int w = 0; w < NW; ++w)
+            for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                S[d] += sh.part[w][d];
-                acc += sh.part[w][d];
-            }
-        __syncthreads();
+                for (int d = 0; d < 8; ++d) {
+                    S[d] += sh.part[w][d];
+                    acc += sh.part[w][d];
+                }
+        }
+        sync();
     }
     if (!lead) return;
     double total = 0.0;
@@ -1477,17 +1504,28 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
 }
 
 // Blocks take the queries of the walk, coarsest query nodes first (their walks
-// are the longest, so they start early): block b the queries b, b + blocks, ...
+// are the longest, so they start early).  With at most four walks per block,
+// each walk takes a whole block; otherwise every wavefront walks queries on its
+// own: wavefront i the queries i, i + waves, ...
 template <int P>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_partner(WalkArgs a) {
     __shared__ WalkShared sh;
     const int32_t *tally = a.qorder + (size_t)kMaxLevels * a.nq;
     int64_t nwalk = 0;
     for (int l = 0; l < kMaxLevels; ++l) nwalk += tally[l];
-    for (int64_t b = blockIdx.x; b < nwalk; b += gridDim.x) {
-        __syncthreads();   // the previous query's shared state is no longer read
-        walk_query<P>(a, walk_query_at(a.qorder, a.nq, b), sh, threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    if (nwalk <= 4 * (int64_t)gridDim.x) {
+        // few walks: each takes a whole block, block b the queries b, b + blocks, ...
+        for (int64_t b = blockIdx.x; b < nwalk; b += gridDim.x) {
+            __syncthreads();   // the previous query's shared state is no longer read
+            walk_query<P, true>(a, walk_query_at(a.qorder, a.nq, b), sh, wv);
+        }
+        return;
     }
+    // many walks: one wavefront each, every wavefront going on to its next query alone
+    const int64_t stride = (int64_t)gridDim.x * kWalkWaves;
+    for (int64_t i = (int64_t)blockIdx.x * kWalkWaves + wv; i < nwalk; i += stride)
+        walk_query<P, false>(a, walk_query_at(a.qorder, a.nq, i), sh, wv);
 }
 
 // The walk's queries (valid ones whose node has children and more than
