@@ -284,6 +284,15 @@ def _batch_bench(args, dev, oracle_threads):
         grads = b.backward(w, gone, sig, is_target=tg, p=args.p, out=grads, use_graph=True)
     torch.cuda.synchronize()
     ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
+    # the same forward and forward + backward with the translation as split bfloat16
+    # products (graph replays)
+    u16 = torch.empty_like(u)
+    b.forward(w, sig, is_target=tg, p=args.p, out=u16, m2l="bf16x3")
+    ms_graph16 = _timed(lambda: b.forward(w, sig, is_target=tg, p=args.p, out=u16, m2l="bf16x3"), args.steps)
+    g16 = b.backward(w, gone, sig, is_target=tg, p=args.p, use_graph=True, m2l="bf16x3")
+    ms_fb16 = _timed(lambda: (b.forward(w, sig, is_target=tg, p=args.p, out=u16, m2l="bf16x3"),
+                              b.backward(w, gone, sig, is_target=tg, p=args.p, out=g16, use_graph=True,
+                                         m2l="bf16x3")), args.steps)
     res = {"workload": "256 populations, n log-uniform 1024-65536, sigma log-uniform 50-300 um, 1 mm cubes",
            "points": int(off[-1]), "targets": n_tgt, "autotune_s": tune_s,
            "routes": {"fgt": routes.count("fgt"), "direct": routes.count("direct")},
@@ -291,7 +300,8 @@ def _batch_bench(args, dev, oracle_threads):
            "forward_ms_graph": ms_graph, "forward_ms_eager": ms_eager,
            "sums_per_s": n_tgt / (ms_graph / 1000.0), "launches_per_forward_eager": launches,
            "instance_ms_p50": float(np.percentile(inst, 50)), "instance_ms_p99": float(np.percentile(inst, 99)),
-           "fwd_bwd_ms": ms_fb}
+           "fwd_bwd_ms": ms_fb,
+           "m2l_bf16x3": {"forward_ms_graph": ms_graph16, "fwd_bwd_ms": ms_fb16}}
     if not args.no_check:
         import oracle
         u_h = u.cpu().numpy()
@@ -305,6 +315,16 @@ def _batch_bench(args, dev, oracle_threads):
         e = np.concatenate(errs)
         res["accuracy"] = {"targets_checked": int(e.size), "max_rel_err": float(e.max()), "bar": 1e-4,
                            "pass": bool(e.max() <= 1e-4)}
+        u16_h = u16.cpu().numpy()
+        e16 = []
+        for k in synth.sample_indices(len(pops), 32, seed=783):
+            wl = pops[k]
+            tgt = np.nonzero(wl.a > 0)[0]
+            sel = tgt[synth.sample_indices(tgt.size, 8, seed=784 + int(k))]
+            ref = oracle.attraction(wl, sel, threads=oracle_threads)
+            e16.append(np.abs(u16_h[off[k]:off[k + 1]][sel].astype(np.float64) - ref) / ref)
+        e16 = np.concatenate(e16)
+        res["m2l_bf16x3"]["max_rel_err"] = float(e16.max())
     b.close()
     return res
 

@@ -413,8 +413,9 @@ int msp_batch_autotune(msp_batch *b, const float *x, const float *y, const float
 /* Forward of every population (as msp_fgt_forward on its slice).  sigma: host
  * float32[npop] (prm->sigma is ignored); the other fields of prm apply to all.
  * use_graph = 0 runs eagerly every time.  The batched translation runs on the
- * fp32 matrix cores on one level: MSP_M2L_VALU, MSP_M2L_BF16X3, MSP_TWO_LEVEL and
- * the partner flags give MSP_ENOTSUP here and in msp_batch_backward and
+ * matrix cores on one level, in fp32 or (MSP_M2L_BF16X3, p = 8 only) as split
+ * bfloat16 products; MSP_M2L_VALU, MSP_TWO_LEVEL, MSP_M2L_BF16X3 with p != 8 and
+ * the weight-staging flags give MSP_ENOTSUP here and in msp_batch_backward and
  * msp_batch_autotune. */
 int msp_batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const float *sigma,
                       const msp_fgt_params *prm, float *u_out, int32_t use_graph, void *stream);

@@ -573,12 +573,14 @@ void msp_batch_destroy(msp_batch *b) {
     delete b;
 }
 
-// the batched kernels run the single-level fp32 matrix-core translation only, and
-// partner flags have no meaning for a batch
+// the batched kernels translate on the matrix cores on one level (fp32, or split
+// bfloat16 at p = 8), and the weight-staging flags have no meaning for a batch
 static int check_batch_flags(const msp_fgt_params *prm) {
-    const uint32_t bad = prm->flags & (uint32_t)(MSP_M2L_VALU | MSP_M2L_BF16X3 | MSP_TWO_LEVEL |
-                                                 MSP_WEIGHTS_STAGED | MSP_STAGE_WEIGHTS);
+    const uint32_t bad = prm->flags & (uint32_t)(MSP_M2L_VALU | MSP_TWO_LEVEL | MSP_WEIGHTS_STAGED |
+                                                 MSP_STAGE_WEIGHTS);
     if (bad) return fail(MSP_ENOTSUP, "flags 0x%x are not supported by the batch entry points", bad);
+    if ((prm->flags & MSP_M2L_BF16X3) && prm->p != 8)
+        return fail(MSP_ENOTSUP, "split-bfloat16 translation in a batch is not supported for p != 8");
     return MSP_OK;
 }
 

@@ -285,12 +285,15 @@ int prepare_fgt(msp_batch *b, const std::vector<PopPlan> &plans, const float *w,
         grid_off.push_back(grid_off.back() + (int64_t)f.G[0] * f.G[1] * f.G[2] * p * p * p);
     }
     // M2L as whole-K GEMM tiles when every population's operator and tile fit in LDS
+    const bool split = !plans.empty() && (plans[0].prm.flags & MSP_M2L_BF16X3) != 0;
     size_t gemm_lds = 0;
     for (const FgtPop &f : fp) {
-        const size_t l = fgt_pop_gemm_lds(f, p);
+        const size_t l = fgt_pop_gemm_lds(f, p, split);
         gemm_lds = l > gemm_lds ? l : gemm_lds;
     }
     const bool gemm = gemm_lds <= 64 * 1024;
+    if (split && !fp.empty() && (p != 8 || !gemm))
+        return fail(MSP_ENOTSUP, "split-bfloat16 translation in a batch needs p = 8 and tiles that fit in LDS");
     for (const FgtPop &f : fp)
         for (int pass = 0; pass < 3; ++pass)
             tile_off[pass].push_back(tile_off[pass].back() + fgt_pop_tiles(f, p, pass, gemm));
@@ -303,6 +306,7 @@ int prepare_fgt(msp_batch *b, const std::vector<PopPlan> &plans, const float *w,
     bp.p = p;
     bp.cus = b->cus;
     bp.gemm = gemm ? 1 : 0;
+    bp.split = split ? 1 : 0;
     bp.gemm_lds = gemm_lds;
     if (nf > 0) {
         int64_t *off = foff.as<int64_t>();

@@ -457,6 +457,33 @@ __global__ void __launch_bounds__(64) k_m2l_pass_mfma(const float *In, float *Ou
     m2l_tile_mfma(In, Out, R, p, G, T, (int64_t)blockIdx.x * MT, (int)blockIdx.y * MT);
 }
 
+// Split bfloat16 products (v_mfma_f32_16x16x32_bf16): each FP32 operand x is
+// split into hi = bf16(x) and lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi is
+// accumulated in FP32.  The dropped lo*lo term and the rounding of lo leave about
+// 2^-16 of each product.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+constexpr int MK2 = 32;
+
+__device__ inline unsigned short bf16_bits(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline void split_bf16(const float *src, int stride, bf16x8 &hi, bf16x8 &lo) {
+    u16x8 h, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float x = src[j * stride];
+        const unsigned short hb = bf16_bits(x);
+        h[j] = hb;
+        l[j] = bf16_bits(x - __uint_as_float((uint32_t)hb << 16));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
 // The same pass with the whole contraction in LDS: a block of four waves takes RT
 // rows r of In (all U columns, staged once) and the operator table T of the axis,
 // and produces Out[v][r] for every v.  Each wave owns 16-row slices of v: it keeps
@@ -470,6 +497,16 @@ __host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
     return ((size_t)RT * (U + 1) + nT + (nT & 1)) * 4 + (size_t)RT * 8 + (size_t)U * 4;
 }
 
+// The split bfloat16 form of the tile (p = 8): the RT input rows and the operator
+// table as hi and lo bfloat16 planes, rows padded to whole 32-term K steps plus 8.
+__host__ __device__ inline int m2l_split_row(int U) { return ((U + 31) / 32) * 32 + 8; }
+__host__ __device__ inline size_t m2l_gemm_lds_split(int U, int G, int RT) {
+    const size_t nT = (size_t)(2 * G - 1) * 64;
+    size_t b = (size_t)RT * m2l_split_row(U) * 4 + nT * 4;   // two 2-byte planes each
+    b = (b + 15) & ~(size_t)15;
+    return b + (size_t)RT * 8;
+}
+
 // Grid layouts.  The M2L passes read rows along one axis of the interleaved layout
 // [kz p + az][ky p + ay][kx p + ax].  The batched route keeps the moment and Taylor
 // grids cell-major instead, [kz][ky][kx][az][ay][ax], so that one cell's p^3
@@ -477,9 +514,135 @@ __host__ __device__ inline size_t m2l_gemm_lds(int U, int G, int p, int RT) {
 // cell-major moments, and its z pass (MODE 2) takes its rows in cell-column order
 // (ky, kx, ay, ax) and writes the cell-major Taylor grid.  Ga: the grid's cells along
 // y (MODE 1) or x (MODE 2).
-template <int RT, int MODE = 0, int PT = 0>
+// m2l_gemm_tile with split bfloat16 products (p = 8): every staged input and
+// operator entry x is split once into hi = bf16(x) and lo = bf16(x - hi), and each
+// 16 x 16 output tile accumulates hi*hi + hi*lo + lo*hi over 32-term K steps with
+// v_mfma_f32_16x16x32_bf16 (four cells of eight terms per step).  Lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j < 8, and receives
+// D[4 (l / 16) + i][l % 16]: one operator row of one cell and eight consecutive
+// terms of one input row, each one 16-byte read from LDS.
+template <int RT, int MODE>
+__device__ void m2l_gemm_tile_split(const float *In, float *Out, int64_t R, int G, const float *T, int64_t r0,
+                                    float *sm, int Ga, int band) {
+    constexpr int NR = RT / 16;
+    constexpr int p = 8, pp = 64, p3 = 512;
+    const int U = G * p;
+    const int UH = m2l_split_row(U);
+    const int nT = (2 * G - 1) * pp;
+    unsigned short *sInH = reinterpret_cast<unsigned short *>(sm);
+    unsigned short *sInL = sInH + (size_t)RT * UH;
+    unsigned short *sTH = sInL + (size_t)RT * UH;
+    unsigned short *sTL = sTH + nT;
+    int64_t *rowbase = reinterpret_cast<int64_t *>(
+        reinterpret_cast<char *>(sm) + ((((size_t)RT * UH * 4 + (size_t)nT * 4) + 15) & ~(size_t)15));
+    auto put = [](unsigned short *h, unsigned short *l, float x) {
+        const unsigned short hb = bf16_bits(x);
+        *h = hb;
+        *l = bf16_bits(x - __uint_as_float((uint32_t)hb << 16));
+    };
+    for (int e = threadIdx.x; e < nT; e += 256) put(sTH + e, sTL + e, T[e]);
+    if constexpr (MODE != 0) {
+        for (int rr = threadIdx.x; rr < RT; rr += 256) {
+            const int64_t r = r0 + rr;
+            int64_t b = -1;
+            if (r < R) {
+                if constexpr (MODE == 1) {
+                    const int Uy = Ga * 8;
+                    const int zq = (int)(r / Uy), yq = (int)(r % Uy);
+                    b = ((int64_t)(zq >> 3) * Ga + (yq >> 3)) * G * 512 + ((zq & 7) * 8 + (yq & 7)) * 8;
+                } else {
+                    const int c = (int)(r >> 6), rem = (int)(r & 63);
+                    b = ((int64_t)((c / Ga) * 8 + (rem >> 3)) * Ga * 8 + (c % Ga) * 8 + (rem & 7)) * U;
+                }
+            }
+            rowbase[rr] = b;
+        }
+        __syncthreads();
+    }
+    // input rows in 16-byte chunks (a chunk never straddles a cell), zeros past U
+    const int U4 = UH / 4;
+    for (int e = threadIdx.x; e < RT * U4; e += 256) {
+        const int rr = e / U4, c4 = e - rr * U4;
+        const int64_t r = r0 + rr;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (4 * c4 < U) {
+            if constexpr (MODE == 0) {
+                if (r < R) v = *reinterpret_cast<const float4 *>(In + r * U + 4 * c4);
+            } else {
+                const int64_t b = rowbase[rr];
+                const int64_t col = MODE == 1 ? (int64_t)(c4 >> 1) * 512 + (c4 & 1) * 4 : 4 * c4;
+                if (b >= 0) v = *reinterpret_cast<const float4 *>(In + b + col);
+            }
+        }
+        unsigned short *dh = sInH + (size_t)rr * UH + 4 * c4, *dl = sInL + (size_t)rr * UH + 4 * c4;
+        put(dh, dl, v.x);
+        put(dh + 1, dl + 1, v.y);
+        put(dh + 2, dl + 2, v.z);
+        put(dh + 3, dl + 3, v.w);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nk = (U + 31) / 32;   // 32-term K steps
+    const int nv = (U + 15) / 16;
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+    for (int vc = wave; vc < nv; vc += 4) {
+        const int v = vc * 16 + (lane & 15);
+        const int tv = v / p, b = v % p;
+        f32x4 acc[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        int kb = 0, ke = nk;
+        if (band < G - 1) {
+            const int vlast = vc * 16 + 15 < U ? vc * 16 + 15 : U - 1;
+            const int c_lo = (vc * 16) / p - band, c_hi = vlast / p + band;
+            kb = (c_lo > 0 ? c_lo : 0) / 4;
+            const int c_end = c_hi + 1 < G ? c_hi + 1 : G;
+            ke = (c_end + 3) / 4 < nk ? (c_end + 3) / 4 : nk;
+        }
+        for (int ks = kb; ks < ke; ++ks) {
+            const int sc = 4 * ks + (lane >> 4);   // the cell of this lane's eight terms
+            bf16x8 ah = zero8, al = zero8;
+            if (v < U && sc < G) {
+                const int row = ((tv - sc + G - 1) * p + b) * p;
+                ah = *reinterpret_cast<const bf16x8 *>(sTH + row);
+                al = *reinterpret_cast<const bf16x8 *>(sTL + row);
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const size_t o = (size_t)(16 * j + (lane & 15)) * UH + 32 * ks + 8 * (lane >> 4);
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sInH + o);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sInL + o);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int vo = vc * 16 + 4 * (lane >> 4) + i;
+                const int64_t r = r0 + 16 * j + (lane & 15);
+                if (vo < U && r < R) {
+                    if constexpr (MODE == 2) {
+                        const int q = (int)r;
+                        Out[(int64_t)(vo / p) * R * p + (vo % p) * pp + (int64_t)(q / pp) * p3 + q % pp] = acc[j][i];
+                    } else {
+                        Out[(int64_t)vo * R + r] = acc[j][i];
+                    }
+                }
+            }
+    }
+}
+
+template <int RT, int MODE = 0, int PT = 0, bool SPLIT = false>
 __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, int G, const float *T, int64_t r0,
                               float *sm, int Ga = 0, int band = 1 << 30) {
+    if constexpr (SPLIT) {
+        static_assert(PT == 8, "the split bfloat16 tile is built for p = 8");
+        m2l_gemm_tile_split<RT, MODE>(In, Out, R, G, T, r0, sm, Ga, band);
+        return;
+    }
     // PT = 8: the term count is a compile-time 8, so the tile's index arithmetic
     // folds into constants and rows are read 16 bytes at a time; PT = 0: any p
     constexpr int NR = RT / 16;   // 16-wide column tiles per block
@@ -657,34 +820,18 @@ __global__ void __launch_bounds__(256) k_m2l_gemm(const float *In, float *Out, i
     else m2l_gemm_tile<RT>(In, Out, R, p, G, T, (int64_t)blockIdx.x * RT, sm, 0, band);
 }
 
-// The same pass with split bfloat16 products (v_mfma_f32_16x16x32_bf16): each
-// FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi), and
-// hi*hi + hi*lo + lo*hi is accumulated in FP32.  The dropped lo*lo term and the
-// rounding of lo leave about 2^-16 of each product.  A lane supplies eight
-// consecutive k of its row of A and of its column of B (the same k for both).
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-constexpr int MK2 = 32;
-
-__device__ inline unsigned short bf16_bits(float f) {   // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+// The whole-K tile with split bfloat16 products (p = 8).
+template <int RT>
+__global__ void __launch_bounds__(256) k_m2l_gemm_bf16x3(const float *In, float *Out, int64_t R, int G,
+                                                         const float *T, int band) {
+    extern __shared__ float sm[];
+    m2l_gemm_tile<RT, 0, 8, true>(In, Out, R, 8, G, T, (int64_t)blockIdx.x * RT, sm, 0, band);
 }
 
-__device__ inline void split_bf16(const float *src, int stride, bf16x8 &hi, bf16x8 &lo) {
-    u16x8 h, l;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float x = src[j * stride];
-        const unsigned short hb = bf16_bits(x);
-        h[j] = hb;
-        l[j] = bf16_bits(x - __uint_as_float((uint32_t)hb << 16));
-    }
-    hi = __builtin_bit_cast(bf16x8, h);
-    lo = __builtin_bit_cast(bf16x8, l);
-}
-
+// The split bfloat16 pass for any p, 32 x 32 output tiles: each K step builds the
+// operator tile from T and splits both operands in registers; a lane supplies
+// eight consecutive k of its row of A and of its column of B (the same k for
+// both).  Used where the whole-K tile does not apply (p != 8, or too little LDS).
 __global__ void __launch_bounds__(64) k_m2l_pass_bf16x3(const float *In, float *Out, int64_t R, int p,
                                                         int G, const float *T) {
     __shared__ float sA[MT][MK2 + 1];   // operator rows v, columns u
@@ -1793,7 +1940,14 @@ __global__ void __launch_bounds__(256) k_bm2l_gemm(FgtBatchPlan bp) {
     const int p = bp.p;
     const int64_t Ux = (int64_t)f.G[0] * p, Uy = (int64_t)f.G[1] * p, Uz = (int64_t)f.G[2] * p;
     const int64_t r0 = (g - bp.tile_off[PASS][k]) * 32;
-    if (p == 8) {
+    if (p == 8 && bp.split) {
+        if constexpr (PASS == 0)
+            m2l_gemm_tile<32, 1, 8, true>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1], f.band[0]);
+        else if constexpr (PASS == 1)
+            m2l_gemm_tile<32, 0, 8, true>(f.B, f.Tmp, Ux * Uz, p, f.G[1], f.opsy, r0, sm, 0, f.band[1]);
+        else
+            m2l_gemm_tile<32, 2, 8, true>(f.Tmp, f.B, Uy * Ux, p, f.G[2], f.opsz, r0, sm, f.G[0], f.band[2]);
+    } else if (p == 8) {
         if constexpr (PASS == 0)
             m2l_gemm_tile<32, 1, 8>(f.A, f.B, Uz * Uy, p, f.G[0], f.opsx, r0, sm, f.G[1], f.band[0]);
         else if constexpr (PASS == 1)
@@ -2189,10 +2343,10 @@ int64_t fgt_pop_tiles(const FgtPop &f, int p, int pass, bool gemm) {
     return ((R + MT - 1) / MT) * ((U[pass] + MT - 1) / MT);
 }
 
-size_t fgt_pop_gemm_lds(const FgtPop &f, int p) {
+size_t fgt_pop_gemm_lds(const FgtPop &f, int p, bool split) {
     size_t m = 0;
     for (int k = 0; k < 3; ++k) {
-        const size_t l = m2l_gemm_lds(f.G[k] * p, f.G[k], p, 32);
+        const size_t l = split ? m2l_gemm_lds_split(f.G[k] * p, f.G[k], 32) : m2l_gemm_lds(f.G[k] * p, f.G[k], p, 32);
         m = l > m ? l : m;
     }
     return m;
@@ -2322,12 +2476,31 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
             dim3 grid((unsigned)((ps.R + TR - 1) / TR), (unsigned)((ps.U + TV - 1) / TV));
             hipLaunchKernelGGL(k_m2l_pass, grid, dim3(kBlock), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
         } else if (bf16x3) {
-            dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
-            hipLaunchKernelGGL(k_m2l_pass_bf16x3, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
-        } else {
-            // rows per block: enough blocks to fill the chip, at most 64
+            // rows per block: enough blocks to fill the chip, at most 64, and fewer
+            // when the tile would not fit in LDS
             int RT = 64;
-            while (RT > 16 && (ps.R + RT - 1) / RT < 1024) RT >>= 1;
+            while (RT > 16 && ((ps.R + RT - 1) / RT < 1024 || m2l_gemm_lds_split((int)ps.U, ps.G, RT) > 64 * 1024))
+                RT >>= 1;
+            const size_t lds = m2l_gemm_lds_split((int)ps.U, ps.G, RT);
+            if (p == 8 && lds <= 64 * 1024) {
+                const dim3 grid((unsigned)((ps.R + RT - 1) / RT));
+                const int band = m2l_band(p, step, ps.G);
+                if (RT == 64)
+                    hipLaunchKernelGGL(k_m2l_gemm_bf16x3<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, ps.G, ps.T, band);
+                else if (RT == 32)
+                    hipLaunchKernelGGL(k_m2l_gemm_bf16x3<32>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, ps.G, ps.T, band);
+                else
+                    hipLaunchKernelGGL(k_m2l_gemm_bf16x3<16>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, ps.G, ps.T, band);
+            } else {
+                dim3 grid((unsigned)((ps.R + MT - 1) / MT), (unsigned)((ps.U + MT - 1) / MT));
+                hipLaunchKernelGGL(k_m2l_pass_bf16x3, grid, dim3(64), 0, s, ps.in, ps.out, ps.R, p, ps.G, ps.T);
+            }
+        } else {
+            // rows per block: enough blocks to fill the chip, at most 64, and fewer
+            // when the tile would not fit in LDS
+            int RT = 64;
+            while (RT > 16 && ((ps.R + RT - 1) / RT < 1024 || m2l_gemm_lds((int)ps.U, ps.G, p, RT) > 64 * 1024))
+                RT >>= 1;
             const size_t lds = m2l_gemm_lds((int)ps.U, ps.G, p, RT);
             if (lds <= 64 * 1024) {
                 const dim3 grid((unsigned)((ps.R + RT - 1) / RT));

@@ -291,6 +291,7 @@ struct FgtBatchPlan {
     int cus;
     int gemm;          // M2L passes as whole-K GEMM tiles of 32 rows with cell-major grids
                        // (else 32 x 32 tiles on interleaved grids)
+    int split;         // the GEMM tiles with split bfloat16 products (p = 8)
     size_t gemm_lds;   // dynamic LDS of the GEMM tiles (largest population)
 };
 
@@ -417,7 +418,7 @@ struct FgtPlan {
 // fgt.hip: grid buffers of a population (allocated here) and the batched forward
 int fgt_pop_prepare(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, FgtPop *out);
 int64_t fgt_pop_tiles(const FgtPop &f, int p, int pass, bool gemm);
-size_t fgt_pop_gemm_lds(const FgtPop &f, int p);
+size_t fgt_pop_gemm_lds(const FgtPop &f, int p, bool split = false);
 int fgt_batch_forward(const FgtBatchPlan &bp, hipStream_t s);
 // value, gradient and (want_lap) Laplacian of every population's field at all its
 // points, into f.rec + i * stride + slot (key order i)

@@ -130,18 +130,20 @@ def test_new_entry_points_check_arguments(lib):
 
 
 def test_batch_refuses_flags_it_does_not_honour(lib):
-    """The batched kernels run one fp32 matrix-core translation level: the
-    split-bf16, vector and two-level flags are refused, not silently ignored."""
+    """The batched kernels translate on the matrix cores on one level (fp32, or
+    split bf16 at p = 8): the vector and two-level flags, split bf16 at other p and
+    the staging flags are refused, not silently ignored."""
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.msp_last_error.restype = ctypes.c_char_p
     lib.msp_batch_forward.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Params), vp, i32, vp]
     lib.msp_batch_backward.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Params), vp, vp, vp, vp, vp, vp,
                                        i32, vp]
-    for flag in (2, 4, 8, 16, 32):   # M2L_VALU, TWO_LEVEL, M2L_BF16X3, WEIGHTS_STAGED, STAGE_WEIGHTS
-        prm = _Params(8, -1, 100.0, 4.5, 0, flag)
+    for p_, flag in ((8, 2), (8, 4), (6, 8), (8, 16), (8, 32)):   # M2L_VALU, TWO_LEVEL, M2L_BF16X3 at
+        prm = _Params(p_, -1, 100.0, 4.5, 0, flag)                 # p != 8, WEIGHTS_STAGED, STAGE_WEIGHTS
         assert lib.msp_batch_forward(None, None, None, None, ctypes.byref(prm), None, 1, None) == -5
         assert b"not supported" in lib.msp_last_error()
         assert lib.msp_batch_backward(None, None, None, None, ctypes.byref(prm), None, None, None, None, None,
                                       None, 0, None) == -5
-    prm = _Params(8, -1, 100.0, 4.5, 0, 1)   # EXCLUDE_SELF is honoured
-    assert lib.msp_batch_forward(None, None, None, None, ctypes.byref(prm), None, 1, None) == -1
+    for flag in (1, 8):   # EXCLUDE_SELF and (at p = 8) M2L_BF16X3 are honoured
+        prm = _Params(8, -1, 100.0, 4.5, 0, flag)
+        assert lib.msp_batch_forward(None, None, None, None, ctypes.byref(prm), None, 1, None) == -1

@@ -268,3 +268,42 @@ def test_batch_forward_and_backward_graphs_alternate(pops):
             np.testing.assert_array_equal(out["pos"][a].cpu().numpy(), g_ref["pos"][a])
         torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_split_bf16_translation(pops):
+    """Split-bfloat16 translation in the batched route (p = 8): forward and
+    backward within the split's rounding of the fp32 batch, the forward within
+    1e-4 of the oracle; p != 8 is refused."""
+    import torch
+    import paper_2301_10570_amd as msp
+    print("batch forward/backward with split bf16 M2L", flush=True)
+    sub = pops[:8]
+    x, y, z, w, tg, off, sig = _concat(sub)
+    b = msp.Batch().build(x, y, z, off)
+    u32 = b.forward(w, sig, is_target=tg, use_graph=False).cpu().numpy()
+    u16 = b.forward(w, sig, is_target=tg, use_graph=False, m2l="bf16x3").cpu().numpy()
+    tgt = tg.cpu().numpy() > 0
+    d = np.abs(u16[tgt].astype(np.float64) - u32[tgt]) / np.abs(u32[tgt])
+    print(f"  forward: max rel diff from fp32 {d.max():.2e}")
+    assert d.max() <= 5e-5
+    errs = []
+    for k in range(len(sub)):
+        wl = sub[k]
+        t_k = np.nonzero(wl.a > 0)[0]
+        sel = t_k[synth.sample_indices(t_k.size, 16, seed=930 + k)]
+        ref = oracle.attraction(wl, sel)
+        errs.append(rel_err(u16[off[k]:off[k + 1]][sel], ref))
+    e = np.concatenate(errs)
+    print(f"  forward vs oracle: max rel err {e.max():.2e}")
+    assert e.max() <= TOL
+    g = torch.from_numpy(synth.uniforms(x.numel(), 931) + np.float32(0.5)).cuda()
+    r32 = b.backward(w, g, sig, is_target=tg)
+    r16 = b.backward(w, g, sig, is_target=tg, m2l="bf16x3")
+    gw32, gw16 = r32["w"].cpu().numpy(), r16["w"].cpu().numpy()
+    assert np.max(np.abs(gw16 - gw32) / np.abs(gw32)) <= 5e-5
+    s32, s16 = r32["sigma"].cpu().numpy(), r16["sigma"].cpu().numpy()
+    assert np.max(np.abs(s16 - s32) / np.abs(s32)) <= 5e-5
+    with pytest.raises(msp.MspError) as ei:
+        b.forward(w, sig, is_target=tg, p=6, m2l="bf16x3")
+    assert ei.value.code == msp.MSP_ENOTSUP
+    b.close()
