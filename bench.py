@@ -128,14 +128,19 @@ def _descent_bench(args, dev):
     tree = msp.Tree()
     tree.build(T(wl.x), T(wl.y), T(wl.z), leaf_max=wl.leaf_max)
     w, a = T(wl.w), T(wl.a)
-    r = tree.partner_descent(w, a, wl.sigma, 11, p=wl.p)            # first call: allocations
-    torch.cuda.synchronize()
     reps = 3
-    t0 = time.perf_counter()
-    for rep in range(reps):
-        r = tree.partner_descent(w, a, wl.sigma, 11 + rep, p=wl.p)
-    torch.cuda.synchronize()
-    ms = 1000.0 * (time.perf_counter() - t0) / reps
+
+    def timed(cutoff):
+        r = tree.partner_descent(w, a, wl.sigma, 11, p=wl.p, cutoff_sigmas=cutoff)   # first call: allocations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for rep in range(reps):
+            r = tree.partner_descent(w, a, wl.sigma, 11 + rep, p=wl.p, cutoff_sigmas=cutoff)
+        torch.cuda.synchronize()
+        return r, 1000.0 * (time.perf_counter() - t0) / reps
+
+    r0, ms_nocut = timed(0.0)
+    r, ms = timed(4.5)
     ax = r["axon"].cpu().numpy()
     dd = r["dendrite"].cpu().numpy()
     acc = r["accepted"].cpu().numpy().astype(bool)
@@ -146,7 +151,8 @@ def _descent_bench(args, dev):
                         "leaf <= 64, cutoff 4.5 sigma",
             "axon_neurons": int(np.count_nonzero(wl.a > 0)), "requests": int(ax.size),
             "accepted": int(acc.sum()), "steps": int(r["steps"]), "ms_per_descent": ms,
-            "requests_per_s": ax.size / (ms / 1000.0), "valid": ok}
+            "requests_per_s": ax.size / (ms / 1000.0), "valid": ok,
+            "no_cutoff": {"ms_per_descent": ms_nocut, "requests": int(r0["axon"].numel())}}
 
 
 def _timed(fn, steps):

@@ -333,7 +333,20 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
  * r = (mix(mix(seed ^ ((step + 1) * 0x9E3779B97F4A7C15)) ^ item) >> 11) * 2^-53 with
  * mix the SplitMix64 output for a state and item the choosing item (two's
  * complement); all-zero values drop the pair.  Att over the children of an inner
- * node is accumulated from partner queries (the accuracy contract of
+ * node: while both nodes of the pair lie above the box level (one below the
+ * coarsest level whose half side is within rho_max(p) sigma, the level the
+ * expansion route picks), the sum of box-pair attractions over the boxes of S_c
+ * and of C (boxes: the nodes at or below the box level whose parent lies above
+ * it, and the leaves above it).  A box pair is summed directly (float64 offsets
+ * and sums, each exponential to about 1e-7) or,
+ * when both boxes lie at or below the box level, hold more than 70 axons /
+ * dendrites (Algorithm 2's c2 / c1) and their centres are within 2.5 sigma, taken
+ * from the dendrite box's Hermite moments (Eq. (7)) translated to a Taylor
+ * series at the axon box (Eq. (6)) and contracted with the axon box's power
+ * sums; with a cutoff, box pairs whose boxes lie farther apart than
+ * cutoff_sigmas * sigma are left out.  For p > 10, or without a cutoff when the
+ * axon boxes times the dendrite boxes exceed 2^22, and below the box level, Att
+ * is accumulated per axon neuron from partner queries (the accuracy contract of
  * msp_partner_probabilities, prm->cutoff_sigmas applies); over neurons it is
  * summed directly in float64.  w: vacant dendritic elements, a: vacant axonal
  * elements, both device float32[n] in input order (>= 0).  prm: sigma, p and
@@ -368,7 +381,12 @@ int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_f
  *   which 2: node moments of the last partner call, float32 [node - first][az][ay][ax]
  *     for the nodes from the first node of the moment level on (entries of nodes
  *     without moments are unspecified);
- *   which 3: per-node flag of that call (uint8 [n_nodes], 1 = node carries moments).
+ *   which 3: per-node flag of that call (uint8 [n_nodes], 1 = node carries moments);
+ *   which 4: box-pair attractions Att(s, c) of the last msp_partner_descent or
+ *     msp_descent_step call, float64 [npair], pairs grouped by axon box in key order;
+ *   which 5, 6: the axon box and the dendrite box of each pair (int32 [npair], box indices);
+ *   which 7: the tree node of each box (int32 [nbox], boxes in key order);
+ *     4..7 give MSP_ESTATE when that call used no box pairs.
  * *bytes receives the buffer size; if dst (device) is non-NULL and dst_bytes >= *bytes
  * the buffer is copied there on `stream`, otherwise MSP_EINVAL (dst too small). */
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,

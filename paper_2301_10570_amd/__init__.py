@@ -353,12 +353,18 @@ class Tree:
 
     def debug_buffer(self, which: int) -> torch.Tensor:
         """Copy of an internal buffer: 0 moment grid, 1 Taylor grid (last expansion-route
-        forward), 2 node moments, 3 node moment flags (last partner call)."""
+        forward), 2 node moments, 3 node moment flags (last partner call), 4 box-pair
+        attractions, 5 / 6 axon / dendrite box of each pair, 7 node of each box (last
+        descent)."""
         nbytes = ctypes.c_size_t()
         _check(_lib.msp_fgt_debug_buffer(self._h, int(which), None, 0, ctypes.byref(nbytes), None),
                "msp_fgt_debug_buffer")
         if which == 3:
             out = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        elif which == 4:
+            out = torch.empty(nbytes.value // 8, dtype=torch.float64, device="cuda")
+        elif which in (5, 6, 7):
+            out = torch.empty(nbytes.value // 4, dtype=torch.int32, device="cuda")
         else:
             out = torch.empty(nbytes.value // 4, dtype=torch.float32, device="cuda")
         _check(_lib.msp_fgt_debug_buffer(self._h, int(which), out.data_ptr(), nbytes.value,

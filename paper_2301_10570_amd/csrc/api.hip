@@ -530,8 +530,22 @@ int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes
         if (t->node_moments_level < 0) return fail(MSP_ESTATE, "no partner call yet");
         *bytes = which == 2 ? (size_t)t->node_moments_bytes : (size_t)t->n_nodes;
         src = which == 2 ? t->nodeA.p : t->node_hasA.p;
+    } else if (which >= 4 && which <= 7) {
+        if (t->desc_box_level < 0) return fail(MSP_ESTATE, "the last descent used no box pairs");
+        const size_t np = (size_t)t->desc_npair, pa = (np * 4 + 255) / 256 * 256;
+        const char *dp = t->desc_pairs.as<char>();
+        if (which == 4) {
+            *bytes = np * 8;
+            src = dp + 2 * pa;
+        } else if (which == 5 || which == 6) {
+            *bytes = np * 4;
+            src = dp + (which == 6 ? pa : 0);
+        } else {
+            *bytes = (size_t)t->desc_nbox * 4;
+            src = t->desc_box.as<char>() + ((size_t)t->n_nodes * 4 + 255) / 256 * 256;
+        }
     } else {
-        return fail(MSP_EINVAL, "which must be 0..3");
+        return fail(MSP_EINVAL, "which must be 0..7");
     }
     if (!dst) return MSP_OK;
     if (dst_bytes < *bytes) return fail(MSP_EINVAL, "destination holds %zu bytes, need %zu", dst_bytes, *bytes);
@@ -671,7 +685,8 @@ const char *msp_phase_name(int phase) {
                                            "scatter", "node_moments", "partner", "direct",
                                            "backward_combine", "sort_hist", "sort_digit_scan",
                                            "sort_scatter", "node_source_counts", "partner_direct",
-                                           "sort_runs", "partner_wave"};
+                                           "sort_runs", "partner_wave", "descent_boxes", "descent_choose",
+                                           "descent_pairs"};
     if (phase < 0 || phase >= PH_COUNT_) return "";
     return names[phase];
 }

@@ -133,7 +133,7 @@ enum Phase {
     PH_BBOX = 0, PH_KEYS, PH_SORT, PH_LEVELS, PH_NODES, PH_GATHER,
     PH_STAGE, PH_OPS, PH_P2M, PH_M2L_X, PH_M2L_Y, PH_M2L_Z, PH_L2P, PH_LISTS, PH_P2P, PH_SCATTER,
     PH_NODE_MOMENTS, PH_PARTNER, PH_DIRECT, PH_BACKWARD, PH_SORT_HIST, PH_SORT_SCAN, PH_SORT_SCATTER,
-    PH_NODE_COUNTS, PH_PARTNER_DIRECT, PH_SORT_RUNS, PH_PARTNER_WAVE, PH_COUNT_
+    PH_NODE_COUNTS, PH_PARTNER_DIRECT, PH_SORT_RUNS, PH_PARTNER_WAVE, PH_DESC_BOXES, PH_DESC_CHOOSE, PH_DESC_PAIRS, PH_COUNT_
 };
 static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 
@@ -248,6 +248,11 @@ struct msp_tree {
     // copy), query sums, direct sums and choices; kept for the next descent
     msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_choice;
     msp::HostBuf desc_stage;
+    // box-pair attractions of a descent: box table, pair lists and values, box
+    // moments, axon weights in key order
+    msp::DevBuf desc_box, desc_pairs, desc_boxmom, desc_akey, desc_boxatt;
+    int desc_box_level = -1;                  // box level of the last descent (-1: no box pairs)
+    int64_t desc_nbox = 0, desc_npair = 0;
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
 };

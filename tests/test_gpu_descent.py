@@ -162,3 +162,99 @@ def test_degenerate_descents():
     acc = got["accepted"].cpu().numpy().astype(bool)
     dd = got["dendrite"].cpu().numpy()
     assert np.all(np.bincount(dd[acc], minlength=n) <= np.floor(wv))
+
+
+def _clustered():
+    """8 tight blobs of 1,024 neurons (std 12 um, sigma 60 um): the central boxes of
+    the box level hold a few hundred neurons, so box pairs go through expansions."""
+    return synth.blobs(8, 1024, extent=600.0, std=12.0, sigma=60.0, seed=35)
+
+
+def _oracle_boxes(ot, level, wl):
+    """Boxes from the oracle tree: nodes at or below `level` whose parent lies above
+    it, and leaves above it, in key order; with their axon and dendrite counts."""
+    lv, par = ot.level.astype(np.int64), ot.parent.astype(np.int64)
+    parent_above = (par < 0) | (lv[np.maximum(par, 0)] < level)
+    isbox = ((lv >= level) & parent_above) | ((ot.is_leaf == 1) & (lv < level))
+    nodes = np.nonzero(isbox)[0]
+    nodes = nodes[np.argsort(ot.first[nodes], kind="stable")]
+    na = np.array([np.count_nonzero(wl.a[ot.perm[ot.first[v]:ot.first[v] + ot.count[v]]] > 0) for v in nodes])
+    nd = np.array([np.count_nonzero(wl.w[ot.perm[ot.first[v]:ot.first[v] + ot.count[v]]] > 0) for v in nodes])
+    cen = np.array([octree.node_box(ot, int(v))[0] for v in nodes])
+    half = np.array([octree.node_box(ot, int(v))[1] for v in nodes])
+    return nodes, na, nd, cen, half
+
+
+@pytest.mark.parametrize("cutoff", [0.0, 1.5])
+def test_box_pairs_match_oracle(cutoff):
+    """The box table and the pair lists of a descent are exactly those the oracle's
+    tree gives (every axon box against every dendrite box within the cutoff), and
+    every sampled pair attraction matches the oracle's direct Att(s, c): expansions
+    (both boxes at or below the box level, more than 70 axons / dendrites, centres
+    within 2.5 sigma) to 1e-4, direct pairs to 1e-6 (FP64 sums of exponentials
+    taken to about 1e-7)."""
+    wl = _clustered()
+    print(f"box pairs, {wl.n} clustered neurons, cutoff {cutoff} sigma", flush=True)
+    tree, od, w, a = _setup(wl, 32)
+    tree.descent_step(w, a, np.array([0]), np.array([0]), 0, 5, wl.sigma, cutoff_sigmas=cutoff)
+    L = tree.plan(wl.sigma, p=8, route="fgt")["level"] + 1
+    nodes, na, nd, cen, half = _oracle_boxes(od.tree, L, wl)
+    bn = tree.debug_buffer(7).cpu().numpy()
+    np.testing.assert_array_equal(bn, nodes)
+    F = tree.debug_buffer(4).cpu().numpy()
+    ps = tree.debug_buffer(5).cpu().numpy()
+    pc = tree.debug_buffer(6).cpu().numpy()
+    # expected pairs, grouped by axon box, dendrite boxes in key order
+    exp_s, exp_c = [], []
+    for s in np.nonzero(na > 0)[0]:
+        gap = np.maximum(np.abs(cen - cen[s]) - half[:, None] - half[s], 0.0)
+        ok = nd > 0
+        if cutoff > 0:
+            ok &= np.sum(gap * gap, 1) <= (cutoff * wl.sigma) ** 2
+        c = np.nonzero(ok)[0]
+        exp_s += [s] * c.size
+        exp_c += c.tolist()
+    np.testing.assert_array_equal(ps, np.array(exp_s))
+    np.testing.assert_array_equal(pc, np.array(exp_c))
+    lv = od.tree.level[nodes]
+    dist = np.linalg.norm(cen[ps] - cen[pc], axis=1) / wl.sigma
+    expo = (lv[ps] >= L) & (lv[pc] >= L) & (na[ps] > 70) & (nd[pc] > 70) & (dist <= 2.5)
+    ie, idr = np.nonzero(expo)[0], np.nonzero(~expo)[0]
+    assert ie.size >= 20, ie.size
+    pick_e = ie[synth.sample_indices(ie.size, min(ie.size, 120), seed=501)]
+    pick_d = idr[synth.sample_indices(idr.size, min(idr.size, 120), seed=502)]
+    worst_e = worst_d = 0.0
+    for k in np.concatenate([pick_e, pick_d]):
+        ref = od.att(int(nodes[ps[k]]), int(nodes[pc[k]]))
+        e = abs(F[k] - ref) / ref if ref > 0 else abs(F[k])
+        if expo[k]:
+            worst_e = max(worst_e, e)
+            assert e <= 1e-4, (k, F[k], ref)
+        else:
+            worst_d = max(worst_d, e)
+            assert e <= 1e-6, (k, F[k], ref)
+    print(f"  {ps.size} pairs, {ie.size} by expansion; max rel err: expansion {worst_e:.2e}, direct {worst_d:.2e}")
+
+
+def test_clustered_steps_match_oracle():
+    """Step by step on the clustered workload (no cutoff): the steps above the box
+    level choose from box-pair sums, expansions included."""
+    wl = _clustered()
+    print(f"clustered descent steps, {wl.n} neurons", flush=True)
+    tree, od, w, a = _setup(wl, 32)
+    S, T = np.array([0]), np.array([0])
+    seed, flips, total = 91, 0, 0
+    for step in range(4):
+        S2, T2, req = tree.descent_step(w, a, S, T, step, seed, wl.sigma, cutoff_sigmas=0.0)
+        onxt, oreq, dec = od.step(list(zip(S.tolist(), T.tolist())), step, seed)
+        assert sorted(map(tuple, req.tolist())) == sorted(oreq)
+        g, o = set(_pairs(S2, T2)), set(onxt)
+        diff = len(g ^ o) // 2
+        near = sum(1 for _, _, m in dec if m < TIE)
+        assert diff <= near, (step, diff, near)
+        flips += diff
+        total += len(dec)
+        # continue from the oracle's frontier so that both sides see the same pairs
+        S = np.array([s for s, _ in onxt], np.int64)
+        T = np.array([t for _, t in onxt], np.int64)
+    print(f"  {total} choices, {flips} near-tie flips")
