@@ -337,8 +337,9 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
  * coarsest level whose half side is within rho_max(p) sigma, the level the
  * expansion route picks), the sum of box-pair attractions over the boxes of S_c
  * and of C (boxes: the nodes at or below the box level whose parent lies above
- * it, and the leaves above it).  A box pair is summed directly (float64 offsets
- * and sums, each exponential to about 1e-7) or,
+ * it, and the leaves above it).  A box pair is summed directly (each term in
+ * float32 relative to the two boxes' closest approach, to about 1e-5; float64
+ * sums) or,
  * when both boxes lie at or below the box level, hold more than 70 axons /
  * dendrites (Algorithm 2's c2 / c1) and their centres are within 2.5 sigma, taken
  * from the dendrite box's Hermite moments (Eq. (7)) translated to a Taylor
@@ -350,13 +351,16 @@ int msp_partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params 
  * msp_partner_probabilities, prm->cutoff_sigmas applies); over neurons it is
  * summed directly in float64.  w: vacant dendritic elements, a: vacant axonal
  * elements, both device float32[n] in input order (>= 0).  prm: sigma, p and
- * cutoff; self pairs are always skipped.  Synchronises `stream` (the frontier is
- * kept on the host). */
+ * cutoff; self pairs are always skipped.  The frontier stays in device memory and
+ * every step runs in kernels; the call synchronises `stream` while it sets up
+ * (tree topology, box pairs) and at the end, and waits for step k - 2 before it
+ * launches step k. */
 
-/* One step on the host frontier (S_in[k], T_in[k]), k < m: the next frontier goes
- * to S_out/T_out (host int64[cap]; *m_out pairs), the requests to req_axon /
- * req_dendrite (host int32[req_cap], input indices; *n_req).  MSP_ENOSPC when a
- * capacity is exceeded (the counts are still set). */
+/* One step of msp_partner_descent from the frontier (S_in[k], T_in[k]), k < m
+ * (host arrays, copied to the device): the next frontier goes to S_out/T_out
+ * (host int64[cap]; *m_out pairs, dropped pairs left out), the requests to
+ * req_axon / req_dendrite (host int32[req_cap], input indices; *n_req).
+ * MSP_ENOSPC when a capacity is exceeded (the counts are still set). */
 int msp_descent_step(msp_tree *t, const float *w, const float *a, const msp_fgt_params *prm, uint64_t seed,
                      int32_t step, const int64_t *S_in, const int64_t *T_in, int64_t m, int64_t *S_out,
                      int64_t *T_out, int64_t cap, int64_t *m_out, int32_t *req_axon, int32_t *req_dendrite,

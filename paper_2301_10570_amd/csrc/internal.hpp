@@ -244,13 +244,15 @@ struct msp_tree {
     msp::DevBuf partner_qpos; // key-order positions of the last query batch's targets
     msp::DevBuf partner_order; // walk queries by level of the query node (segments), then tallies
     msp::SideStream side;      // the partner walk runs here, beside the direct passes
-    // partner descent: one step's lists (staged in page-locked memory, then one
-    // copy), query sums, direct sums and choices; kept for the next descent
-    msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_choice;
+    // partner descent: frontier, per-pair and per-unit tables, query and task
+    // lists, counters (desc_lists, carved), query sums, direct sums; the frontier
+    // size after each step is copied to desc_stage (page-locked); kept for the
+    // next descent
+    msp::DevBuf desc_lists, desc_raw, desc_probs, desc_dv, desc_prefix;
     msp::HostBuf desc_stage;
     // box-pair attractions of a descent: box table, pair lists and values, box
     // moments, axon weights in key order
-    msp::DevBuf desc_box, desc_pairs, desc_boxmom, desc_akey, desc_boxatt;
+    msp::DevBuf desc_box, desc_pairs, desc_boxmom, desc_akey;
     int desc_box_level = -1;                  // box level of the last descent (-1: no box pairs)
     int64_t desc_nbox = 0, desc_npair = 0;
     int node_moments_level = -1, node_moments_p = 0;
@@ -467,11 +469,12 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
                           const float *uniforms, float *probs, int32_t *choice, hipStream_t s);
 // stage the weights and node moments once; then any number of query batches with
 // the unnormalised per-octant sums (raw: double[nq * 8]); qpos: key-order positions
-// of the targets, or NULL to look them up
+// of the targets, or NULL to look them up; nq_dev (or NULL): the number of queries
+// in device memory, at most nq (the arrays' size)
 int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s);
 int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                       const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
-                      hipStream_t s);
+                      hipStream_t s, const int64_t *nq_dev = nullptr);
 
 // api.hip: msp_fgt_forward with every per-call buffer in the workspace ws (checked
 // against the call's need, MSP_ENOSPC if short), and that need in bytes

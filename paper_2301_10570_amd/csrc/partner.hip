@@ -720,7 +720,8 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
 // of the query are left out as in the walk.  Queries without children to choose
 // from (a leaf node, an invalid target or node) get zeros and choice -1 here.
 __global__ void __launch_bounds__(256)
-k_partner_direct(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
+k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, const int32_t *node_id,
+                 const float *uniforms,
                  int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
                  const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
                  const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
@@ -731,7 +732,7 @@ k_partner_direct(int64_t nq, const int32_t *target_idx, const int32_t *node_id, 
     const int64_t q = g >> 3;
     const int c = (int)(g & 7);
     const int lane = threadIdx.x & 63, gbase = lane & ~7;
-    if (q >= nq) return;   // (the eight lanes of a query leave together)
+    if (q >= (nq_dev ? *nq_dev : nq)) return;   // (the eight lanes of a query leave together)
     int32_t ti = target_idx[q], X = node_id[q], nc = 0, fc = 0;
     bool ok = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
     if (ok) {
@@ -880,7 +881,8 @@ k_partner_direct(int64_t nq, const int32_t *target_idx, const int32_t *node_id, 
 // each lane every 64th point with four of its records in flight, the partial
 // sums per octant added by shuffles.  Other queries return at once.
 __global__ void __launch_bounds__(256)
-k_partner_wave(int64_t nq, const int32_t *target_idx, const int32_t *node_id, const float *uniforms,
+k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, const int32_t *node_id,
+               const float *uniforms,
                int64_t n, int64_t n_nodes, const int32_t *qpos, const int32_t *nlevel,
                const int32_t *nfirst, const int32_t *ncount, const int32_t *nfchild,
                const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
@@ -889,7 +891,7 @@ k_partner_wave(int64_t nq, const int32_t *target_idx, const int32_t *node_id, co
                double *raw) {
     const int64_t q = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (q >= nq) return;
+    if (q >= (nq_dev ? *nq_dev : nq)) return;
     const int32_t ti = target_idx[q], X = node_id[q];
     if (!(ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0)) return;
     const int nc = nnchild[X];
@@ -1540,18 +1542,18 @@ __global__ void k_order_clear(int32_t *tally) {
     if (threadIdx.x < kMaxLevels) tally[threadIdx.x] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_order_place(int64_t nq, const int32_t *target_idx, const int32_t *node_id,
-                                                     int64_t n, int64_t n_nodes, const int32_t *qpos,
-                                                     const int32_t *nlevel, const int32_t *ncount,
-                                                     const int32_t *nfchild, const int32_t *nnchild,
-                                                     int32_t *order) {
+__global__ void __launch_bounds__(256) k_order_place(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx,
+                                                     const int32_t *node_id, int64_t n, int64_t n_nodes,
+                                                     const int32_t *qpos, const int32_t *nlevel,
+                                                     const int32_t *ncount, const int32_t *nfchild,
+                                                     const int32_t *nnchild, int32_t *order) {
     __shared__ int32_t cnt[kMaxLevels], base[kMaxLevels];
     int32_t *tally = order + (size_t)kMaxLevels * nq;
     if (threadIdx.x < kMaxLevels) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int l = -1, slot = 0;
-    if (q < nq) {
+    if (q < (nq_dev ? *nq_dev : nq)) {
         const int32_t ti = target_idx[q], X = node_id[q];
         bool walk = ti >= 0 && ti < n && X >= 0 && X < n_nodes && qpos[q] >= 0;
         if (walk) {
@@ -1644,7 +1646,8 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
 template <int P>
 int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                     const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
-                    int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s) {
+                    int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s,
+                    const int64_t *nq_dev = nullptr) {
     if (nq == 0) return MSP_OK;
     if (!qpos) {   // key-order positions of the targets
         MSP_TRY(t->partner_qpos.ensure((size_t)nq * 4));
@@ -1666,7 +1669,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     int32_t *order = t->partner_order.as<int32_t>();
     hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, order + (size_t)kMaxLevels * nq);
     MSP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, target_idx, node_id,
+    hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, nq_dev, target_idx, node_id,
                        t->n, nn, qpos, t->nlevel.as<int32_t>(), t->ncount.as<int32_t>(),
                        t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), order);
     MSP_CHECK_LAUNCH();
@@ -1698,7 +1701,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     }
     {
         PhaseScope pl(&t->timing, PH_PARTNER_DIRECT, s);
-        hipLaunchKernelGGL(k_partner_direct, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, target_idx,
+        hipLaunchKernelGGL(k_partner_direct, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, nq_dev, target_idx,
                            node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
                            t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                            t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
@@ -1709,7 +1712,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     }
     {
         PhaseScope pw(&t->timing, PH_PARTNER_WAVE, s);
-        hipLaunchKernelGGL(k_partner_wave, dim3(grid_for(nq, 4)), dim3(256), 0, s, nq, target_idx, node_id,
+        hipLaunchKernelGGL(k_partner_wave, dim3(grid_for(nq, 4)), dim3(256), 0, s, nq, nq_dev, target_idx, node_id,
                            uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
                            t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
                            t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0],
@@ -1763,9 +1766,9 @@ int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipS
 
 int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                       const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
-                      hipStream_t s) {
+                      hipStream_t s, const int64_t *nq_dev) {
     switch (prm->p) {
-#define CASE(P) case P: return partner_queries<P>(t, prm, target_idx, node_id, nq, nullptr, probs, nullptr, raw, qpos, s);
+#define CASE(P) case P: return partner_queries<P>(t, prm, target_idx, node_id, nq, nullptr, probs, nullptr, raw, qpos, s, nq_dev);
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE

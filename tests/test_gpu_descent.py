@@ -191,8 +191,8 @@ def test_box_pairs_match_oracle(cutoff):
     tree gives (every axon box against every dendrite box within the cutoff), and
     every sampled pair attraction matches the oracle's direct Att(s, c): expansions
     (both boxes at or below the box level, more than 70 axons / dendrites, centres
-    within 2.5 sigma) to 1e-4, direct pairs to 1e-6 (FP64 sums of exponentials
-    taken to about 1e-7)."""
+    within 2.5 sigma) to 1e-4, direct pairs to 2e-5 (float32 terms relative to
+    the boxes' closest approach, float64 sums)."""
     wl = _clustered()
     print(f"box pairs, {wl.n} clustered neurons, cutoff {cutoff} sigma", flush=True)
     tree, od, w, a = _setup(wl, 32)
@@ -232,7 +232,7 @@ def test_box_pairs_match_oracle(cutoff):
             assert e <= 1e-4, (k, F[k], ref)
         else:
             worst_d = max(worst_d, e)
-            assert e <= 1e-6, (k, F[k], ref)
+            assert e <= 2e-5, (k, F[k], ref)
     print(f"  {ps.size} pairs, {ie.size} by expansion; max rel err: expansion {worst_e:.2e}, direct {worst_d:.2e}")
 
 
