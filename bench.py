@@ -26,7 +26,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12}
+PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12, "fp64_vector": 78.6e12}
+# work model of the partner kernels (per unit of counted work)
+PAIR_FLOPS = 12.0        # float64 offsets, square, scale, exponential (as one), weight, sum
+PAIR_BYTES = 16.0        # the point record (x, y, z, staged w)
+NODE_BYTES = 36.0        # level, cell coordinates, first point, count, children, moment flag
+def m2p_flops(p):        # Hermite rows (3 p recurrence steps) and the p^3 contraction, 2 per multiply-add
+    return 2.0 * p ** 3 + 2.0 * p * p + 2.0 * p + 9.0 * p
 
 
 # phase -> kernel it times (one kernel per launch of the phase)
@@ -62,9 +68,20 @@ def _algorithmic(phase, ctx):
     if phase == "sort_runs":
         # (key, index) read and written once, positions gathered into key order
         return "hbm", "GB/s", n * (24.0 + 32.0)
-    if phase in ("partner", "partner_direct", "partner_wave"):
-        # per query: target, node and uniform in, 8 probabilities and the choice out
-        return "hbm", "GB/s", ctx["queries"] * (12.0 + 36.0)
+    if phase in ("partner_direct", "partner_wave"):
+        # the counted point pairs, each in float64 (bound by the vector units)
+        pairs = ctx["work"]["direct_pairs" if phase == "partner_direct" else "wave_pairs"]
+        return "alu64", "TFLOP/s", pairs * PAIR_FLOPS
+    if phase == "partner":
+        # the walk: node records, moment blocks and point records it must read, and
+        # its arithmetic; the bound is whichever needs more time at peak
+        wk = ctx["work"]
+        nbytes = wk["walk_nodes"] * NODE_BYTES + wk["walk_expansions"] * 4.0 * p3 + wk["walk_pairs"] * PAIR_BYTES
+        t_alu = wk["walk_pairs"] * PAIR_FLOPS / PEAK["fp64_vector"] + wk["walk_expansions"] * m2p_flops(p) / PEAK["fp32_vector"]
+        if nbytes / PEAK["hbm"] >= t_alu:
+            return "hbm", "GB/s", nbytes
+        # flops at the float64 rate that take the same time at peak
+        return "alu64", "TFLOP/s", t_alu * PEAK["fp64_vector"]
     if phase == "sort_hist":
         return "hbm", "GB/s", n * 8.0
     if phase == "morton":
@@ -72,6 +89,37 @@ def _algorithmic(phase, ctx):
     if phase == "stage":
         return "hbm", "GB/s", n * (4 + 1 + 4 + 16 + 1.0)
     return None
+
+
+def _partner_work(work, p, phases, steps):
+    """The partner kernels' counted work per step, what it costs at each unit's
+    peak, and the measured time: the 8-outputs-per-query figure beside the work
+    the queries actually did."""
+    def ms_of(ph):
+        return phases[ph][0] / steps if ph in phases else None
+    out = {"counts": work, "outputs_bytes": (work["direct_queries"] + work["wave_queries"] + work["walk_queries"]) * 36.0}
+    for name, ph, pairs in (("eight_lane_pass", "partner_direct", work["direct_pairs"]),
+                            ("wavefront_pass", "partner_wave", work["wave_pairs"])):
+        out[name] = {"kernel": "k_partner_direct" if ph == "partner_direct" else "k_partner_wave",
+                     "pairs": pairs, "flops64": pairs * PAIR_FLOPS, "bytes": pairs * PAIR_BYTES,
+                     "t_alu_ms": 1e3 * pairs * PAIR_FLOPS / PEAK["fp64_vector"],
+                     "t_hbm_ms": 1e3 * pairs * PAIR_BYTES / PEAK["hbm"], "measured_ms": ms_of(ph)}
+    nb = work["walk_nodes"] * NODE_BYTES + work["walk_expansions"] * 4.0 * p ** 3 + work["walk_pairs"] * PAIR_BYTES
+    out["walk"] = {"kernel": "k_partner", "queries": work["walk_queries"], "nodes": work["walk_nodes"],
+                   "expansions": work["walk_expansions"], "expansion_flops32": work["walk_expansions"] * m2p_flops(p),
+                   "pairs": work["walk_pairs"], "pair_flops64": work["walk_pairs"] * PAIR_FLOPS, "bytes": nb,
+                   "t_alu_ms": 1e3 * (work["walk_pairs"] * PAIR_FLOPS / PEAK["fp64_vector"]
+                                      + work["walk_expansions"] * m2p_flops(p) / PEAK["fp32_vector"]),
+                   "t_hbm_ms": 1e3 * nb / PEAK["hbm"],
+                   "rounds_per_query": work["walk_rounds"] / max(work["walk_queries"], 1),
+                   "measured_ms": ms_of("partner"),
+                   "bound_by": "latency: each stack round waits on dependent loads of node records and "
+                               "moment blocks, and the launch lasts as long as its longest query (the root's)"}
+    return out
+
+
+def _peak_of(bound):
+    return {"mfma": PEAK["fp32_mfma"], "alu": PEAK["fp32_vector"], "alu64": PEAK["fp64_vector"]}[bound]
 
 
 def _traffic(kernel):
@@ -462,8 +510,13 @@ def main():
     torch.cuda.synchronize()
     ms_fb = 1000.0 * (time.perf_counter() - t0) / args.steps
 
+    # the partner kernels' work, counted on one more (untimed) step
+    tree.set_work_counting(True)
+    step()
+    work = tree.work_counts()
+    tree.set_work_counting(False)
     ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"],
-           "queries": int(tq.numel())}
+           "queries": int(tq.numel()), "work": work}
     per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                  for k, v in phases.items()}
     # dominant kernel: the single-kernel phase with the most time per step
@@ -477,8 +530,9 @@ def main():
             achieved, peak = amount / avg_s / 1e9, PEAK["hbm"] / 1e9
         else:
             achieved = amount / avg_s / 1e12
-            peak = (PEAK["fp32_mfma"] if bound == "mfma" else PEAK["fp32_vector"]) / 1e12
-        return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            peak = _peak_of(bound) / 1e12
+        out_bound = "alu" if bound == "alu64" else bound
+        return {"bound": out_bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": _traffic(KERNEL_OF_PHASE[ph]),
                 "kernel": KERNEL_OF_PHASE[ph], "phase": ph, "algorithmic_per_launch": amount,
                 "avg_launch_ms": phases[ph][0] / phases[ph][1],
@@ -498,7 +552,7 @@ def main():
             unmodelled_ms += tot_ms / args.steps
             continue
         bound, unit, amount = info
-        pk = PEAK["hbm"] if unit == "GB/s" else (PEAK["fp32_mfma"] if bound == "mfma" else PEAK["fp32_vector"])
+        pk = PEAK["hbm"] if unit == "GB/s" else _peak_of(bound)
         t_ideal += (launches / args.steps) * amount / pk
         modelled.append(ph)
     step_roof = {"t_ideal_ms": 1000.0 * t_ideal, "t_measured_ms": ms_per_step,
@@ -531,6 +585,7 @@ def main():
         "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
         "fwd_bwd_ms": ms_fb,
         "partner_queries_per_step": int(tq.numel()),
+        "partner_work": _partner_work(work, wl.p, phases, args.steps),
         "m2l_bf16x3": {"forward_only_ms": ms_fwd_b, "m2l_ms": m2l_ms["bf16x3"],
                        "m2l_fp32_mfma_ms": m2l_ms["mfma"]},
     }

@@ -480,6 +480,23 @@ int msp_tree_get_timing(msp_tree *t, double *ms /* host [MSP_PHASE_COUNT] */,
                         int64_t *launches /* host [MSP_PHASE_COUNT] */, int reset);
 const char *msp_phase_name(int phase);
 
+/* Work counters of the partner queries (msp_partner_probabilities and the
+ * queries of a descent), for a work model of those kernels.  While counting is
+ * enabled the query kernels add up, per pass:
+ *   [0] queries and [1] point pairs summed by the eight-lane pass (nodes of at
+ *       most 512 points), [2] queries and [3] pairs of the wavefront pass (at
+ *       most 4096 points),
+ *   [4] queries of the walk (larger nodes), [5] nodes it visited, [6] expansions
+ *       (Eq. (7)) it evaluated, [7] point pairs it summed, [8] its stack rounds
+ *       (per query, summed);
+ * the other entries are 0.  msp_tree_get_work_counts waits for the device, copies
+ * the counters to counts (host int64[MSP_WORK_COUNT]) and clears them if reset.
+ * Counting adds atomic additions to those kernels: time them with it off.
+ * Enabling clears the counters. */
+enum { MSP_WORK_COUNT = 16 };
+int msp_tree_set_work_counting(msp_tree *t, int enable);
+int msp_tree_get_work_counts(msp_tree *t, int64_t *counts, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,8 @@ _lib.msp_partner_descent.argtypes = [_vp, _vp, _vp, ctypes.POINTER(FgtParams), c
 _lib.msp_partner_probabilities.argtypes = [_vp, _vp, ctypes.POINTER(FgtParams), _vp, _vp, _i64, _vp,
                                            _vp, _vp, _vp]
 _lib.msp_fgt_debug_buffer.argtypes = [_vp, _i32, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), _vp]
+_lib.msp_tree_set_work_counting.argtypes = [_vp, ctypes.c_int]
+_lib.msp_tree_get_work_counts.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.c_int]
 _lib.msp_tree_set_timing.argtypes = [_vp, ctypes.c_int]
 _lib.msp_tree_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]
 _lib.msp_phase_name.restype = ctypes.c_char_p
@@ -116,7 +118,7 @@ _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
 PHASE_COUNT = 32
 for _f in ("msp_octree_build_weighted", "msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
            "msp_fgt_forward_noalloc",
-           "msp_fgt_backward", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
+           "msp_fgt_backward", "msp_tree_set_work_counting", "msp_tree_get_work_counts", "msp_tree_set_timing", "msp_tree_get_timing", "msp_tree_create", "msp_octree_build", "msp_tree_get_info", "msp_tree_export",
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_descent_step", "msp_partner_descent",
            "msp_fgt_debug_buffer", "msp_batch_create", "msp_batch_build", "msp_batch_autotune",
@@ -309,6 +311,19 @@ class Tree:
             prm.flags |= WEIGHTS_STAGED
         _check(_lib.msp_fgt_forward(self._h, pw, pt, ctypes.byref(prm), po, _stream()), "msp_fgt_forward")
         return out
+
+    def set_work_counting(self, enable: bool = True):
+        """Count the partner query kernels' work (msp_tree_set_work_counting)."""
+        _check(_lib.msp_tree_set_work_counting(self._h, 1 if enable else 0), "msp_tree_set_work_counting")
+
+    WORK_NAMES = ("direct_queries", "direct_pairs", "wave_queries", "wave_pairs", "walk_queries", "walk_nodes",
+                  "walk_expansions", "walk_pairs", "walk_rounds")
+
+    def work_counts(self, reset: bool = True) -> dict:
+        """The partner work counters (msp_tree_get_work_counts) by name."""
+        c = (_i64 * 16)()
+        _check(_lib.msp_tree_get_work_counts(self._h, c, 1 if reset else 0), "msp_tree_get_work_counts")
+        return {name: int(c[k]) for k, name in enumerate(self.WORK_NAMES)}
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around every library phase on the caller's stream."""

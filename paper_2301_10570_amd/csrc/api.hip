@@ -553,6 +553,30 @@ int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes
     return MSP_OK;
 }
 
+int msp_tree_set_work_counting(msp_tree *t, int enable) {
+    set_error("%s", "");
+    if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (enable && !t->counting) {
+        MSP_TRY(t->work.ensure((size_t)MSP_WORK_COUNT * 8));
+        MSP_HIP(hipMemset(t->work.p, 0, (size_t)MSP_WORK_COUNT * 8));
+    }
+    t->counting = enable != 0;
+    return MSP_OK;
+}
+
+int msp_tree_get_work_counts(msp_tree *t, int64_t *counts, int reset) {
+    set_error("%s", "");
+    if (!t || !counts) return fail(MSP_EINVAL, "NULL argument");
+    if (!t->work.p) {
+        for (int k = 0; k < MSP_WORK_COUNT; ++k) counts[k] = 0;
+        return MSP_OK;
+    }
+    MSP_HIP(hipDeviceSynchronize());
+    MSP_HIP(hipMemcpy(counts, t->work.p, (size_t)MSP_WORK_COUNT * 8, hipMemcpyDeviceToHost));
+    if (reset) MSP_HIP(hipMemset(t->work.p, 0, (size_t)MSP_WORK_COUNT * 8));
+    return MSP_OK;
+}
+
 int msp_tree_set_timing(msp_tree *t, int enable) {
     if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
     t->timing.on = enable != 0;

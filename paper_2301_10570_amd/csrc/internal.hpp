@@ -255,6 +255,9 @@ struct msp_tree {
     msp::DevBuf desc_box, desc_pairs, desc_boxmom, desc_akey;
     int desc_box_level = -1;                  // box level of the last descent (-1: no box pairs)
     int64_t desc_nbox = 0, desc_npair = 0;
+    // partner work counters (int64[MSP_WORK_COUNT]) while counting is on
+    msp::DevBuf work;
+    bool counting = false;
     int node_moments_level = -1, node_moments_p = 0;
     int64_t node_moments_bytes = 0;
 };

@@ -40,6 +40,11 @@ constexpr int kDirectPoints = 4096;          // nodes up to this size are summed
 constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
+// work counters (when counting is on): queries and pairs of the eight-lane and the
+// wavefront passes; queries, nodes visited, expansions, pairs and stack rounds of
+// the walk
+enum WorkSlot : int { W_DIRECT_Q = 0, W_DIRECT_PAIRS, W_WAVE_Q, W_WAVE_PAIRS, W_WALK_Q, W_WALK_NODES, W_WALK_M2P,
+                      W_WALK_PAIRS, W_WALK_STEPS };
 
 // Sources (staged weight != 0) below every node, from an exclusive prefix count
 // S over the points in key order: nsrc(v) = S[first + count] - S[first].
@@ -727,7 +732,7 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
                  const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
                  double lox, double loy, double loz, double side, const float4 *ps, double sigma,
                  float cutoff2, int unlimited, int exclude_self, float *probs, int32_t *choice,
-                 double *raw) {
+                 double *raw, unsigned long long *work) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t q = g >> 3;
     const int c = (int)(g & 7);
@@ -855,6 +860,10 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         if (d == c) mine = S[d];
     probs[q * 8 + c] = total > 0.0 ? (float)(mine / total) : 0.f;
     if (raw) raw[q * 8 + c] = mine;
+    if (c == 0 && work) {
+        atomicAdd(&work[W_DIRECT_Q], 1ull);
+        atomicAdd(&work[W_DIRECT_PAIRS], (unsigned long long)ncount[X]);
+    }
     if (c == 0) {
         if (choice) {
             int32_t pick = -1;
@@ -888,7 +897,7 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
                const int32_t *nnchild, const int32_t *nix, const int32_t *niy, const int32_t *niz,
                double lox, double loy, double loz, double side, const float4 *ps, double sigma,
                float cutoff2, int unlimited, int exclude_self, float *probs, int32_t *choice,
-               double *raw) {
+               double *raw, unsigned long long *work) {
     const int64_t q = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= (nq_dev ? *nq_dev : nq)) return;
@@ -991,6 +1000,10 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
         probs[q * 8 + lane] = total > 0.0 ? (float)(mine / total) : 0.f;
         if (raw) raw[q * 8 + lane] = mine;
     }
+    if (lane == 0 && work) {
+        atomicAdd(&work[W_WAVE_Q], 1ull);
+        atomicAdd(&work[W_WAVE_PAIRS], (unsigned long long)cnt);
+    }
     if (lane == 0 && choice) {
         int32_t pick = -1;
         if (total > 0.0 && uniforms) {
@@ -1073,6 +1086,7 @@ struct WalkArgs {
     int32_t *choice;
     double *raw;
     const int32_t *qorder;
+    unsigned long long *work;   // work counters (W_*), or NULL
 };
 
 // One query.  SHARED: walked by all kWalkWaves wavefronts of the block (this is
@@ -1151,6 +1165,8 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
     // only the nodes of the chain that lie within reach contribute.  The first of
     // those carrying moments ends the chain: the nodes below it hold subsets of
     // its sources, so their sums cannot raise the bound beyond its own error.
+    // this wave's work (wave-uniform): nodes visited, expansions evaluated, pairs summed
+    unsigned long long w_nodes = 0, w_m2p = 0, w_pairs = 0, w_steps = 0;
     auto lower_bound = [&]() {
         double lb = 0.0;
         int32_t u = X;
@@ -1165,12 +1181,16 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
                 centre(u, cx, cy, cz, half);
                 double m = m2p_wave<P>(A, (float)((tx - cx) * inv_sigma), (float)((ty - cy) * inv_sigma),
                                        (float)((tz - cz) * inv_sigma), lane);
+                ++w_m2p;
                 if (exclude_self && si >= uf && si < uf + un) m -= (double)qt.w;
                 lb = fmax(lb, m - trunc_bound(half * inv_sigma, P) * fabs((double)A[0]));
                 break;
             }
             if (unc == 0) {
-                if (inside) lb = fmax(lb, wave_direct(uf, un));
+                if (inside) {
+                    lb = fmax(lb, wave_direct(uf, un));
+                    w_pairs += (unsigned long long)un;
+                }
                 break;
             }
             const int32_t f = nfchild[u];
@@ -1222,6 +1242,10 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
         const int slot = (SHARED ? wv * 64 : 0) + lane;   // this lane's place in the popped batch
         const int32_t u = slot < B ? stk[base + slot] : -1;
         const bool u_has = u >= 0 && a.hasA[u];
+        if (a.work) {
+            w_nodes += (unsigned long long)__popcll(__ballot(u >= 0));
+            ++w_steps;
+        }
         // the bound is needed only once a node carrying moments comes up
         if (!have_lb) {
             bool any = __ballot(u_has) != 0;
@@ -1288,6 +1312,7 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
                                 do_m2p = true;   // evaluated below by a lane group
                             } else {
                                 val = (double)m2p_lane<P>(A, my.x, my.y, my.z);
+                                do_m2p = true;   // (counted below; already evaluated)
                                 if (exclude_self && si >= uf && si < uf + un) val -= (double)qt.w;
                             }
                             descend = direct = false;
@@ -1304,6 +1329,7 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
                 }
             }
         }
+        if (a.work) w_m2p += (unsigned long long)__popcll(__ballot(do_m2p));
         if constexpr (P == 8) {
             // Eq. (7) for the nodes taken by expansion, eight nodes at a time: the
             // 8-lane group g evaluates one node, lane s of the group holding the
@@ -1419,6 +1445,7 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
             const int32_t bf = __shfl(uf, bl, 64), bn = __shfl(un, bl, 64);
             const int bd = __shfl(digit, bl, 64);
             add_step(bd, wave_direct(bf, bn));
+            w_pairs += (unsigned long long)bn;
         }
         // the small leaves of the batch, their points spread over the lanes
         double pd[8];
@@ -1426,6 +1453,7 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
         for (int d = 0; d < 8; ++d) pd[d] = (digit == d) ? val : 0.0;
         const int lincl = wave_incl_scan(nleaf, lane);
         const int ltotal = __shfl(lincl, 63, 64);
+        w_pairs += (unsigned long long)ltotal;
         if (ltotal > 0) {
             c_first[lane] = uf - (lincl - nleaf);   // point index = c_first + flattened index
             c_end[lane] = nleaf > 0 ? lincl : -1;
@@ -1462,6 +1490,15 @@ __device__ void walk_query(const WalkArgs &a, int64_t q, WalkShared &sh, int wv)
                 }
         }
         sync();
+    }
+    if (a.work && lane == 0) {
+        atomicAdd(&a.work[W_WALK_NODES], w_nodes);
+        atomicAdd(&a.work[W_WALK_M2P], w_m2p);
+        atomicAdd(&a.work[W_WALK_PAIRS], w_pairs);
+        if (lead) {
+            atomicAdd(&a.work[W_WALK_Q], 1ull);
+            atomicAdd(&a.work[W_WALK_STEPS], w_steps);
+        }
     }
     if (!lead) return;
     double total = 0.0;
@@ -1664,6 +1701,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
     const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * sigma);
+    unsigned long long *work = t->counting ? t->work.as<unsigned long long>() : nullptr;
     // the walk's queries, coarsest first
     MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
     int32_t *order = t->partner_order.as<int32_t>();
@@ -1683,7 +1721,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                     t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
                     t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(),
                     t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma, R * R, unlimited ? 1 : 0,
-                    rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, order};
+                    rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, order, work};
         // as many blocks as the device holds at once (at most one per query)
         static int resident = 0;
         if (resident == 0) {
@@ -1707,7 +1745,7 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                            t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
                            t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
                            t->ps.as<float4>(), sigma, R * R, unlimited ? 1 : 0,
-                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw);
+                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, work);
         MSP_CHECK_LAUNCH();
     }
     {
@@ -1717,7 +1755,8 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                            t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
                            t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0],
                            t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(), sigma, R * R,
-                           unlimited ? 1 : 0, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw);
+                           unlimited ? 1 : 0, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw,
+                           work);
         MSP_CHECK_LAUNCH();
     }
     MSP_TRY(t->side.join(s));

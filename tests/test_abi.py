@@ -58,6 +58,10 @@ def test_argument_checks_without_device(lib):
     assert lib.msp_tree_get_info(None, None) == -1
     lib.msp_fgt_debug_buffer.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
     assert lib.msp_fgt_debug_buffer(None, 0, None, 0, None, None) == -1
+    lib.msp_tree_set_work_counting.argtypes = [vp, ctypes.c_int]
+    assert lib.msp_tree_set_work_counting(None, 1) == -1
+    lib.msp_tree_get_work_counts.argtypes = [vp, vp, ctypes.c_int]
+    assert lib.msp_tree_get_work_counts(None, None, 0) == -1
 
 
 class _Params(ctypes.Structure):

@@ -211,3 +211,35 @@ def test_staged_weights_reused_after_forward():
     with pytest.raises(RuntimeError):
         tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=u, weights_staged=True)
     tree.close()
+
+
+def test_work_counters_match_the_query_classes():
+    """The work counters: queries and point pairs of the eight-lane and wavefront
+    passes equal what the oracle's tree gives for the queries' nodes (nodes with
+    children: up to 512 points, 513 to 4096 points); the walk takes the rest and
+    reports nodes, expansions and pairs; counting does not change the results."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.blobs262k(0.5)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 2000, seed=21)
+    print("partner work counters, blobs 1/2, 2,000 queries", flush=True)
+    d = to_dev(wl)
+    tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+    P0, _ = tree.partner_probabilities(d["w"], T(tq, np.int32), T(nq, np.int32), wl.sigma, cutoff_sigmas=4.5)
+    tree.set_work_counting(True)
+    P1, _ = tree.partner_probabilities(d["w"], T(tq, np.int32), T(nq, np.int32), wl.sigma, cutoff_sigmas=4.5)
+    c = tree.work_counts()
+    tree.set_work_counting(False)
+    assert torch.equal(P0, P1)
+    cnt = tr.count[nq].astype(np.int64)
+    inner = tr.n_children[nq] > 0
+    small, mid, big = inner & (cnt <= 512), inner & (cnt > 512) & (cnt <= 4096), inner & (cnt > 4096)
+    print(f"  counts {c}", flush=True)
+    assert c["direct_queries"] == int(small.sum()) and c["direct_pairs"] == int(cnt[small].sum())
+    assert c["wave_queries"] == int(mid.sum()) and c["wave_pairs"] == int(cnt[mid].sum())
+    assert c["walk_queries"] == int(big.sum())
+    if big.any():
+        assert c["walk_nodes"] >= c["walk_queries"] and c["walk_rounds"] >= c["walk_queries"]
+        assert c["walk_expansions"] + c["walk_pairs"] > 0
