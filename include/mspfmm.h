@@ -308,7 +308,10 @@ int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt
  * model of `prm->p` puts the error below 1e-5 of the node's smallest term or
  * below 1e-7 of the query's running total; it is dropped when even all of its
  * weight at its nearest point stays below 1e-12 of the running total.  All other
- * sources are summed directly, in float64.  If `uniforms`
+ * sources are summed directly: for nodes of at most 4096 points each term in
+ * float32 relative to the node's closest approach to the target (float64 when the
+ * node is so wide that a term could fall below exp(-60) of the largest possible
+ * one), in float64 during the walk of larger nodes; the sums in float64.  If `uniforms`
  * (device float32[nq] in [0,1)) is non-NULL, choice[q] receives the node id of
  * the first child, in octant order, whose running sum of S exceeds
  * uniforms[q] * total, or -1 when the total is 0 or the node is a leaf.

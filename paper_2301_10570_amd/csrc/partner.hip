@@ -24,6 +24,7 @@
 #include "internal.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace msp {
 
@@ -40,6 +41,9 @@ constexpr int kDirectPoints = 4096;          // nodes up to this size are summed
 constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
+// direct sums in float32 when every term of the node lies within exp(-kSpan32) of
+// its largest possible one (float32 holds down to about exp(-87))
+constexpr double kSpan32 = 60.0;
 // work counters (when counting is on): queries and pairs of the eight-lane and the
 // wavefront passes; queries, nodes visited, expansions, pairs and stack rounds of
 // the walk
@@ -765,6 +769,15 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         const double gz = fmax(fabs(tz - (loz + (niz[u] + 0.5) * h)) - half, 0.0);
         return gx * gx + gy * gy + gz * gz;
     };
+    auto box_d2_far = [&](int32_t u, double &far2) {
+        const double h = side / (double)(1ll << nlevel[u]);
+        const double half = 0.5 * h;
+        const double ax = fabs(tx - (lox + (nix[u] + 0.5) * h)), ay = fabs(ty - (loy + (niy[u] + 0.5) * h)),
+                     az = fabs(tz - (loz + (niz[u] + 0.5) * h));
+        far2 = (ax + half) * (ax + half) + (ay + half) * (ay + half) + (az + half) * (az + half);
+        const double gx = fmax(ax - half, 0.0), gy = fmax(ay - half, 0.0), gz = fmax(az - half, 0.0);
+        return gx * gx + gy * gy + gz * gz;
+    };
     int dg = -1, in = 0;
     int32_t uend = 0;
     if (child >= 0) {
@@ -795,46 +808,78 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         return v;
     };
     // the group's eight lanes sum the node's points together, lane c taking every
-    // eighth one (consecutive lanes read consecutive records); per octant partials
+    // eighth one (consecutive lanes read consecutive records).  A lane's points come
+    // child by child, so it sums each run of one child alone and adds the run to
+    // its octant when the child changes.  Each term in float32 relative to the
+    // node's closest approach g0 to the target, exp(-(d^2 - g0^2) / sigma^2) <= 1
+    // (scaled by exp(-g0^2 / sigma^2) at the end), when the node's farthest corner
+    // keeps every term above exp(-kSpan32) (far from float32's underflow); wider
+    // nodes sum in float64.
+    double far2;
+    const double g0 = box_d2_far(X, far2);
+    const bool narrow = (far2 - g0) * kexp <= kSpan32 * 1.4426950408889634;
+    const float g0f = (float)g0, ksf = (float)kexp, txf = qt.x, tyf = qt.y, tzf = qt.z;
     double Sd[8];
+    auto sweep = [&](auto wide) {
+        constexpr bool FP64 = decltype(wide)::value;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
-    {
+        for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
         const int32_t lo = __shfl(child >= 0 ? nfirst[child] : 0, gbase, 64);   // child 0
         const int32_t hi = pick(ce, nc - 1);
         int cur = 0;
         int32_t cur_end = ce[0];
         int cur_in = ci[0], cur_dg = cd[0];
-        // four records of the lane in flight at a time, used in order
-        for (int32_t j0 = lo + c; j0 < hi; j0 += 32) {
-            float4 qv[4];
+        float run = 0.f;
+        double run64 = 0.0;
+        auto flush = [&]() {
+            const double v = FP64 ? run64 : (double)run;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int d = 0; d < 8; ++d)
+                if (d == cur_dg) Sd[d] += v;
+            run = 0.f;
+            run64 = 0.0;
+        };
+        // four records of the lane in flight at a time, used in order (one in the
+        // rare float64 case)
+        constexpr int NB = FP64 ? 1 : 4;
+        for (int32_t j0 = lo + c; j0 < hi; j0 += 8 * NB) {
+            float4 qv[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
                 const int32_t j = j0 + 8 * u;
                 qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NB; ++u) {
                 const int32_t j = j0 + 8 * u;
                 if (j >= hi) continue;
-                while (j >= cur_end && cur + 1 < nc) {
-                    ++cur;
-                    cur_end = pick(ce, cur);
-                    cur_in = pick(ci, cur);
-                    cur_dg = pick(cd, cur);
+                if (j >= cur_end && cur + 1 < nc) {
+                    flush();
+                    while (j >= cur_end && cur + 1 < nc) {
+                        ++cur;
+                        cur_end = pick(ce, cur);
+                        cur_in = pick(ci, cur);
+                        cur_dg = pick(cd, cur);
+                    }
                 }
                 if (!cur_in) continue;
                 const float4 qj = qv[u];
                 if (qj.w == 0.f || (exclude_self && j == si)) continue;
-                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
-#pragma unroll
-                for (int d = 0; d < 8; ++d)
-                    if (d == cur_dg) Sd[d] += e;
+                if constexpr (FP64) {
+                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                    run64 += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+                } else {
+                    const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
+                    run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
+                }
             }
         }
-    }
+        flush();
+    };
+    if (narrow) sweep(std::false_type{});
+    else sweep(std::true_type{});
     // sums over the group's lanes, and child ids by octant
+    const double scale = narrow ? exp2_neg(g0 * kexp) : 1.0;
     double S[8];
     int32_t cid[8];
 #pragma unroll
@@ -843,7 +888,7 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         v += __shfl_xor(v, 1, 64);
         v += __shfl_xor(v, 2, 64);
         v += __shfl_xor(v, 4, 64);
-        S[d] = v;
+        S[d] = v * scale;
         cid[d] = -1;
     }
 #pragma unroll
@@ -944,42 +989,78 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
         ci[k] = __shfl(in, k, 64);
     }
     const int32_t lo = nfirst[X], hi = lo + cnt;
+    // as in the eight-lane pass: float32 terms relative to the node's closest
+    // approach when the node is narrow enough, summed per child run, float64 per
+    // octant
+    double g0, far2;
+    {
+        const double h = side / (double)(1ll << lx), half = 0.5 * h;
+        const double ax = fabs(tx - (lox + (nix[X] + 0.5) * h)), ay = fabs(ty - (loy + (niy[X] + 0.5) * h)),
+                     az = fabs(tz - (loz + (niz[X] + 0.5) * h));
+        far2 = (ax + half) * (ax + half) + (ay + half) * (ay + half) + (az + half) * (az + half);
+        const double gx = fmax(ax - half, 0.0), gy = fmax(ay - half, 0.0), gz = fmax(az - half, 0.0);
+        g0 = gx * gx + gy * gy + gz * gz;
+    }
+    const bool narrow = (far2 - g0) * kexp <= kSpan32 * 1.4426950408889634;
+    const float g0f = (float)g0, ksf = (float)kexp, txf = qt.x, tyf = qt.y, tzf = qt.z;
     double Sd[8];
+    auto sweep = [&](auto wide) {
+        constexpr bool FP64 = decltype(wide)::value;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
-    int cur = 0;
-    for (int32_t j0 = lo + lane; j0 < hi; j0 += 256) {
-        float4 qv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int32_t j = j0 + 64 * u;
-            qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int32_t j = j0 + 64 * u;
-            if (j >= hi) continue;
-            while (cur + 1 < nc && j >= ce[cur]) ++cur;
-            int cin = 0, cdg = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k == cur) {
-                    cin = ci[k];
-                    cdg = cd[k];
-                }
-            const float4 qj = qv[u];
-            if (!cin || qj.w == 0.f || (exclude_self && j == si)) continue;
-            const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-            const double e = (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+        for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
+        int cur = 0, cin = ci[0], cdg = cd[0];
+        float run = 0.f;
+        double run64 = 0.0;
+        auto flush = [&]() {
+            const double v = FP64 ? run64 : (double)run;
 #pragma unroll
             for (int d = 0; d < 8; ++d)
-                if (d == cdg) Sd[d] += e;
+                if (d == cdg) Sd[d] += v;
+            run = 0.f;
+            run64 = 0.0;
+        };
+        constexpr int NB = FP64 ? 1 : 4;   // records of the lane in flight
+        for (int32_t j0 = lo + lane; j0 < hi; j0 += 64 * NB) {
+            float4 qv[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int32_t j = j0 + 64 * u;
+                qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int32_t j = j0 + 64 * u;
+                if (j >= hi) continue;
+                if (cur + 1 < nc && j >= ce[cur]) {
+                    flush();
+                    while (cur + 1 < nc && j >= ce[cur]) ++cur;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k == cur) {
+                            cin = ci[k];
+                            cdg = cd[k];
+                        }
+                }
+                const float4 qj = qv[u];
+                if (!cin || qj.w == 0.f || (exclude_self && j == si)) continue;
+                if constexpr (FP64) {
+                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                    run64 += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
+                } else {
+                    const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
+                    run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
+                }
+            }
         }
-    }
+        flush();
+    };
+    if (narrow) sweep(std::false_type{});
+    else sweep(std::true_type{});
+    const double scale = narrow ? exp2_neg(g0 * kexp) : 1.0;
     double S[8], total = 0.0;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        S[d] = wave_sum(Sd[d]);
+        S[d] = wave_sum(Sd[d]) * scale;
         total += S[d];
     }
     int32_t cids[8];
