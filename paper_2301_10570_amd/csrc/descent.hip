@@ -545,7 +545,9 @@ __global__ void __launch_bounds__(64) k_box_pair_values(BoxArgs g, int64_t npair
         const float g2 = (float)gap2, ks = (float)(g.inv_sigma * g.inv_sigma * 1.4426950408889634);
         double part = 0.0;
         for (int32_t j0 = 0; j0 < nc; j0 += 256) {
-            // four dendrite points per lane, held while the axon points pass
+            // up to four dendrite points per lane (as many as the box needs), held while
+            // the axon points pass
+            const int nb = nc - j0 >= 256 ? 4 : (nc - j0 + 63) / 64;
             float4 q[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -559,6 +561,7 @@ __global__ void __launch_bounds__(64) k_box_pair_values(BoxArgs g, int64_t npair
                 float row = 0.f;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    if (u >= nb) break;
                     const int32_t j = j0 + lane + 64 * u;
                     const float ex = ti.x - q[u].x, ey = ti.y - q[u].y, ez = ti.z - q[u].z;
                     const float e = __builtin_amdgcn_exp2f((g2 - (ex * ex + ey * ey + ez * ez)) * ks);

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Short text summaries of rocprofv3 CSV output, for the files under profiles/.
 
-    python rocprof_summary.py stats KERNEL_STATS_CSV --command CMD
+    python rocprof_summary.py stats KERNEL_STATS_CSV --command CMD [--trace TRACE_CSV --detail K1,K2]
     python rocprof_summary.py traffic --fetch FETCH_CSV --write WRITE_CSV \\
         --kernel NAME --source FILE --copy-bytes B --command CMD
     python rocprof_summary.py util COUNTER_CSV --command CMD --kernels K1,K2
@@ -45,6 +45,24 @@ def stats(path: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def detail(trace: str, kernels) -> str:
+    """Per-dispatch durations (us, in launch order) of the named kernels from a
+    --kernel-trace CSV, with their mean and median."""
+    rows = list(csv.DictReader(open(trace)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    out = ["", "Per-dispatch durations (us, launch order) from the kernel trace:", ""]
+    for k in kernels:
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+             if short_name(r["Kernel_Name"]) == k]
+        if not d:
+            continue
+        srt = sorted(d)
+        med = srt[len(srt) // 2]
+        out.append(f"* {k} ({len(d)}): " + ", ".join(f"{x:.1f}" for x in d)
+                   + f"; mean {sum(d) / len(d):.1f}, median {med:.1f}")
+    return "\n".join(out) + "\n"
+
+
 def _counter(path: str, counter: str):
     """Counter values per kernel, keyed by the short name without template arguments."""
     per = {}
@@ -56,13 +74,17 @@ def _counter(path: str, counter: str):
     return per
 
 
-def traffic(fetch: str, write: str, kernel: str, source: str, copy_bytes: float, command: str) -> str:
+def traffic(fetch: str, write: str, kernel: str, source: str, copy_bytes: float, command: str,
+            first: int = 0) -> str:
     f = _counter(fetch, "FETCH_SIZE")
     w = _counter(write, "WRITE_SIZE")
     if kernel not in f or kernel not in w:
         raise SystemExit(f"kernel {kernel} not found in the counter files")
     copy_f = max(f.get("__amd_rocclr_copyBuffer", [0.0]))
     copy_w = max(w.get("__amd_rocclr_copyBuffer", [0.0]))
+    if first > 0:   # the kernel's first dispatches only (those of the timed step)
+        f[kernel] = f[kernel][:first]
+        w[kernel] = w[kernel][:first]
     if copy_f <= 0 or copy_w <= 0:
         raise SystemExit("no copy kernel in the counter files")
     sf = copy_bytes / (copy_f * 1024.0)
@@ -81,7 +103,10 @@ def traffic(fetch: str, write: str, kernel: str, source: str, copy_bytes: float,
            "",
            f"Calibration: a device copy of {copy_bytes:.0f} bytes (read and written once) reads "
            f"FETCH_SIZE {copy_f:.1f} KiB and WRITE_SIZE {copy_w:.1f} KiB, so the counters are scaled by "
-           f"{sf:.4f} (fetch) and {sw:.4f} (write).", "",
+           f"{sf:.4f} (fetch) and {sw:.4f} (write)."
+           + (f" Only the kernel's first {first} dispatches of each run are used (the warm-up, timed"
+              " and event-timed steps; later dispatches belong to other timings of the run)." if first else ""),
+           "",
            f"traffic_bytes_per_launch: {bytes_per_launch:.6e}",
            f"source_sha256: {os.path.relpath(source)} {sha}", ""]
     return "\n".join(out)
@@ -121,6 +146,9 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("--command", required=True)
+    a.add_argument("--trace", help="kernel trace CSV of the same run, for --detail")
+    a.add_argument("--detail", default="", help="comma-separated short kernel names")
+    a.add_argument("--note", default="", help="a line of text appended after the table")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -128,6 +156,7 @@ def main():
     b.add_argument("--source", required=True)
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--command", required=True)
+    b.add_argument("--first", type=int, default=0, help="use only the kernel's first N dispatches")
     c = sub.add_parser("util")
     c.add_argument("csv")
     c.add_argument("--command", required=True)
@@ -138,9 +167,13 @@ def main():
         return
     if args.what == "stats":
         sys.stdout.write(stats(args.csv, args.command))
+        if args.trace and args.detail:
+            sys.stdout.write(detail(args.trace, args.detail.split(",")))
+        if args.note:
+            sys.stdout.write("\n" + args.note + "\n")
     else:
         sys.stdout.write(traffic(args.fetch, args.write, args.kernel, args.source, args.copy_bytes,
-                                 args.command))
+                                 args.command, args.first))
 
 
 if __name__ == "__main__":
