@@ -286,8 +286,11 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
     const int n16 = lane & 15, azc = n16 & 7, ayh0 = n16 >> 3;
     f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
     fetch(start);
+    // each wavefront stages and reads only its own 64 rows (thread tid writes row
+    // tid, wavefront w reads rows 64 w .. 64 w + 63), so the waves synchronise
+    // only with themselves
     for (int64_t c0 = start; c0 < end; c0 += kBlock) {
-        __syncthreads();
+        wave_sync();
         {
             float *r = pw + tid * kPowStr;
             float xp = 1.f, yp = 1.f, wz = nxt.w;
@@ -301,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
                 wz *= nxt.z;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (c0 + kBlock < end) fetch(c0 + kBlock);
         const int cnt = end - c0 < kBlock ? (int)(end - c0) : kBlock;
         const int w0 = wid * 64;
