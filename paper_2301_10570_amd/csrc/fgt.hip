@@ -911,42 +911,55 @@ __device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *i
     }
     __syncthreads();
     const double cx = lox + (kx + 0.5) * cell, cy = loy + (ky + 0.5) * cell, cz = loz + (kz + 0.5) * cell;
-    for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += 2 * kBlock) {
-        const int64_t i1 = i0 + kBlock;
-        const bool has1 = i1 < end;
-        const float4 q0 = ps[i0];
-        const float4 q1 = has1 ? ps[i1] : q0;
-        const float X0 = ((q0.x - (float)cx) * (float)inv_sigma), X1 = ((q1.x - (float)cx) * (float)inv_sigma);
-        const float Y0 = ((q0.y - (float)cy) * (float)inv_sigma), Y1 = ((q1.y - (float)cy) * (float)inv_sigma);
-        const float Z0 = ((q0.z - (float)cz) * (float)inv_sigma), Z1 = ((q1.z - (float)cz) * (float)inv_sigma);
-        // the scattered reads of the output step are issued before the evaluation
-        const int32_t j0 = perm[i0];
-        const int32_t j1 = has1 ? perm[i1] : j0;
-        const bool t0 = !is_target || is_target[j0];
-        const bool t1 = !is_target || is_target[j1];
-        const float w0 = subtract_self ? w[j0] : 0.f, w1 = subtract_self ? w[j1] : 0.f;
-        float uz0 = 0.f, uz1 = 0.f;
+    // four points per thread and pass, so that every coefficient read from LDS serves
+    // four Horner chains (with fewer, the LDS reads bound the loop)
+    constexpr int NPT = 4;
+    for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += NPT * kBlock) {
+        float X[NPT], Y[NPT], Z[NPT], ws[NPT];
+        int32_t jo[NPT];
+        bool has[NPT], tg[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            has[u] = i < end;
+            const float4 q = ps[has[u] ? i : i0];
+            X[u] = (q.x - (float)cx) * (float)inv_sigma;
+            Y[u] = (q.y - (float)cy) * (float)inv_sigma;
+            Z[u] = (q.z - (float)cz) * (float)inv_sigma;
+            // the scattered reads of the output step are issued before the evaluation
+            jo[u] = perm[has[u] ? i : i0];
+            tg[u] = !is_target || is_target[jo[u]];
+            ws[u] = subtract_self ? w[jo[u]] : 0.f;
+        }
+        float uz[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) uz[u] = 0.f;
         for (int az = P - 1; az >= 0; --az) {
-            float uy0 = 0.f, uy1 = 0.f;
+            float uy[NPT];
+#pragma unroll
+            for (int u = 0; u < NPT; ++u) uy[u] = 0.f;
 #pragma unroll
             for (int ay = P - 1; ay >= 0; --ay) {
                 const float *c = sC + (az * P + ay) * P;
-                float ux0 = c[P - 1], ux1 = c[P - 1];
+                float ux[NPT];
+#pragma unroll
+                for (int u = 0; u < NPT; ++u) ux[u] = c[P - 1];
 #pragma unroll
                 for (int ax = P - 2; ax >= 0; --ax) {
                     const float cv = c[ax];
-                    ux0 = fmaf(ux0, X0, cv);
-                    ux1 = fmaf(ux1, X1, cv);
+#pragma unroll
+                    for (int u = 0; u < NPT; ++u) ux[u] = fmaf(ux[u], X[u], cv);
                 }
-                uy0 = fmaf(uy0, Y0, ux0);
-                uy1 = fmaf(uy1, Y1, ux1);
+#pragma unroll
+                for (int u = 0; u < NPT; ++u) uy[u] = fmaf(uy[u], Y[u], ux[u]);
             }
-            uz0 = fmaf(uz0, Z0, uy0);
-            uz1 = fmaf(uz1, Z1, uy1);
+#pragma unroll
+            for (int u = 0; u < NPT; ++u) uz[u] = fmaf(uz[u], Z[u], uy[u]);
         }
         // back to input order; non-targets get 0
-        u_out[j0] = t0 ? uz0 - w0 : 0.f;
-        if (has1) u_out[j1] = t1 ? uz1 - w1 : 0.f;
+#pragma unroll
+        for (int u = 0; u < NPT; ++u)
+            if (has[u]) u_out[jo[u]] = tg[u] ? uz[u] - ws[u] : 0.f;
     }
 }
 
