@@ -790,112 +790,71 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         }
         uend = nfirst[child] + ncount[child];
     }
-    // the group's children by lane: point range end, cutoff flag, octant, node id
-    // (their point ranges are consecutive in key order and cover the node's)
-    int32_t ce[8], cd[8], cn[8];
-    int ci[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        ce[k] = __shfl(uend, gbase + k, 64);
-        ci[k] = __shfl(in, gbase + k, 64);
-        cd[k] = __shfl(dg, gbase + k, 64);
-        cn[k] = __shfl(child, gbase + k, 64);
-    }
-    auto pick = [](const int32_t(&a)[8], int k) {
-        int32_t v = a[0];
-#pragma unroll
-        for (int kk = 1; kk < 8; ++kk) v = k == kk ? a[kk] : v;
-        return v;
-    };
-    // the group's eight lanes sum the node's points together, lane c taking every
-    // eighth one (consecutive lanes read consecutive records).  A lane's points come
-    // child by child, so it sums each run of one child alone and adds the run to
-    // its octant when the child changes.  Each term in float32 relative to the
-    // node's closest approach g0 to the target, exp(-(d^2 - g0^2) / sigma^2) <= 1
-    // (scaled by exp(-g0^2 / sigma^2) at the end), when the node's farthest corner
-    // keeps every term above exp(-kSpan32) (far from float32's underflow); wider
-    // nodes sum in float64.
+    // lane c sums the points of child c (a contiguous range in key order), four
+    // records in flight.  Each term in float32 relative to the node's closest
+    // approach g0 to the target, exp(-(d^2 - g0^2) / sigma^2) <= 1 (scaled by
+    // exp(-g0^2 / sigma^2) at the end, and moved to float64 every 32 terms), when
+    // the node's farthest corner keeps every term above exp(-kSpan32) (far from
+    // float32's underflow); wider nodes sum in float64.
     double far2;
     const double g0 = box_d2_far(X, far2);
     const bool narrow = (far2 - g0) * kexp <= kSpan32 * 1.4426950408889634;
     const float g0f = (float)g0, ksf = (float)kexp, txf = qt.x, tyf = qt.y, tzf = qt.z;
-    double Sd[8];
-    auto sweep = [&](auto wide) {
-        constexpr bool FP64 = decltype(wide)::value;
+    double mysum = 0.0;
+    if (child >= 0 && in) {
+        const int32_t cf = nfirst[child], cend = uend;
+        if (narrow) {
+            float run = 0.f;
+            int nrun = 0;
+            for (int32_t j0 = cf; j0 < cend; j0 += 4) {
+                float4 qv[4];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
-        const int32_t lo = __shfl(child >= 0 ? nfirst[child] : 0, gbase, 64);   // child 0
-        const int32_t hi = pick(ce, nc - 1);
-        int cur = 0;
-        int32_t cur_end = ce[0];
-        int cur_in = ci[0], cur_dg = cd[0];
-        float run = 0.f;
-        double run64 = 0.0;
-        auto flush = [&]() {
-            const double v = FP64 ? run64 : (double)run;
+                for (int u = 0; u < 4; ++u) qv[u] = j0 + u < cend ? ps[j0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int d = 0; d < 8; ++d)
-                if (d == cur_dg) Sd[d] += v;
-            run = 0.f;
-            run64 = 0.0;
-        };
-        // four records of the lane in flight at a time, used in order (one in the
-        // rare float64 case)
-        constexpr int NB = FP64 ? 1 : 4;
-        for (int32_t j0 = lo + c; j0 < hi; j0 += 8 * NB) {
-            float4 qv[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const int32_t j = j0 + 8 * u;
-                qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const int32_t j = j0 + 8 * u;
-                if (j >= hi) continue;
-                if (j >= cur_end && cur + 1 < nc) {
-                    flush();
-                    while (j >= cur_end && cur + 1 < nc) {
-                        ++cur;
-                        cur_end = pick(ce, cur);
-                        cur_in = pick(ci, cur);
-                        cur_dg = pick(cd, cur);
-                    }
-                }
-                if (!cur_in) continue;
-                const float4 qj = qv[u];
-                if (qj.w == 0.f || (exclude_self && j == si)) continue;
-                if constexpr (FP64) {
-                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                    run64 += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
-                } else {
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t j = j0 + u;
+                    const float4 qj = qv[u];
+                    if (j >= cend || qj.w == 0.f || (exclude_self && j == si)) continue;
                     const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
                     run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
                 }
+                if (++nrun == 8) {
+                    mysum += (double)run;
+                    run = 0.f;
+                    nrun = 0;
+                }
+            }
+            mysum += (double)run;
+            mysum *= exp2_neg(g0 * kexp);
+        } else {
+            for (int32_t j = cf; j < cend; ++j) {
+                const float4 qj = ps[j];
+                if (qj.w == 0.f || (exclude_self && j == si)) continue;
+                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                mysum += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
             }
         }
-        flush();
-    };
-    if (narrow) sweep(std::false_type{});
-    else sweep(std::true_type{});
-    // sums over the group's lanes, and child ids by octant
-    const double scale = narrow ? exp2_neg(g0 * kexp) : 1.0;
+    }
+    // the group's sums and child ids by octant (lane k holds child k)
     double S[8];
     int32_t cid[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        double v = Sd[d];
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        S[d] = v * scale;
+        S[d] = 0.0;
         cid[d] = -1;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 8; ++k) {
+        const double sk = __shfl(mysum, gbase + k, 64);
+        const int dk = __shfl(dg, gbase + k, 64);
+        const int32_t ck = __shfl(child, gbase + k, 64);
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            if (d == cd[k] && cn[k] >= 0) cid[d] = cn[k];
+            if (d == dk && ck >= 0) {
+                S[d] = sk;
+                cid[d] = ck;
+            }
+    }
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < 8; ++d) total += S[d];
@@ -980,18 +939,10 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
             in = box_d2(cid) <= reach * reach;
         }
     }
-    int32_t ce[8];
-    int cd[8], ci[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        ce[k] = __shfl(uend, k, 64);
-        cd[k] = __shfl(dg, k, 64);
-        ci[k] = __shfl(in, k, 64);
-    }
-    const int32_t lo = nfirst[X], hi = lo + cnt;
-    // as in the eight-lane pass: float32 terms relative to the node's closest
-    // approach when the node is narrow enough, summed per child run, float64 per
-    // octant
+    // the lane group g (lanes 8 g .. 8 g + 7) sums the points of child g, lane s of
+    // the group taking every eighth one with four records in flight (the group
+    // reads whole lines); float32 terms relative to the node's closest approach
+    // when the node is narrow enough (as in the eight-lane pass), float64 otherwise
     double g0, far2;
     {
         const double h = side / (double)(1ll << lx), half = 0.5 * h;
@@ -1003,76 +954,69 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
     }
     const bool narrow = (far2 - g0) * kexp <= kSpan32 * 1.4426950408889634;
     const float g0f = (float)g0, ksf = (float)kexp, txf = qt.x, tyf = qt.y, tzf = qt.z;
-    double Sd[8];
-    auto sweep = [&](auto wide) {
-        constexpr bool FP64 = decltype(wide)::value;
+    const int grp = lane >> 3, sl = lane & 7;
+    const int32_t gend = __shfl(uend, grp, 64), gcid = __shfl(cid, grp, 64);
+    const int gin = __shfl(in, grp, 64);
+    double mysum = 0.0;
+    if (gcid >= 0 && gin) {
+        const int32_t cf = nfirst[gcid];
+        if (narrow) {
+            float run = 0.f;
+            int nrun = 0;
+            for (int32_t j0 = cf + sl; j0 < gend; j0 += 32) {
+                float4 qv[4];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) Sd[d] = 0.0;
-        int cur = 0, cin = ci[0], cdg = cd[0];
-        float run = 0.f;
-        double run64 = 0.0;
-        auto flush = [&]() {
-            const double v = FP64 ? run64 : (double)run;
+                for (int u = 0; u < 4; ++u) qv[u] = j0 + 8 * u < gend ? ps[j0 + 8 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int d = 0; d < 8; ++d)
-                if (d == cdg) Sd[d] += v;
-            run = 0.f;
-            run64 = 0.0;
-        };
-        constexpr int NB = FP64 ? 1 : 4;   // records of the lane in flight
-        for (int32_t j0 = lo + lane; j0 < hi; j0 += 64 * NB) {
-            float4 qv[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const int32_t j = j0 + 64 * u;
-                qv[u] = j < hi ? ps[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const int32_t j = j0 + 64 * u;
-                if (j >= hi) continue;
-                if (cur + 1 < nc && j >= ce[cur]) {
-                    flush();
-                    while (cur + 1 < nc && j >= ce[cur]) ++cur;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (k == cur) {
-                            cin = ci[k];
-                            cdg = cd[k];
-                        }
-                }
-                const float4 qj = qv[u];
-                if (!cin || qj.w == 0.f || (exclude_self && j == si)) continue;
-                if constexpr (FP64) {
-                    const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
-                    run64 += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
-                } else {
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t j = j0 + 8 * u;
+                    const float4 qj = qv[u];
+                    if (j >= gend || qj.w == 0.f || (exclude_self && j == si)) continue;
                     const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
                     run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
                 }
+                if (++nrun == 8) {
+                    mysum += (double)run;
+                    run = 0.f;
+                    nrun = 0;
+                }
+            }
+            mysum += (double)run;
+            mysum *= exp2_neg(g0 * kexp);
+        } else {
+            for (int32_t j = cf + sl; j < gend; j += 8) {
+                const float4 qj = ps[j];
+                if (qj.w == 0.f || (exclude_self && j == si)) continue;
+                const double ex = tx - qj.x, ey = ty - qj.y, ez = tz - qj.z;
+                mysum += (double)qj.w * exp2_neg((ex * ex + ey * ey + ez * ez) * kexp);
             }
         }
-        flush();
-    };
-    if (narrow) sweep(std::false_type{});
-    else sweep(std::true_type{});
-    const double scale = narrow ? exp2_neg(g0 * kexp) : 1.0;
-    double S[8], total = 0.0;
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        S[d] = wave_sum(Sd[d]) * scale;
-        total += S[d];
     }
+    mysum += __shfl_xor(mysum, 1, 64);
+    mysum += __shfl_xor(mysum, 2, 64);
+    mysum += __shfl_xor(mysum, 4, 64);
+    // per octant: child k's sum sits in lane 8 k
+    double S[8], total = 0.0;
     int32_t cids[8];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) cids[d] = -1;
+    for (int d = 0; d < 8; ++d) {
+        S[d] = 0.0;
+        cids[d] = -1;
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
+        const double sk = __shfl(mysum, 8 * k, 64);
+        const int dk = __shfl(dg, k, 64);
         const int32_t ck = __shfl(cid, k, 64);
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            if (ck >= 0 && d == cd[k]) cids[d] = ck;
+            if (ck >= 0 && d == dk) {
+                S[d] = sk;
+                cids[d] = ck;
+            }
     }
+#pragma unroll
+    for (int d = 0; d < 8; ++d) total += S[d];
     if (lane < 8) {
         double mine = 0.0;
 #pragma unroll
