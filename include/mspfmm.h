@@ -308,7 +308,7 @@ int msp_direct_sum(const float *tx, const float *ty, const float *tz, int64_t nt
  * model of `prm->p` puts the error below 1e-5 of the node's smallest term or
  * below 1e-7 of the query's running total; it is dropped when even all of its
  * weight at its nearest point stays below 1e-12 of the running total.  All other
- * sources are summed directly: for nodes of at most 4096 points each term in
+ * sources are summed directly: for nodes of at most 16384 points each term in
  * float32 relative to the node's closest approach to the target (float64 when the
  * node is so wide that a term could fall below exp(-60) of the largest possible
  * one), in float64 during the walk of larger nodes; the sums in float64.  If `uniforms`
@@ -488,7 +488,7 @@ const char *msp_phase_name(int phase);
  * enabled the query kernels add up, per pass:
  *   [0] queries and [1] point pairs summed by the eight-lane pass (nodes of at
  *       most 512 points), [2] queries and [3] pairs of the wavefront pass (at
- *       most 4096 points),
+ *       most 16384 points),
  *   [4] queries of the walk (larger nodes), [5] nodes it visited, [6] expansions
  *       (Eq. (7)) it evaluated, [7] point pairs it summed, [8] its stack rounds
  *       (per query, summed);

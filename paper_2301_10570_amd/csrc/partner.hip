@@ -37,7 +37,7 @@ constexpr int kBlock = 256;
 constexpr int kC1 = 70;                    // Algorithm 2's element threshold
 constexpr int kLaneLeaf = 128;               // leaves up to this size are summed by one lane
 constexpr int kSmallNode = 512;              // nodes up to this size: eight lanes per query sum them
-constexpr int kDirectPoints = 4096;          // nodes up to this size are summed directly (no walk)
+constexpr int kDirectPoints = 16384;         // nodes up to this size are summed directly (no walk)
 constexpr double kAdmitTol = 1e-5;   // M2P error vs the node's own smallest contribution
 constexpr double kRunTol = 1e-7;     // M2P error vs the running total of the query
 constexpr double kSkipTol = 1e-12;   // dropped node's largest contribution vs the running total
@@ -722,12 +722,11 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
 
 
 // Queries whose node X holds at most kSmallNode points: the sums over its
-// children straight from the points, in float64 (exact up to rounding), eight
-// queries per wavefront.  The eight lanes of a query read the node's points
-// together (its children's point ranges are consecutive in key order), each
-// point adding to its child's octant.  With a cutoff, children beyond the reach
-// of the query are left out as in the walk.  Queries without children to choose
-// from (a leaf node, an invalid target or node) get zeros and choice -1 here.
+// children straight from the points (direct sums), eight queries per wavefront,
+// lane c of a query's eight summing the points of child c (contiguous in key
+// order).  With a cutoff, children beyond the reach of the query are left out as
+// in the walk.  Queries without children to choose from (a leaf node, an invalid
+// target or node) get zeros and choice -1 here.
 __global__ void __launch_bounds__(256)
 k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, const int32_t *node_id,
                  const float *uniforms,
@@ -890,9 +889,8 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
 }
 
 // Queries whose node holds more than kSmallNode and at most kDirectPoints
-// points: one wavefront per query sums the node's points directly in float64,
-// each lane every 64th point with four of its records in flight, the partial
-// sums per octant added by shuffles.  Other queries return at once.
+// points: one wavefront per query sums the node's points directly, lane group g
+// (eight lanes) the points of child g.  Other queries return at once.
 __global__ void __launch_bounds__(256)
 k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, const int32_t *node_id,
                const float *uniforms,

@@ -216,7 +216,7 @@ def test_staged_weights_reused_after_forward():
 def test_work_counters_match_the_query_classes():
     """The work counters: queries and point pairs of the eight-lane and wavefront
     passes equal what the oracle's tree gives for the queries' nodes (nodes with
-    children: up to 512 points, 513 to 4096 points); the walk takes the rest and
+    children: up to 512 points, 513 to 16384 points); the walk takes the rest and
     reports nodes, expansions and pairs; counting does not change the results."""
     import torch
     import paper_2301_10570_amd as msp
@@ -235,7 +235,7 @@ def test_work_counters_match_the_query_classes():
     assert torch.equal(P0, P1)
     cnt = tr.count[nq].astype(np.int64)
     inner = tr.n_children[nq] > 0
-    small, mid, big = inner & (cnt <= 512), inner & (cnt > 512) & (cnt <= 4096), inner & (cnt > 4096)
+    small, mid, big = inner & (cnt <= 512), inner & (cnt > 512) & (cnt <= 16384), inner & (cnt > 16384)
     print(f"  counts {c}", flush=True)
     assert c["direct_queries"] == int(small.sum()) and c["direct_pairs"] == int(cnt[small].sum())
     assert c["wave_queries"] == int(mid.sum()) and c["wave_pairs"] == int(cnt[mid].sum())
