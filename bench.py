@@ -28,7 +28,9 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12, "fp64_vector": 78.6e12}
 # work model of the partner kernels (per unit of counted work)
-PAIR_FLOPS = 12.0        # float64 offsets, square, scale, exponential (as one), weight, sum
+PAIR_FLOPS = 12.0        # walk pairs in float64: offsets, square, scale, exponential (as one), weight, sum
+PAIR_FLOPS32 = 13.0      # direct-pass pairs in float32: 3 offsets, square (5), minus g0^2, scale,
+                         # exponential (as one), weight multiply-add (2)
 PAIR_BYTES = 16.0        # the point record (x, y, z, staged w)
 NODE_BYTES = 36.0        # level, cell coordinates, first point, count, children, moment flag
 def m2p_flops(p):        # Hermite rows (3 p recurrence steps) and the p^3 contraction, 2 per multiply-add
@@ -69,9 +71,9 @@ def _algorithmic(phase, ctx):
         # (key, index) read and written once, positions gathered into key order
         return "hbm", "GB/s", n * (24.0 + 32.0)
     if phase in ("partner_direct", "partner_wave"):
-        # the counted point pairs, each in float64 (bound by the vector units)
+        # the counted point pairs, each term in float32 (bound by the vector units)
         pairs = ctx["work"]["direct_pairs" if phase == "partner_direct" else "wave_pairs"]
-        return "alu64", "TFLOP/s", pairs * PAIR_FLOPS
+        return "alu", "TFLOP/s", pairs * PAIR_FLOPS32
     if phase == "partner":
         # the walk: node records, moment blocks and point records it must read, and
         # its arithmetic; the bound is whichever needs more time at peak
@@ -101,8 +103,8 @@ def _partner_work(work, p, phases, steps):
     for name, ph, pairs in (("eight_lane_pass", "partner_direct", work["direct_pairs"]),
                             ("wavefront_pass", "partner_wave", work["wave_pairs"])):
         out[name] = {"kernel": "k_partner_direct" if ph == "partner_direct" else "k_partner_wave",
-                     "pairs": pairs, "flops64": pairs * PAIR_FLOPS, "bytes": pairs * PAIR_BYTES,
-                     "t_alu_ms": 1e3 * pairs * PAIR_FLOPS / PEAK["fp64_vector"],
+                     "pairs": pairs, "flops32": pairs * PAIR_FLOPS32, "bytes": pairs * PAIR_BYTES,
+                     "t_alu_ms": 1e3 * pairs * PAIR_FLOPS32 / PEAK["fp32_vector"],
                      "t_hbm_ms": 1e3 * pairs * PAIR_BYTES / PEAK["hbm"], "measured_ms": ms_of(ph)}
     nb = work["walk_nodes"] * NODE_BYTES + work["walk_expansions"] * 4.0 * p ** 3 + work["walk_pairs"] * PAIR_BYTES
     out["walk"] = {"kernel": "k_partner", "queries": work["walk_queries"], "nodes": work["walk_nodes"],
@@ -400,6 +402,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-population batch")
     ap.add_argument("--no-descent", action="store_true", help="skip the partner descent")
     ap.add_argument("--no-configs", action="store_true", help="skip the cube, blob and gradient workloads")
+    ap.add_argument("--serial", action="store_true",
+                    help="forward and partner probabilities on one stream, one after the other")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three copies of 1 GiB (counter calibration runs)")
     args = ap.parse_args()
@@ -430,12 +434,24 @@ def main():
     tq, nq = _partner_queries(tree, args.queries, seed=781)
     uni = T(synth.uniforms(tq.numel(), 782))
 
-    def step():
+    # the forward and the partner probabilities both read the tree and the weights
+    # the weighted build put into key order, and write nothing the other reads: the
+    # partner call runs on a second stream beside the forward (--serial: one stream)
+    side = torch.cuda.Stream()
+
+    def step(serial=args.serial):
         # the vacant element counts ride into key order with the positions
         tree.build(x, y, z, leaf_max=wl.leaf_max, w=w)
+        main = torch.cuda.current_stream()
+        if tq.numel() and not serial:
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
         tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u, weights_staged=True)
-        if tq.numel():
+        if tq.numel() and serial:
             tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
+        if tq.numel() and not serial:
+            main.wait_stream(side)   # the next build rewrites what the partner call reads
 
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -455,17 +471,24 @@ def main():
     print(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} sums/s", file=sys.stderr, flush=True)
 
     # the same steps again with HIP events around every library phase and sort
-    # pass, recorded live on the library's stream (per-kernel durations)
-    tree.set_timing(True)
-    tree.timing(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_events = 1000.0 * (time.perf_counter() - t0) / args.steps
-    phases = tree.timing(reset=True)
-    tree.set_timing(False)
+    # pass, recorded live on the streams that run them: once as timed (phases that
+    # overlap share the GPU), once with every pass alone (one stream, the
+    # library's side-stream passes one after another), which the kernel
+    # rooflines use
+    def event_pass(isolated):
+        tree.set_timing(True, isolated=isolated)
+        tree.timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(serial=args.serial or isolated)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        ph = tree.timing(reset=True)
+        tree.set_timing(False)
+        return ph, ms
+    phases_timed, ms_events = event_pass(False)
+    phases, ms_alone = event_pass(True)
 
     # forward only, cached tree
     torch.cuda.synchronize()
@@ -518,7 +541,9 @@ def main():
     ctx = {"n": wl.n, "n_src": n_src, "n_tgt": n_tgt, "p": wl.p, "grid": plan["grid"],
            "queries": int(tq.numel()), "work": work}
     per_phase = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
-                 for k, v in phases.items()}
+                 for k, v in phases_timed.items()}
+    per_phase_alone = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+                       for k, v in phases.items()}
     # dominant kernel: the single-kernel phase with the most time per step
     def _roof(ph):
         info = _algorithmic(ph, ctx)
@@ -579,8 +604,12 @@ def main():
         "roofline": roof,
         "kernel_rooflines": kernels,
         "step_roofline": step_roof,
+        "schedule": ("one stream" if args.serial else
+                     "forward on the caller's stream, partner probabilities on a second stream"),
         "phases": per_phase,
         "ms_per_step_with_events": ms_events,
+        "phases_alone": per_phase_alone,
+        "ms_per_step_alone": ms_alone,
         "forward_only_ms": ms_fwd,
         "forward_only_sums_per_s": n_tgt / (ms_fwd / 1000.0),
         "fwd_bwd_ms": ms_fb,

@@ -25,7 +25,13 @@
  *     interaction lists) belongs to the msp_tree handle: allocated on demand,
  *     reused by later calls, released by msp_tree_destroy.  A handle must not be
  *     used from two host threads at once, and two calls on one handle must use
- *     the same stream (or be ordered by the caller).
+ *     the same stream (or be ordered by the caller).  One exception: after a
+ *     weighted build (msp_octree_build_weighted), msp_fgt_forward on the
+ *     expansion route (MSP_ROUTE_FGT, or AUTO resolving to it) and
+ *     msp_partner_probabilities, both with MSP_WEIGHTS_STAGED, only read the
+ *     tree and write disjoint buffers, so they may run on two streams at once;
+ *     both must be ordered after the build, and the next call that writes the
+ *     tree (a build, a backward, a call without MSP_WEIGHTS_STAGED) after both.
  *   - Callers that own all device memory use the *_query / *_ws pairs instead:
  *     msp_octree_build_ws keeps the tree's arrays in a caller buffer and builds
  *     in a caller workspace, msp_fgt_forward_ws evaluates in a caller workspace;
@@ -474,9 +480,13 @@ int msp_batch_instance_ms(msp_batch *b, double *ms);
 int msp_batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
 
 /* Per-phase GPU timing.  When enabled, the library records a pair of HIP events
- * around each phase it launches on the caller's stream; msp_tree_get_timing
+ * around each phase it launches, on the stream that runs it; msp_tree_get_timing
  * waits for them and returns, per phase, the summed milliseconds and the number
- * of launches since the last reset.  Phase names come from msp_phase_name. */
+ * of launches since the last reset.  Phase names come from msp_phase_name.
+ * enable: 0 off, 1 on, 2 on and isolated: the passes the library otherwise runs
+ * beside each other (the partner walk on a side stream beside the direct passes)
+ * run one after another on the caller's stream, so that each phase's time is
+ * that of its kernels alone.  Other values: MSP_EINVAL. */
 enum { MSP_PHASE_COUNT = 32 };
 int msp_tree_set_timing(msp_tree *t, int enable);
 int msp_tree_get_timing(msp_tree *t, double *ms /* host [MSP_PHASE_COUNT] */,

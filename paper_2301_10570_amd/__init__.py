@@ -325,9 +325,12 @@ class Tree:
         _check(_lib.msp_tree_get_work_counts(self._h, c, 1 if reset else 0), "msp_tree_get_work_counts")
         return {name: int(c[k]) for k, name in enumerate(self.WORK_NAMES)}
 
-    def set_timing(self, enable: bool = True):
-        """Record HIP events around every library phase on the caller's stream."""
-        _check(_lib.msp_tree_set_timing(self._h, 1 if enable else 0), "msp_tree_set_timing")
+    def set_timing(self, enable: bool = True, isolated: bool = False):
+        """Record HIP events around every library phase on the caller's stream.
+        isolated: the passes the library would overlap on a side stream run one
+        after another on the caller's stream, so each phase's time is its own."""
+        mode = (2 if isolated else 1) if enable else 0
+        _check(_lib.msp_tree_set_timing(self._h, mode), "msp_tree_set_timing")
 
     def timing(self, reset: bool = True) -> dict:
         """{phase: (total ms, launches)} for phases that ran since the last reset."""

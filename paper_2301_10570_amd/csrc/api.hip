@@ -579,7 +579,9 @@ int msp_tree_get_work_counts(msp_tree *t, int64_t *counts, int reset) {
 
 int msp_tree_set_timing(msp_tree *t, int enable) {
     if (!t) return fail(MSP_EINVAL, "tree handle is NULL");
+    if (enable < 0 || enable > 2) return fail(MSP_EINVAL, "timing mode %d outside 0..2", enable);
     t->timing.on = enable != 0;
+    t->timing.isolate = enable == 2;
     return MSP_OK;
 }
 

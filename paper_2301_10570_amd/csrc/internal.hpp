@@ -140,6 +140,7 @@ static_assert(PH_COUNT_ <= MSP_PHASE_COUNT, "phase table too small");
 // Pairs of events recorded around library phases when timing is on.
 struct Timing {
     bool on = false;
+    bool isolate = false;   // no side streams: overlapping passes run one after another
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;

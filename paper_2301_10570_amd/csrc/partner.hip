@@ -1701,14 +1701,29 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     return MSP_OK;
 }
 
-// queries against the node moments of the last partner_moments call; raw (or
-// NULL): the unnormalised per-octant sums
+// What the query kernels share: the queries' key-order positions, the walk's
+// order (coarsest query node first) and the call's parameters.  Needs the node
+// table only, not the node moments.
+struct QuerySet {
+    int64_t nq;
+    const int64_t *nq_dev;
+    const int32_t *target_idx, *node_id, *qpos;
+    const float *uniforms;
+    float *probs;
+    int32_t *choice;
+    double *raw;
+    int32_t *order;
+    double sigma, rmax;
+    float R2;
+    int unlimited, exclude_self;
+    unsigned long long *work;
+};
+
 template <int P>
-int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+int queries_prepare(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                     const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
                     int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s,
-                    const int64_t *nq_dev = nullptr) {
-    if (nq == 0) return MSP_OK;
+                    const int64_t *nq_dev, QuerySet *q) {
     if (!qpos) {   // key-order positions of the targets
         MSP_TRY(t->partner_qpos.ensure((size_t)nq * 4));
         hipLaunchKernelGGL(k_query_pos, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, target_idx, t->n,
@@ -1717,83 +1732,124 @@ int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
         MSP_CHECK_LAUNCH();
         qpos = t->partner_qpos.as<int32_t>();
     }
-    const double sigma = prm->sigma;
-    const double rmax = rho_max_for_p(P);
-    const int lh = moment_level(t, sigma, P);
-    const int64_t nn = t->n_nodes;
-    const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
-    const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * sigma);
-    unsigned long long *work = t->counting ? t->work.as<unsigned long long>() : nullptr;
+    const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * prm->sigma);
     // the walk's queries, coarsest first
     MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
     int32_t *order = t->partner_order.as<int32_t>();
     hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, order + (size_t)kMaxLevels * nq);
     MSP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, nq_dev, target_idx, node_id,
-                       t->n, nn, qpos, t->nlevel.as<int32_t>(), t->ncount.as<int32_t>(),
+                       t->n, t->n_nodes, qpos, t->nlevel.as<int32_t>(), t->ncount.as<int32_t>(),
                        t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), order);
     MSP_CHECK_LAUNCH();
-    // the walk (few, long queries) on a side stream, beside the direct passes (many
-    // short ones) on the caller's stream
-    MSP_TRY(t->side.fork(s));
-    {
-        PhaseScope ps(&t->timing, PH_PARTNER, t->side.stream);
-        WalkArgs wa{nq, target_idx, node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
-                    t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
-                    t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
-                    t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(),
-                    t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, sigma, R * R, unlimited ? 1 : 0,
-                    rmax, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, order, work};
-        // as many blocks as the device holds at once (at most one per query)
-        static int resident = 0;
-        if (resident == 0) {
-            int per_cu = 0, cus = 0, dev = 0;
-            MSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void *>(k_partner<P>), 64 * kWalkWaves, 0));
-            MSP_HIP(hipGetDevice(&dev));
-            MSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-        }
-        const int64_t nblocks = nq < resident ? nq : resident;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nblocks), dim3(64 * kWalkWaves), 0,
-                           t->side.stream, wa);
-        MSP_CHECK_LAUNCH();
+    *q = QuerySet{nq, nq_dev, target_idx, node_id, qpos, uniforms, probs, choice, raw, order, prm->sigma,
+                  rho_max_for_p(P), R * R, unlimited ? 1 : 0, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0,
+                  t->counting ? t->work.as<unsigned long long>() : nullptr};
+    return MSP_OK;
+}
+
+// the walk (the queries whose node holds more than the wavefront pass takes),
+// against the node moments of the last partner_moments call
+template <int P>
+int launch_walk(msp_tree *t, const QuerySet &q, hipStream_t s) {
+    PhaseScope ps(&t->timing, PH_PARTNER, s);
+    const int lh = moment_level(t, q.sigma, P);
+    const int64_t nn = t->n_nodes;
+    const int64_t slot0 = t->level_off[lh < kMaxLevels ? lh : kDepth + 1];
+    WalkArgs wa{q.nq, q.target_idx, q.node_id, q.uniforms, t->n, nn, q.qpos, t->nlevel.as<int32_t>(),
+                t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(),
+                t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(),
+                t->node_hasA.as<uint8_t>(), t->nodeA.as<float>(), slot0, q.sigma, q.R2, q.unlimited,
+                q.rmax, q.exclude_self, q.probs, q.choice, q.raw, q.order, q.work};
+    // as many blocks as the device holds at once (at most one per query)
+    static int resident = 0;
+    if (resident == 0) {
+        int per_cu = 0, cus = 0, dev = 0;
+        MSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_partner<P>), 64 * kWalkWaves, 0));
+        MSP_HIP(hipGetDevice(&dev));
+        MSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
     }
+    const int64_t nblocks = q.nq < resident ? q.nq : resident;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_partner<P>), dim3((unsigned)nblocks), dim3(64 * kWalkWaves), 0, s, wa);
+    MSP_CHECK_LAUNCH();
+    return MSP_OK;
+}
+
+// the eight-lane and wavefront passes (nodes of at most kDirectPoints points):
+// point sums only, no node moments
+int launch_direct(msp_tree *t, const QuerySet &q, hipStream_t s) {
     {
         PhaseScope pl(&t->timing, PH_PARTNER_DIRECT, s);
-        hipLaunchKernelGGL(k_partner_direct, dim3(grid_for(nq * 8, 256)), dim3(256), 0, s, nq, nq_dev, target_idx,
-                           node_id, uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(),
+        hipLaunchKernelGGL(k_partner_direct, dim3(grid_for(q.nq * 8, 256)), dim3(256), 0, s, q.nq, q.nq_dev,
+                           q.target_idx, q.node_id, q.uniforms, t->n, t->n_nodes, q.qpos, t->nlevel.as<int32_t>(),
                            t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
                            t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
                            t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
-                           t->ps.as<float4>(), sigma, R * R, unlimited ? 1 : 0,
-                           (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw, work);
+                           t->ps.as<float4>(), q.sigma, q.R2, q.unlimited, q.exclude_self, q.probs, q.choice,
+                           q.raw, q.work);
         MSP_CHECK_LAUNCH();
     }
     {
         PhaseScope pw(&t->timing, PH_PARTNER_WAVE, s);
-        hipLaunchKernelGGL(k_partner_wave, dim3(grid_for(nq, 4)), dim3(256), 0, s, nq, nq_dev, target_idx, node_id,
-                           uniforms, t->n, nn, qpos, t->nlevel.as<int32_t>(), t->nfirst.as<int32_t>(),
-                           t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(),
-                           t->nix.as<int32_t>(), t->niy.as<int32_t>(), t->niz.as<int32_t>(), t->geo.lo[0],
-                           t->geo.lo[1], t->geo.lo[2], t->geo.side, t->ps.as<float4>(), sigma, R * R,
-                           unlimited ? 1 : 0, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, probs, choice, raw,
-                           work);
+        hipLaunchKernelGGL(k_partner_wave, dim3(grid_for(q.nq, 4)), dim3(256), 0, s, q.nq, q.nq_dev, q.target_idx,
+                           q.node_id, q.uniforms, t->n, t->n_nodes, q.qpos, t->nlevel.as<int32_t>(),
+                           t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->nfchild.as<int32_t>(),
+                           t->nnchild.as<int32_t>(), t->nix.as<int32_t>(), t->niy.as<int32_t>(),
+                           t->niz.as<int32_t>(), t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], t->geo.side,
+                           t->ps.as<float4>(), q.sigma, q.R2, q.unlimited, q.exclude_self, q.probs, q.choice,
+                           q.raw, q.work);
         MSP_CHECK_LAUNCH();
     }
-    MSP_TRY(t->side.join(s));
     return MSP_OK;
+}
+
+// queries against the node moments of the last partner_moments call; raw (or
+// NULL): the unnormalised per-octant sums.  The walk (few, long queries) runs on
+// a side stream beside the direct passes (many short ones) on the caller's stream.
+template <int P>
+int partner_queries(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
+                    const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
+                    int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s,
+                    const int64_t *nq_dev = nullptr) {
+    if (nq == 0) return MSP_OK;
+    QuerySet q;
+    MSP_TRY(queries_prepare<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, raw, qpos, s, nq_dev, &q));
+    if (t->timing.on && t->timing.isolate) {
+        MSP_TRY(launch_walk<P>(t, q, s));
+        return launch_direct(t, q, s);
+    }
+    MSP_TRY(t->side.fork(s));
+    MSP_TRY(launch_walk<P>(t, q, t->side.stream));
+    MSP_TRY(launch_direct(t, q, s));
+    return t->side.join(s);
 }
 
 }  // namespace
 
+// moments and queries: the direct passes need no moments, so they start on a
+// side stream while the caller's stream builds the moment pyramid, then the walk
 template <int P>
 int run_partner(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                 const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
                 int32_t *choice, hipStream_t s) {
+    if (nq == 0) return partner_moments<P>(t, prm, s);
+    QuerySet q;
+    MSP_TRY(queries_prepare<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, nullptr, nullptr, s,
+                               nullptr, &q));
+    if (t->timing.on && t->timing.isolate) {
+        MSP_TRY(launch_direct(t, q, s));
+        MSP_TRY(partner_moments<P>(t, prm, s));
+        return launch_walk<P>(t, q, s);
+    }
+    MSP_TRY(t->side.fork(s));
+    MSP_TRY(launch_direct(t, q, t->side.stream));
     MSP_TRY(partner_moments<P>(t, prm, s));
-    return partner_queries<P>(t, prm, target_idx, node_id, nq, uniforms, probs, choice, nullptr, nullptr, s);
+    MSP_TRY(launch_walk<P>(t, q, s));
+    return t->side.join(s);
 }
 
 int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm,

@@ -243,3 +243,59 @@ def test_work_counters_match_the_query_classes():
     if big.any():
         assert c["walk_nodes"] >= c["walk_queries"] and c["walk_rounds"] >= c["walk_queries"]
         assert c["walk_expansions"] + c["walk_pairs"] > 0
+
+
+def test_forward_and_partner_on_two_streams():
+    """After a weighted build, the forward and the partner probabilities (both with
+    the staged weights) share no device memory of the handle: issued on two streams
+    at once they give the same bits as one after the other on one stream, over
+    several steps of build, forward and partner call."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.slab4m(0.125)
+    print(f"forward and partner on two streams, slab {wl.n} points", flush=True)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 3000, seed=61)
+    d = to_dev(wl)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(d["x"].device)
+    tqd, nqd = T(tq, np.int32), T(nq, np.int32)
+    uni = T(synth.uniforms(len(tq), 62), np.float32)
+    tgt = T((wl.a > 0).astype(np.uint8), np.uint8)
+    u = torch.empty(wl.n, dtype=torch.float32, device=d["x"].device)
+    tree = msp.Tree()
+
+    def step(side):
+        tree.build(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max, w=d["w"])
+        main = torch.cuda.current_stream()
+        if side is None:
+            tree.forward(d["w"], tgt, sigma=wl.sigma, route="fgt", out=u, weights_staged=True)
+            P, c = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni, weights_staged=True)
+        else:
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                P, c = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni,
+                                                  weights_staged=True)
+            tree.forward(d["w"], tgt, sigma=wl.sigma, route="fgt", out=u, weights_staged=True)
+            main.wait_stream(side)
+        return u.clone(), P.clone(), c.clone()
+
+    u0, P0, c0 = step(None)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for it in range(3):
+        u1, P1, c1 = step(side)
+        torch.cuda.synchronize()
+        assert torch.equal(u1, u0), it
+        assert torch.equal(P1, P0), it
+        assert torch.equal(c1, c0), it
+    # isolated timing: the same bits with every pass on the caller's stream
+    tree.set_timing(True, isolated=True)
+    tree.timing(reset=True)
+    u2, P2, c2 = step(None)
+    ph = tree.timing(reset=True)
+    tree.set_timing(False)
+    assert torch.equal(u2, u0) and torch.equal(P2, P0) and torch.equal(c2, c0)
+    for name in ("node_moments", "partner", "partner_direct", "partner_wave", "p2m", "l2p"):
+        assert name in ph and ph[name][1] >= 1, name
+    assert msp._lib.msp_tree_set_timing(tree._h, 3) == msp.MSP_EINVAL
+    tree.close()
