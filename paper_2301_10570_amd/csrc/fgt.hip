@@ -307,16 +307,27 @@ __global__ void __launch_bounds__(kBlock) k_p2m_mfma8(const uint64_t *keys, int6
         wave_sync();
         if (c0 + kBlock < end) fetch(c0 + kBlock);
         const int cnt = end - c0 < kBlock ? (int)(end - c0) : kBlock;
-        const int w0 = wid * 64;
+        const int w0 = __builtin_amdgcn_readfirstlane(wid) * 64;
         if (w0 < cnt) {
-            const int steps = ((cnt - w0 < 64 ? cnt - w0 : 64) + 3) / 4;   // rows past the cell weigh 0
-            for (int st = 0; st < steps; ++st) {
-                const float *r = pw + (w0 + 4 * st + kq) * kPowStr;
-                const float a = r[ax] * r[8 + aylo];
-                const float b0 = r[8 + 2 * ayh0] * r[16 + azc];
-                const float b1 = r[8 + 2 * (ayh0 + 2)] * r[16 + azc];
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
+            // rows past the cell weigh 0, so the steps go in groups of eight (a
+            // wave-uniform count): all operands of a group are read from LDS
+            // before its products
+            const int steps = ((cnt - w0 < 64 ? cnt - w0 : 64) + 3) / 4;
+            for (int s0 = 0; s0 < steps; s0 += 8) {
+                float av[8], b0v[8], b1v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float *r = pw + (w0 + 4 * (s0 + u) + kq) * kPowStr;
+                    av[u] = r[ax] * r[8 + aylo];
+                    b0v[u] = r[8 + 2 * ayh0] * r[16 + azc];
+                    b1v[u] = r[8 + 2 * (ayh0 + 2)] * r[16 + azc];
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b0v[u], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b1v[u], acc1, 0, 0, 0);
+                }
             }
         }
     }

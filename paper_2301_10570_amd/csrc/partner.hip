@@ -314,22 +314,25 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
     }
     __syncthreads();
     for (int64_t v = v0 + blockIdx.x; v < v1; v += gridDim.x) {
-        const bool want = nsrc[v] > kC1;
+        // the node's fields in one round of loads
+        const int32_t ns = nsrc[v], nc = nnchild[v], nf = nfirst[v], ncnt = ncount[v], fch = nfchild[v];
+        const int32_t ix = nix[v], iy = niy[v], iz = niz[v];
+        const bool want = ns > kC1;
         if (lane == 0) hasA[v] = want ? 1 : 0;
         if (!want) continue;
-        const int32_t nc = nnchild[v];
-        const double cx = lox + (nix[v] + 0.5) * h, cy = loy + (niy[v] + 0.5) * h,
-                     cz = loz + (niz[v] + 0.5) * h;
+        const double cx = lox + (ix + 0.5) * h, cy = loy + (iy + 0.5) * h, cz = loz + (iz + 0.5) * h;
         // parts: the children (lanes 0..nc-1), or the node itself when it is a leaf
+        // or when no child can carry moments (then the children's points are the
+        // node's own range and their records need not be read)
         int32_t cf = 0, cn = 0, cdig = 0, cid = -1;
         bool chas = false;
-        if (nc == 0) {
+        if (nc == 0 || !M2M) {
             if (lane == 0) {
-                cf = nfirst[v];
-                cn = ncount[v];
+                cf = nf;
+                cn = ncnt;
             }
         } else if (lane < nc) {
-            cid = nfchild[v] + lane;
+            cid = fch + lane;
             chas = hasA[cid] != 0;
             cf = nfirst[cid];
             cn = ncount[cid];
@@ -387,13 +390,26 @@ k_node_moments(int64_t v0, int64_t v1, int level, const int32_t *nfirst, const i
                 }
                 __syncthreads();
                 if (c0 + 64 < total) fetch(c0 + 64);
-                const int m = total - c0 < 64 ? total - c0 : 64;
-                for (int st = 0; st < (m + 3) / 4; ++st) {
-                    const float *r = pts + (4 * st + kq) * STR;
-                    const float a = r[ax] * r[8 + aylo];
-                    const float wzv = r[16 + azc];
-                    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[8 + 2 * ayh] * wzv, d0, 0, 0, 0);
-                    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[8 + 2 * ayh + 4] * wzv, d1, 0, 0, 0);
+                // rows past the list weigh 0, so the steps go in groups of eight (a
+                // wave-uniform count): all operands of a group are read from LDS
+                // before its products
+                const int m = __builtin_amdgcn_readfirstlane(total - c0 < 64 ? total - c0 : 64);
+                for (int s0 = 0; s0 < (m + 3) / 4; s0 += 8) {
+                    float av[8], b0v[8], b1v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float *r = pts + (4 * (s0 + u) + kq) * STR;
+                        const float wzv = r[16 + azc];
+                        av[u] = r[ax] * r[8 + aylo];
+                        b0v[u] = r[8 + 2 * ayh] * wzv;
+                        b1v[u] = r[8 + 2 * ayh + 4] * wzv;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b0v[u], d0, 0, 0, 0);
+                        d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b1v[u], d1, 0, 0, 0);
+                    }
                 }
             }
             // D[4 kq + i][n] of the two tiles, times 1 / (ax! ay! az!)

@@ -136,19 +136,23 @@ def test_partner_edge_cases():
     assert P.shape == (0, 8)
 
 
-def test_node_moments_m2m_parity():
+@pytest.mark.parametrize("leaf_max", [None, 512])
+def test_node_moments_m2m_parity(leaf_max):
     """Node moments (P2M at the lowest moment-carrying nodes, M2M upward) equal the
     oracle's P2M over all points of the node about its centre (M2M is exact
-    under the tensor truncation), and the slab's large nodes carry them."""
+    under the tensor truncation), and the slab's large nodes carry them; with
+    leaves of up to 512 points, leaves carry moments too (from their own points)."""
     import torch
     import paper_2301_10570_amd as msp
     from oracle import fgt as ofgt
     wl = synth.slab4m(0.0625)
+    if leaf_max is not None:
+        wl.leaf_max = leaf_max
     tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
     d = to_dev(wl)
     tree = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
     e = torch.zeros(0, dtype=torch.int32, device=d["x"].device)
-    print("node moments parity (slab 1/16, p=8)", flush=True)
+    print(f"node moments parity (slab 1/16, p=8, leaf_max {wl.leaf_max})", flush=True)
     p = 8
     tree.partner_probabilities(d["w"], e, e, wl.sigma, p=p)
     has = tree.debug_buffer(3).cpu().numpy()
@@ -166,7 +170,12 @@ def test_node_moments_m2m_parity():
     A = A.reshape(-1, p, p, p)   # [slot][az][ay][ax]
     pos = wl.pos64()
     rng = np.random.default_rng(1)
-    for v in rng.choice(nodes, 40, replace=False):
+    pick = rng.choice(nodes, 40, replace=False)
+    if leaf_max is not None:
+        leaves = nodes[tr.is_leaf[nodes] != 0]
+        assert leaves.size > 0
+        pick = np.concatenate([pick, rng.choice(leaves, min(10, leaves.size), replace=False)])
+    for v in pick:
         c, _ = octree.node_box(tr, v)
         ids = tr.perm[tr.first[v]:tr.first[v] + tr.count[v]]
         ref = ofgt.p2m(pos[ids], wl.w[ids], c, wl.sigma, p)   # [ax, ay, az]
