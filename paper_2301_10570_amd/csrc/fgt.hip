@@ -908,11 +908,13 @@ __global__ void __launch_bounds__(64) k_m2l_pass_bf16x3(const float *In, float *
 // in x, then y, then z), two targets per thread so that every coefficient read
 // from LDS feeds two multiply-adds.
 // Taylor series of cell (kx, ky, kz) at its points [start, end) (block-wide).
-template <int P>
-__device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *is_target, const float *w,
-                         int subtract_self, int Gx, int Gy, double lox, double loy, double loz,
-                         double cell, double inv_sigma, const float *C, float *u_out, int kx, int ky,
-                         int kz, int64_t start, int64_t end) {
+// TGT: target flags given; SUB: the self term w_j is subtracted (both fixed per
+// launch, so the gathers through the permutation issue without branches)
+template <int P, bool TGT, bool SUB>
+__device__ void l2p_cell_impl(const float4 *ps, const int32_t *perm, const uint8_t *is_target,
+                              const float *w, int Gx, int Gy, double lox, double loy, double loz,
+                              double cell, double inv_sigma, const float *C, float *u_out, int kx,
+                              int ky, int kz, int64_t start, int64_t end) {
     constexpr int P3 = P * P * P;
     __shared__ float sC[P3];
     const int64_t Rx = (int64_t)Gx * P, Ry = (int64_t)Gy * P;
@@ -937,10 +939,13 @@ __device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *i
             X[u] = (q.x - (float)cx) * (float)inv_sigma;
             Y[u] = (q.y - (float)cy) * (float)inv_sigma;
             Z[u] = (q.z - (float)cz) * (float)inv_sigma;
-            // the scattered reads of the output step are issued before the evaluation
             jo[u] = perm[has[u] ? i : i0];
-            tg[u] = !is_target || is_target[jo[u]];
-            ws[u] = subtract_self ? w[jo[u]] : 0.f;
+        }
+        // the scattered reads of the output step are issued before the evaluation
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            tg[u] = TGT ? is_target[jo[u]] != 0 : true;
+            ws[u] = SUB ? w[jo[u]] : 0.f;
         }
         float uz[NPT];
 #pragma unroll
@@ -971,6 +976,28 @@ __device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *i
 #pragma unroll
         for (int u = 0; u < NPT; ++u)
             if (has[u]) u_out[jo[u]] = tg[u] ? uz[u] - ws[u] : 0.f;
+    }
+}
+
+template <int P>
+__device__ void l2p_cell(const float4 *ps, const int32_t *perm, const uint8_t *is_target, const float *w,
+                         int subtract_self, int Gx, int Gy, double lox, double loy, double loz,
+                         double cell, double inv_sigma, const float *C, float *u_out, int kx, int ky,
+                         int kz, int64_t start, int64_t end) {
+    if (is_target) {
+        if (subtract_self)
+            l2p_cell_impl<P, true, true>(ps, perm, is_target, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, C,
+                                         u_out, kx, ky, kz, start, end);
+        else
+            l2p_cell_impl<P, true, false>(ps, perm, is_target, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, C,
+                                          u_out, kx, ky, kz, start, end);
+    } else {
+        if (subtract_self)
+            l2p_cell_impl<P, false, true>(ps, perm, is_target, w, Gx, Gy, lox, loy, loz, cell, inv_sigma, C,
+                                          u_out, kx, ky, kz, start, end);
+        else
+            l2p_cell_impl<P, false, false>(ps, perm, is_target, w, Gx, Gy, lox, loy, loz, cell, inv_sigma,
+                                           C, u_out, kx, ky, kz, start, end);
     }
 }
 
@@ -2440,6 +2467,7 @@ int stage_inputs(msp_tree *t, const float *w, const uint8_t *is_target, hipStrea
     MSP_TRY(t->tflag.ensure(nb));
     MSP_TRY(t->usort.ensure(nb * 4));
     if (n == 0) return MSP_OK;
+    ++t->ps_gen;
     PhaseScope ps(&t->timing, PH_STAGE, s);
     hipLaunchKernelGGL(k_stage, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, w, is_target,
                        t->perm.as<int32_t>(), n, t->ps.as<float4>(), t->tflag.as<uint8_t>());
@@ -2452,6 +2480,7 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
     const bool staged = (prm->flags & MSP_WEIGHTS_STAGED) != 0;
     const GridArgs ga{w, staged ? nullptr : w, is_target, (prm->flags & MSP_EXCLUDE_SELF) ? 1 : 0, u_out,
                       !staged && (prm->flags & MSP_STAGE_WEIGHTS) != 0};
+    if (ga.stage) ++t->ps_gen;   // its P2M rewrites the weights of the records
     const int p = pl.p;
     const int64_t ncell = (int64_t)pl.G[0] * pl.G[1] * pl.G[2];
     size_t gbytes = 0, obytes = 0;

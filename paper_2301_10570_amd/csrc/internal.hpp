@@ -217,6 +217,8 @@ struct msp_tree {
     msp::DevBuf keys, perm, iperm, ps;
     bool iperm_valid = false;   // ps: float4 (x, y, z, staged weight) in key order
     bool w_staged = false;      // ps.w holds the weights of the last weight-taking call
+    int64_t ps_gen = 0;         // bumped by every write of ps.w
+    int64_t src_prefix_gen = -1;   // ps_gen that src_prefix was computed from
     // node table (SoA, int32)
     msp::DevBuf nlevel, nfirst, ncount, nparent, nfchild, nnchild, ndigit, nix, niy, niz;
     msp::DevBuf d_level_off;  // int64[kMaxLevels] on the device
@@ -476,6 +478,8 @@ int partner_probabilities(msp_tree *t, const float *w, const msp_fgt_params *prm
 // of the targets, or NULL to look them up; nq_dev (or NULL): the number of queries
 // in device memory, at most nq (the arrays' size)
 int partner_prepare(msp_tree *t, const float *w, const msp_fgt_params *prm, hipStream_t s);
+// the sources (records with w != 0) before each key-order position, from ps.w
+int source_prefix(msp_tree *t, hipStream_t s);
 int partner_query_raw(msp_tree *t, const msp_fgt_params *prm, const int32_t *target_idx,
                       const int32_t *node_id, int64_t nq, float *probs, double *raw, const int32_t *qpos,
                       hipStream_t s, const int64_t *nq_dev = nullptr);

@@ -1650,6 +1650,27 @@ __global__ void __launch_bounds__(256) k_order_place(int64_t nq, const int64_t *
     if (l >= 0) order[(size_t)l * nq + base[l] + slot] = (int32_t)q;
 }
 
+}  // namespace
+
+int source_prefix(msp_tree *t, hipStream_t s) {
+    const int64_t n = t->n;
+    const int64_t ntile = (n + kSrcTile - 1) / kSrcTile;
+    MSP_TRY(t->src_prefix.ensure((size_t)(n + 1 + ntile) * 4));
+    if (n == 0) return MSP_OK;
+    int32_t *S = t->src_prefix.as<int32_t>();
+    int32_t *tile = S + n + 1;
+    hipLaunchKernelGGL(k_src_tiles, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile);
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_src_tile_scan, dim3(1), dim3(1024), 0, s, ntile, tile);
+    MSP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_src_prefix, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile, S);
+    MSP_CHECK_LAUNCH();
+    t->src_prefix_gen = t->ps_gen;
+    return MSP_OK;
+}
+
+namespace {
+
 // coarsest level whose half-side is within rho_max(p) sigma: the moment level
 int moment_level(const msp_tree *t, double sigma, int p) {
     const double rmax = rho_max_for_p(p);
@@ -1675,20 +1696,12 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
         PhaseScope ps(&t->timing, PH_NODE_MOMENTS, s);
         {
             PhaseScope ps_counts(&t->timing, PH_NODE_COUNTS, s);
-            const int64_t n = t->n;
-            const int64_t ntile = (n + kSrcTile - 1) / kSrcTile;
-            MSP_TRY(t->src_prefix.ensure((size_t)(n + 1 + ntile) * 4));
-            int32_t *S = t->src_prefix.as<int32_t>();
-            int32_t *tile = S + n + 1;
-            if (n == 0) return fail(MSP_EINVAL, "node moments of an empty tree");
-            hipLaunchKernelGGL(k_src_tiles, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile);
-            MSP_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_src_tile_scan, dim3(1), dim3(1024), 0, s, ntile, tile);
-            MSP_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_src_prefix, dim3((unsigned)ntile), dim3(256), 0, s, n, t->ps.as<float4>(), tile, S);
-            MSP_CHECK_LAUNCH();
+            if (t->n == 0) return fail(MSP_EINVAL, "node moments of an empty tree");
+            // the prefix may come from the weighted build that staged these weights
+            if (t->src_prefix_gen != t->ps_gen) MSP_TRY(source_prefix(t, s));
             hipLaunchKernelGGL(k_nsrc_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn,
-                               t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), S, t->node_nsrc.as<int32_t>());
+                               t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->src_prefix.as<int32_t>(),
+                               t->node_nsrc.as<int32_t>());
             MSP_CHECK_LAUNCH();
         }
         for (int l = t->depth; l >= 0; --l) {

@@ -859,6 +859,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     t->lists_valid = false;
     t->counts_valid = false;
     t->w_staged = false;
+    ++t->ps_gen;   // the records are rewritten
     t->node_moments_level = -1;
     t->n = n;
     t->leaf_max = leaf_max;
@@ -970,18 +971,38 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
         std::memcpy(t->level_off, h, kMaxLevels * 8);
         return MSP_OK;
     };
+    // a weighted build (handle memory) also counts the sources before each position,
+    // on a side stream beside the node levels and table, for the node moments of a
+    // following partner call on the same weights
+    const bool prefix = w != nullptr && n > 0 && !caller_mem;
+    const bool side = prefix && !(t->timing.on && t->timing.isolate);
     if (n > 0) {
         MSP_TRY(keys_and_sort(false));
+        if (prefix) {
+            hipStream_t ps_stream = s;
+            if (side) {
+                MSP_TRY(t->side.fork(s));
+                ps_stream = t->side.stream;
+            }
+            PhaseScope pc(&t->timing, PH_NODE_COUNTS, ps_stream);
+            MSP_TRY(source_prefix(t, ps_stream));
+        }
         MSP_TRY(levels());
         MSP_TRY(readback());
         const char *h = static_cast<const char *>(t->build_stage.p);
         int flags[2];
         std::memcpy(box, h + kRbBox, 6 * sizeof(float));
         std::memcpy(flags, h + kRbBox + 8 * sizeof(float), sizeof(flags));
-        if (flags[0]) return fail(MSP_EINVAL, "msp_octree_build: non-finite coordinate in input");
+        if (flags[0]) {
+            if (side) MSP_TRY(t->side.join(s));
+            return fail(MSP_EINVAL, "msp_octree_build: non-finite coordinate in input");
+        }
         set_geometry();
         if (flags[1]) {
             // a run of equal 24-bit prefix was too long for the run sort: sort all bits
+            // (after the source prefix, which read the records and is now stale)
+            if (side) MSP_TRY(t->side.join(s));
+            t->src_prefix_gen = -1;
             MSP_TRY(keys_and_sort(true));
             MSP_TRY(levels());
             MSP_TRY(readback());
@@ -1037,6 +1058,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     MSP_CHECK_LAUNCH();
     }
 
+    if (side) MSP_TRY(t->side.join(s));   // (joining twice is harmless)
     t->built = true;
     t->w_staged = w != nullptr && n > 0;   // the sorted records carry the weights
     return MSP_OK;

@@ -290,6 +290,13 @@ def test_forward_and_partner_on_two_streams():
 
     u0, P0, c0 = step(None)
     torch.cuda.synchronize()
+    # the weighted build counted the sources per position for the node moments; a
+    # tree built without weights, whose partner call stages them and counts itself,
+    # gives the same bits
+    plain = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+    Pp, cp = plain.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni)
+    assert torch.equal(Pp, P0) and torch.equal(cp, c0)
+    plain.close()
     side = torch.cuda.Stream()
     for it in range(3):
         u1, P1, c1 = step(side)
