@@ -439,18 +439,24 @@ def main():
     # partner call runs on a second stream beside the forward (--serial: one stream)
     side = torch.cuda.Stream()
 
+    probs = torch.empty(tq.numel() * 8, dtype=torch.float32, device=dev)
+    choice = torch.empty(tq.numel(), dtype=torch.int32, device=dev)
+
     def step(serial=args.serial):
         # the vacant element counts ride into key order with the positions
         tree.build(x, y, z, leaf_max=wl.leaf_max, w=w)
         main = torch.cuda.current_stream()
-        if tq.numel() and not serial:
-            side.wait_stream(main)
-            with torch.cuda.stream(side):
-                tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
+        two = tq.numel() > 0 and not serial
+        if two:
+            side.wait_stream(main)   # the partner call follows the build, not the forward
+        # the forward first: its few launches reach the GPU while the host issues
+        # the partner call's
         tree.forward(w, tgt, sigma=wl.sigma, p=wl.p, route=args.route, out=u, weights_staged=True)
-        if tq.numel() and serial:
-            tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True)
-        if tq.numel() and not serial:
+        if tq.numel():
+            with torch.cuda.stream(side if two else main):
+                tree.partner_probabilities(w, tq, nq, wl.sigma, p=wl.p, uniforms=uni, weights_staged=True,
+                                           out=(probs, choice))
+        if two:
             main.wait_stream(side)   # the next build rewrites what the partner call reads
 
     print("bench: warmup", file=sys.stderr, flush=True)

@@ -390,18 +390,25 @@ class Tree:
         return out
 
     def partner_probabilities(self, w, target_idx, node_id, sigma, p=8, uniforms=None,
-                              exclude_self=False, level=-1, cutoff_sigmas=4.5, weights_staged=False):
+                              exclude_self=False, level=-1, cutoff_sigmas=4.5, weights_staged=False,
+                              out=None):
         """Child probabilities (msp_partner_probabilities): probs [nq, 8] and choice [nq].
         weights_staged: w is the weight array of the last forward, partner or descent
         call on this tree, unchanged since, and the weights that call gathered into
-        key order are used again (MSP_WEIGHTS_STAGED)."""
+        key order are used again (MSP_WEIGHTS_STAGED).  out: (probs, choice) to fill
+        (float32 [nq, 8] or [8 nq], int32 [nq]), else new tensors."""
         nq = target_idx.numel()
         pw = _ptr(w, torch.float32, self.n, "w")
         pti = _ptr(target_idx, torch.int32, nq, "target_idx")
         pni = _ptr(node_id, torch.int32, nq, "node_id")
         pu = _ptr(uniforms, torch.float32, nq, "uniforms")
-        probs = torch.empty(nq * 8, dtype=torch.float32, device=w.device)
-        choice = torch.empty(nq, dtype=torch.int32, device=w.device)
+        if out is None:
+            probs = torch.empty(nq * 8, dtype=torch.float32, device=w.device)
+            choice = torch.empty(nq, dtype=torch.int32, device=w.device)
+        else:
+            probs, choice = out
+            _ptr(probs, torch.float32, nq * 8, "out probs")
+            _ptr(choice, torch.int32, nq, "out choice")
         prm = _params(sigma, p, level, "auto", cutoff_sigmas, exclude_self)
         if weights_staged:
             prm.flags |= WEIGHTS_STAGED

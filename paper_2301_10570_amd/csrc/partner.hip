@@ -126,21 +126,27 @@ __global__ void __launch_bounds__(256) k_src_prefix(int64_t n, const float4 *ps,
     }
 }
 
+// sources per node; the moment flags start cleared (the moment kernels set those
+// of the levels they visit)
 __global__ void k_nsrc_nodes(int64_t nn, const int32_t *nfirst, const int32_t *ncount, const int32_t *S,
-                             int32_t *nsrc) {
+                             int32_t *nsrc, uint8_t *hasA) {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= nn) return;
     const int32_t f = nfirst[v];
     nsrc[v] = S[f + ncount[v]] - S[f];
+    hasA[v] = 0;
 }
 
 // Key-order position of each query's target: its Morton key (as the tree build
 // computes it) is searched among the sorted keys, then the run of equal keys is
 // scanned for the point itself.  -1 for an index out of range.
+// tally (or NULL): per-level counters of the walk's order, cleared here for the
+// k_order_place that follows on the stream
 __global__ void k_query_pos(int64_t nq, const int32_t *target_idx, int64_t n, const float4 *pin,
                             const uint64_t *keys, const int32_t *perm, double lx, double ly, double lz,
-                            double scale, int32_t *qpos) {
+                            double scale, int32_t *qpos, int32_t *tally) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tally && q < kMaxLevels) tally[q] = 0;
     if (q >= nq) return;
     const int32_t t = target_idx[q];
     int32_t pos = -1;
@@ -1691,7 +1697,6 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
     MSP_TRY(t->node_hasA.ensure(nn));
     MSP_TRY(t->node_nsrc.ensure(nn * 4));
     MSP_TRY(t->nodeA.ensure((size_t)(nslots > 0 ? nslots : 1) * P * P * P * 4));
-    MSP_HIP(hipMemsetAsync(t->node_hasA.p, 0, nn, s));
     {
         PhaseScope ps(&t->timing, PH_NODE_MOMENTS, s);
         {
@@ -1701,7 +1706,7 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
             if (t->src_prefix_gen != t->ps_gen) MSP_TRY(source_prefix(t, s));
             hipLaunchKernelGGL(k_nsrc_nodes, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn,
                                t->nfirst.as<int32_t>(), t->ncount.as<int32_t>(), t->src_prefix.as<int32_t>(),
-                               t->node_nsrc.as<int32_t>());
+                               t->node_nsrc.as<int32_t>(), t->node_hasA.as<uint8_t>());
             MSP_CHECK_LAUNCH();
         }
         for (int l = t->depth; l >= 0; --l) {
@@ -1753,21 +1758,24 @@ int queries_prepare(msp_tree *t, const msp_fgt_params *prm, const int32_t *targe
                     const int32_t *node_id, int64_t nq, const float *uniforms, float *probs,
                     int32_t *choice, double *raw, const int32_t *qpos, hipStream_t s,
                     const int64_t *nq_dev, QuerySet *q) {
-    if (!qpos) {   // key-order positions of the targets
+    // the walk's queries, coarsest first: per-level segments and their counters
+    MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
+    int32_t *order = t->partner_order.as<int32_t>();
+    int32_t *tally = order + (size_t)kMaxLevels * nq;
+    if (!qpos) {   // key-order positions of the targets (and the counters cleared)
         MSP_TRY(t->partner_qpos.ensure((size_t)nq * 4));
-        hipLaunchKernelGGL(k_query_pos, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, target_idx, t->n,
+        const int64_t nthreads = nq > kMaxLevels ? nq : kMaxLevels;
+        hipLaunchKernelGGL(k_query_pos, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, s, nq, target_idx, t->n,
                            t->pin.as<float4>(), t->keys.as<uint64_t>(), t->perm.as<int32_t>(), t->geo.lo[0],
-                           t->geo.lo[1], t->geo.lo[2], t->geo.scale, t->partner_qpos.as<int32_t>());
+                           t->geo.lo[1], t->geo.lo[2], t->geo.scale, t->partner_qpos.as<int32_t>(), tally);
         MSP_CHECK_LAUNCH();
         qpos = t->partner_qpos.as<int32_t>();
+    } else {
+        hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, tally);
+        MSP_CHECK_LAUNCH();
     }
     const bool unlimited = !(prm->cutoff_sigmas > 0.f);
     const float R = unlimited ? 0.f : (float)(prm->cutoff_sigmas * prm->sigma);
-    // the walk's queries, coarsest first
-    MSP_TRY(t->partner_order.ensure((size_t)((int64_t)kMaxLevels * nq + kMaxLevels) * 4));
-    int32_t *order = t->partner_order.as<int32_t>();
-    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, order + (size_t)kMaxLevels * nq);
-    MSP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_order_place, dim3(grid_for(nq, kBlock)), dim3(kBlock), 0, s, nq, nq_dev, target_idx, node_id,
                        t->n, t->n_nodes, qpos, t->nlevel.as<int32_t>(), t->ncount.as<int32_t>(),
                        t->nfchild.as<int32_t>(), t->nnchild.as<int32_t>(), order);
