@@ -399,7 +399,12 @@ int msp_partner_descent(msp_tree *t, const float *w, const float *a, const msp_f
  *     msp_descent_step call, float64 [npair], pairs grouped by axon box in key order;
  *   which 5, 6: the axon box and the dendrite box of each pair (int32 [npair], box indices);
  *   which 7: the tree node of each box (int32 [nbox], boxes in key order);
- *     4..7 give MSP_ESTATE when that call used no box pairs.
+ *     4..7 give MSP_ESTATE when that call used no box pairs;
+ *   which 8: the points in key order as the last call left them, float32 [n][4]
+ *     (x, y, z, staged weight; the weight slot is unspecified before any call that
+ *     stages weights);
+ *   which 9: the inverse permutation (int32 [n], input index -> key-order position),
+ *     computed on `stream` first if the build did not leave it.
  * *bytes receives the buffer size; if dst (device) is non-NULL and dst_bytes >= *bytes
  * the buffer is copied there on `stream`, otherwise MSP_EINVAL (dst too small). */
 int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes, size_t *bytes,

@@ -373,7 +373,7 @@ class Tree:
         """Copy of an internal buffer: 0 moment grid, 1 Taylor grid (last expansion-route
         forward), 2 node moments, 3 node moment flags (last partner call), 4 box-pair
         attractions, 5 / 6 axon / dendrite box of each pair, 7 node of each box (last
-        descent)."""
+        descent), 8 points in key order (x, y, z, staged weight), 9 inverse permutation."""
         nbytes = ctypes.c_size_t()
         _check(_lib.msp_fgt_debug_buffer(self._h, int(which), None, 0, ctypes.byref(nbytes), None),
                "msp_fgt_debug_buffer")
@@ -381,7 +381,7 @@ class Tree:
             out = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
         elif which == 4:
             out = torch.empty(nbytes.value // 8, dtype=torch.float64, device="cuda")
-        elif which in (5, 6, 7):
+        elif which in (5, 6, 7, 9):
             out = torch.empty(nbytes.value // 4, dtype=torch.int32, device="cuda")
         else:
             out = torch.empty(nbytes.value // 4, dtype=torch.float32, device="cuda")

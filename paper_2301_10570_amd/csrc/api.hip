@@ -544,8 +544,13 @@ int msp_fgt_debug_buffer(msp_tree *t, int32_t which, void *dst, size_t dst_bytes
             *bytes = (size_t)t->desc_nbox * 4;
             src = t->desc_box.as<char>() + ((size_t)t->n_nodes * 4 + 255) / 256 * 256;
         }
+    } else if (which == 8 || which == 9) {
+        if (!t->built) return fail(MSP_ESTATE, "no tree built");
+        if (which == 9) MSP_TRY(ensure_iperm(t, (hipStream_t)stream));
+        *bytes = (size_t)t->n * (which == 8 ? 16 : 4);
+        src = which == 8 ? t->ps.p : t->iperm.p;
     } else {
-        return fail(MSP_EINVAL, "which must be 0..7");
+        return fail(MSP_EINVAL, "which must be 0..9");
     }
     if (!dst) return MSP_OK;
     if (dst_bytes < *bytes) return fail(MSP_EINVAL, "destination holds %zu bytes, need %zu", dst_bytes, *bytes);

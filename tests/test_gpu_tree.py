@@ -40,7 +40,20 @@ def _compare(x, y, z, leaf_max=64, max_depth=21):
     assert np.array_equal(got["node_iz"], ref.iz)
     lo = np.asarray(info["level_offset"][:len(ref.level_offset)])
     assert np.array_equal(lo, ref.level_offset)
+    _check_records(tree, x, y, z, ref.perm)
     tree.close()
+
+
+def _check_records(tree, x, y, z, perm, w=None):
+    """The points in key order (and the weights, for a weighted build) are the
+    inputs through the permutation, bit for bit, and the inverse permutation
+    inverts it."""
+    n = perm.size
+    rec = tree.debug_buffer(8).cpu().numpy().reshape(n, 4)
+    for k, v in enumerate((x, y, z) if w is None else (x, y, z, w)):
+        assert np.array_equal(rec[:, k], np.asarray(v, np.float32)[perm]), k
+    ip = tree.debug_buffer(9).cpu().numpy()
+    assert np.array_equal(ip[perm], np.arange(n, dtype=np.int32))
 
 
 @pytest.mark.parametrize("make,scale", [("uniform4k", 1.0), ("blobs262k", 1.0), ("slab4m", 0.0625)])
@@ -62,6 +75,20 @@ def test_tree_full_slab():
     wl = synth.slab4m()
     print("tree bit-exact: full slab", flush=True)
     _compare(wl.x, wl.y, wl.z)
+
+
+def test_weighted_build_records():
+    """A weighted build carries the weights into key order with the positions."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.slab4m(0.0625)
+    print("weighted build records, slab 1/16", flush=True)
+    ref = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    d = to_dev(wl)
+    tree = msp.Tree()
+    tree.build(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max, w=d["w"])
+    _check_records(tree, wl.x, wl.y, wl.z, ref.perm, wl.w)
+    tree.close()
 
 
 def test_tree_edge_cases():
