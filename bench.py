@@ -43,7 +43,8 @@ KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "so
                    "l2p": "k_l2p", "m2l_x": "k_m2l_gemm", "m2l_y": "k_m2l_gemm",
                    "m2l_z": "k_m2l_gemm", "morton": "k_morton", "stage": "k_stage",
                    "partner": "k_partner", "partner_direct": "k_partner_direct",
-                   "partner_wave": "k_partner_wave"}
+                   "partner_wave": "k_partner_wave",
+                   "scatter": "k_finish_u"}   # (expansion route: flags and self term in input order)
 
 
 def _algorithmic(phase, ctx):
@@ -90,6 +91,9 @@ def _algorithmic(phase, ctx):
         return "hbm", "GB/s", n * (12 + 8 + 4 + 16.0)
     if phase == "stage":
         return "hbm", "GB/s", n * (4 + 1 + 4 + 16 + 1.0)
+    if phase == "scatter":
+        # target flag read, u read and written in input order
+        return "hbm", "GB/s", n * (1 + 4 + 4.0)
     return None
 
 

@@ -1467,10 +1467,7 @@ int launch_p2m_l2p(msp_tree *t, const FgtPlan &pl, double inv_sigma, bool l2p, c
                            t->keys.as<uint64_t>(), t->n, t->ps.as<float4>(), t->perm.as<int32_t>(),
                            (const uint8_t *)nullptr, ga.w, 0, pl.level, pl.G[0], pl.G[1], pl.G[2],
                            t->geo.lo[0], t->geo.lo[1], t->geo.lo[2], pl.cell, inv_sigma, C, ga.u_out);
-        MSP_CHECK_LAUNCH();
-        if (ga.is_target || ga.subtract_self)
-            hipLaunchKernelGGL(k_finish_u, dim3(grid_for(t->n, kBlock)), dim3(kBlock), 0, s, t->n, ga.is_target,
-                               ga.w, ga.subtract_self, ga.u_out);
+        // (the target flags and the self term follow in fgt_forward_grid)
     }
     MSP_CHECK_LAUNCH();
     return MSP_OK;
@@ -2575,8 +2572,19 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
         MSP_CHECK_LAUNCH();
     }
     if (!u_out) return MSP_OK;   // callers that evaluate the Taylor grid themselves
-    PhaseScope ps(&t->timing, PH_L2P, s);
-    return dispatch_p2m_l2p(t, pl, inv_sigma, true, B, nullptr, ga, s);
+    {
+        PhaseScope ps(&t->timing, PH_L2P, s);
+        MSP_TRY(dispatch_p2m_l2p(t, pl, inv_sigma, true, B, nullptr, ga, s));
+    }
+    // the single-level L2P writes every point's sum: target flags and self term in
+    // input order afterwards (the two-level L2P applies them itself)
+    if (pl.pf == 0 && (ga.is_target || ga.subtract_self)) {
+        PhaseScope ps(&t->timing, PH_SCATTER, s);
+        hipLaunchKernelGGL(k_finish_u, dim3(grid_for(t->n, kBlock)), dim3(kBlock), 0, s, t->n, ga.is_target, ga.w,
+                           ga.subtract_self, ga.u_out);
+        MSP_CHECK_LAUNCH();
+    }
+    return MSP_OK;
 }
 
 int scatter_output(msp_tree *t, float *u_out, uint32_t flags, bool subtract_self, hipStream_t s) {
