@@ -229,8 +229,10 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t *kin, cons
                                                        const float4 *pin, float4 *ps) {
     constexpr int kWaves = kBlock / 64;
     constexpr int kPerWave = kTile / kWaves;   // items of one wavefront, contiguous
+    // the tile in digit order passes through LDS twice, keys then indices, in one
+    // buffer (38 KB per block, so that four blocks share a compute unit)
     __shared__ uint64_t sk[kTile];
-    __shared__ int32_t sv[kTile];
+    int32_t *sv = reinterpret_cast<int32_t *>(sk);
     __shared__ uint32_t lds[kWaves];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t toff[256];
@@ -287,26 +289,37 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t *kin, cons
         o += t;
     }
     __syncthreads();
+    uint32_t off[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        if (wid * kPerWave + j * 64 + lane < cnt) {
-            const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
-            const uint32_t off = wcnt[wid][d] + r[j];
-            sk[off] = k[j];
-            sv[off] = v[j];
-        }
+        const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+        off[j] = wcnt[wid][d] + r[j];
+        if (wid * kPerWave + j * 64 + lane < cnt) sk[off[j]] = k[j];
     }
     __syncthreads();
+    uint32_t pos[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int p = j * kBlock + tid;
         if (p < cnt) {
             const uint64_t key = sk[p];
             const uint32_t d = (uint32_t)(key >> shift) & 255u;
-            const uint32_t pos = gbase[d] + (uint32_t)p - toff[d];
-            kout[pos] = key;
-            vout[pos] = sv[p];
-            if (ps) ps[pos] = pin[sv[p]];   // last pass: positions into key order
+            pos[j] = gbase[d] + (uint32_t)p - toff[d];
+            kout[pos[j]] = key;
+        }
+    }
+    __syncthreads();   // the keys are read: the buffer takes the indices
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        if (wid * kPerWave + j * 64 + lane < cnt) sv[off[j]] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int p = j * kBlock + tid;
+        if (p < cnt) {
+            const int32_t val = sv[p];
+            vout[pos[j]] = val;
+            if (ps) ps[pos[j]] = pin[val];   // last pass: positions into key order
         }
     }
 }
