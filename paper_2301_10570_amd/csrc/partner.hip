@@ -1715,7 +1715,7 @@ int partner_moments(msp_tree *t, const msp_fgt_params *prm, hipStream_t s) {
             if (l < lh) break;
             // the deepest level holds only leaves, which never exceed leaf_max points
             if (l == t->depth && t->leaf_max <= kC1 && l < t->max_depth) continue;
-            const int64_t nb = b - a < 8192 ? b - a : 8192;
+            const int64_t nb = b - a < 65536 ? b - a : 65536;   // one node per block where it fits
             // children at the deepest level are leaves of at most leaf_max points: no moments
             const bool leaf_children = l + 1 == t->depth && t->leaf_max <= kC1 && l + 1 < t->max_depth;
             auto kern = leaf_children ? k_node_moments<P, false> : k_node_moments<P, true>;
