@@ -63,7 +63,7 @@ def test_tree_bitexact_workloads(make, scale):
     _compare(wl.x, wl.y, wl.z)
 
 
-@pytest.mark.parametrize("leaf_max,max_depth", [(1, 21), (7, 21), (64, 3), (100, 21), (64, 0)])
+@pytest.mark.parametrize("leaf_max,max_depth", [(1, 21), (7, 21), (64, 3), (100, 21), (64, 0), (1500, 21)])
 def test_tree_bitexact_params(leaf_max, max_depth):
     wl = synth.blobs(6, 700, extent=1500.0, std=40.0, seed=12)
     print(f"tree params leaf_max={leaf_max} max_depth={max_depth}", flush=True)
