@@ -315,3 +315,54 @@ def test_forward_and_partner_on_two_streams():
         assert name in ph and ph[name][1] >= 1, name
     assert msp._lib.msp_tree_set_timing(tree._h, 3) == msp.MSP_EINVAL
     tree.close()
+
+
+def test_source_counts_follow_the_staged_weights():
+    """The node moments reuse the per-position source counts of a weighted build only
+    while the staged weights are those of the build: after a forward that stages
+    other weights, or a partner call that stages its own, the counts are taken
+    again, and every result equals that of a fresh tree given the same weights."""
+    import torch
+    import paper_2301_10570_amd as msp
+    wl = synth.slab4m(0.0625)
+    print(f"source counts and staged weights, slab {wl.n} points", flush=True)
+    tr = octree.build(wl.x, wl.y, wl.z, leaf_max=wl.leaf_max)
+    tq, nq = _queries(tr, wl.n, 600, seed=71)
+    d = to_dev(wl)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(d["x"].device)
+    tqd, nqd = T(tq, np.int32), T(nq, np.int32)
+    uni = T(synth.uniforms(len(tq), 72), np.float32)
+    tgt = T((wl.a > 0).astype(np.uint8), np.uint8)
+    # other weights: about half the sources switched off, so that the nodes' source
+    # counts (and with them which nodes carry moments) change
+    keep = np.random.default_rng(73).random(wl.n) < 0.5
+    w2 = T(np.where(keep, wl.w, 0).astype(np.float32), np.float32)
+
+    def fresh(w):
+        t = msp.build_tree(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max)
+        P, c = t.partner_probabilities(w, tqd, nqd, wl.sigma, uniforms=uni)
+        t.close()
+        return P, c
+
+    P1r, c1r = fresh(d["w"])
+    P2r, c2r = fresh(w2)
+    assert not torch.equal(P1r, P2r)
+    tree = msp.Tree()
+    tree.build(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max, w=d["w"])
+    P, c = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni, weights_staged=True)
+    assert torch.equal(P, P1r) and torch.equal(c, c1r)
+    # a forward that stages w2 into the records
+    u = torch.empty(wl.n, dtype=torch.float32, device=d["x"].device)
+    tree.forward(w2, tgt, sigma=wl.sigma, route="fgt", out=u, stage_weights=True)
+    P, c = tree.partner_probabilities(w2, tqd, nqd, wl.sigma, uniforms=uni, weights_staged=True)
+    assert torch.equal(P, P2r) and torch.equal(c, c2r)
+    # a partner call that stages its own weights, then one that reuses them
+    P, c = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni)
+    assert torch.equal(P, P1r) and torch.equal(c, c1r)
+    P, c = tree.partner_probabilities(d["w"], tqd, nqd, wl.sigma, uniforms=uni, weights_staged=True)
+    assert torch.equal(P, P1r) and torch.equal(c, c1r)
+    # a weighted build with w2, then its counts
+    tree.build(d["x"], d["y"], d["z"], leaf_max=wl.leaf_max, w=w2)
+    P, c = tree.partner_probabilities(w2, tqd, nqd, wl.sigma, uniforms=uni, weights_staged=True)
+    assert torch.equal(P, P2r) and torch.equal(c, c2r)
+    tree.close()
