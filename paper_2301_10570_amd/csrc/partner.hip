@@ -811,7 +811,7 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         }
         uend = nfirst[child] + ncount[child];
     }
-    // lane c sums the points of child c (a contiguous range in key order), four
+    // lane c sums the points of child c (a contiguous range in key order), eight
     // records in flight.  Each term in float32 relative to the node's closest
     // approach g0 to the target, exp(-(d^2 - g0^2) / sigma^2) <= 1 (scaled by
     // exp(-g0^2 / sigma^2) at the end, and moved to float64 every 32 terms), when
@@ -827,19 +827,19 @@ k_partner_direct(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, c
         if (narrow) {
             float run = 0.f;
             int nrun = 0;
-            for (int32_t j0 = cf; j0 < cend; j0 += 4) {
-                float4 qv[4];
+            for (int32_t j0 = cf; j0 < cend; j0 += 8) {
+                float4 qv[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) qv[u] = j0 + u < cend ? ps[j0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int u = 0; u < 8; ++u) qv[u] = j0 + u < cend ? ps[j0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const int32_t j = j0 + u;
                     const float4 qj = qv[u];
                     if (j >= cend || qj.w == 0.f || (exclude_self && j == si)) continue;
                     const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
                     run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
                 }
-                if (++nrun == 8) {
+                if (++nrun == 4) {
                     mysum += (double)run;
                     run = 0.f;
                     nrun = 0;
@@ -960,7 +960,7 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
         }
     }
     // the lane group g (lanes 8 g .. 8 g + 7) sums the points of child g, lane s of
-    // the group taking every eighth one with four records in flight (the group
+    // the group taking every eighth one with eight records in flight (the group
     // reads whole lines); float32 terms relative to the node's closest approach
     // when the node is narrow enough (as in the eight-lane pass), float64 otherwise
     double g0, far2;
@@ -983,19 +983,19 @@ k_partner_wave(int64_t nq, const int64_t *nq_dev, const int32_t *target_idx, con
         if (narrow) {
             float run = 0.f;
             int nrun = 0;
-            for (int32_t j0 = cf + sl; j0 < gend; j0 += 32) {
-                float4 qv[4];
+            for (int32_t j0 = cf + sl; j0 < gend; j0 += 64) {
+                float4 qv[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) qv[u] = j0 + 8 * u < gend ? ps[j0 + 8 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int u = 0; u < 8; ++u) qv[u] = j0 + 8 * u < gend ? ps[j0 + 8 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const int32_t j = j0 + 8 * u;
                     const float4 qj = qv[u];
                     if (j >= gend || qj.w == 0.f || (exclude_self && j == si)) continue;
                     const float ex = txf - qj.x, ey = tyf - qj.y, ez = tzf - qj.z;
                     run = fmaf(qj.w, __builtin_amdgcn_exp2f((g0f - (ex * ex + ey * ey + ez * ez)) * ksf), run);
                 }
-                if (++nrun == 8) {
+                if (++nrun == 4) {
                     mysum += (double)run;
                     run = 0.f;
                     nrun = 0;
