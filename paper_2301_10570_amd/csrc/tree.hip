@@ -26,6 +26,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kBlock * kItems;   // points per block in tiled passes
+// the node-level passes (point levels, node emission) take a tile with twice the
+// threads: their rounds over the tile are sequential, half as many finish sooner
+constexpr int kLvThreads = 512;
 
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds, uint32_t &total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -385,26 +388,27 @@ __device__ inline PointLevels point_levels(const uint64_t *keys, int64_t n, int6
 // containing i.  Points are striped over threads (coalesced); per-level start
 // counts come from wave ballots.
 constexpr int kWinMax = 1024;
-__global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, int64_t n, int leaf_max,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_levels_tile(const uint64_t *keys, int64_t n, int leaf_max,
                                                         int max_depth, uint8_t *dlev, uint8_t *llev,
                                                         uint32_t *blkcnt, int nblk) {
     __shared__ int8_t Ls[kTile + kWinMax];
     // window maxima by prefix and suffix maxima over blocks of W = leaf_max + 1
     // values (van Herk / Gil-Werman): the window [a, a + W - 1] is max(suf[a], pre[a + W - 1])
     __shared__ int8_t pre[kTile + kWinMax], suf[kTile + kWinMax];
-    __shared__ uint32_t wc[kBlock / 64][kDepth + 1];
+    __shared__ uint32_t wc[NT / 64][kDepth + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kTile;
     const int64_t m = n - leaf_max;
     const int NL = kTile + leaf_max, W = leaf_max + 1, NB = (NL + W - 1) / W;
-    for (int idx = tid; idx < NL; idx += kBlock) {
+    for (int idx = tid; idx < NL; idx += NT) {
         const int64_t j = tile - leaf_max + idx;
         Ls[idx] = (j >= 0 && j < m) ? (int8_t)common_level(keys[j], keys[j + leaf_max]) : (int8_t)-1;
     }
     if (tid <= kDepth)
-        for (int w = 0; w < kBlock / 64; ++w) wc[w][tid] = 0;
+        for (int w = 0; w < NT / 64; ++w) wc[w][tid] = 0;
     __syncthreads();
-    for (int b = tid; b < 2 * NB; b += kBlock) {
+    for (int b = tid; b < 2 * NB; b += NT) {
         const int blk = b < NB ? b : b - NB;
         const int p0 = blk * W, p1 = p0 + W < NL ? p0 + W : NL;
         int mx = -1;
@@ -424,8 +428,8 @@ __global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, in
     uint32_t mycnt[kDepth + 1];
 #pragma unroll
     for (int l = 0; l <= kDepth; ++l) mycnt[l] = 0;
-    for (int r = 0; r < kItems; ++r) {
-        const int off = r * kBlock + tid;
+    for (int r = 0; r < kTile / NT; ++r) {
+        const int off = r * NT + tid;
         const int64_t i = tile + off;
         int d = 255, ll = 0;
         if (i < n) {
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, in
     __syncthreads();
     if (tid <= kDepth) {
         uint32_t c = 0;
-        for (int w = 0; w < kBlock / 64; ++w) c += wc[w][tid];
+        for (int w = 0; w < NT / 64; ++w) c += wc[w][tid];
         blkcnt[(int64_t)tid * nblk + blockIdx.x] = c;
     }
 }
@@ -457,21 +461,22 @@ __global__ void __launch_bounds__(kBlock) k_levels_tile(const uint64_t *keys, in
 // Node emission with striped points: for every level, the rank of a starting
 // point among the block's starts at that level (in point order) from ballots,
 // wave offsets and a running count per level.
-__global__ void __launch_bounds__(kBlock) k_emit_tile(const uint8_t *dlev, const uint8_t *llev,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_emit_tile(const uint8_t *dlev, const uint8_t *llev,
                                                       int64_t n, const uint32_t *blkoff, int nblk,
                                                       const int64_t *level_off, int32_t *nfirst,
                                                       int32_t *nlevel) {
     // per-wave counts, double-buffered by item: the running totals of item r read
     // them after the second barrier while waves may already count item r + 1
-    __shared__ uint32_t wcb[2][kBlock / 64][kDepth + 1];
+    __shared__ uint32_t wcb[2][NT / 64][kDepth + 1];
     __shared__ uint32_t run[kDepth + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     if (tid <= kDepth) run[tid] = 0;
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kTile / NT; ++r) {
         uint32_t(*wc)[kDepth + 1] = wcb[r & 1];
-        const int64_t i = tile + r * kBlock + tid;
+        const int64_t i = tile + r * NT + tid;
         const int d = i < n ? dlev[i] : 255;
         const int ll = i < n ? llev[i] : 0;
         // the levels at which some point of this wave starts a node (most points start
@@ -502,7 +507,7 @@ __global__ void __launch_bounds__(kBlock) k_emit_tile(const uint8_t *dlev, const
         __syncthreads();
         if (tid <= kDepth) {
             uint32_t add = 0;
-            for (int w = 0; w < kBlock / 64; ++w) add += wc[w][tid];
+            for (int w = 0; w < NT / 64; ++w) add += wc[w][tid];
             run[tid] += add;
         }
     }
@@ -946,7 +951,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     auto levels = [&]() -> int {
         PhaseScope ps(&t->timing, PH_LEVELS, s);
         if (leaf_max <= kWinMax) {
-            hipLaunchKernelGGL(k_levels_tile, dim3(nblk), dim3(kBlock), 0, s, t->keys.as<uint64_t>(), n,
+            hipLaunchKernelGGL(k_levels_tile<kLvThreads>, dim3(nblk), dim3(kLvThreads), 0, s, t->keys.as<uint64_t>(), n,
                                leaf_max, max_depth, t->dlev.as<uint8_t>(), t->llev.as<uint8_t>(),
                                blkcnt, nblk);
             MSP_CHECK_LAUNCH();
@@ -1049,7 +1054,7 @@ int build_tree(msp_tree *t, const float *x, const float *y, const float *z, int6
     {
     PhaseScope ps_nodes(&t->timing, PH_NODES, s);
     if (n > 0) {
-        hipLaunchKernelGGL(k_emit_tile, dim3(nblk), dim3(kBlock), 0, s, t->dlev.as<uint8_t>(),
+        hipLaunchKernelGGL(k_emit_tile<kLvThreads>, dim3(nblk), dim3(kLvThreads), 0, s, t->dlev.as<uint8_t>(),
                            t->llev.as<uint8_t>(), n, blkcnt, nblk, t->d_level_off.as<int64_t>(),
                            t->nfirst.as<int32_t>(), t->nlevel.as<int32_t>());
         MSP_CHECK_LAUNCH();
