@@ -754,7 +754,9 @@ __device__ void m2l_gemm_tile(const float *In, float *Out, int64_t R, int p_rt, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nk = (U + 3) / 4;
     const int nv = (U + 15) / 16;
-    for (int vc = wave; vc < nv; vc += 4) {
+    // the grid's y index picks a group of four 16-wide column blocks (one group
+    // when the grid is one-dimensional)
+    for (int vc = wave + 4 * (int)blockIdx.y; vc < nv; vc += 4 * (int)gridDim.y) {
         const int v = vc * 16 + (lane & 15);
         const int tv = v / p, b = v % p;
         f32x4 acc[NR];
@@ -2556,7 +2558,9 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
                 RT >>= 1;
             const size_t lds = m2l_gemm_lds((int)ps.U, ps.G, p, RT);
             if (lds <= 64 * 1024) {
-                const dim3 grid((unsigned)((ps.R + RT - 1) / RT));
+                // column groups of four 16-wide blocks, one per wavefront, as the grid's y
+                const int cg = ((int)(ps.U + 15) / 16 + 3) / 4;
+                const dim3 grid((unsigned)((ps.R + RT - 1) / RT), (unsigned)cg);
                 const int band = m2l_band(p, step, ps.G);
                 if (RT == 64)
                     hipLaunchKernelGGL(k_m2l_gemm<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T, band);
