@@ -2558,9 +2558,14 @@ int fgt_forward_grid(msp_tree *t, const FgtPlan &pl, const msp_fgt_params *prm, 
                 RT >>= 1;
             const size_t lds = m2l_gemm_lds((int)ps.U, ps.G, p, RT);
             if (lds <= 64 * 1024) {
-                // column groups of four 16-wide blocks, one per wavefront, as the grid's y
-                const int cg = ((int)(ps.U + 15) / 16 + 3) / 4;
-                const dim3 grid((unsigned)((ps.R + RT - 1) / RT), (unsigned)cg);
+                // column groups of four 16-wide blocks, one per wavefront, as the grid's y,
+                // only while the row tiles alone make fewer than 1024 blocks (every group
+                // stages the whole input rows)
+                const int64_t rows = (ps.R + RT - 1) / RT;
+                const int ngroup = ((int)(ps.U + 15) / 16 + 3) / 4;
+                const int64_t want = (1024 + rows - 1) / rows;
+                const int cg = want < ngroup ? (int)want : ngroup;
+                const dim3 grid((unsigned)rows, (unsigned)cg);
                 const int band = m2l_band(p, step, ps.G);
                 if (RT == 64)
                     hipLaunchKernelGGL(k_m2l_gemm<64>, grid, dim3(256), lds, s, ps.in, ps.out, ps.R, p, ps.G, ps.T, band);
