@@ -44,7 +44,7 @@ KERNEL_OF_PHASE = {"sort_scatter": "k_rs_scatter", "sort_hist": "k_rs_hist", "so
                    "m2l_z": "k_m2l_gemm", "morton": "k_morton", "stage": "k_stage",
                    "partner": "k_partner", "partner_direct": "k_partner_direct",
                    "partner_wave": "k_partner_wave",
-                   "scatter": "k_finish_u"}   # (expansion route: flags and self term in input order)
+                   "scatter": "k_finish_u4"}   # (expansion route: flags and self term in input order)
 
 
 def _algorithmic(phase, ctx):

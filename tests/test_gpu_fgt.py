@@ -136,6 +136,17 @@ def test_deterministic_and_linear():
     u_a = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, route="fgt").double()
     u_b = tree.forward(2.0 * d["w"], d["tgt"], sigma=wl.sigma, route="fgt").double()
     assert torch.allclose(u_b, 2 * u_a, rtol=1e-6, atol=0)
+    # outputs, weights and flags at unaligned offsets (the expansion route's flag and
+    # self-term pass then takes one point per thread instead of four): the same bits
+    for exclude in (False, True):
+        ref = tree.forward(d["w"], d["tgt"], sigma=wl.sigma, route="fgt", exclude_self=exclude)
+        ub = torch.empty(wl.n + 1, dtype=torch.float32, device=d["x"].device)
+        wb = torch.empty(wl.n + 1, dtype=torch.float32, device=d["x"].device)
+        tb = torch.empty(wl.n + 1, dtype=torch.uint8, device=d["x"].device)
+        wb[1:] = d["w"]
+        tb[1:] = d["tgt"]
+        tree.forward(wb[1:], tb[1:], sigma=wl.sigma, route="fgt", exclude_self=exclude, out=ub[1:])
+        assert torch.equal(ub[1:], ref), exclude
 
 
 def test_edge_cases():
