@@ -31,6 +31,8 @@ PEAK = {"hbm": 8.0e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12, "fp64_vec
 PAIR_FLOPS = 12.0        # walk pairs in float64: offsets, square, scale, exponential (as one), weight, sum
 PAIR_FLOPS32 = 13.0      # direct-pass pairs in float32: 3 offsets, square (5), minus g0^2, scale,
                          # exponential (as one), weight multiply-add (2)
+P2P_FLOPS32 = 11.0       # leaf P2P pairs in float32 (offsets scaled once per point): 3 offsets,
+                         # square (5), exponential (as one), weight multiply-add (2)
 PAIR_BYTES = 16.0        # the point record (x, y, z, staged w)
 NODE_BYTES = 36.0        # level, cell coordinates, first point, count, children, moment flag
 def m2p_flops(p):        # Hermite rows (3 p recurrence steps) and the p^3 contraction, 2 per multiply-add
@@ -330,6 +332,7 @@ def _batch_bench(args, dev, oracle_threads):
     torch.cuda.synchronize()
     ms_graph = 1000.0 * (time.perf_counter() - t0) / args.steps
     inst = b.instance_ms()
+    pairs, span = b.pair_count()   # the direct-route populations of the last replay
     t0 = time.perf_counter()
     for _ in range(args.steps):
         b.forward(w, sig, is_target=tg, p=args.p, out=u, use_graph=False)
@@ -361,7 +364,15 @@ def _batch_bench(args, dev, oracle_threads):
            "sums_per_s": n_tgt / (ms_graph / 1000.0), "launches_per_forward_eager": launches,
            "instance_ms_p50": float(np.percentile(inst, 50)), "instance_ms_p99": float(np.percentile(inst, 99)),
            "fwd_bwd_ms": ms_fb,
-           "m2l_bf16x3": {"forward_ms_graph": ms_graph16, "fwd_bwd_ms": ms_fb16}}
+           "m2l_bf16x3": {"forward_ms_graph": ms_graph16, "fwd_bwd_ms": ms_fb16},
+           # k_batch_p2p: the point pairs of the direct-route populations over the span from
+           # the launch's first to its last work item (beside the expansion-route branch)
+           "direct_route": {"pairs": pairs, "span_ms": span,
+                            "pairs_per_s": pairs / (span / 1000.0) if span > 0 else None,
+                            "bound": "alu", "peak_tflops": PEAK["fp32_vector"] / 1e12,
+                            "achieved_tflops": pairs * P2P_FLOPS32 / (span / 1000.0) / 1e12 if span > 0 else None,
+                            "frac": pairs * P2P_FLOPS32 / (span / 1000.0) / PEAK["fp32_vector"] if span > 0
+                            else None}}
     if not args.no_check:
         import oracle
         u_h = u.cpu().numpy()

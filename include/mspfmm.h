@@ -484,6 +484,18 @@ int msp_batch_instance_ms(msp_batch *b, double *ms);
 /* Number of populations; launches of the last eager forward call. */
 int msp_batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
 
+/* Work of the direct-route populations in the last forward call (Eq. (8) over the
+ * leaf interaction lists): *pairs (or NULL) gets the number of (target point,
+ * source point) pairs their P2P pass evaluates, the sum over leaves of the leaf's
+ * point count times the point counts of the leaves its list names, counted on the
+ * device on `stream` (one small launch, then a wait for `stream`); *span_ms (or
+ * NULL) gets the time from the first to the last work item of the shared
+ * persistent launch, from device timestamps (0 without direct-route populations).
+ * Both are 0 when no population took the direct route.  MSP_ESTATE before the
+ * first forward after a build, or when a later call rebuilt or moved the
+ * populations' lists (a backward with other parameters). */
+int msp_batch_pair_count(msp_batch *b, int64_t *pairs, double *span_ms, void *stream);
+
 /* Per-phase GPU timing.  When enabled, the library records a pair of HIP events
  * around each phase it launches, on the stream that runs it; msp_tree_get_timing
  * waits for them and returns, per phase, the summed milliseconds and the number

@@ -115,6 +115,7 @@ _lib.msp_batch_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(FgtParams
                                     _vp, ctypes.c_int32, _vp]
 _lib.msp_batch_instance_ms.argtypes = [_vp, _vp]
 _lib.msp_batch_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
+_lib.msp_batch_pair_count.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _vp]
 PHASE_COUNT = 32
 for _f in ("msp_octree_build_weighted", "msp_octree_build_query", "msp_octree_build_ws", "msp_fgt_forward_query", "msp_fgt_forward_ws",
            "msp_fgt_forward_noalloc",
@@ -122,7 +123,8 @@ for _f in ("msp_octree_build_weighted", "msp_octree_build_query", "msp_octree_bu
            "msp_fgt_plan", "msp_fgt_forward", "msp_direct_sum", "msp_partner_probabilities",
            "msp_descent_step", "msp_partner_descent",
            "msp_fgt_debug_buffer", "msp_batch_create", "msp_batch_build", "msp_batch_autotune",
-           "msp_batch_forward", "msp_batch_backward", "msp_batch_instance_ms", "msp_batch_info"):
+           "msp_batch_forward", "msp_batch_backward", "msp_batch_instance_ms", "msp_batch_info",
+           "msp_batch_pair_count"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -604,6 +606,15 @@ class Batch:
         npop, launches = _i32(), _i64()
         _check(_lib.msp_batch_info(self._h, ctypes.byref(npop), ctypes.byref(launches)), "msp_batch_info")
         return {"populations": npop.value, "launches_last_eager_forward": launches.value}
+
+    def pair_count(self) -> tuple[int, float]:
+        """(point pairs, span in ms) of the direct-route populations in the last forward:
+        the pairs their P2P pass evaluates and the time from the first to the last work
+        item of the shared persistent launch (msp_batch_pair_count)."""
+        pairs, span = _i64(), ctypes.c_double()
+        _check(_lib.msp_batch_pair_count(self._h, ctypes.byref(pairs), ctypes.byref(span), _stream()),
+               "msp_batch_pair_count")
+        return pairs.value, span.value
 
 
 def build_query(n, leaf_max=64, max_depth=21) -> tuple[int, int]:

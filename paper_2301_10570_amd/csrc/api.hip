@@ -709,6 +709,11 @@ int msp_batch_info(const msp_batch *b, int32_t *npop, int64_t *launches) {
     return batch_info(b, npop, launches);
 }
 
+int msp_batch_pair_count(msp_batch *b, int64_t *pairs, double *span_ms, void *stream) {
+    if (!b) return fail(MSP_EINVAL, "batch handle is NULL");
+    return batch_pair_count(b, pairs, span_ms, (hipStream_t)stream);
+}
+
 const char *msp_phase_name(int phase) {
     static const char *names[PH_COUNT_] = {"bbox", "morton", "radix_sort", "node_levels", "node_table",
                                            "gather_sorted", "stage", "m2l_operators", "p2m", "m2l_x",

@@ -121,6 +121,36 @@ __global__ void __launch_bounds__(256) k_batch_p2p(const PopDesc *desc, const in
     }
 }
 
+// Point pairs the direct-route passes evaluate: over every leaf, its point count
+// times the point counts of the leaves its interaction list names (the list read
+// with the same bounds as the P2P pass), summed into *pairs.
+__global__ void __launch_bounds__(256) k_batch_pairs(const PopDesc *desc, const int64_t *item_off, int nd,
+                                                     unsigned long long *pairs) {
+    __shared__ unsigned long long red[4];
+    const int64_t total = item_off[nd];
+    unsigned long long acc = 0ull;
+    for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < total;
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int d = find_segment(item_off, nd, item);
+        const LeafSet &L = desc[d].ls;
+        const int64_t v = item - item_off[d];
+        if (v >= L.n_nodes || L.nnchild[v] != 0) continue;
+        const int64_t l0 = L.off[v];
+        int64_t l1 = L.off[v + 1];
+        if (l1 - l0 > L.n_nodes) l1 = l0 + L.n_nodes;
+        unsigned long long src = 0ull;
+        for (int64_t e = l0; e < l1; ++e) {
+            const int32_t u = L.lst[e];
+            if (u >= 0 && u < L.n_nodes) src += (unsigned)L.ncount[u];
+        }
+        acc += (unsigned long long)(unsigned)L.ncount[v] * src;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(pairs, red[0] + red[1] + red[2] + red[3]);
+}
+
 __global__ void k_batch_scatter(const PopDesc *desc, const int64_t *pt_off, int nd, float *u_out) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= pt_off[nd]) return;
@@ -378,6 +408,8 @@ int prepare_batch(msp_batch *b, const std::vector<PopPlan> &plans, const float *
         }
     }
     b->n_direct = (int32_t)d.size();
+    b->direct_pops.clear();
+    for (const PopDesc &q : d) b->direct_pops.push_back(q.pop);
     b->direct_points = poff.back();
     b->direct_items = ioff.back();
     MSP_TRY(b->desc.ensure((d.size() + 1) * sizeof(PopDesc)));
@@ -501,7 +533,10 @@ int batch_forward(msp_batch *b, const float *w, const uint8_t *is_target, const 
         return MSP_OK;
     }
     b->drop_fwd_graph();
+    b->pair_gen = -1;
     MSP_TRY(prepare_batch(b, plans, w, is_target, u_out, s));
+    b->pair_gen = b->generation;
+    b->dsig = state_signature(b);
     MSP_TRY(enqueue_forward(b, plans, w, is_target, u_out, s));
     if (!use_graph) return MSP_OK;
     // capture the same sequence for later calls
@@ -788,6 +823,42 @@ int batch_instance_ms(msp_batch *b, double *ms) {
     for (int k = 0; k < b->npop; ++k) {
         const uint64_t a = st[2 * k], c = st[2 * k + 1];
         ms[k] = (c > a && a != ~0ull) ? (double)(c - a) / (double)khz : 0.0;
+    }
+    return MSP_OK;
+}
+
+int batch_pair_count(msp_batch *b, int64_t *pairs, double *span_ms, hipStream_t s) {
+    if (b->pair_gen != b->generation || state_signature(b) != b->dsig)
+        return fail(MSP_ESTATE, "no forward since the populations were built or their lists changed");
+    unsigned long long sum = 0ull;
+    if (b->n_direct > 0 && b->direct_items > 0) {
+        MSP_TRY(b->pair_sum.ensure(8));
+        auto *ps = b->pair_sum.as<unsigned long long>();
+        MSP_HIP(hipMemsetAsync(ps, 0, 8, s));
+        const int64_t want = (b->direct_items + kBlock - 1) / kBlock;
+        const int64_t grid = want < 4096 ? want : 4096;
+        hipLaunchKernelGGL(k_batch_pairs, dim3((unsigned)grid), dim3(kBlock), 0, s, b->desc.as<PopDesc>(),
+                           b->item_off.as<int64_t>(), b->n_direct, ps);
+        MSP_CHECK_LAUNCH();
+        MSP_HIP(hipMemcpyAsync(&sum, ps, 8, hipMemcpyDeviceToHost, s));
+        MSP_HIP(hipStreamSynchronize(s));
+    }
+    if (pairs) *pairs = (int64_t)sum;
+    if (span_ms) {
+        *span_ms = 0.0;
+        if (!b->direct_pops.empty()) {
+            MSP_HIP(hipStreamSynchronize(s));
+            std::vector<uint64_t> st((size_t)b->npop * 2, 0);
+            MSP_HIP(hipMemcpy(st.data(), b->stamps.p, st.size() * 8, hipMemcpyDeviceToHost));
+            uint64_t lo = ~0ull, hi = 0ull;
+            for (int32_t k : b->direct_pops) {
+                lo = st[2 * k] < lo ? st[2 * k] : lo;
+                hi = st[2 * k + 1] > hi ? st[2 * k + 1] : hi;
+            }
+            int khz = 100000;
+            (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device);
+            if (hi > lo && lo != ~0ull) *span_ms = (double)(hi - lo) / (double)khz;
+        }
     }
     return MSP_OK;
 }

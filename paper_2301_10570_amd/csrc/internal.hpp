@@ -323,6 +323,12 @@ struct msp_batch {
     int32_t n_direct = 0;
     int cus = 256;
     int64_t direct_points = 0, direct_items = 0;
+    // populations of the direct-route launch; the pair-count query's sum and the
+    // state (build generation, tree buffers) the last forward prepared its descriptors on
+    std::vector<int32_t> direct_pops;
+    msp::DevBuf pair_sum;
+    int64_t pair_gen = -1;
+    std::vector<uintptr_t> dsig;
     // expansion-route populations: descriptors, offsets, range list, launch plan
     msp::DevBuf fdesc, foff, franges;
     msp::FgtBatchPlan fplan{};
@@ -403,6 +409,7 @@ int batch_autotune(msp_batch *b, const float *x, const float *y, const float *z,
                    float *scratch_u, int32_t *leaf_out, int32_t *route_out, hipStream_t s);
 int batch_instance_ms(msp_batch *b, double *ms);
 int batch_info(const msp_batch *b, int32_t *npop, int64_t *launches);
+int batch_pair_count(msp_batch *b, int64_t *pairs, double *span_ms, hipStream_t s);
 
 // tree.hip
 // tree_buf == NULL: handle-owned memory; otherwise the tree's arrays go to tree_buf

@@ -131,6 +131,9 @@ def test_new_entry_points_check_arguments(lib):
     assert lib.msp_fgt_forward_query(None, ctypes.byref(prm), ctypes.byref(out), None) == -1
     lib.msp_fgt_forward_ws.argtypes = [vp, vp, vp, ctypes.POINTER(_Params), vp, vp, sz, vp]
     assert lib.msp_fgt_forward_ws(None, None, None, ctypes.byref(prm), None, None, 0, None) == -1
+    lib.msp_batch_pair_count.argtypes = [vp, vp, vp, vp]
+    assert lib.msp_batch_pair_count(None, None, None, None) == -1
+    assert b"NULL" in lib.msp_last_error()
 
 
 def test_batch_refuses_flags_it_does_not_honour(lib):

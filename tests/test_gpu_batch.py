@@ -307,3 +307,33 @@ def test_batch_split_bf16_translation(pops):
         b.forward(w, sig, is_target=tg, p=6, m2l="bf16x3")
     assert ei.value.code == msp.MSP_ENOTSUP
     b.close()
+
+
+def test_batch_pair_count(pops):
+    """The direct-route pair count: with no cutoff every leaf lists every leaf, so a
+    population of n points contributes n^2 pairs; with the cutoff it lies between n
+    (each leaf lists itself) and n^2, and below the count without a cutoff."""
+    import paper_2301_10570_amd as msp
+    print("batch pair count: no cutoff (closed form), cutoff (bounds), state checks", flush=True)
+    sub = pops[:6]
+    x, y, z, w, tg, off, sig = _concat(sub, empty_at=2)
+    b = msp.Batch().build(x, y, z, off)
+    with pytest.raises(msp.MspError) as e:
+        b.pair_count()
+    assert e.value.code == -6
+    sizes = np.diff(off)
+    b.forward(w, sig, is_target=tg, route="direct", cutoff_sigmas=0.0, use_graph=False)
+    pairs_all, span = b.pair_count()
+    assert pairs_all == int((sizes.astype(np.int64) ** 2).sum())
+    assert span > 0.0
+    b.forward(w, sig, is_target=tg, route="direct", use_graph=True)
+    pairs_cut, _ = b.pair_count()
+    assert int(sizes.sum()) <= pairs_cut < pairs_all
+    b.forward(w, sig, is_target=tg, route="direct", use_graph=True)   # graph replay: same lists
+    assert b.pair_count()[0] == pairs_cut
+    b.forward(w, sig, is_target=tg, route="fgt", use_graph=False)     # no direct-route population
+    assert b.pair_count() == (0, 0.0)
+    b.build(x, y, z, off)
+    with pytest.raises(msp.MspError):
+        b.pair_count()
+    b.close()
