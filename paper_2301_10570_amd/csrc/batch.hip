@@ -85,7 +85,7 @@ __global__ void k_batch_stage(const PopDesc *desc, const int64_t *pt_off, int nd
 // work) and leaves the loop once the counter passes the last item; population
 // timestamps are recorded once per run of items of one population.
 constexpr int kP2PTake = 1;
-__global__ void __launch_bounds__(256) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
+__global__ void __launch_bounds__(256, 8) k_batch_p2p(const PopDesc *desc, const int64_t *item_off, int nd,
                                                    unsigned long long *counter,
                                                    unsigned long long *stamps) {
     __shared__ P2PShared sh[4];

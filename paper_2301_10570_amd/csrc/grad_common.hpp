@@ -99,13 +99,20 @@ __device__ inline void p2p_grad_leaf_t(const GradLeafSet &L, const float *g2, in
             for (int c0 = 0; c0 < tot; c0 += 64) {
                 const int ns = tot - c0 < 64 ? tot - c0 : 64;
                 wave_sync();
-                if (lane < ns) {
-                    sh.src[lane] = make_float4(nxt.x - ct[0], nxt.y - ct[1], nxt.z - ct[2], nxt.w);
-                    if (TWO) sh.sg[lane] = ngw;
-                }
+                // slots past the chunk's end hold a zero record (weights 0)
+                const bool live = lane < ns;
+                sh.src[lane] = live ? make_float4(nxt.x - ct[0], nxt.y - ct[1], nxt.z - ct[2], nxt.w)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (TWO) sh.sg[lane] = live ? ngw : 0.f;
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
-                for (int j = grp; j < ns; j += G) {
+                // group grp takes sources grp, grp + G, ...: the same trip count on every lane
+                // (a scalar loop that unrolls); G divides 64, so the slots read stay below 64,
+                // and a slot past the chunk's end adds zeros
+                const int nit = __builtin_amdgcn_readfirstlane((ns + G - 1) / G);
+                const int Gs = __builtin_amdgcn_readfirstlane(G);
+                for (int it = 0; it < nit; ++it) {
+                    const int j = it * Gs + grp;
                     const float4 s4 = sh.src[j];
                     const float dx = tx - s4.x, dy = ty - s4.y, dz = tz - s4.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));

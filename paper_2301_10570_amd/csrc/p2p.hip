@@ -93,7 +93,7 @@ __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
 }
 
 // One wavefront per target leaf (non-leaf nodes return at once).
-__global__ void __launch_bounds__(256) k_p2p(int64_t n_nodes, const int32_t *nfirst,
+__global__ void __launch_bounds__(256, 8) k_p2p(int64_t n_nodes, const int32_t *nfirst,
                                             const int32_t *ncount, const int32_t *nnchild,
                                             const int32_t *nlevel, const int32_t *nix,
                                             const int32_t *niy, const int32_t *niz, BoxGeo geo,

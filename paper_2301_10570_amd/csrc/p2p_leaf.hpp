@@ -112,25 +112,35 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
             for (int c0 = 0; c0 < tot; c0 += 64) {
                 const int ns = tot - c0 < 64 ? tot - c0 : 64;
                 wave_sync();
-                if (lane < ns) {
-                    sh.sp[lane] = make_float4((nxt.x - ct[0]) * L.k_scale, (nxt.y - ct[1]) * L.k_scale,
-                                              (nxt.z - ct[2]) * L.k_scale, nxt.w);
-                    sh.sid[lane] = nid;
-                }
+                // slots past the chunk's end hold a zero record (weight 0, no point)
+                const bool live = lane < ns;
+                sh.sp[lane] = live ? make_float4((nxt.x - ct[0]) * L.k_scale, (nxt.y - ct[1]) * L.k_scale,
+                                                 (nxt.z - ct[2]) * L.k_scale, nxt.w)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                sh.sid[lane] = live ? nid : -1;
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
+                // a group takes sources grp, grp + G, ... of the chunk.  The trip count is the
+                // same for every lane (a scalar loop that unrolls): G divides 64, so the last
+                // slots read stay below 64, and a slot past the chunk's end adds exactly 0
                 float part = 0.f;
+                const int nit = __builtin_amdgcn_readfirstlane((ns + G - 1) / G);
+                const float4 *sp = sh.sp + grp;
+                const int32_t *sid = sh.sid + grp;
+                const int Gs = __builtin_amdgcn_readfirstlane(G);
                 if (L.exclude_self) {
-                    for (int j = grp; j < ns; j += G) {
-                        const float4 q = sh.sp[j];
+#pragma unroll 4
+                    for (int it = 0; it < nit; ++it) {
+                        const float4 q = sp[it * Gs];
                         const float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
                         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                         const float e = q.w * __builtin_amdgcn_exp2f(-d2);
-                        part += sh.sid[j] == ti ? 0.f : e;
+                        part += sid[it * Gs] == ti ? 0.f : e;
                     }
                 } else {
-                    for (int j = grp; j < ns; j += G) {
-                        const float4 q = sh.sp[j];
+#pragma unroll 4
+                    for (int it = 0; it < nit; ++it) {
+                        const float4 q = sp[it * Gs];
                         const float dx = tx - q.x, dy = ty - q.y, dz = tz - q.z;
                         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                         part = fmaf(q.w, __builtin_amdgcn_exp2f(-d2), part);
