@@ -196,7 +196,7 @@ __global__ void k_bw_reset(unsigned long long *counter) { *counter = 0ull; }
 // Persistent P2P with derivatives of both fields over the nodes of every
 // direct-route population (four independent wavefronts per block, one item per
 // counter addition).
-__global__ void __launch_bounds__(256) k_batch_p2p_grad(const GradDesc *desc, const int64_t *item_off, int nd,
+__global__ void __launch_bounds__(256, 7) k_batch_p2p_grad(const GradDesc *desc, const int64_t *item_off, int nd,
                                                         unsigned long long *counter, int want_lap) {
     __shared__ GradShared sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

@@ -29,17 +29,19 @@ struct GradLeafSet {
 };
 
 struct GradShared {
-    float4 src[64];                 // staged sources: offsets from the leaf centre, weight
-    float sg[64];                   // their second weights (two fields at once)
+    // staged sources (offsets from the leaf centre, weight) and their second weights
+    // (two fields at once); slots 64..127 hold zeros for the idle lanes' reads
+    float4 src[128];
+    float sg[128];
     float red[9][64];
     int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
 };
 
 // For every point of target leaf v (one wavefront; sh private to it): the sums
 // over the source leaves of its list of e = w exp(-r^2/sigma^2), e (x - s) and
-// e r^2, written as value, gradient and Laplacian of the field.  Lanes are split
-// into G = 64 / tp groups for leaves with tp <= 32 targets, each group taking
-// every G-th source of a staged chunk; the source points of up to 64 list entries
+// e r^2, written as value, gradient and Laplacian of the field.  A block of nt <= 64
+// targets splits the lanes into G = floor(64 / nt) groups of nt (the lanes past G nt
+// idle), each group taking every G-th source of a staged chunk; the source points of up to 64 list entries
 // at a time form one sequence staged 64 per chunk, the next chunk loaded while
 // the current one is used; group partials are added in group order.
 // TWO: a second field at once, with the key-order weights g2 of the sources (value
@@ -56,13 +58,16 @@ __device__ inline void p2p_grad_leaf_t(const GradLeafSet &L, const float *g2, in
     const int64_t l0 = L.off[v];
     int64_t l1 = L.off[v + 1];
     if (l1 - l0 > L.n_nodes) l1 = l0 + L.n_nodes;   // a list names each node at most once
+    sh.src[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.sg[64 + lane] = 0.f;
     for (int t0 = 0; t0 < tn; t0 += 64) {
         const int nt = tn - t0 < 64 ? tn - t0 : 64;
-        int tp = 1;
-        while (tp < nt) tp <<= 1;
+        const int tp = __builtin_amdgcn_readfirstlane(nt);
         const int G = 64 / tp;
-        const int a = lane % tp, grp = lane / tp;
-        const int32_t ti = tf + t0 + (a < nt ? a : 0);
+        // lane / tp as a multiply by ceil(2^16 / tp): exact for lane < 64, tp <= 64
+        const int grp = (lane * ((65536 + tp - 1) / tp)) >> 16;   // grp == G: an idle lane
+        const int a = lane - grp * tp;
+        const int32_t ti = tf + t0 + a;
         const float4 qt = L.ps[ti];
         const float tx = qt.x - ct[0], ty = qt.y - ct[1], tz = qt.z - ct[2];
         float su = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, sr = 0.f;
@@ -107,8 +112,8 @@ __device__ inline void p2p_grad_leaf_t(const GradLeafSet &L, const float *g2, in
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
                 // group grp takes sources grp, grp + G, ...: the same trip count on every lane
-                // (a scalar loop that unrolls); G divides 64, so the slots read stay below 64,
-                // and a slot past the chunk's end adds zeros
+                // (a scalar loop); the slots read stay below ns + G <= 128, and a slot past the
+                // chunk's end adds zeros
                 const int nit = __builtin_amdgcn_readfirstlane((ns + G - 1) / G);
                 const int Gs = __builtin_amdgcn_readfirstlane(G);
                 for (int it = 0; it < nit; ++it) {

@@ -1,9 +1,10 @@
 // P2P of one target leaf against its interaction list (Eq. (8)); shared by the
 // single-tree direct route and the batched persistent kernel.
 //
-// One wavefront per target leaf (sh is private to the wave).  Lanes are split into G = 64 / tp groups for
-// leaves with tp <= 32 targets; each group takes every G-th source of a staged
-// chunk, and the group partials are added in group order at the end.  The source
+// One wavefront per target leaf (sh is private to the wave).  A block of nt <= 64
+// targets splits the lanes into G = floor(64 / nt) groups of nt (the lanes past G nt
+// idle); each group takes every G-th source of a staged chunk, and the group
+// partials are added in group order at the end.  The source
 // leaves of the list are read 64 entries at a time and their points concatenated,
 // so that a chunk of 64 staged sources may span several leaves.  Chunk partials
 // are added with compensation.  exp(-d^2/sigma^2) is evaluated as
@@ -44,8 +45,10 @@ struct LeafSet {
 };
 
 struct P2PShared {
-    float4 sp[64];   // staged sources: scaled offsets from the leaf centre, weight
-    int32_t sid[64];
+    // staged sources (scaled offsets from the leaf centre, weight) and their point
+    // indices; slots 64..127 hold zero records for the idle lanes' reads
+    float4 sp[128];
+    int32_t sid[128];
     float red[64];
     int32_t efirst[64], eend[64];   // a window of list entries: point offset and end
 };
@@ -67,13 +70,16 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
     const int64_t l0 = L.off[v];
     int64_t l1 = L.off[v + 1];
     if (l1 - l0 > L.n_nodes) l1 = l0 + L.n_nodes;   // a list names each node at most once
+    sh.sp[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.sid[64 + lane] = -1;
     for (int t0 = 0; t0 < tn; t0 += 64) {
         const int nt = tn - t0 < 64 ? tn - t0 : 64;
-        int tp = 1;
-        while (tp < nt) tp <<= 1;
+        const int tp = __builtin_amdgcn_readfirstlane(nt);
         const int G = 64 / tp;
-        const int a = lane % tp, grp = lane / tp;
-        const int32_t ti = tf + t0 + (a < nt ? a : 0);
+        // lane / tp as a multiply by ceil(2^16 / tp): exact for lane < 64, tp <= 64
+        const int grp = (lane * ((65536 + tp - 1) / tp)) >> 16;   // grp == G: an idle lane
+        const int a = lane - grp * tp;
+        const int32_t ti = tf + t0 + a;
         const float4 qt = L.ps[ti];
         const float tx = (qt.x - ct[0]) * L.k_scale;
         const float ty = (qt.y - ct[1]) * L.k_scale;
@@ -121,8 +127,8 @@ __device__ inline void p2p_leaf(const LeafSet &L, int64_t v, P2PShared &sh) {
                 wave_sync();
                 if (c0 + 64 < tot) fetch(c0 + 64);
                 // a group takes sources grp, grp + G, ... of the chunk.  The trip count is the
-                // same for every lane (a scalar loop that unrolls): G divides 64, so the last
-                // slots read stay below 64, and a slot past the chunk's end adds exactly 0
+                // same for every lane (a scalar loop that unrolls); the slots read stay below
+                // ns + G <= 128, and a slot past the chunk's end adds exactly 0
                 float part = 0.f;
                 const int nit = __builtin_amdgcn_readfirstlane((ns + G - 1) / G);
                 const float4 *sp = sh.sp + grp;
